@@ -1,0 +1,324 @@
+"""FP64 CPU oracle for the boundary-integral Poisson-Boltzmann hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library never calls it and shares no code with it.
+
+Plain and slow on purpose: the per-pair quadrature lives in ``pbm_oracle.c``
+(plain C loops, FP64); this module composes the paper's block systems from
+dense operator matrices with NumPy, applies the block-diagonal
+preconditioner, runs unrestarted GMRES (modified Gram-Schmidt, Givens
+rotations) and evaluates the solvation energy.
+
+Citations are to Search, Cooper & van 't Wout, arXiv 2108.10481:
+  * internal direct formulation ........ Eq. bie:dirichlet:int
+  * Juffer formulation .................. Eq. bie:juffer:int
+  * source projections .................. Eq. sources
+  * reaction potential, energy .......... Eqs. phireac_bie and dG
+  * block-diagonal preconditioner ....... Preconditioning / Algebraic preconditioners
+  * GMRES, tol 1e-5, no restart ......... Results and Discussion (setup paragraph)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "pbm_oracle.c")
+
+#: e^2 / (4 pi eps0 * 1 angstrom) in kcal/mol.  Potentials here carry a
+#: 1/(4 pi) without eps0, so energies are multiplied by 4 pi times this.
+COULOMB_KCAL = 332.0637
+ENERGY_C = 4.0 * math.pi * COULOMB_KCAL
+
+DIRECT = 0
+JUFFER = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle with gcc (FP64, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+_dp = np.ctypeslib.ndpointer(np.float64, flags="C")
+_ip = np.ctypeslib.ndpointer(np.int32, flags="C")
+_c_int = ctypes.c_int
+_c_dbl = ctypes.c_double
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.orc_regular_rule.argtypes = [_dp, _dp]
+        L.orc_gauss_legendre01.argtypes = [_c_int, _dp, _dp]
+        L.orc_triangle_geometry.argtypes = [_dp, _ip, _c_int, _dp, _dp]
+        L.orc_pair_block.argtypes = [_dp, _ip, _c_int, _c_int, _c_dbl, _c_int, _c_int, _c_int, _dp, _dp]
+        L.orc_pair_block.restype = _c_int
+        L.orc_operator_rows.argtypes = [_c_int, _c_int, _dp, _ip, _c_dbl, _c_int, _c_int, _ip, _c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_mass_rows.argtypes = [_c_int, _c_int, _dp, _ip, _c_int, _ip, _dp]
+        L.orc_rhs.argtypes = [_c_int, _c_int, _dp, _ip, _c_int, _dp, _dp, _c_dbl, _dp, _dp]
+        L.orc_reaction_potential.argtypes = [_c_int, _c_int, _dp, _ip, _dp, _dp, _c_int, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _mesh_arrays(mesh):
+    return (np.ascontiguousarray(mesh.xyz, dtype=np.float64),
+            np.ascontiguousarray(mesh.tri, dtype=np.int32))
+
+
+# ------------------------------------------------------------------ rules
+def regular_rule():
+    b = np.zeros(18)
+    w = np.zeros(6)
+    lib().orc_regular_rule(b, w)
+    return b.reshape(6, 3), w
+
+
+def gauss_legendre01(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    if lib().orc_gauss_legendre01(n, x, w) != 0:
+        raise ValueError(n)
+    return x, w
+
+
+def triangle_geometry(mesh):
+    xyz, tri = _mesh_arrays(mesh)
+    a = np.zeros(len(tri))
+    n = np.zeros((len(tri), 3))
+    lib().orc_triangle_geometry(xyz, tri, len(tri), a, n)
+    return a, n
+
+
+def pair_block(mesh, t: int, s: int, kappa: float, nss: int = 4,
+               kernel_mode: int = 0, quad_mode: int = 0):
+    """Local 3x3 blocks (V, K) of the ordered pair (test t, trial s)."""
+    xyz, tri = _mesh_arrays(mesh)
+    V = np.zeros(9)
+    K = np.zeros(9)
+    ns = lib().orc_pair_block(xyz, tri, int(t), int(s), float(kappa), int(nss),
+                              int(kernel_mode), int(quad_mode), V, K)
+    return V.reshape(3, 3), K.reshape(3, 3), ns
+
+
+# -------------------------------------------------------------- operators
+def operator_rows(mesh, kappa: float, rows, mode: int = 0, want=("V", "K", "D"), nss: int = 4):
+    """Rows (mode 0) or columns (mode 1) of V, K, D for the kernel exp(-kappa r)/(4 pi r)."""
+    xyz, tri = _mesh_arrays(mesh)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    nv = len(xyz)
+    out = {k: np.zeros((len(rows), nv)) for k in want}
+    ptr = lambda k: out[k].ctypes.data_as(ctypes.c_void_p) if k in out else None
+    lib().orc_operator_rows(nv, len(tri), xyz, tri, float(kappa), int(nss), len(rows), rows,
+                            int(mode), ptr("V"), ptr("K"), ptr("D"))
+    return out
+
+
+def assemble(mesh, kappa: float, want=("V", "K", "D"), nss: int = 4):
+    """Dense V, K, D (rows = test vertex, columns = trial vertex)."""
+    return operator_rows(mesh, kappa, np.arange(mesh.n_vertices), 0, want, nss)
+
+
+def mass_rows(mesh, rows):
+    xyz, tri = _mesh_arrays(mesh)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((len(rows), len(xyz)))
+    lib().orc_mass_rows(len(xyz), len(tri), xyz, tri, len(rows), rows, out)
+    return out
+
+
+def mass(mesh):
+    return mass_rows(mesh, np.arange(mesh.n_vertices))
+
+
+# --------------------------------------------------------------- sources
+def rhs(mesh, charges, eps_in: float):
+    """Galerkin-tested source projections (b_D, b_N) of Eq. sources."""
+    xyz, tri = _mesh_arrays(mesh)
+    bD = np.zeros(len(xyz))
+    bN = np.zeros(len(xyz))
+    lib().orc_rhs(len(xyz), len(tri), xyz, tri, charges.n,
+                  np.ascontiguousarray(charges.xyz, dtype=np.float64),
+                  np.ascontiguousarray(charges.q, dtype=np.float64), float(eps_in), bD, bN)
+    return bD, bN
+
+
+def reaction_potential(mesh, phi, dphi, pts):
+    """phi_reac at points (Eq. phireac_bie), Laplace potentials of the traces."""
+    xyz, tri = _mesh_arrays(mesh)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(len(pts))
+    lib().orc_reaction_potential(len(xyz), len(tri), xyz, tri,
+                                 np.ascontiguousarray(phi, dtype=np.float64),
+                                 np.ascontiguousarray(dphi, dtype=np.float64), len(pts), pts, out)
+    return out
+
+
+def solvation_energy(mesh, charges, phi, dphi):
+    """Delta G = 1/2 sum_j q_j phi_reac(x_j) (Eq. dG), in kcal/mol."""
+    pr = reaction_potential(mesh, phi, dphi, charges.xyz)
+    return 0.5 * ENERGY_C * float(np.dot(charges.q, pr))
+
+
+# ------------------------------------------------------------ formulations
+def system_blocks(ops_L, ops_Y, M, eps_in, eps_out, formulation):
+    """2x2 block system of the chosen formulation, Galerkin form.
+
+    ops_L / ops_Y hold V, K and (for Juffer) D and T of the Laplace ("int")
+    and Yukawa ("ext") kernels; the identity becomes the mass matrix M.
+    """
+    if formulation == DIRECT:                       # Eq. bie:dirichlet:int
+        A11 = 0.5 * M + ops_L["K"]
+        A12 = -ops_L["V"]
+        A21 = 0.5 * M - ops_Y["K"]
+        A22 = (eps_in / eps_out) * ops_Y["V"]
+    elif formulation == JUFFER:                     # Eq. bie:juffer:int
+        a = eps_out / eps_in
+        b = eps_in / eps_out
+        A11 = 0.5 * (1.0 + a) * M + ops_L["K"] - a * ops_Y["K"]
+        A12 = -ops_L["V"] + ops_Y["V"]
+        A21 = -ops_L["D"] + ops_Y["D"]
+        A22 = 0.5 * (1.0 + b) * M - ops_L["T"] + b * ops_Y["T"]
+    else:
+        raise ValueError(formulation)
+    return A11, A12, A21, A22
+
+
+def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4):
+    want = ("V", "K") if formulation == DIRECT else ("V", "K", "D")
+    oL = assemble(mesh, 0.0, want, nss)
+    oY = assemble(mesh, kappa, want, nss)
+    if formulation == JUFFER:
+        oL["T"] = oL["K"].T.copy()                  # adjoint double layer as K^T
+        oY["T"] = oY["K"].T.copy()
+    M = mass(mesh)
+    A11, A12, A21, A22 = system_blocks(oL, oY, M, eps_in, eps_out, formulation)
+    return np.block([[A11, A12], [A21, A22]])
+
+
+def system_rhs(bD, bN, formulation):
+    if formulation == DIRECT:
+        return np.concatenate([bD, np.zeros_like(bD)])
+    return np.concatenate([bD, bN])
+
+
+def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4):
+    """Sampled rows of y = A x for large meshes: returns (y1[rows], y2[rows])."""
+    rows = np.asarray(rows, dtype=np.int32)
+    nv = mesh.n_vertices
+    x1, x2 = x[:nv], x[nv:]
+    want = ("V", "K") if formulation == DIRECT else ("V", "K", "D")
+    oL = operator_rows(mesh, 0.0, rows, 0, want, nss)
+    oY = operator_rows(mesh, kappa, rows, 0, want, nss)
+    if formulation == JUFFER:
+        oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss)["K"]
+        oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss)["K"]
+    M = mass_rows(mesh, rows)
+    A11, A12, A21, A22 = system_blocks(oL, oY, M, eps_in, eps_out, formulation)
+    return A11 @ x1 + A12 @ x2, A21 @ x1 + A22 @ x2
+
+
+def block_diagonal_inverse(A, nv):
+    """Per-vertex 2x2 inverse of [[A11_ii, A12_ii], [A21_ii, A22_ii]]."""
+    d = np.arange(nv)
+    a = A[d, d]
+    b = A[d, nv + d]
+    c = A[nv + d, d]
+    e = A[nv + d, nv + d]
+    det = a * e - b * c
+    inv = np.empty((nv, 2, 2))
+    inv[:, 0, 0] = e / det
+    inv[:, 0, 1] = -b / det
+    inv[:, 1, 0] = -c / det
+    inv[:, 1, 1] = a / det
+    return inv
+
+
+def apply_block_diag(inv, v):
+    nv = inv.shape[0]
+    v1, v2 = v[:nv], v[nv:]
+    return np.concatenate([inv[:, 0, 0] * v1 + inv[:, 0, 1] * v2,
+                           inv[:, 1, 0] * v1 + inv[:, 1, 1] * v2])
+
+
+def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
+    """Unrestarted GMRES from x0 = 0 with modified Gram-Schmidt and Givens
+    rotations; stops when the residual estimate drops below tol * |b|.
+    Returns (x, iterations, residual-estimate history)."""
+    n = b.size
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        return np.zeros(n), 0, [0.0]
+    m = min(max_iter, n)
+    Q = np.zeros((m + 1, n))
+    H = np.zeros((m + 1, m))
+    cs = np.zeros(m)
+    sn = np.zeros(m)
+    g = np.zeros(m + 1)
+    g[0] = beta
+    Q[0] = b / beta
+    hist = [beta]
+    k = 0
+    for j in range(m):
+        w = apply(Q[j])
+        for i in range(j + 1):
+            H[i, j] = np.dot(w, Q[i])
+            w = w - H[i, j] * Q[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] > 0:
+            Q[j + 1] = w / H[j + 1, j]
+        for i in range(j):
+            t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+            H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+            H[i, j] = t
+        den = math.hypot(H[j, j], H[j + 1, j])
+        cs[j] = H[j, j] / den
+        sn[j] = H[j + 1, j] / den
+        H[j, j] = den
+        H[j + 1, j] = 0.0
+        g[j + 1] = -sn[j] * g[j]
+        g[j] = cs[j] * g[j]
+        k = j + 1
+        hist.append(abs(g[j + 1]))
+        if abs(g[j + 1]) <= tol * beta:
+            break
+    y = np.zeros(k)
+    for i in range(k - 1, -1, -1):
+        y[i] = (g[i] - np.dot(H[i, i + 1:k], y[i + 1:k])) / H[i, i]
+    return Q[:k].T @ y, k, hist
+
+
+def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRECT,
+          preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None):
+    """Dense FP64 solve: returns dict(phi, dphi, dG, iterations, rel_residual)."""
+    nv = mesh.n_vertices
+    if A is None:
+        A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss)
+    bD, bN = rhs(mesh, charges, eps_in)
+    b = system_rhs(bD, bN, formulation)
+    if preconditioner:
+        inv = block_diagonal_inverse(A, nv)
+        P = lambda v: apply_block_diag(inv, v)
+    else:
+        P = lambda v: v
+    pb = P(b)
+    u, its, hist = gmres(lambda v: P(A @ v), pb, tol, max_iter)
+    res = float(np.linalg.norm(pb - P(A @ u)) / np.linalg.norm(pb))
+    phi, dphi = u[:nv], u[nv:]
+    dG = solvation_energy(mesh, charges, phi, dphi)
+    return {"phi": phi, "dphi": dphi, "dG": dG, "iterations": its, "rel_residual": res,
+            "history": hist, "A": A, "b": b}

@@ -1,0 +1,365 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test names what it pins.  None of them re-types an oracle formula: they
+use exact integrals, library routines (NumPy, SciPy), identities stated in the
+paper (jump relations -> Gauss law, Eq. bie Green's identities), textbook
+closed forms (Kirkwood, sphere spectra) and convergence rates.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from kirkwood import kirkwood_central, kirkwood_energy, sphere_eigenvalues
+
+
+# ------------------------------------------------------------------ rules
+def test_regular_rule_exact_to_degree_4():
+    """int_T x^a y^b = a! b! / (a+b+2)! on the unit right triangle, a+b <= 4."""
+    bary, w = oracle.regular_rule()
+    assert abs(w.sum() - 1.0) < 1e-15
+    x, y = bary[:, 1], bary[:, 2]
+    for a in range(5):
+        for b in range(5 - a):
+            got = 0.5 * np.sum(w * x ** a * y ** b)
+            exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            assert abs(got - exact) < 2e-16 * 10, (a, b, got, exact)
+    # and it is NOT exact at degree 5 (catches a swapped weight / point pair)
+    got = 0.5 * np.sum(w * x ** 5)
+    assert abs(got - math.factorial(5) / math.factorial(7)) > 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 8, 12])
+def test_gauss_legendre_matches_numpy(n):
+    x, w = oracle.gauss_legendre01(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    order = np.argsort(xr)
+    assert np.allclose(np.sort(x), 0.5 * (xr[order] + 1.0), atol=1e-15, rtol=0)
+    assert np.allclose(w[np.argsort(x)], 0.5 * wr[order], atol=1e-15, rtol=0)
+    # exactness on [0,1]: int t^d = 1/(d+1) for d <= 2n-1
+    for d in range(2 * n):
+        assert abs(np.sum(w * x ** d) - 1.0 / (d + 1)) < 1e-14
+
+
+# ------------------------------------------------------- singular quadrature
+@pytest.fixture(scope="module")
+def skew_mesh():
+    """A coarse non-spherical closed mesh: pairs are skewed and non-coplanar."""
+    m, _ = inputs.star_surface(7, 2, 3.0)
+    tri = m.tri
+    pairs = {3: (0, 0)}
+    for s in range(1, len(tri)):
+        k = len(set(tri[0]) & set(tri[s]))
+        if k in (1, 2) and k not in pairs:
+            pairs[k] = (0, s)
+    # a second set of pairs from another triangle, in the opposite order
+    for s in range(len(tri)):
+        k = len(set(tri[7]) & set(tri[s]))
+        if k in (1, 2) and (10 + k) not in pairs:
+            pairs[10 + k] = (s, 7)
+    return m, pairs
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_sauter_schwab_polynomial_exactness(skew_mesh, mode):
+    """The region maps and Jacobians integrate polynomial kernels exactly: the
+    singular rule must agree with the (exact) regular tensor rule."""
+    m, pairs = skew_mesh
+    for key, (t, s) in pairs.items():
+        Vs, Ks, ns = oracle.pair_block(m, t, s, 0.0, 4, kernel_mode=mode, quad_mode=0)
+        Vr, Kr, _ = oracle.pair_block(m, t, s, 0.0, 4, kernel_mode=mode, quad_mode=1)
+        assert ns == key % 10
+        scale = np.abs(Vr).max()
+        assert np.abs(Vs - Vr).max() < 1e-13 * scale, (key, mode)
+        scale = max(np.abs(Kr).max(), 1e-3 * scale)
+        assert np.abs(Ks - Kr).max() < 1e-13 * scale, (key, mode)
+
+
+@pytest.mark.parametrize("kappa", [0.0, 0.125])
+def test_sauter_schwab_exponential_convergence(skew_mesh, kappa):
+    """Singular integrals converge exponentially in the Gauss order (the maps
+    cancel the 1/r singularity): errors vs order 14 fall below 1e-8 at order 8."""
+    m, pairs = skew_mesh
+    for key, (t, s) in pairs.items():
+        Vref, Kref, ns = oracle.pair_block(m, t, s, kappa, 14)
+        errs = []
+        for n in (3, 4, 6, 8):
+            V, K, _ = oracle.pair_block(m, t, s, kappa, n)
+            e = np.abs(V - Vref).max() / np.abs(Vref).max()
+            if ns < 3:   # K vanishes identically on a coincident flat pair
+                e = max(e, np.abs(K - Kref).max() / np.abs(Kref).max())
+            errs.append(e)
+        assert errs[-1] < 1e-8, (key, errs)
+        assert errs[0] > errs[1] > errs[2] > errs[3], (key, errs)
+        assert errs[1] < 1e-4, (key, errs)
+
+
+def test_coincident_double_layer_vanishes(skew_mesh):
+    """(x - y).n_y = 0 for x, y on the same flat triangle, so K_tt = 0."""
+    m, _ = skew_mesh
+    for t in range(0, m.n_triangles, 5):
+        V, K, ns = oracle.pair_block(m, t, t, 0.125, 4)
+        assert ns == 3
+        assert np.abs(K).max() < 1e-14 * np.abs(V).max()
+
+
+# ---------------------------------------------------------------- operators
+@pytest.fixture(scope="module")
+def sphere8():
+    m = inputs.icosphere(8, 1.0)
+    return m, oracle.assemble(m, 0.0), oracle.assemble(m, 0.7), oracle.mass(m)
+
+
+@pytest.fixture(scope="module")
+def sphere4():
+    m = inputs.icosphere(4, 1.0)
+    return m, oracle.assemble(m, 0.0), oracle.assemble(m, 0.7), oracle.mass(m)
+
+
+def test_mass_matrix(sphere8):
+    m, _, _, M = sphere8
+    area, _ = oracle.triangle_geometry(m)
+    assert abs(M.sum() - area.sum()) < 1e-13 * area.sum()
+    assert np.allclose(M, M.T, atol=0, rtol=0)
+    np.linalg.cholesky(M)
+
+
+def test_gauss_law_double_layer(sphere8):
+    """Jump relations (Methodology): the interior trace of the Laplace double
+    layer of 1 is -1, so K_int[1] = -1/2, i.e. K_L 1 = -1/2 M 1 on a closed
+    surface.  Only quadrature error remains (flat faces subtend exactly 2 pi)."""
+    m, oL, _, M = sphere8
+    one = np.ones(m.n_vertices)
+    lhs = oL["K"] @ one
+    rhs = -0.5 * M @ one
+    assert np.abs(lhs - rhs).max() < 1e-5 * np.abs(rhs).max()
+
+
+def test_gauss_law_double_layer_star():
+    m, _ = inputs.star_surface(11, 4, 5.0)
+    o = oracle.assemble(m, 0.0, want=("K",))
+    M = oracle.mass(m)
+    one = np.ones(m.n_vertices)
+    assert np.abs(o["K"] @ one + 0.5 * M @ one).max() < 2e-5 * np.abs(M @ one).max()
+
+
+def test_hypersingular_annihilates_constants(sphere8):
+    """curl of a constant is 0: D_L 1 = 0 exactly; D_Y 1 = kappa^2 (n.n) V part only."""
+    m, oL, oY, _ = sphere8
+    one = np.ones(m.n_vertices)
+    assert np.abs(oL["D"] @ one).max() < 1e-13 * np.abs(oL["D"]).max()
+    assert np.abs(oY["D"] @ one).max() > 1e-3 * np.abs(oY["D"]).max()
+
+
+def test_single_layer_symmetric_positive(sphere8):
+    m, oL, oY, _ = sphere8
+    for o in (oL, oY):
+        V = o["V"]
+        assert np.abs(V - V.T).max() < 1e-6 * np.abs(V).max()
+        np.linalg.cholesky(0.5 * (V + V.T))
+        D = o["D"]
+        assert np.abs(D - D.T).max() < 1e-6 * np.abs(D).max()
+
+
+def _rayleigh(A, u, M):
+    return float(u @ A @ u) / float(u @ M @ u)
+
+
+@pytest.mark.parametrize("kind", ["L", "Y"])
+def test_sphere_spectra_converge(sphere4, sphere8, kind):
+    """Galerkin Rayleigh quotients of interpolated spherical harmonics converge
+    at O(h^2) to the textbook sphere eigenvalues of V, K, T (= K^T) and D."""
+    kap = 0.0 if kind == "L" else 0.7
+    errs = {}
+    for tag, (m, oL, oY, M) in (("4", sphere4), ("8", sphere8)):
+        o = oL if kind == "L" else oY
+        z = m.xyz[:, 2] / np.linalg.norm(m.xyz, axis=1)
+        xx = m.xyz[:, 0] / np.linalg.norm(m.xyz, axis=1)
+        harmonics = {0: np.ones_like(z), 1: z, 2: 1.5 * z * z - 0.5, 3: xx * (5 * z * z - 1)}
+        for l, u in harmonics.items():
+            ex = sphere_eigenvalues(l, 1.0, kap)
+            for op in ("V", "K", "D"):
+                if op == "D" and l == 0 and kind == "L":
+                    assert abs(_rayleigh(o["D"], u, M)) < 1e-12
+                    continue
+                got = _rayleigh(o[op], u, M)
+                errs[(tag, l, op)] = abs(got - ex[op]) / abs(ex[op])
+            gotT = _rayleigh(o["K"].T, u, M)
+            assert abs(gotT - _rayleigh(o["K"], u, M)) < 1e-12
+    for key, e8 in errs.items():
+        if key[0] != "8":
+            continue
+        e4 = errs[("4",) + key[1:]]
+        assert e8 < 0.01, (key, e8)
+        if key[1] <= 2:   # l = 3 is still pre-asymptotic on these meshes
+            assert e8 < e4 / 2.5 or e8 < 2e-4, (key, e4, e8)
+
+
+def _traces_laplace_interior(m, x1):
+    """u = 1/|x - x1| (x1 outside) and its normal derivative on the unit sphere."""
+    d = m.xyz - x1
+    r = np.linalg.norm(d, axis=1)
+    n = m.xyz / np.linalg.norm(m.xyz, axis=1, keepdims=True)
+    return 1.0 / r, -np.sum(d * n, axis=1) / r ** 3
+
+
+def _traces_yukawa_exterior(m, x0, kap):
+    """u = exp(-kappa |x - x0|)/|x - x0| (x0 inside) and its normal derivative."""
+    d = m.xyz - x0
+    r = np.linalg.norm(d, axis=1)
+    n = m.xyz / np.linalg.norm(m.xyz, axis=1, keepdims=True)
+    u = np.exp(-kap * r) / r
+    du = -np.exp(-kap * r) * (1 + kap * r) / r ** 3 * np.sum(d * n, axis=1)
+    return u, du
+
+
+def test_green_identities(sphere4, sphere8):
+    """Eq. bie with zero sources: the Calderon systems annihilate the traces of
+    interior harmonic and exterior Yukawa fields.  Residuals fall at O(h^2).
+    This pins the signs and scalings of V, K, T and D for both kernels."""
+    x1 = np.array([1.7, 0.4, -0.3])
+    x0 = np.array([0.2, -0.3, 0.25])
+    kap = 0.7
+    res = {}
+    for tag, (m, oL, oY, M) in (("4", sphere4), ("8", sphere8)):
+        uD, uN = _traces_laplace_interior(m, x1)
+        r1 = (0.5 * M + oL["K"]) @ uD - oL["V"] @ uN
+        r2 = -oL["D"] @ uD + (0.5 * M - oL["K"].T) @ uN
+        vD, vN = _traces_yukawa_exterior(m, x0, kap)
+        r3 = (0.5 * M - oY["K"]) @ vD + oY["V"] @ vN
+        r4 = oY["D"] @ vD + (0.5 * M + oY["K"].T) @ vN
+        res[tag] = [np.linalg.norm(r1) / np.linalg.norm(M @ uD), np.linalg.norm(r2) / np.linalg.norm(M @ uN),
+                    np.linalg.norm(r3) / np.linalg.norm(M @ vD), np.linalg.norm(r4) / np.linalg.norm(M @ vN)]
+    for a, b in zip(res["4"], res["8"]):
+        assert b < 0.02 and b < a / 2.5, (res)
+    # a flipped sign in any block leaves an O(1) residual
+    m, oL, oY, M = sphere8
+    uD, uN = _traces_laplace_interior(m, x1)
+    bad = (0.5 * M - oL["K"]) @ uD - oL["V"] @ uN
+    assert np.linalg.norm(bad) / np.linalg.norm(M @ uD) > 0.1
+
+
+def test_reaction_potential_representation():
+    """Interior representation formula (Eq. representation, no charges): the
+    potentials V[du] - K[u] of the traces of a harmonic u reproduce u inside."""
+    x1 = np.array([1.6, -0.5, 0.4])
+    pts = np.array([[0.1, 0.2, -0.1], [-0.4, 0.1, 0.3], [0.0, 0.0, 0.0]])
+    exact = 1.0 / np.linalg.norm(pts - x1, axis=1)
+    errs = []
+    for f in (4, 8):
+        m = inputs.icosphere(f, 1.0)
+        uD, uN = _traces_laplace_interior(m, x1)
+        got = oracle.reaction_potential(m, uD, uN, pts)
+        errs.append(np.abs(got - exact).max() / np.abs(exact).max())
+    assert errs[1] < 5e-3 and errs[1] < errs[0] / 2.5, errs
+
+
+def test_rhs_gauss_flux_and_central_charge():
+    """Eq. sources: the flux of the charges' field through the closed surface
+    is -sum q / eps_in (Gauss), so sum_i bN_i = -sum q / eps_in; a central
+    charge gives constant traces q/(4 pi eps a) and -q/(4 pi eps a^2)."""
+    m = inputs.icosphere(8, 2.0)
+    ch = inputs.charges_ball(5, 7, 1.2)
+    bD, bN = oracle.rhs(m, ch, 4.0)
+    assert abs(bN.sum() + ch.q.sum() / 4.0) < 1e-4 * np.abs(ch.q).sum() / 4.0
+    mk, c1 = inputs.config_kirkwood(8, 2.0)
+    bD, bN = oracle.rhs(mk, c1, 4.0)
+    M1 = oracle.mass(mk) @ np.ones(mk.n_vertices)
+    assert np.abs(bD / M1 - 1.0 / (4 * np.pi * 4.0 * 2.0)).max() < 2e-2 / (4 * np.pi * 8.0)
+    assert np.abs(bN / M1 + 1.0 / (4 * np.pi * 4.0 * 4.0)).max() < 4e-2 / (4 * np.pi * 16.0)
+
+
+# ------------------------------------------------------------- full solve
+def test_kirkwood_central_charge_converges():
+    """Configuration of a 2 A sphere with a central +1 e charge: Delta G
+    approaches the closed form -19.9238 kcal/mol at O(h^2) for both
+    formulations, and the two formulations agree closely."""
+    assert abs(kirkwood_central(2.0) + 19.9238) < 1e-4
+    out = {}
+    for f in (4, 8):
+        m, ch = inputs.config_kirkwood(f, 2.0)
+        for form in (oracle.DIRECT, oracle.JUFFER):
+            r = oracle.solve(m, ch, formulation=form)
+            assert r["rel_residual"] < 1e-5 * 1.01
+            out[(f, form)] = (r["dG"] - kirkwood_central(2.0)) / kirkwood_central(2.0)
+    for form in (oracle.DIRECT, oracle.JUFFER):
+        assert abs(out[(4, form)]) < 0.015
+        assert abs(out[(8, form)]) < 0.004
+        assert 3.0 < out[(4, form)] / out[(8, form)] < 5.0
+    assert abs(out[(8, 0)] - out[(8, 1)]) < 5e-4
+
+
+def test_kirkwood_series_multi_charge():
+    """Several off-centre charges in a 10 A sphere: Delta G converges to the
+    Kirkwood multipole series (l <= 60) at O(h^2)."""
+    ch = inputs.charges_ball(2, 6, 8.0)
+    ref = kirkwood_energy(10.0, ch.xyz, ch.q)
+    errs = []
+    for f in (4, 8):
+        m = inputs.icosphere(f, 10.0)
+        r = oracle.solve(m, ch, formulation=oracle.DIRECT)
+        errs.append(abs(r["dG"] - ref) / abs(ref))
+    assert errs[1] < 0.03 and errs[1] < errs[0] / 2.5, (errs, ref)
+
+
+def test_gmres_matches_dense_lu_and_preconditioner_invariance():
+    """GMRES equals a dense LU solve at tight tolerance, with or without the
+    block-diagonal preconditioner; P P^-1 = I per vertex."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    for form in (oracle.DIRECT, oracle.JUFFER):
+        A = oracle.system_matrix(m, 4.0, 80.0, 0.125, form)
+        bD, bN = oracle.rhs(m, ch, 4.0)
+        b = oracle.system_rhs(bD, bN, form)
+        x = np.linalg.solve(A, b)
+        for prec in (True, False):
+            r = oracle.solve(m, ch, formulation=form, preconditioner=prec, tol=1e-13, A=A)
+            u = np.concatenate([r["phi"], r["dphi"]])
+            assert np.abs(u - x).max() < 1e-9 * np.abs(x).max()
+            h = np.array(r["history"])
+            assert np.all(np.diff(h) <= 1e-12 * h[0])
+        nv = m.n_vertices
+        inv = oracle.block_diagonal_inverse(A, nv)
+        d = np.arange(nv)
+        P = np.zeros((nv, 2, 2))
+        P[:, 0, 0], P[:, 0, 1] = A[d, d], A[d, nv + d]
+        P[:, 1, 0], P[:, 1, 1] = A[nv + d, d], A[nv + d, nv + d]
+        assert np.abs(np.einsum("vij,vjk->vik", P, inv) - np.eye(2)).max() < 1e-12
+
+
+def test_block_diagonal_reduces_direct_iterations():
+    """Block-diagonal preconditioning of the direct formulation cuts GMRES
+    iterations (the paper reports up to 6.6x fewer on arginine)."""
+    m, ch = inputs.config_sphere(8, 10.0, 10, 8.0, 2)
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, oracle.DIRECT)
+    r0 = oracle.solve(m, ch, preconditioner=False, A=A)
+    r1 = oracle.solve(m, ch, preconditioner=True, A=A)
+    assert r1["iterations"] < r0["iterations"]
+    assert abs(r1["dG"] - r0["dG"]) < 1e-3 * abs(r0["dG"])
+
+
+def test_juffer_mass_spectrum_approaches_printed_points():
+    """The paper prints 10.5 and 0.525 as the accumulation points of the
+    mass-preconditioned Juffer system (tests/golden).  The oracle's discrete
+    spectrum of blockdiag(M, M)^-1 A splits into two clusters whose lower
+    edges approach those points as the mesh is refined."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "juffer_mass_accumulation_points.txt")
+    eps_in, eps_out, p_hi, p_lo = [float(v) for v in
+                                    [ln for ln in open(path) if not ln.startswith("#")][0].split()]
+    dist = []
+    for f in (4, 8):
+        m = inputs.icosphere(f, 2.0)
+        nv = m.n_vertices
+        A = oracle.system_matrix(m, eps_in, eps_out, 0.125, oracle.JUFFER)
+        M = oracle.mass(m)
+        Z = np.zeros_like(M)
+        ev = np.linalg.eigvals(np.linalg.solve(np.block([[M, Z], [Z, M]]), A))
+        assert np.abs(ev.imag).max() < 1e-8
+        ev = ev.real
+        lo, hi = ev[ev < 0.5 * (p_lo + p_hi)], ev[ev >= 0.5 * (p_lo + p_hi)]
+        assert len(lo) == nv and len(hi) == nv
+        dist.append((lo.min() / p_lo - 1.0, hi.min() / p_hi - 1.0))
+    for k in range(2):
+        assert 0 < dist[1][k] < 0.05 and dist[1][k] < 0.7 * dist[0][k], dist
