@@ -1,0 +1,221 @@
+/*
+ * pbm.h -- C ABI of the MI355X boundary-element Poisson-Boltzmann library.
+ *
+ * The library computes, for a closed triangulated molecular surface Gamma
+ * with point charges inside, the interior surface potential gamma_D^- phi and
+ * its normal derivative gamma_N^- phi (the unknowns of the paper's internal
+ * direct formulation, Eq. bie:dirichlet:int, and Juffer formulation,
+ * Eq. bie:juffer:int) and the polar solvation energy Delta G (Eq. dG) of the
+ * linearised Poisson-Boltzmann interface problem (Eq. poissonboltzmann) of
+ * Search, Cooper & van 't Wout, arXiv 2108.10481.
+ *
+ * Discretisation: continuous piecewise-linear (P1) Galerkin on flat
+ * triangles (Numerical discretization), one degree of freedom per vertex per
+ * trace; the Laplace ("int") and Yukawa ("ext", screening kappa) single-,
+ * double-, adjoint double-layer and hypersingular operators (Eq.
+ * layer_potentials); regular 6-point degree-4 quadrature on triangle pairs
+ * sharing no vertex and Sauter-Schwab quadrature on pairs sharing a vertex;
+ * block-diagonal preconditioner (Preconditioning, Algebraic preconditioners);
+ * GMRES without restart (Results, tolerance 1e-5).
+ *
+ * Conventions for every entry point:
+ *   - Units: angstrom, elementary charge, 1/angstrom; Delta G in kcal/mol.
+ *   - Unless a name ends in _device, pointer arguments are HOST pointers.
+ *     Inputs are read-only and copied during the call; the caller keeps
+ *     ownership.  Output arrays are caller-allocated with the stated length.
+ *   - Handles are owned by the library: every *_create has a *_destroy.
+ *   - Return value: PB_OK (0); a positive value is a warning with a valid
+ *     result; a negative value is an error with no result, and
+ *     pb_last_error() returns a message for the calling thread.
+ *   - No exceptions or callbacks cross the ABI.  Calls on one handle must not
+ *     overlap in time; different handles may be used from different threads.
+ *   - All device work of a handle runs on its own HIP stream (default
+ *     priority).  The library allocates its own device memory.
+ */
+#ifndef PBM_H
+#define PBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status codes */
+typedef int32_t pb_status;
+#define PB_OK              0
+#define PB_NOT_CONVERGED   1   /* max_iter reached; outputs filled, rel_residual > tol */
+#define PB_E_INVALID_ARG  (-1) /* NULL pointer, bad size, NaN input, bad option value */
+#define PB_E_MESH         (-2) /* open, non-manifold, inverted or degenerate mesh */
+#define PB_E_CHARGES      (-3) /* a charge lies outside the surface */
+#define PB_E_NOMEM        (-4) /* device memory or admission budget exceeded */
+#define PB_E_DEVICE       (-5) /* HIP runtime error or no usable GPU */
+#define PB_E_STATE        (-6) /* call not valid for this handle's configuration */
+
+/* ------------------------------------------------------------------ options */
+#define PB_DIRECT_INT   0  /* Eq. bie:dirichlet:int: [[M/2+K_L, -V_L], [M/2-K_Y, (e_in/e_out) V_Y]] */
+#define PB_JUFFER       1  /* Eq. bie:juffer:int: second-kind, uses all four operators */
+
+#define PB_PREC_NONE    0
+#define PB_BLOCK_DIAG   1  /* per-vertex 2x2 inverse of the four blocks' diagonals */
+
+#define PB_FP64         0  /* every kernel evaluation and sum in FP64 */
+#define PB_FP32         1  /* far-field kernel evaluations in FP32, tile sums FP32,
+                              cross-tile sums, near field and Krylov in FP64 */
+#define PB_MIXED_BF16   2  /* assembled far field stored BF16 (FP32 accumulate) for an
+                              inner GMRES; FP64 iterative refinement on the FP32 operator */
+#define PB_MIXED_FP16   3  /* as PB_MIXED_BF16 with FP16 storage and per-block scales */
+
+#define PB_MATRIX_FREE  0  /* far field recomputed on every matvec */
+#define PB_ASSEMBLED    1  /* far field assembled once as a dense 2V x 2V matrix */
+#define PB_AUTO         2  /* assembled when it fits the device-memory budget */
+
+typedef struct {
+    int32_t n_vertices;
+    int32_t n_triangles;
+    const double *xyz;    /* n_vertices x 3, row-major, angstrom */
+    const int32_t *tri;   /* n_triangles x 3, 0-based vertex ids, counter-clockwise
+                             seen from the solvent (outward normal) */
+} pb_mesh;
+
+typedef struct {
+    int32_t n;
+    const double *xyz;    /* n x 3, angstrom, strictly inside the surface */
+    const double *q;      /* n, elementary charges */
+} pb_charges;
+
+typedef struct {
+    double eps_in;            /* interior permittivity (paper: 4) */
+    double eps_out;           /* exterior permittivity (paper: 80) */
+    double kappa;             /* inverse Debye length, 1/angstrom (paper: 0.125) */
+    int32_t formulation;      /* PB_DIRECT_INT or PB_JUFFER */
+    int32_t preconditioner;   /* PB_BLOCK_DIAG or PB_PREC_NONE */
+    int32_t precision;        /* PB_FP64, PB_FP32, PB_MIXED_BF16, PB_MIXED_FP16 */
+    int32_t operator_mode;    /* PB_MATRIX_FREE, PB_ASSEMBLED, PB_AUTO */
+    double tol;               /* relative preconditioned residual (paper: 1e-5) */
+    int32_t max_iter;         /* GMRES iterations (no restart), default 1000 */
+    int32_t singular_order;   /* Gauss points per dimension, Sauter-Schwab (default 4) */
+    int32_t source_chunks;    /* far-field split of the source range; 0 = automatic */
+    int32_t inner_max_iter;   /* mixed modes: inner GMRES cap (default 200) */
+    double inner_tol;         /* mixed modes: inner relative tolerance (default 1e-3) */
+    size_t memory_budget;     /* bytes the handle may hold on the device; 0 = 90% of free */
+} pb_options;
+
+typedef struct {
+    double *phi;              /* caller-allocated, n_vertices: gamma_D^- phi at the vertices */
+    double *dphi;             /* caller-allocated, n_vertices: gamma_N^- phi at the vertices */
+    double dG_kcal;           /* polar solvation energy, kcal/mol */
+    int32_t iterations;       /* total GMRES iterations (inner iterations in mixed modes) */
+    int32_t outer_iterations; /* iterative-refinement sweeps (1 outside mixed modes) */
+    double rel_residual;      /* final |P^-1(b - A u)| / |P^-1 b|, recomputed */
+    double t_setup;           /* seconds: geometry, near field, assembly ("LHS") */
+    double t_rhs;             /* seconds: source projections ("RHS") */
+    double t_prec;            /* seconds: preconditioner build and apply to b */
+    double t_gmres;           /* seconds: Krylov solve */
+    double t_dG;              /* seconds: reaction potential and Delta G */
+    size_t device_bytes;      /* device memory held by the mesh handle */
+} pb_result;
+
+typedef struct pb_mesh_handle pb_mesh_handle;
+
+typedef struct {
+    int32_t n_vertices, n_triangles;
+    int64_t n_near_pairs;     /* ordered triangle pairs sharing >= 1 vertex */
+    int64_t near_nnz;         /* nonzeros of each near-field vertex block */
+    int32_t source_chunks;    /* far-field source split in use */
+    int32_t assembled;        /* 1 if the far field is held as a dense matrix */
+    size_t device_bytes;
+} pb_mesh_info;
+
+/* Fill *opt with the paper's settings: eps 4/80, kappa 0.125, direct
+ * formulation, block-diagonal preconditioner, FP64, matrix-free, tol 1e-5,
+ * max_iter 1000, singular order 4. */
+void pb_default_options(pb_options *opt);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *pb_last_error(void);
+
+/* Number of visible GPUs (0 if none); does not initialise a context. */
+int32_t pb_device_count(void);
+
+/* ------------------------------------------------------------- whole solve */
+
+/* One complete solve (setup, RHS, preconditioner, GMRES, Delta G).
+ * result->phi / result->dphi must hold n_vertices doubles each, or be NULL. */
+pb_status pb_solve(const pb_mesh *mesh, const pb_charges *charges,
+                   const pb_options *opt, pb_result *result);
+
+/* -------------------------------------------------------- resident meshes */
+
+/* Validate the mesh, sort its triangles along a space-filling curve, compute
+ * geometry, the Sauter-Schwab near field (FP64, Numerical discretization), the
+ * mass matrix, the block-diagonal preconditioner and, in assembled modes, the
+ * dense far field.  All of it stays on the device until pb_mesh_destroy.
+ * The options fix formulation, precision and operator mode for the handle. */
+pb_status pb_mesh_create(const pb_mesh *mesh, const pb_options *opt, pb_mesh_handle **out);
+pb_status pb_mesh_destroy(pb_mesh_handle *h);
+pb_status pb_mesh_get_info(const pb_mesh_handle *h, pb_mesh_info *info);
+
+/* Solve for one charge set on a resident mesh (same outputs as pb_solve). */
+pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result *result);
+
+/* Solve for n_sets charge sets on one resident mesh.  In assembled modes the
+ * right-hand sides are advanced together and every operator application is
+ * one batched dense product (MFMA for 16-bit storage).  out[k] follows the
+ * pb_result contract for set k. */
+pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *sets,
+                         pb_result *out);
+
+/* ------------------------------------------------- hot-path building blocks
+ * Exposed for verification and measurement; each runs on the handle's stream
+ * and returns after the result is on the host. */
+
+/* y = A x (flags & PB_APPLY_PRECOND: y = P^-1 A x) for the handle's
+ * formulation.  x and y are host arrays of 2 n_vertices doubles laid out as
+ * [trace_D; trace_N].  PB_APPLY_FAR_ONLY / PB_APPLY_NEAR_ONLY restrict the sum
+ * to triangle pairs sharing no vertex / sharing a vertex (plus the mass terms). */
+#define PB_APPLY_PRECOND    1
+#define PB_APPLY_FAR_ONLY   2
+#define PB_APPLY_NEAR_ONLY  4
+pb_status pb_mesh_apply(pb_mesh_handle *h, const double *x, double *y, int32_t flags);
+
+/* Same as pb_mesh_apply on device vectors (2 n_vertices doubles each) and on
+ * the caller's HIP stream (NULL = the handle's stream); returns without
+ * synchronising. */
+pb_status pb_mesh_apply_device(pb_mesh_handle *h, const double *x_device, double *y_device,
+                               int32_t flags, void *hip_stream);
+
+/* Galerkin-tested source projections of Eq. sources: b = [<phi_i, phi_D>;
+ * <phi_i, phi_N>] (host array of 2 n_vertices doubles).  The second half is
+ * computed for both formulations (the direct formulation does not use it). */
+pb_status pb_mesh_rhs(pb_mesh_handle *h, const pb_charges *charges, double *b);
+
+/* Reaction potential (Eq. phireac_bie) at npts points from P1 traces phi and
+ * dphi (host, n_vertices each); out: npts doubles. */
+pb_status pb_mesh_reaction_potential(pb_mesh_handle *h, const double *phi, const double *dphi,
+                                     int32_t npts, const double *pts, double *out);
+
+/* Sauter-Schwab local blocks of near pairs (original triangle ids t[k], s[k],
+ * which must share a vertex): out[36 k + 9 op + 3 a + b] with op = 0 V_L,
+ * 1 K_L, 2 V_Y, 3 K_Y, a the local vertex of t[k], b of s[k] (input order). */
+pb_status pb_mesh_near_blocks(pb_mesh_handle *h, int32_t n, const int32_t *t, const int32_t *s,
+                              double *out);
+
+/* Per-vertex 2x2 preconditioner inverses, out: n_vertices x 4 (row-major). */
+pb_status pb_mesh_preconditioner(pb_mesh_handle *h, double *out);
+
+/* Kernel timing for measurement: when enabled, the far-field operator kernel
+ * (or the dense product in assembled modes) is bracketed by HIP events on the
+ * stream it runs on; read returns the launches and summed milliseconds since
+ * the last reset.  kind 0 = far-field / dense operator kernel. */
+pb_status pb_mesh_profile(pb_mesh_handle *h, int32_t enable);
+pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launches, double *total_ms);
+
+/* Block until all work of the handle is done. */
+pb_status pb_mesh_synchronize(pb_mesh_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBM_H */

@@ -1,0 +1,326 @@
+// Far field, matrix-free: regular 6 x 6 point quadrature over every ordered
+// triangle pair that shares no vertex (Numerical discretization), fused over
+// the operators of one formulation (Eqs. bie:dirichlet:int, bie:juffer:int).
+//
+// Work split:
+//   k_source_prep : x (2V) -> per-triangle source weights b1 = w|s| u1(y_q),
+//                   b2 = w|s| u2(y_q), C = |s| curl u1|_s.
+//   k_far         : one lane per target triangle (6 target points held in
+//                   registers), grid.y splits the source triangles into chunks;
+//                   the source loop is wavefront-uniform, so source records
+//                   come through scalar loads and feed the VALU as scalar
+//                   operands.  Pairs sharing a vertex are skipped (they are in
+//                   the near field).  Per-chunk partial sums are written out.
+//   k_far_finish  : FP64 sum over chunks, P1 test projection on the target
+//                   triangle -> 3 values per block row.
+//   k_gather      : per vertex, fixed-order sum of triangle contributions,
+//                   near-field CSR product, optional 2x2 preconditioner.
+#include "pbm_internal.h"
+
+namespace pbm {
+
+__global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, const double *__restrict__ geo,
+                              const double *__restrict__ x, double *__restrict__ dyn64, float *__restrict__ dyn32)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T) return;
+    const double *g = geo + (size_t)s * kGeo;
+    const double area = g[21];
+    double u1[3], u2[3];
+    for (int k = 0; k < 3; ++k) {
+        int v = tri[3 * s + k];
+        u1[k] = x[v];
+        u2[k] = x[V + v];
+    }
+    double *d64 = dyn64 + (size_t)s * kDyn;
+    float *d32 = dyn32 + (size_t)s * kDyn;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        double a = rule_bary(q, 0) * u1[0] + rule_bary(q, 1) * u1[1] + rule_bary(q, 2) * u1[2];
+        double b = rule_bary(q, 0) * u2[0] + rule_bary(q, 1) * u2[1] + rule_bary(q, 2) * u2[2];
+        double w = rule_w(q) * area;
+        d64[q] = w * a;
+        d64[6 + q] = w * b;
+        d32[q] = (float)(w * a);
+        d32[6 + q] = (float)(w * b);
+    }
+    for (int c = 0; c < 3; ++c) {
+        double cu = area * (u1[0] * g[22 + c] + u1[1] * g[25 + c] + u1[2] * g[28 + c]);
+        d64[12 + c] = cu;
+        d32[12 + c] = (float)cu;
+    }
+    d64[15] = 0.0;
+    d32[15] = 0.0f;
+}
+
+void launch_source_prep(DevMesh &d, const double *x, bool)
+{
+    int T = d.hm.T;
+    hipLaunchKernelGGL(k_source_prep, dim3((T + 255) / 256), dim3(256), 0, d.stream, T, d.hm.V, d.tri, d.geo, x,
+                       d.dyn64, d.dyn32);
+    HIPCHECK(hipGetLastError());
+}
+
+// ----------------------------------------------------------- math helpers
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x)
+{
+    // hardware estimate refined by two Newton steps: y <- y (3 - x y^2) / 2
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    return y;
+}
+// exp(-kappa r) given kl = kappa * log2(e) (FP32) or kappa (FP64)
+__device__ __forceinline__ float expneg(float kl, float r) { return __builtin_amdgcn_exp2f(-kl * r); }
+__device__ __forceinline__ double expneg(double k, double r) { return exp(-k * r); }
+
+template <typename R>
+struct FarCoef {
+    R kappa;   // screening
+    R kexp;    // argument scale for expneg
+    R c1;      // direct: eps_in/eps_out       Juffer: alpha = eps_out/eps_in
+    R c2;      // Juffer: beta = eps_in/eps_out
+    R k2;      // Juffer: kappa^2
+};
+
+constexpr int kFarBlock = 256;
+
+// FORM 0: internal direct.  Per target point p accumulates (no 1/4pi)
+//   a1 += F_L (d.n_s) b1 - G_L b2                 (K_L u1 - V_L u2)
+//   a2 += -F_Y (d.n_s) b1 + c1 G_Y b2             (-K_Y u1 + eps V_Y u2)
+// FORM 1: Juffer.
+//   a1 += (F_L - alpha F_Y)(d.n_s) b1 + (G_Y - G_L) b2
+//   a2 += (F_L - beta F_Y)(d.n_t) b2 + kappa^2 (n_t.n_s) G_Y b1
+//   and the hypersingular curl part, per source triangle:
+//   W  += [sum_pq w_p w_q (G_Y - G_L)] C_s
+// with d = x_p - y_q, G = e/r, F = e (1 + kappa r)/r^3 (e = 1 for Laplace).
+template <typename R, int FORM>
+__global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> cf, const int32_t *__restrict__ tri,
+                                                    const R *__restrict__ stat, const R *__restrict__ dyn,
+                                                    R *__restrict__ part)
+{
+    const int t = blockIdx.x * kFarBlock + threadIdx.x;
+    const int s0 = blockIdx.y * chunk;
+    const int s1 = min(T, s0 + chunk);
+    if (t >= T) return;
+    const R *ts = stat + (size_t)t * kStat;
+    R tx[6], ty[6], tz[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) { tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2]; }
+    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+    R xnt[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) xnt[p] = ts[21 + p];
+    const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
+    R a1[6], a2[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) { a1[p] = 0; a2[p] = 0; }
+    R W0 = 0, W1 = 0, W2 = 0;
+
+    for (int s = s0; s < s1; ++s) {
+        const int j0 = tri[3 * s], j1 = tri[3 * s + 1], j2 = tri[3 * s + 2];
+        const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
+                         (j2 == v0) | (j2 == v1) | (j2 == v2);
+        if (adj) continue;
+        const R *st = stat + (size_t)s * kStat;
+        const R *sd = dyn + (size_t)s * kDyn;
+        const R nsx = st[18], nsy = st[19], nsz = st[20];
+        R xns[6];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) xns[p] = tx[p] * nsx + ty[p] * nsy + tz[p] * nsz;
+        R g = 0, k2nn = 0;
+        if (FORM == 1) k2nn = cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const R yx = st[3 * q], yy = st[3 * q + 1], yz = st[3 * q + 2];
+            const R yns = st[21 + q];
+            const R b1 = sd[q], b2 = sd[6 + q];
+            R ynt = 0, kb1 = 0;
+            if (FORM == 1) { ynt = yx * ntx + yy * nty + yz * ntz; kb1 = k2nn * b1; }
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = rsqrt_r(r2);
+                const R r = r2 * ri;
+                const R e = expneg(cf.kexp, r);
+                const R ri3 = ri * ri * ri;
+                const R dns = xns[p] - yns;
+                const R tt = cf.kappa * r + R(1);
+                if (FORM == 0) {
+                    const R fl = dns * ri3;
+                    const R rb2 = ri * b2;
+                    a1[p] += fl * b1 - rb2;
+                    a2[p] += e * (cf.c1 * rb2 - fl * tt * b1);
+                } else {
+                    const R fy = e * tt * ri3;
+                    const R gy = e * ri;
+                    const R dg = gy - ri;
+                    const R dnt = xnt[p] - ynt;
+                    a1[p] += (ri3 - cf.c1 * fy) * dns * b1 + dg * b2;
+                    a2[p] += (ri3 - cf.c2 * fy) * dnt * b2 + kb1 * gy;
+                    g += R(rule_w(p) * rule_w(q)) * dg;
+                }
+            }
+        }
+        if (FORM == 1) {
+            W0 += g * sd[12];
+            W1 += g * sd[13];
+            W2 += g * sd[14];
+        }
+    }
+    R *o = part + ((size_t)blockIdx.y * T + t) * 16;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) { o[p] = a1[p]; o[6 + p] = a2[p]; }
+    o[12] = W0; o[13] = W1; o[14] = W2; o[15] = 0;
+}
+
+template <typename R>
+__global__ void k_far_finish(int T, int S, int form, const double *__restrict__ geo, const R *__restrict__ part,
+                             double *__restrict__ triout)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    double pot[15];
+    for (int v = 0; v < 15; ++v) pot[v] = 0.0;
+    for (int c = 0; c < S; ++c) {
+        const R *o = part + ((size_t)c * T + t) * 16;
+        for (int v = 0; v < 15; ++v) pot[v] += (double)o[v];
+    }
+    const double *g = geo + (size_t)t * kGeo;
+    const double sc = g[21] * kInv4Pi;
+    for (int k = 0; k < 3; ++k) {
+        double y1 = 0.0, y2 = 0.0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const double w = rule_w(p) * rule_bary(p, k);
+            y1 += w * pot[p];
+            y2 += w * pot[6 + p];
+        }
+        if (form == PB_JUFFER)
+            y2 += g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14];
+        triout[6 * (size_t)t + k] = sc * y1;
+        triout[6 * (size_t)t + 3 + k] = sc * y2;
+    }
+}
+
+// flags: PB_APPLY_PRECOND, PB_APPLY_NEAR_ONLY, PB_APPLY_FAR_ONLY (near part skipped)
+__global__ void k_gather(int V, int use_far, int use_near, int precond, const int32_t *__restrict__ inc_ptr,
+                         const int32_t *__restrict__ inc_tk, const double *__restrict__ triout,
+                         const double *__restrict__ yfar,
+                         const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                         const double *__restrict__ N, int64_t nnz, const double *__restrict__ pinv,
+                         const double *__restrict__ x, double *__restrict__ y)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    double y1 = 0.0, y2 = 0.0;
+    if (use_far == 2) {
+        y1 = yfar[i];
+        y2 = yfar[V + i];
+    } else if (use_far == 1) {
+        for (int e = inc_ptr[i]; e < inc_ptr[i + 1]; ++e) {
+            const int tk = inc_tk[e];
+            const int t = tk >> 2, k = tk & 3;
+            y1 += triout[6 * (size_t)t + k];
+            y2 += triout[6 * (size_t)t + 3 + k];
+        }
+    }
+    if (use_near) {
+        double n1 = 0.0, n2 = 0.0;
+        for (int sl = row_ptr[i]; sl < row_ptr[i + 1]; ++sl) {
+            const int j = col[sl];
+            const double x1 = x[j], x2 = x[V + j];
+            n1 += N[sl] * x1 + N[nnz + sl] * x2;
+            n2 += N[2 * nnz + sl] * x1 + N[3 * nnz + sl] * x2;
+        }
+        y1 += n1;
+        y2 += n2;
+    }
+    if (precond) {
+        const double *P = pinv + 4 * (size_t)i;
+        const double z1 = P[0] * y1 + P[1] * y2, z2 = P[2] * y1 + P[3] * y2;
+        y1 = z1;
+        y2 = z2;
+    }
+    y[i] = y1;
+    y[V + i] = y2;
+}
+
+int choose_chunks(int T)
+{
+    // enough wavefronts for >= 4 per SIMD on 256 CUs x 4 SIMDs, chunks >= 32 triangles
+    const int waves = (T + 63) / 64;
+    int S = (4096 + waves - 1) / waves;
+    S = std::max(1, std::min(S, 64));
+    while (S > 1 && (T + S - 1) / S < 32) --S;
+    return S;
+}
+
+template <typename R>
+static void far_launch(DevMesh &d, const R *stat, const R *dyn)
+{
+    const int T = d.hm.T, S = d.S;
+    const int chunk = (T + S - 1) / S;
+    FarCoef<R> cf;
+    const double kap = d.prm.kappa;
+    cf.kappa = (R)kap;
+    cf.kexp = (sizeof(R) == 4) ? (R)(kap * 1.4426950408889634) : (R)kap;
+    const bool direct = d.prm.formulation == PB_DIRECT_INT;
+    cf.c1 = (R)(direct ? d.prm.eps_in / d.prm.eps_out : d.prm.eps_out / d.prm.eps_in);
+    cf.c2 = (R)(d.prm.eps_in / d.prm.eps_out);
+    cf.k2 = (R)(kap * kap);
+    dim3 grid((T + kFarBlock - 1) / kFarBlock, S), block(kFarBlock);
+    R *part = (R *)d.part;
+    if (direct)
+        hipLaunchKernelGGL((k_far<R, 0>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part);
+    else
+        hipLaunchKernelGGL((k_far<R, 1>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_far(DevMesh &d, bool fp32)
+{
+    Profiler &pf = d.prof;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pf.enabled) {
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, d.stream));
+    }
+    if (fp32) far_launch<float>(d, d.stat32, d.dyn32);
+    else far_launch<double>(d, d.stat64, d.dyn64);
+    if (pf.enabled) {
+        HIPCHECK(hipEventRecord(e1, d.stream));
+        pf.ev.push_back(e0);
+        pf.ev.push_back(e1);
+    }
+}
+
+void launch_far_finish(DevMesh &d, bool fp32)
+{
+    const int T = d.hm.T;
+    dim3 grid((T + 255) / 256), block(256);
+    if (fp32)
+        hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, d.prm.formulation, d.geo,
+                           (const float *)d.part, d.triout);
+    else
+        hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, d.prm.formulation, d.geo,
+                           (const double *)d.part, d.triout);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far)
+{
+    const int V = d.hm.V;
+    const int use_near = (flags & PB_APPLY_FAR_ONLY) ? 0 : 1;
+    hipLaunchKernelGGL(k_gather, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, use_far, use_near,
+                       (flags & PB_APPLY_PRECOND) ? 1 : 0, d.inc_ptr, d.inc_tk, d.triout, d.yfar, d.row_ptr, d.col, d.N,
+                       d.nnz(), d.pinv, x, y);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace pbm

@@ -1,0 +1,303 @@
+// Near field: Sauter-Schwab quadrature of every ordered triangle pair that
+// shares a vertex (Numerical discretization; S. Sauter and C. Schwab, Boundary
+// Element Methods, Springer 2011, sec. 5.2), assembly of the four near-field
+// vertex blocks of the chosen formulation (mass terms included), and the
+// block-diagonal preconditioner (Preconditioning, Algebraic preconditioners).
+// Everything here is FP64 in every precision mode.
+#include "pbm_internal.h"
+
+namespace pbm {
+
+constexpr int kMaxGL = 16;
+__constant__ double c_gl_x[kMaxGL + 1][kMaxGL];
+__constant__ double c_gl_w[kMaxGL + 1][kMaxGL];
+
+void upload_gauss_tables()
+{
+    static bool done = false;
+    if (done) return;
+    double hx[kMaxGL + 1][kMaxGL] = {}, hw[kMaxGL + 1][kMaxGL] = {};
+    for (int n = 1; n <= kMaxGL; ++n) gauss_legendre01(n, hx[n], hw[n]);
+    HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_x), hx, sizeof(hx)));
+    HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), hw, sizeof(hw)));
+    done = true;
+}
+
+// Reference triangle {0 <= u2 <= u1 <= 1}, chi(u) = P0 + u1 (P1 - P0) + u2 (P2 - P1),
+// barycentrics (1 - u1, u1 - u2, u2), surface element 2|T| du.  The unit
+// hypercube (xi, a, b, c) is split into regions mapped onto the pair of
+// reference triangles with Jacobians that cancel the 1/r singularity.
+struct SSPoint { double u1, u2, v1, v2, jac; };
+
+__device__ inline SSPoint ss_map(int cas, int r, double xi, double a, double b, double c)
+{
+    SSPoint m;
+    if (cas == 3) {          // identical triangles: 6 regions
+        m.jac = xi * xi * xi * a * a * b;
+        switch (r) {
+        case 0: m.u1 = xi; m.u2 = xi * (1 - a + a * b); m.v1 = xi * (1 - a * b * c); m.v2 = xi * (1 - a); break;
+        case 1: m.u1 = xi * (1 - a * b * c); m.u2 = xi * (1 - a); m.v1 = xi; m.v2 = xi * (1 - a + a * b); break;
+        case 2: m.u1 = xi; m.u2 = xi * a * (1 - b + b * c); m.v1 = xi * (1 - a * b); m.v2 = xi * a * (1 - b); break;
+        case 3: m.u1 = xi * (1 - a * b); m.u2 = xi * a * (1 - b); m.v1 = xi; m.v2 = xi * a * (1 - b + b * c); break;
+        case 4: m.u1 = xi * (1 - a * b * c); m.u2 = xi * a * (1 - b * c); m.v1 = xi; m.v2 = xi * a * (1 - b); break;
+        default: m.u1 = xi; m.u2 = xi * a * (1 - b); m.v1 = xi * (1 - a * b * c); m.v2 = xi * a * (1 - b * c); break;
+        }
+    } else if (cas == 2) {   // common edge P0-P1 (u2 = 0 on both): 5 regions
+        m.jac = xi * xi * xi * a * a * (r == 0 ? 1.0 : b);
+        switch (r) {
+        case 0: m.u1 = xi; m.u2 = xi * a * c; m.v1 = xi * (1 - a * b); m.v2 = xi * a * (1 - b); break;
+        case 1: m.u1 = xi; m.u2 = xi * a; m.v1 = xi * (1 - a * b * c); m.v2 = xi * a * b * (1 - c); break;
+        case 2: m.u1 = xi * (1 - a * b); m.u2 = xi * a * (1 - b); m.v1 = xi; m.v2 = xi * a * b * c; break;
+        case 3: m.u1 = xi * (1 - a * b * c); m.u2 = xi * a * b * (1 - c); m.v1 = xi; m.v2 = xi * a; break;
+        default: m.u1 = xi * (1 - a * b * c); m.u2 = xi * a * (1 - b * c); m.v1 = xi; m.v2 = xi * a * b; break;
+        }
+    } else {                 // common vertex P0: 2 regions
+        m.jac = xi * xi * xi * b;
+        if (r == 0) { m.u1 = xi; m.u2 = xi * a; m.v1 = xi * b; m.v2 = xi * b * c; }
+        else { m.u1 = xi * b; m.u2 = xi * b * c; m.v1 = xi; m.v2 = xi * a; }
+    }
+    return m;
+}
+
+// Local vertex order: shared vertices first.  Identical: stored order.  Edge:
+// the test triangle is rotated so the shared edge is (0,1) in its own cyclic
+// order; the trial triangle lists the same two vertices in the same order
+// then its free vertex.  Vertex: both rotated so the shared vertex is first.
+// The stored (outward) normals are kept whatever the local order.
+__device__ inline int ss_order(int t, int s, const int *tv, const int *sv, int *pt, int *ps)
+{
+    pt[0] = ps[0] = 0; pt[1] = ps[1] = 1; pt[2] = ps[2] = 2;
+    if (t == s) return 3;
+    int ns = 0, kt[3] = {0, 0, 0}, ks[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l)
+            if (tv[k] == sv[l]) { kt[ns] = k; ks[ns] = l; ++ns; }
+    if (ns == 2) {
+        int k0 = kt[0], k1 = kt[1];
+        if ((k0 + 1) % 3 != k1) { int tmp = k0; k0 = k1; k1 = tmp; }
+        pt[0] = k0; pt[1] = k1; pt[2] = 3 - k0 - k1;
+        for (int l = 0; l < 3; ++l) {
+            if (sv[l] == tv[k0]) ps[0] = l;
+            if (sv[l] == tv[k1]) ps[1] = l;
+        }
+        ps[2] = 3 - ps[0] - ps[1];
+    } else if (ns == 1) {
+        for (int m = 0; m < 3; ++m) { pt[m] = (kt[0] + m) % 3; ps[m] = (ks[0] + m) % 3; }
+    }
+    return ns;
+}
+
+// One wavefront per ordered pair (t, s).  Lanes stride over the regions x N^4
+// Gauss points; each lane accumulates the 4 x 3 x 3 products in FP64, then a
+// butterfly reduction over the wavefront.  out[36 p + 9 op + 3 a + b], op =
+// V_L, K_L, V_Y, K_Y; a, b local vertex ids of t and s in stored order.
+template <int N>
+__global__ __launch_bounds__(256) void k_near_ss(int npair, const int32_t *__restrict__ pair_t,
+                                                 const int32_t *__restrict__ pair_s, const int32_t *__restrict__ tri,
+                                                 const double *__restrict__ xyz, const double *__restrict__ geo,
+                                                 double kappa, double *__restrict__ out)
+{
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= npair) return;
+    const int t = pair_t[wave], s = pair_s[wave];
+    int tv[3], sv[3];
+    for (int k = 0; k < 3; ++k) { tv[k] = tri[3 * t + k]; sv[k] = tri[3 * s + k]; }
+    int pt[3], ps[3];
+    const int cas = ss_order(t, s, tv, sv, pt, ps);
+    double P[3][3], Q[3][3];
+    for (int m = 0; m < 3; ++m)
+        for (int c = 0; c < 3; ++c) {
+            P[m][c] = xyz[3 * tv[pt[m]] + c];
+            Q[m][c] = xyz[3 * sv[ps[m]] + c];
+        }
+    const double *gs = geo + (size_t)s * kGeo;
+    const double nsx = gs[18], nsy = gs[19], nsz = gs[20];
+    const double at = geo[(size_t)t * kGeo + 21], as = gs[21];
+    double e1[3], e2[3], f1[3], f2[3];
+    for (int c = 0; c < 3; ++c) {
+        e1[c] = P[1][c] - P[0][c]; e2[c] = P[2][c] - P[1][c];
+        f1[c] = Q[1][c] - Q[0][c]; f2[c] = Q[2][c] - Q[1][c];
+    }
+    constexpr int N4 = N * N * N * N;
+    const int nreg = cas == 3 ? 6 : cas == 2 ? 5 : 2;
+    const int npts = nreg * N4;
+    double acc[36];
+#pragma unroll
+    for (int v = 0; v < 36; ++v) acc[v] = 0.0;
+    for (int idx = lane; idx < npts; idx += 64) {
+        const int r = idx / N4;
+        int rem = idx - r * N4;
+        const int i0 = rem / (N * N * N); rem -= i0 * N * N * N;
+        const int i1 = rem / (N * N); rem -= i1 * N * N;
+        const int i2 = rem / N;
+        const int i3 = rem - i2 * N;
+        const SSPoint m = ss_map(cas, r, c_gl_x[N][i0], c_gl_x[N][i1], c_gl_x[N][i2], c_gl_x[N][i3]);
+        const double W = c_gl_w[N][i0] * c_gl_w[N][i1] * c_gl_w[N][i2] * c_gl_w[N][i3] * m.jac;
+        double dx = (P[0][0] + m.u1 * e1[0] + m.u2 * e2[0]) - (Q[0][0] + m.v1 * f1[0] + m.v2 * f2[0]);
+        double dy = (P[0][1] + m.u1 * e1[1] + m.u2 * e2[1]) - (Q[0][1] + m.v1 * f1[1] + m.v2 * f2[1]);
+        double dz = (P[0][2] + m.u1 * e1[2] + m.u2 * e2[2]) - (Q[0][2] + m.v1 * f1[2] + m.v2 * f2[2]);
+        double r2 = dx * dx + dy * dy + dz * dz;
+        double rr = sqrt(r2);
+        double ri = 1.0 / rr;
+        double ek = exp(-kappa * rr);
+        double dn = dx * nsx + dy * nsy + dz * nsz;
+        double ri3 = ri * ri * ri;
+        double gL = ri, fL = dn * ri3, gY = ek * ri, fY = ek * (1.0 + kappa * rr) * dn * ri3;
+        const double lx[3] = {1.0 - m.u1, m.u1 - m.u2, m.u2};
+        const double ly[3] = {1.0 - m.v1, m.v1 - m.v2, m.v2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double wk = W * lx[k];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const double bb = wk * ly[l];
+                acc[3 * k + l] += bb * gL;
+                acc[9 + 3 * k + l] += bb * fL;
+                acc[18 + 3 * k + l] += bb * gY;
+                acc[27 + 3 * k + l] += bb * fY;
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 36; ++v) {
+        double x = acc[v];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        acc[v] = x;
+    }
+    if (lane == 0) {
+        const double scale = at * as / kPi;   // (2|t|)(2|s|) / (4 pi)
+        double *o = out + (size_t)wave * 36;
+#pragma unroll
+        for (int op = 0; op < 4; ++op)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int l = 0; l < 3; ++l) o[9 * op + 3 * pt[k] + ps[l]] = acc[9 * op + 3 * k + l] * scale;
+    }
+}
+
+static void launch_ss(DevMesh &d, int npair, const int32_t *pt, const int32_t *ps, double *out)
+{
+    if (npair == 0) return;
+    upload_gauss_tables();
+    dim3 grid((npair + 3) / 4), block(256);
+    const double kap = d.prm.kappa;
+    switch (d.opt.singular_order) {
+#define SS_CASE(n) \
+    case n: hipLaunchKernelGGL(k_near_ss<n>, grid, block, 0, d.stream, npair, pt, ps, d.tri, d.xyz, d.geo, kap, out); break;
+        SS_CASE(1) SS_CASE(2) SS_CASE(3) SS_CASE(4) SS_CASE(5) SS_CASE(6) SS_CASE(7) SS_CASE(8)
+#undef SS_CASE
+    default: fail(PB_E_INVALID_ARG, "singular_order must be in [1, 8]");
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_near_field(DevMesh &d) { launch_ss(d, (int)d.npair(), d.pair_t, d.pair_s, d.pairblk); }
+
+void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const int32_t *s_sorted, double *out)
+{
+    launch_ss(d, n, t_sorted, s_sorted, out);
+}
+
+// One thread per vertex row i: accumulates, in fixed order, every near pair's
+// contribution to the four blocks of row i.  Columns are found by binary search
+// in the row's sorted column list; the row is owned by one thread, so there is
+// no atomic and the result is deterministic.
+struct NearCoef {
+    int form;
+    double kappa, ceps;        // direct: eps_in / eps_out
+    double alpha, beta;        // Juffer: eps_out / eps_in, eps_in / eps_out
+};
+
+__global__ void k_near_assemble(int V, NearCoef cf, const int32_t *__restrict__ inc_ptr,
+                                const int32_t *__restrict__ inc_tk, const int32_t *__restrict__ pair_ptr,
+                                const int32_t *__restrict__ pair_s, const int32_t *__restrict__ pair_rev,
+                                const int32_t *__restrict__ tri, const int32_t *__restrict__ row_ptr,
+                                const int32_t *__restrict__ col, const double *__restrict__ geo,
+                                const double *__restrict__ blk, int64_t nnz, double *__restrict__ N)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    const int r0 = row_ptr[i], r1 = row_ptr[i + 1];
+    for (int sl = r0; sl < r1; ++sl) N[sl] = N[nnz + sl] = N[2 * nnz + sl] = N[3 * nnz + sl] = 0.0;
+    for (int e = inc_ptr[i]; e < inc_ptr[i + 1]; ++e) {
+        const int t = inc_tk[e] >> 2, k = inc_tk[e] & 3;
+        const double *gt = geo + (size_t)t * kGeo;
+        const double at = gt[21];
+        for (int p = pair_ptr[t]; p < pair_ptr[t + 1]; ++p) {
+            const int s = pair_s[p];
+            const double *B = blk + (size_t)p * 36;
+            const double *R = blk + (size_t)pair_rev[p] * 36;
+            const double *gs = geo + (size_t)s * kGeo;
+            double SL = 0.0, SY = 0.0;
+            for (int a = 0; a < 9; ++a) { SL += B[a]; SY += B[18 + a]; }
+            const double nn = gt[18] * gs[18] + gt[19] * gs[19] + gt[20] * gs[20];
+            for (int l = 0; l < 3; ++l) {
+                const int j = tri[3 * s + l];
+                int lo = r0, hi = r1 - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (col[mid] < j) lo = mid + 1; else hi = mid;
+                }
+                const double vL = B[3 * k + l], kL = B[9 + 3 * k + l];
+                const double vY = B[18 + 3 * k + l], kY = B[27 + 3 * k + l];
+                const double mss = (s == t) ? at / 12.0 * (k == l ? 2.0 : 1.0) : 0.0;
+                double n11, n12, n21, n22;
+                if (cf.form == PB_DIRECT_INT) {          // Eq. bie:dirichlet:int
+                    n11 = 0.5 * mss + kL;
+                    n12 = -vL;
+                    n21 = 0.5 * mss - kY;
+                    n22 = cf.ceps * vY;
+                } else {                                  // Eq. bie:juffer:int
+                    const double cc = gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
+                                      gt[24 + 3 * k] * gs[24 + 3 * l];
+                    const double dL = cc * SL;
+                    const double dY = cc * SY + cf.kappa * cf.kappa * nn * vY;
+                    const double tL = R[9 + 3 * l + k], tY = R[27 + 3 * l + k];   // T = K^T
+                    n11 = 0.5 * (1.0 + cf.alpha) * mss + kL - cf.alpha * kY;
+                    n12 = -vL + vY;
+                    n21 = -dL + dY;
+                    n22 = 0.5 * (1.0 + cf.beta) * mss - tL + cf.beta * tY;
+                }
+                N[lo] += n11;
+                N[nnz + lo] += n12;
+                N[2 * nnz + lo] += n21;
+                N[3 * nnz + lo] += n22;
+            }
+        }
+    }
+}
+
+// per-vertex analytic inverse of [[A11_ii, A12_ii], [A21_ii, A22_ii]]; every
+// diagonal entry comes from pairs sharing vertex i, i.e. from the near field.
+__global__ void k_block_diag(int V, int enabled, const int32_t *__restrict__ diag, const double *__restrict__ N,
+                             int64_t nnz, double *__restrict__ pinv)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    double *o = pinv + 4 * (size_t)i;
+    if (!enabled) { o[0] = 1.0; o[1] = 0.0; o[2] = 0.0; o[3] = 1.0; return; }
+    const int sl = diag[i];
+    const double a = N[sl], b = N[nnz + sl], c = N[2 * nnz + sl], e = N[3 * nnz + sl];
+    const double det = a * e - b * c;
+    o[0] = e / det; o[1] = -b / det; o[2] = -c / det; o[3] = a / det;
+}
+
+void launch_near_assemble(DevMesh &d)
+{
+    NearCoef cf;
+    cf.form = d.prm.formulation;
+    cf.kappa = d.prm.kappa;
+    cf.ceps = d.prm.eps_in / d.prm.eps_out;
+    cf.alpha = d.prm.eps_out / d.prm.eps_in;
+    cf.beta = d.prm.eps_in / d.prm.eps_out;
+    const int V = d.hm.V;
+    hipLaunchKernelGGL(k_near_assemble, dim3((V + 127) / 128), dim3(128), 0, d.stream, V, cf, d.inc_ptr, d.inc_tk,
+                       d.pair_ptr, d.pair_s, d.pair_rev, d.tri, d.row_ptr, d.col, d.geo, d.pairblk, d.nnz(), d.N);
+    hipLaunchKernelGGL(k_block_diag, dim3((V + 255) / 256), dim3(256), 0, d.stream, V,
+                       d.prm.preconditioner == PB_BLOCK_DIAG ? 1 : 0, d.diag_slot, d.N, d.nnz(), d.pinv);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace pbm

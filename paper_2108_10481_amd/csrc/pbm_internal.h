@@ -1,0 +1,179 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pbm.h"
+
+namespace pbm {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+struct Error {
+    pb_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(pb_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define HIPCHECK(x) ::pbm::hip_check((x), #x, __FILE__, __LINE__)
+
+// ------------------------------------------------------------- quadrature
+// 6-point degree-4 symmetric triangle rule (Dunavant 1985, symmetric rule of
+// degree 4): orbits (1-2a, a, a) with weight wa and (1-2b, b, b) with weight
+// wb, weights relative to the triangle area (they sum to 1).
+constexpr double kRuleA = 0.445948490915964886318329253883;
+constexpr double kRuleB = 0.0915762135097707434595714634022;
+constexpr double kRuleWA = 0.223381589678011465695007008433;
+constexpr double kRuleWB = 0.1099517436553218676383263249;
+// barycentric coordinate k of rule point p, and its weight
+__host__ __device__ constexpr double rule_bary(int p, int k)
+{
+    return p < 3 ? (k == p ? 1.0 - 2.0 * kRuleA : kRuleA) : (k == p - 3 ? 1.0 - 2.0 * kRuleB : kRuleB);
+}
+__host__ __device__ constexpr double rule_w(int p) { return p < 3 ? kRuleWA : kRuleWB; }
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kInv4Pi = 1.0 / (4.0 * kPi);
+// Gauss-Legendre on [0,1] (Golub-Welsch: eigenvalues of the Jacobi matrix).
+void gauss_legendre01(int n, double *x, double *w);
+
+// ----------------------------------------------------------- host mesh prep
+// Everything here is index work on the host: validation, a Morton ordering
+// of triangles, vertex -> triangle incidence, the near-pair lists (ordered
+// pairs of triangles sharing >= 1 vertex) and the sparsity of the near-field
+// vertex blocks.
+struct HostMesh {
+    int V = 0, T = 0;
+    std::vector<double> xyz;          // V x 3
+    std::vector<int32_t> tri;         // T x 3, sorted triangle order, input local order
+    std::vector<int32_t> perm;        // sorted position -> input triangle id
+    std::vector<int32_t> iperm;       // input triangle id -> sorted position
+    std::vector<int32_t> inc_ptr;     // V + 1
+    std::vector<int32_t> inc_tk;      // 4 t + k for each incidence (t sorted id)
+    std::vector<int32_t> pair_ptr;    // T + 1 (sorted t)
+    std::vector<int32_t> pair_s;      // sorted s, ascending within a row
+    std::vector<int32_t> pair_rev;    // index of the reversed pair (s, t)
+    std::vector<int32_t> row_ptr;     // V + 1, near vertex CSR
+    std::vector<int32_t> col;         // columns, ascending within a row
+    std::vector<int32_t> diag_slot;   // V: slot of (i, i)
+};
+void build_host_mesh(const pb_mesh *m, HostMesh &hm);
+
+// ------------------------------------------------------------ device state
+// Source / target records of the far-field kernels, one per triangle:
+//   static  (kStat reals): 6 quadrature points x 3, normal 3, y_q . n 6, ids 3 (bit-cast)
+//   dynamic (kDyn reals) : b1[6] = w_q|s| u1(y_q), b2[6] = w_q|s| u2(y_q), C[3] = |s| curl u1|_s
+constexpr int kStat = 32;
+constexpr int kDyn = 16;
+// per-triangle FP64 geometry: pts 18, normal 3, area 1, curl 9 -> 31, padded
+constexpr int kGeo = 32;
+
+struct Params {
+    double eps_in, eps_out, kappa;
+    int formulation, preconditioner, precision, operator_mode;
+};
+
+struct Profiler {
+    bool enabled = false;
+    std::vector<hipEvent_t> ev;   // pairs
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+struct Dense;   // assembled far field (k_dense.hip)
+
+struct Krylov {
+    double *basis = nullptr;   // cap x n Arnoldi vectors
+    int cap = 0;
+    double *kbuf = nullptr;    // dot-product results copied to the host each iteration
+    double *y = nullptr;       // least-squares coefficients
+};
+
+struct DevMesh {
+    HostMesh hm;
+    Params prm;
+    pb_options opt;
+    int S = 1;                     // far-field source chunks
+    hipStream_t stream = nullptr;
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+
+    // geometry (sorted triangle order)
+    double *xyz = nullptr;         // V x 3
+    int32_t *tri = nullptr;        // T x 3
+    double *geo = nullptr;         // T x kGeo
+    double *stat64 = nullptr;      // T x kStat
+    float *stat32 = nullptr;       // T x kStat
+    int32_t *inc_ptr = nullptr, *inc_tk = nullptr;
+    int32_t *pair_ptr = nullptr, *pair_s = nullptr, *pair_rev = nullptr, *pair_t = nullptr;
+    int32_t *row_ptr = nullptr, *col = nullptr, *diag_slot = nullptr;
+    double *pairblk = nullptr;     // npair x 36
+    double *N = nullptr;           // 4 x nnz near blocks (N11, N12, N21, N22), mass included
+    double *pinv = nullptr;        // V x 4
+    // matvec workspaces
+    double *dyn64 = nullptr;       // T x kDyn
+    float *dyn32 = nullptr;        // T x kDyn
+    void *part = nullptr;          // S x T x 16 reals
+    double *triout = nullptr;      // T x 6
+    double *xtmp = nullptr;        // 2V
+    double *ytmp = nullptr;        // 2V
+    double *ztmp = nullptr;        // 2V
+    double *yfar = nullptr;        // 2V far-field product (assembled mode)
+    double *u = nullptr;           // 2V solution
+    Krylov kry;
+    double t_setup = 0.0;
+    // charges workspace
+    double *qbuf = nullptr;        // 7 x qcap: SoA x, y, z, q then AoS xyz
+    int qcap = 0;
+    double *fpts = nullptr;        // 2 x T x 6 (RHS point values)
+    double *red = nullptr;         // reduction scratch
+    int redcap = 0;
+    Dense *dense = nullptr;
+
+    Profiler prof;
+    int64_t npair() const { return (int64_t)hm.pair_s.size(); }
+    int64_t nnz() const { return (int64_t)hm.col.size(); }
+    void *alloc(size_t n);
+    ~DevMesh();
+};
+
+// kernels / launchers (k_*.hip)
+void launch_geometry(DevMesh &d);
+void launch_near_field(DevMesh &d);
+void launch_near_assemble(DevMesh &d);
+void launch_source_prep(DevMesh &d, const double *x, bool fp32);
+void launch_far(DevMesh &d, bool fp32);
+void launch_far_finish(DevMesh &d, bool fp32);
+// use_far: 0 = near only, 1 = far from per-triangle outputs, 2 = far from d.yfar
+void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far);
+void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream_t s);
+void launch_rhs(DevMesh &d, int nq, const double *qbuf, double *b);
+void launch_reaction(DevMesh &d, int nq, const double *qpts, double *out);
+void launch_inside_test(DevMesh &d, int nq, const double *qbuf, double *out);
+void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const int32_t *s_sorted,
+                               double *out);
+int choose_chunks(int T);
+int reduction_chunks(int T);
+pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res);
+
+// assembled far field and mixed precision (k_dense.hip)
+bool dense_fits(const DevMesh &d);
+void build_dense(DevMesh &d);
+void destroy_dense(DevMesh &d);
+void dense_apply(DevMesh &d, const double *x, double *yfar);
+int mixed_refinement_solve(DevMesh &d, const double *b, const double *pb, double *u, double *est, int *outer);
+pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result *out);
+
+// Krylov kernels (k_krylov.hip)
+void kr_dots(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *w, double *out);
+void kr_update(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *h, double *w,
+               double sign);
+void kr_scale_copy(hipStream_t s, int n, const double *x, double a, double *y);
+void kr_axpy(hipStream_t s, int n, double a, const double *x, double *y);
+void kr_combine(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *y, double *x);
+void kr_precond(hipStream_t s, int V, const double *pinv, const double *x, double *y);
+
+}  // namespace pbm

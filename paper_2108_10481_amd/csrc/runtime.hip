@@ -1,0 +1,622 @@
+// Host runtime and C ABI: mesh handles, operator application, GMRES
+// (Preconditioning; tolerance 1e-5 without restart in the Results), right-hand
+// side (Eq. sources), reaction potential and solvation energy (Eqs.
+// phireac_bie, dG).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "pbm_internal.h"
+
+namespace pbm {
+
+// e^2 / (4 pi eps0 angstrom) in kcal/mol; potentials here carry 1/(4 pi).
+constexpr double kCoulombKcal = 332.0637;
+constexpr double kEnergyC = 4.0 * kPi * kCoulombKcal;
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+void fail(pb_status code, const std::string &msg) { throw Error{code, msg}; }
+void hip_check(hipError_t e, const char *what, const char *file, int line)
+{
+    if (e == hipSuccess) return;
+    std::string m = std::string(what) + " failed: " + hipGetErrorString(e) + " (" + file + ":" + std::to_string(line) + ")";
+    throw Error{e == hipErrorOutOfMemory ? PB_E_NOMEM : PB_E_DEVICE, m};
+}
+
+void *DevMesh::alloc(size_t n)
+{
+    void *p = nullptr;
+    n = std::max<size_t>(n, 256);
+    if (opt.memory_budget && bytes + n > opt.memory_budget)
+        fail(PB_E_NOMEM, "device memory budget of the handle exceeded");
+    HIPCHECK(hipMalloc(&p, n));
+    allocs.push_back(p);
+    bytes += n;
+    return p;
+}
+
+DevMesh::~DevMesh()
+{
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (hipEvent_t e : prof.ev) (void)hipEventDestroy(e);
+    destroy_dense(*this);
+    for (void *p : allocs) (void)hipFree(p);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+template <typename T>
+static T *upload(DevMesh &d, const std::vector<T> &v)
+{
+    T *p = (T *)d.alloc(sizeof(T) * v.size());
+    if (!v.empty()) HIPCHECK(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, d.stream));
+    return p;
+}
+
+static double now()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static void check_options(const pb_options *o)
+{
+    if (!o) fail(PB_E_INVALID_ARG, "options must not be NULL");
+    if (!(o->eps_in > 0) || !(o->eps_out > 0) || !(o->kappa >= 0) || !std::isfinite(o->kappa))
+        fail(PB_E_INVALID_ARG, "eps_in, eps_out must be > 0 and kappa >= 0");
+    if (o->formulation != PB_DIRECT_INT && o->formulation != PB_JUFFER) fail(PB_E_INVALID_ARG, "unknown formulation");
+    if (o->preconditioner != PB_BLOCK_DIAG && o->preconditioner != PB_PREC_NONE)
+        fail(PB_E_INVALID_ARG, "unknown preconditioner");
+    if (o->precision < PB_FP64 || o->precision > PB_MIXED_FP16) fail(PB_E_INVALID_ARG, "unknown precision");
+    if (o->operator_mode < PB_MATRIX_FREE || o->operator_mode > PB_AUTO) fail(PB_E_INVALID_ARG, "unknown operator mode");
+    if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
+    if (o->singular_order < 1 || o->singular_order > 8) fail(PB_E_INVALID_ARG, "singular_order must be in [1, 8]");
+    if (o->source_chunks < 0 || o->source_chunks > 1024) fail(PB_E_INVALID_ARG, "source_chunks must be in [0, 1024]");
+}
+
+static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
+{
+    check_options(opt);
+    const double t0 = now();
+    std::unique_ptr<DevMesh> d(new DevMesh());
+    d->opt = *opt;
+    d->prm = {opt->eps_in, opt->eps_out, opt->kappa, opt->formulation, opt->preconditioner, opt->precision,
+              opt->operator_mode};
+    build_host_mesh(mesh, d->hm);   // validation happens before any device call
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(PB_E_DEVICE, "no HIP device available");
+    HIPCHECK(hipSetDevice(0));
+    HIPCHECK(hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking));
+    const HostMesh &hm = d->hm;
+    const int V = hm.V, T = hm.T;
+    d->S = opt->source_chunks > 0 ? std::min(opt->source_chunks, T) : choose_chunks(T);
+
+    d->xyz = upload(*d, hm.xyz);
+    d->tri = upload(*d, hm.tri);
+    d->inc_ptr = upload(*d, hm.inc_ptr);
+    d->inc_tk = upload(*d, hm.inc_tk);
+    d->pair_ptr = upload(*d, hm.pair_ptr);
+    d->pair_s = upload(*d, hm.pair_s);
+    d->pair_rev = upload(*d, hm.pair_rev);
+    {
+        std::vector<int32_t> pt(hm.pair_s.size());
+        for (int t = 0; t < T; ++t)
+            for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) pt[p] = t;
+        d->pair_t = upload(*d, pt);
+    }
+    d->row_ptr = upload(*d, hm.row_ptr);
+    d->col = upload(*d, hm.col);
+    d->diag_slot = upload(*d, hm.diag_slot);
+    d->geo = (double *)d->alloc(sizeof(double) * kGeo * T);
+    d->stat64 = (double *)d->alloc(sizeof(double) * kStat * T);
+    d->stat32 = (float *)d->alloc(sizeof(float) * kStat * T);
+    d->pairblk = (double *)d->alloc(sizeof(double) * 36 * d->npair());
+    d->N = (double *)d->alloc(sizeof(double) * 4 * d->nnz());
+    d->pinv = (double *)d->alloc(sizeof(double) * 4 * V);
+    d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
+    d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
+    d->part = d->alloc(sizeof(double) * 16 * (size_t)d->S * T);
+    d->triout = (double *)d->alloc(sizeof(double) * 6 * T);
+    d->fpts = (double *)d->alloc(sizeof(double) * 12 * T);
+    d->xtmp = (double *)d->alloc(sizeof(double) * 2 * V);
+    d->ytmp = (double *)d->alloc(sizeof(double) * 2 * V);
+    d->ztmp = (double *)d->alloc(sizeof(double) * 2 * V);
+    d->yfar = (double *)d->alloc(sizeof(double) * 2 * V);
+
+    launch_geometry(*d);
+    launch_near_field(*d);
+    launch_near_assemble(*d);
+    const bool want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
+                            (opt->operator_mode == PB_AUTO && dense_fits(*d));
+    if (want_dense) build_dense(*d);
+    HIPCHECK(hipStreamSynchronize(d->stream));
+    d->t_setup = now() - t0;
+    return d.release();
+}
+
+// y = A x (or P^-1 A x) on device vectors, on stream s of the handle.
+void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream_t s)
+{
+    hipStream_t keep = d.stream;
+    if (s) d.stream = s;
+    const bool near_only = flags & PB_APPLY_NEAR_ONLY;
+    int use_far = 0;
+    if (!near_only) {
+        if (d.dense) {
+            dense_apply(d, x, d.yfar);
+            use_far = 2;
+        } else {
+            const bool fp32 = d.prm.precision == PB_FP32;
+            launch_source_prep(d, x, fp32);
+            launch_far(d, fp32);
+            launch_far_finish(d, fp32);
+            use_far = 1;
+        }
+    }
+    launch_gather(d, x, y, flags, use_far);
+    d.stream = keep;
+}
+
+// ------------------------------------------------------------------- GMRES
+
+static void ensure_krylov(DevMesh &d, int m)
+{
+    const int n = 2 * d.hm.V;
+    if (d.kry.cap >= m + 1) return;
+    d.kry.basis = (double *)d.alloc(sizeof(double) * (size_t)n * (m + 1));
+    d.kry.kbuf = (double *)d.alloc(sizeof(double) * (2 * (m + 2) + 2));
+    d.kry.y = (double *)d.alloc(sizeof(double) * (m + 1));
+    d.kry.cap = m + 1;
+}
+
+// Unrestarted GMRES from x0 = 0 on P^-1 A u = pb (pb already preconditioned):
+// classical Gram-Schmidt applied twice (CGS2) for the Arnoldi step, Givens
+// rotations on the host.  Returns the number of iterations; *est receives the
+// final residual estimate relative to |pb|.
+int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est)
+{
+    const int n = 2 * d.hm.V;
+    const int m = std::min(max_iter, n);
+    ensure_krylov(d, m);
+    double *Vb = d.kry.basis, *kb = d.kry.kbuf;
+    hipStream_t s = d.stream;
+    kr_dots(s, n, 1, pb, n, pb, kb);
+    double beta2 = 0.0;
+    HIPCHECK(hipMemcpyAsync(&beta2, kb, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double beta = std::sqrt(beta2);
+    if (!(beta > 0.0)) {
+        HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+        *est = 0.0;
+        return 0;
+    }
+    kr_scale_copy(s, n, pb, 1.0 / beta, Vb);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), hb(2 * (m + 1) + 1);
+    g[0] = beta;
+    int k = 0;
+    double res = beta;
+    for (int j = 0; j < m; ++j) {
+        double *w = Vb + (size_t)(j + 1) * n;
+        apply_operator(d, Vb + (size_t)j * n, w, PB_APPLY_PRECOND, nullptr);
+        double *h1 = kb, *h2 = kb + (j + 1), *nr = kb + 2 * (j + 1);
+        kr_dots(s, n, j + 1, Vb, n, w, h1);
+        kr_update(s, n, j + 1, Vb, n, h1, w, -1.0);
+        kr_dots(s, n, j + 1, Vb, n, w, h2);
+        kr_update(s, n, j + 1, Vb, n, h2, w, -1.0);
+        kr_dots(s, n, 1, w, n, w, nr);
+        HIPCHECK(hipMemcpyAsync(hb.data(), kb, sizeof(double) * (2 * (j + 1) + 1), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        double *col = &H[(size_t)j * (m + 1)];
+        for (int i = 0; i <= j; ++i) col[i] = hb[i] + hb[j + 1 + i];
+        col[j + 1] = std::sqrt(std::max(hb[2 * (j + 1)], 0.0));
+        if (col[j + 1] > 0.0) kr_scale_copy(s, n, w, 1.0 / col[j + 1], w);
+        for (int i = 0; i < j; ++i) {
+            const double a = cs[i] * col[i] + sn[i] * col[i + 1];
+            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+            col[i] = a;
+        }
+        const double den = std::hypot(col[j], col[j + 1]);
+        cs[j] = col[j] / den;
+        sn[j] = col[j + 1] / den;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        k = j + 1;
+        res = std::fabs(g[j + 1]);
+        if (res <= tol * beta || !(den > 0.0)) break;
+    }
+    std::vector<double> y(k);
+    for (int i = k - 1; i >= 0; --i) {
+        double a = g[i];
+        for (int l = i + 1; l < k; ++l) a -= H[(size_t)l * (m + 1) + i] * y[l];
+        y[i] = a / H[(size_t)i * (m + 1) + i];
+    }
+    HIPCHECK(hipMemcpyAsync(d.kry.y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    kr_combine(s, n, k, Vb, n, d.kry.y, x);
+    *est = res / beta;
+    return k;
+}
+
+// ------------------------------------------------------------ charges, dG
+static void upload_charges(DevMesh &d, const pb_charges *c)
+{
+    if (!c || c->n < 1 || !c->xyz || !c->q) fail(PB_E_INVALID_ARG, "charges must hold n >= 1 points");
+    const int nq = c->n;
+    for (int i = 0; i < 3 * nq; ++i)
+        if (!std::isfinite(c->xyz[i])) fail(PB_E_INVALID_ARG, "charge positions must be finite");
+    for (int i = 0; i < nq; ++i)
+        if (!std::isfinite(c->q[i])) fail(PB_E_INVALID_ARG, "charge values must be finite");
+    if (nq > d.qcap) {
+        d.qbuf = (double *)d.alloc(sizeof(double) * 7 * (size_t)nq);
+        d.qcap = nq;
+    }
+    std::vector<double> h(7 * (size_t)nq);
+    for (int i = 0; i < nq; ++i) {
+        for (int c3 = 0; c3 < 3; ++c3) {
+            h[(size_t)c3 * nq + i] = c->xyz[3 * i + c3];
+            h[(size_t)4 * nq + 3 * i + c3] = c->xyz[3 * i + c3];
+        }
+        h[(size_t)3 * nq + i] = c->q[i];
+    }
+    HIPCHECK(hipMemcpyAsync(d.qbuf, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, d.stream));
+}
+
+static double *reduction_buffer(DevMesh &d, int npts)
+{
+    const int need = npts * reduction_chunks(d.hm.T);
+    if (need > d.redcap) {
+        d.red = (double *)d.alloc(sizeof(double) * need);
+        d.redcap = need;
+    }
+    return d.red;
+}
+
+static void check_inside(DevMesh &d, int nq)
+{
+    const int C = reduction_chunks(d.hm.T);
+    double *part = reduction_buffer(d, nq);
+    launch_inside_test(d, nq, d.qbuf + 4 * (size_t)nq, part);
+    std::vector<double> h((size_t)nq * C);
+    HIPCHECK(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    for (int k = 0; k < nq; ++k) {
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) s += h[(size_t)k * C + c];
+        if (!(s > 2.0 * kPi)) fail(PB_E_CHARGES, "charge " + std::to_string(k) + " lies outside the surface");
+    }
+}
+
+// phi_reac at npts device points (AoS) from the device traces u (2V)
+static void reaction_potential(DevMesh &d, const double *u, int npts, const double *pts_dev, double *out_host)
+{
+    const int C = reduction_chunks(d.hm.T);
+    launch_source_prep(d, u, false);
+    double *part = reduction_buffer(d, npts);
+    launch_reaction(d, npts, pts_dev, part);
+    std::vector<double> h((size_t)npts * C);
+    HIPCHECK(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    for (int k = 0; k < npts; ++k) {
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) s += h[(size_t)k * C + c];
+        out_host[k] = s * kInv4Pi;
+    }
+}
+
+static void rhs_device(DevMesh &d, int nq, double *b)
+{
+    launch_rhs(d, nq, d.qbuf, b);
+}
+
+pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
+{
+    if (!res) fail(PB_E_INVALID_ARG, "result must not be NULL");
+    const int V = d.hm.V, n = 2 * V;
+    double t0 = now();
+    upload_charges(d, ch);
+    const int nq = ch->n;
+    check_inside(d, nq);
+    double *b = d.xtmp, *pb = d.ytmp;
+    rhs_device(d, nq, b);
+    if (d.prm.formulation == PB_DIRECT_INT) HIPCHECK(hipMemsetAsync(b + V, 0, sizeof(double) * V, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    double t1 = now();
+    kr_precond(d.stream, V, d.pinv, b, pb);
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    double t2 = now();
+    if (!d.u) d.u = (double *)d.alloc(sizeof(double) * n);
+    double est = 0.0;
+    int outer = 1, its;
+    if (d.prm.precision >= PB_MIXED_BF16)
+        its = mixed_refinement_solve(d, b, pb, d.u, &est, &outer);
+    else
+        its = gmres(d, pb, d.u, d.opt.tol, d.opt.max_iter, &est);
+    // recomputed preconditioned residual
+    apply_operator(d, d.u, d.ztmp, PB_APPLY_PRECOND, nullptr);
+    kr_axpy(d.stream, n, -1.0, pb, d.ztmp);
+    double *kb = d.kry.kbuf;
+    kr_dots(d.stream, n, 1, d.ztmp, n, d.ztmp, kb);
+    kr_dots(d.stream, n, 1, pb, n, pb, kb + 1);
+    double rr[2];
+    HIPCHECK(hipMemcpyAsync(rr, kb, sizeof(rr), hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    double t3 = now();
+    std::vector<double> pr(nq);
+    reaction_potential(d, d.u, nq, d.qbuf + 4 * (size_t)nq, pr.data());
+    double e = 0.0;
+    for (int k = 0; k < nq; ++k) e += ch->q[k] * pr[k];
+    res->dG_kcal = 0.5 * kEnergyC * e;
+    if (res->phi) HIPCHECK(hipMemcpyAsync(res->phi, d.u, sizeof(double) * V, hipMemcpyDeviceToHost, d.stream));
+    if (res->dphi) HIPCHECK(hipMemcpyAsync(res->dphi, d.u + V, sizeof(double) * V, hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    double t4 = now();
+    res->iterations = its;
+    res->outer_iterations = outer;
+    res->rel_residual = rr[1] > 0 ? std::sqrt(std::max(rr[0], 0.0) / rr[1]) : 0.0;
+    res->t_setup = d.t_setup;
+    res->t_rhs = t1 - t0;
+    res->t_prec = t2 - t1;
+    res->t_gmres = t3 - t2;
+    res->t_dG = t4 - t3;
+    res->device_bytes = d.bytes;
+    return res->rel_residual <= d.opt.tol * 1.0000001 ? PB_OK : PB_NOT_CONVERGED;
+}
+
+}  // namespace pbm
+
+// =================================================================== C ABI
+using namespace pbm;
+
+struct pb_mesh_handle {
+    DevMesh *d;
+};
+
+#define PB_TRY try {
+#define PB_CATCH                                                         \
+    }                                                                    \
+    catch (const Error &e) {                                             \
+        set_error(e.msg);                                                \
+        return e.code;                                                   \
+    }                                                                    \
+    catch (const std::bad_alloc &) {                                     \
+        set_error("host out of memory");                                 \
+        return PB_E_NOMEM;                                               \
+    }                                                                    \
+    catch (...) {                                                        \
+        set_error("unexpected internal error");                          \
+        return PB_E_DEVICE;                                              \
+    }
+
+extern "C" {
+
+void pb_default_options(pb_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->eps_in = 4.0;
+    o->eps_out = 80.0;
+    o->kappa = 0.125;
+    o->formulation = PB_DIRECT_INT;
+    o->preconditioner = PB_BLOCK_DIAG;
+    o->precision = PB_FP64;
+    o->operator_mode = PB_MATRIX_FREE;
+    o->tol = 1e-5;
+    o->max_iter = 1000;
+    o->singular_order = 4;
+    o->source_chunks = 0;
+    o->inner_max_iter = 200;
+    o->inner_tol = 1e-3;
+    o->memory_budget = 0;
+}
+
+const char *pb_last_error(void) { return g_err.c_str(); }
+
+int32_t pb_device_count(void)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+pb_status pb_mesh_create(const pb_mesh *mesh, const pb_options *opt, pb_mesh_handle **out)
+{
+    PB_TRY
+    if (!out) fail(PB_E_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    DevMesh *d = create_mesh(mesh, opt);
+    *out = new pb_mesh_handle{d};
+    set_error("");
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_destroy(pb_mesh_handle *h)
+{
+    PB_TRY
+    if (!h) return PB_OK;
+    delete h->d;
+    delete h;
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_get_info(const pb_mesh_handle *h, pb_mesh_info *info)
+{
+    PB_TRY
+    if (!h || !info) fail(PB_E_INVALID_ARG, "NULL argument");
+    const DevMesh &d = *h->d;
+    info->n_vertices = d.hm.V;
+    info->n_triangles = d.hm.T;
+    info->n_near_pairs = d.npair();
+    info->near_nnz = d.nnz();
+    info->source_chunks = d.S;
+    info->assembled = d.dense ? 1 : 0;
+    info->device_bytes = d.bytes;
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result *result)
+{
+    PB_TRY
+    if (!h) fail(PB_E_INVALID_ARG, "NULL handle");
+    return solve_on_mesh(*h->d, charges, result);
+    PB_CATCH
+}
+
+pb_status pb_solve(const pb_mesh *mesh, const pb_charges *charges, const pb_options *opt, pb_result *result)
+{
+    PB_TRY
+    std::unique_ptr<DevMesh> d(create_mesh(mesh, opt));
+    return solve_on_mesh(*d, charges, result);
+    PB_CATCH
+}
+
+pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *sets, pb_result *out)
+{
+    PB_TRY
+    if (!h || n_sets < 1 || !sets || !out) fail(PB_E_INVALID_ARG, "bad pb_solve_multi arguments");
+    return solve_multi(*h->d, n_sets, sets, out);
+    PB_CATCH
+}
+
+pb_status pb_mesh_apply(pb_mesh_handle *h, const double *x, double *y, int32_t flags)
+{
+    PB_TRY
+    if (!h || !x || !y) fail(PB_E_INVALID_ARG, "NULL argument");
+    DevMesh &d = *h->d;
+    const int n = 2 * d.hm.V;
+    HIPCHECK(hipMemcpyAsync(d.xtmp, x, sizeof(double) * n, hipMemcpyHostToDevice, d.stream));
+    apply_operator(d, d.xtmp, d.ytmp, flags, nullptr);
+    HIPCHECK(hipMemcpyAsync(y, d.ytmp, sizeof(double) * n, hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_apply_device(pb_mesh_handle *h, const double *x, double *y, int32_t flags, void *stream)
+{
+    PB_TRY
+    if (!h || !x || !y) fail(PB_E_INVALID_ARG, "NULL argument");
+    apply_operator(*h->d, x, y, flags, (hipStream_t)stream);
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_rhs(pb_mesh_handle *h, const pb_charges *charges, double *b)
+{
+    PB_TRY
+    if (!h || !b) fail(PB_E_INVALID_ARG, "NULL argument");
+    DevMesh &d = *h->d;
+    upload_charges(d, charges);
+    rhs_device(d, charges->n, d.xtmp);
+    HIPCHECK(hipMemcpyAsync(b, d.xtmp, sizeof(double) * 2 * d.hm.V, hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_reaction_potential(pb_mesh_handle *h, const double *phi, const double *dphi, int32_t npts,
+                                     const double *pts, double *out)
+{
+    PB_TRY
+    if (!h || !phi || !dphi || !pts || !out || npts < 1) fail(PB_E_INVALID_ARG, "bad arguments");
+    DevMesh &d = *h->d;
+    const int V = d.hm.V;
+    HIPCHECK(hipMemcpyAsync(d.xtmp, phi, sizeof(double) * V, hipMemcpyHostToDevice, d.stream));
+    HIPCHECK(hipMemcpyAsync(d.xtmp + V, dphi, sizeof(double) * V, hipMemcpyHostToDevice, d.stream));
+    std::vector<double> q(npts, 0.0);
+    pb_charges c{npts, pts, q.data()};
+    upload_charges(d, &c);
+    reaction_potential(d, d.xtmp, npts, d.qbuf + 4 * (size_t)npts, out);
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_near_blocks(pb_mesh_handle *h, int32_t n, const int32_t *t, const int32_t *s, double *out)
+{
+    PB_TRY
+    if (!h || !t || !s || !out || n < 1) fail(PB_E_INVALID_ARG, "bad arguments");
+    DevMesh &d = *h->d;
+    const HostMesh &hm = d.hm;
+    std::vector<int32_t> ts(n), ss(n);
+    for (int k = 0; k < n; ++k) {
+        if (t[k] < 0 || t[k] >= hm.T || s[k] < 0 || s[k] >= hm.T) fail(PB_E_INVALID_ARG, "triangle id out of range");
+        ts[k] = hm.iperm[t[k]];
+        ss[k] = hm.iperm[s[k]];
+        int shared = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) shared += hm.tri[3 * ts[k] + a] == hm.tri[3 * ss[k] + b];
+        if (shared == 0) fail(PB_E_INVALID_ARG, "pair does not share a vertex");
+    }
+    int32_t *dt = (int32_t *)d.alloc(sizeof(int32_t) * n), *ds = (int32_t *)d.alloc(sizeof(int32_t) * n);
+    double *o = (double *)d.alloc(sizeof(double) * 36 * n);
+    HIPCHECK(hipMemcpyAsync(dt, ts.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, d.stream));
+    HIPCHECK(hipMemcpyAsync(ds, ss.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, d.stream));
+    launch_pair_blocks_subset(d, n, dt, ds, o);
+    HIPCHECK(hipMemcpyAsync(out, o, sizeof(double) * 36 * n, hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_preconditioner(pb_mesh_handle *h, double *out)
+{
+    PB_TRY
+    if (!h || !out) fail(PB_E_INVALID_ARG, "NULL argument");
+    DevMesh &d = *h->d;
+    HIPCHECK(hipMemcpyAsync(out, d.pinv, sizeof(double) * 4 * d.hm.V, hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_profile(pb_mesh_handle *h, int32_t enable)
+{
+    PB_TRY
+    if (!h) fail(PB_E_INVALID_ARG, "NULL handle");
+    Profiler &p = h->d->prof;
+    HIPCHECK(hipStreamSynchronize(h->d->stream));
+    for (hipEvent_t e : p.ev) (void)hipEventDestroy(e);
+    p.ev.clear();
+    p.launches = 0;
+    p.total_ms = 0.0;
+    p.enabled = enable != 0;
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launches, double *total_ms)
+{
+    PB_TRY
+    if (!h || !launches || !total_ms || kind != 0) fail(PB_E_INVALID_ARG, "bad arguments");
+    Profiler &p = h->d->prof;
+    HIPCHECK(hipStreamSynchronize(h->d->stream));
+    for (size_t i = 0; i + 1 < p.ev.size(); i += 2) {
+        float ms = 0.0f;
+        HIPCHECK(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+        p.total_ms += ms;
+        p.launches += 1;
+        (void)hipEventDestroy(p.ev[i]);
+        (void)hipEventDestroy(p.ev[i + 1]);
+    }
+    p.ev.clear();
+    *launches = p.launches;
+    *total_ms = p.total_ms;
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_synchronize(pb_mesh_handle *h)
+{
+    PB_TRY
+    if (!h) fail(PB_E_INVALID_ARG, "NULL handle");
+    HIPCHECK(hipStreamSynchronize(h->d->stream));
+    return PB_OK;
+    PB_CATCH
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (from the arithmetic):
+  * FP64 operator products, source projections, reaction potentials,
+    preconditioner blocks: 1e-12 relative (2-norm).  Both sides evaluate the
+    same quadrature sums in FP64; only the summation order differs.
+  * Near-field Sauter-Schwab blocks: 1e-13 relative to the block's largest entry.
+  * FP32 far-field evaluation: 1e-5 relative on the operator product.
+  * Delta G: 1e-6 relative in FP64 at the solver tolerance 1e-5 (the GPU and
+    the oracle run the same Krylov iteration; rounding differences stay far
+    below the stopping tolerance), 1e-4 in reduced precision.
+Sizes: small meshes span several 256-triangle tiles with a ragged tail
+(T = 720, 980, 1280); the full-size sphere (20480 triangles) is checked on
+sampled rows the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+pbm = pytest.importorskip("paper_2108_10481_amd")
+
+
+def _opts(form=0, precision=0, **kw):
+    return pbm.pb_default_options(formulation=form, precision=precision, **kw)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def meshes():
+    m1 = inputs.icosphere(6, 2.0)                 # T = 720
+    m2, _ = inputs.star_surface(5, 7, 6.0)        # T = 980
+    return {"sphere6": m1, "star7": m2}
+
+
+@pytest.fixture(scope="module")
+def dense_systems(meshes):
+    out = {}
+    for name, m in meshes.items():
+        for form in (0, 1):
+            out[(name, form)] = oracle.system_matrix(m, 4.0, 80.0, 0.125, form)
+    return out
+
+
+def test_library_sees_gpu():
+    assert pbm.pb_device_count() >= 1
+
+
+@pytest.mark.parametrize("name", ["sphere6", "star7"])
+def test_near_field_blocks(meshes, name):
+    """Sauter-Schwab local blocks of coincident, edge and vertex pairs."""
+    m = meshes[name]
+    tri = m.tri
+    ts, ss = [], []
+    for t in (0, 17, 311, m.n_triangles - 1):
+        for s in range(m.n_triangles):
+            if len(set(tri[t]) & set(tri[s])) > 0:
+                ts.append(t)
+                ss.append(s)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts()) as h:
+        got = pbm.pb_mesh_near_blocks(h, ts, ss)
+    for k, (t, s) in enumerate(zip(ts, ss)):
+        VL, KL, _ = oracle.pair_block(m, t, s, 0.0, 4)
+        VY, KY, _ = oracle.pair_block(m, t, s, 0.125, 4)
+        ref = np.stack([VL, KL, VY, KY])
+        scale = np.abs(ref[0]).max()
+        assert np.abs(got[k] - ref).max() < 1e-13 * scale, (t, s)
+
+
+@pytest.mark.parametrize("name", ["sphere6", "star7"])
+@pytest.mark.parametrize("form", [0, 1])
+def test_operator_fp64(meshes, dense_systems, name, form):
+    m = meshes[name]
+    A = dense_systems[(name, form)]
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(2 * m.n_vertices)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form)) as h:
+        y = pbm.pb_mesh_apply(h, x)
+        y2 = pbm.pb_mesh_apply(h, x)
+        yf = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_FAR_ONLY)
+        yn = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_NEAR_ONLY)
+        yp = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+        pinv = pbm.pb_mesh_preconditioner(h)
+    ref = A @ x
+    assert _rel(y, ref) < 1e-12
+    assert np.array_equal(y, y2), "operator product must be deterministic"
+    assert _rel(yf + yn, ref) < 1e-12
+    inv = oracle.block_diagonal_inverse(A, m.n_vertices)
+    assert np.abs(pinv - inv).max() < 1e-12 * np.abs(inv).max()
+    assert _rel(yp, oracle.apply_block_diag(inv, ref)) < 1e-12
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_operator_fp32(meshes, dense_systems, form):
+    m = meshes["star7"]
+    A = dense_systems[("star7", form)]
+    x = np.random.default_rng(5).standard_normal(2 * m.n_vertices)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32)) as h:
+        y = pbm.pb_mesh_apply(h, x)
+    assert _rel(y, A @ x) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["sphere6", "star7"])
+def test_rhs_and_reaction_potential(meshes, name):
+    m = meshes[name]
+    ch = inputs.charges_ball(3, 13, 1.0)
+    bD, bN = oracle.rhs(m, ch, 4.0)
+    rng = np.random.default_rng(2)
+    phi, dphi = rng.standard_normal(m.n_vertices), rng.standard_normal(m.n_vertices)
+    ref_pr = oracle.reaction_potential(m, phi, dphi, ch.xyz)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts()) as h:
+        b = pbm.pb_mesh_rhs(h, ch.xyz, ch.q)
+        pr = pbm.pb_mesh_reaction_potential(h, phi, dphi, ch.xyz)
+    assert _rel(b[:m.n_vertices], bD) < 1e-12
+    assert _rel(b[m.n_vertices:], bN) < 1e-12
+    assert _rel(pr, ref_pr) < 1e-12
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_kirkwood_solve_parity(form):
+    """Sphere of radius 2 A, 320 triangles, central +1 e: GPU Delta G equals the
+    oracle's within 1e-6 (FP64) and 1e-4 (FP32), same iteration count."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    ref = oracle.solve(m, ch, formulation=form)
+    got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form))
+    assert got["status"] == pbm.PB_OK
+    assert abs(got["dG"] - ref["dG"]) < 1e-6 * abs(ref["dG"])
+    assert got["iterations"] == ref["iterations"]
+    assert _rel(np.concatenate([got["phi"], got["dphi"]]), np.concatenate([ref["phi"], ref["dphi"]])) < 1e-6
+    tight = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, tol=1e-11))
+    reft = oracle.solve(m, ch, formulation=form, tol=1e-11, A=ref["A"])
+    assert abs(tight["dG"] - reft["dG"]) < 1e-10 * abs(reft["dG"])
+    g32 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, pbm.PB_FP32))
+    assert abs(g32["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"])
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_small_solve_parity_multi_charge(meshes, dense_systems, form):
+    m = meshes["star7"]
+    ch = inputs.charges_ball(9, 20, 2.5)
+    ref = oracle.solve(m, ch, formulation=form, A=dense_systems[("star7", form)])
+    got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form))
+    assert abs(got["dG"] - ref["dG"]) < 1e-6 * abs(ref["dG"])
+    assert abs(got["iterations"] - ref["iterations"]) <= 1
+
+
+@pytest.fixture(scope="module")
+def sphere32():
+    return inputs.config_sphere()   # 20480 triangles, 10242 vertices, 50 charges
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_full_size_sampled_rows(sphere32, form):
+    """Radius-10 sphere, 20480 triangles: sampled rows of A x, in the launch
+    configuration the benchmark uses, against rows the oracle computes."""
+    m, _ = sphere32
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(2 * m.n_vertices)
+    rows = np.sort(rng.choice(m.n_vertices, 12, replace=False))
+    r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, form, rows, x)
+    for prec, tol in ((pbm.PB_FP64, 1e-12), (pbm.PB_FP32, 2e-5)):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec)) as h:
+            y = pbm.pb_mesh_apply(h, x)
+        nv = m.n_vertices
+        got = np.concatenate([y[rows], y[nv + rows]])
+        ref = np.concatenate([r1, r2])
+        assert _rel(got, ref) < tol, (prec, _rel(got, ref))
+
+
+def test_full_size_solve_kirkwood(sphere32):
+    """Full-size sphere: FP64 and FP32 GPU solves agree to 1e-4 on Delta G and
+    both sit within the discretisation error of the Kirkwood series."""
+    from kirkwood import kirkwood_energy
+    m, ch = sphere32
+    ref = kirkwood_energy(10.0, ch.xyz, ch.q)
+    for form in (0, 1):
+        g64 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form))
+        g32 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, pbm.PB_FP32))
+        assert g64["status"] == pbm.PB_OK
+        assert abs(g64["dG"] - ref) < 5e-3 * abs(ref), (g64["dG"], ref)
+        assert abs(g32["dG"] - g64["dG"]) < 1e-4 * abs(g64["dG"])
+
+
+def test_tetrahedron_all_near():
+    """Every pair of a tetrahedron shares a vertex: the far field is empty."""
+    xyz = np.array([[1, 1, 1], [-1, -1, 1], [-1, 1, -1], [1, -1, -1]], dtype=float)
+    tri = np.array([[0, 2, 1], [0, 1, 3], [0, 3, 2], [1, 2, 3]], dtype=np.int32)
+    m = inputs.Mesh(xyz, tri)
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, 1)
+    x = np.random.default_rng(0).standard_normal(8)
+    with pbm.MeshHandle(xyz, tri, _opts(1)) as h:
+        y = pbm.pb_mesh_apply(h, x)
+        yf = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_FAR_ONLY)
+    assert _rel(y, A @ x) < 1e-12
+    assert np.abs(yf).max() == 0.0
+
+
+def test_error_paths_on_device():
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    with pytest.raises(pbm.PbError) as e:
+        pbm.pb_solve(m.xyz, m.tri, np.array([[0.0, 0.0, 5.0]]), np.array([1.0]), _opts())
+    assert e.value.code == pbm.PB_E_CHARGES
+    with pytest.raises(pbm.PbError) as e:
+        pbm.pb_solve(m.xyz, m.tri, np.array([[0.0, 0.0, np.nan]]), np.array([1.0]), _opts())
+    assert e.value.code == pbm.PB_E_INVALID_ARG
+    r = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(max_iter=1))
+    assert r["status"] == pbm.PB_NOT_CONVERGED and r["iterations"] == 1
