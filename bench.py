@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: complete boundary-element Poisson-Boltzmann solves on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): sphere of
+radius 10 A meshed as a frequency-32 icosphere (20480 flat triangles, 10242
+vertices), 50 charges uniform in r < 8 A with values U[-1, 1] e (seed 2),
+eps_in 4, eps_out 80, kappa 0.125 / A, block-diagonal preconditioner, GMRES
+tolerance 1e-5 without restart.
+
+One step = one complete solve with the internal direct formulation plus one
+with the Juffer formulation, each covering every stage of the hot path:
+geometry, Sauter-Schwab near field, mass terms, preconditioner, right-hand
+side, GMRES with the far-field operator, reaction potential and Delta G.
+The mesh's host-side index plan (validation, Morton order, sparsity) is built
+once before timing; every device stage is redone in every step.
+
+Prints one JSON line (rank 0; there is only one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import inputs  # noqa: E402
+
+METRIC = ("operator matvec kernel-pairs/s; solves/s + p99 latency at ΔG rel err ≤1e-4")
+# algorithmic flops per kernel pair of the fused far-field formula (FMA = 2,
+# exp and rsqrt = 1 each), counted from the kernel formula
+FLOPS_PER_PAIR = {0: 28, 1: 38}
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X published vector peaks
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "mixed-bf16", "mixed-fp16"])
+    ap.add_argument("--operator-mode", default="auto", choices=["matrix-free", "assembled", "auto"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=160, help="oracle rows per formulation in the CPU sample")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+              "(the design of a sharded path is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import paper_2108_10481_amd as pbm
+    if pbm.pb_device_count() < 1:
+        print("bench.py: no GPU visible to the HIP library", file=sys.stderr)
+        sys.exit(1)
+
+    prec = {"fp64": pbm.PB_FP64, "fp32": pbm.PB_FP32, "mixed-bf16": pbm.PB_MIXED_BF16,
+            "mixed-fp16": pbm.PB_MIXED_FP16}[a.precision]
+    mode = {"matrix-free": pbm.PB_MATRIX_FREE, "assembled": pbm.PB_ASSEMBLED, "auto": pbm.PB_AUTO}[a.operator_mode]
+    mesh, ch = inputs.config_sphere()
+    T = mesh.n_triangles
+    P = 6 * T
+    forms = (pbm.PB_DIRECT_INT, pbm.PB_JUFFER)
+
+    # FP64 matrix-free reference (outside the timed region) for the accuracy gate
+    ref = {}
+    for f in forms:
+        r = pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q,
+                         pbm.pb_default_options(formulation=f, precision=pbm.PB_FP64,
+                                                operator_mode=pbm.PB_MATRIX_FREE))
+        ref[f] = r
+
+    handles = {f: pbm.MeshHandle(mesh.xyz, mesh.tri,
+                                 pbm.pb_default_options(formulation=f, precision=prec, operator_mode=mode))
+               for f in forms}
+
+    def step():
+        out = {}
+        for f in forms:
+            h = handles[f]
+            pbm.pb_mesh_refresh(h)
+            out[f] = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+        return out
+
+    for _ in range(a.warmup):
+        step()
+    for h in handles.values():
+        pbm.pb_mesh_profile(h, True)
+    lat = []
+    results = None
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s0 = time.perf_counter()
+        results = step()
+        lat.append(time.perf_counter() - s0)
+    for h in handles.values():
+        pbm.pb_mesh_synchronize(h)
+    elapsed = time.perf_counter() - t0
+
+    # dominant kernel: far-field operator kernel (or dense product), HIP events on its stream
+    prof = {f: pbm.pb_mesh_profile_read(handles[f]) for f in forms}
+    info = {f: handles[f].info() for f in forms}
+    assembled = any(info[f]["assembled"] for f in forms)
+    launches = sum(prof[f][0] for f in forms)
+    kern_ms = sum(prof[f][1] for f in forms)
+    matvecs = sum(prof[f][0] for f in forms)
+    kernel_pairs = matvecs * float(P) * P
+    dtype = "f64" if prec == pbm.PB_FP64 else "f32"
+    if assembled:
+        roof = dense_roofline(handles, prof, info)
+    else:
+        flops = sum(prof[f][0] * FLOPS_PER_PAIR[f] * float(P) * P for f in forms)
+        achieved = flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS[dtype], 4), "traffic": None,
+                "kernel": "k_far", "launches": launches,
+                "avg_launch_ms": round(kern_ms / max(launches, 1), 4)}
+
+    solves = len(forms) * a.steps
+    rel_err = max(abs(results[f]["dG"] - ref[f]["dG"]) / abs(ref[f]["dG"]) for f in forms)
+    lat_ms = sorted(1e3 * x / len(forms) for x in lat)
+    rec = {
+        "metric": METRIC,
+        "value": round(solves / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * elapsed / a.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": "sphere R=10 A, icosphere 20480 triangles / 10242 vertices, 50 charges U[-1,1] e "
+                               "in r<8 A (seed 2), eps 4/80, kappa 0.125, direct + Juffer, block-diagonal, "
+                               "GMRES tol 1e-5; one step = one solve per formulation",
+                   "precision": a.precision, "operator_mode": "assembled" if assembled else "matrix-free",
+                   "source_chunks": info[forms[0]]["source_chunks"]},
+        "kernel_pairs_per_s": round(kernel_pairs / (kern_ms * 1e-3), 1) if kern_ms > 0 and not assembled else None,
+        "p50_ms": round(lat_ms[len(lat_ms) // 2], 3),
+        "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)], 3),
+        "dG_kcal": {str(f): results[f]["dG"] for f in forms},
+        "dG_rel_err_vs_fp64": rel_err,
+        "iterations": {str(f): results[f]["iterations"] for f in forms},
+        "fp64_matrix_free_solve_s": {str(f): round(ref[f]["t_setup"] + ref[f]["t_rhs"] + ref[f]["t_prec"]
+                                                   + ref[f]["t_gmres"] + ref[f]["t_dG"], 4) for f in forms},
+        "roofline": roof,
+    }
+    if rel_err > 1e-4:
+        rec["accuracy_gate"] = "FAILED"
+
+    if not a.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(mesh, rec["iterations"], a.cpu_rows, P)
+    for h in handles.values():
+        h.close()
+    print(json.dumps(rec), flush=True)
+
+
+def dense_roofline(handles, prof, info):
+    """HBM roofline of the dense far-field product (assembled modes)."""
+    raise NotImplementedError
+
+
+def cpu_baseline(mesh, iterations, nrows, P):
+    """The FP64 oracle timed on this host: operator rows for a bounded sample
+    of vertices, extrapolated to full matvecs and to solves/s with the GPU
+    run's iteration counts (other phases are negligible next to the matvecs)."""
+    import oracle
+    oracle.lib()
+    rng = np.random.default_rng(7)
+    rows = np.sort(rng.choice(mesh.n_vertices, nrows, replace=False))
+    x = rng.standard_normal(2 * mesh.n_vertices)
+    t_solve = 0.0
+    pairs = 0.0
+    t_all = 0.0
+    for f in (0, 1):
+        t0 = time.perf_counter()
+        oracle.system_rows(mesh, 4.0, 80.0, 0.125, f, rows, x)
+        dt = time.perf_counter() - t0
+        t_all += dt
+        t_matvec = dt * mesh.n_vertices / nrows
+        t_solve += t_matvec * iterations[str(f)]
+        pairs += float(P) * P * nrows / mesh.n_vertices
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    return {"value": round(2.0 / t_solve, 6), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "kernel_pairs_per_s": round(pairs / t_all, 1),
+            "sample": f"oracle operator rows for {nrows} sampled vertices per formulation (direct, Juffer) on the "
+                      f"20480-triangle sphere, {t_all:.1f} s of CPU time, scaled to full matvecs x the GPU "
+                      f"run's GMRES iterations"}
+
+
+if __name__ == "__main__":
+    main()

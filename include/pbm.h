@@ -157,6 +157,13 @@ pb_status pb_mesh_create(const pb_mesh *mesh, const pb_options *opt, pb_mesh_han
 pb_status pb_mesh_destroy(pb_mesh_handle *h);
 pb_status pb_mesh_get_info(const pb_mesh_handle *h, pb_mesh_info *info);
 
+/* Redo every device-side setup stage of the handle from the resident mesh:
+ * geometry, Sauter-Schwab near field, near-field blocks and preconditioner,
+ * and the dense far field in assembled modes.  The host-side index plan
+ * (validation, triangle order, sparsity) is kept.  Used to time complete
+ * solves with inputs resident on the device. */
+pb_status pb_mesh_refresh(pb_mesh_handle *h);
+
 /* Solve for one charge set on a resident mesh (same outputs as pb_solve). */
 pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result *result);
 

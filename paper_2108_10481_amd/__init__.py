@@ -81,7 +81,7 @@ class pb_mesh_info(ctypes.Structure):
 
 
 EXPORTS = ["pb_default_options", "pb_last_error", "pb_device_count", "pb_solve", "pb_mesh_create",
-           "pb_mesh_destroy", "pb_mesh_get_info", "pb_mesh_solve", "pb_solve_multi", "pb_mesh_apply",
+           "pb_mesh_destroy", "pb_mesh_get_info", "pb_mesh_refresh", "pb_mesh_solve", "pb_solve_multi", "pb_mesh_apply",
            "pb_mesh_apply_device", "pb_mesh_rhs", "pb_mesh_reaction_potential", "pb_mesh_near_blocks",
            "pb_mesh_preconditioner", "pb_mesh_profile", "pb_mesh_profile_read", "pb_mesh_synchronize"]
 
@@ -106,6 +106,7 @@ def load():
     L.pb_mesh_create.argtypes = [P(pb_mesh), P(pb_options), P(vp)]
     L.pb_mesh_destroy.argtypes = [vp]
     L.pb_mesh_get_info.argtypes = [vp, P(pb_mesh_info)]
+    L.pb_mesh_refresh.argtypes = [vp]
     L.pb_mesh_solve.argtypes = [vp, P(pb_charges), P(pb_result)]
     L.pb_solve_multi.argtypes = [vp, ctypes.c_int32, P(pb_charges), P(pb_result)]
     L.pb_mesh_apply.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int32]
@@ -250,6 +251,10 @@ def pb_mesh_destroy(h: MeshHandle) -> None:
 
 def pb_mesh_get_info(h: MeshHandle) -> dict:
     return h.info()
+
+
+def pb_mesh_refresh(h: MeshHandle) -> None:
+    _check(load().pb_mesh_refresh(h.h))
 
 
 def pb_mesh_solve(h: MeshHandle, qxyz, q) -> dict:

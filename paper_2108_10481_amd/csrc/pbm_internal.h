@@ -125,6 +125,7 @@ struct DevMesh {
     double *u = nullptr;           // 2V solution
     Krylov kry;
     double t_setup = 0.0;
+    bool want_dense = false;
     // charges workspace
     double *qbuf = nullptr;        // 7 x qcap: SoA x, y, z, q then AoS xyz
     int qcap = 0;

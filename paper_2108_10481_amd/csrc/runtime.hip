@@ -76,6 +76,16 @@ static void check_options(const pb_options *o)
     if (o->source_chunks < 0 || o->source_chunks > 1024) fail(PB_E_INVALID_ARG, "source_chunks must be in [0, 1024]");
 }
 
+// every device-side setup stage: geometry, near field, near blocks +
+// preconditioner, dense far field (assembled modes)
+static void device_setup(DevMesh &d)
+{
+    launch_geometry(d);
+    launch_near_field(d);
+    launch_near_assemble(d);
+    if (d.want_dense) build_dense(d);
+}
+
 static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
 {
     check_options(opt);
@@ -125,12 +135,9 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->ztmp = (double *)d->alloc(sizeof(double) * 2 * V);
     d->yfar = (double *)d->alloc(sizeof(double) * 2 * V);
 
-    launch_geometry(*d);
-    launch_near_field(*d);
-    launch_near_assemble(*d);
-    const bool want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
-                            (opt->operator_mode == PB_AUTO && dense_fits(*d));
-    if (want_dense) build_dense(*d);
+    d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
+                    (opt->operator_mode == PB_AUTO && dense_fits(*d));
+    device_setup(*d);
     HIPCHECK(hipStreamSynchronize(d->stream));
     d->t_setup = now() - t0;
     return d.release();
@@ -455,6 +462,19 @@ pb_status pb_mesh_get_info(const pb_mesh_handle *h, pb_mesh_info *info)
     info->source_chunks = d.S;
     info->assembled = d.dense ? 1 : 0;
     info->device_bytes = d.bytes;
+    return PB_OK;
+    PB_CATCH
+}
+
+pb_status pb_mesh_refresh(pb_mesh_handle *h)
+{
+    PB_TRY
+    if (!h) fail(PB_E_INVALID_ARG, "NULL handle");
+    DevMesh &d = *h->d;
+    const double t0 = now();
+    device_setup(d);
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    d.t_setup = now() - t0;
     return PB_OK;
     PB_CATCH
 }
