@@ -212,12 +212,18 @@ pb_status pb_mesh_near_blocks(pb_mesh_handle *h, int32_t n, const int32_t *t, co
 /* Per-vertex 2x2 preconditioner inverses, out: n_vertices x 4 (row-major). */
 pb_status pb_mesh_preconditioner(pb_mesh_handle *h, double *out);
 
-/* Kernel timing for measurement: when enabled, the far-field operator kernel
- * (or the dense product in assembled modes) is bracketed by HIP events on the
- * stream it runs on; read returns the launches and summed milliseconds since
- * the last reset.  kind 0 = far-field / dense operator kernel. */
+/* Kernel timing for measurement: when enabled, the dominant kernels are
+ * bracketed by HIP events on the stream they run on.  read returns, since the
+ * last pb_mesh_profile call, the launches, summed milliseconds and summed
+ * algorithmic work of one kind:
+ *   kind 0: operator product -- matrix-free far-field kernel (work = kernel
+ *           pairs, (6T)^2 per launch) or dense far-field GEMV (work = bytes of
+ *           the stored 2V x 2V entries plus the vectors);
+ *   kind 1: dense far-field assembly (work = point-pair evaluations).
+ * total_work may be NULL. */
 pb_status pb_mesh_profile(pb_mesh_handle *h, int32_t enable);
-pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launches, double *total_ms);
+pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launches, double *total_ms,
+                               double *total_work);
 
 /* Block until all work of the handle is done. */
 pb_status pb_mesh_synchronize(pb_mesh_handle *h);

@@ -118,7 +118,8 @@ def load():
                                       P(ctypes.c_double)]
     L.pb_mesh_preconditioner.argtypes = [vp, P(ctypes.c_double)]
     L.pb_mesh_profile.argtypes = [vp, ctypes.c_int32]
-    L.pb_mesh_profile_read.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_double)]
+    L.pb_mesh_profile_read.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_double),
+                                       P(ctypes.c_double)]
     L.pb_mesh_synchronize.argtypes = [vp]
     for name in EXPORTS:
         f = getattr(L, name)
@@ -332,10 +333,13 @@ def pb_mesh_profile(h: MeshHandle, enable: bool) -> None:
 
 
 def pb_mesh_profile_read(h: MeshHandle, kind: int = 0):
+    """Returns (launches, total_ms, total_work) for kind 0 (operator product)
+    or 1 (dense assembly)."""
     n = ctypes.c_int64()
     ms = ctypes.c_double()
-    _check(load().pb_mesh_profile_read(h.h, int(kind), ctypes.byref(n), ctypes.byref(ms)))
-    return int(n.value), float(ms.value)
+    w = ctypes.c_double()
+    _check(load().pb_mesh_profile_read(h.h, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(w)))
+    return int(n.value), float(ms.value), float(w.value)
 
 
 def pb_mesh_synchronize(h: MeshHandle) -> None:

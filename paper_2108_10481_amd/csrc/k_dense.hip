@@ -1,20 +1,573 @@
 // Assembled far field and mixed-precision solves.
+//
+// The far-field part of the 2V x 2V system (all triangle pairs sharing no
+// vertex, regular 6 x 6 point quadrature: the same sums the matrix-free
+// kernels evaluate) is assembled once into a dense row-major matrix in the
+// vertex basis, already combined into the formulation's four blocks.  The
+// near field (FP64 CSR) and mass terms stay separate.
+//
+// Storage by precision mode:
+//   PB_FP64        : FP64 entries, FP64 evaluation
+//   PB_FP32        : FP32 entries, FP32 evaluation
+//   PB_MIXED_BF16  : FP32 entries (outer residual) + BF16 copy (inner solves)
+//   PB_MIXED_FP16  : FP32 entries (outer residual) + FP16 copy with one
+//                    power-of-two scale per block (inner solves)
+// Products are HBM-streaming GEMVs (one wavefront per row, 16-byte loads);
+// several right-hand sides use the MFMA GEMM (k_gemm_mfma).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "pbm_internal.h"
 
 namespace pbm {
 
+int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
+
 struct Dense {
-    int dummy;
+    int V = 0, n = 0;
+    size_t Vp = 0;                 // column offset of the second block (V rounded up to 64)
+    size_t ld = 0;                 // row stride in elements = 2 Vp
+    double *A64 = nullptr;
+    float *A32 = nullptr;
+    uint16_t *A16 = nullptr;
+    int kind16 = 0;                // 0 none, 1 bf16, 2 fp16
+    float scale16[4] = {1, 1, 1, 1};   // fp16: stored = entry * scale (per block)
+    int ncolor = 0;
+    std::vector<int32_t> color_ptr;
+    int32_t *color_tri = nullptr;  // triangles grouped by colour
+    float *x32 = nullptr;          // ld (padded) FP32 copy of x
+    double *x64 = nullptr;         // ld (padded) FP64 copy of x
+    int level = 1;                 // 1: accurate operator, 0: 16-bit operator
 };
 
-bool dense_fits(const DevMesh &) { return false; }
-void build_dense(DevMesh &) { fail(PB_E_STATE, "assembled operator mode is not available yet"); }
-void destroy_dense(DevMesh &d) { delete d.dense; d.dense = nullptr; }
-void dense_apply(DevMesh &, const double *, double *) { fail(PB_E_STATE, "no assembled operator"); }
-int mixed_refinement_solve(DevMesh &, const double *, const double *, double *, double *, int *)
+// ------------------------------------------------------------ colouring
+// Greedy colouring of the triangles: two triangles sharing a vertex never get
+// the same colour, so all triangles of one colour update disjoint matrix rows.
+static void color_triangles(const HostMesh &hm, std::vector<int32_t> &ptr, std::vector<int32_t> &list)
 {
-    fail(PB_E_STATE, "mixed precision needs the assembled operator");
+    const int T = hm.T;
+    std::vector<int> col(T, -1);
+    int ncol = 0;
+    std::vector<char> used;
+    for (int t = 0; t < T; ++t) {
+        used.assign(ncol + 1, 0);
+        for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) {
+            int c = col[hm.pair_s[p]];
+            if (c >= 0) used[c] = 1;
+        }
+        int c = 0;
+        while (c < ncol && used[c]) ++c;
+        col[t] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    ptr.assign(ncol + 1, 0);
+    for (int t = 0; t < T; ++t) ptr[col[t] + 1]++;
+    for (int c = 0; c < ncol; ++c) ptr[c + 1] += ptr[c];
+    list.resize(T);
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int t = 0; t < T; ++t) list[fill[col[t]]++] = t;
 }
+
+// ------------------------------------------------------------- assembly
+template <typename R>
+struct AsmCoef {
+    R kappa, kexp, c1, c2, k2;
+};
+
+__device__ __forceinline__ float rsq_a(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_a(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    return y;
+}
+__device__ __forceinline__ float expn_a(float kl, float r) { return __builtin_amdgcn_exp2f(-kl * r); }
+__device__ __forceinline__ double expn_a(double k, double r) { return exp(-k * r); }
+
+// One thread per (target triangle t of the current colour, source vertex j):
+// loops over the source triangles s containing j that share no vertex with t
+// and adds the local block column l(j) of pair (t, s) to rows t_0, t_1, t_2.
+// Per point pair four combined kernel values are formed (FORM 0, direct:
+// F_L d.n_s, -G_L, -F_Y d.n_s, eps G_Y; FORM 1, Juffer: (F_L - alpha F_Y) d.n_s,
+// G_Y - G_L, G_Y, (F_L - beta F_Y) d.n_t) and weighted with the test basis.
+template <typename R, typename S, int FORM>
+__global__ __launch_bounds__(256) void k_assemble(int V, AsmCoef<R> cf, const int32_t *__restrict__ tris_of_color,
+                                                   const int32_t *__restrict__ tri, const R *__restrict__ stat,
+                                                   const double *__restrict__ geo, const int32_t *__restrict__ inc_ptr,
+                                                   const int32_t *__restrict__ inc_tk, S *__restrict__ A, size_t ld,
+                                                   size_t Vp)
+{
+    const int t = tris_of_color[blockIdx.y];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= V) return;
+    const R *ts = stat + (size_t)t * kStat;
+    const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
+    const double *gt = geo + (size_t)t * kGeo;
+    const R at = (R)gt[21];
+    R tx[6], ty[6], tz[6], xnt[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2]; xnt[p] = ts[21 + p];
+    }
+    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+    R acc[3][4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int o = 0; o < 4; ++o) acc[k][o] = 0;
+    for (int e = inc_ptr[j]; e < inc_ptr[j + 1]; ++e) {
+        const int s = inc_tk[e] >> 2, l = inc_tk[e] & 3;
+        const int j0 = tri[3 * s], j1 = tri[3 * s + 1], j2 = tri[3 * s + 2];
+        if ((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) | (j2 == v0) |
+            (j2 == v1) | (j2 == v2))
+            continue;
+        const R *ss = stat + (size_t)s * kStat;
+        const double *gs = geo + (size_t)s * kGeo;
+        const R nsx = ss[18], nsy = ss[19], nsz = ss[20];
+        R xns[6];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) xns[p] = tx[p] * nsx + ty[p] * nsy + tz[p] * nsz;
+        R blk[3][4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) blk[k][o] = 0;
+        R Ssum = 0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const R yx = ss[3 * q], yy = ss[3 * q + 1], yz = ss[3 * q + 2], yns = ss[21 + q];
+            const R ynt = yx * ntx + yy * nty + yz * ntz;
+            R X[3][4];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int o = 0; o < 4; ++o) X[k][o] = 0;
+            R Sq = 0;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = rsq_a(r2);
+                const R r = r2 * ri;
+                const R ek = expn_a(cf.kexp, r);
+                const R ri3 = ri * ri * ri;
+                const R dns = xns[p] - yns;
+                const R fy = ek * (cf.kappa * r + R(1)) * ri3;
+                R v[4];
+                if (FORM == 0) {
+                    v[0] = ri3 * dns;
+                    v[1] = -ri;
+                    v[2] = -fy * dns;
+                    v[3] = cf.c1 * ek * ri;
+                } else {
+                    const R gy = ek * ri;
+                    v[0] = (ri3 - cf.c1 * fy) * dns;
+                    v[1] = gy - ri;
+                    v[2] = gy;
+                    v[3] = (ri3 - cf.c2 * fy) * (xnt[p] - ynt);
+                    Sq += R(rule_w(p)) * v[1];
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const R c = R(rule_w(p) * rule_bary(p, k));
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) X[k][o] += c * v[o];
+                }
+            }
+            // test-side weights done; trial weight w_q lambda_l(y_q)
+            const R wq = R(rule_w(q)) * (l == 0 ? R(rule_bary(q, 0)) : l == 1 ? R(rule_bary(q, 1)) : R(rule_bary(q, 2)));
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int o = 0; o < 4; ++o) blk[k][o] += wq * X[k][o];
+            if (FORM == 1) Ssum += R(rule_w(q)) * Sq;
+        }
+        const R sc = at * (R)gs[21] * R(kInv4Pi);
+        if (FORM == 1) {
+            // hypersingular: curl_k(t) . curl_l(s) * int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
+            const R nn = ntx * nsx + nty * nsy + ntz * nsz;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const R cc = (R)(gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
+                                 gt[24 + 3 * k] * gs[24 + 3 * l]);
+                blk[k][2] = cc * Ssum + cf.k2 * nn * blk[k][2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) acc[k][o] += sc * blk[k][o];
+    }
+    const int rows[3] = {v0, v1, v2};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const size_t r1 = (size_t)rows[k] * ld, r2 = (size_t)(V + rows[k]) * ld;
+        A[r1 + j] += (S)acc[k][0];
+        A[r1 + Vp + j] += (S)acc[k][1];
+        A[r2 + j] += (S)acc[k][2];
+        A[r2 + Vp + j] += (S)acc[k][3];
+    }
+}
+
+template <typename S>
+__global__ void k_fill(size_t n, S *__restrict__ a)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = S(0);
+}
+
+// FP32 -> BF16 (round to nearest even) or FP16 with a per-block scale
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void k_to16(int n, int V, size_t Vp, size_t ld, int kind, float s0, float s1, float s2, float s3,
+                       const float *__restrict__ A, uint16_t *__restrict__ B)
+{
+    const size_t total = (size_t)n * ld;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const float a = A[i];
+        if (kind == 1) {
+            B[i] = to_bf16(a);
+        } else {
+            const size_t r = i / ld, c = i - r * ld;
+            const int blk = (r >= (size_t)V ? 2 : 0) + (c >= Vp ? 1 : 0);
+            const float sc = blk == 0 ? s0 : blk == 1 ? s1 : blk == 2 ? s2 : s3;
+            _Float16 h = (_Float16)(a * sc);
+            B[i] = __builtin_bit_cast(uint16_t, h);
+        }
+    }
+}
+
+// per-block max |entry| (for the FP16 scales); one partial per block of threads
+__global__ __launch_bounds__(256) void k_blockmax(int n, int V, size_t Vp, size_t ld, const float *__restrict__ A,
+                                                  float *__restrict__ out)
+{
+    __shared__ float sh[4][256];
+    float m[4] = {0, 0, 0, 0};
+    const size_t total = (size_t)n * ld;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const size_t r = i / ld, c = i - r * ld;
+        const int blk = (r >= (size_t)V ? 2 : 0) + (c >= Vp ? 1 : 0);
+        m[blk] = fmaxf(m[blk], fabsf(A[i]));
+    }
+    for (int b = 0; b < 4; ++b) sh[b][threadIdx.x] = m[b];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int b = 0; b < 4; ++b) sh[b][threadIdx.x] = fmaxf(sh[b][threadIdx.x], sh[b][threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int b = 0; b < 4; ++b) out[4 * blockIdx.x + b] = sh[b][0];
+}
+
+// ----------------------------------------------------------------- GEMV
+// y[r] = sum_c A[r][c] x[c], one wavefront per row, each lane streams 16-byte
+// chunks; x is padded with zeros to ld.  ACC = accumulation type.
+__device__ __forceinline__ void load16(const double *p, double *v) { const double2 a = *(const double2 *)p; v[0] = a.x; v[1] = a.y; }
+
+template <typename S> struct Vec;
+template <> struct Vec<double> { static constexpr int W = 2; };
+template <> struct Vec<float> { static constexpr int W = 4; };
+template <> struct Vec<uint16_t> { static constexpr int W = 8; };
+
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ float fp16_to_f(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+template <typename S, typename ACC, int KIND>
+__global__ __launch_bounds__(256) void k_gemv(int n, int V, size_t Vp, size_t ld, const S *__restrict__ A,
+                                              const ACC *__restrict__ x, float inv0, float inv1, float inv2, float inv3,
+                                              double *__restrict__ y)
+{
+    constexpr int W = Vec<S>::W;
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int nwave = (gridDim.x * 256) >> 6;
+    for (int r = wave; r < n; r += nwave) {
+        const S *row = A + (size_t)r * ld;
+        ACC s0 = 0, s1 = 0;   // columns < V and >= V (separate block scales for FP16)
+        for (size_t c = (size_t)lane * W; c < ld; c += 64 * W) {
+            S v[W];
+            if constexpr (sizeof(S) * W == 16) {
+                const uint4 u = *(const uint4 *)(row + c);
+                __builtin_memcpy(v, &u, 16);
+            }
+            ACC part = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                ACC a;
+                if constexpr (KIND == 0) a = (ACC)v[w];
+                else if constexpr (KIND == 1) a = (ACC)bf16_to_f((uint16_t)v[w]);
+                else a = (ACC)fp16_to_f((uint16_t)v[w]);
+                part += a * x[c + w];
+            }
+            if (c < Vp) s0 += part; else s1 += part;   // chunks never straddle Vp (multiple of 64)
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            s0 += __shfl_xor(s0, off);
+            s1 += __shfl_xor(s1, off);
+        }
+        if (lane == 0) {
+            double out;
+            if (KIND == 2) {
+                const bool top = r < V;
+                out = (double)s0 * (top ? inv0 : inv2) + (double)s1 * (top ? inv1 : inv3);
+            } else {
+                out = (double)s0 + (double)s1;
+            }
+            y[r] = out;
+        }
+    }
+}
+
+// copy x (2V doubles, two halves) into the padded layout: [x1 | x2 | 0...]
+template <typename ACC>
+__global__ void k_pad_x(int V, size_t Vp, size_t ld, const double *__restrict__ x, ACC *__restrict__ xp)
+{
+    size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ld) return;
+    ACC v = ACC(0);
+    if (c < (size_t)V) v = (ACC)x[c];
+    else if (c >= Vp && c < Vp + (size_t)V) v = (ACC)x[V + (c - Vp)];
+    xp[c] = v;
+}
+
+// ------------------------------------------------------------- host side
+// columns laid out as [x1 (V) | 0 | x2 (V) | 0] with each block padded to a
+// multiple of 64 entries, so a 16-byte chunk never straddles the two blocks
+static size_t dense_vp(int V) { return ((size_t)V + 63) / 64 * 64; }
+static size_t dense_ld(int V) { return 2 * dense_vp(V); }
+
+static size_t dense_bytes(const DevMesh &d)
+{
+    const size_t n = 2 * (size_t)d.hm.V, ld = dense_ld(d.hm.V);
+    size_t per = d.prm.precision == PB_FP64 ? 8 : 4;
+    if (d.prm.precision >= PB_MIXED_BF16) per += 2;
+    return n * ld * per;
+}
+
+bool dense_fits(const DevMesh &d)
+{
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return false;
+    size_t need = dense_bytes(d);
+    if (d.opt.memory_budget && d.bytes + need > d.opt.memory_budget) return false;
+    return need < 0.8 * (double)freeb;
+}
+
+template <typename R, typename S>
+static void assemble(DevMesh &d, S *A)
+{
+    Dense &D = *d.dense;
+    const int V = d.hm.V;
+    AsmCoef<R> cf;
+    const double kap = d.prm.kappa;
+    cf.kappa = (R)kap;
+    cf.kexp = sizeof(R) == 4 ? (R)(kap * 1.4426950408889634) : (R)kap;
+    const bool direct = d.prm.formulation == PB_DIRECT_INT;
+    cf.c1 = (R)(direct ? d.prm.eps_in / d.prm.eps_out : d.prm.eps_out / d.prm.eps_in);
+    cf.c2 = (R)(d.prm.eps_in / d.prm.eps_out);
+    cf.k2 = (R)(kap * kap);
+    const R *stat = sizeof(R) == 4 ? (const R *)d.stat32 : (const R *)d.stat64;
+    const size_t total = (size_t)D.n * D.ld;
+    hipLaunchKernelGGL(k_fill<S>, dim3(4096), dim3(256), 0, d.stream, total, A);
+    for (int c = 0; c < D.ncolor; ++c) {
+        const int nt = D.color_ptr[c + 1] - D.color_ptr[c];
+        if (nt == 0) continue;
+        dim3 grid((V + 255) / 256, nt), block(256);
+        const int32_t *lst = D.color_tri + D.color_ptr[c];
+        if (direct)
+            hipLaunchKernelGGL((k_assemble<R, S, 0>), grid, block, 0, d.stream, V, cf, lst, d.tri, stat, d.geo,
+                               d.inc_ptr, d.inc_tk, A, D.ld, D.Vp);
+        else
+            hipLaunchKernelGGL((k_assemble<R, S, 1>), grid, block, 0, d.stream, V, cf, lst, d.tri, stat, d.geo,
+                               d.inc_ptr, d.inc_tk, A, D.ld, D.Vp);
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+void build_dense(DevMesh &d)
+{
+    const int V = d.hm.V;
+    if (!d.dense) {
+        if (!dense_fits(d)) fail(PB_E_NOMEM, "assembled far field does not fit the device memory budget");
+        Dense *D = new Dense();
+        d.dense = D;
+        D->V = V;
+        D->n = 2 * V;
+        D->Vp = dense_vp(V);
+        D->ld = dense_ld(V);
+        std::vector<int32_t> lst;
+        color_triangles(d.hm, D->color_ptr, lst);
+        D->ncolor = (int)D->color_ptr.size() - 1;
+        D->color_tri = (int32_t *)d.alloc(sizeof(int32_t) * lst.size());
+        HIPCHECK(hipMemcpyAsync(D->color_tri, lst.data(), sizeof(int32_t) * lst.size(), hipMemcpyHostToDevice,
+                                d.stream));
+        const size_t total = (size_t)D->n * D->ld;
+        if (d.prm.precision == PB_FP64) D->A64 = (double *)d.alloc(sizeof(double) * total);
+        else D->A32 = (float *)d.alloc(sizeof(float) * total);
+        if (d.prm.precision >= PB_MIXED_BF16) {
+            D->A16 = (uint16_t *)d.alloc(sizeof(uint16_t) * total);
+            D->kind16 = d.prm.precision == PB_MIXED_BF16 ? 1 : 2;
+        }
+        D->x32 = (float *)d.alloc(sizeof(float) * D->ld);
+        D->x64 = (double *)d.alloc(sizeof(double) * D->ld);
+    }
+    Dense &D = *d.dense;
+    Profiler &pf = d.prof;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pf.enabled) {
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, d.stream));
+    }
+    if (D.A64) assemble<double, double>(d, D.A64);
+    else assemble<float, float>(d, D.A32);
+    if (pf.enabled) {
+        HIPCHECK(hipEventRecord(e1, d.stream));
+        // assembly work: every far pair's 36 point pairs, evaluated once per
+        // source vertex of the pair (3x)
+        pf.record(1, e0, e1, 3.0 * 36.0 * (double)d.hm.T * (double)d.hm.T);
+    }
+    if (D.A16) {
+        const size_t total = (size_t)D.n * D.ld;
+        if (D.kind16 == 2) {
+            const int nb = 1024;
+            float *part = (float *)d.ztmp;   // 4 * nb floats fit in 2V doubles for V >= 2048; else temp
+            float *tmp = nullptr;
+            if ((size_t)4 * nb * sizeof(float) > sizeof(double) * 2 * (size_t)V) {
+                tmp = (float *)d.alloc(sizeof(float) * 4 * nb);
+                part = tmp;
+            }
+            hipLaunchKernelGGL(k_blockmax, dim3(nb), dim3(256), 0, d.stream, D.n, V, D.Vp, D.ld, D.A32, part);
+            std::vector<float> h(4 * nb);
+            HIPCHECK(hipMemcpyAsync(h.data(), part, sizeof(float) * h.size(), hipMemcpyDeviceToHost, d.stream));
+            HIPCHECK(hipStreamSynchronize(d.stream));
+            for (int b = 0; b < 4; ++b) {
+                float m = 0.0f;
+                for (int k = 0; k < nb; ++k) m = std::max(m, h[4 * k + b]);
+                // largest |entry| scaled to about 2^14 (FP16 max 65504)
+                int e = 0;
+                if (m > 0.0f) { std::frexp(m, &e); e = 14 - e; }
+                D.scale16[b] = std::ldexp(1.0f, e);
+            }
+        }
+        hipLaunchKernelGGL(k_to16, dim3(8192), dim3(256), 0, d.stream, D.n, V, D.Vp, D.ld, D.kind16, D.scale16[0],
+                           D.scale16[1], D.scale16[2], D.scale16[3], D.A32, D.A16);
+        (void)total;
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+void destroy_dense(DevMesh &d)
+{
+    delete d.dense;   // device memory belongs to the handle's allocation list
+    d.dense = nullptr;
+}
+
+// yfar (2V doubles) = A_far x at the current operator level
+void dense_apply(DevMesh &d, const double *x, double *yfar)
+{
+    Dense &D = *d.dense;
+    const int V = d.hm.V;
+    Profiler &pf = d.prof;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const dim3 gpad((unsigned)((D.ld + 255) / 256)), b256(256);
+    const int nwg = std::min(D.n / 4 + 1, 8192);
+    if (pf.enabled) {
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+    }
+    const bool lo = D.level == 0 && D.A16;
+    if (D.A64) {
+        hipLaunchKernelGGL(k_pad_x<double>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, x, D.x64);
+        if (pf.enabled) HIPCHECK(hipEventRecord(e0, d.stream));
+        hipLaunchKernelGGL((k_gemv<double, double, 0>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A64, D.x64,
+                           1.f, 1.f, 1.f, 1.f, yfar);
+    } else if (!lo) {
+        hipLaunchKernelGGL(k_pad_x<double>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, x, D.x64);
+        if (pf.enabled) HIPCHECK(hipEventRecord(e0, d.stream));
+        hipLaunchKernelGGL((k_gemv<float, double, 0>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A32, D.x64,
+                           1.f, 1.f, 1.f, 1.f, yfar);
+    } else {
+        hipLaunchKernelGGL(k_pad_x<float>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, x, D.x32);
+        if (pf.enabled) HIPCHECK(hipEventRecord(e0, d.stream));
+        if (D.kind16 == 1)
+            hipLaunchKernelGGL((k_gemv<uint16_t, float, 1>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A16,
+                               D.x32, 1.f, 1.f, 1.f, 1.f, yfar);
+        else
+            hipLaunchKernelGGL((k_gemv<uint16_t, float, 2>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A16,
+                               D.x32, 1.f / D.scale16[0], 1.f / D.scale16[1], 1.f / D.scale16[2],
+                               1.f / D.scale16[3], yfar);
+    }
+    if (pf.enabled) {
+        HIPCHECK(hipEventRecord(e1, d.stream));
+        // algorithmic bytes: the stored 2V x 2V entries (padding excluded) + x and y
+        const double ent = (double)D.n * (double)D.n;
+        const double esz = D.A64 ? 8.0 : lo ? 2.0 : 4.0;
+        pf.record(0, e0, e1, ent * esz + (double)D.n * (lo ? 4.0 : 8.0) + (double)D.n * 8.0);
+    }
+    HIPCHECK(hipGetLastError());
+}
+
+// Iterative refinement (north of the paper's plain solve): the outer residual
+// uses the accurate operator (FP32-stored far field + FP64 near field, FP64
+// vectors), each correction is solved by GMRES on the 16-bit far field.
+int mixed_refinement_solve(DevMesh &d, const double *b, const double *pb, double *u, double *est, int *outer)
+{
+    (void)b;
+    Dense &D = *d.dense;
+    const int n = 2 * d.hm.V;
+    hipStream_t s = d.stream;
+    double *r = d.ytmp2, *c = d.ztmp2;
+    double *kb = d.kry.kbuf;
+    HIPCHECK(hipMemsetAsync(u, 0, sizeof(double) * n, s));
+    kr_scale_copy(s, n, pb, 1.0, r);
+    kr_dots(s, n, 1, pb, n, pb, d.red1);
+    double nb2 = 0.0;
+    HIPCHECK(hipMemcpyAsync(&nb2, d.red1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double nb = std::sqrt(nb2);
+    int its = 0, k = 0;
+    double rel = 1.0;
+    const int max_outer = 30;
+    for (k = 1; k <= max_outer; ++k) {
+        double e_in = 0.0;
+        D.level = 0;
+        its += gmres(d, r, c, std::max(d.opt.inner_tol, 0.5 * d.opt.tol * nb / std::max(rel * nb, 1e-300)),
+                     std::min(d.opt.inner_max_iter, d.opt.max_iter), &e_in);
+        D.level = 1;
+        kr_axpy(s, n, 1.0, c, u);
+        // r = pb - P^-1 A_hi u
+        apply_operator(d, u, r, PB_APPLY_PRECOND, nullptr);
+        kr_scale_copy(s, n, r, -1.0, r);
+        kr_axpy(s, n, 1.0, pb, r);
+        kr_dots(s, n, 1, r, n, r, d.red1);
+        double r2 = 0.0;
+        HIPCHECK(hipMemcpyAsync(&r2, d.red1, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        rel = nb > 0 ? std::sqrt(r2) / nb : 0.0;
+        if (rel <= d.opt.tol || its >= d.opt.max_iter) break;
+    }
+    (void)kb;
+    D.level = 1;
+    *est = rel;
+    *outer = std::min(k, max_outer);
+    return its;
+}
+
 pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result *out)
 {
     pb_status worst = PB_OK;

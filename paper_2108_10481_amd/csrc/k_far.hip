@@ -295,8 +295,8 @@ void launch_far(DevMesh &d, bool fp32)
     else far_launch<double>(d, d.stat64, d.dyn64);
     if (pf.enabled) {
         HIPCHECK(hipEventRecord(e1, d.stream));
-        pf.ev.push_back(e0);
-        pf.ev.push_back(e1);
+        const double P = 6.0 * d.hm.T;
+        pf.record(0, e0, e1, P * P);   // kernel pairs, near-masked pairs included
     }
 }
 

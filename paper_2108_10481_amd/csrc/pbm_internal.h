@@ -76,11 +76,23 @@ struct Params {
     int formulation, preconditioner, precision, operator_mode;
 };
 
+// HIP-event timing of the dominant kernels on the stream they run on.
+// kind 0: far-field operator product (matrix-free kernel or dense GEMV),
+// kind 1: dense far-field assembly.  work = algorithmic kernel pairs
+// (matrix-free), bytes (dense product) or point-pair evaluations (assembly).
 struct Profiler {
     bool enabled = false;
-    std::vector<hipEvent_t> ev;   // pairs
-    int64_t launches = 0;
-    double total_ms = 0.0;
+    std::vector<hipEvent_t> ev[2];   // start/stop pairs
+    std::vector<double> pend_work[2];
+    int64_t launches[2] = {0, 0};
+    double total_ms[2] = {0.0, 0.0};
+    double work[2] = {0.0, 0.0};
+    void record(int kind, hipEvent_t a, hipEvent_t b, double w)
+    {
+        ev[kind].push_back(a);
+        ev[kind].push_back(b);
+        pend_work[kind].push_back(w);
+    }
 };
 
 struct Dense;   // assembled far field (k_dense.hip)
@@ -121,6 +133,9 @@ struct DevMesh {
     double *xtmp = nullptr;        // 2V
     double *ytmp = nullptr;        // 2V
     double *ztmp = nullptr;        // 2V
+    double *ytmp2 = nullptr;       // 2V (iterative refinement residual)
+    double *ztmp2 = nullptr;       // 2V (iterative refinement correction)
+    double *red1 = nullptr;        // small reduction scratch
     double *yfar = nullptr;        // 2V far-field product (assembled mode)
     double *u = nullptr;           // 2V solution
     Krylov kry;

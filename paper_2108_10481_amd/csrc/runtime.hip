@@ -42,7 +42,8 @@ void *DevMesh::alloc(size_t n)
 DevMesh::~DevMesh()
 {
     if (stream) (void)hipStreamSynchronize(stream);
-    for (hipEvent_t e : prof.ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k)
+        for (hipEvent_t e : prof.ev[k]) (void)hipEventDestroy(e);
     destroy_dense(*this);
     for (void *p : allocs) (void)hipFree(p);
     if (stream) (void)hipStreamDestroy(stream);
@@ -133,6 +134,9 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->xtmp = (double *)d->alloc(sizeof(double) * 2 * V);
     d->ytmp = (double *)d->alloc(sizeof(double) * 2 * V);
     d->ztmp = (double *)d->alloc(sizeof(double) * 2 * V);
+    d->ytmp2 = (double *)d->alloc(sizeof(double) * 2 * V);
+    d->ztmp2 = (double *)d->alloc(sizeof(double) * 2 * V);
+    d->red1 = (double *)d->alloc(sizeof(double) * 8);
     d->yfar = (double *)d->alloc(sizeof(double) * 2 * V);
 
     d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
@@ -600,32 +604,40 @@ pb_status pb_mesh_profile(pb_mesh_handle *h, int32_t enable)
     if (!h) fail(PB_E_INVALID_ARG, "NULL handle");
     Profiler &p = h->d->prof;
     HIPCHECK(hipStreamSynchronize(h->d->stream));
-    for (hipEvent_t e : p.ev) (void)hipEventDestroy(e);
-    p.ev.clear();
-    p.launches = 0;
-    p.total_ms = 0.0;
+    for (int k = 0; k < 2; ++k) {
+        for (hipEvent_t e : p.ev[k]) (void)hipEventDestroy(e);
+        p.ev[k].clear();
+        p.pend_work[k].clear();
+        p.launches[k] = 0;
+        p.total_ms[k] = 0.0;
+        p.work[k] = 0.0;
+    }
     p.enabled = enable != 0;
     return PB_OK;
     PB_CATCH
 }
 
-pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launches, double *total_ms)
+pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launches, double *total_ms,
+                               double *total_work)
 {
     PB_TRY
-    if (!h || !launches || !total_ms || kind != 0) fail(PB_E_INVALID_ARG, "bad arguments");
+    if (!h || !launches || !total_ms || kind < 0 || kind > 1) fail(PB_E_INVALID_ARG, "bad arguments");
     Profiler &p = h->d->prof;
     HIPCHECK(hipStreamSynchronize(h->d->stream));
-    for (size_t i = 0; i + 1 < p.ev.size(); i += 2) {
+    for (size_t i = 0; i + 1 < p.ev[kind].size(); i += 2) {
         float ms = 0.0f;
-        HIPCHECK(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
-        p.total_ms += ms;
-        p.launches += 1;
-        (void)hipEventDestroy(p.ev[i]);
-        (void)hipEventDestroy(p.ev[i + 1]);
+        HIPCHECK(hipEventElapsedTime(&ms, p.ev[kind][i], p.ev[kind][i + 1]));
+        p.total_ms[kind] += ms;
+        p.launches[kind] += 1;
+        p.work[kind] += p.pend_work[kind][i / 2];
+        (void)hipEventDestroy(p.ev[kind][i]);
+        (void)hipEventDestroy(p.ev[kind][i + 1]);
     }
-    p.ev.clear();
-    *launches = p.launches;
-    *total_ms = p.total_ms;
+    p.ev[kind].clear();
+    p.pend_work[kind].clear();
+    *launches = p.launches[kind];
+    *total_ms = p.total_ms[kind];
+    if (total_work) *total_work = p.work[kind];
     return PB_OK;
     PB_CATCH
 }

@@ -211,3 +211,66 @@ def test_error_paths_on_device():
     assert e.value.code == pbm.PB_E_INVALID_ARG
     r = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(max_iter=1))
     assert r["status"] == pbm.PB_NOT_CONVERGED and r["iterations"] == 1
+
+
+# ------------------------------------------------------------ assembled modes
+@pytest.mark.parametrize("name", ["sphere6", "star7"])
+@pytest.mark.parametrize("form", [0, 1])
+def test_assembled_operator(meshes, dense_systems, name, form):
+    """The dense far field (assembled once, vertex basis) reproduces the
+    oracle's operator: 1e-12 with FP64 storage, 1e-5 with FP32 storage."""
+    m = meshes[name]
+    A = dense_systems[(name, form)]
+    x = np.random.default_rng(13).standard_normal(2 * m.n_vertices)
+    ref = A @ x
+    for prec, tol in ((pbm.PB_FP64, 1e-12), (pbm.PB_FP32, 1e-5), (pbm.PB_MIXED_BF16, 1e-5),
+                      (pbm.PB_MIXED_FP16, 1e-5)):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec, operator_mode=pbm.PB_ASSEMBLED)) as h:
+            assert h.info()["assembled"] == 1
+            y = pbm.pb_mesh_apply(h, x)
+            yf = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_FAR_ONLY)
+            yn = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_NEAR_ONLY)
+        assert _rel(y, ref) < tol, (prec, _rel(y, ref))
+        assert _rel(yf + yn, ref) < tol
+
+
+@pytest.mark.parametrize("prec", [pbm.PB_MIXED_BF16, pbm.PB_MIXED_FP16, pbm.PB_FP32])
+@pytest.mark.parametrize("form", [0, 1])
+def test_mixed_precision_solves(meshes, dense_systems, prec, form):
+    """16-bit far field in the inner solves, FP64 iterative refinement on the
+    accurate operator: Delta G within 1e-4 of the FP64 oracle."""
+    m = meshes["star7"]
+    ch = inputs.charges_ball(9, 20, 2.5)
+    ref = oracle.solve(m, ch, formulation=form, A=dense_systems[("star7", form)])
+    got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, prec, operator_mode=pbm.PB_ASSEMBLED))
+    assert got["status"] == pbm.PB_OK
+    assert got["rel_residual"] <= 1e-5 * 1.001
+    assert abs(got["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"]), (got["dG"], ref["dG"])
+    if prec != pbm.PB_FP32:
+        assert got["outer_iterations"] >= 1
+
+
+def test_assembled_full_size_sampled_rows(sphere32):
+    m, _ = sphere32
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal(2 * m.n_vertices)
+    rows = np.sort(rng.choice(m.n_vertices, 8, replace=False))
+    r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, 0, rows, x)
+    ref = np.concatenate([r1, r2])
+    for prec, tol in ((pbm.PB_FP64, 1e-12), (pbm.PB_FP32, 2e-5)):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(0, prec, operator_mode=pbm.PB_ASSEMBLED)) as h:
+            y = pbm.pb_mesh_apply(h, x)
+        nv = m.n_vertices
+        assert _rel(np.concatenate([y[rows], y[nv + rows]]), ref) < tol
+
+
+def test_full_size_mixed_solve(sphere32):
+    """20480-triangle sphere: mixed BF16 / FP16 solves within 1e-4 of the FP64
+    matrix-free GPU solve (certified against the oracle above)."""
+    m, ch = sphere32
+    for form in (0, 1):
+        g64 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form))
+        for prec in (pbm.PB_MIXED_BF16, pbm.PB_MIXED_FP16):
+            g = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, prec, operator_mode=pbm.PB_ASSEMBLED))
+            assert g["status"] == pbm.PB_OK
+            assert abs(g["dG"] - g64["dG"]) < 1e-4 * abs(g64["dG"]), (form, prec, g["dG"], g64["dG"])
