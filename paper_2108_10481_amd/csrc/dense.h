@@ -1,0 +1,34 @@
+// Assembled far field: shared between the single- and multi-right-hand-side paths.
+#pragma once
+#include <vector>
+
+#include "pbm_internal.h"
+
+namespace pbm {
+
+// Dense row-major far-field matrix in the vertex basis.  Rows: [block row 0
+// (V) | block row 1 (V)]; columns: [x1 (V) | 0 | x2 (V) | 0] with each column
+// block padded to Vp (a multiple of 64) so 16-byte loads never straddle blocks.
+struct Dense {
+    int V = 0, n = 0;
+    size_t Vp = 0;                 // column offset of the second block
+    size_t ld = 0;                 // row stride in elements = 2 Vp
+    double *A64 = nullptr;
+    float *A32 = nullptr;
+    uint16_t *A16 = nullptr;
+    int kind16 = 0;                // 0 none, 1 bf16, 2 fp16
+    float scale16[4] = {1, 1, 1, 1};   // fp16: stored = entry * scale (blocks 11, 12, 21, 22)
+    int ncolor = 0;
+    std::vector<int32_t> color_ptr;
+    int32_t *color_tri = nullptr;  // triangles grouped by colour
+    float *x32 = nullptr;          // ld (padded) FP32 copy of x
+    double *x64 = nullptr;         // ld (padded) FP64 copy of x
+    int level = 1;                 // 1: accurate operator, 0: 16-bit operator
+    // multi right-hand side workspaces (allocated on first use)
+    uint16_t *X16 = nullptr;       // 16 x ld
+    double *Y16 = nullptr;         // 16 x n
+};
+
+constexpr int kMaxBatch = 16;
+
+}  // namespace pbm

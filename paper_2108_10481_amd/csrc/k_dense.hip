@@ -19,28 +19,12 @@
 #include <cstring>
 #include <vector>
 
-#include "pbm_internal.h"
+#include "dense.h"
 
 namespace pbm {
 
 int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
 
-struct Dense {
-    int V = 0, n = 0;
-    size_t Vp = 0;                 // column offset of the second block (V rounded up to 64)
-    size_t ld = 0;                 // row stride in elements = 2 Vp
-    double *A64 = nullptr;
-    float *A32 = nullptr;
-    uint16_t *A16 = nullptr;
-    int kind16 = 0;                // 0 none, 1 bf16, 2 fp16
-    float scale16[4] = {1, 1, 1, 1};   // fp16: stored = entry * scale (per block)
-    int ncolor = 0;
-    std::vector<int32_t> color_ptr;
-    int32_t *color_tri = nullptr;  // triangles grouped by colour
-    float *x32 = nullptr;          // ld (padded) FP32 copy of x
-    double *x64 = nullptr;         // ld (padded) FP64 copy of x
-    int level = 1;                 // 1: accurate operator, 0: 16-bit operator
-};
 
 // ------------------------------------------------------------ colouring
 // Greedy colouring of the triangles: two triangles sharing a vertex never get
@@ -566,17 +550,6 @@ int mixed_refinement_solve(DevMesh &d, const double *b, const double *pb, double
     *est = rel;
     *outer = std::min(k, max_outer);
     return its;
-}
-
-pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result *out)
-{
-    pb_status worst = PB_OK;
-    for (int k = 0; k < n_sets; ++k) {
-        pb_status st = solve_on_mesh(d, &sets[k], &out[k]);
-        if (st < 0) return st;
-        if (st > worst) worst = st;
-    }
-    return worst;
 }
 
 }  // namespace pbm

@@ -95,7 +95,8 @@ struct Profiler {
     }
 };
 
-struct Dense;   // assembled far field (k_dense.hip)
+struct Dense;       // assembled far field (k_dense.hip)
+struct BatchWork;   // multi right-hand side workspaces (k_batch.hip)
 
 struct Krylov {
     double *basis = nullptr;   // cap x n Arnoldi vectors
@@ -148,6 +149,7 @@ struct DevMesh {
     double *red = nullptr;         // reduction scratch
     int redcap = 0;
     Dense *dense = nullptr;
+    BatchWork *bw = nullptr;
 
     Profiler prof;
     int64_t npair() const { return (int64_t)hm.pair_s.size(); }
@@ -182,6 +184,11 @@ void destroy_dense(DevMesh &d);
 void dense_apply(DevMesh &d, const double *x, double *yfar);
 int mixed_refinement_solve(DevMesh &d, const double *b, const double *pb, double *u, double *est, int *outer);
 pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result *out);
+void destroy_batch(DevMesh &d);
+void charges_to_device(DevMesh &d, const pb_charges *c);
+void check_charges_inside(DevMesh &d, int nq);
+pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, double *u, int its, int outer,
+                        double t_rhs, double t_prec, double t_gmres, pb_result *res);
 
 // Krylov kernels (k_krylov.hip)
 void kr_dots(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *w, double *out);

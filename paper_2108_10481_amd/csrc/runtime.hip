@@ -45,6 +45,7 @@ DevMesh::~DevMesh()
     for (int k = 0; k < 2; ++k)
         for (hipEvent_t e : prof.ev[k]) (void)hipEventDestroy(e);
     destroy_dense(*this);
+    destroy_batch(*this);
     for (void *p : allocs) (void)hipFree(p);
     if (stream) (void)hipStreamDestroy(stream);
 }
@@ -252,7 +253,7 @@ int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, dou
 }
 
 // ------------------------------------------------------------ charges, dG
-static void upload_charges(DevMesh &d, const pb_charges *c)
+void charges_to_device(DevMesh &d, const pb_charges *c)
 {
     if (!c || c->n < 1 || !c->xyz || !c->q) fail(PB_E_INVALID_ARG, "charges must hold n >= 1 points");
     const int nq = c->n;
@@ -285,7 +286,7 @@ static double *reduction_buffer(DevMesh &d, int npts)
     return d.red;
 }
 
-static void check_inside(DevMesh &d, int nq)
+void check_charges_inside(DevMesh &d, int nq)
 {
     const int C = reduction_chunks(d.hm.T);
     double *part = reduction_buffer(d, nq);
@@ -322,14 +323,49 @@ static void rhs_device(DevMesh &d, int nq, double *b)
     launch_rhs(d, nq, d.qbuf, b);
 }
 
+// Accurate preconditioned residual, reaction potential and Delta G for the
+// solution u of one charge set; fills *res.
+pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, double *u, int its, int outer,
+                        double t_rhs, double t_prec, double t_gmres, pb_result *res)
+{
+    const int V = d.hm.V, n = 2 * V;
+    const double t3 = now();
+        apply_operator(d, u, d.ztmp, PB_APPLY_PRECOND, nullptr);
+    kr_axpy(d.stream, n, -1.0, pb, d.ztmp);
+    kr_dots(d.stream, n, 1, d.ztmp, n, d.ztmp, d.red1);
+    kr_dots(d.stream, n, 1, pb, n, pb, d.red1 + 1);
+    double rr[2];
+    HIPCHECK(hipMemcpyAsync(rr, d.red1, sizeof(rr), hipMemcpyDeviceToHost, d.stream));
+    charges_to_device(d, ch);
+    const int nq = ch->n;
+    std::vector<double> pr(nq);
+    reaction_potential(d, u, nq, d.qbuf + 4 * (size_t)nq, pr.data());
+    double e = 0.0;
+    for (int k = 0; k < nq; ++k) e += ch->q[k] * pr[k];
+    res->dG_kcal = 0.5 * kEnergyC * e;
+    if (res->phi) HIPCHECK(hipMemcpyAsync(res->phi, u, sizeof(double) * V, hipMemcpyDeviceToHost, d.stream));
+    if (res->dphi) HIPCHECK(hipMemcpyAsync(res->dphi, u + V, sizeof(double) * V, hipMemcpyDeviceToHost, d.stream));
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    res->iterations = its;
+    res->outer_iterations = outer;
+    res->rel_residual = rr[1] > 0 ? std::sqrt(std::max(rr[0], 0.0) / rr[1]) : 0.0;
+    res->t_setup = d.t_setup;
+    res->t_rhs = t_rhs;
+    res->t_prec = t_prec;
+    res->t_gmres = t_gmres;
+    res->t_dG = now() - t3;
+    res->device_bytes = d.bytes;
+    return res->rel_residual <= d.opt.tol * 1.0000001 ? PB_OK : PB_NOT_CONVERGED;
+}
+
 pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
 {
     if (!res) fail(PB_E_INVALID_ARG, "result must not be NULL");
     const int V = d.hm.V, n = 2 * V;
     double t0 = now();
-    upload_charges(d, ch);
+    charges_to_device(d, ch);
     const int nq = ch->n;
-    check_inside(d, nq);
+    check_charges_inside(d, nq);
     double *b = d.xtmp, *pb = d.ytmp;
     rhs_device(d, nq, b);
     if (d.prm.formulation == PB_DIRECT_INT) HIPCHECK(hipMemsetAsync(b + V, 0, sizeof(double) * V, d.stream));
@@ -345,35 +381,9 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
         its = mixed_refinement_solve(d, b, pb, d.u, &est, &outer);
     else
         its = gmres(d, pb, d.u, d.opt.tol, d.opt.max_iter, &est);
-    // recomputed preconditioned residual
-    apply_operator(d, d.u, d.ztmp, PB_APPLY_PRECOND, nullptr);
-    kr_axpy(d.stream, n, -1.0, pb, d.ztmp);
-    double *kb = d.kry.kbuf;
-    kr_dots(d.stream, n, 1, d.ztmp, n, d.ztmp, kb);
-    kr_dots(d.stream, n, 1, pb, n, pb, kb + 1);
-    double rr[2];
-    HIPCHECK(hipMemcpyAsync(rr, kb, sizeof(rr), hipMemcpyDeviceToHost, d.stream));
     HIPCHECK(hipStreamSynchronize(d.stream));
     double t3 = now();
-    std::vector<double> pr(nq);
-    reaction_potential(d, d.u, nq, d.qbuf + 4 * (size_t)nq, pr.data());
-    double e = 0.0;
-    for (int k = 0; k < nq; ++k) e += ch->q[k] * pr[k];
-    res->dG_kcal = 0.5 * kEnergyC * e;
-    if (res->phi) HIPCHECK(hipMemcpyAsync(res->phi, d.u, sizeof(double) * V, hipMemcpyDeviceToHost, d.stream));
-    if (res->dphi) HIPCHECK(hipMemcpyAsync(res->dphi, d.u + V, sizeof(double) * V, hipMemcpyDeviceToHost, d.stream));
-    HIPCHECK(hipStreamSynchronize(d.stream));
-    double t4 = now();
-    res->iterations = its;
-    res->outer_iterations = outer;
-    res->rel_residual = rr[1] > 0 ? std::sqrt(std::max(rr[0], 0.0) / rr[1]) : 0.0;
-    res->t_setup = d.t_setup;
-    res->t_rhs = t1 - t0;
-    res->t_prec = t2 - t1;
-    res->t_gmres = t3 - t2;
-    res->t_dG = t4 - t3;
-    res->device_bytes = d.bytes;
-    return res->rel_residual <= d.opt.tol * 1.0000001 ? PB_OK : PB_NOT_CONVERGED;
+    return finish_result(d, ch, pb, d.u, its, outer, t1 - t0, t2 - t1, t3 - t2, res);
 }
 
 }  // namespace pbm
@@ -535,7 +545,7 @@ pb_status pb_mesh_rhs(pb_mesh_handle *h, const pb_charges *charges, double *b)
     PB_TRY
     if (!h || !b) fail(PB_E_INVALID_ARG, "NULL argument");
     DevMesh &d = *h->d;
-    upload_charges(d, charges);
+    charges_to_device(d, charges);
     rhs_device(d, charges->n, d.xtmp);
     HIPCHECK(hipMemcpyAsync(b, d.xtmp, sizeof(double) * 2 * d.hm.V, hipMemcpyDeviceToHost, d.stream));
     HIPCHECK(hipStreamSynchronize(d.stream));
@@ -554,7 +564,7 @@ pb_status pb_mesh_reaction_potential(pb_mesh_handle *h, const double *phi, const
     HIPCHECK(hipMemcpyAsync(d.xtmp + V, dphi, sizeof(double) * V, hipMemcpyHostToDevice, d.stream));
     std::vector<double> q(npts, 0.0);
     pb_charges c{npts, pts, q.data()};
-    upload_charges(d, &c);
+    charges_to_device(d, &c);
     reaction_potential(d, d.xtmp, npts, d.qbuf + 4 * (size_t)npts, out);
     return PB_OK;
     PB_CATCH

@@ -274,3 +274,51 @@ def test_full_size_mixed_solve(sphere32):
             g = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, prec, operator_mode=pbm.PB_ASSEMBLED))
             assert g["status"] == pbm.PB_OK
             assert abs(g["dG"] - g64["dG"]) < 1e-4 * abs(g64["dG"]), (form, prec, g["dG"], g64["dG"])
+
+
+# ------------------------------------------------------- several charge sets
+def _sets(k0, n, nq=12, radius=2.5):
+    return [inputs.charges_ball(k0 + k, nq, radius) for k in range(n)]
+
+
+def test_solve_multi_fp32_bitwise_equals_single(meshes):
+    """Batched lock-step GMRES runs each system's arithmetic exactly as a lone
+    solve does: FP32 assembled results are bitwise identical alone and in the batch."""
+    m = meshes["star7"]
+    sets = _sets(100, 5)
+    opt = _opts(1, pbm.PB_FP32, operator_mode=pbm.PB_ASSEMBLED)
+    with pbm.MeshHandle(m.xyz, m.tri, opt) as h:
+        multi = pbm.pb_solve_multi(h, [(c.xyz, c.q) for c in sets])
+        single = [pbm.pb_mesh_solve(h, c.xyz, c.q) for c in sets]
+    for a, b in zip(multi, single):
+        assert a["dG"] == b["dG"] and a["iterations"] == b["iterations"]
+        assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["dphi"], b["dphi"])
+
+
+@pytest.mark.parametrize("prec", [pbm.PB_MIXED_BF16, pbm.PB_MIXED_FP16])
+@pytest.mark.parametrize("form", [0, 1])
+def test_solve_multi_mfma_matches_oracle(meshes, dense_systems, prec, form):
+    """16 right-hand sides through the MFMA GEMM (16-bit far field) with FP64
+    refinement: every set's Delta G within 1e-4 of the oracle."""
+    m = meshes["star7"]
+    sets = _sets(200, 16)
+    A = dense_systems[("star7", form)]
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec, operator_mode=pbm.PB_ASSEMBLED)) as h:
+        multi = pbm.pb_solve_multi(h, [(c.xyz, c.q) for c in sets])
+    for c, r in zip(sets, multi):
+        ref = oracle.solve(m, c, formulation=form, A=A)
+        assert r["status"] == pbm.PB_OK and r["rel_residual"] <= 1e-5 * 1.001
+        assert abs(r["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"]), (r["dG"], ref["dG"])
+
+
+def test_solve_multi_ragged_batch_and_full_size(sphere32):
+    """20480-triangle sphere, 19 charge sets (a batch of 16 plus a ragged 3):
+    mixed BF16 MFMA solves within 1e-4 of FP64 matrix-free GPU solves."""
+    m, _ = sphere32
+    sets = [inputs.charges_ball(40 + k, 50, 8.0) for k in range(19)]
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(0, pbm.PB_MIXED_BF16, operator_mode=pbm.PB_ASSEMBLED)) as h:
+        multi = pbm.pb_solve_multi(h, [(c.xyz, c.q) for c in sets])
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(0)) as h64:
+        for k in (0, 7, 15, 16, 18):
+            ref = pbm.pb_mesh_solve(h64, sets[k].xyz, sets[k].q)
+            assert abs(multi[k]["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"]), (k, multi[k]["dG"], ref["dG"])
