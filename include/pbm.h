@@ -225,6 +225,49 @@ pb_status pb_mesh_profile(pb_mesh_handle *h, int32_t enable);
 pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launches, double *total_ms,
                                double *total_work);
 
+/* ------------------------------------------------------------------ serving
+ * A solve server batches independent requests continuously: each submitted
+ * request (mesh, charges, options; all copied at submission) waits in arrival
+ * order until a slot is free and its estimated device footprint fits in the
+ * budget beside the requests already running (first fit in arrival order);
+ * then it runs on its own worker thread, HIP stream and memory, overlapping on
+ * the device with the other running requests.  A request's result does not
+ * depend on what runs beside it.  Times are seconds since pb_server_create. */
+typedef struct pb_server pb_server;
+
+typedef struct {
+    double t_submit, t_start, t_end;
+} pb_request_times;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, failed;
+    int32_t running, queued, peak_running;
+    size_t inflight_bytes, peak_inflight_bytes, budget;
+} pb_server_stats;
+
+/* Device bytes a handle for this mesh and these options is expected to hold
+ * (the admission footprint; the server caps each request's handle at it). */
+pb_status pb_estimate_device_bytes(const pb_mesh *mesh, const pb_options *opt, size_t *bytes);
+
+/* hbm_budget: device bytes shared by running requests (0 = 90% of free memory);
+ * max_slots: concurrent requests, 1..64. */
+pb_status pb_server_create(size_t hbm_budget, int32_t max_slots, pb_server **out);
+/* Cancels queued requests, waits for running ones, frees everything. */
+pb_status pb_server_destroy(pb_server *s);
+/* Queue a request; *ticket identifies it.  PB_E_NOMEM if its footprint exceeds
+ * the whole budget (it could never be admitted). */
+pb_status pb_submit(pb_server *s, const pb_mesh *mesh, const pb_charges *charges, const pb_options *opt,
+                    uint64_t *ticket);
+/* *done = 1 once the request has finished (successfully or not). */
+pb_status pb_poll(pb_server *s, uint64_t ticket, int32_t *done);
+/* Remove a request that has not started; PB_E_STATE if it is running or done. */
+pb_status pb_cancel(pb_server *s, uint64_t ticket);
+/* Block until the request finishes, fill *out (phi / dphi: caller buffers of
+ * n_vertices doubles or NULL) and *times (may be NULL), and release the
+ * ticket.  Returns the solve's status (or the error that ended it). */
+pb_status pb_wait(pb_server *s, uint64_t ticket, pb_result *out, pb_request_times *times);
+pb_status pb_server_get_stats(pb_server *s, pb_server_stats *stats);
+
 /* Block until all work of the handle is done. */
 pb_status pb_mesh_synchronize(pb_mesh_handle *h);
 

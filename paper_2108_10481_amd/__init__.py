@@ -73,6 +73,17 @@ class pb_result(ctypes.Structure):
                 ("t_gmres", ctypes.c_double), ("t_dG", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
 
 
+class pb_request_times(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_end", ctypes.c_double)]
+
+
+class pb_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("running", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("peak_running", ctypes.c_int32), ("inflight_bytes", ctypes.c_size_t),
+                ("peak_inflight_bytes", ctypes.c_size_t), ("budget", ctypes.c_size_t)]
+
+
 class pb_mesh_info(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int32), ("n_triangles", ctypes.c_int32),
                 ("n_near_pairs", ctypes.c_int64), ("near_nnz", ctypes.c_int64),
@@ -83,7 +94,9 @@ class pb_mesh_info(ctypes.Structure):
 EXPORTS = ["pb_default_options", "pb_last_error", "pb_device_count", "pb_solve", "pb_mesh_create",
            "pb_mesh_destroy", "pb_mesh_get_info", "pb_mesh_refresh", "pb_mesh_solve", "pb_solve_multi", "pb_mesh_apply",
            "pb_mesh_apply_device", "pb_mesh_rhs", "pb_mesh_reaction_potential", "pb_mesh_near_blocks",
-           "pb_mesh_preconditioner", "pb_mesh_profile", "pb_mesh_profile_read", "pb_mesh_synchronize"]
+           "pb_mesh_preconditioner", "pb_mesh_profile", "pb_mesh_profile_read", "pb_mesh_synchronize",
+           "pb_estimate_device_bytes", "pb_server_create", "pb_server_destroy", "pb_submit", "pb_poll", "pb_cancel",
+           "pb_wait", "pb_server_get_stats"]
 
 _lib = None
 
@@ -121,6 +134,14 @@ def load():
     L.pb_mesh_profile_read.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_double),
                                        P(ctypes.c_double)]
     L.pb_mesh_synchronize.argtypes = [vp]
+    L.pb_estimate_device_bytes.argtypes = [P(pb_mesh), P(pb_options), P(ctypes.c_size_t)]
+    L.pb_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, P(vp)]
+    L.pb_server_destroy.argtypes = [vp]
+    L.pb_submit.argtypes = [vp, P(pb_mesh), P(pb_charges), P(pb_options), P(ctypes.c_uint64)]
+    L.pb_poll.argtypes = [vp, ctypes.c_uint64, P(ctypes.c_int32)]
+    L.pb_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.pb_wait.argtypes = [vp, ctypes.c_uint64, P(pb_result), P(pb_request_times)]
+    L.pb_server_get_stats.argtypes = [vp, P(pb_server_stats)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("pb_default_options", "pb_last_error", "pb_device_count"):
@@ -344,3 +365,72 @@ def pb_mesh_profile_read(h: MeshHandle, kind: int = 0):
 
 def pb_mesh_synchronize(h: MeshHandle) -> None:
     _check(load().pb_mesh_synchronize(h.h))
+
+
+def pb_estimate_device_bytes(xyz, tri, options: pb_options | None = None) -> int:
+    m, keep = _mesh_struct(xyz, tri)
+    b = ctypes.c_size_t()
+    _check(load().pb_estimate_device_bytes(ctypes.byref(m), ctypes.byref(options or pb_default_options()),
+                                           ctypes.byref(b)))
+    return int(b.value)
+
+
+class Server:
+    """Continuous-batching solve server (pb_server_create / pb_server_destroy)."""
+
+    def __init__(self, hbm_budget: int = 0, max_slots: int = 4):
+        h = ctypes.c_void_p()
+        _check(load().pb_server_create(int(hbm_budget), int(max_slots), ctypes.byref(h)))
+        self.h = h
+        self.nv = {}
+
+    def submit(self, xyz, tri, qxyz, q, options: pb_options | None = None) -> int:
+        m, k1 = _mesh_struct(xyz, tri)
+        c, k2 = _charges_struct(qxyz, q)
+        t = ctypes.c_uint64()
+        _check(load().pb_submit(self.h, ctypes.byref(m), ctypes.byref(c),
+                                ctypes.byref(options or pb_default_options()), ctypes.byref(t)))
+        self.nv[t.value] = m.n_vertices
+        return int(t.value)
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(load().pb_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        return bool(d.value)
+
+    def cancel(self, ticket: int) -> None:
+        _check(load().pb_cancel(self.h, ctypes.c_uint64(ticket)))
+
+    def wait(self, ticket: int) -> dict:
+        r, phi, dphi = _result(self.nv.pop(ticket))
+        tm = pb_request_times()
+        st = _check(load().pb_wait(self.h, ctypes.c_uint64(ticket), ctypes.byref(r), ctypes.byref(tm)))
+        out = _result_dict(st, r, phi, dphi)
+        out.update({"t_submit": tm.t_submit, "t_start": tm.t_start, "t_end": tm.t_end})
+        return out
+
+    def stats(self) -> dict:
+        s = pb_server_stats()
+        _check(load().pb_server_get_stats(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in pb_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _check(load().pb_server_destroy(self.h))
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pb_server_create(hbm_budget: int = 0, max_slots: int = 4) -> Server:
+    return Server(hbm_budget, max_slots)

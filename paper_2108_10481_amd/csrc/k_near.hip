@@ -4,6 +4,8 @@
 // vertex blocks of the chosen formulation (mass terms included), and the
 // block-diagonal preconditioner (Preconditioning, Algebraic preconditioners).
 // Everything here is FP64 in every precision mode.
+#include <mutex>
+
 #include "pbm_internal.h"
 
 namespace pbm {
@@ -14,13 +16,13 @@ __constant__ double c_gl_w[kMaxGL + 1][kMaxGL];
 
 void upload_gauss_tables()
 {
-    static bool done = false;
-    if (done) return;
-    double hx[kMaxGL + 1][kMaxGL] = {}, hw[kMaxGL + 1][kMaxGL] = {};
-    for (int n = 1; n <= kMaxGL; ++n) gauss_legendre01(n, hx[n], hw[n]);
-    HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_x), hx, sizeof(hx)));
-    HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), hw, sizeof(hw)));
-    done = true;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        static double hx[kMaxGL + 1][kMaxGL] = {}, hw[kMaxGL + 1][kMaxGL] = {};
+        for (int n = 1; n <= kMaxGL; ++n) gauss_legendre01(n, hx[n], hw[n]);
+        HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_x), hx, sizeof(hx)));
+        HIPCHECK(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), hw, sizeof(hw)));
+    });
 }
 
 // Reference triangle {0 <= u2 <= u1 <= 1}, chi(u) = P0 + u1 (P1 - P0) + u2 (P2 - P1),

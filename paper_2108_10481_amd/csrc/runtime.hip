@@ -33,7 +33,8 @@ void *DevMesh::alloc(size_t n)
     n = std::max<size_t>(n, 256);
     if (opt.memory_budget && bytes + n > opt.memory_budget)
         fail(PB_E_NOMEM, "device memory budget of the handle exceeded");
-    HIPCHECK(hipMalloc(&p, n));
+    // stream-ordered allocation: frees of one handle never stall another handle's stream
+    HIPCHECK(hipMallocAsync(&p, n, stream));
     allocs.push_back(p);
     bytes += n;
     return p;
@@ -46,7 +47,8 @@ DevMesh::~DevMesh()
         for (hipEvent_t e : prof.ev[k]) (void)hipEventDestroy(e);
     destroy_dense(*this);
     destroy_batch(*this);
-    for (void *p : allocs) (void)hipFree(p);
+    for (void *p : allocs) (void)hipFreeAsync(p, stream);
+    if (stream) (void)hipStreamSynchronize(stream);
     if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -146,6 +148,32 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     HIPCHECK(hipStreamSynchronize(d->stream));
     d->t_setup = now() - t0;
     return d.release();
+}
+
+DevMesh *create_mesh_checked(const pb_mesh *mesh, const pb_options *opt) { return create_mesh(mesh, opt); }
+
+// Device bytes a handle is expected to hold for V vertices, T triangles:
+// geometry and source/target records, far-field partial sums, near pairs and
+// near blocks (about 14 T pairs and 20 V nonzeros per block on molecular
+// surfaces, with margin), work vectors, the Arnoldi basis, and the dense far
+// field in assembled modes.
+size_t estimate_device_bytes(int V, int T, const pb_options *o)
+{
+    const double v = V, t = T, n = 2.0 * V;
+    const int S = o->source_chunks > 0 ? std::min(o->source_chunks, T) : choose_chunks(T);
+    double b = t * (kGeo * 8 + kStat * 12 + kDyn * 12 + 6 * 8 + 12 * 8 + 3 * 4 * 2);
+    b += (double)S * t * 16 * 8;
+    b += 16.0 * t * (36 * 8 + 3 * 4);
+    b += 24.0 * v * (4 * 8 + 4) + v * (4 * 8 + 4 * 4);
+    b += 12.0 * n * 8;
+    const bool mixed = o->precision >= PB_MIXED_BF16;
+    const double m = std::min<double>(mixed ? std::min(o->inner_max_iter, o->max_iter) : o->max_iter, n) + 2;
+    b += m * n * 8;
+    const double Vp = std::ceil(v / 64.0) * 64.0;
+    const double dense = n * 2.0 * Vp * (o->precision == PB_FP64 ? 8.0 : 4.0) + (mixed ? n * 2.0 * Vp * 2.0 : 0.0);
+    if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense;
+    b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
+    return (size_t)(b * 1.1);
 }
 
 // y = A x (or P^-1 A x) on device vectors, on stream s of the handle.

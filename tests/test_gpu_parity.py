@@ -322,3 +322,67 @@ def test_solve_multi_ragged_batch_and_full_size(sphere32):
         for k in (0, 7, 15, 16, 18):
             ref = pbm.pb_mesh_solve(h64, sets[k].xyz, sets[k].q)
             assert abs(multi[k]["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"]), (k, multi[k]["dG"], ref["dG"])
+
+
+# ------------------------------------------------------------------ serving
+def _requests():
+    out = []
+    for k, (f, prec, form) in enumerate([(4, pbm.PB_MIXED_BF16, 0), (9, pbm.PB_FP32, 1), (6, pbm.PB_MIXED_FP16, 1),
+                                         (12, pbm.PB_MIXED_BF16, 1), (5, pbm.PB_FP32, 0), (10, pbm.PB_MIXED_BF16, 0)]):
+        base = 18.0 * (20 * f * f / 81920.0) ** 0.5
+        mesh, shape = inputs.star_surface(300 + k, f, base)
+        ch = inputs.charges_in_star(400 + k, 30 + 10 * k, shape, values="uniform")
+        opt = pbm.pb_default_options(formulation=form, precision=prec, operator_mode=pbm.PB_ASSEMBLED)
+        out.append((mesh, ch, opt))
+    return out
+
+
+def test_server_same_alone_and_in_the_mix():
+    """Requests of different sizes, formulations and precisions run together on
+    the server (overlapping on the device) give bitwise the results they give
+    alone."""
+    reqs = _requests()
+    alone = []
+    for mesh, ch, opt in reqs:
+        o = pbm.pb_default_options()
+        for f, _ in pbm.pb_options._fields_:
+            setattr(o, f, getattr(opt, f))
+        o.memory_budget = pbm.pb_estimate_device_bytes(mesh.xyz, mesh.tri, opt)
+        alone.append(pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q, o))
+    with pbm.Server(max_slots=4) as s:
+        tickets = [s.submit(m.xyz, m.tri, c.xyz, c.q, o) for m, c, o in reqs]
+        mixed = [s.wait(t) for t in tickets]
+        st = s.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["peak_running"] >= 2, st
+    for a, b in zip(alone, mixed):
+        assert a["dG"] == b["dG"] and a["iterations"] == b["iterations"]
+        assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["dphi"], b["dphi"])
+
+
+def test_server_admission_by_footprint_and_cancel():
+    """Equal-size requests under a budget that fits only one of them run one
+    at a time; a queued request can be cancelled; results stay correct."""
+    mesh, ch, opt = _requests()[3]
+    sets = [inputs.charges_ball(500 + k, 20, 2.0) for k in range(3)]
+    est = pbm.pb_estimate_device_bytes(mesh.xyz, mesh.tri, opt)
+    with pbm.Server(hbm_budget=int(est * 1.5), max_slots=4) as s:
+        tickets = [s.submit(mesh.xyz, mesh.tri, c.xyz, c.q, opt) for c in sets]
+        extra = s.submit(mesh.xyz, mesh.tri, ch.xyz, ch.q, opt)
+        try:
+            s.cancel(extra)
+            cancelled = True
+        except pbm.PbError as e:
+            assert e.code == pbm.PB_E_STATE     # it had already started
+            cancelled = False
+        res = [s.wait(t) for t in tickets]
+        if not cancelled:
+            s.wait(extra)
+        st = s.stats()
+    assert st["peak_running"] == 1, st
+    assert st["peak_inflight_bytes"] <= int(est * 1.5)
+    for r in res:
+        assert r["status"] == pbm.PB_OK
+    spans = sorted((r["t_start"], r["t_end"]) for r in res)
+    for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
+        assert s1 >= e0 - 1e-3, spans     # never two requests on the device at once

@@ -100,3 +100,30 @@ def test_valid_mesh_without_gpu_fails_loudly(pbm):
     m = inputs.icosphere(2, 1.0)
     assert _create_status(pbm, m.xyz, m.tri) == pbm.PB_E_DEVICE
     assert "device" in pbm.pb_last_error().lower()
+
+
+def test_server_host_logic_without_gpu(pbm):
+    """Queueing, admission refusal and error propagation run on the host."""
+    m = inputs.icosphere(4, 2.0)
+    ch = inputs.charges_ball(1, 3, 1.0)
+    opt = pbm.pb_default_options(operator_mode=pbm.PB_ASSEMBLED, precision=pbm.PB_MIXED_BF16)
+    est = pbm.pb_estimate_device_bytes(m.xyz, m.tri, opt)
+    big = inputs.icosphere(16, 2.0)
+    assert pbm.pb_estimate_device_bytes(big.xyz, big.tri, opt) > est
+    with pbm.Server(hbm_budget=3 * est, max_slots=2) as s:
+        with pytest.raises(pbm.PbError) as e:
+            s.submit(big.xyz, big.tri, ch.xyz, ch.q, opt)          # can never be admitted
+        assert e.value.code == pbm.PB_E_NOMEM
+        bad = m.tri.copy()
+        bad[0] = bad[0][::-1]
+        t_bad = s.submit(m.xyz, bad, ch.xyz, ch.q, opt)
+        with pytest.raises(pbm.PbError) as e:
+            s.wait(t_bad)
+        assert e.value.code == pbm.PB_E_MESH                        # validated in the worker
+        if pbm.pb_device_count() == 0:
+            t = s.submit(m.xyz, m.tri, ch.xyz, ch.q, opt)
+            with pytest.raises(pbm.PbError) as e:
+                s.wait(t)
+            assert e.value.code == pbm.PB_E_DEVICE
+        st = s.stats()
+        assert st["submitted"] >= 1 and st["failed"] >= 1 and st["running"] == 0
