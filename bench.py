@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--operator-mode", default="auto", choices=["matrix-free", "assembled", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=160, help="oracle rows per formulation in the CPU sample")
-    return ap.parse_args()
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "star", "multi", "serving"])
+    return ap.parse_known_args()[0]
 
 
 def main():
@@ -65,7 +66,16 @@ def main():
     prec = {"fp64": pbm.PB_FP64, "fp32": pbm.PB_FP32, "mixed-bf16": pbm.PB_MIXED_BF16,
             "mixed-fp16": pbm.PB_MIXED_FP16}[a.precision]
     mode = {"matrix-free": pbm.PB_MATRIX_FREE, "assembled": pbm.PB_ASSEMBLED, "auto": pbm.PB_AUTO}[a.operator_mode]
-    mesh, ch = inputs.config_sphere()
+    if a.workload == "star":
+        mesh, ch = inputs.config_star()
+        workload = ("star surface R=18 A (1 + 0.15 sum Y_lm, l<=6, seed 3), 81920 triangles / 40962 vertices, 2000 "
+                    "charges N(0,0.4) e inside 0.8 r, eps 4/80, kappa 0.125, direct + Juffer, block-diagonal, "
+                    "GMRES tol 1e-5; one step = one solve per formulation")
+    else:
+        mesh, ch = inputs.config_sphere()
+        workload = ("sphere R=10 A, icosphere 20480 triangles / 10242 vertices, 50 charges U[-1,1] e in r<8 A "
+                    "(seed 2), eps 4/80, kappa 0.125, direct + Juffer, block-diagonal, GMRES tol 1e-5; "
+                    "one step = one solve per formulation")
     T = mesh.n_triangles
     P = 6 * T
     forms = (pbm.PB_DIRECT_INT, pbm.PB_JUFFER)
@@ -118,9 +128,9 @@ def main():
         # dominant kernel: the far-field assembly (VALU); the dense product is
         # reported against the HBM roofline beside it
         evals = sum(prof_asm[f][2] for f in forms)
-        # algorithmic: each far point pair once (recorded work counts it once
-        # per source vertex, 3x), kernel formula + 4 values x 9 basis products (FMA)
-        flops = sum(prof_asm[f][2] / 3.0 * (FLOPS_PER_PAIR[f] + 72) for f in forms)
+        # algorithmic: each far point pair once (the recorded work), kernel
+        # formula + 4 combined values x 9 basis products (FMA = 2 flops)
+        flops = sum(prof_asm[f][2] * (FLOPS_PER_PAIR[f] + 72) for f in forms)
         achieved = flops / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0
         nasm = sum(prof_asm[f][0] for f in forms)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
@@ -154,9 +164,7 @@ def main():
         "ms_per_step": round(1e3 * elapsed / a.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": "sphere R=10 A, icosphere 20480 triangles / 10242 vertices, 50 charges U[-1,1] e "
-                               "in r<8 A (seed 2), eps 4/80, kappa 0.125, direct + Juffer, block-diagonal, "
-                               "GMRES tol 1e-5; one step = one solve per formulation",
+        "config": {"workload": workload,
                    "precision": a.precision, "operator_mode": "assembled" if assembled else "matrix-free",
                    "source_chunks": info[forms[0]]["source_chunks"]},
         "kernel_pairs_per_s": round(kernel_pairs / (kern_ms * 1e-3), 1) if kernel_pairs and kern_ms > 0 else None,
@@ -303,8 +311,57 @@ def serving(argv=None):
     print(json.dumps(rec), flush=True)
 
 
+def multi(argv=None):
+    """16 charge sets on the 40962-vertex sphere, solved together on one
+    resident mesh (pb_solve_multi): the MFMA GEMM on the 16-bit far field."""
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--freq", type=int, default=64)
+    a, _ = ap.parse_known_args(argv)
+    import paper_2108_10481_amd as pbm
+    mesh, sets = inputs.config_sphere_multi(freq=a.freq)
+    args = [(c.xyz, c.q) for c in sets]
+    out = {}
+    ref = None
+    for name, prec in (("fp64", pbm.PB_FP64), ("fp32", pbm.PB_FP32), ("mixed-bf16", pbm.PB_MIXED_BF16),
+                       ("mixed-fp16", pbm.PB_MIXED_FP16)):
+        with pbm.MeshHandle(mesh.xyz, mesh.tri, pbm.pb_default_options(precision=prec,
+                                                                       operator_mode=pbm.PB_ASSEMBLED)) as h:
+            t_setup = h.info()
+            res = pbm.pb_solve_multi(h, args)
+            if name == "fp64":
+                ref = [r["dG"] for r in res]
+            steps = 1 if name == "fp64" else a.steps
+            for _ in range(0 if name == "fp64" else a.warmup):
+                pbm.pb_solve_multi(h, args)
+            pbm.pb_mesh_profile(h, True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res = pbm.pb_solve_multi(h, args)
+            dt = (time.perf_counter() - t0) / steps
+            n, ms, work = pbm.pb_mesh_profile_read(h, 0)
+            err = max(abs(r["dG"] - g) / abs(g) for r, g in zip(res, ref))
+            out[name] = {"solves_per_s": round(len(sets) / dt, 3), "s_per_16_set_batch": round(dt, 4),
+                         "inner_iterations_max": max(r["iterations"] for r in res),
+                         "outer_iterations_max": max(r["outer_iterations"] for r in res),
+                         "dG_rel_err_vs_fp64_max": err,
+                         "operator_product": {"launches": n, "avg_ms": round(ms / max(n, 1), 4),
+                                              "GB_per_s": round(work / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                                              "hbm_frac": round(work / (ms * 1e-3) / 8e12, 4) if ms > 0 else None},
+                         "device_GB": round(t_setup["device_bytes"] / 1e9, 2)}
+    rec = {"workload": f"sphere R=10 A, {mesh.n_triangles} triangles / {mesh.n_vertices} vertices, 16 charge sets x "
+                       "50 charges (seeds 40..55), direct formulation, assembled far field; resident mesh, "
+                       "pb_solve_multi per batch (setup excluded)", "results": out}
+    print(json.dumps(rec), flush=True)
+
+
 if __name__ == "__main__":
-    if "--workload" in sys.argv and "serving" in sys.argv:
+    wl = sys.argv[sys.argv.index("--workload") + 1] if "--workload" in sys.argv else "sphere"
+    if wl == "serving":
         serving()
+    elif wl == "multi":
+        multi()
     else:
         main()

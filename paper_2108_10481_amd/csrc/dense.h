@@ -20,10 +20,21 @@ struct Dense {
     float scale16[4] = {1, 1, 1, 1};   // fp16: stored = entry * scale (blocks 11, 12, 21, 22)
     int ncolor = 0;
     std::vector<int32_t> color_ptr;
-    int32_t *color_tri = nullptr;  // triangles grouped by colour
+    int32_t *color_tri = nullptr;  // target triangles grouped by colour
+    // source tiles: consecutive Morton-ordered triangles, coloured so that
+    // tiles of one colour touch disjoint vertices
+    int tile = 256;
+    int ntile = 0, ntcolor = 0;
+    std::vector<int32_t> tcolor_ptr;
+    int32_t *tcolor_tile = nullptr;
+    int32_t *tv_ptr = nullptr, *tv_col = nullptr, *tv_eptr = nullptr, *te = nullptr;
+    // dense index of each vertex (first touch in tile order) and its inverse
+    int32_t *vpos = nullptr, *vperm = nullptr;
     float *x32 = nullptr;          // ld (padded) FP32 copy of x
     double *x64 = nullptr;         // ld (padded) FP64 copy of x
     int level = 1;                 // 1: accurate operator, 0: 16-bit operator
+    int gemv_hi = -1, gemv_lo = -1;   // autotuned GEMV variants (-1: not tuned yet)
+    int gemm_rows = 0;                // autotuned rows per wavefront of the MFMA GEMM (0: not tuned)
     // multi right-hand side workspaces (allocated on first use)
     uint16_t *X16 = nullptr;       // 16 x ld
     double *Y16 = nullptr;         // 16 x n

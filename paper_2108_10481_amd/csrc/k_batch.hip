@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <functional>
+#include <string>
 #include <vector>
 
 #include "dense.h"
@@ -26,6 +28,7 @@ pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, doub
                         double t_rhs, double t_prec, double t_gmres, pb_result *res);
 void charges_to_device(DevMesh &d, const pb_charges *c);
 void check_charges_inside(DevMesh &d, int nq);
+int autotune_pick(const std::string &key, int nvariants, const std::function<void(int)> &run, hipStream_t st);
 
 // ------------------------------------------------------------------ GEMM
 // One wavefront per 16-row tile, all 16 right-hand sides.  v_mfma_f32_16x16x32
@@ -33,6 +36,16 @@ void check_charges_inside(DevMesh &d, int nq);
 // l%16]; result D[row 4(l/16) + i][col l%16], i = 0..3.  The two column blocks
 // are accumulated separately so FP16 block scales can be undone per block.
 template <int KIND>
+__device__ __forceinline__ f32x4 mfma16(const uint16_t *a, const uint16_t *b, f32x4 c)
+{
+    if constexpr (KIND == 1)
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf16x8 *)a, *(const bf16x8 *)b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(*(const f16x8 *)a, *(const f16x8 *)b, c, 0, 0, 0);
+}
+
+// RT row tiles of 16 per wavefront share each B (x) fragment.
+template <int KIND, int RT>
 __global__ __launch_bounds__(256) void k_gemm16(int n, int V, size_t Vp, size_t ld, const uint16_t *__restrict__ A,
                                                 const uint16_t *__restrict__ X, float i0, float i1, float i2, float i3,
                                                 double *__restrict__ Y)
@@ -40,43 +53,39 @@ __global__ __launch_bounds__(256) void k_gemm16(int n, int V, size_t Vp, size_t 
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
     const int nwave = gridDim.x * 4;
-    const int ntile = (n + 15) / 16;
+    const int ntile = (n + 16 * RT - 1) / (16 * RT);
     const int kq = (lane >> 4) * 8;
     const int cl = lane & 15;
+    const uint16_t *xrow = X + (size_t)cl * ld + kq;
     for (int tile = wave; tile < ntile; tile += nwave) {
-        const int r0 = tile * 16;
-        const int ar = min(r0 + cl, n - 1);   // rows past n re-read row n-1; their results are dropped
-        const uint16_t *arow = A + (size_t)ar * ld + kq;
-        const uint16_t *xrow = X + (size_t)cl * ld + kq;
-        f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-        for (size_t k = 0; k < Vp; k += 32) {
-            if constexpr (KIND == 1) {
-                const bf16x8 a = *(const bf16x8 *)(arow + k), b = *(const bf16x8 *)(xrow + k);
-                c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c0, 0, 0, 0);
-            } else {
-                const f16x8 a = *(const f16x8 *)(arow + k), b = *(const f16x8 *)(xrow + k);
-                c0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c0, 0, 0, 0);
-            }
-        }
-#pragma unroll 4
-        for (size_t k = Vp; k < ld; k += 32) {
-            if constexpr (KIND == 1) {
-                const bf16x8 a = *(const bf16x8 *)(arow + k), b = *(const bf16x8 *)(xrow + k);
-                c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c1, 0, 0, 0);
-            } else {
-                const f16x8 a = *(const f16x8 *)(arow + k), b = *(const f16x8 *)(xrow + k);
-                c1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c1, 0, 0, 0);
-            }
-        }
+        const int r0 = tile * 16 * RT;
+        const uint16_t *arow[RT];
+        f32x4 c0[RT], c1[RT];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = r0 + 4 * (lane >> 4) + i;
-            if (r < n) {
-                const bool top = r < V;
-                Y[(size_t)cl * n + r] = (double)c0[i] * (top ? i0 : i2) + (double)c1[i] * (top ? i1 : i3);
-            }
+        for (int t = 0; t < RT; ++t) {
+            // rows past n re-read row n-1; their results are dropped
+            arow[t] = A + (size_t)min(r0 + 16 * t + cl, n - 1) * ld + kq;
+            c0[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            c1[t] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
+#pragma unroll 4
+        for (size_t k = 0; k < Vp; k += 32)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) c0[t] = mfma16<KIND>(arow[t] + k, xrow + k, c0[t]);
+#pragma unroll 4
+        for (size_t k = Vp; k < ld; k += 32)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) c1[t] = mfma16<KIND>(arow[t] + k, xrow + k, c1[t]);
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + 16 * t + 4 * (lane >> 4) + i;
+                if (r < n) {
+                    const bool top = r < V;
+                    Y[(size_t)cl * n + r] = (double)c0[t][i] * (top ? i0 : i2) + (double)c1[t][i] * (top ? i1 : i3);
+                }
+            }
     }
 }
 
@@ -88,16 +97,16 @@ __device__ __forceinline__ uint16_t f2bf16(float f)
 }
 
 // X16[c][k] in the padded column layout, c < nb from the FP64 systems, zero otherwise
-__global__ void k_pad_batch(int V, int n, int nb, size_t Vp, size_t ld, int kind, const double *__restrict__ Xs,
-                            uint16_t *__restrict__ X16)
+__global__ void k_pad_batch(int V, int n, int nb, size_t Vp, size_t ld, int kind, const int32_t *__restrict__ vperm,
+                            const double *__restrict__ Xs, uint16_t *__restrict__ X16)
 {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (k >= ld) return;
     double v = 0.0;
     if (c < nb) {
-        if (k < (size_t)V) v = Xs[(size_t)c * n + k];
-        else if (k >= Vp && k < Vp + (size_t)V) v = Xs[(size_t)c * n + V + (k - Vp)];
+        if (k < (size_t)V) v = Xs[(size_t)c * n + vperm[k]];
+        else if (k >= Vp && k < Vp + (size_t)V) v = Xs[(size_t)c * n + V + vperm[k - Vp]];
     }
     uint16_t o;
     if (kind == 1) o = f2bf16((float)v);
@@ -109,14 +118,15 @@ __global__ void k_pad_batch(int V, int n, int nb, size_t Vp, size_t ld, int kind
 // optional 2x2 preconditioner
 __global__ void k_gather_batch(int V, int n, int precond, const int32_t *__restrict__ row_ptr,
                                const int32_t *__restrict__ col, const double *__restrict__ N, int64_t nnz,
-                               const double *__restrict__ pinv, const double *__restrict__ Yfar,
-                               const double *__restrict__ X, double *__restrict__ Y)
+                               const double *__restrict__ pinv, const int32_t *__restrict__ vpos,
+                               const double *__restrict__ Yfar, const double *__restrict__ X, double *__restrict__ Y)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
     if (i >= V) return;
     const double *x = X + (size_t)s * n;
-    double y1 = Yfar[(size_t)s * n + i], y2 = Yfar[(size_t)s * n + V + i];
+    const int r = vpos[i];   // dense row order
+    double y1 = Yfar[(size_t)s * n + r], y2 = Yfar[(size_t)s * n + V + r];
     double n1 = 0.0, n2 = 0.0;
     for (int sl = row_ptr[i]; sl < row_ptr[i + 1]; ++sl) {
         const int j = col[sl];
@@ -241,7 +251,31 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
             D->Y16 = (double *)d.alloc(sizeof(double) * kMaxBatch * n);
         }
         hipLaunchKernelGGL(k_pad_batch, dim3((unsigned)((D->ld + 255) / 256), kMaxBatch), dim3(256), 0, d.stream, V, n,
-                           nb, D->Vp, D->ld, D->kind16, X, D->X16);
+                           nb, D->Vp, D->ld, D->kind16, D->vperm, X, D->X16);
+        float inv[4] = {1.f, 1.f, 1.f, 1.f};
+        if (D->kind16 == 2)
+            for (int b = 0; b < 4; ++b) inv[b] = 1.f / D->scale16[b];
+        auto launch = [&](int v) {   // v = 0: one 16-row tile per wavefront, 1: two
+            const int rt = v == 0 ? 1 : 2;
+            const int ntile = (n + 16 * rt - 1) / (16 * rt);
+            const int nwg = std::min((ntile + 3) / 4, 4096);
+            if (D->kind16 == 1 && rt == 1)
+                hipLaunchKernelGGL((k_gemm16<1, 1>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
+                                   D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
+            else if (D->kind16 == 1)
+                hipLaunchKernelGGL((k_gemm16<1, 2>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
+                                   D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
+            else if (rt == 1)
+                hipLaunchKernelGGL((k_gemm16<2, 1>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
+                                   D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
+            else
+                hipLaunchKernelGGL((k_gemm16<2, 2>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
+                                   D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
+        };
+        if (D->gemm_rows == 0) {
+            const std::string key = std::string("gemm16/") + (D->kind16 == 1 ? "bf16/" : "fp16/") + std::to_string(n);
+            D->gemm_rows = 1 + autotune_pick(key, 2, launch, d.stream);
+        }
         Profiler &pf = d.prof;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (pf.enabled) {
@@ -249,23 +283,13 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
             HIPCHECK(hipEventCreate(&e1));
             HIPCHECK(hipEventRecord(e0, d.stream));
         }
-        const int ntile = (n + 15) / 16;
-        const int nwg = std::min((ntile + 3) / 4, 4096);
-        float inv[4] = {1.f, 1.f, 1.f, 1.f};
-        if (D->kind16 == 2)
-            for (int b = 0; b < 4; ++b) inv[b] = 1.f / D->scale16[b];
-        if (D->kind16 == 1)
-            hipLaunchKernelGGL(k_gemm16<1>, dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16, D->X16,
-                               inv[0], inv[1], inv[2], inv[3], D->Y16);
-        else
-            hipLaunchKernelGGL(k_gemm16<2>, dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16, D->X16,
-                               inv[0], inv[1], inv[2], inv[3], D->Y16);
+        launch(D->gemm_rows - 1);
         if (pf.enabled) {
             HIPCHECK(hipEventRecord(e1, d.stream));
             pf.record(0, e0, e1, (double)n * n * 2.0 + kMaxBatch * (double)n * (2.0 + 8.0));
         }
         hipLaunchKernelGGL(k_gather_batch, dim3((V + 255) / 256, nb), dim3(256), 0, d.stream, V, n, 1, d.row_ptr, d.col,
-                           d.N, d.nnz(), d.pinv, D->Y16, X, Y);
+                           d.N, d.nnz(), d.pinv, D->vpos, D->Y16, X, Y);
         HIPCHECK(hipGetLastError());
     } else {
         for (int s = 0; s < nb; ++s) apply_operator(d, X + (size_t)s * n, Y + (size_t)s * n, PB_APPLY_PRECOND, nullptr);

@@ -17,6 +17,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
+#include <string>
 #include <vector>
 
 #include "dense.h"
@@ -73,59 +75,61 @@ __device__ __forceinline__ double rsq_a(double x)
 __device__ __forceinline__ float expn_a(float kl, float r) { return __builtin_amdgcn_exp2f(-kl * r); }
 __device__ __forceinline__ double expn_a(double k, double r) { return exp(-k * r); }
 
-// One thread per (target triangle t of the current colour, source vertex j):
-// loops over the source triangles s containing j that share no vertex with t
-// and adds the local block column l(j) of pair (t, s) to rows t_0, t_1, t_2.
-// Per point pair four combined kernel values are formed (FORM 0, direct:
-// F_L d.n_s, -G_L, -F_Y d.n_s, eps G_Y; FORM 1, Juffer: (F_L - alpha F_Y) d.n_s,
-// G_Y - G_L, G_Y, (F_L - beta F_Y) d.n_t) and weighted with the test basis.
-template <typename R, typename S, int FORM>
-__global__ __launch_bounds__(256) void k_assemble(int V, AsmCoef<R> cf, const int32_t *__restrict__ tris_of_color,
-                                                   const int32_t *__restrict__ tri, const R *__restrict__ stat,
-                                                   const double *__restrict__ geo, const int32_t *__restrict__ inc_ptr,
-                                                   const int32_t *__restrict__ inc_tk, S *__restrict__ A, size_t ld,
-                                                   size_t Vp)
+// Block = (target triangle t of the current colour, tile of TILE Morton-ordered
+// source triangles of the current tile colour).
+// Phase 1: lane s computes the whole local 3 x 3 block of the pair (t, s) for
+//   the four combined operator values -- every far point pair is evaluated
+//   exactly once -- into LDS (zero if s shares a vertex with t).  Per point
+//   pair (FORM 0, direct) F_L d.n_s, -G_L, -F_Y d.n_s, eps G_Y, or (FORM 1,
+//   Juffer) (F_L - alpha F_Y) d.n_s, G_Y - G_L, G_Y, (F_L - beta F_Y) d.n_t, with
+//   the hypersingular curl part added from sum (G_Y - G_L) per pair.
+// Phase 2: lane v sums, for one vertex touched by the tile, the block columns
+//   of its incident tile triangles, and adds the 3 x 4 values to rows t_0..t_2.
+// Target colours keep rows disjoint and tile colours keep columns disjoint
+// between concurrently running blocks, so there is no atomic and the result
+// is deterministic.
+template <typename R, typename S, int FORM, int TILE>
+__global__ __launch_bounds__(TILE) void k_assemble_tile(
+    int T, int V, AsmCoef<R> cf, const int32_t *__restrict__ targets, const int32_t *__restrict__ tiles,
+    const int32_t *__restrict__ tri, const R *__restrict__ stat, const double *__restrict__ geo,
+    const int32_t *__restrict__ vpos, const int32_t *__restrict__ tv_ptr, const int32_t *__restrict__ tv_col,
+    const int32_t *__restrict__ tv_eptr, const int32_t *__restrict__ te, S *__restrict__ A, size_t ld, size_t Vp)
 {
-    const int t = tris_of_color[blockIdx.y];
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= V) return;
-    const R *ts = stat + (size_t)t * kStat;
+    __shared__ R lds[36 * TILE];
+    const int t = targets[blockIdx.y];
+    const int tile = tiles[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int s = tile * TILE + tid;
     const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
-    const double *gt = geo + (size_t)t * kGeo;
-    const R at = (R)gt[21];
-    R tx[6], ty[6], tz[6], xnt[6];
+    R blk[3][3][4];   // [l][k][o]
 #pragma unroll
-    for (int p = 0; p < 6; ++p) {
-        tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2]; xnt[p] = ts[21 + p];
-    }
-    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
-    R acc[3][4];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int o = 0; o < 4; ++o) acc[k][o] = 0;
-    for (int e = inc_ptr[j]; e < inc_ptr[j + 1]; ++e) {
-        const int s = inc_tk[e] >> 2, l = inc_tk[e] & 3;
-        const int j0 = tri[3 * s], j1 = tri[3 * s + 1], j2 = tri[3 * s + 2];
-        if ((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) | (j2 == v0) |
-            (j2 == v1) | (j2 == v2))
-            continue;
-        const R *ss = stat + (size_t)s * kStat;
-        const double *gs = geo + (size_t)s * kGeo;
-        const R nsx = ss[18], nsy = ss[19], nsz = ss[20];
-        R xns[6];
-#pragma unroll
-        for (int p = 0; p < 6; ++p) xns[p] = tx[p] * nsx + ty[p] * nsy + tz[p] * nsz;
-        R blk[3][4];
+    for (int l = 0; l < 3; ++l)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int o = 0; o < 4; ++o) blk[k][o] = 0;
+            for (int o = 0; o < 4; ++o) blk[l][k][o] = 0;
+    bool live = s < T;
+    int j0 = 0, j1 = 0, j2 = 0;
+    if (live) {
+        j0 = tri[3 * s]; j1 = tri[3 * s + 1]; j2 = tri[3 * s + 2];
+        live = !((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) | (j2 == v0) |
+                 (j2 == v1) | (j2 == v2));
+    }
+    if (live) {
+        const R *ts = stat + (size_t)t * kStat;   // uniform: scalar loads
+        const R *ss = stat + (size_t)s * kStat;
+        const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+        const R nsx = ss[18], nsy = ss[19], nsz = ss[20];
+        R sy[6][3], yns[6], ynt[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            sy[q][0] = ss[3 * q]; sy[q][1] = ss[3 * q + 1]; sy[q][2] = ss[3 * q + 2];
+            yns[q] = ss[21 + q];
+            ynt[q] = sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz;
+        }
         R Ssum = 0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const R yx = ss[3 * q], yy = ss[3 * q + 1], yz = ss[3 * q + 2], yns = ss[21 + q];
-            const R ynt = yx * ntx + yy * nty + yz * ntz;
             R X[3][4];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -134,13 +138,14 @@ __global__ __launch_bounds__(256) void k_assemble(int V, AsmCoef<R> cf, const in
             R Sq = 0;
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
-                const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
+                const R tx = ts[3 * p], ty = ts[3 * p + 1], tz = ts[3 * p + 2];
+                const R dx = tx - sy[q][0], dy = ty - sy[q][1], dz = tz - sy[q][2];
                 const R r2 = dx * dx + dy * dy + dz * dz;
                 const R ri = rsq_a(r2);
                 const R r = r2 * ri;
                 const R ek = expn_a(cf.kexp, r);
                 const R ri3 = ri * ri * ri;
-                const R dns = xns[p] - yns;
+                const R dns = (tx * nsx + ty * nsy + tz * nsz) - yns[q];
                 const R fy = ek * (cf.kappa * r + R(1)) * ri3;
                 R v[4];
                 if (FORM == 0) {
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(256) void k_assemble(int V, AsmCoef<R> cf, const in
                     v[0] = (ri3 - cf.c1 * fy) * dns;
                     v[1] = gy - ri;
                     v[2] = gy;
-                    v[3] = (ri3 - cf.c2 * fy) * (xnt[p] - ynt);
+                    v[3] = (ri3 - cf.c2 * fy) * (ts[21 + p] - ynt[q]);
                     Sq += R(rule_w(p)) * v[1];
                 }
 #pragma unroll
@@ -163,38 +168,67 @@ __global__ __launch_bounds__(256) void k_assemble(int V, AsmCoef<R> cf, const in
                     for (int o = 0; o < 4; ++o) X[k][o] += c * v[o];
                 }
             }
-            // test-side weights done; trial weight w_q lambda_l(y_q)
-            const R wq = R(rule_w(q)) * (l == 0 ? R(rule_bary(q, 0)) : l == 1 ? R(rule_bary(q, 1)) : R(rule_bary(q, 2)));
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const R wq = R(rule_w(q) * rule_bary(q, l));
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) blk[l][k][o] += wq * X[k][o];
+            }
+            if (FORM == 1) Ssum += R(rule_w(q)) * Sq;
+        }
+        const double *gt = geo + (size_t)t * kGeo, *gs = geo + (size_t)s * kGeo;
+        const R sc = (R)(gt[21] * gs[21] * kInv4Pi);
+        if (FORM == 1) {
+            // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
+            const R nn = ntx * nsx + nty * nsy + ntz * nsz;
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const R cc = (R)(gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
+                                     gt[24 + 3 * k] * gs[24 + 3 * l]);
+                    blk[l][k][2] = cc * Ssum + cf.k2 * nn * blk[l][k][2];
+                }
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int o = 0; o < 4; ++o) blk[k][o] += wq * X[k][o];
-            if (FORM == 1) Ssum += R(rule_w(q)) * Sq;
-        }
-        const R sc = at * (R)gs[21] * R(kInv4Pi);
-        if (FORM == 1) {
-            // hypersingular: curl_k(t) . curl_l(s) * int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
-            const R nn = ntx * nsx + nty * nsy + ntz * nsz;
+                for (int o = 0; o < 4; ++o) blk[l][k][o] *= sc;
+    }
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const R cc = (R)(gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
-                                 gt[24 + 3 * k] * gs[24 + 3 * l]);
-                blk[k][2] = cc * Ssum + cf.k2 * nn * blk[k][2];
-            }
-        }
+    for (int l = 0; l < 3; ++l)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int o = 0; o < 4; ++o) acc[k][o] += sc * blk[k][o];
-    }
-    const int rows[3] = {v0, v1, v2};
+            for (int o = 0; o < 4; ++o) lds[(12 * l + 4 * k + o) * TILE + tid] = blk[l][k][o];
+    __syncthreads();
+    const size_t rk[3] = {(size_t)vpos[v0], (size_t)vpos[v1], (size_t)vpos[v2]};
+    for (int e = tv_ptr[tile] + tid; e < tv_ptr[tile + 1]; e += TILE) {
+        const size_t c = (size_t)tv_col[e];
+        R acc[3][4];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const size_t r1 = (size_t)rows[k] * ld, r2 = (size_t)(V + rows[k]) * ld;
-        A[r1 + j] += (S)acc[k][0];
-        A[r1 + Vp + j] += (S)acc[k][1];
-        A[r2 + j] += (S)acc[k][2];
-        A[r2 + Vp + j] += (S)acc[k][3];
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) acc[k][o] = 0;
+        for (int f = tv_eptr[e]; f < tv_eptr[e + 1]; ++f) {
+            const int slot = te[f] >> 2, l = te[f] & 3;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int o = 0; o < 4; ++o) acc[k][o] += lds[(12 * l + 4 * k + o) * TILE + slot];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            S *r1 = A + rk[k] * ld, *r2 = A + ((size_t)V + rk[k]) * ld;
+            r1[c] += (S)acc[k][0];
+            r1[Vp + c] += (S)acc[k][1];
+            r2[c] += (S)acc[k][2];
+            r2[Vp + c] += (S)acc[k][3];
+        }
     }
 }
 
@@ -262,6 +296,8 @@ __global__ __launch_bounds__(256) void k_blockmax(int n, int V, size_t Vp, size_
 // chunks; x is padded with zeros to ld.  ACC = accumulation type.
 __device__ __forceinline__ void load16(const double *p, double *v) { const double2 a = *(const double2 *)p; v[0] = a.x; v[1] = a.y; }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <typename S> struct Vec;
 template <> struct Vec<double> { static constexpr int W = 2; };
 template <> struct Vec<float> { static constexpr int W = 4; };
@@ -282,12 +318,12 @@ __global__ __launch_bounds__(256) void k_gemv(int n, int V, size_t Vp, size_t ld
     for (int r = wave; r < n; r += nwave) {
         const S *row = A + (size_t)r * ld;
         ACC s0 = 0, s1 = 0;   // columns < V and >= V (separate block scales for FP16)
-        for (size_t c = (size_t)lane * W; c < ld; c += 64 * W) {
+        // four independent 16-byte streaming loads in flight per lane; the
+        // matrix is read once, so loads are non-temporal and x stays in L2
+        constexpr size_t step = 64 * W;
+        auto consume = [&](size_t c, const u32x4 &u) {
             S v[W];
-            if constexpr (sizeof(S) * W == 16) {
-                const uint4 u = *(const uint4 *)(row + c);
-                __builtin_memcpy(v, &u, 16);
-            }
+            __builtin_memcpy(v, &u, 16);
             ACC part = 0;
 #pragma unroll
             for (int w = 0; w < W; ++w) {
@@ -298,7 +334,19 @@ __global__ __launch_bounds__(256) void k_gemv(int n, int V, size_t Vp, size_t ld
                 part += a * x[c + w];
             }
             if (c < Vp) s0 += part; else s1 += part;   // chunks never straddle Vp (multiple of 64)
+        };
+        size_t c = (size_t)lane * W;
+        for (; c + 3 * step < ld; c += 4 * step) {
+            const u32x4 u0 = __builtin_nontemporal_load((const u32x4 *)(row + c));
+            const u32x4 u1 = __builtin_nontemporal_load((const u32x4 *)(row + c + step));
+            const u32x4 u2 = __builtin_nontemporal_load((const u32x4 *)(row + c + 2 * step));
+            const u32x4 u3 = __builtin_nontemporal_load((const u32x4 *)(row + c + 3 * step));
+            consume(c, u0);
+            consume(c + step, u1);
+            consume(c + 2 * step, u2);
+            consume(c + 3 * step, u3);
         }
+        for (; c < ld; c += step) consume(c, __builtin_nontemporal_load((const u32x4 *)(row + c)));
         for (int off = 32; off > 0; off >>= 1) {
             s0 += __shfl_xor(s0, off);
             s1 += __shfl_xor(s1, off);
@@ -316,15 +364,90 @@ __global__ __launch_bounds__(256) void k_gemv(int n, int V, size_t Vp, size_t ld
     }
 }
 
+// Row-tile GEMV: one wavefront per tile of 16 consecutive rows.  Each lane
+// walks its column chunks once, loads the x chunk once and applies it to the
+// 16 rows (16 independent 16-byte streaming loads in flight), keeping the
+// x traffic at 1/16 of the matrix traffic.  Per-row lane partials are reduced
+// across the wavefront at the end (fixed butterfly, deterministic).
+template <typename S, typename ACC, int KIND, int R>
+__global__ __launch_bounds__(256) void k_gemv_tile(int n, int V, size_t Vp, size_t ld, const S *__restrict__ A,
+                                                   const ACC *__restrict__ x, float inv0, float inv1, float inv2,
+                                                   float inv3, double *__restrict__ y)
+{
+    constexpr int W = Vec<S>::W;
+    constexpr size_t step = 64 * W;
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int nwave = (gridDim.x * 256) >> 6;
+    const int ntile = (n + R - 1) / R;
+    for (int tile = wave; tile < ntile; tile += nwave) {
+        const int r0 = tile * R;
+        const S *rows[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) rows[i] = A + (size_t)min(r0 + i, n - 1) * ld;
+        ACC s0[R], s1[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) { s0[i] = 0; s1[i] = 0; }
+        for (size_t c = (size_t)lane * W; c < ld; c += step) {
+            ACC xv[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) xv[w] = x[c + w];
+            u32x4 u[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) u[i] = __builtin_nontemporal_load((const u32x4 *)(rows[i] + c));
+            const bool first = c < Vp;   // chunks never straddle Vp (multiple of 64)
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                S v[W];
+                __builtin_memcpy(v, &u[i], 16);
+                ACC part = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    ACC a;
+                    if constexpr (KIND == 0) a = (ACC)v[w];
+                    else if constexpr (KIND == 1) a = (ACC)bf16_to_f((uint16_t)v[w]);
+                    else a = (ACC)fp16_to_f((uint16_t)v[w]);
+                    part += a * xv[w];
+                }
+                if (first) s0[i] += part; else s1[i] += part;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            for (int off = 32; off > 0; off >>= 1) {
+                s0[i] += __shfl_xor(s0[i], off);
+                s1[i] += __shfl_xor(s1[i], off);
+            }
+        if (lane < R && r0 + lane < n) {
+            ACC a0 = 0, a1 = 0;
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if (i == lane) { a0 = s0[i]; a1 = s1[i]; }
+            const int r = r0 + lane;
+            double out;
+            if (KIND == 2) {
+                const bool top = r < V;
+                out = (double)a0 * (top ? inv0 : inv2) + (double)a1 * (top ? inv1 : inv3);
+            } else {
+                out = (double)a0 + (double)a1;
+            }
+            y[r] = out;
+        }
+    }
+}
+
 // copy x (2V doubles, two halves) into the padded layout: [x1 | x2 | 0...]
+// x (2V doubles, vertex order) into the padded dense column order
+// [x1 (dense index order) | 0 | x2 | 0]
 template <typename ACC>
-__global__ void k_pad_x(int V, size_t Vp, size_t ld, const double *__restrict__ x, ACC *__restrict__ xp)
+__global__ void k_pad_x(int V, size_t Vp, size_t ld, const int32_t *__restrict__ vperm, const double *__restrict__ x,
+                        ACC *__restrict__ xp)
 {
     size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ld) return;
     ACC v = ACC(0);
-    if (c < (size_t)V) v = (ACC)x[c];
-    else if (c >= Vp && c < Vp + (size_t)V) v = (ACC)x[V + (c - Vp)];
+    if (c < (size_t)V) v = (ACC)x[vperm[c]];
+    else if (c >= Vp && c < Vp + (size_t)V) v = (ACC)x[V + vperm[c - Vp]];
     xp[c] = v;
 }
 
@@ -351,11 +474,79 @@ bool dense_fits(const DevMesh &d)
     return need < 0.8 * (double)freeb;
 }
 
-template <typename R, typename S>
+// Source tiles of `tile` consecutive Morton-ordered triangles; dense vertex
+// numbering by first touch in tile order; per tile the touched vertices (in
+// dense order) with their (slot, local vertex) incidences; tile colouring so
+// that tiles of one colour share no vertex.
+static void build_tiles(const HostMesh &hm, DevMesh &d, Dense &D)
+{
+    const int T = hm.T, V = hm.V, TL = D.tile;
+    D.ntile = (T + TL - 1) / TL;
+    std::vector<int32_t> vpos(V, -1), vperm(V);
+    int next = 0;
+    for (int s = 0; s < T; ++s)
+        for (int k = 0; k < 3; ++k) {
+            const int v = hm.tri[3 * s + k];
+            if (vpos[v] < 0) { vpos[v] = next; vperm[next] = v; ++next; }
+        }
+    std::vector<int32_t> tv_ptr(D.ntile + 1, 0), tv_col, tv_eptr(1, 0), te;
+    std::vector<std::pair<int32_t, int32_t>> buf;
+    std::vector<std::vector<int32_t>> vtiles(V);
+    for (int tl = 0; tl < D.ntile; ++tl) {
+        buf.clear();
+        for (int s = tl * TL; s < std::min(T, (tl + 1) * TL); ++s)
+            for (int l = 0; l < 3; ++l) buf.push_back({vpos[hm.tri[3 * s + l]], ((s - tl * TL) << 2) | l});
+        std::sort(buf.begin(), buf.end());
+        for (size_t a = 0; a < buf.size();) {
+            size_t b = a;
+            while (b < buf.size() && buf[b].first == buf[a].first) te.push_back(buf[b++].second);
+            tv_col.push_back(buf[a].first);
+            tv_eptr.push_back((int32_t)te.size());
+            vtiles[vperm[buf[a].first]].push_back(tl);
+            a = b;
+        }
+        tv_ptr[tl + 1] = (int32_t)tv_col.size();
+    }
+    // colour tiles: neighbours = tiles sharing a vertex
+    std::vector<int> col(D.ntile, -1);
+    int ncol = 0;
+    std::vector<char> used;
+    for (int tl = 0; tl < D.ntile; ++tl) {
+        used.assign(ncol + 1, 0);
+        for (int e = tv_ptr[tl]; e < tv_ptr[tl + 1]; ++e)
+            for (int o : vtiles[vperm[tv_col[e]]])
+                if (col[o] >= 0) used[col[o]] = 1;
+        int c = 0;
+        while (c < ncol && used[c]) ++c;
+        col[tl] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    D.ntcolor = ncol;
+    D.tcolor_ptr.assign(ncol + 1, 0);
+    for (int tl = 0; tl < D.ntile; ++tl) D.tcolor_ptr[col[tl] + 1]++;
+    for (int c = 0; c < ncol; ++c) D.tcolor_ptr[c + 1] += D.tcolor_ptr[c];
+    std::vector<int32_t> lst(D.ntile), fill(D.tcolor_ptr.begin(), D.tcolor_ptr.end() - 1);
+    for (int tl = 0; tl < D.ntile; ++tl) lst[fill[col[tl]]++] = tl;
+    auto up = [&](const std::vector<int32_t> &v) {
+        int32_t *p = (int32_t *)d.alloc(sizeof(int32_t) * std::max<size_t>(v.size(), 1));
+        if (!v.empty()) HIPCHECK(hipMemcpyAsync(p, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, d.stream));
+        return p;
+    };
+    D.tcolor_tile = up(lst);
+    D.tv_ptr = up(tv_ptr);
+    D.tv_col = up(tv_col);
+    D.tv_eptr = up(tv_eptr);
+    D.te = up(te);
+    D.vpos = up(vpos);
+    D.vperm = up(vperm);
+    HIPCHECK(hipStreamSynchronize(d.stream));   // host vectors go out of scope
+}
+
+template <typename R, typename S, int TILE>
 static void assemble(DevMesh &d, S *A)
 {
     Dense &D = *d.dense;
-    const int V = d.hm.V;
+    const int V = d.hm.V, T = d.hm.T;
     AsmCoef<R> cf;
     const double kap = d.prm.kappa;
     cf.kappa = (R)kap;
@@ -370,14 +561,19 @@ static void assemble(DevMesh &d, S *A)
     for (int c = 0; c < D.ncolor; ++c) {
         const int nt = D.color_ptr[c + 1] - D.color_ptr[c];
         if (nt == 0) continue;
-        dim3 grid((V + 255) / 256, nt), block(256);
-        const int32_t *lst = D.color_tri + D.color_ptr[c];
-        if (direct)
-            hipLaunchKernelGGL((k_assemble<R, S, 0>), grid, block, 0, d.stream, V, cf, lst, d.tri, stat, d.geo,
-                               d.inc_ptr, d.inc_tk, A, D.ld, D.Vp);
-        else
-            hipLaunchKernelGGL((k_assemble<R, S, 1>), grid, block, 0, d.stream, V, cf, lst, d.tri, stat, d.geo,
-                               d.inc_ptr, d.inc_tk, A, D.ld, D.Vp);
+        const int32_t *tg = D.color_tri + D.color_ptr[c];
+        for (int kc = 0; kc < D.ntcolor; ++kc) {
+            const int nk = D.tcolor_ptr[kc + 1] - D.tcolor_ptr[kc];
+            if (nk == 0) continue;
+            const int32_t *tl = D.tcolor_tile + D.tcolor_ptr[kc];
+            dim3 grid(nk, nt), block(TILE);
+            if (direct)
+                hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE>), grid, block, 0, d.stream, T, V, cf, tg, tl, d.tri,
+                                   stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp);
+            else
+                hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE>), grid, block, 0, d.stream, T, V, cf, tg, tl, d.tri,
+                                   stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp);
+        }
     }
     HIPCHECK(hipGetLastError());
 }
@@ -408,6 +604,9 @@ void build_dense(DevMesh &d)
         }
         D->x32 = (float *)d.alloc(sizeof(float) * D->ld);
         D->x64 = (double *)d.alloc(sizeof(double) * D->ld);
+        D->tile = d.prm.precision == PB_FP64 ? 128 : 256;
+        build_tiles(d.hm, d, *D);
+        d.dense_vpos = D->vpos;
     }
     Dense &D = *d.dense;
     Profiler &pf = d.prof;
@@ -417,13 +616,12 @@ void build_dense(DevMesh &d)
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, d.stream));
     }
-    if (D.A64) assemble<double, double>(d, D.A64);
-    else assemble<float, float>(d, D.A32);
+    if (D.A64) assemble<double, double, 128>(d, D.A64);
+    else assemble<float, float, 256>(d, D.A32);
     if (pf.enabled) {
         HIPCHECK(hipEventRecord(e1, d.stream));
-        // assembly work: every far pair's 36 point pairs, evaluated once per
-        // source vertex of the pair (3x)
-        pf.record(1, e0, e1, 3.0 * 36.0 * (double)d.hm.T * (double)d.hm.T);
+        // assembly work: 36 point pairs per ordered triangle pair, each evaluated once
+        pf.record(1, e0, e1, 36.0 * (double)d.hm.T * (double)d.hm.T);
     }
     if (D.A16) {
         const size_t total = (size_t)D.n * D.ld;
@@ -461,7 +659,53 @@ void destroy_dense(DevMesh &d)
     d.dense = nullptr;
 }
 
-// yfar (2V doubles) = A_far x at the current operator level
+// GEMV variants: 0 = one wavefront per row (four loads in flight per lane),
+// 1 = 8-row tiles, 2 = 16-row tiles.  The fastest for a given storage type and
+// matrix is picked by timing them once on the real matrix (autotune cache).
+template <typename S, typename ACC, int KIND>
+static void gemv_launch(int variant, hipStream_t st, int n, int V, size_t Vp, size_t ld, const S *A, const ACC *x,
+                        const float *inv, double *y)
+{
+    if (variant == 0) {
+        const int nwg = std::min(n / 4 + 1, 8192);
+        hipLaunchKernelGGL((k_gemv<S, ACC, KIND>), dim3(nwg), dim3(256), 0, st, n, V, Vp, ld, A, x, inv[0], inv[1],
+                           inv[2], inv[3], y);
+    } else if (variant == 1) {
+        const int nwg = std::min((n + 31) / 32, 8192);
+        hipLaunchKernelGGL((k_gemv_tile<S, ACC, KIND, 8>), dim3(nwg), dim3(256), 0, st, n, V, Vp, ld, A, x, inv[0],
+                           inv[1], inv[2], inv[3], y);
+    } else {
+        const int nwg = std::min((n + 63) / 64, 8192);
+        hipLaunchKernelGGL((k_gemv_tile<S, ACC, KIND, 16>), dim3(nwg), dim3(256), 0, st, n, V, Vp, ld, A, x, inv[0],
+                           inv[1], inv[2], inv[3], y);
+    }
+}
+
+static void gemv_dispatch(Dense &D, int variant, hipStream_t st, bool lo, double *yfar)
+{
+    const int V = D.V;
+    float one[4] = {1.f, 1.f, 1.f, 1.f}, inv[4];
+    for (int b = 0; b < 4; ++b) inv[b] = 1.f / D.scale16[b];
+    if (D.A64) gemv_launch<double, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A64, D.x64, one, yfar);
+    else if (!lo) gemv_launch<float, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A32, D.x64, one, yfar);
+    else if (D.kind16 == 1) gemv_launch<uint16_t, float, 1>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, one, yfar);
+    else gemv_launch<uint16_t, float, 2>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, inv, yfar);
+}
+
+int autotune_pick(const std::string &key, int nvariants, const std::function<void(int)> &run, hipStream_t st);
+
+static int gemv_variant(DevMesh &d, bool lo)
+{
+    Dense &D = *d.dense;
+    int &slot = lo ? D.gemv_lo : D.gemv_hi;
+    if (slot >= 0) return slot;
+    const char *kind = D.A64 ? "f64" : !lo ? "f32" : D.kind16 == 1 ? "bf16" : "fp16";
+    const std::string key = std::string("gemv/") + kind + "/" + std::to_string(D.n);
+    slot = autotune_pick(key, 3, [&](int v) { gemv_dispatch(D, v, d.stream, lo, d.yfar); }, d.stream);
+    return slot;
+}
+
+// yfar (2V doubles, dense row order) = A_far x at the current operator level
 void dense_apply(DevMesh &d, const double *x, double *yfar)
 {
     Dense &D = *d.dense;
@@ -469,33 +713,16 @@ void dense_apply(DevMesh &d, const double *x, double *yfar)
     Profiler &pf = d.prof;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const dim3 gpad((unsigned)((D.ld + 255) / 256)), b256(256);
-    const int nwg = std::min(D.n / 4 + 1, 8192);
+    const bool lo = D.level == 0 && D.A16;
+    if (!lo) hipLaunchKernelGGL(k_pad_x<double>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, D.vperm, x, D.x64);
+    else hipLaunchKernelGGL(k_pad_x<float>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, D.vperm, x, D.x32);
+    const int variant = gemv_variant(d, lo);
     if (pf.enabled) {
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, d.stream));
     }
-    const bool lo = D.level == 0 && D.A16;
-    if (D.A64) {
-        hipLaunchKernelGGL(k_pad_x<double>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, x, D.x64);
-        if (pf.enabled) HIPCHECK(hipEventRecord(e0, d.stream));
-        hipLaunchKernelGGL((k_gemv<double, double, 0>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A64, D.x64,
-                           1.f, 1.f, 1.f, 1.f, yfar);
-    } else if (!lo) {
-        hipLaunchKernelGGL(k_pad_x<double>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, x, D.x64);
-        if (pf.enabled) HIPCHECK(hipEventRecord(e0, d.stream));
-        hipLaunchKernelGGL((k_gemv<float, double, 0>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A32, D.x64,
-                           1.f, 1.f, 1.f, 1.f, yfar);
-    } else {
-        hipLaunchKernelGGL(k_pad_x<float>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, x, D.x32);
-        if (pf.enabled) HIPCHECK(hipEventRecord(e0, d.stream));
-        if (D.kind16 == 1)
-            hipLaunchKernelGGL((k_gemv<uint16_t, float, 1>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A16,
-                               D.x32, 1.f, 1.f, 1.f, 1.f, yfar);
-        else
-            hipLaunchKernelGGL((k_gemv<uint16_t, float, 2>), dim3(nwg), b256, 0, d.stream, D.n, V, D.Vp, D.ld, D.A16,
-                               D.x32, 1.f / D.scale16[0], 1.f / D.scale16[1], 1.f / D.scale16[2],
-                               1.f / D.scale16[3], yfar);
-    }
+    gemv_dispatch(D, variant, d.stream, lo, yfar);
     if (pf.enabled) {
         HIPCHECK(hipEventRecord(e1, d.stream));
         // algorithmic bytes: the stored 2V x 2V entries (padding excluded) + x and y

@@ -210,7 +210,7 @@ __global__ void k_far_finish(int T, int S, int form, const double *__restrict__ 
 // flags: PB_APPLY_PRECOND, PB_APPLY_NEAR_ONLY, PB_APPLY_FAR_ONLY (near part skipped)
 __global__ void k_gather(int V, int use_far, int use_near, int precond, const int32_t *__restrict__ inc_ptr,
                          const int32_t *__restrict__ inc_tk, const double *__restrict__ triout,
-                         const double *__restrict__ yfar,
+                         const double *__restrict__ yfar, const int32_t *__restrict__ vpos,
                          const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                          const double *__restrict__ N, int64_t nnz, const double *__restrict__ pinv,
                          const double *__restrict__ x, double *__restrict__ y)
@@ -218,9 +218,10 @@ __global__ void k_gather(int V, int use_far, int use_near, int precond, const in
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= V) return;
     double y1 = 0.0, y2 = 0.0;
-    if (use_far == 2) {
-        y1 = yfar[i];
-        y2 = yfar[V + i];
+    if (use_far == 2) {   // dense far product, rows in dense vertex order
+        const int r = vpos[i];
+        y1 = yfar[r];
+        y2 = yfar[V + r];
     } else if (use_far == 1) {
         for (int e = inc_ptr[i]; e < inc_ptr[i + 1]; ++e) {
             const int tk = inc_tk[e];
@@ -318,7 +319,7 @@ void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_fa
     const int V = d.hm.V;
     const int use_near = (flags & PB_APPLY_FAR_ONLY) ? 0 : 1;
     hipLaunchKernelGGL(k_gather, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, use_far, use_near,
-                       (flags & PB_APPLY_PRECOND) ? 1 : 0, d.inc_ptr, d.inc_tk, d.triout, d.yfar, d.row_ptr, d.col, d.N,
+                       (flags & PB_APPLY_PRECOND) ? 1 : 0, d.inc_ptr, d.inc_tk, d.triout, d.yfar, d.dense_vpos, d.row_ptr, d.col, d.N,
                        d.nnz(), d.pinv, x, y);
     HIPCHECK(hipGetLastError());
 }

@@ -149,6 +149,7 @@ struct DevMesh {
     double *red = nullptr;         // reduction scratch
     int redcap = 0;
     Dense *dense = nullptr;
+    const int32_t *dense_vpos = nullptr;   // vertex -> row of the dense far field
     BatchWork *bw = nullptr;
 
     Profiler prof;

@@ -386,3 +386,21 @@ def test_server_admission_by_footprint_and_cancel():
     spans = sorted((r["t_start"], r["t_end"]) for r in res)
     for (s0, e0), (s1, e1) in zip(spans, spans[1:]):
         assert s1 >= e0 - 1e-3, spans     # never two requests on the device at once
+
+
+def test_star_full_size_sampled_rows():
+    """Star surface, 81920 triangles / 40962 vertices (the matrix-free FP32
+    configuration): sampled rows of A x for both formulations against rows the
+    oracle computes, in the launch configuration the benchmark uses."""
+    m, _ = inputs.config_star()
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(2 * m.n_vertices)
+    rows = np.sort(rng.choice(m.n_vertices, 4, replace=False))
+    nv = m.n_vertices
+    for form in (0, 1):
+        r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, form, rows, x)
+        ref = np.concatenate([r1, r2])
+        for prec, tol in ((pbm.PB_FP32, 2e-5), (pbm.PB_FP64, 1e-12)):
+            with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec)) as h:
+                y = pbm.pb_mesh_apply(h, x)
+            assert _rel(np.concatenate([y[rows], y[nv + rows]]), ref) < tol, (form, prec)
