@@ -102,8 +102,11 @@ def main():
 
     for _ in range(a.warmup):
         step()
+    assembled = any(h.info()["assembled"] for h in handles.values())
+    # assembled: time the dominant kernel (assembly) and keep the captured GMRES
+    # graphs; matrix-free: time the far-field kernel (GMRES then runs eagerly)
     for h in handles.values():
-        pbm.pb_mesh_profile(h, True)
+        pbm.pb_mesh_profile(h, 2 if assembled else 1)
     lat = []
     results = None
     t0 = time.perf_counter()
@@ -116,10 +119,16 @@ def main():
     elapsed = time.perf_counter() - t0
 
     # dominant kernel: far-field operator kernel (or dense product), HIP events on its stream
-    prof = {f: pbm.pb_mesh_profile_read(handles[f], 0) for f in forms}
     prof_asm = {f: pbm.pb_mesh_profile_read(handles[f], 1) for f in forms}
+    if assembled:
+        # the dense product, timed on its own stream right after the timed steps
+        xs = np.random.default_rng(0).standard_normal(2 * mesh.n_vertices)
+        for h in handles.values():
+            pbm.pb_mesh_profile(h, 1)
+            for _ in range(20):
+                pbm.pb_mesh_apply(h, xs)
+    prof = {f: pbm.pb_mesh_profile_read(handles[f], 0) for f in forms}
     info = {f: handles[f].info() for f in forms}
-    assembled = any(info[f]["assembled"] for f in forms)
     launches = sum(prof[f][0] for f in forms)
     kern_ms = sum(prof[f][1] for f in forms)
     dtype = "f64" if prec == pbm.PB_FP64 else "f32"
@@ -238,7 +247,9 @@ def serving(argv=None):
     prec = {"fp32": pbm.PB_FP32, "mixed-bf16": pbm.PB_MIXED_BF16, "mixed-fp16": pbm.PB_MIXED_FP16}[a.precision]
     trace = inputs.serving_trace(5, a.requests, a.rate)
     reqs = []
-    for r in trace:
+    for k, r in enumerate(trace):
+        if k % 64 == 0:
+            print(f"serving: building request {k}/{len(trace)}", file=sys.stderr, flush=True)
         mesh, ch = inputs.build_request(r)
         opt = pbm.pb_default_options(formulation=r["formulation"], precision=prec, operator_mode=pbm.PB_ASSEMBLED)
         reqs.append((r, mesh, ch, opt))
@@ -265,6 +276,8 @@ def serving(argv=None):
             res = srv.wait(tk)
             res["latency_s"] = res["t_end"] - res["t_submit"]
             results[k] = res
+            if k % 64 == 63:
+                print(f"serving: {k + 1}/{len(reqs)} done", file=sys.stderr, flush=True)
         th.join()
         stats = srv.stats()
     first = min(r["t_submit"] for r in results)
@@ -280,6 +293,7 @@ def serving(argv=None):
     worst = 0.0
     for k in pick:
         r, mesh, ch, _ = reqs[k]
+        print(f"serving: FP64 comparator solve, {r['n_triangles']} triangles", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         g = pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q,
                          pbm.pb_default_options(formulation=r["formulation"], precision=pbm.PB_FP64))
@@ -357,7 +371,28 @@ def multi(argv=None):
     print(json.dumps(rec), flush=True)
 
 
+def calibrate_copy(nbytes=1 << 30):
+    """A plain device-to-device copy of known size (the runtime's copy kernel),
+    used to scale the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import ctypes
+    import paper_2108_10481_amd as pbm
+    pbm.load()
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(a), ctypes.c_size_t(nbytes)) == 0
+    assert hip.hipMalloc(ctypes.byref(b), ctypes.c_size_t(nbytes)) == 0
+    for _ in range(3):
+        assert hip.hipMemcpy(b, a, ctypes.c_size_t(nbytes), 3) == 0   # hipMemcpyDeviceToDevice
+    assert hip.hipDeviceSynchronize() == 0
+    hip.hipFree(a)
+    hip.hipFree(b)
+    print(json.dumps({"calibration_copy_bytes": nbytes, "copies": 3}), flush=True)
+
+
 if __name__ == "__main__":
+    if "--calibrate-copy" in sys.argv:
+        calibrate_copy()
+        sys.exit(0)
     wl = sys.argv[sys.argv.index("--workload") + 1] if "--workload" in sys.argv else "sphere"
     if wl == "serving":
         serving()

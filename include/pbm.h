@@ -100,6 +100,8 @@ typedef struct {
     int32_t inner_max_iter;   /* mixed modes: inner GMRES cap (default 200) */
     double inner_tol;         /* mixed modes: inner relative tolerance (default 1e-3) */
     size_t memory_budget;     /* bytes the handle may hold on the device; 0 = 90% of free */
+    int32_t use_graph;        /* 1 (default): GMRES iterations replayed from a captured HIP
+                                 graph with device-side Givens rotations; 0: eager launches */
 } pb_options;
 
 typedef struct {
@@ -212,9 +214,11 @@ pb_status pb_mesh_near_blocks(pb_mesh_handle *h, int32_t n, const int32_t *t, co
 /* Per-vertex 2x2 preconditioner inverses, out: n_vertices x 4 (row-major). */
 pb_status pb_mesh_preconditioner(pb_mesh_handle *h, double *out);
 
-/* Kernel timing for measurement: when enabled, the dominant kernels are
- * bracketed by HIP events on the stream they run on.  read returns, since the
- * last pb_mesh_profile call, the launches, summed milliseconds and summed
+/* Kernel timing for measurement: `enable` is a bit mask of kinds whose kernels
+ * are bracketed by HIP events on the stream they run on (bit 0: kind 0, bit 1:
+ * kind 1; 0 turns timing off).  Timing kind 0 makes GMRES launch its iterations
+ * eagerly instead of replaying a captured graph.  read returns, since the last
+ * pb_mesh_profile call, the launches, summed milliseconds and summed
  * algorithmic work of one kind:
  *   kind 0: operator product -- matrix-free far-field kernel (work = kernel
  *           pairs, (6T)^2 per launch) or dense far-field GEMV (work = bytes of

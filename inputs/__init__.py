@@ -89,6 +89,23 @@ def _icosahedron():
 
 
 def icosphere(freq: int, radius: float = 1.0) -> Mesh:
+    """Frequency-``freq`` class-I geodesic icosphere of the given radius (cached per frequency)."""
+    xyz, tri = _unit_icosphere(int(freq))
+    return Mesh(xyz * radius, tri.copy(), {"kind": "icosphere", "freq": int(freq), "radius": float(radius)})
+
+
+_ICO_CACHE: dict = {}
+
+
+def _unit_icosphere(freq: int):
+    if freq not in _ICO_CACHE:
+        m = _build_icosphere(freq)
+        m.xyz.setflags(write=False)
+        _ICO_CACHE[freq] = (m.xyz, m.tri)
+    return _ICO_CACHE[freq]
+
+
+def _build_icosphere(freq: int, radius: float = 1.0) -> Mesh:
     """Frequency-``freq`` class-I geodesic icosphere of the given radius.
 
     Every icosahedron face (A, B, C) is split into freq^2 triangles on the
@@ -136,16 +153,6 @@ def icosphere(freq: int, radius: float = 1.0) -> Mesh:
     return Mesh(xyz, tri, {"kind": "icosphere", "freq": n, "radius": float(radius)})
 
 
-def _real_sph_harm(l: int, m: int, polar: np.ndarray, azim: np.ndarray) -> np.ndarray:
-    from scipy.special import sph_harm_y
-    if m == 0:
-        return np.real(sph_harm_y(l, 0, polar, azim))
-    y = sph_harm_y(l, abs(m), polar, azim)
-    if m > 0:
-        return math.sqrt(2.0) * (-1) ** m * np.real(y)
-    return math.sqrt(2.0) * (-1) ** m * np.imag(y)
-
-
 class StarShape:
     """Radial function r(u) = R (1 + amp * sum_lm c_lm Y_lm(u)) for unit u."""
 
@@ -169,12 +176,20 @@ class StarShape:
         self.sub_seed = sub
 
     def _f(self, u: np.ndarray) -> np.ndarray:
+        from scipy.special import sph_harm_y
         u = u / np.linalg.norm(u, axis=1, keepdims=True)
         polar = np.arccos(np.clip(u[:, 2], -1.0, 1.0))
         azim = np.arctan2(u[:, 1], u[:, 0])
+        coef = {(l, m): c for l, m, c in self.coef}
         f = np.zeros(u.shape[0])
-        for l, m, c in self.coef:
-            f += c * _real_sph_harm(l, m, polar, azim)
+        for l in range(self.lmax + 1):
+            for m in range(0, l + 1):
+                y = sph_harm_y(l, m, polar, azim)   # one evaluation serves +m and -m
+                if m == 0:
+                    f += coef[(l, 0)] * np.real(y)
+                else:
+                    s = math.sqrt(2.0) * (-1) ** m
+                    f += coef[(l, m)] * s * np.real(y) + coef[(l, -m)] * s * np.imag(y)
         return f
 
     def radius(self, u: np.ndarray) -> np.ndarray:
@@ -205,12 +220,12 @@ def charges_in_star(seed: int, n: int, shape: StarShape, frac: float = 0.8,
                     values: str = "normal", sigma: float = 0.4) -> Charges:
     """n charges uniform in {|x| < frac * r(x/|x|)}; values N(0, sigma) or U[-1, 1]."""
     rng = np.random.default_rng(int(seed))
-    rmax = frac * shape.base_radius * (1.0 + shape.amp * 4.0 * math.sqrt(2.0 * shape.lmax + 1.0))
+    rmax = 1.05 * frac * float(np.max(shape.radius(icosphere(16).xyz)))
     out = []
     while sum(len(o) for o in out) < n:
-        d = rng.standard_normal((4 * n, 3))
+        d = rng.standard_normal((16 * n, 3))
         d /= np.linalg.norm(d, axis=1, keepdims=True)
-        r = rmax * rng.random(4 * n) ** (1.0 / 3.0)
+        r = rmax * rng.random(16 * n) ** (1.0 / 3.0)
         keep = r < frac * shape.radius(d)
         out.append(d[keep] * r[keep, None])
     xyz = np.concatenate(out)[:n]

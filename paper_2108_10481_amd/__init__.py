@@ -62,7 +62,7 @@ class pb_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("operator_mode", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("singular_order", ctypes.c_int32),
                 ("source_chunks", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("memory_budget", ctypes.c_size_t)]
+                ("inner_tol", ctypes.c_double), ("memory_budget", ctypes.c_size_t), ("use_graph", ctypes.c_int32)]
 
 
 class pb_result(ctypes.Structure):
@@ -349,8 +349,11 @@ def pb_mesh_preconditioner(h: MeshHandle) -> np.ndarray:
     return out
 
 
-def pb_mesh_profile(h: MeshHandle, enable: bool) -> None:
-    _check(load().pb_mesh_profile(h.h, 1 if enable else 0))
+def pb_mesh_profile(h: MeshHandle, enable) -> None:
+    """enable: bit mask of kinds to time (1: operator product, 2: assembly);
+    True means both."""
+    mask = 3 if enable is True else (0 if enable is False else int(enable))
+    _check(load().pb_mesh_profile(h.h, mask))
 
 
 def pb_mesh_profile_read(h: MeshHandle, kind: int = 0):

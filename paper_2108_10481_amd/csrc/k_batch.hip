@@ -278,13 +278,13 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
         }
         Profiler &pf = d.prof;
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (pf.enabled) {
+        if (pf.on(0)) {
             HIPCHECK(hipEventCreate(&e0));
             HIPCHECK(hipEventCreate(&e1));
             HIPCHECK(hipEventRecord(e0, d.stream));
         }
         launch(D->gemm_rows - 1);
-        if (pf.enabled) {
+        if (pf.on(0)) {
             HIPCHECK(hipEventRecord(e1, d.stream));
             pf.record(0, e0, e1, (double)n * n * 2.0 + kMaxBatch * (double)n * (2.0 + 8.0));
         }
@@ -348,12 +348,12 @@ static void gmres_batch(DevMesh &d, int nb, const double *PB, double *X, const s
             double *col = &H[s][(size_t)j * (m + 1)];
             for (int i = 0; i <= j; ++i) col[i] = hs[i] + hs[j + 1 + i];
             col[j + 1] = std::sqrt(std::max(hs[2 * (j + 1)], 0.0));
-            for (int i = 0; i < j; ++i) {
-                const double a = cs[s][i] * col[i] + sn[s][i] * col[i + 1];
-                col[i + 1] = -sn[s][i] * col[i] + cs[s][i] * col[i + 1];
+            for (int i = 0; i < j; ++i) {   // explicit FMAs: same arithmetic as the device Givens kernel
+                const double a = std::fma(cs[s][i], col[i], sn[s][i] * col[i + 1]);
+                col[i + 1] = std::fma(-sn[s][i], col[i], cs[s][i] * col[i + 1]);
                 col[i] = a;
             }
-            const double den = std::hypot(col[j], col[j + 1]);
+            const double den = std::sqrt(std::fma(col[j], col[j], col[j + 1] * col[j + 1]));
             cs[s][j] = col[j] / den;
             sn[s][j] = col[j + 1] / den;
             col[j] = den;

@@ -25,8 +25,6 @@
 
 namespace pbm {
 
-int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
-
 
 // ------------------------------------------------------------ colouring
 // Greedy colouring of the triangles: two triangles sharing a vertex never get
@@ -309,8 +307,9 @@ __device__ __forceinline__ float fp16_to_f(uint16_t h) { return (float)__builtin
 template <typename S, typename ACC, int KIND>
 __global__ __launch_bounds__(256) void k_gemv(int n, int V, size_t Vp, size_t ld, const S *__restrict__ A,
                                               const ACC *__restrict__ x, float inv0, float inv1, float inv2, float inv3,
-                                              double *__restrict__ y)
+                                              double *__restrict__ y, DevCtl ctl)
 {
+    if (ctl_skip(ctl)) return;
     constexpr int W = Vec<S>::W;
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
@@ -372,8 +371,9 @@ __global__ __launch_bounds__(256) void k_gemv(int n, int V, size_t Vp, size_t ld
 template <typename S, typename ACC, int KIND, int R>
 __global__ __launch_bounds__(256) void k_gemv_tile(int n, int V, size_t Vp, size_t ld, const S *__restrict__ A,
                                                    const ACC *__restrict__ x, float inv0, float inv1, float inv2,
-                                                   float inv3, double *__restrict__ y)
+                                                   float inv3, double *__restrict__ y, DevCtl ctl)
 {
+    if (ctl_skip(ctl)) return;
     constexpr int W = Vec<S>::W;
     constexpr size_t step = 64 * W;
     const int lane = threadIdx.x & 63;
@@ -441,10 +441,11 @@ __global__ __launch_bounds__(256) void k_gemv_tile(int n, int V, size_t Vp, size
 // [x1 (dense index order) | 0 | x2 | 0]
 template <typename ACC>
 __global__ void k_pad_x(int V, size_t Vp, size_t ld, const int32_t *__restrict__ vperm, const double *__restrict__ x,
-                        ACC *__restrict__ xp)
+                        ACC *__restrict__ xp, DevCtl ctl)
 {
     size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ld) return;
+    if (c >= ld || ctl_skip(ctl)) return;
+    x += ctl_off(ctl);
     ACC v = ACC(0);
     if (c < (size_t)V) v = (ACC)x[vperm[c]];
     else if (c >= Vp && c < Vp + (size_t)V) v = (ACC)x[V + vperm[c - Vp]];
@@ -611,14 +612,14 @@ void build_dense(DevMesh &d)
     Dense &D = *d.dense;
     Profiler &pf = d.prof;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (pf.enabled) {
+    if (pf.on(1)) {
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, d.stream));
     }
     if (D.A64) assemble<double, double, 128>(d, D.A64);
     else assemble<float, float, 256>(d, D.A32);
-    if (pf.enabled) {
+    if (pf.on(1)) {
         HIPCHECK(hipEventRecord(e1, d.stream));
         // assembly work: 36 point pairs per ordered triangle pair, each evaluated once
         pf.record(1, e0, e1, 36.0 * (double)d.hm.T * (double)d.hm.T);
@@ -664,32 +665,32 @@ void destroy_dense(DevMesh &d)
 // matrix is picked by timing them once on the real matrix (autotune cache).
 template <typename S, typename ACC, int KIND>
 static void gemv_launch(int variant, hipStream_t st, int n, int V, size_t Vp, size_t ld, const S *A, const ACC *x,
-                        const float *inv, double *y)
+                        const float *inv, double *y, const DevCtl &ctl)
 {
     if (variant == 0) {
         const int nwg = std::min(n / 4 + 1, 8192);
         hipLaunchKernelGGL((k_gemv<S, ACC, KIND>), dim3(nwg), dim3(256), 0, st, n, V, Vp, ld, A, x, inv[0], inv[1],
-                           inv[2], inv[3], y);
+                           inv[2], inv[3], y, ctl);
     } else if (variant == 1) {
         const int nwg = std::min((n + 31) / 32, 8192);
         hipLaunchKernelGGL((k_gemv_tile<S, ACC, KIND, 8>), dim3(nwg), dim3(256), 0, st, n, V, Vp, ld, A, x, inv[0],
-                           inv[1], inv[2], inv[3], y);
+                           inv[1], inv[2], inv[3], y, ctl);
     } else {
         const int nwg = std::min((n + 63) / 64, 8192);
         hipLaunchKernelGGL((k_gemv_tile<S, ACC, KIND, 16>), dim3(nwg), dim3(256), 0, st, n, V, Vp, ld, A, x, inv[0],
-                           inv[1], inv[2], inv[3], y);
+                           inv[1], inv[2], inv[3], y, ctl);
     }
 }
 
-static void gemv_dispatch(Dense &D, int variant, hipStream_t st, bool lo, double *yfar)
+static void gemv_dispatch(Dense &D, int variant, hipStream_t st, bool lo, double *yfar, const DevCtl &ctl = DevCtl())
 {
     const int V = D.V;
     float one[4] = {1.f, 1.f, 1.f, 1.f}, inv[4];
     for (int b = 0; b < 4; ++b) inv[b] = 1.f / D.scale16[b];
-    if (D.A64) gemv_launch<double, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A64, D.x64, one, yfar);
-    else if (!lo) gemv_launch<float, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A32, D.x64, one, yfar);
-    else if (D.kind16 == 1) gemv_launch<uint16_t, float, 1>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, one, yfar);
-    else gemv_launch<uint16_t, float, 2>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, inv, yfar);
+    if (D.A64) gemv_launch<double, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A64, D.x64, one, yfar, ctl);
+    else if (!lo) gemv_launch<float, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A32, D.x64, one, yfar, ctl);
+    else if (D.kind16 == 1) gemv_launch<uint16_t, float, 1>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, one, yfar, ctl);
+    else gemv_launch<uint16_t, float, 2>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, inv, yfar, ctl);
 }
 
 int autotune_pick(const std::string &key, int nvariants, const std::function<void(int)> &run, hipStream_t st);
@@ -714,16 +715,16 @@ void dense_apply(DevMesh &d, const double *x, double *yfar)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     const dim3 gpad((unsigned)((D.ld + 255) / 256)), b256(256);
     const bool lo = D.level == 0 && D.A16;
-    if (!lo) hipLaunchKernelGGL(k_pad_x<double>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, D.vperm, x, D.x64);
-    else hipLaunchKernelGGL(k_pad_x<float>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, D.vperm, x, D.x32);
+    if (!lo) hipLaunchKernelGGL(k_pad_x<double>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, D.vperm, x, D.x64, d.ctl);
+    else hipLaunchKernelGGL(k_pad_x<float>, gpad, b256, 0, d.stream, V, D.Vp, D.ld, D.vperm, x, D.x32, d.ctl);
     const int variant = gemv_variant(d, lo);
-    if (pf.enabled) {
+    if (pf.on(0)) {
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, d.stream));
     }
-    gemv_dispatch(D, variant, d.stream, lo, yfar);
-    if (pf.enabled) {
+    gemv_dispatch(D, variant, d.stream, lo, yfar, d.ctl);
+    if (pf.on(0)) {
         HIPCHECK(hipEventRecord(e1, d.stream));
         // algorithmic bytes: the stored 2V x 2V entries (padding excluded) + x and y
         const double ent = (double)D.n * (double)D.n;
@@ -757,7 +758,7 @@ int mixed_refinement_solve(DevMesh &d, const double *b, const double *pb, double
     for (k = 1; k <= max_outer; ++k) {
         double e_in = 0.0;
         D.level = 0;
-        its += gmres(d, r, c, std::max(d.opt.inner_tol, 0.5 * d.opt.tol * nb / std::max(rel * nb, 1e-300)),
+        its += gmres_solve(d, r, c, std::max(d.opt.inner_tol, 0.5 * d.opt.tol * nb / std::max(rel * nb, 1e-300)),
                      std::min(d.opt.inner_max_iter, d.opt.max_iter), &e_in);
         D.level = 1;
         kr_axpy(s, n, 1.0, c, u);

@@ -20,10 +20,12 @@
 namespace pbm {
 
 __global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, const double *__restrict__ geo,
-                              const double *__restrict__ x, double *__restrict__ dyn64, float *__restrict__ dyn32)
+                              const double *__restrict__ x, double *__restrict__ dyn64, float *__restrict__ dyn32,
+                              DevCtl ctl)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= T) return;
+    if (s >= T || ctl_skip(ctl)) return;
+    x += ctl_off(ctl);
     const double *g = geo + (size_t)s * kGeo;
     const double area = g[21];
     double u1[3], u2[3];
@@ -57,7 +59,7 @@ void launch_source_prep(DevMesh &d, const double *x, bool)
 {
     int T = d.hm.T;
     hipLaunchKernelGGL(k_source_prep, dim3((T + 255) / 256), dim3(256), 0, d.stream, T, d.hm.V, d.tri, d.geo, x,
-                       d.dyn64, d.dyn32);
+                       d.dyn64, d.dyn32, d.ctl);
     HIPCHECK(hipGetLastError());
 }
 
@@ -100,12 +102,12 @@ constexpr int kFarBlock = 256;
 template <typename R, int FORM>
 __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> cf, const int32_t *__restrict__ tri,
                                                     const R *__restrict__ stat, const R *__restrict__ dyn,
-                                                    R *__restrict__ part)
+                                                    R *__restrict__ part, DevCtl ctl)
 {
     const int t = blockIdx.x * kFarBlock + threadIdx.x;
     const int s0 = blockIdx.y * chunk;
     const int s1 = min(T, s0 + chunk);
-    if (t >= T) return;
+    if (t >= T || ctl_skip(ctl)) return;
     const R *ts = stat + (size_t)t * kStat;
     R tx[6], ty[6], tz[6];
 #pragma unroll
@@ -180,10 +182,10 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
 
 template <typename R>
 __global__ void k_far_finish(int T, int S, int form, const double *__restrict__ geo, const R *__restrict__ part,
-                             double *__restrict__ triout)
+                             double *__restrict__ triout, DevCtl ctl)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
+    if (t >= T || ctl_skip(ctl)) return;
     double pot[15];
     for (int v = 0; v < 15; ++v) pot[v] = 0.0;
     for (int c = 0; c < S; ++c) {
@@ -213,10 +215,12 @@ __global__ void k_gather(int V, int use_far, int use_near, int precond, const in
                          const double *__restrict__ yfar, const int32_t *__restrict__ vpos,
                          const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                          const double *__restrict__ N, int64_t nnz, const double *__restrict__ pinv,
-                         const double *__restrict__ x, double *__restrict__ y)
+                         const double *__restrict__ x, double *__restrict__ y, DevCtl ctl)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V) return;
+    if (i >= V || ctl_skip(ctl)) return;
+    x += ctl_off(ctl);
+    y += ctl_off(ctl);
     double y1 = 0.0, y2 = 0.0;
     if (use_far == 2) {   // dense far product, rows in dense vertex order
         const int r = vpos[i];
@@ -277,9 +281,9 @@ static void far_launch(DevMesh &d, const R *stat, const R *dyn)
     dim3 grid((T + kFarBlock - 1) / kFarBlock, S), block(kFarBlock);
     R *part = (R *)d.part;
     if (direct)
-        hipLaunchKernelGGL((k_far<R, 0>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part);
+        hipLaunchKernelGGL((k_far<R, 0>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     else
-        hipLaunchKernelGGL((k_far<R, 1>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part);
+        hipLaunchKernelGGL((k_far<R, 1>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     HIPCHECK(hipGetLastError());
 }
 
@@ -287,14 +291,14 @@ void launch_far(DevMesh &d, bool fp32)
 {
     Profiler &pf = d.prof;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (pf.enabled) {
+    if (pf.on(0)) {
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, d.stream));
     }
     if (fp32) far_launch<float>(d, d.stat32, d.dyn32);
     else far_launch<double>(d, d.stat64, d.dyn64);
-    if (pf.enabled) {
+    if (pf.on(0)) {
         HIPCHECK(hipEventRecord(e1, d.stream));
         const double P = 6.0 * d.hm.T;
         pf.record(0, e0, e1, P * P);   // kernel pairs, near-masked pairs included
@@ -307,10 +311,10 @@ void launch_far_finish(DevMesh &d, bool fp32)
     dim3 grid((T + 255) / 256), block(256);
     if (fp32)
         hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, d.prm.formulation, d.geo,
-                           (const float *)d.part, d.triout);
+                           (const float *)d.part, d.triout, d.ctl);
     else
         hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, d.prm.formulation, d.geo,
-                           (const double *)d.part, d.triout);
+                           (const double *)d.part, d.triout, d.ctl);
     HIPCHECK(hipGetLastError());
 }
 
@@ -320,7 +324,7 @@ void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_fa
     const int use_near = (flags & PB_APPLY_FAR_ONLY) ? 0 : 1;
     hipLaunchKernelGGL(k_gather, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, use_far, use_near,
                        (flags & PB_APPLY_PRECOND) ? 1 : 0, d.inc_ptr, d.inc_tk, d.triout, d.yfar, d.dense_vpos, d.row_ptr, d.col, d.N,
-                       d.nnz(), d.pinv, x, y);
+                       d.nnz(), d.pinv, x, y, d.ctl);
     HIPCHECK(hipGetLastError());
 }
 

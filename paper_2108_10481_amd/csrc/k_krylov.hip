@@ -96,3 +96,109 @@ void kr_precond(hipStream_t s, int V, const double *pinv, const double *x, doubl
 }
 
 }  // namespace pbm
+
+// ----------------------------------------------- captured GMRES iteration
+// The iteration index and the stopping flag live in device memory, so one
+// captured graph serves every iteration; blocks beyond the current basis size
+// return at once.
+namespace pbm {
+
+__global__ __launch_bounds__(kKB) void k_gdots(int n, const double *__restrict__ Vb, const GState *__restrict__ st,
+                                               double *__restrict__ out)
+{
+    __shared__ double sh[kKB];
+    const int i = blockIdx.x;
+    if (st->done || i > st->j) return;
+    const double *v = Vb + (size_t)i * n;
+    const double *w = Vb + (size_t)(st->j + 1) * n;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n; e += kKB) acc += v[e] * w[e];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kKB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sh[0];
+}
+
+__global__ void k_gupdate(int n, const double *__restrict__ Vb, const GState *__restrict__ st,
+                          const double *__restrict__ h)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n || st->done) return;
+    const int j = st->j;
+    double acc = 0.0;
+    for (int i = 0; i <= j; ++i) acc += h[i] * Vb[(size_t)i * n + e];
+    ((double *)Vb)[(size_t)(j + 1) * n + e] -= acc;
+}
+
+// |w|^2 with one block, same reduction shape as k_dots
+__global__ __launch_bounds__(kKB) void k_gnorm(int n, const double *__restrict__ Vb, GState *__restrict__ st)
+{
+    __shared__ double sh[kKB];
+    if (st->done) return;
+    const double *w = Vb + (size_t)(st->j + 1) * n;
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < n; e += kKB) acc += w[e] * w[e];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kKB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st->nrm2 = sh[0];
+}
+
+// Hessenberg column j = h1 + h2 (two Gram-Schmidt passes), previous Givens
+// rotations, new rotation, residual estimate |g_{j+1}|; advances j.  The
+// rotations are written with explicit fused multiply-adds, exactly as the host
+// implementations are, so eager, batched and captured solves agree bitwise.
+__global__ void k_givens(GState *__restrict__ st, double *__restrict__ H, double *__restrict__ cs,
+                         double *__restrict__ sn, double *__restrict__ g, const double *__restrict__ h1,
+                         const double *__restrict__ h2)
+{
+    if (threadIdx.x != 0 || st->done) return;
+    const int j = st->j, m = st->m;
+    double *col = H + (size_t)j * (m + 1);
+    for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+    const double hn = sqrt(fmax(st->nrm2, 0.0));
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = fma(cs[i], col[i], sn[i] * col[i + 1]);
+        col[i + 1] = fma(-sn[i], col[i], cs[i] * col[i + 1]);
+        col[i] = a;
+    }
+    const double den = sqrt(fma(col[j], col[j], col[j + 1] * col[j + 1]));
+    cs[j] = col[j] / den;
+    sn[j] = col[j + 1] / den;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    st->res = fabs(g[j + 1]);
+    st->inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    st->j = j + 1;
+    if (st->res <= st->tolb || !(den > 0.0) || j + 1 >= m) st->done = 1;
+}
+
+__global__ void k_gnormalize(int n, double *__restrict__ Vb, const GState *__restrict__ st)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n || st->done) return;
+    Vb[(size_t)st->j * n + e] *= st->inv;
+}
+
+void kr_graph_iteration_tail(hipStream_t s, int n, int m, double *Vb, GState *st, double *H, double *cs, double *sn,
+                             double *g, double *h1, double *h2)
+{
+    hipLaunchKernelGGL(k_gdots, dim3(m + 1), dim3(kKB), 0, s, n, Vb, st, h1);
+    hipLaunchKernelGGL(k_gupdate, g1(n), dim3(kKB), 0, s, n, Vb, st, h1);
+    hipLaunchKernelGGL(k_gdots, dim3(m + 1), dim3(kKB), 0, s, n, Vb, st, h2);
+    hipLaunchKernelGGL(k_gupdate, g1(n), dim3(kKB), 0, s, n, Vb, st, h2);
+    hipLaunchKernelGGL(k_gnorm, dim3(1), dim3(kKB), 0, s, n, Vb, st);
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, st, H, cs, sn, g, h1, h2);
+    hipLaunchKernelGGL(k_gnormalize, g1(n), dim3(kKB), 0, s, n, Vb, st);
+}
+
+}  // namespace pbm

@@ -71,6 +71,31 @@ constexpr int kDyn = 16;
 // per-triangle FP64 geometry: pts 18, normal 3, area 1, curl 9 -> 31, padded
 constexpr int kGeo = 32;
 
+// Device-side control of a captured GMRES iteration: kernels offset their
+// vector arguments by (*j) * stride and return at once when *skip is set.
+// Default-constructed (eager launches): no offset, never skip.
+struct DevCtl {
+    const int *j = nullptr;
+    const int *skip = nullptr;
+    size_t stride = 0;
+};
+__device__ inline bool ctl_skip(const DevCtl &c) { return c.skip && *c.skip; }
+__device__ inline size_t ctl_off(const DevCtl &c) { return c.j ? (size_t)(*c.j) * c.stride : 0; }
+
+struct GraphGmres;   // captured GMRES iteration (runtime.hip)
+
+// device state of a captured GMRES solve
+struct GState {
+    int j;          // iterations done (basis vectors 0..j exist)
+    int done;       // stop flag: converged, breakdown, or m reached
+    int m;          // capacity (max iterations)
+    int pad;
+    double tolb;    // tol * |pb|
+    double res;     // current residual estimate |g_j|
+    double nrm2;    // |w|^2 of the new vector
+    double inv;     // 1 / |w|
+};
+
 struct Params {
     double eps_in, eps_out, kappa;
     int formulation, preconditioner, precision, operator_mode;
@@ -81,7 +106,8 @@ struct Params {
 // kind 1: dense far-field assembly.  work = algorithmic kernel pairs
 // (matrix-free), bytes (dense product) or point-pair evaluations (assembly).
 struct Profiler {
-    bool enabled = false;
+    int mask = 0;   // bit 0: kind 0 (operator product), bit 1: kind 1 (assembly)
+    bool on(int kind) const { return (mask >> kind) & 1; }
     std::vector<hipEvent_t> ev[2];   // start/stop pairs
     std::vector<double> pend_work[2];
     int64_t launches[2] = {0, 0};
@@ -140,6 +166,8 @@ struct DevMesh {
     double *yfar = nullptr;        // 2V far-field product (assembled mode)
     double *u = nullptr;           // 2V solution
     Krylov kry;
+    DevCtl ctl;                    // set while a GMRES iteration is being captured
+    GraphGmres *gg[2] = {nullptr, nullptr};   // per operator level
     double t_setup = 0.0;
     bool want_dense = false;
     // charges workspace
@@ -177,6 +205,9 @@ void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const
 int choose_chunks(int T);
 int reduction_chunks(int T);
 pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res);
+int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
+int gmres_solve(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
+void destroy_graphs(DevMesh &d);
 
 // assembled far field and mixed precision (k_dense.hip)
 bool dense_fits(const DevMesh &d);
@@ -199,5 +230,7 @@ void kr_scale_copy(hipStream_t s, int n, const double *x, double a, double *y);
 void kr_axpy(hipStream_t s, int n, double a, const double *x, double *y);
 void kr_combine(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *y, double *x);
 void kr_precond(hipStream_t s, int V, const double *pinv, const double *x, double *y);
+void kr_graph_iteration_tail(hipStream_t s, int n, int m, double *Vb, GState *st, double *H, double *cs, double *sn,
+                             double *g, double *h1, double *h2);
 
 }  // namespace pbm

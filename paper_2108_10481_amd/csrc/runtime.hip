@@ -9,7 +9,7 @@
 #include <memory>
 #include <vector>
 
-#include "pbm_internal.h"
+#include "dense.h"
 
 namespace pbm {
 
@@ -45,6 +45,7 @@ DevMesh::~DevMesh()
     if (stream) (void)hipStreamSynchronize(stream);
     for (int k = 0; k < 2; ++k)
         for (hipEvent_t e : prof.ev[k]) (void)hipEventDestroy(e);
+    destroy_graphs(*this);
     destroy_dense(*this);
     destroy_batch(*this);
     for (void *p : allocs) (void)hipFreeAsync(p, stream);
@@ -252,12 +253,12 @@ int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, dou
         for (int i = 0; i <= j; ++i) col[i] = hb[i] + hb[j + 1 + i];
         col[j + 1] = std::sqrt(std::max(hb[2 * (j + 1)], 0.0));
         if (col[j + 1] > 0.0) kr_scale_copy(s, n, w, 1.0 / col[j + 1], w);
-        for (int i = 0; i < j; ++i) {
-            const double a = cs[i] * col[i] + sn[i] * col[i + 1];
-            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        for (int i = 0; i < j; ++i) {   // explicit FMAs: same arithmetic as the device Givens kernel
+            const double a = std::fma(cs[i], col[i], sn[i] * col[i + 1]);
+            col[i + 1] = std::fma(-sn[i], col[i], cs[i] * col[i + 1]);
             col[i] = a;
         }
-        const double den = std::hypot(col[j], col[j + 1]);
+        const double den = std::sqrt(std::fma(col[j], col[j], col[j + 1] * col[j + 1]));
         cs[j] = col[j] / den;
         sn[j] = col[j + 1] / den;
         col[j] = den;
@@ -278,6 +279,139 @@ int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, dou
     kr_combine(s, n, k, Vb, n, d.kry.y, x);
     *est = res / beta;
     return k;
+}
+
+// ------------------------------------------------------ captured GMRES
+// One Arnoldi step (operator product, CGS2, norm, device Givens, normalise)
+// is captured once per handle and operator level as a HIP graph whose kernels
+// read the iteration index and stop flag from device memory; the host replays
+// it kReplay times between convergence checks, so iterations run back to back
+// without a host round trip.  Same arithmetic as the eager loop except that the
+// Givens rotations run on the device.
+struct GraphGmres {
+    int m = 0, n = 0;
+    const double *basis = nullptr;
+    GState *st = nullptr;
+    double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *h1 = nullptr, *h2 = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphGmres()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+constexpr int kReplay = 8;
+
+static GraphGmres *capture_iteration(DevMesh &d, int m)
+{
+    const int n = 2 * d.hm.V;
+    std::unique_ptr<GraphGmres> G(new GraphGmres());
+    G->m = m;
+    G->n = n;
+    G->basis = d.kry.basis;
+    G->st = (GState *)d.alloc(sizeof(GState));
+    G->H = (double *)d.alloc(sizeof(double) * (size_t)(m + 1) * m);
+    G->cs = (double *)d.alloc(sizeof(double) * m);
+    G->sn = (double *)d.alloc(sizeof(double) * m);
+    G->g = (double *)d.alloc(sizeof(double) * (m + 1));
+    G->h1 = (double *)d.alloc(sizeof(double) * (m + 1));
+    G->h2 = (double *)d.alloc(sizeof(double) * (m + 1));
+    // one eager product first: settles autotuned launch shapes outside the capture
+    apply_operator(d, d.kry.basis, d.ztmp, PB_APPLY_PRECOND, nullptr);
+    HIPCHECK(hipStreamSynchronize(d.stream));
+    double *Vb = d.kry.basis;
+    d.ctl = DevCtl{&G->st->j, &G->st->done, (size_t)n};
+    HIPCHECK(hipStreamBeginCapture(d.stream, hipStreamCaptureModeThreadLocal));
+    try {
+        apply_operator(d, Vb, Vb + n, PB_APPLY_PRECOND, nullptr);
+        kr_graph_iteration_tail(d.stream, n, m, Vb, G->st, G->H, G->cs, G->sn, G->g, G->h1, G->h2);
+        HIPCHECK(hipGetLastError());
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(d.stream, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        d.ctl = DevCtl();
+        throw;
+    }
+    d.ctl = DevCtl();
+    HIPCHECK(hipStreamEndCapture(d.stream, &G->graph));
+    HIPCHECK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
+    return G.release();
+}
+
+void destroy_graphs(DevMesh &d)
+{
+    for (auto &g : d.gg) {
+        delete g;
+        g = nullptr;
+    }
+}
+
+static int gmres_graph(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est)
+{
+    const int n = 2 * d.hm.V;
+    const int m = std::min(max_iter, n);
+    ensure_krylov(d, m);
+    const int level = d.dense ? d.dense->level : 1;
+    GraphGmres *&G = d.gg[level];
+    if (G && (G->m != m || G->basis != d.kry.basis)) {
+        delete G;
+        G = nullptr;
+    }
+    hipStream_t s = d.stream;
+    kr_dots(s, n, 1, pb, n, pb, d.red1);
+    double beta2 = 0.0;
+    HIPCHECK(hipMemcpyAsync(&beta2, d.red1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    const double beta = std::sqrt(beta2);
+    if (!(beta > 0.0)) {
+        HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+        *est = 0.0;
+        return 0;
+    }
+    kr_scale_copy(s, n, pb, 1.0 / beta, d.kry.basis);
+    if (!G) G = capture_iteration(d, m);
+    GState h0{};
+    h0.j = 0;
+    h0.done = 0;
+    h0.m = m;
+    h0.tolb = tol * beta;
+    h0.res = beta;
+    std::vector<double> g0(m + 1, 0.0);
+    g0[0] = beta;
+    HIPCHECK(hipMemcpyAsync(G->st, &h0, sizeof(GState), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(G->g, g0.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
+    GState hs{};
+    for (;;) {
+        for (int r = 0; r < kReplay; ++r) HIPCHECK(hipGraphLaunch(G->exec, s));
+        HIPCHECK(hipMemcpyAsync(&hs, G->st, sizeof(GState), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (hs.done || hs.j >= m) break;
+    }
+    const int k = hs.j;
+    std::vector<double> H((size_t)(m + 1) * k), g(k + 1), y(k);
+    HIPCHECK(hipMemcpyAsync(H.data(), G->H, sizeof(double) * H.size(), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(g.data(), G->g, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int i = k - 1; i >= 0; --i) {
+        double a = g[i];
+        for (int l = i + 1; l < k; ++l) a -= H[(size_t)l * (m + 1) + i] * y[l];
+        y[i] = a / H[(size_t)i * (m + 1) + i];
+    }
+    HIPCHECK(hipMemcpyAsync(d.kry.y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    kr_combine(s, n, k, d.kry.basis, n, d.kry.y, x);
+    *est = hs.res / beta;
+    return k;
+}
+
+// captured iterations unless profiling the operator kernels (their events
+// are recorded eagerly) or the handle asks for eager launches
+int gmres_solve(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est)
+{
+    if (d.prof.on(0) || d.opt.use_graph == 0) return gmres(d, pb, x, tol, max_iter, est);
+    return gmres_graph(d, pb, x, tol, max_iter, est);
 }
 
 // ------------------------------------------------------------ charges, dG
@@ -408,7 +542,7 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
     if (d.prm.precision >= PB_MIXED_BF16)
         its = mixed_refinement_solve(d, b, pb, d.u, &est, &outer);
     else
-        its = gmres(d, pb, d.u, d.opt.tol, d.opt.max_iter, &est);
+        its = gmres_solve(d, pb, d.u, d.opt.tol, d.opt.max_iter, &est);
     HIPCHECK(hipStreamSynchronize(d.stream));
     double t3 = now();
     return finish_result(d, ch, pb, d.u, its, outer, t1 - t0, t2 - t1, t3 - t2, res);
@@ -459,6 +593,7 @@ void pb_default_options(pb_options *o)
     o->inner_max_iter = 200;
     o->inner_tol = 1e-3;
     o->memory_budget = 0;
+    o->use_graph = 1;
 }
 
 const char *pb_last_error(void) { return g_err.c_str(); }
@@ -650,7 +785,7 @@ pb_status pb_mesh_profile(pb_mesh_handle *h, int32_t enable)
         p.total_ms[k] = 0.0;
         p.work[k] = 0.0;
     }
-    p.enabled = enable != 0;
+    p.mask = enable & 3;
     return PB_OK;
     PB_CATCH
 }

@@ -404,3 +404,39 @@ def test_star_full_size_sampled_rows():
             with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec)) as h:
                 y = pbm.pb_mesh_apply(h, x)
             assert _rel(np.concatenate([y[rows], y[nv + rows]]), ref) < tol, (form, prec)
+
+
+# ---------------------------------------------------------- captured GMRES
+@pytest.mark.parametrize("prec,mode", [(pbm.PB_FP64, pbm.PB_MATRIX_FREE), (pbm.PB_FP32, pbm.PB_ASSEMBLED),
+                                       (pbm.PB_MIXED_BF16, pbm.PB_ASSEMBLED)])
+@pytest.mark.parametrize("form", [0, 1])
+def test_graph_gmres_matches_eager(meshes, prec, mode, form):
+    """GMRES iterations replayed from a captured HIP graph (device Givens) give
+    the eager solve's iterations and Delta G; the graph is replayed across
+    several solves on one handle with eager work between them."""
+    m = meshes["star7"]
+    sets = [inputs.charges_ball(600 + k, 15, 2.5) for k in range(3)]
+    x = np.random.default_rng(3).standard_normal(2 * m.n_vertices)
+    og = _opts(form, prec, operator_mode=mode)
+    oe = _opts(form, prec, operator_mode=mode, use_graph=0)
+    with pbm.MeshHandle(m.xyz, m.tri, og) as hg, pbm.MeshHandle(m.xyz, m.tri, oe) as he:
+        for c in sets:
+            rg = pbm.pb_mesh_solve(hg, c.xyz, c.q)
+            yg = pbm.pb_mesh_apply(hg, x)          # eager work between graph replays
+            re = pbm.pb_mesh_solve(he, c.xyz, c.q)
+            ye = pbm.pb_mesh_apply(he, x)
+            assert np.array_equal(yg, ye)
+            assert rg["iterations"] == re["iterations"] and rg["outer_iterations"] == re["outer_iterations"]
+            assert abs(rg["dG"] - re["dG"]) <= 1e-12 * abs(re["dG"])
+            assert rg["status"] == pbm.PB_OK
+
+
+def test_graph_gmres_small_and_nonconverged():
+    """Kirkwood sphere (tiny, launch-latency bound) through the graph path, and
+    a max_iter stop inside a replay batch."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    ref = oracle.solve(m, ch)
+    r = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts())
+    assert abs(r["dG"] - ref["dG"]) < 1e-6 * abs(ref["dG"]) and r["iterations"] == ref["iterations"]
+    r3 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(max_iter=3))
+    assert r3["status"] == pbm.PB_NOT_CONVERGED and r3["iterations"] == 3
