@@ -37,6 +37,16 @@ METRIC = ("operator matvec kernel-pairs/s; solves/s + p99 latency at ΔG rel err
 # exp and rsqrt = 1 each), counted from the kernel formula
 FLOPS_PER_PAIR = {0: 28, 1: 38}
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X published vector peaks
+# far-field assembly, per far point pair evaluated once, counted from the
+# assembly formula: kernel values (direct 21.8 flops / 18.5 lane operations,
+# Juffer 30.5 / 24.5) plus the basis contraction in the two-orbit form of the
+# 6-point rule (17.3 flops / 12 lane operations per point pair)
+ASM_FLOPS_PER_PP = {0: 39.17, 1: 47.83}
+ASM_LANE_OPS_PER_PP = {0: 30.5, 1: 36.5}   # two of them transcendental (rsqrt, exp2)
+# VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane operations per second
+# without packed FP32; a transcendental occupies four issue slots
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+TRANS_SLOTS = 4
 
 
 def parse():
@@ -137,15 +147,19 @@ def main():
         # dominant kernel: the far-field assembly (VALU); the dense product is
         # reported against the HBM roofline beside it
         evals = sum(prof_asm[f][2] for f in forms)
-        # algorithmic: each far point pair once (the recorded work), kernel
-        # formula + 4 combined values x 9 basis products (FMA = 2 flops)
-        flops = sum(prof_asm[f][2] * (FLOPS_PER_PAIR[f] + 72) for f in forms)
+        # algorithmic: each far point pair once (the recorded work) times the
+        # formula's flops per point pair
+        flops = sum(prof_asm[f][2] * ASM_FLOPS_PER_PP[f] for f in forms)
         achieved = flops / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0
+        slots = sum(prof_asm[f][2] * (ASM_LANE_OPS_PER_PP[f] + 2 * (TRANS_SLOTS - 1)) for f in forms)
+        issue = slots / (asm_ms * 1e-3) if asm_ms > 0 else 0.0
         nasm = sum(prof_asm[f][0] for f in forms)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS[dtype], 4), "traffic": None, "kernel": "k_assemble",
                 "launches": nasm, "avg_launch_ms": round(asm_ms / max(nasm, 1), 4),
-                "point_pair_evals_per_s": round(evals / (asm_ms * 1e-3), 1) if asm_ms > 0 else None}
+                "point_pair_evals_per_s": round(evals / (asm_ms * 1e-3), 1) if asm_ms > 0 else None,
+                "valu_issue": {"slots_per_s": round(issue, 1), "peak_slots_per_s": VALU_SLOTS_PER_S,
+                               "frac": round(issue / VALU_SLOTS_PER_S, 4)} if dtype == "f32" else None}
         gbytes = sum(prof[f][2] for f in forms)
         gbs = gbytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
         dense_product = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",

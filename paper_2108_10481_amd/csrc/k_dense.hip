@@ -73,6 +73,23 @@ __device__ __forceinline__ double rsq_a(double x)
 __device__ __forceinline__ float expn_a(float kl, float r) { return __builtin_amdgcn_exp2f(-kl * r); }
 __device__ __forceinline__ double expn_a(double k, double r) { return exp(-k * r); }
 
+// Orbit form of the 6-point rule (Numerical integration): its points form two
+// orbits of three with barycentric coordinates (1-2a, a, a) and (1-2b, b, b).
+// For any values v_p, sum_p w_p lambda_k(x_p) v_p equals
+//   cA (v_k + rho v_{k+3} + al (v_0+v_1+v_2) + be (v_3+v_4+v_5))
+// with cA = wA(1-3a), rho = wB(1-3b)/cA, al = wA a/cA, be = wB b/cA, which is
+// 12 instead of 18 operations per value and weight pass.
+struct RuleOrbit {
+    static constexpr double cA = kRuleWA * (1.0 - 3.0 * kRuleA);
+    static constexpr double rho = kRuleWB * (1.0 - 3.0 * kRuleB) / cA;
+    static constexpr double al = kRuleWA * kRuleA / cA;
+    static constexpr double be = kRuleWB * kRuleB / cA;
+};
+
+template <typename R> struct alignas(4 * sizeof(R)) Quad {
+    R v[4];
+};
+
 // Block = (target triangle t of the current colour, tile of TILE Morton-ordered
 // source triangles of the current tile colour).
 // Phase 1: lane s computes the whole local 3 x 3 block of the pair (t, s) for
@@ -80,9 +97,12 @@ __device__ __forceinline__ double expn_a(double k, double r) { return exp(-k * r
 //   exactly once -- into LDS (zero if s shares a vertex with t).  Per point
 //   pair (FORM 0, direct) F_L d.n_s, -G_L, -F_Y d.n_s, eps G_Y, or (FORM 1,
 //   Juffer) (F_L - alpha F_Y) d.n_s, G_Y - G_L, G_Y, (F_L - beta F_Y) d.n_t, with
-//   the hypersingular curl part added from sum (G_Y - G_L) per pair.
+//   the hypersingular curl part added from sum (G_Y - G_L) per pair.  Signs
+//   and constant factors are applied once per block, not per point pair.
 // Phase 2: lane v sums, for one vertex touched by the tile, the block columns
 //   of its incident tile triangles, and adds the 3 x 4 values to rows t_0..t_2.
+//   The 12 matrix entries of the lane's first vertex are read before phase 1,
+//   so the read-modify-write does not wait on HBM at the end.
 // Target colours keep rows disjoint and tile colours keep columns disjoint
 // between concurrently running blocks, so there is no atomic and the result
 // is deterministic.
@@ -93,120 +113,147 @@ __global__ __launch_bounds__(TILE) void k_assemble_tile(
     const int32_t *__restrict__ vpos, const int32_t *__restrict__ tv_ptr, const int32_t *__restrict__ tv_col,
     const int32_t *__restrict__ tv_eptr, const int32_t *__restrict__ te, S *__restrict__ A, size_t ld, size_t Vp)
 {
-    __shared__ R lds[36 * TILE];
+    __shared__ Quad<R> lds[9 * TILE];
     const int t = targets[blockIdx.y];
     const int tile = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int s = tile * TILE + tid;
+    // lanes past the last triangle evaluate the last one and are zeroed below
+    const int sl = s < T ? s : T - 1;
     const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
-    R blk[3][3][4];   // [l][k][o]
+    const int j0 = tri[3 * sl], j1 = tri[3 * sl + 1], j2 = tri[3 * sl + 2];
+    const bool live = (s < T) & !((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
+                                 (j2 == v0) | (j2 == v1) | (j2 == v2));
+    const R *ts = stat + (size_t)t * kStat;   // uniform: scalar loads
+    const R *ss = stat + (size_t)sl * kStat;
+    const R nsx = ss[18], nsy = ss[19], nsz = ss[20];
+    R sy[6][3], yns[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        sy[q][0] = ss[3 * q]; sy[q][1] = ss[3 * q + 1]; sy[q][2] = ss[3 * q + 2];
+        yns[q] = ss[21 + q];
+    }
+
+    const int eb = tv_ptr[tile], ee = tv_ptr[tile + 1];
+    const size_t rk[3] = {(size_t)vpos[v0], (size_t)vpos[v1], (size_t)vpos[v2]};
+    size_t c = 0;
+    S old[3][4];
+    auto fetch = [&](int e) {
+        c = (size_t)tv_col[e];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const S *r1 = A + rk[k] * ld, *r2 = A + ((size_t)V + rk[k]) * ld;
+            old[k][0] = r1[c];
+            old[k][1] = r1[Vp + c];
+            old[k][2] = r2[c];
+            old[k][3] = r2[Vp + c];
+        }
+    };
+    // unconditional (a lane without a vertex re-reads the tile's first one and
+    // never stores it), so the loads stay in flight through phase 1
+    fetch(eb + tid < ee ? eb + tid : eb);
+
+    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+    const R rho = (R)RuleOrbit::rho, al = (R)RuleOrbit::al, be = (R)RuleOrbit::be;
+    R blk[3][3][4], Cq[3][4];   // [l][k][o]; Cq: rank-two part of the target-side weights
+    R Ssum = 0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const R ynt = FORM == 1 ? sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz : R(0);
+        R X[3][4], SA[4], SB[4];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const R tx = ts[3 * p], ty = ts[3 * p + 1], tz = ts[3 * p + 2];
+            const R dx = tx - sy[q][0], dy = ty - sy[q][1], dz = tz - sy[q][2];
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            const R ri = rsq_a(r2);
+            const R r = r2 * ri;
+            const R ek = expn_a(cf.kexp, r);
+            const R ri3 = ri * ri * ri;
+            const R dns = (tx * nsx + ty * nsy + tz * nsz) - yns[q];
+            const R ekk = ek * (cf.kappa * r + R(1));
+            R v[4];
+            if (FORM == 0) {
+                // F_L d.n_s, G_L, F_Y d.n_s, G_Y without the factors 1, -1, -1, eps
+                v[0] = ri3 * dns;
+                v[1] = ri;
+                v[2] = ekk * v[0];
+                v[3] = ek * ri;
+            } else {
+                const R fy = ekk * ri3;
+                const R gy = ek * ri;
+                v[0] = (ri3 - cf.c1 * fy) * dns;
+                v[1] = gy - ri;
+                v[2] = gy;
+                v[3] = (ri3 - cf.c2 * fy) * (ts[21 + p] - ynt);
+            }
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                if (p < 3) {
+                    X[p][o] = v[o];
+                    SA[o] = p == 0 ? v[o] : SA[o] + v[o];
+                } else {
+                    X[p - 3][o] += rho * v[o];
+                    SB[o] = p == 3 ? v[o] : SB[o] + v[o];
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const R cc = al * SA[o] + be * SB[o];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) X[k][o] += cc;
+        }
+        if (FORM == 1) Ssum += R(rule_w(q)) * (R(kRuleWA) * SA[1] + R(kRuleWB) * SB[1]);
+        const R wc = q < 3 ? al : be;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                if (q < 3) blk[q][k][o] = X[k][o];
+                else blk[q - 3][k][o] += rho * X[k][o];
+                Cq[k][o] = q == 0 ? wc * X[k][o] : Cq[k][o] + wc * X[k][o];
+            }
+    }
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int o = 0; o < 4; ++o) blk[l][k][o] = 0;
-    bool live = s < T;
-    int j0 = 0, j1 = 0, j2 = 0;
-    if (live) {
-        j0 = tri[3 * s]; j1 = tri[3 * s + 1]; j2 = tri[3 * s + 2];
-        live = !((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) | (j2 == v0) |
-                 (j2 == v1) | (j2 == v2));
-    }
-    if (live) {
-        const R *ts = stat + (size_t)t * kStat;   // uniform: scalar loads
-        const R *ss = stat + (size_t)s * kStat;
-        const R ntx = ts[18], nty = ts[19], ntz = ts[20];
-        const R nsx = ss[18], nsy = ss[19], nsz = ss[20];
-        R sy[6][3], yns[6], ynt[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            sy[q][0] = ss[3 * q]; sy[q][1] = ss[3 * q + 1]; sy[q][2] = ss[3 * q + 2];
-            yns[q] = ss[21 + q];
-            ynt[q] = sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz;
-        }
-        R Ssum = 0;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            R X[3][4];
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int o = 0; o < 4; ++o) X[k][o] = 0;
-            R Sq = 0;
-#pragma unroll
-            for (int p = 0; p < 6; ++p) {
-                const R tx = ts[3 * p], ty = ts[3 * p + 1], tz = ts[3 * p + 2];
-                const R dx = tx - sy[q][0], dy = ty - sy[q][1], dz = tz - sy[q][2];
-                const R r2 = dx * dx + dy * dy + dz * dz;
-                const R ri = rsq_a(r2);
-                const R r = r2 * ri;
-                const R ek = expn_a(cf.kexp, r);
-                const R ri3 = ri * ri * ri;
-                const R dns = (tx * nsx + ty * nsy + tz * nsz) - yns[q];
-                const R fy = ek * (cf.kappa * r + R(1)) * ri3;
-                R v[4];
-                if (FORM == 0) {
-                    v[0] = ri3 * dns;
-                    v[1] = -ri;
-                    v[2] = -fy * dns;
-                    v[3] = cf.c1 * ek * ri;
-                } else {
-                    const R gy = ek * ri;
-                    v[0] = (ri3 - cf.c1 * fy) * dns;
-                    v[1] = gy - ri;
-                    v[2] = gy;
-                    v[3] = (ri3 - cf.c2 * fy) * (ts[21 + p] - ynt[q]);
-                    Sq += R(rule_w(p)) * v[1];
-                }
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const R c = R(rule_w(p) * rule_bary(p, k));
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) X[k][o] += c * v[o];
-                }
-            }
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                const R wq = R(rule_w(q) * rule_bary(q, l));
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int o = 0; o < 4; ++o) blk[l][k][o] += wq * X[k][o];
-            }
-            if (FORM == 1) Ssum += R(rule_w(q)) * Sq;
-        }
-        const double *gt = geo + (size_t)t * kGeo, *gs = geo + (size_t)s * kGeo;
-        const R sc = (R)(gt[21] * gs[21] * kInv4Pi);
-        if (FORM == 1) {
-            // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
-            const R nn = ntx * nsx + nty * nsy + ntz * nsz;
-#pragma unroll
-            for (int l = 0; l < 3; ++l)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const R cc = (R)(gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
-                                     gt[24 + 3 * k] * gs[24 + 3 * l]);
-                    blk[l][k][2] = cc * Ssum + cf.k2 * nn * blk[l][k][2];
-                }
+            for (int o = 0; o < 4; ++o) blk[l][k][o] += Cq[k][o];
+    {
+        const R sc = ts[27] * ss[27] * (R)kInv4Pi;
+        const R sw = sc * (R)(RuleOrbit::cA * RuleOrbit::cA);
+        R f[4];
+        if (FORM == 0) {
+            f[0] = sw; f[1] = -sw; f[2] = -sw; f[3] = sw * cf.c1;
+        } else {
+            f[0] = f[1] = f[3] = sw;
+            f[2] = sw * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
         }
 #pragma unroll
         for (int l = 0; l < 3; ++l)
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3; ++k) {
+                Quad<R> qd;
 #pragma unroll
-                for (int o = 0; o < 4; ++o) blk[l][k][o] *= sc;
+                for (int o = 0; o < 4; ++o) qd.v[o] = blk[l][k][o] * f[o];
+                if (FORM == 1) {
+                    const double *gt = geo + (size_t)t * kGeo, *gs = geo + (size_t)sl * kGeo;
+                    // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
+                    const R cc = (R)(gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
+                                     gt[24 + 3 * k] * gs[24 + 3 * l]);
+                    qd.v[2] += sc * cc * Ssum;
+                }
+                // a pair sharing a vertex may have produced inf or NaN: select, not scale
+#pragma unroll
+                for (int o = 0; o < 4; ++o) qd.v[o] = live ? qd.v[o] : R(0);
+                lds[(3 * l + k) * TILE + tid] = qd;
+            }
     }
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int o = 0; o < 4; ++o) lds[(12 * l + 4 * k + o) * TILE + tid] = blk[l][k][o];
     __syncthreads();
-    const size_t rk[3] = {(size_t)vpos[v0], (size_t)vpos[v1], (size_t)vpos[v2]};
-    for (int e = tv_ptr[tile] + tid; e < tv_ptr[tile + 1]; e += TILE) {
-        const size_t c = (size_t)tv_col[e];
+    for (int e = eb + tid; e < ee; e += TILE) {
+        if (e != eb + tid) fetch(e);
         R acc[3][4];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -215,17 +262,19 @@ __global__ __launch_bounds__(TILE) void k_assemble_tile(
         for (int f = tv_eptr[e]; f < tv_eptr[e + 1]; ++f) {
             const int slot = te[f] >> 2, l = te[f] & 3;
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3; ++k) {
+                const Quad<R> qd = lds[(3 * l + k) * TILE + slot];
 #pragma unroll
-                for (int o = 0; o < 4; ++o) acc[k][o] += lds[(12 * l + 4 * k + o) * TILE + slot];
+                for (int o = 0; o < 4; ++o) acc[k][o] += qd.v[o];
+            }
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             S *r1 = A + rk[k] * ld, *r2 = A + ((size_t)V + rk[k]) * ld;
-            r1[c] += (S)acc[k][0];
-            r1[Vp + c] += (S)acc[k][1];
-            r2[c] += (S)acc[k][2];
-            r2[Vp + c] += (S)acc[k][3];
+            r1[c] = old[k][0] + (S)acc[k][0];
+            r1[Vp + c] = old[k][1] + (S)acc[k][1];
+            r2[c] = old[k][2] + (S)acc[k][2];
+            r2[Vp + c] = old[k][3] + (S)acc[k][3];
         }
     }
 }

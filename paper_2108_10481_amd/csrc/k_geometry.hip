@@ -52,7 +52,9 @@ __global__ void k_geometry(int T, const double *__restrict__ xyz, const int32_t 
         for (int c = 0; c < 3; ++c) g[22 + 3 * k + c] = -(P[b][c] - P[a][c]) / (2.0 * area);
     }
     g[31] = 0.0;
-    for (int i = 27; i < kStat; ++i) { s64[i] = 0.0; s32[i] = 0.0f; }
+    s64[27] = area;
+    s32[27] = (float)area;
+    for (int i = 28; i < kStat; ++i) { s64[i] = 0.0; s32[i] = 0.0f; }
 }
 
 void launch_geometry(DevMesh &d)
