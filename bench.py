@@ -37,12 +37,15 @@ METRIC = ("operator matvec kernel-pairs/s; solves/s + p99 latency at ΔG rel err
 # exp and rsqrt = 1 each), counted from the kernel formula
 FLOPS_PER_PAIR = {0: 28, 1: 38}
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X published vector peaks
-# far-field assembly, per far point pair evaluated once, counted from the
-# assembly formula: kernel values (direct 21.8 flops / 18.5 lane operations,
-# Juffer 30.5 / 24.5) plus the basis contraction in the two-orbit form of the
-# 6-point rule (17.3 flops / 12 lane operations per point pair)
-ASM_FLOPS_PER_PP = {0: 39.17, 1: 47.83}
-ASM_LANE_OPS_PER_PP = {0: 30.5, 1: 36.5}   # two of them transcendental (rsqrt, exp2)
+# far-field assembly, per ordered far point pair (the recorded work), counted
+# from the assembly formula: each unordered point pair is evaluated once and
+# yields six values (the four of the (t, s) block and the two non-symmetric
+# ones of (s, t)): kernel values direct 25.7 flops / 22 lane operations,
+# Juffer 32.5 / 26.5, plus the basis contraction in the two-orbit form of the
+# 6-point rule (4.33 flops / 3 lane operations per value); halved per ordered pair
+ASM_FLOPS_PER_PP = {0: 25.83, 1: 29.25}
+ASM_LANE_OPS_PER_PP = {0: 20.0, 1: 22.25}   # one of them transcendental (half of rsqrt + exp2)
+ASM_TRANS_PER_PP = 1.0
 # VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane operations per second
 # without packed FP32; a transcendental occupies four issue slots
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
@@ -151,7 +154,7 @@ def main():
         # formula's flops per point pair
         flops = sum(prof_asm[f][2] * ASM_FLOPS_PER_PP[f] for f in forms)
         achieved = flops / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0
-        slots = sum(prof_asm[f][2] * (ASM_LANE_OPS_PER_PP[f] + 2 * (TRANS_SLOTS - 1)) for f in forms)
+        slots = sum(prof_asm[f][2] * (ASM_LANE_OPS_PER_PP[f] + ASM_TRANS_PER_PP * (TRANS_SLOTS - 1)) for f in forms)
         issue = slots / (asm_ms * 1e-3) if asm_ms > 0 else 0.0
         nasm = sum(prof_asm[f][0] for f in forms)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",

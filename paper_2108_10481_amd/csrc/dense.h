@@ -25,6 +25,16 @@ struct Dense {
     // tiles of one colour touch disjoint vertices
     int tile = 256;
     int ntile = 0, ntcolor = 0;
+    // targets one assembly block processes in turn against its tile
+    int asm_group = 4;
+    // one evaluation per unordered triangle pair (FP32 storage): per launch
+    // (tile colour, target colour) the blocks {tile, first, end, 0} of targets
+    // t < (tile + 1) * tile size, and the side matrix C (2V x Vp) of the
+    // swapped pairs' non-symmetric values; C aliases A16 in mixed modes
+    bool sym = false;
+    std::vector<size_t> sym_ptr;
+    int4 *sym_blocks = nullptr;
+    float *C32 = nullptr;
     std::vector<int32_t> tcolor_ptr;
     int32_t *tcolor_tile = nullptr;
     int32_t *tv_ptr = nullptr, *tv_col = nullptr, *tv_eptr = nullptr, *te = nullptr;

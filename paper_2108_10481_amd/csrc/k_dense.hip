@@ -90,193 +90,332 @@ template <typename R> struct alignas(4 * sizeof(R)) Quad {
     R v[4];
 };
 
-// Block = (target triangle t of the current colour, tile of TILE Morton-ordered
-// source triangles of the current tile colour).
+// Block = (group of targets of the current colour, tile of TILE Morton-ordered
+// source triangles of the current tile colour).  The source data and the
+// tile's vertex lists are loaded once per block and reused for every target of
+// the group, which is processed one after the other:
 // Phase 1: lane s computes the whole local 3 x 3 block of the pair (t, s) for
-//   the four combined operator values -- every far point pair is evaluated
-//   exactly once -- into LDS (zero if s shares a vertex with t).  Per point
-//   pair (FORM 0, direct) F_L d.n_s, -G_L, -F_Y d.n_s, eps G_Y, or (FORM 1,
-//   Juffer) (F_L - alpha F_Y) d.n_s, G_Y - G_L, G_Y, (F_L - beta F_Y) d.n_t, with
-//   the hypersingular curl part added from sum (G_Y - G_L) per pair.  Signs
-//   and constant factors are applied once per block, not per point pair.
+//   the four combined operator values into LDS (zero if s shares a vertex with
+//   t).  Per point pair (FORM 0, direct) F_L d.n_s, -G_L, -F_Y d.n_s, eps G_Y,
+//   or (FORM 1, Juffer) (F_L - alpha F_Y) d.n_s, G_Y - G_L, G_Y,
+//   (F_L - beta F_Y) d.n_t, with the hypersingular curl part added from
+//   sum (G_Y - G_L) per pair.  Signs and constant factors are applied once per
+//   block, not per point pair.
 // Phase 2: lane v sums, for one vertex touched by the tile, the block columns
 //   of its incident tile triangles, and adds the 3 x 4 values to rows t_0..t_2.
-//   The 12 matrix entries of the lane's first vertex are read before phase 1,
-//   so the read-modify-write does not wait on HBM at the end.
+//   The lane's matrix entries are read before phase 1, so the read-modify-write
+//   does not wait on memory at the end.
+// SYM (one evaluation per unordered pair): only pairs with s > t are
+// evaluated.  The symmetric values (V-type, and D in the Juffer system) are
+// added in the (t, s) orientation only; the two non-symmetric ones (K-type,
+// and K or T in the second block row) of the swapped pair (s, t) are computed
+// from the same point-pair kernels and added, in the same (t, s) layout, to
+// the side matrix C.  k_sym_finish then adds the transposes.
 // Target colours keep rows disjoint and tile colours keep columns disjoint
 // between concurrently running blocks, so there is no atomic and the result
 // is deterministic.
-template <typename R, typename S, int FORM, int TILE>
-__global__ __launch_bounds__(TILE) void k_assemble_tile(
-    int T, int V, AsmCoef<R> cf, const int32_t *__restrict__ targets, const int32_t *__restrict__ tiles,
-    const int32_t *__restrict__ tri, const R *__restrict__ stat, const double *__restrict__ geo,
-    const int32_t *__restrict__ vpos, const int32_t *__restrict__ tv_ptr, const int32_t *__restrict__ tv_col,
-    const int32_t *__restrict__ tv_eptr, const int32_t *__restrict__ te, S *__restrict__ A, size_t ld, size_t Vp)
+template <typename R, typename S, int FORM, int TILE, bool SYM>
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 1))) void k_assemble_tile(
+    int T, int V, AsmCoef<R> cf, const int32_t *__restrict__ targets, int ntarget, int group,
+    const int32_t *__restrict__ tiles, const int4 *__restrict__ sym_blocks, const int32_t *__restrict__ tri,
+    const R *__restrict__ stat, const double *__restrict__ geo, const int32_t *__restrict__ vpos,
+    const int32_t *__restrict__ tv_ptr, const int32_t *__restrict__ tv_col, const int32_t *__restrict__ tv_eptr,
+    const int32_t *__restrict__ te, S *__restrict__ A, size_t ld, size_t Vp, S *__restrict__ C, size_t ldc)
 {
+    constexpr int NV = SYM ? 6 : 4;
     __shared__ Quad<R> lds[9 * TILE];
-    const int t = targets[blockIdx.y];
-    const int tile = tiles[blockIdx.x];
+    __shared__ R lds2[SYM ? 18 * TILE : 1];
+    int tile, gbeg, gend;
+    if (SYM) {
+        const int4 bk = sym_blocks[blockIdx.x];
+        tile = bk.x; gbeg = bk.y; gend = bk.z;
+    } else {
+        tile = tiles[blockIdx.x];
+        gbeg = blockIdx.y * group;
+        gend = min(gbeg + group, ntarget);
+    }
     const int tid = threadIdx.x;
     const int s = tile * TILE + tid;
     // lanes past the last triangle evaluate the last one and are zeroed below
     const int sl = s < T ? s : T - 1;
-    const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
     const int j0 = tri[3 * sl], j1 = tri[3 * sl + 1], j2 = tri[3 * sl + 2];
-    const bool live = (s < T) & !((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
-                                 (j2 == v0) | (j2 == v1) | (j2 == v2));
-    const R *ts = stat + (size_t)t * kStat;   // uniform: scalar loads
     const R *ss = stat + (size_t)sl * kStat;
-    const R nsx = ss[18], nsy = ss[19], nsz = ss[20];
+    const R nsx = ss[18], nsy = ss[19], nsz = ss[20], sarea = ss[27];
     R sy[6][3], yns[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         sy[q][0] = ss[3 * q]; sy[q][1] = ss[3 * q + 1]; sy[q][2] = ss[3 * q + 2];
         yns[q] = ss[21 + q];
     }
-
+    // the lane's vertex column of the tile (a lane without one re-reads the
+    // tile's first and never stores it) and its first kPre incidences
+    // (tile slot << 2 | local vertex)
     const int eb = tv_ptr[tile], ee = tv_ptr[tile + 1];
-    const size_t rk[3] = {(size_t)vpos[v0], (size_t)vpos[v1], (size_t)vpos[v2]};
-    size_t c = 0;
-    S old[3][4];
-    auto fetch = [&](int e) {
-        c = (size_t)tv_col[e];
+    const int e0 = eb + tid < ee ? eb + tid : eb;
+    const size_t c0 = (size_t)tv_col[e0];
+    const int fb0 = tv_eptr[e0], fe0 = tv_eptr[e0 + 1];
+    // codes are below 4 TILE, so two share a register
+    constexpr int kPre = 8;
+    uint32_t ter[kPre / 2];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const S *r1 = A + rk[k] * ld, *r2 = A + ((size_t)V + rk[k]) * ld;
-            old[k][0] = r1[c];
-            old[k][1] = r1[Vp + c];
-            old[k][2] = r2[c];
-            old[k][3] = r2[Vp + c];
-        }
-    };
-    // unconditional (a lane without a vertex re-reads the tile's first one and
-    // never stores it), so the loads stay in flight through phase 1
-    fetch(eb + tid < ee ? eb + tid : eb);
+    for (int i = 0; i < kPre; i += 2)
+        ter[i / 2] = (uint32_t)te[min(fb0 + i, fe0 - 1)] | ((uint32_t)te[min(fb0 + i + 1, fe0 - 1)] << 16);
 
-    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
-    const R rho = (R)RuleOrbit::rho, al = (R)RuleOrbit::al, be = (R)RuleOrbit::be;
-    R blk[3][3][4], Cq[3][4];   // [l][k][o]; Cq: rank-two part of the target-side weights
-    R Ssum = 0;
+    for (int g = gbeg; g < gend; ++g) {
+        const int t = targets[g];
+        const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
+        const bool live = (s < T) & (!SYM | (s > t)) &
+                          !((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
+                            (j2 == v0) | (j2 == v1) | (j2 == v2));
+        const R *ts = stat + (size_t)t * kStat;   // uniform: scalar loads
+        const size_t rk[3] = {(size_t)vpos[v0], (size_t)vpos[v1], (size_t)vpos[v2]};
+        S old[3][NV];
+        auto load_old = [&](size_t c) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const R ynt = FORM == 1 ? sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz : R(0);
-        R X[3][4], SA[4], SB[4];
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const R tx = ts[3 * p], ty = ts[3 * p + 1], tz = ts[3 * p + 2];
-            const R dx = tx - sy[q][0], dy = ty - sy[q][1], dz = tz - sy[q][2];
-            const R r2 = dx * dx + dy * dy + dz * dz;
-            const R ri = rsq_a(r2);
-            const R r = r2 * ri;
-            const R ek = expn_a(cf.kexp, r);
-            const R ri3 = ri * ri * ri;
-            const R dns = (tx * nsx + ty * nsy + tz * nsz) - yns[q];
-            const R ekk = ek * (cf.kappa * r + R(1));
-            R v[4];
-            if (FORM == 0) {
-                // F_L d.n_s, G_L, F_Y d.n_s, G_Y without the factors 1, -1, -1, eps
-                v[0] = ri3 * dns;
-                v[1] = ri;
-                v[2] = ekk * v[0];
-                v[3] = ek * ri;
-            } else {
-                const R fy = ekk * ri3;
-                const R gy = ek * ri;
-                v[0] = (ri3 - cf.c1 * fy) * dns;
-                v[1] = gy - ri;
-                v[2] = gy;
-                v[3] = (ri3 - cf.c2 * fy) * (ts[21 + p] - ynt);
-            }
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                if (p < 3) {
-                    X[p][o] = v[o];
-                    SA[o] = p == 0 ? v[o] : SA[o] + v[o];
-                } else {
-                    X[p - 3][o] += rho * v[o];
-                    SB[o] = p == 3 ? v[o] : SB[o] + v[o];
+            for (int k = 0; k < 3; ++k) {
+                const S *r1 = A + rk[k] * ld, *r2 = A + ((size_t)V + rk[k]) * ld;
+                old[k][0] = r1[c];
+                old[k][1] = r1[Vp + c];
+                old[k][2] = r2[c];
+                old[k][3] = r2[Vp + c];
+                if (SYM) {
+                    old[k][4] = C[rk[k] * ldc + c];
+                    old[k][5] = C[((size_t)V + rk[k]) * ldc + c];
                 }
             }
-        }
+        };
+        load_old(c0);
+
+        const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+        const R rho = (R)RuleOrbit::rho, al = (R)RuleOrbit::al, be = (R)RuleOrbit::be;
+        R blk[3][3][NV], Cq[3][NV];   // [l][k][o]; Cq: rank-two part of the target-side weights
+        R Ssum = 0;
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            const R cc = al * SA[o] + be * SB[o];
+        for (int q = 0; q < 6; ++q) {
+            const R ynt = (FORM == 1 || SYM) ? sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz : R(0);
+            R X[3][NV], SA[NV], SB[NV];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) X[k][o] += cc;
-        }
-        if (FORM == 1) Ssum += R(rule_w(q)) * (R(kRuleWA) * SA[1] + R(kRuleWB) * SB[1]);
-        const R wc = q < 3 ? al : be;
+            for (int p = 0; p < 6; ++p) {
+                const R tx = ts[3 * p], ty = ts[3 * p + 1], tz = ts[3 * p + 2];
+                const R dx = tx - sy[q][0], dy = ty - sy[q][1], dz = tz - sy[q][2];
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = rsq_a(r2);
+                const R r = r2 * ri;
+                const R ek = expn_a(cf.kexp, r);
+                const R ri3 = ri * ri * ri;
+                const R dns = (tx * nsx + ty * nsy + tz * nsz) - yns[q];
+                const R ekk = ek * (cf.kappa * r + R(1));
+                R v[NV];
+                if (FORM == 0) {
+                    // F_L d.n_s, G_L, F_Y d.n_s, G_Y without the factors 1, -1, -1, eps;
+                    // swapped pair: F_L d.n_t, F_Y d.n_t
+                    v[0] = ri3 * dns;
+                    v[1] = ri;
+                    v[2] = ekk * v[0];
+                    v[3] = ek * ri;
+                    if (SYM) {
+                        v[4] = ri3 * (ts[21 + p] - ynt);
+                        v[5] = ekk * v[4];
+                    }
+                } else {
+                    const R fy = ekk * ri3;
+                    const R gy = ek * ri;
+                    const R a1 = ri3 - cf.c1 * fy, a2 = ri3 - cf.c2 * fy;
+                    const R dnt = ts[21 + p] - ynt;
+                    v[0] = a1 * dns;
+                    v[1] = gy - ri;
+                    v[2] = gy;
+                    v[3] = a2 * dnt;
+                    if (SYM) {
+                        v[4] = a1 * dnt;
+                        v[5] = a2 * dns;
+                    }
+                }
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-                if (q < 3) blk[q][k][o] = X[k][o];
-                else blk[q - 3][k][o] += rho * X[k][o];
-                Cq[k][o] = q == 0 ? wc * X[k][o] : Cq[k][o] + wc * X[k][o];
+                for (int o = 0; o < NV; ++o) {
+                    if (p < 3) {
+                        X[p][o] = v[o];
+                        SA[o] = p == 0 ? v[o] : SA[o] + v[o];
+                    } else {
+                        X[p - 3][o] += rho * v[o];
+                        SB[o] = p == 3 ? v[o] : SB[o] + v[o];
+                    }
+                }
             }
-    }
 #pragma unroll
-    for (int l = 0; l < 3; ++l)
+            for (int o = 0; o < NV; ++o) {
+                const R cc = al * SA[o] + be * SB[o];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+                for (int k = 0; k < 3; ++k) X[k][o] += cc;
+            }
+            if (FORM == 1) Ssum += R(rule_w(q)) * (R(kRuleWA) * SA[1] + R(kRuleWB) * SB[1]);
+            const R wc = q < 3 ? al : be;
 #pragma unroll
-            for (int o = 0; o < 4; ++o) blk[l][k][o] += Cq[k][o];
-    {
-        const R sc = ts[27] * ss[27] * (R)kInv4Pi;
-        const R sw = sc * (R)(RuleOrbit::cA * RuleOrbit::cA);
-        R f[4];
-        if (FORM == 0) {
-            f[0] = sw; f[1] = -sw; f[2] = -sw; f[3] = sw * cf.c1;
-        } else {
-            f[0] = f[1] = f[3] = sw;
-            f[2] = sw * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int o = 0; o < NV; ++o) {
+                    if (q < 3) blk[q][k][o] = X[k][o];
+                    else blk[q - 3][k][o] += rho * X[k][o];
+                    Cq[k][o] = q == 0 ? wc * X[k][o] : Cq[k][o] + wc * X[k][o];
+                }
         }
 #pragma unroll
         for (int l = 0; l < 3; ++l)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                Quad<R> qd;
+            for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int o = 0; o < 4; ++o) qd.v[o] = blk[l][k][o] * f[o];
+                for (int o = 0; o < NV; ++o) blk[l][k][o] += Cq[k][o];
+
+        const R sc = ts[27] * sarea * (R)kInv4Pi;
+        const R sw = sc * (R)(RuleOrbit::cA * RuleOrbit::cA);
+        R f[NV];
+        if (FORM == 0) {
+            f[0] = sw; f[1] = -sw; f[2] = -sw; f[3] = sw * cf.c1;
+            if (SYM) { f[4] = -sw; f[5] = sw; }
+        } else {
+            f[0] = f[1] = f[3] = sw;
+            f[2] = sw * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
+            if (SYM) { f[4] = -sw; f[5] = -sw; }
+        }
+        if (g > gbeg) __syncthreads();   // the previous target's phase 2 is done with lds
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                R val[NV];
+#pragma unroll
+                for (int o = 0; o < NV; ++o) val[o] = blk[l][k][o] * f[o];
                 if (FORM == 1) {
                     const double *gt = geo + (size_t)t * kGeo, *gs = geo + (size_t)sl * kGeo;
                     // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
                     const R cc = (R)(gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
                                      gt[24 + 3 * k] * gs[24 + 3 * l]);
-                    qd.v[2] += sc * cc * Ssum;
+                    val[2] += sc * cc * Ssum;
                 }
                 // a pair sharing a vertex may have produced inf or NaN: select, not scale
+                Quad<R> qd;
 #pragma unroll
-                for (int o = 0; o < 4; ++o) qd.v[o] = live ? qd.v[o] : R(0);
+                for (int o = 0; o < 4; ++o) qd.v[o] = live ? val[o] : R(0);
                 lds[(3 * l + k) * TILE + tid] = qd;
+                if (SYM) {
+                    lds2[(2 * (3 * l + k)) * TILE + tid] = live ? val[4] : R(0);
+                    lds2[(2 * (3 * l + k) + 1) * TILE + tid] = live ? val[5] : R(0);
+                }
             }
-    }
-    __syncthreads();
-    for (int e = eb + tid; e < ee; e += TILE) {
-        if (e != eb + tid) fetch(e);
-        R acc[3][4];
+        __syncthreads();
+
+        for (int e = eb + tid; e < ee; e += TILE) {
+            size_t c = c0;
+            int fb = fb0, fe = fe0;
+            if (e != eb + tid) {   // a tile with more vertices than lanes
+                c = (size_t)tv_col[e];
+                fb = tv_eptr[e];
+                fe = tv_eptr[e + 1];
+                load_old(c);
+            }
+            R acc[3][NV];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+            for (int k = 0; k < 3; ++k)
 #pragma unroll
-            for (int o = 0; o < 4; ++o) acc[k][o] = 0;
-        for (int f = tv_eptr[e]; f < tv_eptr[e + 1]; ++f) {
-            const int slot = te[f] >> 2, l = te[f] & 3;
+                for (int o = 0; o < NV; ++o) acc[k][o] = 0;
+            auto add = [&](int code) {
+                const int slot = code >> 2, l = code & 3;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const Quad<R> qd = lds[(3 * l + k) * TILE + slot];
+#pragma unroll
+                    for (int o = 0; o < 4; ++o) acc[k][o] += qd.v[o];
+                    if (SYM) {
+                        acc[k][4] += lds2[(2 * (3 * l + k)) * TILE + slot];
+                        acc[k][5] += lds2[(2 * (3 * l + k) + 1) * TILE + slot];
+                    }
+                }
+            };
+            if (e == eb + tid) {
+#pragma unroll
+                for (int i = 0; i < kPre; ++i)
+                    if (fb + i < fe) add((int)((ter[i / 2] >> (16 * (i & 1))) & 0xffffu));
+                for (int f = fb + kPre; f < fe; ++f) add(te[f]);
+            } else {
+                for (int f = fb; f < fe; ++f) add(te[f]);
+            }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const Quad<R> qd = lds[(3 * l + k) * TILE + slot];
-#pragma unroll
-                for (int o = 0; o < 4; ++o) acc[k][o] += qd.v[o];
+                S *r1 = A + rk[k] * ld, *r2 = A + ((size_t)V + rk[k]) * ld;
+                r1[c] = old[k][0] + (S)acc[k][0];
+                r1[Vp + c] = old[k][1] + (S)acc[k][1];
+                r2[c] = old[k][2] + (S)acc[k][2];
+                r2[Vp + c] = old[k][3] + (S)acc[k][3];
+                if (SYM) {
+                    C[rk[k] * ldc + c] = old[k][4] + (S)acc[k][4];
+                    C[((size_t)V + rk[k]) * ldc + c] = old[k][5] + (S)acc[k][5];
+                }
             }
         }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            S *r1 = A + rk[k] * ld, *r2 = A + ((size_t)V + rk[k]) * ld;
-            r1[c] = old[k][0] + (S)acc[k][0];
-            r1[Vp + c] = old[k][1] + (S)acc[k][1];
-            r2[c] = old[k][2] + (S)acc[k][2];
-            r2[Vp + c] = old[k][3] + (S)acc[k][3];
-        }
     }
+}
+
+// Completion of the one-evaluation-per-pair assembly on one V x V block of A
+// (rows r0.., columns c0..), in 64 x 64 tiles through LDS with 16-byte global
+// accesses (A's row stride and both column offsets are multiples of 64):
+//   MODE 0 (symmetric operator): A <- A + A^T;
+//   MODE 1: A <- A + C_b^T, C_b = rows cr0.. of the side matrix C.
+// Rows at or beyond V are neither read nor written; columns beyond V (zero
+// padding) are read but never written.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_sym_finish(int V, float *__restrict__ A, size_t ld, size_t r0, size_t c0,
+                                                    const float *__restrict__ C, size_t ldc, size_t cr0)
+{
+    __shared__ float ta[64][65], tb[64][65];
+    const int I = blockIdx.y, J = blockIdx.x;   // tile row, tile column of the block
+    if (MODE == 0 && I > J) return;
+    const int cx = (threadIdx.x & 15) * 4, ry = threadIdx.x >> 4;
+    auto arow = [&](int i) { return A + (r0 + (size_t)i) * ld + c0; };
+    auto put = [&](float (*t)[65], int r, float4 v) {
+        t[r][cx] = v.x; t[r][cx + 1] = v.y; t[r][cx + 2] = v.z; t[r][cx + 3] = v.w;
+    };
+    // tb <- the mirrored tile (rows of J, columns of I) of A or of C; ta <- tile (I, J)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = ry + 16 * i, gi = J * 64 + r, gj = I * 64 + cx;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gi < V) v = MODE == 0 ? *(const float4 *)(arow(gi) + gj) : *(const float4 *)(C + (cr0 + gi) * ldc + gj);
+        put(tb, r, v);
+    }
+    float4 base[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int gi = I * 64 + ry + 16 * i, gj = J * 64 + cx;
+        base[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gi < V && !(MODE == 0 && I == J)) base[i] = *(const float4 *)(arow(gi) + gj);
+        if (MODE == 0 && I != J) put(ta, ry + 16 * i, base[i]);
+    }
+    __syncthreads();
+    auto store = [&](int gi, int gj, float4 v) {
+        if (gi >= V) return;
+        float *p = arow(gi) + gj;
+        if (gj + 3 < V) {
+            *(float4 *)p = v;
+        } else {
+            const float e[4] = {v.x, v.y, v.z, v.w};
+            for (int k = 0; k < 4 && gj + k < V; ++k) p[k] = e[k];
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = ry + 16 * i;
+        float4 v = MODE == 0 && I == J ? make_float4(tb[r][cx], tb[r][cx + 1], tb[r][cx + 2], tb[r][cx + 3]) : base[i];
+        v.x += tb[cx][r]; v.y += tb[cx + 1][r]; v.z += tb[cx + 2][r]; v.w += tb[cx + 3][r];
+        store(I * 64 + r, J * 64 + cx, v);
+    }
+    if (MODE == 0 && I != J)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = ry + 16 * i;
+            float4 v = make_float4(tb[r][cx], tb[r][cx + 1], tb[r][cx + 2], tb[r][cx + 3]);
+            v.x += ta[cx][r]; v.y += ta[cx + 1][r]; v.z += ta[cx + 2][r]; v.w += ta[cx + 3][r];
+            store(J * 64 + r, I * 64 + cx, v);
+        }
 }
 
 template <typename S>
@@ -511,7 +650,8 @@ static size_t dense_bytes(const DevMesh &d)
 {
     const size_t n = 2 * (size_t)d.hm.V, ld = dense_ld(d.hm.V);
     size_t per = d.prm.precision == PB_FP64 ? 8 : 4;
-    if (d.prm.precision >= PB_MIXED_BF16) per += 2;
+    // 16-bit copy; in FP32 mode the side matrix C of the same size
+    if (d.prm.precision != PB_FP64) per += 2;
     return n * ld * per;
 }
 
@@ -528,7 +668,7 @@ bool dense_fits(const DevMesh &d)
 // numbering by first touch in tile order; per tile the touched vertices (in
 // dense order) with their (slot, local vertex) incidences; tile colouring so
 // that tiles of one colour share no vertex.
-static void build_tiles(const HostMesh &hm, DevMesh &d, Dense &D)
+static void build_tiles(const HostMesh &hm, DevMesh &d, Dense &D, const std::vector<int32_t> &tcol_list)
 {
     const int T = hm.T, V = hm.V, TL = D.tile;
     D.ntile = (T + TL - 1) / TL;
@@ -583,6 +723,28 @@ static void build_tiles(const HostMesh &hm, DevMesh &d, Dense &D)
         return p;
     };
     D.tcolor_tile = up(lst);
+    if (D.sym) {
+        // colour lists ascend in t, so the targets with t < (k + 1) * TL are a prefix
+        std::vector<int4> blocks;
+        D.sym_ptr.assign(1, 0);
+        for (int kc = 0; kc < D.ntcolor; ++kc)
+            for (int c = 0; c < D.ncolor; ++c) {
+                const int32_t *cl = tcol_list.data() + D.color_ptr[c];
+                const int n = D.color_ptr[c + 1] - D.color_ptr[c];
+                for (int i = D.tcolor_ptr[kc]; i < D.tcolor_ptr[kc + 1]; ++i) {
+                    const int k = lst[i];
+                    const int nk = (int)(std::lower_bound(cl, cl + n, (k + 1) * TL) - cl);
+                    for (int g = 0; g < nk; g += D.asm_group)
+                        blocks.push_back(make_int4(k, D.color_ptr[c] + g, D.color_ptr[c] + std::min(g + D.asm_group, nk), 0));
+                }
+                D.sym_ptr.push_back(blocks.size());
+            }
+        D.sym_blocks = (int4 *)d.alloc(sizeof(int4) * std::max<size_t>(blocks.size(), 1));
+        if (!blocks.empty())
+            HIPCHECK(hipMemcpyAsync(D.sym_blocks, blocks.data(), sizeof(int4) * blocks.size(), hipMemcpyHostToDevice,
+                                    d.stream));
+        HIPCHECK(hipStreamSynchronize(d.stream));
+    }
     D.tv_ptr = up(tv_ptr);
     D.tv_col = up(tv_col);
     D.tv_eptr = up(tv_eptr);
@@ -608,21 +770,59 @@ static void assemble(DevMesh &d, S *A)
     const R *stat = sizeof(R) == 4 ? (const R *)d.stat32 : (const R *)d.stat64;
     const size_t total = (size_t)D.n * D.ld;
     hipLaunchKernelGGL(k_fill<S>, dim3(4096), dim3(256), 0, d.stream, total, A);
-    for (int c = 0; c < D.ncolor; ++c) {
-        const int nt = D.color_ptr[c + 1] - D.color_ptr[c];
-        if (nt == 0) continue;
-        const int32_t *tg = D.color_tri + D.color_ptr[c];
+    if constexpr (sizeof(R) == 4) {
+        // one evaluation per unordered pair, then the transposes
+        hipLaunchKernelGGL(k_fill<float>, dim3(4096), dim3(256), 0, d.stream, (size_t)D.n * D.Vp, D.C32);
+        int li = 0;
+        for (int kc = 0; kc < D.ntcolor; ++kc)
+            for (int c = 0; c < D.ncolor; ++c, ++li) {
+                const size_t b0 = D.sym_ptr[li], nb = D.sym_ptr[li + 1] - b0;
+                if (nb == 0) continue;
+                if (direct)
+                    hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE, true>), dim3(nb), dim3(TILE), 0, d.stream, T,
+                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat, d.geo,
+                                       D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp);
+                else
+                    hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE, true>), dim3(nb), dim3(TILE), 0, d.stream, T,
+                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat, d.geo,
+                                       D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp);
+            }
+        // V x V blocks of A (row block, column block): symmetric operators take
+        // their own transpose, the others the transpose of C's rows.  Direct:
+        // K_L, -V_L / -K_Y, eps V_Y.  Juffer: K, V / D, T.
+        const int nt = (V + 63) / 64;
+        const dim3 fg(nt, nt), fb(256);
+        const size_t z = 0, Vs = (size_t)V;
+        hipLaunchKernelGGL(k_sym_finish<1>, fg, fb, 0, d.stream, V, A, D.ld, z, z, D.C32, D.Vp, z);
+        hipLaunchKernelGGL(k_sym_finish<0>, fg, fb, 0, d.stream, V, A, D.ld, z, D.Vp, D.C32, D.Vp, z);
+        if (direct) {
+            hipLaunchKernelGGL(k_sym_finish<1>, fg, fb, 0, d.stream, V, A, D.ld, Vs, z, D.C32, D.Vp, Vs);
+            hipLaunchKernelGGL(k_sym_finish<0>, fg, fb, 0, d.stream, V, A, D.ld, Vs, D.Vp, D.C32, D.Vp, z);
+        } else {
+            hipLaunchKernelGGL(k_sym_finish<0>, fg, fb, 0, d.stream, V, A, D.ld, Vs, z, D.C32, D.Vp, z);
+            hipLaunchKernelGGL(k_sym_finish<1>, fg, fb, 0, d.stream, V, A, D.ld, Vs, D.Vp, D.C32, D.Vp, Vs);
+        }
+    } else {
+        // every ordered pair once, target colour x tile colour launches
         for (int kc = 0; kc < D.ntcolor; ++kc) {
             const int nk = D.tcolor_ptr[kc + 1] - D.tcolor_ptr[kc];
             if (nk == 0) continue;
             const int32_t *tl = D.tcolor_tile + D.tcolor_ptr[kc];
-            dim3 grid(nk, nt), block(TILE);
-            if (direct)
-                hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE>), grid, block, 0, d.stream, T, V, cf, tg, tl, d.tri,
-                                   stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp);
-            else
-                hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE>), grid, block, 0, d.stream, T, V, cf, tg, tl, d.tri,
-                                   stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp);
+            for (int c = 0; c < D.ncolor; ++c) {
+                const int nt = D.color_ptr[c + 1] - D.color_ptr[c];
+                if (nt == 0) continue;
+                const int32_t *tg = D.color_tri + D.color_ptr[c];
+                const int grp = D.asm_group;
+                dim3 grid(nk, (nt + grp - 1) / grp), block(TILE);
+                if (direct)
+                    hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE, false>), grid, block, 0, d.stream, T, V, cf, tg,
+                                       nt, grp, tl, nullptr, d.tri, stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
+                                       D.te, A, D.ld, D.Vp, nullptr, (size_t)0);
+                else
+                    hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE, false>), grid, block, 0, d.stream, T, V, cf, tg,
+                                       nt, grp, tl, nullptr, d.tri, stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
+                                       D.te, A, D.ld, D.Vp, nullptr, (size_t)0);
+            }
         }
     }
     HIPCHECK(hipGetLastError());
@@ -655,7 +855,13 @@ void build_dense(DevMesh &d)
         D->x32 = (float *)d.alloc(sizeof(float) * D->ld);
         D->x64 = (double *)d.alloc(sizeof(double) * D->ld);
         D->tile = d.prm.precision == PB_FP64 ? 128 : 256;
-        build_tiles(d.hm, d, *D);
+        D->sym = d.prm.precision != PB_FP64;
+        if (D->sym) {
+            // n x Vp floats: the same bytes as the n x ld 16-bit copy, which is
+            // written only after the assembly
+            D->C32 = D->A16 ? (float *)D->A16 : (float *)d.alloc(sizeof(float) * (size_t)D->n * D->Vp);
+        }
+        build_tiles(d.hm, d, *D, lst);
         d.dense_vpos = D->vpos;
     }
     Dense &D = *d.dense;

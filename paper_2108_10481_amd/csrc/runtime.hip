@@ -171,7 +171,9 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     const double m = std::min<double>(mixed ? std::min(o->inner_max_iter, o->max_iter) : o->max_iter, n) + 2;
     b += m * n * 8;
     const double Vp = std::ceil(v / 64.0) * 64.0;
-    const double dense = n * 2.0 * Vp * (o->precision == PB_FP64 ? 8.0 : 4.0) + (mixed ? n * 2.0 * Vp * 2.0 : 0.0);
+    // FP64 matrix, or FP32 matrix plus the 16-bit copy (mixed) or the assembly's
+    // side matrix (FP32) of the same size
+    const double dense = n * 2.0 * Vp * (o->precision == PB_FP64 ? 8.0 : 6.0);
     if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense;
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
     return (size_t)(b * 1.1);
