@@ -89,24 +89,41 @@ __device__ inline int ss_order(int t, int s, const int *tv, const int *sv, int *
     return ns;
 }
 
-// One wavefront per ordered pair (t, s).  Lanes stride over the regions x N^4
-// Gauss points; each lane accumulates the 4 x 3 x 3 products in FP64, then a
-// butterfly reduction over the wavefront.  out[36 p + 9 op + 3 a + b], op =
-// V_L, K_L, V_Y, K_Y; a, b local vertex ids of t and s in stored order.
-template <int N>
-__global__ __launch_bounds__(256) void k_near_ss(int npair, const int32_t *__restrict__ pair_t,
-                                                 const int32_t *__restrict__ pair_s, const int32_t *__restrict__ tri,
-                                                 const double *__restrict__ xyz, const double *__restrict__ geo,
-                                                 double kappa, double *__restrict__ out)
+// 1/sqrt(x) in FP64: hardware estimate and two Newton steps
+__device__ inline double rsq64(double x)
 {
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (wave >= npair) return;
-    const int t = pair_t[wave], s = pair_s[wave];
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    h = x * y;
+    y = fma(0.5 * y, fma(-h, y, 1.0), y);
+    return y;
+}
+
+// LANES lanes per ordered pair (t, s), 64 / LANES pairs per wavefront, all of
+// one case (CASE shared vertices, so the region of a Gauss point is uniform
+// across the wavefront).  Lanes stride over the regions x N^4 Gauss points;
+// each lane accumulates the 4 x 3 x 3 products in FP64, then a butterfly
+// reduction inside the lane group.  out[36 p + 9 op + 3 a + b], op = V_L, K_L,
+// V_Y, K_Y; a, b local vertex ids of t and s in stored order; p = idx[item].
+template <int N, int CASE, int LANES>
+__global__ __launch_bounds__(256) void k_near_ss(int count, const int32_t *__restrict__ idx,
+                                                 const int32_t *__restrict__ pair_t, const int32_t *__restrict__ pair_s,
+                                                 const int32_t *__restrict__ tri, const double *__restrict__ xyz,
+                                                 const double *__restrict__ geo, double kappa, double *__restrict__ out)
+{
+    constexpr int G = 64 / LANES;
+    const int lane = threadIdx.x & 63, sub = lane % LANES;
+    const int first = (blockIdx.x * 4 + (threadIdx.x >> 6)) * G;
+    if (first >= count) return;   // whole wavefront idle
+    const int item = first + lane / LANES;
+    const bool active = item < count;   // idle groups repeat the last pair and do not store
+    const int p = idx[active ? item : count - 1];
+    const int t = pair_t[p], s = pair_s[p];
     int tv[3], sv[3];
     for (int k = 0; k < 3; ++k) { tv[k] = tri[3 * t + k]; sv[k] = tri[3 * s + k]; }
     int pt[3], ps[3];
-    const int cas = ss_order(t, s, tv, sv, pt, ps);
+    (void)ss_order(t, s, tv, sv, pt, ps);
     double P[3][3], Q[3][3];
     for (int m = 0; m < 3; ++m)
         for (int c = 0; c < 3; ++c) {
@@ -122,30 +139,30 @@ __global__ __launch_bounds__(256) void k_near_ss(int npair, const int32_t *__res
         f1[c] = Q[1][c] - Q[0][c]; f2[c] = Q[2][c] - Q[1][c];
     }
     constexpr int N4 = N * N * N * N;
-    const int nreg = cas == 3 ? 6 : cas == 2 ? 5 : 2;
-    const int npts = nreg * N4;
+    constexpr int nreg = CASE == 3 ? 6 : CASE == 2 ? 5 : 2;
+    constexpr int npts = nreg * N4;
     double acc[36];
 #pragma unroll
     for (int v = 0; v < 36; ++v) acc[v] = 0.0;
-    for (int idx = lane; idx < npts; idx += 64) {
-        const int r = idx / N4;
-        int rem = idx - r * N4;
+    for (int ix = sub; ix < npts; ix += LANES) {
+        const int r = ix / N4;
+        int rem = ix - r * N4;
         const int i0 = rem / (N * N * N); rem -= i0 * N * N * N;
         const int i1 = rem / (N * N); rem -= i1 * N * N;
         const int i2 = rem / N;
         const int i3 = rem - i2 * N;
-        const SSPoint m = ss_map(cas, r, c_gl_x[N][i0], c_gl_x[N][i1], c_gl_x[N][i2], c_gl_x[N][i3]);
+        const SSPoint m = ss_map(CASE, r, c_gl_x[N][i0], c_gl_x[N][i1], c_gl_x[N][i2], c_gl_x[N][i3]);
         const double W = c_gl_w[N][i0] * c_gl_w[N][i1] * c_gl_w[N][i2] * c_gl_w[N][i3] * m.jac;
-        double dx = (P[0][0] + m.u1 * e1[0] + m.u2 * e2[0]) - (Q[0][0] + m.v1 * f1[0] + m.v2 * f2[0]);
-        double dy = (P[0][1] + m.u1 * e1[1] + m.u2 * e2[1]) - (Q[0][1] + m.v1 * f1[1] + m.v2 * f2[1]);
-        double dz = (P[0][2] + m.u1 * e1[2] + m.u2 * e2[2]) - (Q[0][2] + m.v1 * f1[2] + m.v2 * f2[2]);
-        double r2 = dx * dx + dy * dy + dz * dz;
-        double rr = sqrt(r2);
-        double ri = 1.0 / rr;
-        double ek = exp(-kappa * rr);
-        double dn = dx * nsx + dy * nsy + dz * nsz;
-        double ri3 = ri * ri * ri;
-        double gL = ri, fL = dn * ri3, gY = ek * ri, fY = ek * (1.0 + kappa * rr) * dn * ri3;
+        const double dx = (P[0][0] + m.u1 * e1[0] + m.u2 * e2[0]) - (Q[0][0] + m.v1 * f1[0] + m.v2 * f2[0]);
+        const double dy = (P[0][1] + m.u1 * e1[1] + m.u2 * e2[1]) - (Q[0][1] + m.v1 * f1[1] + m.v2 * f2[1]);
+        const double dz = (P[0][2] + m.u1 * e1[2] + m.u2 * e2[2]) - (Q[0][2] + m.v1 * f1[2] + m.v2 * f2[2]);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ri = rsq64(r2);
+        const double rr = r2 * ri;
+        const double ek = exp(-kappa * rr);
+        const double dn = dx * nsx + dy * nsy + dz * nsz;
+        const double ri3 = ri * ri * ri;
+        const double gL = ri, fL = dn * ri3, gY = ek * ri, fY = ek * (1.0 + kappa * rr) * dn * ri3;
         const double lx[3] = {1.0 - m.u1, m.u1 - m.u2, m.u2};
         const double ly[3] = {1.0 - m.v1, m.v1 - m.v2, m.v2};
 #pragma unroll
@@ -164,12 +181,13 @@ __global__ __launch_bounds__(256) void k_near_ss(int npair, const int32_t *__res
 #pragma unroll
     for (int v = 0; v < 36; ++v) {
         double x = acc[v];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+#pragma unroll
+        for (int off = LANES / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
         acc[v] = x;
     }
-    if (lane == 0) {
+    if (active && sub == 0) {
         const double scale = at * as / kPi;   // (2|t|)(2|s|) / (4 pi)
-        double *o = out + (size_t)wave * 36;
+        double *o = out + (size_t)p * 36;
 #pragma unroll
         for (int op = 0; op < 4; ++op)
 #pragma unroll
@@ -179,15 +197,52 @@ __global__ __launch_bounds__(256) void k_near_ss(int npair, const int32_t *__res
     }
 }
 
-static void launch_ss(DevMesh &d, int npair, const int32_t *pt, const int32_t *ps, double *out)
+// Pair indices 0..n-1 grouped by the number of shared vertices: identical,
+// then edge, then vertex pairs; count[c] pairs share c vertices.
+void ss_group(const std::vector<int32_t> &tri, int n, const int32_t *t, const int32_t *s, std::vector<int32_t> &idx,
+              int count[4])
 {
-    if (npair == 0) return;
+    std::vector<int32_t> by[4];
+    for (int i = 0; i < n; ++i) {
+        int c = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) c += tri[3 * t[i] + a] == tri[3 * s[i] + b];
+        if (t[i] == s[i]) c = 3;
+        by[std::min(c, 3)].push_back(i);
+    }
+    idx.clear();
+    for (int c = 3; c >= 1; --c) idx.insert(idx.end(), by[c].begin(), by[c].end());
+    for (int c = 0; c < 4; ++c) count[c] = (int)by[c].size();
+    if (count[0]) fail(PB_E_INVALID_ARG, "pair does not share a vertex");
+}
+
+template <int N>
+static void launch_ss_n(hipStream_t st, const int count[4], const int32_t *idx, const int32_t *pt, const int32_t *ps,
+                        const DevMesh &d, double kap, double *out)
+{
+    const int n3 = count[3], n2 = count[2], n1 = count[1];
+    // wavefronts of 64 / LANES pairs, 4 wavefronts per block
+    auto grid = [](int n, int lanes) { const int per = 4 * (64 / lanes); return dim3((n + per - 1) / per); };
+    if (n3)
+        hipLaunchKernelGGL((k_near_ss<N, 3, 64>), grid(n3, 64), dim3(256), 0, st, n3, idx, pt, ps, d.tri, d.xyz, d.geo,
+                           kap, out);
+    if (n2)
+        hipLaunchKernelGGL((k_near_ss<N, 2, 32>), grid(n2, 32), dim3(256), 0, st, n2, idx + n3, pt, ps, d.tri, d.xyz,
+                           d.geo, kap, out);
+    if (n1)
+        hipLaunchKernelGGL((k_near_ss<N, 1, 16>), grid(n1, 16), dim3(256), 0, st, n1, idx + n3 + n2, pt, ps, d.tri,
+                           d.xyz, d.geo, kap, out);
+}
+
+static void launch_ss(DevMesh &d, const int count[4], const int32_t *idx, const int32_t *pt, const int32_t *ps,
+                      double *out)
+{
+    if (count[1] + count[2] + count[3] == 0) return;
     upload_gauss_tables();
-    dim3 grid((npair + 3) / 4), block(256);
     const double kap = d.prm.kappa;
     switch (d.opt.singular_order) {
 #define SS_CASE(n) \
-    case n: hipLaunchKernelGGL(k_near_ss<n>, grid, block, 0, d.stream, npair, pt, ps, d.tri, d.xyz, d.geo, kap, out); break;
+    case n: launch_ss_n<n>(d.stream, count, idx, pt, ps, d, kap, out); break;
         SS_CASE(1) SS_CASE(2) SS_CASE(3) SS_CASE(4) SS_CASE(5) SS_CASE(6) SS_CASE(7) SS_CASE(8)
 #undef SS_CASE
     default: fail(PB_E_INVALID_ARG, "singular_order must be in [1, 8]");
@@ -195,80 +250,80 @@ static void launch_ss(DevMesh &d, int npair, const int32_t *pt, const int32_t *p
     HIPCHECK(hipGetLastError());
 }
 
-void launch_near_field(DevMesh &d) { launch_ss(d, (int)d.npair(), d.pair_t, d.pair_s, d.pairblk); }
+void launch_near_field(DevMesh &d) { launch_ss(d, d.ss_count, d.ss_idx, d.pair_t, d.pair_s, d.pairblk); }
 
-void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const int32_t *s_sorted, double *out)
+void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const int32_t *s_sorted,
+                               const int32_t *idx, const int count[4], double *out)
 {
-    launch_ss(d, n, t_sorted, s_sorted, out);
+    (void)n;
+    launch_ss(d, count, idx, t_sorted, s_sorted, out);
 }
 
-// One thread per vertex row i: accumulates, in fixed order, every near pair's
-// contribution to the four blocks of row i.  Columns are found by binary search
-// in the row's sorted column list; the row is owned by one thread, so there is
-// no atomic and the result is deterministic.
+// Near-field vertex blocks (mass terms included) of the chosen formulation.
+// One thread per nonzero slot (i, j) sums, in the fixed order row i visits
+// them, the contributions of the near pairs (t containing i as local vertex k,
+// s containing j as local vertex l); the slot is owned by one thread, so there
+// is no atomic and the result is deterministic.
 struct NearCoef {
     int form;
     double kappa, ceps;        // direct: eps_in / eps_out
     double alpha, beta;        // Juffer: eps_out / eps_in, eps_in / eps_out
 };
 
-__global__ void k_near_assemble(int V, NearCoef cf, const int32_t *__restrict__ inc_ptr,
-                                const int32_t *__restrict__ inc_tk, const int32_t *__restrict__ pair_ptr,
-                                const int32_t *__restrict__ pair_s, const int32_t *__restrict__ pair_rev,
-                                const int32_t *__restrict__ tri, const int32_t *__restrict__ row_ptr,
-                                const int32_t *__restrict__ col, const double *__restrict__ geo,
-                                const double *__restrict__ blk, int64_t nnz, double *__restrict__ N)
+// per pair: sum of its 3 x 3 V_L and V_Y entries (the hypersingular curl part)
+__global__ void k_pair_sums(int64_t npair, const double *__restrict__ blk, double *__restrict__ sums)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V) return;
-    const int r0 = row_ptr[i], r1 = row_ptr[i + 1];
-    for (int sl = r0; sl < r1; ++sl) N[sl] = N[nnz + sl] = N[2 * nnz + sl] = N[3 * nnz + sl] = 0.0;
-    for (int e = inc_ptr[i]; e < inc_ptr[i + 1]; ++e) {
-        const int t = inc_tk[e] >> 2, k = inc_tk[e] & 3;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npair) return;
+    const double *B = blk + p * 36;
+    double SL = 0.0, SY = 0.0;
+    for (int a = 0; a < 9; ++a) { SL += B[a]; SY += B[18 + a]; }
+    sums[2 * p] = SL;
+    sums[2 * p + 1] = SY;
+}
+
+__global__ void k_near_slots(int64_t nnz, NearCoef cf, const int32_t *__restrict__ slot_ptr,
+                             const uint32_t *__restrict__ slot_code, const int32_t *__restrict__ pair_t,
+                             const int32_t *__restrict__ pair_s, const int32_t *__restrict__ pair_rev,
+                             const double *__restrict__ geo, const double *__restrict__ blk,
+                             const double *__restrict__ sums, double *__restrict__ N)
+{
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= nnz) return;
+    double n11 = 0.0, n12 = 0.0, n21 = 0.0, n22 = 0.0;
+    for (int c = slot_ptr[slot]; c < slot_ptr[slot + 1]; ++c) {
+        const uint32_t code = slot_code[c];
+        const int p = (int)(code >> 4), k = (code >> 2) & 3, l = code & 3;
+        const int t = pair_t[p], s = pair_s[p];
+        const double *B = blk + (size_t)p * 36;
         const double *gt = geo + (size_t)t * kGeo;
-        const double at = gt[21];
-        for (int p = pair_ptr[t]; p < pair_ptr[t + 1]; ++p) {
-            const int s = pair_s[p];
-            const double *B = blk + (size_t)p * 36;
-            const double *R = blk + (size_t)pair_rev[p] * 36;
+        const double vL = B[3 * k + l], kL = B[9 + 3 * k + l];
+        const double vY = B[18 + 3 * k + l], kY = B[27 + 3 * k + l];
+        const double mss = (s == t) ? gt[21] / 12.0 * (k == l ? 2.0 : 1.0) : 0.0;
+        if (cf.form == PB_DIRECT_INT) {          // Eq. bie:dirichlet:int
+            n11 += 0.5 * mss + kL;
+            n12 += -vL;
+            n21 += 0.5 * mss - kY;
+            n22 += cf.ceps * vY;
+        } else {                                  // Eq. bie:juffer:int
             const double *gs = geo + (size_t)s * kGeo;
-            double SL = 0.0, SY = 0.0;
-            for (int a = 0; a < 9; ++a) { SL += B[a]; SY += B[18 + a]; }
+            const double *R = blk + (size_t)pair_rev[p] * 36;
             const double nn = gt[18] * gs[18] + gt[19] * gs[19] + gt[20] * gs[20];
-            for (int l = 0; l < 3; ++l) {
-                const int j = tri[3 * s + l];
-                int lo = r0, hi = r1 - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi) >> 1;
-                    if (col[mid] < j) lo = mid + 1; else hi = mid;
-                }
-                const double vL = B[3 * k + l], kL = B[9 + 3 * k + l];
-                const double vY = B[18 + 3 * k + l], kY = B[27 + 3 * k + l];
-                const double mss = (s == t) ? at / 12.0 * (k == l ? 2.0 : 1.0) : 0.0;
-                double n11, n12, n21, n22;
-                if (cf.form == PB_DIRECT_INT) {          // Eq. bie:dirichlet:int
-                    n11 = 0.5 * mss + kL;
-                    n12 = -vL;
-                    n21 = 0.5 * mss - kY;
-                    n22 = cf.ceps * vY;
-                } else {                                  // Eq. bie:juffer:int
-                    const double cc = gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
-                                      gt[24 + 3 * k] * gs[24 + 3 * l];
-                    const double dL = cc * SL;
-                    const double dY = cc * SY + cf.kappa * cf.kappa * nn * vY;
-                    const double tL = R[9 + 3 * l + k], tY = R[27 + 3 * l + k];   // T = K^T
-                    n11 = 0.5 * (1.0 + cf.alpha) * mss + kL - cf.alpha * kY;
-                    n12 = -vL + vY;
-                    n21 = -dL + dY;
-                    n22 = 0.5 * (1.0 + cf.beta) * mss - tL + cf.beta * tY;
-                }
-                N[lo] += n11;
-                N[nnz + lo] += n12;
-                N[2 * nnz + lo] += n21;
-                N[3 * nnz + lo] += n22;
-            }
+            const double cc = gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
+                              gt[24 + 3 * k] * gs[24 + 3 * l];
+            const double dL = cc * sums[2 * (size_t)p];
+            const double dY = cc * sums[2 * (size_t)p + 1] + cf.kappa * cf.kappa * nn * vY;
+            const double tL = R[9 + 3 * l + k], tY = R[27 + 3 * l + k];   // T = K^T
+            n11 += 0.5 * (1.0 + cf.alpha) * mss + kL - cf.alpha * kY;
+            n12 += -vL + vY;
+            n21 += -dL + dY;
+            n22 += 0.5 * (1.0 + cf.beta) * mss - tL + cf.beta * tY;
         }
     }
+    N[slot] = n11;
+    N[nnz + slot] = n12;
+    N[2 * nnz + slot] = n21;
+    N[3 * nnz + slot] = n22;
 }
 
 // per-vertex analytic inverse of [[A11_ii, A12_ii], [A21_ii, A22_ii]]; every
@@ -295,8 +350,12 @@ void launch_near_assemble(DevMesh &d)
     cf.alpha = d.prm.eps_out / d.prm.eps_in;
     cf.beta = d.prm.eps_in / d.prm.eps_out;
     const int V = d.hm.V;
-    hipLaunchKernelGGL(k_near_assemble, dim3((V + 127) / 128), dim3(128), 0, d.stream, V, cf, d.inc_ptr, d.inc_tk,
-                       d.pair_ptr, d.pair_s, d.pair_rev, d.tri, d.row_ptr, d.col, d.geo, d.pairblk, d.nnz(), d.N);
+    const int64_t np = d.npair(), nnz = d.nnz();
+    if (cf.form != PB_DIRECT_INT)
+        hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, d.stream, np, d.pairblk,
+                           d.pair_sums);
+    hipLaunchKernelGGL(k_near_slots, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, d.stream, nnz, cf,
+                       d.slot_ptr, d.slot_code, d.pair_t, d.pair_s, d.pair_rev, d.geo, d.pairblk, d.pair_sums, d.N);
     hipLaunchKernelGGL(k_block_diag, dim3((V + 255) / 256), dim3(256), 0, d.stream, V,
                        d.prm.preconditioner == PB_BLOCK_DIAG ? 1 : 0, d.diag_slot, d.N, d.nnz(), d.pinv);
     HIPCHECK(hipGetLastError());

@@ -213,6 +213,35 @@ void build_host_mesh(const pb_mesh *m, HostMesh &hm)
         hm.col.insert(hm.col.end(), buf.begin(), buf.end());
         hm.row_ptr[i + 1] = (int32_t)hm.col.size();
     }
+
+    // per nonzero slot (i, j), its contributions (near pair p, local vertex k
+    // of i in t, local vertex l of j in s) in the order row i visits them --
+    // incidence, pair, l -- as codes p << 4 | k << 2 | l
+    if (np >= ((size_t)1 << 28)) fail(PB_E_INVALID_ARG, "mesh too large");
+    const size_t nnz = hm.col.size();
+    hm.slot_ptr.assign(nnz + 1, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        std::vector<int32_t> fill;
+        if (pass == 1) {
+            for (size_t a = 0; a < nnz; ++a) hm.slot_ptr[a + 1] += hm.slot_ptr[a];
+            hm.slot_code.assign(hm.slot_ptr[nnz], 0);
+            fill.assign(hm.slot_ptr.begin(), hm.slot_ptr.end() - 1);
+        }
+        for (int i = 0; i < V; ++i) {
+            const auto cb = hm.col.begin() + hm.row_ptr[i], ce = hm.col.begin() + hm.row_ptr[i + 1];
+            for (int e2 = hm.inc_ptr[i]; e2 < hm.inc_ptr[i + 1]; ++e2) {
+                const int t = hm.inc_tk[e2] >> 2, k = hm.inc_tk[e2] & 3;
+                for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) {
+                    const int s = hm.pair_s[p];
+                    for (int l = 0; l < 3; ++l) {
+                        const size_t slot = (size_t)(std::lower_bound(cb, ce, hm.tri[3 * s + l]) - hm.col.begin());
+                        if (pass == 0) hm.slot_ptr[slot + 1]++;
+                        else hm.slot_code[fill[slot]++] = ((uint32_t)p << 4) | ((uint32_t)k << 2) | (uint32_t)l;
+                    }
+                }
+            }
+        }
+    }
 }
 
 }  // namespace pbm

@@ -59,6 +59,8 @@ struct HostMesh {
     std::vector<int32_t> row_ptr;     // V + 1, near vertex CSR
     std::vector<int32_t> col;         // columns, ascending within a row
     std::vector<int32_t> diag_slot;   // V: slot of (i, i)
+    std::vector<int32_t> slot_ptr;    // nnz + 1
+    std::vector<uint32_t> slot_code;  // p << 4 | k << 2 | l per contribution, in row visiting order
 };
 void build_host_mesh(const pb_mesh *m, HostMesh &hm);
 
@@ -148,7 +150,12 @@ struct DevMesh {
     float *stat32 = nullptr;       // T x kStat
     int32_t *inc_ptr = nullptr, *inc_tk = nullptr;
     int32_t *pair_ptr = nullptr, *pair_s = nullptr, *pair_rev = nullptr, *pair_t = nullptr;
+    int32_t *ss_idx = nullptr;     // near pairs grouped by case (identical, edge, vertex)
+    int ss_count[4] = {0, 0, 0, 0};   // pairs sharing 0..3 vertices
     int32_t *row_ptr = nullptr, *col = nullptr, *diag_slot = nullptr;
+    int32_t *slot_ptr = nullptr;
+    uint32_t *slot_code = nullptr;
+    double *pair_sums = nullptr;   // npair x 2: sum of the 3 x 3 V_L and V_Y entries
     double *pairblk = nullptr;     // npair x 36
     double *N = nullptr;           // 4 x nnz near blocks (N11, N12, N21, N22), mass included
     double *pinv = nullptr;        // V x 4
@@ -201,7 +208,9 @@ void launch_rhs(DevMesh &d, int nq, const double *qbuf, double *b);
 void launch_reaction(DevMesh &d, int nq, const double *qpts, double *out);
 void launch_inside_test(DevMesh &d, int nq, const double *qbuf, double *out);
 void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const int32_t *s_sorted,
-                               double *out);
+                               const int32_t *idx, const int count[4], double *out);
+void ss_group(const std::vector<int32_t> &tri, int n, const int32_t *t, const int32_t *s, std::vector<int32_t> &idx,
+              int count[4]);
 int choose_chunks(int T);
 int reduction_chunks(int T);
 pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res);

@@ -120,10 +120,16 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
         for (int t = 0; t < T; ++t)
             for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) pt[p] = t;
         d->pair_t = upload(*d, pt);
+        std::vector<int32_t> gi;
+        ss_group(hm.tri, (int)pt.size(), pt.data(), hm.pair_s.data(), gi, d->ss_count);
+        d->ss_idx = upload(*d, gi);
     }
     d->row_ptr = upload(*d, hm.row_ptr);
     d->col = upload(*d, hm.col);
     d->diag_slot = upload(*d, hm.diag_slot);
+    d->slot_ptr = upload(*d, hm.slot_ptr);
+    d->slot_code = upload(*d, hm.slot_code);
+    d->pair_sums = (double *)d->alloc(sizeof(double) * 2 * std::max<int64_t>(d->npair(), 1));
     d->geo = (double *)d->alloc(sizeof(double) * kGeo * T);
     d->stat64 = (double *)d->alloc(sizeof(double) * kStat * T);
     d->stat32 = (float *)d->alloc(sizeof(float) * kStat * T);
@@ -751,11 +757,16 @@ pb_status pb_mesh_near_blocks(pb_mesh_handle *h, int32_t n, const int32_t *t, co
             for (int b = 0; b < 3; ++b) shared += hm.tri[3 * ts[k] + a] == hm.tri[3 * ss[k] + b];
         if (shared == 0) fail(PB_E_INVALID_ARG, "pair does not share a vertex");
     }
+    std::vector<int32_t> gi;
+    int count[4];
+    ss_group(hm.tri, n, ts.data(), ss.data(), gi, count);
     int32_t *dt = (int32_t *)d.alloc(sizeof(int32_t) * n), *ds = (int32_t *)d.alloc(sizeof(int32_t) * n);
+    int32_t *di = (int32_t *)d.alloc(sizeof(int32_t) * n);
     double *o = (double *)d.alloc(sizeof(double) * 36 * n);
     HIPCHECK(hipMemcpyAsync(dt, ts.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, d.stream));
     HIPCHECK(hipMemcpyAsync(ds, ss.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, d.stream));
-    launch_pair_blocks_subset(d, n, dt, ds, o);
+    HIPCHECK(hipMemcpyAsync(di, gi.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, d.stream));
+    launch_pair_blocks_subset(d, n, dt, ds, di, count, o);
     HIPCHECK(hipMemcpyAsync(out, o, sizeof(double) * 36 * n, hipMemcpyDeviceToHost, d.stream));
     HIPCHECK(hipStreamSynchronize(d.stream));
     return PB_OK;
