@@ -118,7 +118,7 @@ template <typename R, typename S, int FORM, int TILE, bool SYM>
 __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 1))) void k_assemble_tile(
     int T, int V, AsmCoef<R> cf, const int32_t *__restrict__ targets, int ntarget, int group,
     const int32_t *__restrict__ tiles, const int4 *__restrict__ sym_blocks, const int32_t *__restrict__ tri,
-    const R *__restrict__ stat, const double *__restrict__ geo, const int32_t *__restrict__ vpos,
+    const R *__restrict__ stat, const int32_t *__restrict__ vpos,
     const int32_t *__restrict__ tv_ptr, const int32_t *__restrict__ tv_col, const int32_t *__restrict__ tv_eptr,
     const int32_t *__restrict__ te, S *__restrict__ A, size_t ld, size_t Vp, S *__restrict__ C, size_t ldc)
 {
@@ -286,10 +286,9 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
 #pragma unroll
                 for (int o = 0; o < NV; ++o) val[o] = blk[l][k][o] * f[o];
                 if (FORM == 1) {
-                    const double *gt = geo + (size_t)t * kGeo, *gs = geo + (size_t)sl * kGeo;
                     // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
-                    const R cc = (R)(gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
-                                     gt[24 + 3 * k] * gs[24 + 3 * l]);
+                    const R cc = ts[28 + 3 * k] * ss[28 + 3 * l] + ts[29 + 3 * k] * ss[29 + 3 * l] +
+                                 ts[30 + 3 * k] * ss[30 + 3 * l];
                     val[2] += sc * cc * Ssum;
                 }
                 // a pair sharing a vertex may have produced inf or NaN: select, not scale
@@ -780,11 +779,11 @@ static void assemble(DevMesh &d, S *A)
                 if (nb == 0) continue;
                 if (direct)
                     hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE, true>), dim3(nb), dim3(TILE), 0, d.stream, T,
-                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat, d.geo,
+                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat,
                                        D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp);
                 else
                     hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE, true>), dim3(nb), dim3(TILE), 0, d.stream, T,
-                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat, d.geo,
+                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat,
                                        D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp);
             }
         // V x V blocks of A (row block, column block): symmetric operators take
@@ -816,11 +815,11 @@ static void assemble(DevMesh &d, S *A)
                 dim3 grid(nk, (nt + grp - 1) / grp), block(TILE);
                 if (direct)
                     hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE, false>), grid, block, 0, d.stream, T, V, cf, tg,
-                                       nt, grp, tl, nullptr, d.tri, stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
+                                       nt, grp, tl, nullptr, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
                                        D.te, A, D.ld, D.Vp, nullptr, (size_t)0);
                 else
                     hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE, false>), grid, block, 0, d.stream, T, V, cf, tg,
-                                       nt, grp, tl, nullptr, d.tri, stat, d.geo, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
+                                       nt, grp, tl, nullptr, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
                                        D.te, A, D.ld, D.Vp, nullptr, (size_t)0);
             }
         }

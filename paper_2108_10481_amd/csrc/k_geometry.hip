@@ -54,7 +54,11 @@ __global__ void k_geometry(int T, const double *__restrict__ xyz, const int32_t 
     g[31] = 0.0;
     s64[27] = area;
     s32[27] = (float)area;
-    for (int i = 28; i < kStat; ++i) { s64[i] = 0.0; s32[i] = 0.0f; }
+    for (int i = 0; i < 9; ++i) {
+        s64[28 + i] = g[22 + i];
+        s32[28 + i] = (float)g[22 + i];
+    }
+    for (int i = 37; i < kStat; ++i) { s64[i] = 0.0; s32[i] = 0.0f; }
 }
 
 void launch_geometry(DevMesh &d)

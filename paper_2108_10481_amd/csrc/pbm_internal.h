@@ -66,9 +66,10 @@ void build_host_mesh(const pb_mesh *m, HostMesh &hm);
 
 // ------------------------------------------------------------ device state
 // Source / target records of the far-field kernels, one per triangle:
-//   static  (kStat reals): 6 quadrature points x 3, normal 3, y_q . n 6, area 1, zero padding
+//   static  (kStat reals): 6 quadrature points x 3, normal 3, y_q . n 6, area 1,
+//                          surface curls of the three hat functions 9, zero padding
 //   dynamic (kDyn reals) : b1[6] = w_q|s| u1(y_q), b2[6] = w_q|s| u2(y_q), C[3] = |s| curl u1|_s
-constexpr int kStat = 32;
+constexpr int kStat = 40;
 constexpr int kDyn = 16;
 // per-triangle FP64 geometry: pts 18, normal 3, area 1, curl 9 -> 31, padded
 constexpr int kGeo = 32;
