@@ -4,8 +4,9 @@
 Workload (the configuration the headline metric is quoted on): sphere of
 radius 10 A meshed as a frequency-32 icosphere (20480 flat triangles, 10242
 vertices), 50 charges uniform in r < 8 A with values U[-1, 1] e (seed 2),
-eps_in 4, eps_out 80, kappa 0.125 / A, block-diagonal preconditioner, GMRES
-tolerance 1e-5 without restart.
+eps_in 4, eps_out 80, kappa 0.125 / A, block-diagonal preconditioner (with
+--preconditioner scaled-mass, the Juffer solves use the scaled mass matrix),
+GMRES tolerance 1e-5 without restart.
 
 One step = one complete solve with the internal direct formulation plus one
 with the Juffer formulation, each covering every stage of the hot path:
@@ -62,6 +63,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=160, help="oracle rows per formulation in the CPU sample")
     ap.add_argument("--workload", default="sphere", choices=["sphere", "star", "multi", "serving"])
+    ap.add_argument("--preconditioner", default="block-diag", choices=["block-diag", "scaled-mass"],
+                    help="scaled-mass: the Juffer solves use blockdiag(aM, bM)^-1 (the paper's Case 10), "
+                         "the direct ones keep the block-diagonal preconditioner (Case 2)")
     return ap.parse_known_args()[0]
 
 
@@ -82,12 +86,12 @@ def main():
     if a.workload == "star":
         mesh, ch = inputs.config_star()
         workload = ("star surface R=18 A (1 + 0.15 sum Y_lm, l<=6, seed 3), 81920 triangles / 40962 vertices, 2000 "
-                    "charges N(0,0.4) e inside 0.8 r, eps 4/80, kappa 0.125, direct + Juffer, block-diagonal, "
+                    "charges N(0,0.4) e inside 0.8 r, eps 4/80, kappa 0.125, direct + Juffer, "
                     "GMRES tol 1e-5; one step = one solve per formulation")
     else:
         mesh, ch = inputs.config_sphere()
         workload = ("sphere R=10 A, icosphere 20480 triangles / 10242 vertices, 50 charges U[-1,1] e in r<8 A "
-                    "(seed 2), eps 4/80, kappa 0.125, direct + Juffer, block-diagonal, GMRES tol 1e-5; "
+                    "(seed 2), eps 4/80, kappa 0.125, direct + Juffer, GMRES tol 1e-5; "
                     "one step = one solve per formulation")
     T = mesh.n_triangles
     P = 6 * T
@@ -101,8 +105,11 @@ def main():
                                                 operator_mode=pbm.PB_MATRIX_FREE))
         ref[f] = r
 
+    precs = {f: pbm.PB_SCALED_MASS if (a.preconditioner == "scaled-mass" and f == pbm.PB_JUFFER)
+             else pbm.PB_BLOCK_DIAG for f in forms}
     handles = {f: pbm.MeshHandle(mesh.xyz, mesh.tri,
-                                 pbm.pb_default_options(formulation=f, precision=prec, operator_mode=mode))
+                                 pbm.pb_default_options(formulation=f, precision=prec, operator_mode=mode,
+                                                        preconditioner=precs[f]))
                for f in forms}
 
     def step():
@@ -192,7 +199,10 @@ def main():
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": workload,
                    "precision": a.precision, "operator_mode": "assembled" if assembled else "matrix-free",
-                   "source_chunks": info[forms[0]]["source_chunks"]},
+                   "source_chunks": info[forms[0]]["source_chunks"],
+                   "preconditioner": {"direct": "block-diagonal",
+                                      "juffer": "scaled mass" if a.preconditioner == "scaled-mass"
+                                      else "block-diagonal"}},
         "kernel_pairs_per_s": round(kernel_pairs / (kern_ms * 1e-3), 1) if kernel_pairs and kern_ms > 0 else None,
         "dense_product": dense_product,
         "p50_ms": round(lat_ms[len(lat_ms) // 2], 3),

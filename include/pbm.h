@@ -59,6 +59,9 @@ typedef int32_t pb_status;
 
 #define PB_PREC_NONE    0
 #define PB_BLOCK_DIAG   1  /* per-vertex 2x2 inverse of the four blocks' diagonals */
+#define PB_MASS         2  /* blockdiag(M, M)^-1, M the P1 mass matrix (Eq. prec:mass) */
+#define PB_SCALED_MASS  3  /* blockdiag(aM, bM)^-1 with a = 1 + e_out/e_in, b = 1 + e_in/e_out
+                              (Eq. prec:mass:scaled; Juffer formulation only) */
 
 #define PB_FP64         0  /* every kernel evaluation and sum in FP64 */
 #define PB_FP32         1  /* far-field kernel evaluations in FP32, tile sums FP32,

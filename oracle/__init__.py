@@ -6,8 +6,8 @@ library never calls it and shares no code with it.
 
 Plain and slow on purpose: the per-pair quadrature lives in ``pbm_oracle.c``
 (plain C loops, FP64); this module composes the paper's block systems from
-dense operator matrices with NumPy, applies the block-diagonal
-preconditioner, runs unrestarted GMRES (modified Gram-Schmidt, Givens
+dense operator matrices with NumPy, applies the block-diagonal or the (scaled)
+mass-matrix preconditioner, runs unrestarted GMRES (modified Gram-Schmidt, Givens
 rotations) and evaluates the solvation energy.
 
 Citations are to Search, Cooper & van 't Wout, arXiv 2108.10481:
@@ -16,6 +16,7 @@ Citations are to Search, Cooper & van 't Wout, arXiv 2108.10481:
   * source projections .................. Eq. sources
   * reaction potential, energy .......... Eqs. phireac_bie and dG
   * block-diagonal preconditioner ....... Preconditioning / Algebraic preconditioners
+  * (scaled) mass-matrix preconditioner . Eqs. prec:mass and prec:mass:scaled
   * GMRES, tol 1e-5, no restart ......... Results and Discussion (setup paragraph)
 """
 from __future__ import annotations
@@ -255,6 +256,30 @@ def apply_block_diag(inv, v):
                            inv[:, 1, 0] * v1 + inv[:, 1, 1] * v2])
 
 
+def mass_scales(eps_in, eps_out, formulation, scaled: bool):
+    """(a, b) of blockdiag(aM, bM): 1, 1 for the plain mass matrix (Eq.
+    prec:mass); for the Juffer formulation scaled as the Mass-matrix
+    preconditioning paragraph states, a = 1 + eps_out/eps_in and
+    b = 1 + eps_in/eps_out (Eq. prec:mass:scaled)."""
+    if not scaled:
+        return 1.0, 1.0
+    if formulation != JUFFER:
+        raise ValueError("the scaled mass preconditioner is defined for the Juffer formulation")
+    return 1.0 + eps_out / eps_in, 1.0 + eps_in / eps_out
+
+
+def mass_preconditioner(mesh, a: float = 1.0, b: float = 1.0):
+    """v -> blockdiag(aM, bM)^-1 v with M the P1 mass matrix, through a dense
+    Cholesky factorisation of M (M is symmetric positive definite)."""
+    import scipy.linalg as sla
+    nv = mesh.n_vertices
+    F = sla.cho_factor(mass(mesh))
+
+    def apply(v):
+        return np.concatenate([sla.cho_solve(F, v[:nv]) / a, sla.cho_solve(F, v[nv:]) / b])
+    return apply
+
+
 def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
     """Unrestarted GMRES from x0 = 0 with modified Gram-Schmidt and Givens
     rotations; stops when the residual estimate drops below tol * |b|.
@@ -304,17 +329,23 @@ def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
 
 def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRECT,
           preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None):
-    """Dense FP64 solve: returns dict(phi, dphi, dG, iterations, rel_residual)."""
+    """Dense FP64 solve: returns dict(phi, dphi, dG, iterations, rel_residual).
+    preconditioner: True or "block_diag", False or None, "mass", "scaled_mass"."""
     nv = mesh.n_vertices
     if A is None:
         A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss)
     bD, bN = rhs(mesh, charges, eps_in)
     b = system_rhs(bD, bN, formulation)
-    if preconditioner:
+    if preconditioner is True or preconditioner == "block_diag":
         inv = block_diagonal_inverse(A, nv)
         P = lambda v: apply_block_diag(inv, v)
-    else:
+    elif preconditioner in ("mass", "scaled_mass"):
+        a, bb = mass_scales(eps_in, eps_out, formulation, preconditioner == "scaled_mass")
+        P = mass_preconditioner(mesh, a, bb)
+    elif preconditioner is False or preconditioner is None:
         P = lambda v: v
+    else:
+        raise ValueError(f"unknown preconditioner {preconditioner!r}")
     pb = P(b)
     u, its, hist = gmres(lambda v: P(A @ v), pb, tol, max_iter)
     res = float(np.linalg.norm(pb - P(A @ u)) / np.linalg.norm(pb))

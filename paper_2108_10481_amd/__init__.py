@@ -28,6 +28,8 @@ PB_DIRECT_INT = 0
 PB_JUFFER = 1
 PB_PREC_NONE = 0
 PB_BLOCK_DIAG = 1
+PB_MASS = 2
+PB_SCALED_MASS = 3
 PB_FP64 = 0
 PB_FP32 = 1
 PB_MIXED_BF16 = 2

@@ -288,8 +288,14 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
             HIPCHECK(hipEventRecord(e1, d.stream));
             pf.record(0, e0, e1, (double)n * n * 2.0 + kMaxBatch * (double)n * (2.0 + 8.0));
         }
-        hipLaunchKernelGGL(k_gather_batch, dim3((V + 255) / 256, nb), dim3(256), 0, d.stream, V, n, 1, d.row_ptr, d.col,
-                           d.N, d.nnz(), d.pinv, D->vpos, D->Y16, X, Y);
+        if (mass_mode(d)) {
+            hipLaunchKernelGGL(k_gather_batch, dim3((V + 255) / 256, nb), dim3(256), 0, d.stream, V, n, 0, d.row_ptr,
+                               d.col, d.N, d.nnz(), d.pinv, D->vpos, D->Y16, X, d.mtmp);
+            mass_precond(d, nb, d.mtmp, Y, DevCtl());
+        } else {
+            hipLaunchKernelGGL(k_gather_batch, dim3((V + 255) / 256, nb), dim3(256), 0, d.stream, V, n, 1, d.row_ptr,
+                               d.col, d.N, d.nnz(), d.pinv, D->vpos, D->Y16, X, Y);
+        }
         HIPCHECK(hipGetLastError());
     } else {
         for (int s = 0; s < nb; ++s) apply_operator(d, X + (size_t)s * n, Y + (size_t)s * n, PB_APPLY_PRECOND, nullptr);
@@ -415,7 +421,9 @@ pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result 
         }
         HIPCHECK(hipStreamSynchronize(st));
         const double t1 = now_s();
-        for (int s = 0; s < nb; ++s) kr_precond(st, V, d.pinv, w.B + (size_t)s * n, w.PB + (size_t)s * n);
+        if (mass_mode(d)) mass_precond(d, nb, w.B, w.PB, DevCtl());
+        else
+            for (int s = 0; s < nb; ++s) kr_precond(st, V, d.pinv, w.B + (size_t)s * n, w.PB + (size_t)s * n);
         HIPCHECK(hipStreamSynchronize(st));
         const double t2 = now_s();
         std::vector<int> its(nb, 0), itot(nb, 0), outer(nb, 1);

@@ -215,12 +215,12 @@ __global__ void k_gather(int V, int use_far, int use_near, int precond, const in
                          const double *__restrict__ yfar, const int32_t *__restrict__ vpos,
                          const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                          const double *__restrict__ N, int64_t nnz, const double *__restrict__ pinv,
-                         const double *__restrict__ x, double *__restrict__ y, DevCtl ctl)
+                         const double *__restrict__ x, double *__restrict__ y, DevCtl ctl, DevCtl ctly)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= V || ctl_skip(ctl)) return;
     x += ctl_off(ctl);
-    y += ctl_off(ctl);
+    y += ctl_off(ctly);
     double y1 = 0.0, y2 = 0.0;
     if (use_far == 2) {   // dense far product, rows in dense vertex order
         const int r = vpos[i];
@@ -318,13 +318,15 @@ void launch_far_finish(DevMesh &d, bool fp32)
     HIPCHECK(hipGetLastError());
 }
 
-void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far)
+void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far, bool y_offset)
 {
     const int V = d.hm.V;
     const int use_near = (flags & PB_APPLY_FAR_ONLY) ? 0 : 1;
+    DevCtl ctly = d.ctl;
+    if (!y_offset) ctly.stride = 0;
     hipLaunchKernelGGL(k_gather, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, use_far, use_near,
                        (flags & PB_APPLY_PRECOND) ? 1 : 0, d.inc_ptr, d.inc_tk, d.triout, d.yfar, d.dense_vpos, d.row_ptr, d.col, d.N,
-                       d.nnz(), d.pinv, x, y, d.ctl);
+                       d.nnz(), d.pinv, x, y, d.ctl, ctly);
     HIPCHECK(hipGetLastError());
 }
 

@@ -286,11 +286,11 @@ __global__ void k_near_slots(int64_t nnz, NearCoef cf, const int32_t *__restrict
                              const uint32_t *__restrict__ slot_code, const int32_t *__restrict__ pair_t,
                              const int32_t *__restrict__ pair_s, const int32_t *__restrict__ pair_rev,
                              const double *__restrict__ geo, const double *__restrict__ blk,
-                             const double *__restrict__ sums, double *__restrict__ N)
+                             const double *__restrict__ sums, double *__restrict__ N, double *__restrict__ Mval)
 {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= nnz) return;
-    double n11 = 0.0, n12 = 0.0, n21 = 0.0, n22 = 0.0;
+    double n11 = 0.0, n12 = 0.0, n21 = 0.0, n22 = 0.0, mass = 0.0;
     for (int c = slot_ptr[slot]; c < slot_ptr[slot + 1]; ++c) {
         const uint32_t code = slot_code[c];
         const int p = (int)(code >> 4), k = (code >> 2) & 3, l = code & 3;
@@ -300,6 +300,7 @@ __global__ void k_near_slots(int64_t nnz, NearCoef cf, const int32_t *__restrict
         const double vL = B[3 * k + l], kL = B[9 + 3 * k + l];
         const double vY = B[18 + 3 * k + l], kY = B[27 + 3 * k + l];
         const double mss = (s == t) ? gt[21] / 12.0 * (k == l ? 2.0 : 1.0) : 0.0;
+        mass += mss;
         if (cf.form == PB_DIRECT_INT) {          // Eq. bie:dirichlet:int
             n11 += 0.5 * mss + kL;
             n12 += -vL;
@@ -324,6 +325,7 @@ __global__ void k_near_slots(int64_t nnz, NearCoef cf, const int32_t *__restrict
     N[nnz + slot] = n12;
     N[2 * nnz + slot] = n21;
     N[3 * nnz + slot] = n22;
+    if (Mval) Mval[slot] = mass;
 }
 
 // per-vertex analytic inverse of [[A11_ii, A12_ii], [A21_ii, A22_ii]]; every
@@ -341,6 +343,95 @@ __global__ void k_block_diag(int V, int enabled, const int32_t *__restrict__ dia
     o[0] = e / det; o[1] = -b / det; o[2] = -c / det; o[3] = a / det;
 }
 
+// ------------------------------------------------ mass preconditioners
+// blockdiag(aM, bM)^-1 (Eqs. prec:mass, prec:mass:scaled), M the P1 mass
+// matrix.  M^-1 is applied as a fixed-degree Chebyshev iteration on the
+// Jacobi-scaled mass matrix D^-1 M (Y. Saad, Iterative Methods for Sparse
+// Linear Systems, 2nd ed., sec. 12.3): for P1 triangles every element's
+// generalised eigenvalues against its diagonal are 2, 1/2, 1/2, so the
+// spectrum of D^-1 M lies in [1/2, 2] on any mesh (element-by-element bound)
+// and each step reduces the error by 1/3 at least.  kChebSteps steps give a
+// fixed linear operator within 2 (1/3)^20 = 6e-10 of M^-1; no reductions, so
+// it is capturable like every other part of an iteration.
+constexpr int kChebSteps = 20;
+constexpr double kChebTheta = 1.25, kChebDelta = 0.75;   // centre and half-width of [1/2, 2]
+
+__global__ void k_mass_diag(int V, const int32_t *__restrict__ diag, const double *__restrict__ Mval,
+                            double *__restrict__ Mdinv)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < V) Mdinv[i] = 1.0 / Mval[diag[i]];
+}
+
+// systems s < nvec of 2V entries (both halves use M); x = 0, r = in, d = D^-1 r / theta
+__global__ void k_cheb_init(int V, const double *__restrict__ Mdinv, const double *__restrict__ in,
+                            double *__restrict__ x, double *__restrict__ r, double *__restrict__ dv, DevCtl ctl)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * V || ctl_skip(ctl)) return;
+    const size_t o = (size_t)blockIdx.y * 2 * V + e;
+    const int i = e < V ? e : e - V;
+    const double v = in[o];
+    x[o] = 0.0;
+    r[o] = v;
+    dv[o] = v * Mdinv[i] * (1.0 / kChebTheta);
+}
+
+// x += d; r -= M d; d' = c1 d + c2 D^-1 r
+__global__ void k_cheb_step(int V, const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ Mval, const double *__restrict__ Mdinv, double c1, double c2,
+                            double *__restrict__ x, double *__restrict__ r, const double *__restrict__ dv,
+                            double *__restrict__ dn, DevCtl ctl)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * V || ctl_skip(ctl)) return;
+    const size_t base = (size_t)blockIdx.y * 2 * V + (e < V ? 0 : V);
+    const int i = e < V ? e : e - V;
+    const size_t o = base + i;
+    double md = 0.0;
+    for (int sl = row_ptr[i]; sl < row_ptr[i + 1]; ++sl) md += Mval[sl] * dv[base + col[sl]];
+    const double rv = r[o] - md;
+    x[o] += dv[o];
+    r[o] = rv;
+    dn[o] = c1 * dv[o] + c2 * Mdinv[i] * rv;
+}
+
+// out = (x + d) scaled by 1/a (first half) and 1/b (second half)
+__global__ void k_cheb_final(int V, double sa, double sb, const double *__restrict__ x, const double *__restrict__ dv,
+                             double *__restrict__ out, DevCtl ctl)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * V || ctl_skip(ctl)) return;
+    const size_t o = (size_t)blockIdx.y * 2 * V + e;
+    out[o + ctl_off(ctl)] = (x[o] + dv[o]) * (e < V ? sa : sb);
+}
+
+void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl)
+{
+    const int V = d.hm.V;
+    if (nvec < 1 || nvec > kMassBatch) fail(PB_E_INVALID_ARG, "mass preconditioner batch size");
+    double sa = 1.0, sb = 1.0;
+    if (d.prm.preconditioner == PB_SCALED_MASS) {
+        sa = 1.0 / (1.0 + d.prm.eps_out / d.prm.eps_in);
+        sb = 1.0 / (1.0 + d.prm.eps_in / d.prm.eps_out);
+    }
+    const size_t n = 2 * (size_t)V * kMassBatch;
+    double *x = d.cheb, *r = d.cheb + n, *dv[2] = {d.cheb + 2 * n, d.cheb + 3 * n};
+    const dim3 g((unsigned)((2 * V + 255) / 256), (unsigned)nvec), b(256);
+    hipLaunchKernelGGL(k_cheb_init, g, b, 0, d.stream, V, d.Mdinv, in, x, r, dv[0], ctl);
+    const double s1 = kChebTheta / kChebDelta;
+    double rho = 1.0 / s1;
+    int cur = 0;
+    for (int k = 1; k < kChebSteps; ++k, cur ^= 1) {
+        const double rn = 1.0 / (2.0 * s1 - rho);
+        hipLaunchKernelGGL(k_cheb_step, g, b, 0, d.stream, V, d.row_ptr, d.col, d.Mval, d.Mdinv, rn * rho,
+                           2.0 * rn / kChebDelta, x, r, dv[cur], dv[cur ^ 1], ctl);
+        rho = rn;
+    }
+    hipLaunchKernelGGL(k_cheb_final, g, b, 0, d.stream, V, sa, sb, x, dv[cur], out, ctl);
+    HIPCHECK(hipGetLastError());
+}
+
 void launch_near_assemble(DevMesh &d)
 {
     NearCoef cf;
@@ -355,7 +446,11 @@ void launch_near_assemble(DevMesh &d)
         hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, d.stream, np, d.pairblk,
                            d.pair_sums);
     hipLaunchKernelGGL(k_near_slots, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, d.stream, nnz, cf,
-                       d.slot_ptr, d.slot_code, d.pair_t, d.pair_s, d.pair_rev, d.geo, d.pairblk, d.pair_sums, d.N);
+                       d.slot_ptr, d.slot_code, d.pair_t, d.pair_s, d.pair_rev, d.geo, d.pairblk, d.pair_sums, d.N,
+                       d.Mval);
+    if (d.Mval)
+        hipLaunchKernelGGL(k_mass_diag, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, d.diag_slot, d.Mval,
+                           d.Mdinv);
     hipLaunchKernelGGL(k_block_diag, dim3((V + 255) / 256), dim3(256), 0, d.stream, V,
                        d.prm.preconditioner == PB_BLOCK_DIAG ? 1 : 0, d.diag_slot, d.N, d.nnz(), d.pinv);
     HIPCHECK(hipGetLastError());

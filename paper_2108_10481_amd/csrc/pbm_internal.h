@@ -160,6 +160,9 @@ struct DevMesh {
     double *pairblk = nullptr;     // npair x 36
     double *N = nullptr;           // 4 x nnz near blocks (N11, N12, N21, N22), mass included
     double *pinv = nullptr;        // V x 4
+    // mass preconditioners: M over the near CSR slots, 1 / M_ii, Chebyshev
+    // state and a product buffer (kMassBatch systems)
+    double *Mval = nullptr, *Mdinv = nullptr, *cheb = nullptr, *mtmp = nullptr;
     // matvec workspaces
     double *dyn64 = nullptr;       // T x kDyn
     float *dyn32 = nullptr;        // T x kDyn
@@ -203,7 +206,8 @@ void launch_source_prep(DevMesh &d, const double *x, bool fp32);
 void launch_far(DevMesh &d, bool fp32);
 void launch_far_finish(DevMesh &d, bool fp32);
 // use_far: 0 = near only, 1 = far from per-triangle outputs, 2 = far from d.yfar
-void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far);
+// y_offset false: y is a plain vector even inside a captured iteration
+void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far, bool y_offset);
 void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream_t s);
 void launch_rhs(DevMesh &d, int nq, const double *qbuf, double *b);
 void launch_reaction(DevMesh &d, int nq, const double *qpts, double *out);
@@ -240,6 +244,13 @@ void kr_scale_copy(hipStream_t s, int n, const double *x, double a, double *y);
 void kr_axpy(hipStream_t s, int n, double a, const double *x, double *y);
 void kr_combine(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *y, double *x);
 void kr_precond(hipStream_t s, int V, const double *pinv, const double *x, double *y);
+// mass preconditioners (k_near.hip)
+constexpr int kMassBatch = 16;
+inline bool mass_mode(const DevMesh &d)
+{
+    return d.prm.preconditioner == PB_MASS || d.prm.preconditioner == PB_SCALED_MASS;
+}
+void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl);
 void kr_graph_iteration_tail(hipStream_t s, int n, int m, double *Vb, GState *st, double *H, double *cs, double *sn,
                              double *g, double *h1, double *h2);
 

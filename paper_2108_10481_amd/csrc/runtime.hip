@@ -72,8 +72,10 @@ static void check_options(const pb_options *o)
     if (!(o->eps_in > 0) || !(o->eps_out > 0) || !(o->kappa >= 0) || !std::isfinite(o->kappa))
         fail(PB_E_INVALID_ARG, "eps_in, eps_out must be > 0 and kappa >= 0");
     if (o->formulation != PB_DIRECT_INT && o->formulation != PB_JUFFER) fail(PB_E_INVALID_ARG, "unknown formulation");
-    if (o->preconditioner != PB_BLOCK_DIAG && o->preconditioner != PB_PREC_NONE)
+    if (o->preconditioner < PB_PREC_NONE || o->preconditioner > PB_SCALED_MASS)
         fail(PB_E_INVALID_ARG, "unknown preconditioner");
+    if (o->preconditioner == PB_SCALED_MASS && o->formulation != PB_JUFFER)
+        fail(PB_E_INVALID_ARG, "the scaled mass preconditioner is defined for the Juffer formulation");
     if (o->precision < PB_FP64 || o->precision > PB_MIXED_FP16) fail(PB_E_INVALID_ARG, "unknown precision");
     if (o->operator_mode < PB_MATRIX_FREE || o->operator_mode > PB_AUTO) fail(PB_E_INVALID_ARG, "unknown operator mode");
     if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
@@ -136,6 +138,14 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->pairblk = (double *)d->alloc(sizeof(double) * 36 * d->npair());
     d->N = (double *)d->alloc(sizeof(double) * 4 * d->nnz());
     d->pinv = (double *)d->alloc(sizeof(double) * 4 * V);
+    if (opt->preconditioner == PB_MASS || opt->preconditioner == PB_SCALED_MASS) {
+        d->Mval = (double *)d->alloc(sizeof(double) * std::max<int64_t>(d->nnz(), 1));
+        d->Mdinv = (double *)d->alloc(sizeof(double) * V);
+        // Chebyshev state (x, r, d, d') and the unpreconditioned products, for
+        // up to kMassBatch systems
+        d->cheb = (double *)d->alloc(sizeof(double) * 4 * kMassBatch * 2 * (size_t)V);
+        d->mtmp = (double *)d->alloc(sizeof(double) * kMassBatch * 2 * (size_t)V);
+    }
     d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
     d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
     d->part = d->alloc(sizeof(double) * 16 * (size_t)d->S * T);
@@ -181,6 +191,8 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     // side matrix (FP32) of the same size
     const double dense = n * 2.0 * Vp * (o->precision == PB_FP64 ? 8.0 : 6.0);
     if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense;
+    if (o->preconditioner == PB_MASS || o->preconditioner == PB_SCALED_MASS)
+        b += 5.0 * kMassBatch * n * 8 + 20.0 * v * 8 + v * 8;   // Chebyshev state, products, M, 1 / M_ii
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
     return (size_t)(b * 1.1);
 }
@@ -204,7 +216,12 @@ void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream
             use_far = 1;
         }
     }
-    launch_gather(d, x, y, flags, use_far);
+    if ((flags & PB_APPLY_PRECOND) && mass_mode(d)) {
+        launch_gather(d, x, d.mtmp, flags & ~PB_APPLY_PRECOND, use_far, false);
+        mass_precond(d, 1, d.mtmp, y, d.ctl);
+    } else {
+        launch_gather(d, x, y, flags, use_far, true);
+    }
     d.stream = keep;
 }
 
@@ -541,7 +558,8 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
     if (d.prm.formulation == PB_DIRECT_INT) HIPCHECK(hipMemsetAsync(b + V, 0, sizeof(double) * V, d.stream));
     HIPCHECK(hipStreamSynchronize(d.stream));
     double t1 = now();
-    kr_precond(d.stream, V, d.pinv, b, pb);
+    if (mass_mode(d)) mass_precond(d, 1, b, pb, DevCtl());
+    else kr_precond(d.stream, V, d.pinv, b, pb);
     HIPCHECK(hipStreamSynchronize(d.stream));
     double t2 = now();
     if (!d.u) d.u = (double *)d.alloc(sizeof(double) * n);

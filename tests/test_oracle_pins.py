@@ -363,3 +363,56 @@ def test_juffer_mass_spectrum_approaches_printed_points():
         dist.append((lo.min() / p_lo - 1.0, hi.min() / p_hi - 1.0))
     for k in range(2):
         assert 0 < dist[1][k] < 0.05 and dist[1][k] < 0.7 * dist[0][k], dist
+
+
+def test_scaled_mass_single_accumulation_point():
+    """With blockdiag(aM, bM), a = 1 + eps_out/eps_in, b = 1 + eps_in/eps_out
+    (Eq. prec:mass:scaled), both identity terms of the Juffer system,
+    (1 + eps_out/eps_in)/2 and (1 + eps_in/eps_out)/2, map to 1/2: the
+    spectrum gathers around one point, and ever closer as the mesh is
+    refined, while the plain mass matrix (Eq. prec:mass) keeps two clusters."""
+    med = []
+    for f in (4, 8):
+        m = inputs.icosphere(f, 2.0)
+        A = oracle.system_matrix(m, 4.0, 80.0, 0.125, oracle.JUFFER)
+        M = oracle.mass(m)
+        Z = np.zeros_like(M)
+        a, b = oracle.mass_scales(4.0, 80.0, oracle.JUFFER, True)
+        assert (a, b) == (21.0, 1.05)
+        ev = np.linalg.eigvals(np.linalg.solve(np.block([[a * M, Z], [Z, b * M]]), A))
+        med.append(np.median(np.abs(ev - 0.5)))
+        q = np.quantile(ev.real, [0.05, 0.95])
+        assert 0.5 < q[0] and q[1] < 0.7, q
+        ev0 = np.linalg.eigvals(np.linalg.solve(np.block([[M, Z], [Z, M]]), A)).real
+        assert np.sum(ev0 > 5.0) == m.n_vertices   # one cluster per block
+    assert med[1] < 0.6 * med[0] and med[1] < 0.03, med
+
+
+def test_mass_preconditioners_solution_and_iterations():
+    """Mass-preconditioned GMRES reaches the dense LU solution; for the
+    Juffer system the scaled mass matrix needs fewer iterations than the
+    plain one and than none (the paper's Cases 9 and 10)."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    for form, precs in ((oracle.DIRECT, ("mass",)), (oracle.JUFFER, ("mass", "scaled_mass"))):
+        A = oracle.system_matrix(m, 4.0, 80.0, 0.125, form)
+        bD, bN = oracle.rhs(m, ch, 4.0)
+        x = np.linalg.solve(A, oracle.system_rhs(bD, bN, form))
+        for prec in precs:
+            r = oracle.solve(m, ch, formulation=form, preconditioner=prec, tol=1e-13, A=A)
+            u = np.concatenate([r["phi"], r["dphi"]])
+            assert np.abs(u - x).max() < 1e-9 * np.abs(x).max(), (form, prec)
+    with pytest.raises(ValueError):
+        oracle.mass_scales(4.0, 80.0, oracle.DIRECT, True)
+    for m, ch in (inputs.config_sphere(8, 10.0, 10, 8.0, 2),):
+        A = oracle.system_matrix(m, 4.0, 80.0, 0.125, oracle.JUFFER)
+        its = {p: oracle.solve(m, ch, formulation=oracle.JUFFER, preconditioner=p, A=A)["iterations"]
+               for p in (None, "mass", "scaled_mass")}
+        assert its["scaled_mass"] < its["mass"] < its[None], its
+    P = oracle.mass_preconditioner(m, 2.0, 3.0)
+    M = oracle.mass(m)
+    v = np.random.default_rng(0).standard_normal(2 * m.n_vertices)
+    w = P(v)
+    nv = m.n_vertices
+    # the inverse of the sparse mass matrix, checked by applying M itself
+    assert np.abs(2.0 * M @ w[:nv] - v[:nv]).max() < 1e-12 * np.abs(v).max()
+    assert np.abs(3.0 * M @ w[nv:] - v[nv:]).max() < 1e-12 * np.abs(v).max()
