@@ -53,6 +53,22 @@ VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 TRANS_SLOTS = 4
 
 
+def measured_traffic(workload_key: str):
+    """HBM bytes per assembly (and per GEMV launch) from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs summarised in profiles/traffic.json, scaled by the copy-kernel
+    calibration stored there; None when the assembly source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        t = json.load(open(path))
+        src = open(os.path.join(ROOT, t["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if t.get("workload") != workload_key or hashlib.sha256(src).hexdigest() != t.get("source_sha256"):
+        return None
+    return t
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,8 +180,13 @@ def main():
         slots = sum(prof_asm[f][2] * (ASM_LANE_OPS_PER_PP[f] + ASM_TRANS_PER_PP * (TRANS_SLOTS - 1)) for f in forms)
         issue = slots / (asm_ms * 1e-3) if asm_ms > 0 else 0.0
         nasm = sum(prof_asm[f][0] for f in forms)
+        tr = measured_traffic("sphere20480") if (a.workload == "sphere" and dtype == "f32") else None
+        traffic = None
+        if tr and nasm > 0:
+            traffic = round(sum(tr["assembly_bytes"][str(f)] * prof_asm[f][0] for f in forms) / nasm, 1)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[dtype], 4), "traffic": None, "kernel": "k_assemble",
+                "frac": round(achieved / PEAK_TFLOPS[dtype], 4), "traffic": traffic,
+                "kernel": "far-field assembly (k_fill x2, k_assemble_tile x80, k_sym_finish x4 per assembly)",
                 "launches": nasm, "avg_launch_ms": round(asm_ms / max(nasm, 1), 4),
                 "point_pair_evals_per_s": round(evals / (asm_ms * 1e-3), 1) if asm_ms > 0 else None,
                 "valu_issue": {"slots_per_s": round(issue, 1), "peak_slots_per_s": VALU_SLOTS_PER_S,
