@@ -54,8 +54,20 @@ typedef int32_t pb_status;
 #define PB_E_STATE        (-6) /* call not valid for this handle's configuration */
 
 /* ------------------------------------------------------------------ options */
-#define PB_DIRECT_INT   0  /* Eq. bie:dirichlet:int: [[M/2+K_L, -V_L], [M/2-K_Y, (e_in/e_out) V_Y]] */
+/* Formulations (e = e_in/e_out; L, Y = Laplace, Yukawa kernels; unknowns are the
+ * interior traces (gamma_D^- phi, gamma_N^- phi) unless marked exterior, in which
+ * case the solver converts the exterior traces to interior ones,
+ * gamma_N^- = (e_out/e_in) gamma_N^+, before Delta G and before returning them). */
+#define PB_DIRECT_INT   0  /* Eq. bie:dirichlet:int: [[M/2+K_L, -V_L], [M/2-K_Y, e V_Y]] */
 #define PB_JUFFER       1  /* Eq. bie:juffer:int: second-kind, uses all four operators */
+#define PB_DIRECT_EXT   2  /* Eq. bie:dirichlet:ext (exterior): [[M/2-K_Y, V_Y], [M/2+K_L, -V_L/e]] */
+#define PB_DIRECT_INT_PERM 3  /* Eq. bie:dirichlet:int with its rows swapped */
+#define PB_DIRECT_EXT_PERM 4  /* Eq. bie:dirichlet:ext with its rows swapped (exterior) */
+#define PB_MULLER_INT   5  /* Eq. bie:muller:int: second-kind */
+#define PB_MULLER_EXT   6  /* Eq. bie:muller:ext: second-kind (exterior) */
+#define PB_LU           7  /* Eq. bie:lu:ext: second-kind (exterior) */
+#define PB_PMCHWT_INT   8  /* Eq. bie:pmchwt:int: first-kind */
+#define PB_PMCHWT_EXT   9  /* Eq. bie:pmchwt:ext: first-kind (exterior) */
 
 #define PB_PREC_NONE    0
 #define PB_BLOCK_DIAG   1  /* per-vertex 2x2 inverse of the four blocks' diagonals */

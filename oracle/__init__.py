@@ -11,8 +11,9 @@ mass-matrix preconditioner, runs unrestarted GMRES (modified Gram-Schmidt, Given
 rotations) and evaluates the solvation energy.
 
 Citations are to Search, Cooper & van 't Wout, arXiv 2108.10481:
-  * internal direct formulation ........ Eq. bie:dirichlet:int
-  * Juffer formulation .................. Eq. bie:juffer:int
+  * internal / external direct ......... Eqs. bie:dirichlet:int, bie:dirichlet:ext
+  * Juffer, Lu formulations ............. Eqs. bie:juffer:int, bie:lu:ext
+  * Mueller, PMCHWT formulations ........ Eqs. bie:muller:int/ext, bie:pmchwt:int/ext
   * source projections .................. Eq. sources
   * reaction potential, energy .......... Eqs. phireac_bie and dG
   * block-diagonal preconditioner ....... Preconditioning / Algebraic preconditioners
@@ -37,8 +38,21 @@ SRC_PATH = os.path.join(HERE, "pbm_oracle.c")
 COULOMB_KCAL = 332.0637
 ENERGY_C = 4.0 * math.pi * COULOMB_KCAL
 
-DIRECT = 0
-JUFFER = 1
+DIRECT = 0            # internal direct, Eq. bie:dirichlet:int
+JUFFER = 1            # Eq. bie:juffer:int
+DIRECT_EXT = 2        # external direct, Eq. bie:dirichlet:ext
+DIRECT_INT_PERM = 3   # Eq. bie:dirichlet:int with its two rows swapped ("permuted")
+DIRECT_EXT_PERM = 4   # Eq. bie:dirichlet:ext with its two rows swapped
+MULLER_INT = 5        # Eq. bie:muller:int
+MULLER_EXT = 6        # Eq. bie:muller:ext
+LU = 7                # Eq. bie:lu:ext
+PMCHWT_INT = 8        # Eq. bie:pmchwt:int
+PMCHWT_EXT = 9        # Eq. bie:pmchwt:ext
+FORMULATIONS = tuple(range(10))
+#: formulations whose unknowns are the exterior traces (gamma_D^+, gamma_N^+)
+EXTERIOR = (DIRECT_EXT, DIRECT_EXT_PERM, MULLER_EXT, LU, PMCHWT_EXT)
+#: formulations with only single- and double-layer operators
+DIRECT_FAMILY = (DIRECT, DIRECT_EXT, DIRECT_INT_PERM, DIRECT_EXT_PERM)
 
 
 def build(force: bool = False) -> str:
@@ -177,33 +191,81 @@ def solvation_energy(mesh, charges, phi, dphi):
 
 # ------------------------------------------------------------ formulations
 def system_blocks(ops_L, ops_Y, M, eps_in, eps_out, formulation):
-    """2x2 block system of the chosen formulation, Galerkin form.
+    """2x2 block system of the chosen formulation, Galerkin form, typed in as
+    the paper prints it.
 
-    ops_L / ops_Y hold V, K and (for Juffer) D and T of the Laplace ("int")
-    and Yukawa ("ext") kernels; the identity becomes the mass matrix M.
+    ops_L / ops_Y hold V, K and (second-kind and PMCHWT formulations) D and T
+    of the Laplace ("int") and Yukawa ("ext") kernels; the identity becomes
+    the mass matrix M.  e = eps_in / eps_out.
     """
+    e = eps_in / eps_out
+    L, Y = ops_L, ops_Y
     if formulation == DIRECT:                       # Eq. bie:dirichlet:int
-        A11 = 0.5 * M + ops_L["K"]
-        A12 = -ops_L["V"]
-        A21 = 0.5 * M - ops_Y["K"]
-        A22 = (eps_in / eps_out) * ops_Y["V"]
+        A11 = 0.5 * M + L["K"]
+        A12 = -L["V"]
+        A21 = 0.5 * M - Y["K"]
+        A22 = e * Y["V"]
+    elif formulation == DIRECT_EXT:                 # Eq. bie:dirichlet:ext
+        A11 = 0.5 * M - Y["K"]
+        A12 = Y["V"]
+        A21 = 0.5 * M + L["K"]
+        A22 = -(1.0 / e) * L["V"]
+    elif formulation == DIRECT_INT_PERM:            # rows of Eq. bie:dirichlet:int swapped
+        A11 = 0.5 * M - Y["K"]
+        A12 = e * Y["V"]
+        A21 = 0.5 * M + L["K"]
+        A22 = -L["V"]
+    elif formulation == DIRECT_EXT_PERM:            # rows of Eq. bie:dirichlet:ext swapped
+        A11 = 0.5 * M + L["K"]
+        A12 = -(1.0 / e) * L["V"]
+        A21 = 0.5 * M - Y["K"]
+        A22 = Y["V"]
     elif formulation == JUFFER:                     # Eq. bie:juffer:int
         a = eps_out / eps_in
         b = eps_in / eps_out
-        A11 = 0.5 * (1.0 + a) * M + ops_L["K"] - a * ops_Y["K"]
-        A12 = -ops_L["V"] + ops_Y["V"]
-        A21 = -ops_L["D"] + ops_Y["D"]
-        A22 = 0.5 * (1.0 + b) * M - ops_L["T"] + b * ops_Y["T"]
+        A11 = 0.5 * (1.0 + a) * M + L["K"] - a * Y["K"]
+        A12 = -L["V"] + Y["V"]
+        A21 = -L["D"] + Y["D"]
+        A22 = 0.5 * (1.0 + b) * M - L["T"] + b * Y["T"]
+    elif formulation == MULLER_INT:                 # Eq. bie:muller:int
+        A11 = M + L["K"] - Y["K"]
+        A12 = -L["V"] + e * Y["V"]
+        A21 = -L["D"] + (1.0 / e) * Y["D"]
+        A22 = M - L["T"] + Y["T"]
+    elif formulation == MULLER_EXT:                 # Eq. bie:muller:ext
+        A11 = M - Y["K"] + L["K"]
+        A12 = Y["V"] - (1.0 / e) * L["V"]
+        A21 = Y["D"] - e * L["D"]
+        A22 = M + Y["T"] - L["T"]
+    elif formulation == LU:                         # Eq. bie:lu:ext
+        A11 = 0.5 * (1.0 + e) * M - Y["K"] + e * L["K"]
+        A12 = Y["V"] - L["V"]
+        A21 = e * Y["D"] - e * L["D"]
+        A22 = 0.5 * (1.0 + e) * M + e * Y["T"] - L["T"]
+    elif formulation == PMCHWT_INT:                 # Eq. bie:pmchwt:int
+        A11 = -L["K"] - Y["K"]
+        A12 = L["V"] + e * Y["V"]
+        A21 = L["D"] + (1.0 / e) * Y["D"]
+        A22 = L["T"] + Y["T"]
+    elif formulation == PMCHWT_EXT:                 # Eq. bie:pmchwt:ext
+        A11 = -Y["K"] - L["K"]
+        A12 = Y["V"] + (1.0 / e) * L["V"]
+        A21 = Y["D"] + e * L["D"]
+        A22 = Y["T"] + L["T"]
     else:
         raise ValueError(formulation)
     return A11, A12, A21, A22
 
 
+def _want(formulation):
+    return ("V", "K") if formulation in DIRECT_FAMILY else ("V", "K", "D")
+
+
 def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4):
-    want = ("V", "K") if formulation == DIRECT else ("V", "K", "D")
+    want = _want(formulation)
     oL = assemble(mesh, 0.0, want, nss)
     oY = assemble(mesh, kappa, want, nss)
-    if formulation == JUFFER:
+    if "D" in want:
         oL["T"] = oL["K"].T.copy()                  # adjoint double layer as K^T
         oY["T"] = oY["K"].T.copy()
     M = mass(mesh)
@@ -211,10 +273,25 @@ def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4):
     return np.block([[A11, A12], [A21, A22]])
 
 
-def system_rhs(bD, bN, formulation):
-    if formulation == DIRECT:
-        return np.concatenate([bD, np.zeros_like(bD)])
-    return np.concatenate([bD, bN])
+def system_rhs(bD, bN, formulation, eps_in: float = 4.0, eps_out: float = 80.0):
+    """Right-hand side of the formulation from the source projections
+    <phi_i, varphi_D>, <phi_i, varphi_N> (Eq. sources), as printed."""
+    e = eps_in / eps_out
+    z = np.zeros_like(bD)
+    rhs = {DIRECT: (bD, z), DIRECT_EXT: (z, bD), DIRECT_INT_PERM: (z, bD), DIRECT_EXT_PERM: (bD, z),
+           JUFFER: (bD, bN), MULLER_INT: (bD, bN), MULLER_EXT: (bD, e * bN), LU: (e * bD, e * bN),
+           PMCHWT_INT: (-bD, -bN), PMCHWT_EXT: (-bD, -e * bN)}[formulation]
+    return np.concatenate(rhs)
+
+
+def interior_traces(u, nv, formulation, eps_in: float = 4.0, eps_out: float = 80.0):
+    """(gamma_D^- phi, gamma_N^- phi) from a solution vector: exterior traces
+    give the interior ones by the interface conditions (potential continuous,
+    eps_in gamma_N^- = eps_out gamma_N^+)."""
+    phi, dphi = u[:nv], u[nv:]
+    if formulation in EXTERIOR:
+        dphi = (eps_out / eps_in) * dphi
+    return phi, dphi
 
 
 def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4):
@@ -222,10 +299,10 @@ def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4
     rows = np.asarray(rows, dtype=np.int32)
     nv = mesh.n_vertices
     x1, x2 = x[:nv], x[nv:]
-    want = ("V", "K") if formulation == DIRECT else ("V", "K", "D")
+    want = _want(formulation)
     oL = operator_rows(mesh, 0.0, rows, 0, want, nss)
     oY = operator_rows(mesh, kappa, rows, 0, want, nss)
-    if formulation == JUFFER:
+    if "D" in want:
         oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss)["K"]
         oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss)["K"]
     M = mass_rows(mesh, rows)
@@ -335,7 +412,7 @@ def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRE
     if A is None:
         A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss)
     bD, bN = rhs(mesh, charges, eps_in)
-    b = system_rhs(bD, bN, formulation)
+    b = system_rhs(bD, bN, formulation, eps_in, eps_out)
     if preconditioner is True or preconditioner == "block_diag":
         inv = block_diagonal_inverse(A, nv)
         P = lambda v: apply_block_diag(inv, v)
@@ -349,7 +426,7 @@ def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRE
     pb = P(b)
     u, its, hist = gmres(lambda v: P(A @ v), pb, tol, max_iter)
     res = float(np.linalg.norm(pb - P(A @ u)) / np.linalg.norm(pb))
-    phi, dphi = u[:nv], u[nv:]
+    phi, dphi = interior_traces(u, nv, formulation, eps_in, eps_out)
     dG = solvation_energy(mesh, charges, phi, dphi)
     return {"phi": phi, "dphi": dphi, "dG": dG, "iterations": its, "rel_residual": res,
             "history": hist, "A": A, "b": b}

@@ -26,6 +26,14 @@ PB_E_STATE = -6
 
 PB_DIRECT_INT = 0
 PB_JUFFER = 1
+PB_DIRECT_EXT = 2
+PB_DIRECT_INT_PERM = 3
+PB_DIRECT_EXT_PERM = 4
+PB_MULLER_INT = 5
+PB_MULLER_EXT = 6
+PB_LU = 7
+PB_PMCHWT_INT = 8
+PB_PMCHWT_EXT = 9
 PB_PREC_NONE = 0
 PB_BLOCK_DIAG = 1
 PB_MASS = 2

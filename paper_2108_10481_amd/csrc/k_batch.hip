@@ -415,9 +415,7 @@ pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result 
         for (int s = 0; s < nb; ++s) {
             charges_to_device(d, &sets[c0 + s]);
             check_charges_inside(d, sets[c0 + s].n);
-            launch_rhs(d, sets[c0 + s].n, d.qbuf, w.B + (size_t)s * n);
-            if (d.prm.formulation == PB_DIRECT_INT)
-                HIPCHECK(hipMemsetAsync(w.B + (size_t)s * n + V, 0, sizeof(double) * V, st));
+            formulation_rhs(d, sets[c0 + s].n, d.qbuf, w.B + (size_t)s * n);
         }
         HIPCHECK(hipStreamSynchronize(st));
         const double t1 = now_s();

@@ -57,7 +57,11 @@ static void color_triangles(const HostMesh &hm, std::vector<int32_t> &ptr, std::
 // ------------------------------------------------------------- assembly
 template <typename R>
 struct AsmCoef {
-    R kappa, kexp, c1, c2, k2;
+    R kappa, kexp, k2;
+    // block (r, c) = aL[r][c] Op_L + aY[r][c] Op_Y (far field: no mass term)
+    R aL[2][2], aY[2][2];
+    // FORM 1: ratios aY / aL of the K, V, D and T blocks (aL != 0 there)
+    R rK, rV, rD, rT;
 };
 
 __device__ __forceinline__ float rsq_a(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -207,8 +211,8 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                 const R ekk = ek * (cf.kappa * r + R(1));
                 R v[NV];
                 if (FORM == 0) {
-                    // F_L d.n_s, G_L, F_Y d.n_s, G_Y without the factors 1, -1, -1, eps;
-                    // swapped pair: F_L d.n_t, F_Y d.n_t
+                    // the four operators' kernels F_L d.n_s, G_L, F_Y d.n_s, G_Y (combined
+                    // per block after the contraction); swapped pair: F_L d.n_t, F_Y d.n_t
                     v[0] = ri3 * dns;
                     v[1] = ri;
                     v[2] = ekk * v[0];
@@ -218,12 +222,14 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                         v[5] = ekk * v[4];
                     }
                 } else {
+                    // (F_L + rK F_Y) d.n_s, G_L + rV G_Y, G_Y, (F_L + rT F_Y) d.n_t, without the
+                    // factors aL; swapped pair: K with d.n_t, T with d.n_s
                     const R fy = ekk * ri3;
                     const R gy = ek * ri;
-                    const R a1 = ri3 - cf.c1 * fy, a2 = ri3 - cf.c2 * fy;
+                    const R a1 = ri3 + cf.rK * fy, a2 = ri3 + cf.rT * fy;
                     const R dnt = ts[21 + p] - ynt;
                     v[0] = a1 * dns;
-                    v[1] = gy - ri;
+                    v[1] = ri + cf.rV * gy;
                     v[2] = gy;
                     v[3] = a2 * dnt;
                     if (SYM) {
@@ -248,7 +254,10 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
 #pragma unroll
                 for (int k = 0; k < 3; ++k) X[k][o] += cc;
             }
-            if (FORM == 1) Ssum += R(rule_w(q)) * (R(kRuleWA) * SA[1] + R(kRuleWB) * SB[1]);
+            // D's curl part integrates G_L + rD G_Y = v1 + (rD - rV) v2
+            if (FORM == 1)
+                Ssum += R(rule_w(q)) * ((R(kRuleWA) * SA[1] + R(kRuleWB) * SB[1]) +
+                                        (cf.rD - cf.rV) * (R(kRuleWA) * SA[2] + R(kRuleWB) * SB[2]));
             const R wc = q < 3 ? al : be;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -268,14 +277,16 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
 
         const R sc = ts[27] * sarea * (R)kInv4Pi;
         const R sw = sc * (R)(RuleOrbit::cA * RuleOrbit::cA);
+        // FORM 1 factors (FORM 0 combines the four kernels per block below).  The
+        // double-layer kernel is +F d.n_y, the adjoint one -F d.n_x, with d the
+        // test point minus the trial point; for the swapped pair d changes sign.
         R f[NV];
-        if (FORM == 0) {
-            f[0] = sw; f[1] = -sw; f[2] = -sw; f[3] = sw * cf.c1;
-            if (SYM) { f[4] = -sw; f[5] = sw; }
-        } else {
-            f[0] = f[1] = f[3] = sw;
-            f[2] = sw * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
-            if (SYM) { f[4] = -sw; f[5] = -sw; }
+        if (FORM == 1) {
+            f[0] = sw * cf.aL[0][0];
+            f[1] = sw * cf.aL[0][1];
+            f[2] = sw * cf.aY[1][0] * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
+            f[3] = -sw * cf.aL[1][1];
+            if (SYM) { f[4] = -sw * cf.aL[0][0]; f[5] = sw * cf.aL[1][1]; }
         }
         if (g > gbeg) __syncthreads();   // the previous target's phase 2 is done with lds
 #pragma unroll
@@ -283,13 +294,25 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 R val[NV];
+                if (FORM == 0) {
+                    const R *B = blk[l][k];
+                    val[0] = sw * (cf.aL[0][0] * B[0] + cf.aY[0][0] * B[2]);
+                    val[1] = sw * (cf.aL[0][1] * B[1] + cf.aY[0][1] * B[3]);
+                    val[2] = sw * (cf.aL[1][0] * B[0] + cf.aY[1][0] * B[2]);
+                    val[3] = sw * (cf.aL[1][1] * B[1] + cf.aY[1][1] * B[3]);
+                    if (SYM) {
+                        val[4] = -sw * (cf.aL[0][0] * B[4] + cf.aY[0][0] * B[5]);
+                        val[5] = -sw * (cf.aL[1][0] * B[4] + cf.aY[1][0] * B[5]);
+                    }
+                } else {
 #pragma unroll
-                for (int o = 0; o < NV; ++o) val[o] = blk[l][k][o] * f[o];
+                    for (int o = 0; o < NV; ++o) val[o] = blk[l][k][o] * f[o];
+                }
                 if (FORM == 1) {
                     // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
                     const R cc = ts[28 + 3 * k] * ss[28 + 3 * l] + ts[29 + 3 * k] * ss[29 + 3 * l] +
                                  ts[30 + 3 * k] * ss[30 + 3 * l];
-                    val[2] += sc * cc * Ssum;
+                    val[2] += sc * cf.aL[1][0] * cc * Ssum;
                 }
                 // a pair sharing a vertex may have produced inf or NaN: select, not scale
                 Quad<R> qd;
@@ -762,10 +785,22 @@ static void assemble(DevMesh &d, S *A)
     const double kap = d.prm.kappa;
     cf.kappa = (R)kap;
     cf.kexp = sizeof(R) == 4 ? (R)(kap * 1.4426950408889634) : (R)kap;
-    const bool direct = d.prm.formulation == PB_DIRECT_INT;
-    cf.c1 = (R)(direct ? d.prm.eps_in / d.prm.eps_out : d.prm.eps_out / d.prm.eps_in);
-    cf.c2 = (R)(d.prm.eps_in / d.prm.eps_out);
     cf.k2 = (R)(kap * kap);
+    const FormCoef &fm = d.fm;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) { cf.aL[r][c] = (R)fm.aL[r][c]; cf.aY[r][c] = (R)fm.aY[r][c]; }
+    const bool direct = fm.family == 0;   // FORM 0: K and V rows; FORM 1: K, V / D, T
+    if (!direct) {
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c)
+                if (fm.aL[r][c] == 0.0) fail(PB_E_STATE, "formulation without a Laplace term in a block");
+        cf.rK = (R)(fm.aY[0][0] / fm.aL[0][0]);
+        cf.rV = (R)(fm.aY[0][1] / fm.aL[0][1]);
+        cf.rD = (R)(fm.aY[1][0] / fm.aL[1][0]);
+        cf.rT = (R)(fm.aY[1][1] / fm.aL[1][1]);
+    } else {
+        cf.rK = cf.rV = cf.rD = cf.rT = R(0);
+    }
     const R *stat = sizeof(R) == 4 ? (const R *)d.stat32 : (const R *)d.stat64;
     const size_t total = (size_t)D.n * D.ld;
     hipLaunchKernelGGL(k_fill<S>, dim3(4096), dim3(256), 0, d.stream, total, A);

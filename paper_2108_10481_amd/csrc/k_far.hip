@@ -83,21 +83,27 @@ template <typename R>
 struct FarCoef {
     R kappa;   // screening
     R kexp;    // argument scale for expneg
-    R c1;      // direct: eps_in/eps_out       Juffer: alpha = eps_out/eps_in
-    R c2;      // Juffer: beta = eps_in/eps_out
-    R k2;      // Juffer: kappa^2
+    R k2;      // kappa^2
+    // FORM 0: coefficients of the Laplace row (kL K_L + vL V_L) and of the
+    // Yukawa row (kY K_Y + vY V_Y)
+    R kL, vL, kY, vY;
+    // FORM 1, 2: factors aL of the K and V blocks, -aL of the T block, aY of D's
+    // kappa^2 term; ratios aY / aL of the K, V, D, T blocks
+    R aK, aV, aT, aDY, rK, rV, rD, rT;
 };
 
 constexpr int kFarBlock = 256;
 
-// FORM 0: internal direct.  Per target point p accumulates (no 1/4pi)
-//   a1 += F_L (d.n_s) b1 - G_L b2                 (K_L u1 - V_L u2)
-//   a2 += -F_Y (d.n_s) b1 + c1 G_Y b2             (-K_Y u1 + eps V_Y u2)
-// FORM 1: Juffer.
-//   a1 += (F_L - alpha F_Y)(d.n_s) b1 + (G_Y - G_L) b2
-//   a2 += (F_L - beta F_Y)(d.n_t) b2 + kappa^2 (n_t.n_s) G_Y b1
+// FORM 0: direct formulations (one row Laplace, the other Yukawa).  Per target
+// point p accumulates (no 1/4pi)
+//   a1 += kL F_L (d.n_s) b1 + vL G_L b2                (Laplace row)
+//   a2 += kY F_Y (d.n_s) b1 + vY G_Y b2                (Yukawa row)
+// FORM 1, 2: second-kind and PMCHWT formulations.
+//   a1 += aK (F_L + rK F_Y)(d.n_s) b1 + aV (G_L + rV G_Y) b2
+//   a2 += aT (F_L + rT F_Y)(d.n_t) b2 + aDY kappa^2 (n_t.n_s) G_Y b1   (aT = -aL of T)
 //   and the hypersingular curl part, per source triangle:
-//   W  += [sum_pq w_p w_q (G_Y - G_L)] C_s
+//   W  += [sum_pq w_p w_q (G_L + rD G_Y)] C_s     (times aD_L in k_far_finish)
+//   (FORM 1: rD = rV, the V sum is reused)
 // with d = x_p - y_q, G = e/r, F = e (1 + kappa r)/r^3 (e = 1 for Laplace).
 template <typename R, int FORM>
 __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> cf, const int32_t *__restrict__ tri,
@@ -134,14 +140,15 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
 #pragma unroll
         for (int p = 0; p < 6; ++p) xns[p] = tx[p] * nsx + ty[p] * nsy + tz[p] * nsz;
         R g = 0, k2nn = 0;
-        if (FORM == 1) k2nn = cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
+        if (FORM >= 1) k2nn = cf.aDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const R yx = st[3 * q], yy = st[3 * q + 1], yz = st[3 * q + 2];
             const R yns = st[21 + q];
             const R b1 = sd[q], b2 = sd[6 + q];
-            R ynt = 0, kb1 = 0;
-            if (FORM == 1) { ynt = yx * ntx + yy * nty + yz * ntz; kb1 = k2nn * b1; }
+            R ynt = 0, kb1 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+            if (FORM == 0) { c1 = cf.kL * b1; c2 = cf.vL * b2; c3 = cf.kY * b1; c4 = cf.vY * b2; }
+            else { ynt = yx * ntx + yy * nty + yz * ntz; kb1 = k2nn * b1; c1 = cf.aK * b1; c2 = cf.aV * b2; c3 = cf.aT * b2; }
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
@@ -154,21 +161,20 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
                 const R tt = cf.kappa * r + R(1);
                 if (FORM == 0) {
                     const R fl = dns * ri3;
-                    const R rb2 = ri * b2;
-                    a1[p] += fl * b1 - rb2;
-                    a2[p] += e * (cf.c1 * rb2 - fl * tt * b1);
+                    a1[p] += fl * c1 + ri * c2;
+                    a2[p] += e * (fl * tt * c3 + ri * c4);
                 } else {
                     const R fy = e * tt * ri3;
                     const R gy = e * ri;
-                    const R dg = gy - ri;
+                    const R gv = ri + cf.rV * gy;
                     const R dnt = xnt[p] - ynt;
-                    a1[p] += (ri3 - cf.c1 * fy) * dns * b1 + dg * b2;
-                    a2[p] += (ri3 - cf.c2 * fy) * dnt * b2 + kb1 * gy;
-                    g += R(rule_w(p) * rule_w(q)) * dg;
+                    a1[p] += (ri3 + cf.rK * fy) * dns * c1 + gv * c2;
+                    a2[p] += (ri3 + cf.rT * fy) * dnt * c3 + kb1 * gy;
+                    g += R(rule_w(p) * rule_w(q)) * (FORM == 1 ? gv : ri + cf.rD * gy);
                 }
             }
         }
-        if (FORM == 1) {
+        if (FORM >= 1) {
             W0 += g * sd[12];
             W1 += g * sd[13];
             W2 += g * sd[14];
@@ -180,9 +186,11 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
     o[12] = W0; o[13] = W1; o[14] = W2; o[15] = 0;
 }
 
+// family 0: rows (Laplace, Yukawa), swapped when the Laplace row is row 2;
+// family 1: row 2 gets D's curl part times aDL
 template <typename R>
-__global__ void k_far_finish(int T, int S, int form, const double *__restrict__ geo, const R *__restrict__ part,
-                             double *__restrict__ triout, DevCtl ctl)
+__global__ void k_far_finish(int T, int S, int family, int swap, double aDL, const double *__restrict__ geo,
+                             const R *__restrict__ part, double *__restrict__ triout, DevCtl ctl)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T || ctl_skip(ctl)) return;
@@ -202,8 +210,9 @@ __global__ void k_far_finish(int T, int S, int form, const double *__restrict__ 
             y1 += w * pot[p];
             y2 += w * pot[6 + p];
         }
-        if (form == PB_JUFFER)
-            y2 += g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14];
+        if (family == 1)
+            y2 += aDL * (g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14]);
+        if (swap) { const double tmp = y1; y1 = y2; y2 = tmp; }
         triout[6 * (size_t)t + k] = sc * y1;
         triout[6 * (size_t)t + 3 + k] = sc * y2;
     }
@@ -265,6 +274,16 @@ int choose_chunks(int T)
     return S;
 }
 
+// direct formulations: one row has only Laplace, the other only Yukawa terms
+static int far_laplace_row(const FormCoef &f)
+{
+    const bool r0L = f.aY[0][0] == 0.0 && f.aY[0][1] == 0.0;
+    const bool r1Y = f.aL[1][0] == 0.0 && f.aL[1][1] == 0.0;
+    if (r0L && r1Y) return 0;
+    if (f.aL[0][0] == 0.0 && f.aL[0][1] == 0.0 && f.aY[1][0] == 0.0 && f.aY[1][1] == 0.0) return 1;
+    fail(PB_E_STATE, "direct formulation with mixed kernels in one row");
+}
+
 template <typename R>
 static void far_launch(DevMesh &d, const R *stat, const R *dyn)
 {
@@ -274,16 +293,31 @@ static void far_launch(DevMesh &d, const R *stat, const R *dyn)
     const double kap = d.prm.kappa;
     cf.kappa = (R)kap;
     cf.kexp = (sizeof(R) == 4) ? (R)(kap * 1.4426950408889634) : (R)kap;
-    const bool direct = d.prm.formulation == PB_DIRECT_INT;
-    cf.c1 = (R)(direct ? d.prm.eps_in / d.prm.eps_out : d.prm.eps_out / d.prm.eps_in);
-    cf.c2 = (R)(d.prm.eps_in / d.prm.eps_out);
     cf.k2 = (R)(kap * kap);
+    const FormCoef &f = d.fm;
+    int form = 0;
+    if (f.family == 0) {
+        const int lr = far_laplace_row(f);
+        cf.kL = (R)f.aL[lr][0]; cf.vL = (R)f.aL[lr][1];
+        cf.kY = (R)f.aY[1 - lr][0]; cf.vY = (R)f.aY[1 - lr][1];
+    } else {
+        // the adjoint double layer's kernel is -F d.n_t: its factor carries the sign
+        cf.aK = (R)f.aL[0][0]; cf.aV = (R)f.aL[0][1]; cf.aT = (R)(-f.aL[1][1]); cf.aDY = (R)f.aY[1][0];
+        const double rV = f.aY[0][1] / f.aL[0][1], rD = f.aY[1][0] / f.aL[1][0];
+        cf.rK = (R)(f.aY[0][0] / f.aL[0][0]);
+        cf.rV = (R)rV;
+        cf.rD = (R)rD;
+        cf.rT = (R)(f.aY[1][1] / f.aL[1][1]);
+        form = rD == rV ? 1 : 2;
+    }
     dim3 grid((T + kFarBlock - 1) / kFarBlock, S), block(kFarBlock);
     R *part = (R *)d.part;
-    if (direct)
+    if (form == 0)
         hipLaunchKernelGGL((k_far<R, 0>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
-    else
+    else if (form == 1)
         hipLaunchKernelGGL((k_far<R, 1>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
+    else
+        hipLaunchKernelGGL((k_far<R, 2>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     HIPCHECK(hipGetLastError());
 }
 
@@ -309,11 +343,14 @@ void launch_far_finish(DevMesh &d, bool fp32)
 {
     const int T = d.hm.T;
     dim3 grid((T + 255) / 256), block(256);
+    const FormCoef &f = d.fm;
+    const int swap = f.family == 0 && far_laplace_row(f) == 1;
+    const double aDL = f.family == 1 ? f.aL[1][0] : 0.0;
     if (fp32)
-        hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, d.prm.formulation, d.geo,
+        hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, f.family, swap, aDL, d.geo,
                            (const float *)d.part, d.triout, d.ctl);
     else
-        hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, d.prm.formulation, d.geo,
+        hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, f.family, swap, aDL, d.geo,
                            (const double *)d.part, d.triout, d.ctl);
     HIPCHECK(hipGetLastError());
 }

@@ -141,6 +141,26 @@ void launch_rhs(DevMesh &d, int nq, const double *qbuf, double *b)
     HIPCHECK(hipGetLastError());
 }
 
+// right-hand side of the formulation from [<phi_i, varphi_D>; <phi_i, varphi_N>], in place
+__global__ void k_rhs_combine(int V, double d1, double n1, double d2, double n2, double *__restrict__ b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    const double bD = b[i], bN = b[V + i];
+    b[i] = d1 * bD + n1 * bN;
+    b[V + i] = d2 * bD + n2 * bN;
+}
+
+void formulation_rhs(DevMesh &d, int nq, const double *qbuf, double *b)
+{
+    launch_rhs(d, nq, qbuf, b);
+    const FormCoef &f = d.fm;
+    const int V = d.hm.V;
+    hipLaunchKernelGGL(k_rhs_combine, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, f.rhsD[0], f.rhsN[0],
+                       f.rhsD[1], f.rhsN[1], b);
+    HIPCHECK(hipGetLastError());
+}
+
 // --------------------------------------------------------- reaction potential
 // grid (point k, source chunk c); each block sums, over its chunk of source
 // triangles, G(x_k, y) b2 - dG/dn_y(x_k, y) b1 with the Laplace kernel (no 4 pi),

@@ -265,9 +265,8 @@ void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const
 // s containing j as local vertex l); the slot is owned by one thread, so there
 // is no atomic and the result is deterministic.
 struct NearCoef {
-    int form;
-    double kappa, ceps;        // direct: eps_in / eps_out
-    double alpha, beta;        // Juffer: eps_out / eps_in, eps_in / eps_out
+    double kappa;
+    FormCoef f;                // the formulation's block coefficients
 };
 
 // per pair: sum of its 3 x 3 V_L and V_Y entries (the hypersingular curl part)
@@ -301,24 +300,25 @@ __global__ void k_near_slots(int64_t nnz, NearCoef cf, const int32_t *__restrict
         const double vY = B[18 + 3 * k + l], kY = B[27 + 3 * k + l];
         const double mss = (s == t) ? gt[21] / 12.0 * (k == l ? 2.0 : 1.0) : 0.0;
         mass += mss;
-        if (cf.form == PB_DIRECT_INT) {          // Eq. bie:dirichlet:int
-            n11 += 0.5 * mss + kL;
-            n12 += -vL;
-            n21 += 0.5 * mss - kY;
-            n22 += cf.ceps * vY;
-        } else {                                  // Eq. bie:juffer:int
+        const FormCoef &f = cf.f;
+        // row 1: K and V (Dirichlet trace equations)
+        n11 += f.mass[0][0] * mss + f.aL[0][0] * kL + f.aY[0][0] * kY;
+        n12 += f.mass[0][1] * mss + f.aL[0][1] * vL + f.aY[0][1] * vY;
+        if (f.family == 0) {
+            n21 += f.mass[1][0] * mss + f.aL[1][0] * kL + f.aY[1][0] * kY;
+            n22 += f.mass[1][1] * mss + f.aL[1][1] * vL + f.aY[1][1] * vY;
+        } else {                                  // row 2: D and T (Neumann trace equations)
             const double *gs = geo + (size_t)s * kGeo;
             const double *R = blk + (size_t)pair_rev[p] * 36;
             const double nn = gt[18] * gs[18] + gt[19] * gs[19] + gt[20] * gs[20];
             const double cc = gt[22 + 3 * k] * gs[22 + 3 * l] + gt[23 + 3 * k] * gs[23 + 3 * l] +
                               gt[24 + 3 * k] * gs[24 + 3 * l];
+            // D: curl_k . curl_l V + kappa^2 (n_t . n_s) V, by parts; T = K^T
             const double dL = cc * sums[2 * (size_t)p];
             const double dY = cc * sums[2 * (size_t)p + 1] + cf.kappa * cf.kappa * nn * vY;
-            const double tL = R[9 + 3 * l + k], tY = R[27 + 3 * l + k];   // T = K^T
-            n11 += 0.5 * (1.0 + cf.alpha) * mss + kL - cf.alpha * kY;
-            n12 += -vL + vY;
-            n21 += -dL + dY;
-            n22 += 0.5 * (1.0 + cf.beta) * mss - tL + cf.beta * tY;
+            const double tL = R[9 + 3 * l + k], tY = R[27 + 3 * l + k];
+            n21 += f.mass[1][0] * mss + f.aL[1][0] * dL + f.aY[1][0] * dY;
+            n22 += f.mass[1][1] * mss + f.aL[1][1] * tL + f.aY[1][1] * tY;
         }
     }
     N[slot] = n11;
@@ -435,14 +435,11 @@ void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const Dev
 void launch_near_assemble(DevMesh &d)
 {
     NearCoef cf;
-    cf.form = d.prm.formulation;
     cf.kappa = d.prm.kappa;
-    cf.ceps = d.prm.eps_in / d.prm.eps_out;
-    cf.alpha = d.prm.eps_out / d.prm.eps_in;
-    cf.beta = d.prm.eps_in / d.prm.eps_out;
+    cf.f = d.fm;
     const int V = d.hm.V;
     const int64_t np = d.npair(), nnz = d.nnz();
-    if (cf.form != PB_DIRECT_INT)
+    if (cf.f.family == 1)
         hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, d.stream, np, d.pairblk,
                            d.pair_sums);
     hipLaunchKernelGGL(k_near_slots, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, d.stream, nnz, cf,

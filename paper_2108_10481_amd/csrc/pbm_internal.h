@@ -104,6 +104,24 @@ struct Params {
     int formulation, preconditioner, precision, operator_mode;
 };
 
+// A formulation's Galerkin block system as combinations of the Laplace (L)
+// and Yukawa (Y) operators.  Every formulation of the paper takes, for each
+// output row, c_I times an interior trace equation plus c_E times an exterior
+// one (Eqs. bie, bie:ext:int, bie:int:ext, with interior or exterior traces as
+// unknowns): rows of kind 1 (Dirichlet trace equations) use K in column 1 and
+// V in column 2, rows of kind 2 (Neumann trace equations) D and T.
+//   family 0: both rows of kind 1 (direct formulations, permuted or not);
+//   family 1: row 1 of kind 1, row 2 of kind 2 (Juffer, Mueller, Lu, PMCHWT).
+// block (r, c) = mass[r][c] M + aL[r][c] Op_L + aY[r][c] Op_Y, and the
+// right-hand side row r = rhsD[r] <phi_i, varphi_D> + rhsN[r] <phi_i, varphi_N>.
+struct FormCoef {
+    int family = 0;
+    int exterior = 0;          // unknowns are the exterior traces
+    double mass[2][2] = {}, aL[2][2] = {}, aY[2][2] = {};
+    double rhsD[2] = {}, rhsN[2] = {};
+};
+FormCoef formulation_coef(int formulation, double eps_in, double eps_out);
+
 // HIP-event timing of the dominant kernels on the stream they run on.
 // kind 0: far-field operator product (matrix-free kernel or dense GEMV),
 // kind 1: dense far-field assembly.  work = algorithmic kernel pairs
@@ -193,6 +211,7 @@ struct DevMesh {
 
     Profiler prof;
     int64_t npair() const { return (int64_t)hm.pair_s.size(); }
+    FormCoef fm;                    // the formulation's block coefficients
     int64_t nnz() const { return (int64_t)hm.col.size(); }
     void *alloc(size_t n);
     ~DevMesh();
@@ -210,6 +229,8 @@ void launch_far_finish(DevMesh &d, bool fp32);
 void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far, bool y_offset);
 void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream_t s);
 void launch_rhs(DevMesh &d, int nq, const double *qbuf, double *b);
+// launch_rhs combined into the formulation's right-hand side rows
+void formulation_rhs(DevMesh &d, int nq, const double *qbuf, double *b);
 void launch_reaction(DevMesh &d, int nq, const double *qpts, double *out);
 void launch_inside_test(DevMesh &d, int nq, const double *qbuf, double *out);
 void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const int32_t *s_sorted,

@@ -71,7 +71,7 @@ static void check_options(const pb_options *o)
     if (!o) fail(PB_E_INVALID_ARG, "options must not be NULL");
     if (!(o->eps_in > 0) || !(o->eps_out > 0) || !(o->kappa >= 0) || !std::isfinite(o->kappa))
         fail(PB_E_INVALID_ARG, "eps_in, eps_out must be > 0 and kappa >= 0");
-    if (o->formulation != PB_DIRECT_INT && o->formulation != PB_JUFFER) fail(PB_E_INVALID_ARG, "unknown formulation");
+    if (o->formulation < PB_DIRECT_INT || o->formulation > PB_PMCHWT_EXT) fail(PB_E_INVALID_ARG, "unknown formulation");
     if (o->preconditioner < PB_PREC_NONE || o->preconditioner > PB_SCALED_MASS)
         fail(PB_E_INVALID_ARG, "unknown preconditioner");
     if (o->preconditioner == PB_SCALED_MASS && o->formulation != PB_JUFFER)
@@ -81,6 +81,62 @@ static void check_options(const pb_options *o)
     if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
     if (o->singular_order < 1 || o->singular_order > 8) fail(PB_E_INVALID_ARG, "singular_order must be in [1, 8]");
     if (o->source_chunks < 0 || o->source_chunks > 1024) fail(PB_E_INVALID_ARG, "source_chunks must be in [0, 1024]");
+}
+
+// Coefficients of a formulation from the combination rule: output row r is
+// c_I (interior equation of kind k) + c_E (exterior equation of kind k), in
+// interior or exterior unknowns.  With e = eps_in / eps_out the four trace
+// equations read, in interior unknowns (Eqs. bie:int:int, bie:ext:int):
+//   kind 1, interior: [M/2 + K_L, -V_L]          = varphi_D
+//   kind 1, exterior: [M/2 - K_Y, e V_Y]         = 0
+//   kind 2, interior: [-D_L, M/2 - T_L]          = varphi_N
+//   kind 2, exterior: [D_Y / e, M/2 + T_Y]       = 0
+// and in exterior unknowns (Eqs. bie:ext:ext, bie:int:ext):
+//   kind 1, interior: [M/2 + K_L, -V_L / e]      = varphi_D
+//   kind 1, exterior: [M/2 - K_Y, V_Y]           = 0
+//   kind 2, interior: [-e D_L, M/2 - T_L]        = e varphi_N
+//   kind 2, exterior: [D_Y, M/2 + T_Y]           = 0
+FormCoef formulation_coef(int formulation, double eps_in, double eps_out)
+{
+    const double e = eps_in / eps_out;
+    struct Row { int kind; double cI, cE; };
+    Row r[2];
+    int ext = 0;
+    switch (formulation) {
+    case PB_DIRECT_INT: r[0] = {1, 1, 0}; r[1] = {1, 0, 1}; break;                  // Eq. bie:dirichlet:int
+    case PB_DIRECT_EXT: ext = 1; r[0] = {1, 0, 1}; r[1] = {1, 1, 0}; break;         // Eq. bie:dirichlet:ext
+    case PB_DIRECT_INT_PERM: r[0] = {1, 0, 1}; r[1] = {1, 1, 0}; break;
+    case PB_DIRECT_EXT_PERM: ext = 1; r[0] = {1, 1, 0}; r[1] = {1, 0, 1}; break;
+    case PB_JUFFER: r[0] = {1, 1, 1 / e}; r[1] = {2, 1, e}; break;                  // alpha, beta = 1/e, e
+    case PB_MULLER_INT: r[0] = {1, 1, 1}; r[1] = {2, 1, 1}; break;
+    case PB_MULLER_EXT: ext = 1; r[0] = {1, 1, 1}; r[1] = {2, 1, 1}; break;
+    case PB_LU: ext = 1; r[0] = {1, e, 1}; r[1] = {2, 1, e}; break;                 // alpha = e, beta = 1/e, row 2 times e
+    case PB_PMCHWT_INT: r[0] = {1, -1, 1}; r[1] = {2, -1, 1}; break;                // the paper's sign: -(I) + (E)
+    case PB_PMCHWT_EXT: ext = 1; r[0] = {1, -1, 1}; r[1] = {2, -1, 1}; break;
+    default: fail(PB_E_INVALID_ARG, "unknown formulation");
+    }
+    FormCoef f;
+    f.exterior = ext;
+    f.family = r[1].kind == 2 ? 1 : 0;
+    for (int i = 0; i < 2; ++i) {
+        const double cI = r[i].cI, cE = r[i].cE, h = 0.5 * (cI + cE);
+        if (r[i].kind == 1) {
+            f.mass[i][0] = h;
+            f.aL[i][0] = cI;                      // K_L
+            f.aY[i][0] = -cE;                     // K_Y
+            f.aL[i][1] = ext ? -cI / e : -cI;     // V_L
+            f.aY[i][1] = ext ? cE : cE * e;       // V_Y
+            f.rhsD[i] = cI;
+        } else {
+            f.aL[i][0] = ext ? -cI * e : -cI;     // D_L
+            f.aY[i][0] = ext ? cE : cE / e;       // D_Y
+            f.mass[i][1] = h;
+            f.aL[i][1] = -cI;                     // T_L
+            f.aY[i][1] = cE;                      // T_Y
+            f.rhsN[i] = ext ? cI * e : cI;
+        }
+    }
+    return f;
 }
 
 // every device-side setup stage: geometry, near field, near blocks +
@@ -101,6 +157,7 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->opt = *opt;
     d->prm = {opt->eps_in, opt->eps_out, opt->kappa, opt->formulation, opt->preconditioner, opt->precision,
               opt->operator_mode};
+    d->fm = formulation_coef(opt->formulation, opt->eps_in, opt->eps_out);
     build_host_mesh(mesh, d->hm);   // validation happens before any device call
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(PB_E_DEVICE, "no HIP device available");
@@ -523,6 +580,8 @@ pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, doub
     kr_dots(d.stream, n, 1, pb, n, pb, d.red1 + 1);
     double rr[2];
     HIPCHECK(hipMemcpyAsync(rr, d.red1, sizeof(rr), hipMemcpyDeviceToHost, d.stream));
+    // exterior unknowns -> interior traces (interface conditions)
+    if (d.fm.exterior) kr_scale_copy(d.stream, V, u + V, d.prm.eps_out / d.prm.eps_in, u + V);
     charges_to_device(d, ch);
     const int nq = ch->n;
     std::vector<double> pr(nq);
@@ -554,8 +613,7 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
     const int nq = ch->n;
     check_charges_inside(d, nq);
     double *b = d.xtmp, *pb = d.ytmp;
-    rhs_device(d, nq, b);
-    if (d.prm.formulation == PB_DIRECT_INT) HIPCHECK(hipMemsetAsync(b + V, 0, sizeof(double) * V, d.stream));
+    formulation_rhs(d, nq, d.qbuf, b);
     HIPCHECK(hipStreamSynchronize(d.stream));
     double t1 = now();
     if (mass_mode(d)) mass_precond(d, 1, b, pb, DevCtl());

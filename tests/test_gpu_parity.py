@@ -540,3 +540,88 @@ def test_mass_preconditioner_full_size_rows(sphere32):
     bd = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(1, pbm.PB_FP32, operator_mode=pbm.PB_ASSEMBLED))
     assert r["status"] == pbm.PB_OK and r["iterations"] < bd["iterations"], (r["iterations"], bd["iterations"])
     assert abs(r["dG"] - bd["dG"]) < 1e-4 * abs(bd["dG"])
+
+
+# ------------------------------------------------------ every formulation
+_FORMS = [pbm.PB_DIRECT_INT, pbm.PB_JUFFER, pbm.PB_DIRECT_EXT, pbm.PB_DIRECT_INT_PERM, pbm.PB_DIRECT_EXT_PERM,
+          pbm.PB_MULLER_INT, pbm.PB_MULLER_EXT, pbm.PB_LU, pbm.PB_PMCHWT_INT, pbm.PB_PMCHWT_EXT]
+_DIRECT_FAMILY = (pbm.PB_DIRECT_INT, pbm.PB_DIRECT_EXT, pbm.PB_DIRECT_INT_PERM, pbm.PB_DIRECT_EXT_PERM)
+
+
+@pytest.fixture(scope="module")
+def base_operators(meshes):
+    """V, K, D, T = K^T of both kernels and M on the 980-triangle star, from
+    which every formulation's system is composed as the paper prints it."""
+    m = meshes["star7"]
+    oL = oracle.assemble(m, 0.0, ("V", "K", "D"))
+    oY = oracle.assemble(m, 0.125, ("V", "K", "D"))
+    for o in (oL, oY):
+        o["T"] = o["K"].T.copy()
+    return oL, oY, oracle.mass(m)
+
+
+def _system(base, form):
+    A11, A12, A21, A22 = oracle.system_blocks(base[0], base[1], base[2], 4.0, 80.0, form)
+    return np.block([[A11, A12], [A21, A22]])
+
+
+@pytest.mark.parametrize("form", _FORMS)
+def test_formulation_operator(meshes, base_operators, form):
+    """The library's coefficient model of each formulation (combination of the
+    interior and exterior trace equations) against the oracle's systems typed
+    in as printed: matrix-free FP64 (1e-12), assembled FP64 (1e-12), assembled
+    FP32 one evaluation per pair (1e-5) and matrix-free FP32 (1e-5)."""
+    m = meshes["star7"]
+    A = _system(base_operators, form)
+    x = np.random.default_rng(71 + form).standard_normal(2 * m.n_vertices)
+    ref = A @ x
+    for prec, mode, tol in ((pbm.PB_FP64, pbm.PB_MATRIX_FREE, 1e-12), (pbm.PB_FP64, pbm.PB_ASSEMBLED, 1e-12),
+                            (pbm.PB_FP32, pbm.PB_ASSEMBLED, 1e-5), (pbm.PB_FP32, pbm.PB_MATRIX_FREE, 1e-5)):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec, operator_mode=mode)) as h:
+            y = pbm.pb_mesh_apply(h, x)
+        assert _rel(y, ref) < tol, (form, prec, mode, _rel(y, ref))
+
+
+@pytest.mark.parametrize("form", _FORMS)
+def test_formulation_solve_parity(form):
+    """Kirkwood sphere: each formulation (block-diagonal preconditioner for the
+    direct ones, mass matrix for the others, as the paper pairs them) takes the
+    oracle's iterations and gives its Delta G and interior traces; exterior
+    unknowns come back as interior traces."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    direct = form in _DIRECT_FAMILY
+    ref = oracle.solve(m, ch, formulation=form, preconditioner=True if direct else "mass")
+    got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q,
+                       _opts(form, preconditioner=pbm.PB_BLOCK_DIAG if direct else pbm.PB_MASS))
+    assert got["status"] == pbm.PB_OK
+    assert got["iterations"] == ref["iterations"], (form, got["iterations"], ref["iterations"])
+    assert abs(got["dG"] - ref["dG"]) < 1e-6 * abs(ref["dG"])
+    assert _rel(np.concatenate([got["phi"], got["dphi"]]), np.concatenate([ref["phi"], ref["dphi"]])) < 1e-5
+    g32 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q,
+                       _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_ASSEMBLED,
+                             preconditioner=pbm.PB_BLOCK_DIAG if direct else pbm.PB_MASS))
+    assert abs(g32["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"])
+
+
+def test_lu_full_size(sphere32):
+    """20480-triangle sphere, Lu formulation (exterior unknowns) with the mass
+    preconditioner (the paper's Case 12): sampled rows of A x in FP32 assembled
+    against the oracle, and the FP32 / BF16 solves within 1e-4 of the FP64
+    matrix-free GPU solve."""
+    m, ch = sphere32
+    nv = m.n_vertices
+    rng = np.random.default_rng(29)
+    x = rng.standard_normal(2 * nv)
+    rows = np.sort(rng.choice(nv, 8, replace=False))
+    r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, oracle.LU, rows, x)
+    ref = np.concatenate([r1, r2])
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(pbm.PB_LU, pbm.PB_FP32, operator_mode=pbm.PB_ASSEMBLED,
+                                            preconditioner=pbm.PB_MASS)) as h:
+        y = pbm.pb_mesh_apply(h, x)
+        r32 = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+    assert _rel(np.concatenate([y[rows], y[nv + rows]]), ref) < 2e-5
+    g64 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(pbm.PB_LU, preconditioner=pbm.PB_MASS))
+    gbf = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(pbm.PB_LU, pbm.PB_MIXED_BF16, operator_mode=pbm.PB_ASSEMBLED,
+                                                          preconditioner=pbm.PB_MASS))
+    for g in (r32, gbf):
+        assert g["status"] == pbm.PB_OK and abs(g["dG"] - g64["dG"]) < 1e-4 * abs(g64["dG"])

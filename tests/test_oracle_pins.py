@@ -416,3 +416,31 @@ def test_mass_preconditioners_solution_and_iterations():
     # the inverse of the sparse mass matrix, checked by applying M itself
     assert np.abs(2.0 * M @ w[:nv] - v[:nv]).max() < 1e-12 * np.abs(v).max()
     assert np.abs(3.0 * M @ w[nv:] - v[nv:]).max() < 1e-12 * np.abs(v).max()
+
+
+@pytest.mark.parametrize("form", [oracle.DIRECT_EXT, oracle.DIRECT_INT_PERM, oracle.DIRECT_EXT_PERM,
+                                  oracle.MULLER_INT, oracle.MULLER_EXT, oracle.LU,
+                                  oracle.PMCHWT_INT, oracle.PMCHWT_EXT])
+def test_every_formulation_reaches_kirkwood(form):
+    """External direct, permuted, Mueller, Lu and PMCHWT formulations (Eqs.
+    bie:dirichlet:ext ... bie:pmchwt:ext, typed in as printed): a central
+    charge converges to the closed form at O(h^2), and off-centre charges in
+    a 10 A sphere (non-constant traces, so every block of the system takes
+    part) converge to the Kirkwood multipole series; the exterior unknowns are
+    turned into interior traces by the interface conditions before Delta G."""
+    prec = "mass" if form not in oracle.DIRECT_FAMILY else True
+    err = []
+    for f in (4, 8):
+        m, ch = inputs.config_kirkwood(f, 2.0)
+        r = oracle.solve(m, ch, formulation=form, preconditioner=prec)
+        assert r["rel_residual"] < 1e-5 * 1.01
+        err.append((r["dG"] - kirkwood_central(2.0)) / kirkwood_central(2.0))
+    assert abs(err[0]) < 0.015 and abs(err[1]) < 0.004 and 3.0 < err[0] / err[1] < 5.0, err
+    ch = inputs.charges_ball(2, 6, 8.0)
+    ref = kirkwood_energy(10.0, ch.xyz, ch.q)
+    errs = []
+    for f in (4, 8):
+        m = inputs.icosphere(f, 10.0)
+        r = oracle.solve(m, ch, formulation=form, preconditioner=prec)
+        errs.append(abs(r["dG"] - ref) / abs(ref))
+    assert errs[1] < 0.03 and errs[1] < errs[0] / 2.5, (errs, ref)
