@@ -121,19 +121,27 @@ __global__ void k_gather_batch(int V, int n, int precond, const int32_t *__restr
                                const double *__restrict__ pinv, const int32_t *__restrict__ vpos,
                                const double *__restrict__ Yfar, const double *__restrict__ X, double *__restrict__ Y)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // kRowLanes lanes per row, the same slot order and butterfly as k_gather
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
+    const int c = threadIdx.x % kRowLanes;
     const int s = blockIdx.y;
     if (i >= V) return;
     const double *x = X + (size_t)s * n;
-    const int r = vpos[i];   // dense row order
-    double y1 = Yfar[(size_t)s * n + r], y2 = Yfar[(size_t)s * n + V + r];
     double n1 = 0.0, n2 = 0.0;
-    for (int sl = row_ptr[i]; sl < row_ptr[i + 1]; ++sl) {
+    for (int sl = row_ptr[i] + c; sl < row_ptr[i + 1]; sl += kRowLanes) {
         const int j = col[sl];
         const double x1 = x[j], x2 = x[V + j];
         n1 += N[sl] * x1 + N[nnz + sl] * x2;
         n2 += N[2 * nnz + sl] * x1 + N[3 * nnz + sl] * x2;
     }
+#pragma unroll
+    for (int off = 1; off < kRowLanes; off <<= 1) {
+        n1 += __shfl_xor(n1, off);
+        n2 += __shfl_xor(n2, off);
+    }
+    if (c != 0) return;
+    const int r = vpos[i];   // dense row order
+    double y1 = Yfar[(size_t)s * n + r], y2 = Yfar[(size_t)s * n + V + r];
     y1 += n1;
     y2 += n2;
     if (precond) {
@@ -148,22 +156,18 @@ __global__ void k_gather_batch(int V, int n, int precond, const int32_t *__restr
 
 // ------------------------------------------------------- batched Krylov
 // basis layout [vector i][system s][n]
-__global__ __launch_bounds__(256) void k_bdots(int n, int nb, const double *__restrict__ Vb,
-                                               const double *__restrict__ W, double *__restrict__ out, int ostride)
+__global__ __launch_bounds__(kDotThreads) void k_bdots(int n, int nb, const double *__restrict__ Vb,
+                                                       const double *__restrict__ W, double *__restrict__ out,
+                                                       int ostride)
 {
-    __shared__ double sh[256];
+    __shared__ double sh[kDotThreads];
     const int i = blockIdx.x, s = blockIdx.y;
     const double *v = Vb + ((size_t)i * nb + s) * n;
     const double *w = W + (size_t)s * n;
     double acc = 0.0;
-    for (int e = threadIdx.x; e < n; e += 256) acc += v[e] * w[e];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[(size_t)s * ostride + i] = sh[0];
+    for (int e = threadIdx.x; e < n; e += kDotThreads) acc += v[e] * w[e];
+    const double r = dot_block_sum(acc, sh);
+    if (threadIdx.x == 0) out[(size_t)s * ostride + i] = r;
 }
 
 __global__ void k_bupdate(int n, int nvec, int nb, const double *__restrict__ Vb, const double *__restrict__ h,
@@ -289,11 +293,11 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
             pf.record(0, e0, e1, (double)n * n * 2.0 + kMaxBatch * (double)n * (2.0 + 8.0));
         }
         if (mass_mode(d)) {
-            hipLaunchKernelGGL(k_gather_batch, dim3((V + 255) / 256, nb), dim3(256), 0, d.stream, V, n, 0, d.row_ptr,
+            hipLaunchKernelGGL(k_gather_batch, dim3((V + 256 / kRowLanes - 1) / (256 / kRowLanes), nb), dim3(256), 0, d.stream, V, n, 0, d.row_ptr,
                                d.col, d.N, d.nnz(), d.pinv, D->vpos, D->Y16, X, d.mtmp);
             mass_precond(d, nb, d.mtmp, Y, DevCtl());
         } else {
-            hipLaunchKernelGGL(k_gather_batch, dim3((V + 255) / 256, nb), dim3(256), 0, d.stream, V, n, 1, d.row_ptr,
+            hipLaunchKernelGGL(k_gather_batch, dim3((V + 256 / kRowLanes - 1) / (256 / kRowLanes), nb), dim3(256), 0, d.stream, V, n, 1, d.row_ptr,
                                d.col, d.N, d.nnz(), d.pinv, D->vpos, D->Y16, X, Y);
         }
         HIPCHECK(hipGetLastError());
@@ -313,7 +317,7 @@ static void gmres_batch(DevMesh &d, int nb, const double *PB, double *X, const s
     hipStream_t st = d.stream;
     const int ks = 2 * (m + 1) + 1;   // kbuf stride per system
     const dim3 gv((n + 255) / 256, nb), b256(256);
-    hipLaunchKernelGGL(k_bdots, dim3(1, nb), b256, 0, st, n, 1, PB, PB, w.kbuf, ks);
+    hipLaunchKernelGGL(k_bdots, dim3(1, nb), dim3(kDotThreads), 0, st, n, 1, PB, PB, w.kbuf, ks);
     std::vector<double> hb((size_t)ks * nb);
     HIPCHECK(hipMemcpyAsync(hb.data(), w.kbuf, sizeof(double) * ks * nb, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
@@ -340,11 +344,11 @@ static void gmres_batch(DevMesh &d, int nb, const double *PB, double *X, const s
         double *Vj = w.basis + (size_t)j * nb * n, *Wn = w.basis + (size_t)(j + 1) * nb * n;
         apply_batch(d, nb, Vj, Wn);
         double *h1 = w.kbuf, *h2 = w.kbuf + (j + 1), *nr = w.kbuf + 2 * (j + 1);
-        hipLaunchKernelGGL(k_bdots, dim3(j + 1, nb), b256, 0, st, n, nb, w.basis, Wn, h1, ks);
+        hipLaunchKernelGGL(k_bdots, dim3(j + 1, nb), dim3(kDotThreads), 0, st, n, nb, w.basis, Wn, h1, ks);
         hipLaunchKernelGGL(k_bupdate, gv, b256, 0, st, n, j + 1, nb, w.basis, h1, ks, Wn, -1.0);
-        hipLaunchKernelGGL(k_bdots, dim3(j + 1, nb), b256, 0, st, n, nb, w.basis, Wn, h2, ks);
+        hipLaunchKernelGGL(k_bdots, dim3(j + 1, nb), dim3(kDotThreads), 0, st, n, nb, w.basis, Wn, h2, ks);
         hipLaunchKernelGGL(k_bupdate, gv, b256, 0, st, n, j + 1, nb, w.basis, h2, ks, Wn, -1.0);
-        hipLaunchKernelGGL(k_bdots, dim3(1, nb), b256, 0, st, n, 1, Wn, Wn, nr, ks);
+        hipLaunchKernelGGL(k_bdots, dim3(1, nb), dim3(kDotThreads), 0, st, n, 1, Wn, Wn, nr, ks);
         hipLaunchKernelGGL(k_bnormalize, gv, b256, 0, st, n, nr, ks, Wn);
         HIPCHECK(hipMemcpyAsync(hb.data(), w.kbuf, sizeof(double) * ks * nb, hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
@@ -431,7 +435,7 @@ pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result 
             HIPCHECK(hipMemsetAsync(w.U, 0, sizeof(double) * n * nb, st));
             HIPCHECK(hipMemcpyAsync(w.R, w.PB, sizeof(double) * n * nb, hipMemcpyDeviceToDevice, st));
             std::vector<double> nb2(nb), rel(nb, 1.0), tol(nb);
-            hipLaunchKernelGGL(k_bdots, dim3(1, nb), dim3(256), 0, st, n, 1, w.PB, w.PB, w.kbuf, 1);
+            hipLaunchKernelGGL(k_bdots, dim3(1, nb), dim3(kDotThreads), 0, st, n, 1, w.PB, w.PB, w.kbuf, 1);
             HIPCHECK(hipMemcpyAsync(nb2.data(), w.kbuf, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
             HIPCHECK(hipStreamSynchronize(st));
             std::vector<char> conv(nb, 0);
@@ -450,7 +454,7 @@ pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result 
                     kr_scale_copy(st, n, w.R + (size_t)s * n, -1.0, w.R + (size_t)s * n);
                     kr_axpy(st, n, 1.0, w.PB + (size_t)s * n, w.R + (size_t)s * n);
                 }
-                hipLaunchKernelGGL(k_bdots, dim3(1, nb), dim3(256), 0, st, n, 1, w.R, w.R, w.kbuf, 1);
+                hipLaunchKernelGGL(k_bdots, dim3(1, nb), dim3(kDotThreads), 0, st, n, 1, w.R, w.R, w.kbuf, 1);
                 std::vector<double> r2(nb);
                 HIPCHECK(hipMemcpyAsync(r2.data(), w.kbuf, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
                 HIPCHECK(hipStreamSynchronize(st));

@@ -226,10 +226,28 @@ __global__ void k_gather(int V, int use_far, int use_near, int precond, const in
                          const double *__restrict__ N, int64_t nnz, const double *__restrict__ pinv,
                          const double *__restrict__ x, double *__restrict__ y, DevCtl ctl, DevCtl ctly)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // kRowLanes lanes per row; the lane group sits inside one wavefront, so a
+    // whole group is either active or retired together
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
+    const int c = threadIdx.x % kRowLanes;
     if (i >= V || ctl_skip(ctl)) return;
     x += ctl_off(ctl);
     y += ctl_off(ctly);
+    double n1 = 0.0, n2 = 0.0;
+    if (use_near) {
+        for (int sl = row_ptr[i] + c; sl < row_ptr[i + 1]; sl += kRowLanes) {
+            const int j = col[sl];
+            const double x1 = x[j], x2 = x[V + j];
+            n1 += N[sl] * x1 + N[nnz + sl] * x2;
+            n2 += N[2 * nnz + sl] * x1 + N[3 * nnz + sl] * x2;
+        }
+#pragma unroll
+        for (int off = 1; off < kRowLanes; off <<= 1) {
+            n1 += __shfl_xor(n1, off);
+            n2 += __shfl_xor(n2, off);
+        }
+    }
+    if (c != 0) return;
     double y1 = 0.0, y2 = 0.0;
     if (use_far == 2) {   // dense far product, rows in dense vertex order
         const int r = vpos[i];
@@ -244,13 +262,6 @@ __global__ void k_gather(int V, int use_far, int use_near, int precond, const in
         }
     }
     if (use_near) {
-        double n1 = 0.0, n2 = 0.0;
-        for (int sl = row_ptr[i]; sl < row_ptr[i + 1]; ++sl) {
-            const int j = col[sl];
-            const double x1 = x[j], x2 = x[V + j];
-            n1 += N[sl] * x1 + N[nnz + sl] * x2;
-            n2 += N[2 * nnz + sl] * x1 + N[3 * nnz + sl] * x2;
-        }
         y1 += n1;
         y2 += n2;
     }
@@ -361,7 +372,8 @@ void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_fa
     const int use_near = (flags & PB_APPLY_FAR_ONLY) ? 0 : 1;
     DevCtl ctly = d.ctl;
     if (!y_offset) ctly.stride = 0;
-    hipLaunchKernelGGL(k_gather, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, use_far, use_near,
+    hipLaunchKernelGGL(k_gather, dim3((V + 256 / kRowLanes - 1) / (256 / kRowLanes)), dim3(256), 0, d.stream, V,
+                       use_far, use_near,
                        (flags & PB_APPLY_PRECOND) ? 1 : 0, d.inc_ptr, d.inc_tk, d.triout, d.yfar, d.dense_vpos, d.row_ptr, d.col, d.N,
                        d.nnz(), d.pinv, x, y, d.ctl, ctly);
     HIPCHECK(hipGetLastError());

@@ -9,20 +9,15 @@ namespace pbm {
 constexpr int kKB = 256;
 
 // out[i] = <V_i, w> for i < nvec; one block per basis vector.
-__global__ __launch_bounds__(kKB) void k_dots(int n, const double *__restrict__ Vb, size_t ldv,
-                                              const double *__restrict__ w, double *__restrict__ out)
+__global__ __launch_bounds__(kDotThreads) void k_dots(int n, const double *__restrict__ Vb, size_t ldv,
+                                                      const double *__restrict__ w, double *__restrict__ out)
 {
-    __shared__ double sh[kKB];
+    __shared__ double sh[kDotThreads];
     const double *v = Vb + (size_t)blockIdx.x * ldv;
     double acc = 0.0;
-    for (int e = threadIdx.x; e < n; e += kKB) acc += v[e] * w[e];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kKB / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+    for (int e = threadIdx.x; e < n; e += kDotThreads) acc += v[e] * w[e];
+    const double r = dot_block_sum(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
 // w += sign * sum_i h[i] V_i
@@ -72,7 +67,7 @@ static inline dim3 g1(int n) { return dim3((n + kKB - 1) / kKB); }
 
 void kr_dots(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *w, double *out)
 {
-    hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(kKB), 0, s, n, V, ldv, w, out);
+    hipLaunchKernelGGL(k_dots, dim3(nvec), dim3(kDotThreads), 0, s, n, V, ldv, w, out);
 }
 void kr_update(hipStream_t s, int n, int nvec, const double *V, size_t ldv, const double *h, double *w, double sign)
 {
@@ -103,23 +98,18 @@ void kr_precond(hipStream_t s, int V, const double *pinv, const double *x, doubl
 // return at once.
 namespace pbm {
 
-__global__ __launch_bounds__(kKB) void k_gdots(int n, const double *__restrict__ Vb, const GState *__restrict__ st,
-                                               double *__restrict__ out)
+__global__ __launch_bounds__(kDotThreads) void k_gdots(int n, const double *__restrict__ Vb,
+                                                       const GState *__restrict__ st, double *__restrict__ out)
 {
-    __shared__ double sh[kKB];
+    __shared__ double sh[kDotThreads];
     const int i = blockIdx.x;
     if (st->done || i > st->j) return;
     const double *v = Vb + (size_t)i * n;
     const double *w = Vb + (size_t)(st->j + 1) * n;
     double acc = 0.0;
-    for (int e = threadIdx.x; e < n; e += kKB) acc += v[e] * w[e];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kKB / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[i] = sh[0];
+    for (int e = threadIdx.x; e < n; e += kDotThreads) acc += v[e] * w[e];
+    const double r = dot_block_sum(acc, sh);
+    if (threadIdx.x == 0) out[i] = r;
 }
 
 __global__ void k_gupdate(int n, const double *__restrict__ Vb, const GState *__restrict__ st,
@@ -134,20 +124,15 @@ __global__ void k_gupdate(int n, const double *__restrict__ Vb, const GState *__
 }
 
 // |w|^2 with one block, same reduction shape as k_dots
-__global__ __launch_bounds__(kKB) void k_gnorm(int n, const double *__restrict__ Vb, GState *__restrict__ st)
+__global__ __launch_bounds__(kDotThreads) void k_gnorm(int n, const double *__restrict__ Vb, GState *__restrict__ st)
 {
-    __shared__ double sh[kKB];
+    __shared__ double sh[kDotThreads];
     if (st->done) return;
     const double *w = Vb + (size_t)(st->j + 1) * n;
     double acc = 0.0;
-    for (int e = threadIdx.x; e < n; e += kKB) acc += w[e] * w[e];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kKB / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) st->nrm2 = sh[0];
+    for (int e = threadIdx.x; e < n; e += kDotThreads) acc += w[e] * w[e];
+    const double r = dot_block_sum(acc, sh);
+    if (threadIdx.x == 0) st->nrm2 = r;
 }
 
 // Hessenberg column j = h1 + h2 (two Gram-Schmidt passes), previous Givens
@@ -192,11 +177,11 @@ __global__ void k_gnormalize(int n, double *__restrict__ Vb, const GState *__res
 void kr_graph_iteration_tail(hipStream_t s, int n, int m, double *Vb, GState *st, double *H, double *cs, double *sn,
                              double *g, double *h1, double *h2)
 {
-    hipLaunchKernelGGL(k_gdots, dim3(m + 1), dim3(kKB), 0, s, n, Vb, st, h1);
+    hipLaunchKernelGGL(k_gdots, dim3(m + 1), dim3(kDotThreads), 0, s, n, Vb, st, h1);
     hipLaunchKernelGGL(k_gupdate, g1(n), dim3(kKB), 0, s, n, Vb, st, h1);
-    hipLaunchKernelGGL(k_gdots, dim3(m + 1), dim3(kKB), 0, s, n, Vb, st, h2);
+    hipLaunchKernelGGL(k_gdots, dim3(m + 1), dim3(kDotThreads), 0, s, n, Vb, st, h2);
     hipLaunchKernelGGL(k_gupdate, g1(n), dim3(kKB), 0, s, n, Vb, st, h2);
-    hipLaunchKernelGGL(k_gnorm, dim3(1), dim3(kKB), 0, s, n, Vb, st);
+    hipLaunchKernelGGL(k_gnorm, dim3(1), dim3(kDotThreads), 0, s, n, Vb, st);
     hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, st, H, cs, sn, g, h1, h2);
     hipLaunchKernelGGL(k_gnormalize, g1(n), dim3(kKB), 0, s, n, Vb, st);
 }

@@ -85,6 +85,25 @@ struct DevCtl {
 __device__ inline bool ctl_skip(const DevCtl &c) { return c.skip && *c.skip; }
 __device__ inline size_t ctl_off(const DevCtl &c) { return c.j ? (size_t)(*c.j) * c.stride : 0; }
 
+// Every FP64 dot product of the Krylov solvers (eager, captured, batched) has
+// this one shape: kDotThreads threads stride over the vector, then a fixed
+// LDS tree, so the three paths round identically.
+constexpr int kDotThreads = 1024;
+__device__ inline double dot_block_sum(double acc, double *sh)
+{
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kDotThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+// The near-field product of one vertex row uses kRowLanes lanes (slots
+// strided by kRowLanes, then a butterfly inside the lane group), in the
+// single and the batched gather alike.
+constexpr int kRowLanes = 4;
+
 struct GraphGmres;   // captured GMRES iteration (runtime.hip)
 
 // device state of a captured GMRES solve
