@@ -42,6 +42,7 @@ struct Dense {
     int32_t *vpos = nullptr, *vperm = nullptr;
     float *x32 = nullptr;          // ld (padded) FP32 copy of x
     double *x64 = nullptr;         // ld (padded) FP64 copy of x
+    double *gpart = nullptr;       // 2 n partial row sums of the split GEMV
     int level = 1;                 // 1: accurate operator, 0: 16-bit operator
     int gemv_hi = -1, gemv_lo = -1;   // autotuned GEMV variants (-1: not tuned yet)
     int gemm_rows = 0;                // autotuned rows per wavefront of the MFMA GEMM (0: not tuned)

@@ -646,6 +646,83 @@ __global__ __launch_bounds__(256) void k_gemv_tile(int n, int V, size_t Vp, size
     }
 }
 
+// Split row-tile GEMV: the work unit is (tile of R rows, one of the two column
+// blocks), so there are twice as many units as tiles and the wavefronts spread
+// more evenly over the SIMDs; each unit writes its R partial sums, and
+// k_gemv_join adds the two blocks' partials of a row in a fixed order.
+template <typename S, typename ACC, int KIND, int R>
+__global__ __launch_bounds__(256) void k_gemv_split(int n, size_t Vp, size_t ld, const S *__restrict__ A,
+                                                    const ACC *__restrict__ x, ACC *__restrict__ part, DevCtl ctl)
+{
+    if (ctl_skip(ctl)) return;
+    constexpr int W = Vec<S>::W;
+    constexpr size_t step = 64 * W;
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int nwave = (gridDim.x * 256) >> 6;
+    const int nunit = 2 * ((n + R - 1) / R);
+    for (int u = wave; u < nunit; u += nwave) {
+        const int r0 = (u >> 1) * R;
+        const size_t c0 = (u & 1) * Vp;   // column block; chunks never straddle Vp (multiple of 64)
+        const S *rows[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) rows[i] = A + (size_t)min(r0 + i, n - 1) * ld + c0;
+        ACC sacc[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) sacc[i] = 0;
+        for (size_t c = (size_t)lane * W; c < Vp; c += step) {
+            ACC xv[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) xv[w] = x[c0 + c + w];
+            u32x4 uu[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) uu[i] = __builtin_nontemporal_load((const u32x4 *)(rows[i] + c));
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                S v[W];
+                __builtin_memcpy(v, &uu[i], 16);
+                ACC pp = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    ACC a;
+                    if constexpr (KIND == 0) a = (ACC)v[w];
+                    else if constexpr (KIND == 1) a = (ACC)bf16_to_f((uint16_t)v[w]);
+                    else a = (ACC)fp16_to_f((uint16_t)v[w]);
+                    pp += a * xv[w];
+                }
+                sacc[i] += pp;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            for (int off = 32; off > 0; off >>= 1) sacc[i] += __shfl_xor(sacc[i], off);
+        if (lane < R && r0 + lane < n) {
+            ACC a = 0;
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if (i == lane) a = sacc[i];
+            part[(size_t)(u & 1) * n + r0 + lane] = a;
+        }
+    }
+}
+
+template <typename ACC, int KIND>
+__global__ void k_gemv_join(int n, int V, float inv0, float inv1, float inv2, float inv3,
+                            const ACC *__restrict__ part, double *__restrict__ y, DevCtl ctl)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || ctl_skip(ctl)) return;
+    const ACC a0 = part[r], a1 = part[(size_t)n + r];
+    double out;
+    if (KIND == 2) {
+        const bool top = r < V;
+        out = (double)a0 * (top ? inv0 : inv2) + (double)a1 * (top ? inv1 : inv3);
+    } else {
+        out = (double)a0 + (double)a1;
+    }
+    y[r] = out;
+}
+
 // copy x (2V doubles, two halves) into the padded layout: [x1 | x2 | 0...]
 // x (2V doubles, vertex order) into the padded dense column order
 // [x1 (dense index order) | 0 | x2 | 0]
@@ -888,6 +965,7 @@ void build_dense(DevMesh &d)
         }
         D->x32 = (float *)d.alloc(sizeof(float) * D->ld);
         D->x64 = (double *)d.alloc(sizeof(double) * D->ld);
+        D->gpart = (double *)d.alloc(sizeof(double) * 2 * (size_t)D->n);
         D->tile = d.prm.precision == PB_FP64 ? 128 : 256;
         D->sym = d.prm.precision != PB_FP64;
         if (D->sym) {
@@ -950,13 +1028,28 @@ void destroy_dense(DevMesh &d)
 }
 
 // GEMV variants: 0 = one wavefront per row (four loads in flight per lane),
-// 1 = 8-row tiles, 2 = 16-row tiles.  The fastest for a given storage type and
+// 1 = 8-row tiles, 2 = 16-row tiles, 3-5 = split 4-, 8-, 16-row tiles.  The fastest for a given storage type and
 // matrix is picked by timing them once on the real matrix (autotune cache).
 template <typename S, typename ACC, int KIND>
 static void gemv_launch(int variant, hipStream_t st, int n, int V, size_t Vp, size_t ld, const S *A, const ACC *x,
-                        const float *inv, double *y, const DevCtl &ctl)
+                        const float *inv, double *y, const DevCtl &ctl, double *part)
 {
-    if (variant == 0) {
+    if (variant >= 3) {
+        // split variants: R = 4, 8, 16 rows per tile, two column blocks per tile
+        const int R = variant == 3 ? 4 : variant == 4 ? 8 : 16;
+        const int nunit = 2 * ((n + R - 1) / R);
+        const int nwg = std::min((nunit + 3) / 4, 8192);
+        ACC *pp = (ACC *)part;
+        if (R == 4)
+            hipLaunchKernelGGL((k_gemv_split<S, ACC, KIND, 4>), dim3(nwg), dim3(256), 0, st, n, Vp, ld, A, x, pp, ctl);
+        else if (R == 8)
+            hipLaunchKernelGGL((k_gemv_split<S, ACC, KIND, 8>), dim3(nwg), dim3(256), 0, st, n, Vp, ld, A, x, pp, ctl);
+        else
+            hipLaunchKernelGGL((k_gemv_split<S, ACC, KIND, 16>), dim3(nwg), dim3(256), 0, st, n, Vp, ld, A, x, pp,
+                               ctl);
+        hipLaunchKernelGGL((k_gemv_join<ACC, KIND>), dim3((n + 255) / 256), dim3(256), 0, st, n, V, inv[0], inv[1],
+                           inv[2], inv[3], pp, y, ctl);
+    } else if (variant == 0) {
         const int nwg = std::min(n / 4 + 1, 8192);
         hipLaunchKernelGGL((k_gemv<S, ACC, KIND>), dim3(nwg), dim3(256), 0, st, n, V, Vp, ld, A, x, inv[0], inv[1],
                            inv[2], inv[3], y, ctl);
@@ -976,10 +1069,11 @@ static void gemv_dispatch(Dense &D, int variant, hipStream_t st, bool lo, double
     const int V = D.V;
     float one[4] = {1.f, 1.f, 1.f, 1.f}, inv[4];
     for (int b = 0; b < 4; ++b) inv[b] = 1.f / D.scale16[b];
-    if (D.A64) gemv_launch<double, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A64, D.x64, one, yfar, ctl);
-    else if (!lo) gemv_launch<float, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A32, D.x64, one, yfar, ctl);
-    else if (D.kind16 == 1) gemv_launch<uint16_t, float, 1>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, one, yfar, ctl);
-    else gemv_launch<uint16_t, float, 2>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, inv, yfar, ctl);
+    if (D.A64) gemv_launch<double, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A64, D.x64, one, yfar, ctl, D.gpart);
+    else if (!lo) gemv_launch<float, double, 0>(variant, st, D.n, V, D.Vp, D.ld, D.A32, D.x64, one, yfar, ctl, D.gpart);
+    else if (D.kind16 == 1)
+        gemv_launch<uint16_t, float, 1>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, one, yfar, ctl, D.gpart);
+    else gemv_launch<uint16_t, float, 2>(variant, st, D.n, V, D.Vp, D.ld, D.A16, D.x32, inv, yfar, ctl, D.gpart);
 }
 
 int autotune_pick(const std::string &key, int nvariants, const std::function<void(int)> &run, hipStream_t st);
@@ -991,7 +1085,7 @@ static int gemv_variant(DevMesh &d, bool lo)
     if (slot >= 0) return slot;
     const char *kind = D.A64 ? "f64" : !lo ? "f32" : D.kind16 == 1 ? "bf16" : "fp16";
     const std::string key = std::string("gemv/") + kind + "/" + std::to_string(D.n);
-    slot = autotune_pick(key, 3, [&](int v) { gemv_dispatch(D, v, d.stream, lo, d.yfar); }, d.stream);
+    slot = autotune_pick(key, 6, [&](int v) { gemv_dispatch(D, v, d.stream, lo, d.yfar); }, d.stream);
     return slot;
 }
 
