@@ -118,7 +118,7 @@ template <typename R> struct alignas(4 * sizeof(R)) Quad {
 // Target colours keep rows disjoint and tile colours keep columns disjoint
 // between concurrently running blocks, so there is no atomic and the result
 // is deterministic.
-template <typename R, typename S, int FORM, int TILE, bool SYM>
+template <typename R, typename S, int FORM, int TILE, bool SYM, int LROW>
 __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 1))) void k_assemble_tile(
     int T, int V, AsmCoef<R> cf, const int32_t *__restrict__ targets, int ntarget, int group,
     const int32_t *__restrict__ tiles, const int4 *__restrict__ sym_blocks, const int32_t *__restrict__ tri,
@@ -211,15 +211,18 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                 const R ekk = ek * (cf.kappa * r + R(1));
                 R v[NV];
                 if (FORM == 0) {
-                    // the four operators' kernels F_L d.n_s, G_L, F_Y d.n_s, G_Y (combined
-                    // per block after the contraction); swapped pair: F_L d.n_t, F_Y d.n_t
-                    v[0] = ri3 * dns;
-                    v[1] = ri;
-                    v[2] = ekk * v[0];
-                    v[3] = ek * ri;
+                    // direct formulations: one row has Laplace (F_L d.n_s, G_L), the other
+                    // Yukawa kernels (F_Y d.n_s, G_Y); the swapped pair's K of the first
+                    // column with d.n_t.  Values ordered by block; LROW = the Laplace row.
+                    const R kl = ri3 * dns, ky = ekk * kl;
+                    v[LROW == 0 ? 0 : 2] = kl;
+                    v[LROW == 0 ? 1 : 3] = ri;
+                    v[LROW == 0 ? 2 : 0] = ky;
+                    v[LROW == 0 ? 3 : 1] = ek * ri;
                     if (SYM) {
-                        v[4] = ri3 * (ts[21 + p] - ynt);
-                        v[5] = ekk * v[4];
+                        const R klt = ri3 * (ts[21 + p] - ynt);
+                        v[LROW == 0 ? 4 : 5] = klt;
+                        v[LROW == 0 ? 5 : 4] = ekk * klt;
                     }
                 } else {
                     // (F_L + rK F_Y) d.n_s, G_L + rV G_Y, G_Y, (F_L + rT F_Y) d.n_t, without the
@@ -268,46 +271,38 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                     Cq[k][o] = q == 0 ? wc * X[k][o] : Cq[k][o] + wc * X[k][o];
                 }
         }
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-#pragma unroll
-                for (int o = 0; o < NV; ++o) blk[l][k][o] += Cq[k][o];
-
         const R sc = ts[27] * sarea * (R)kInv4Pi;
         const R sw = sc * (R)(RuleOrbit::cA * RuleOrbit::cA);
-        // FORM 1 factors (FORM 0 combines the four kernels per block below).  The
-        // double-layer kernel is +F d.n_y, the adjoint one -F d.n_x, with d the
-        // test point minus the trial point; for the swapped pair d changes sign.
+        // Per-value factors.  The double-layer kernel is +F d.n_y, the adjoint one
+        // -F d.n_x, with d the test point minus the trial point; for the swapped
+        // pair d changes sign.  FORM 0: each value has one block's coefficient
+        // (Laplace row LROW, Yukawa row 1 - LROW).
         R f[NV];
-        if (FORM == 1) {
+        if (FORM == 0) {
+            const R c00 = LROW == 0 ? cf.aL[0][0] : cf.aY[0][0], c01 = LROW == 0 ? cf.aL[0][1] : cf.aY[0][1];
+            const R c10 = LROW == 0 ? cf.aY[1][0] : cf.aL[1][0], c11 = LROW == 0 ? cf.aY[1][1] : cf.aL[1][1];
+            f[0] = sw * c00; f[1] = sw * c01; f[2] = sw * c10; f[3] = sw * c11;
+            if (SYM) { f[4] = -sw * c00; f[5] = -sw * c10; }
+        } else {
             f[0] = sw * cf.aL[0][0];
             f[1] = sw * cf.aL[0][1];
             f[2] = sw * cf.aY[1][0] * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
             f[3] = -sw * cf.aL[1][1];
             if (SYM) { f[4] = -sw * cf.aL[0][0]; f[5] = sw * cf.aL[1][1]; }
         }
+        // the rank-two target-side part, scaled once: value = f (blk + Cq)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int o = 0; o < NV; ++o) Cq[k][o] *= f[o];
         if (g > gbeg) __syncthreads();   // the previous target's phase 2 is done with lds
 #pragma unroll
         for (int l = 0; l < 3; ++l)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 R val[NV];
-                if (FORM == 0) {
-                    const R *B = blk[l][k];
-                    val[0] = sw * (cf.aL[0][0] * B[0] + cf.aY[0][0] * B[2]);
-                    val[1] = sw * (cf.aL[0][1] * B[1] + cf.aY[0][1] * B[3]);
-                    val[2] = sw * (cf.aL[1][0] * B[0] + cf.aY[1][0] * B[2]);
-                    val[3] = sw * (cf.aL[1][1] * B[1] + cf.aY[1][1] * B[3]);
-                    if (SYM) {
-                        val[4] = -sw * (cf.aL[0][0] * B[4] + cf.aY[0][0] * B[5]);
-                        val[5] = -sw * (cf.aL[1][0] * B[4] + cf.aY[1][0] * B[5]);
-                    }
-                } else {
 #pragma unroll
-                    for (int o = 0; o < NV; ++o) val[o] = blk[l][k][o] * f[o];
-                }
+                for (int o = 0; o < NV; ++o) val[o] = blk[l][k][o] * f[o] + Cq[k][o];
                 if (FORM == 1) {
                     // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
                     const R cc = ts[28 + 3 * k] * ss[28 + 3 * l] + ts[29 + 3 * k] * ss[29 + 3 * l] +
@@ -867,6 +862,7 @@ static void assemble(DevMesh &d, S *A)
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 2; ++c) { cf.aL[r][c] = (R)fm.aL[r][c]; cf.aY[r][c] = (R)fm.aY[r][c]; }
     const bool direct = fm.family == 0;   // FORM 0: K and V rows; FORM 1: K, V / D, T
+    const int lrow = direct ? laplace_row(fm) : 0;
     if (!direct) {
         for (int r = 0; r < 2; ++r)
             for (int c = 0; c < 2; ++c)
@@ -889,14 +885,14 @@ static void assemble(DevMesh &d, S *A)
             for (int c = 0; c < D.ncolor; ++c, ++li) {
                 const size_t b0 = D.sym_ptr[li], nb = D.sym_ptr[li + 1] - b0;
                 if (nb == 0) continue;
-                if (direct)
-                    hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE, true>), dim3(nb), dim3(TILE), 0, d.stream, T,
-                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat,
-                                       D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp);
-                else
-                    hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE, true>), dim3(nb), dim3(TILE), 0, d.stream, T,
-                                       V, cf, D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat,
-                                       D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp);
+#define ASM_SYM(F, L)                                                                                              \
+    hipLaunchKernelGGL((k_assemble_tile<R, S, F, TILE, true, L>), dim3(nb), dim3(TILE), 0, d.stream, T, V, cf,      \
+                       D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col,       \
+                       D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp)
+                if (!direct) ASM_SYM(1, 0);
+                else if (lrow == 0) ASM_SYM(0, 0);
+                else ASM_SYM(0, 1);
+#undef ASM_SYM
             }
         // V x V blocks of A (row block, column block): symmetric operators take
         // their own transpose, the others the transpose of C's rows.  Direct:
@@ -925,14 +921,14 @@ static void assemble(DevMesh &d, S *A)
                 const int32_t *tg = D.color_tri + D.color_ptr[c];
                 const int grp = D.asm_group;
                 dim3 grid(nk, (nt + grp - 1) / grp), block(TILE);
-                if (direct)
-                    hipLaunchKernelGGL((k_assemble_tile<R, S, 0, TILE, false>), grid, block, 0, d.stream, T, V, cf, tg,
-                                       nt, grp, tl, nullptr, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
-                                       D.te, A, D.ld, D.Vp, nullptr, (size_t)0);
-                else
-                    hipLaunchKernelGGL((k_assemble_tile<R, S, 1, TILE, false>), grid, block, 0, d.stream, T, V, cf, tg,
-                                       nt, grp, tl, nullptr, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr,
-                                       D.te, A, D.ld, D.Vp, nullptr, (size_t)0);
+#define ASM_ALL(F, L)                                                                                              \
+    hipLaunchKernelGGL((k_assemble_tile<R, S, F, TILE, false, L>), grid, block, 0, d.stream, T, V, cf, tg, nt, grp, \
+                       tl, nullptr, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp,       \
+                       nullptr, (size_t)0)
+                if (!direct) ASM_ALL(1, 0);
+                else if (lrow == 0) ASM_ALL(0, 0);
+                else ASM_ALL(0, 1);
+#undef ASM_ALL
             }
         }
     }

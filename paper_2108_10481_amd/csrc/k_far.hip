@@ -285,16 +285,6 @@ int choose_chunks(int T)
     return S;
 }
 
-// direct formulations: one row has only Laplace, the other only Yukawa terms
-static int far_laplace_row(const FormCoef &f)
-{
-    const bool r0L = f.aY[0][0] == 0.0 && f.aY[0][1] == 0.0;
-    const bool r1Y = f.aL[1][0] == 0.0 && f.aL[1][1] == 0.0;
-    if (r0L && r1Y) return 0;
-    if (f.aL[0][0] == 0.0 && f.aL[0][1] == 0.0 && f.aY[1][0] == 0.0 && f.aY[1][1] == 0.0) return 1;
-    fail(PB_E_STATE, "direct formulation with mixed kernels in one row");
-}
-
 template <typename R>
 static void far_launch(DevMesh &d, const R *stat, const R *dyn)
 {
@@ -308,7 +298,7 @@ static void far_launch(DevMesh &d, const R *stat, const R *dyn)
     const FormCoef &f = d.fm;
     int form = 0;
     if (f.family == 0) {
-        const int lr = far_laplace_row(f);
+        const int lr = laplace_row(f);
         cf.kL = (R)f.aL[lr][0]; cf.vL = (R)f.aL[lr][1];
         cf.kY = (R)f.aY[1 - lr][0]; cf.vY = (R)f.aY[1 - lr][1];
     } else {
@@ -355,7 +345,7 @@ void launch_far_finish(DevMesh &d, bool fp32)
     const int T = d.hm.T;
     dim3 grid((T + 255) / 256), block(256);
     const FormCoef &f = d.fm;
-    const int swap = f.family == 0 && far_laplace_row(f) == 1;
+    const int swap = f.family == 0 && laplace_row(f) == 1;
     const double aDL = f.family == 1 ? f.aL[1][0] : 0.0;
     if (fp32)
         hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, f.family, swap, aDL, d.geo,

@@ -140,6 +140,7 @@ struct FormCoef {
     double rhsD[2] = {}, rhsN[2] = {};
 };
 FormCoef formulation_coef(int formulation, double eps_in, double eps_out);
+int laplace_row(const FormCoef &f);   // family 0: the row with only Laplace terms
 
 // HIP-event timing of the dominant kernels on the stream they run on.
 // kind 0: far-field operator product (matrix-free kernel or dense GEMV),

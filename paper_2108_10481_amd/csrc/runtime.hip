@@ -139,6 +139,15 @@ FormCoef formulation_coef(int formulation, double eps_in, double eps_out)
     return f;
 }
 
+// direct formulations: one row has only Laplace, the other only Yukawa terms;
+// returns the Laplace row
+int laplace_row(const FormCoef &f)
+{
+    if (f.aY[0][0] == 0.0 && f.aY[0][1] == 0.0 && f.aL[1][0] == 0.0 && f.aL[1][1] == 0.0) return 0;
+    if (f.aL[0][0] == 0.0 && f.aL[0][1] == 0.0 && f.aY[1][0] == 0.0 && f.aY[1][1] == 0.0) return 1;
+    fail(PB_E_STATE, "direct formulation with mixed kernels in one row");
+}
+
 // every device-side setup stage: geometry, near field, near blocks +
 // preconditioner, dense far field (assembled modes)
 static void device_setup(DevMesh &d)
