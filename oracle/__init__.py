@@ -18,6 +18,8 @@ Citations are to Search, Cooper & van 't Wout, arXiv 2108.10481:
   * reaction potential, energy .......... Eqs. phireac_bie and dG
   * block-diagonal preconditioner ....... Preconditioning / Algebraic preconditioners
   * (scaled) mass-matrix preconditioner . Eqs. prec:mass and prec:mass:scaled
+  * Calderon preconditioners (PMCHWT) ... Eqs. prec:calderon:int, prec:calderon:ext,
+                                          precond:calderon:eigenval(_semi)
   * GMRES, tol 1e-5, no restart ......... Results and Discussion (setup paragraph)
 """
 from __future__ import annotations
@@ -357,6 +359,98 @@ def mass_preconditioner(mesh, a: float = 1.0, b: float = 1.0):
     return apply
 
 
+# ------------------------------------------------------------- Calderon
+#: preconditioner names of the Calderon-preconditioned PMCHWT systems: the
+#: whole PMCHWT matrix, its interior-kernel or its exterior-kernel part as
+#: the preconditioning operator, the halves optionally with the scaled mass
+#: matrix on top (Calderon preconditioning paragraph)
+CALDERON = ("calderon", "calderon_int", "calderon_ext", "scaled_calderon_int", "scaled_calderon_ext")
+
+
+def calderon_part(preconditioner: str) -> str:
+    return {"calderon": "full", "calderon_int": "int", "calderon_ext": "ext",
+            "scaled_calderon_int": "int", "scaled_calderon_ext": "ext"}[preconditioner]
+
+
+def calderon_blocks(ops_L, ops_Y, M, eps_in, eps_out, formulation, part):
+    """Blocks of the preconditioning operator P of the Calderon-preconditioned
+    PMCHWT systems, typed in as printed: the full PMCHWT matrix (Eqs.
+    prec:calderon:int:full, prec:calderon:ext:full), its interior-kernel part
+    (Eqs. prec:calderon:int:int, prec:calderon:ext:int) or its exterior-kernel
+    part (Eqs. prec:calderon:int:ext, prec:calderon:ext:ext).  "Int" is the
+    Laplace kernel, "ext" the Yukawa kernel; D is the hypersingular and T the
+    adjoint double-layer operator.  e = eps_in / eps_out."""
+    if formulation not in (PMCHWT_INT, PMCHWT_EXT):
+        raise ValueError("Calderon preconditioning is defined for the PMCHWT formulations")
+    e = eps_in / eps_out
+    L, Y = ops_L, ops_Y
+    if part == "full":
+        return system_blocks(ops_L, ops_Y, M, eps_in, eps_out, formulation)
+    if formulation == PMCHWT_INT:
+        if part == "int":                           # Eq. prec:calderon:int:int
+            return -L["K"], L["V"], L["D"], L["T"]
+        if part == "ext":                           # Eq. prec:calderon:int:ext
+            return -Y["K"], e * Y["V"], (1.0 / e) * Y["D"], Y["T"]
+    else:
+        if part == "ext":                           # Eq. prec:calderon:ext:ext
+            return -Y["K"], Y["V"], Y["D"], Y["T"]
+        if part == "int":                           # Eq. prec:calderon:ext:int
+            return -L["K"], (1.0 / e) * L["V"], e * L["D"], L["T"]
+    raise ValueError(part)
+
+
+def calderon_matrix(mesh, eps_in, eps_out, kappa, formulation, part, nss: int = 4):
+    """Galerkin matrix of the preconditioning operator P (weak form, 2V x 2V)."""
+    oL = assemble(mesh, 0.0, ("V", "K", "D"), nss)
+    oY = assemble(mesh, kappa, ("V", "K", "D"), nss)
+    oL["T"] = oL["K"].T.copy()
+    oY["T"] = oY["K"].T.copy()
+    P11, P12, P21, P22 = calderon_blocks(oL, oY, mass(mesh), eps_in, eps_out, formulation, part)
+    return np.block([[P11, P12], [P21, P22]])
+
+
+def calderon_points(eps_in, eps_out):
+    """Accumulation points of the Calderon-preconditioned PMCHWT spectra:
+    full (Eq. precond:calderon:eigenval) and the two half points (Eq.
+    precond:calderon:eigenval_semi)."""
+    full = 0.5 + eps_out / (4.0 * eps_in) + eps_in / (4.0 * eps_out)
+    return full, 0.25 + eps_out / (4.0 * eps_in), 0.25 + eps_in / (4.0 * eps_out)
+
+
+def calderon_scales(eps_in, eps_out, formulation, part):
+    """(a, b) of the scaled mass matrix on top of a half Calderon
+    preconditioner.  The paper takes the two half points as a and b "or vice
+    versa"; which point belongs to which block row follows from the leading
+    (high-frequency) part of the product, where V D = D V = 1/4 for either
+    kernel while K K, K V and V T vanish: with A = [[., alpha V], [beta D, .]]
+    and P = [[., gamma V], [delta D, .]], P A becomes lower triangular with
+    diagonal (gamma beta, delta alpha) / 4, its eigenvalues.
+    Internal PMCHWT: alpha = 1 + e, beta = 1 + 1/e; its interior part has
+    gamma = delta = 1 -> (half_1, half_2), its exterior part gamma = e,
+    delta = 1/e -> (half_2, half_1).  External PMCHWT: alpha = 1 + 1/e,
+    beta = 1 + e; exterior part gamma = delta = 1 -> (half_2, half_1),
+    interior part gamma = 1/e, delta = e -> (half_1, half_2).  With P = A
+    both rows give the full point."""
+    _, h1, h2 = calderon_points(eps_in, eps_out)
+    if formulation == PMCHWT_INT:
+        return (h1, h2) if part == "int" else (h2, h1)
+    if formulation == PMCHWT_EXT:
+        return (h2, h1) if part == "ext" else (h1, h2)
+    raise ValueError("Calderon preconditioning is defined for the PMCHWT formulations")
+
+
+def calderon_preconditioner(mesh, P, a: float = 1.0, b: float = 1.0):
+    """v -> blockdiag(aM, bM)^-1 P blockdiag(M, M)^-1 v: the Galerkin form of
+    the operator product P A (the mass matrix maps the weak form of A back
+    to coefficients before P acts, and after it for the strong form)."""
+    M1 = mass_preconditioner(mesh)
+    Ms = mass_preconditioner(mesh, a, b)
+
+    def apply(v):
+        return Ms(P @ M1(v))
+    return apply
+
+
 def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
     """Unrestarted GMRES from x0 = 0 with modified Gram-Schmidt and Givens
     rotations; stops when the residual estimate drops below tol * |b|.
@@ -407,7 +501,8 @@ def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
 def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRECT,
           preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None):
     """Dense FP64 solve: returns dict(phi, dphi, dG, iterations, rel_residual).
-    preconditioner: True or "block_diag", False or None, "mass", "scaled_mass"."""
+    preconditioner: True or "block_diag", False or None, "mass", "scaled_mass",
+    or one of CALDERON (PMCHWT formulations)."""
     nv = mesh.n_vertices
     if A is None:
         A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss)
@@ -419,6 +514,12 @@ def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRE
     elif preconditioner in ("mass", "scaled_mass"):
         a, bb = mass_scales(eps_in, eps_out, formulation, preconditioner == "scaled_mass")
         P = mass_preconditioner(mesh, a, bb)
+    elif preconditioner in CALDERON:
+        part = calderon_part(preconditioner)
+        Pm = A if part == "full" else calderon_matrix(mesh, eps_in, eps_out, kappa, formulation, part, nss)
+        a, bb = (calderon_scales(eps_in, eps_out, formulation, part) if preconditioner.startswith("scaled")
+                 else (1.0, 1.0))
+        P = calderon_preconditioner(mesh, Pm, a, bb)
     elif preconditioner is False or preconditioner is None:
         P = lambda v: v
     else:

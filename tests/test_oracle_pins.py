@@ -444,3 +444,135 @@ def test_every_formulation_reaches_kirkwood(form):
         r = oracle.solve(m, ch, formulation=form, preconditioner=prec)
         errs.append(abs(r["dG"] - ref) / abs(ref))
     assert errs[1] < 0.03 and errs[1] < errs[0] / 2.5, (errs, ref)
+
+
+# ----------------------------------------------------------- Calderon (PMCHWT)
+def _sphere_symbol(l, kap, form, part, eps_in=4.0, eps_out=80.0):
+    """2 x 2 symbol of P A on degree-l spherical harmonics of the unit sphere,
+    from the textbook eigenvalues of V, K (= T) and D."""
+    L = sphere_eigenvalues(l, 1.0, 0.0)
+    Y = sphere_eigenvalues(l, 1.0, kap)
+    oL = {"V": L["V"], "K": L["K"], "D": L["D"], "T": L["K"]}
+    oY = {"V": Y["V"], "K": Y["K"], "D": Y["D"], "T": Y["K"]}
+    A = np.array(oracle.system_blocks(oL, oY, 1.0, eps_in, eps_out, form)).reshape(2, 2)
+    P = np.array(oracle.calderon_blocks(oL, oY, 1.0, eps_in, eps_out, form, part)).reshape(2, 2)
+    return P @ A
+
+
+@pytest.mark.parametrize("form", [oracle.PMCHWT_INT, oracle.PMCHWT_EXT])
+def test_calderon_products_match_sphere_symbols(form):
+    """Every block of the Calderon preconditioners (Eqs. prec:calderon:int,
+    prec:calderon:ext) and the mass-matrix coupling of the product: applied
+    to interpolated spherical harmonics (degrees 0-3, both trace slots), the
+    oracle's blockdiag(M, M)^-1 P blockdiag(M, M)^-1 A reproduces the 2 x 2
+    product of the textbook sphere symbols, converging at O(h^2).  A dropped
+    term, a wrong factor e or a wrong sign in any block of P or A moves some
+    entry by far more than the discretisation error."""
+    kap = 0.7
+    errs = {}
+    for f in (4, 8):
+        m = inputs.icosphere(f, 1.0)
+        nv = m.n_vertices
+        oL = oracle.assemble(m, 0.0, ("V", "K", "D"))
+        oY = oracle.assemble(m, kap, ("V", "K", "D"))
+        oL["T"] = oL["K"].T.copy()
+        oY["T"] = oY["K"].T.copy()
+        M = oracle.mass(m)
+        A = np.block([list(oracle.system_blocks(oL, oY, M, 4.0, 80.0, form))[:2],
+                      list(oracle.system_blocks(oL, oY, M, 4.0, 80.0, form))[2:]])
+        z = m.xyz[:, 2] / np.linalg.norm(m.xyz, axis=1)
+        xx = m.xyz[:, 0] / np.linalg.norm(m.xyz, axis=1)
+        harmonics = {0: np.ones_like(z), 1: z, 2: 1.5 * z * z - 0.5, 3: xx * (5 * z * z - 1)}
+        for part in ("full", "int", "ext"):
+            Pb = oracle.calderon_blocks(oL, oY, M, 4.0, 80.0, form, part)
+            pre = oracle.calderon_preconditioner(m, np.block([[Pb[0], Pb[1]], [Pb[2], Pb[3]]]))
+            worst = 0.0
+            for l, u in harmonics.items():
+                S = _sphere_symbol(l, kap, form, part)
+                got = np.zeros((2, 2))
+                for j in range(2):
+                    x = np.zeros(2 * nv)
+                    x[j * nv:(j + 1) * nv] = u
+                    w = pre(A @ x)
+                    for i in range(2):
+                        got[i, j] = (u @ M @ w[i * nv:(i + 1) * nv]) / (u @ M @ u)
+                worst = max(worst, np.abs(got - S).max() / np.abs(S).max())
+            errs[(f, part)] = worst
+    for part in ("full", "int", "ext"):
+        assert errs[(8, part)] < 6e-3 and errs[(8, part)] < errs[(4, part)] / 3.0, errs
+
+
+def test_calderon_points_and_scales_from_symbols():
+    """The accumulation points the paper prints (Eqs.
+    precond:calderon:eigenval, precond:calderon:eigenval_semi), and the block
+    row each half point belongs to (the scales of the scaled-mass variants),
+    against the sphere symbols of P A at high degree, where K and T vanish."""
+    full, h1, h2 = oracle.calderon_points(4.0, 80.0)
+    assert (full, h1, h2) == (5.5125, 5.25, 0.2625)
+    for form in (oracle.PMCHWT_INT, oracle.PMCHWT_EXT):
+        S = _sphere_symbol(20000, 0.0, form, "full")
+        assert np.abs(S - full * np.eye(2)).max() < 1e-3 * full
+        for part in ("int", "ext"):
+            a, b = oracle.calderon_scales(4.0, 80.0, form, part)
+            S = _sphere_symbol(20000, 0.0, form, part)
+            assert abs(S[0, 0] - a) < 1e-3 * a and abs(S[1, 1] - b) < 1e-3 * b, (form, part, S)
+            # triangular at high degree (V T and K V vanish, D K does not), so
+            # the diagonal entries are the eigenvalues
+            assert abs(S[0, 1]) < 1e-6
+            assert np.allclose(np.sort(np.linalg.eigvals(S).real), np.sort([a, b]), rtol=1e-3)
+            # and at the degrees a 642-vertex mesh resolves, Yukawa included
+            S6 = _sphere_symbol(6, 0.7, form, part)
+            assert abs(S6[0, 0] / a - 1) < 0.05 and abs(S6[1, 1] / b - 1) < 0.05
+
+
+def test_calderon_spectra_cluster():
+    """Discrete spectra of the Calderon-preconditioned PMCHWT systems on a
+    642-vertex sphere: the full variant gathers around the full point, the
+    half variants split into one cluster per block row at the half points,
+    and the scaled mass matrix on top joins them around 1."""
+    m = inputs.icosphere(8, 2.0)
+    nv = m.n_vertices
+    full, h1, h2 = oracle.calderon_points(4.0, 80.0)
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, oracle.PMCHWT_INT)
+    for prec in oracle.CALDERON:
+        part = oracle.calderon_part(prec)
+        Pm = A if part == "full" else oracle.calderon_matrix(m, 4.0, 80.0, 0.125, oracle.PMCHWT_INT, part)
+        a, b = oracle.calderon_scales(4.0, 80.0, oracle.PMCHWT_INT, part) if prec.startswith("scaled") else (1, 1)
+        pre = oracle.calderon_preconditioner(m, Pm, a, b)
+        B = np.column_stack([pre(A[:, j]) for j in range(2 * nv)])
+        ev = np.linalg.eigvals(B)
+        assert np.abs(ev.imag).max() < 1e-3 * np.abs(ev).max()
+        ev = np.sort(ev.real)
+        if part == "full":
+            assert np.quantile(np.abs(ev / full - 1), 0.9) < 0.08, prec
+        elif not prec.startswith("scaled"):
+            lo, hi = ev[:nv], ev[nv:]
+            assert np.quantile(np.abs(lo / h2 - 1), 0.9) < 0.1 and np.quantile(np.abs(hi / h1 - 1), 0.9) < 0.1
+        else:
+            assert np.quantile(np.abs(ev - 1), 0.9) < 0.1, prec
+
+
+@pytest.mark.parametrize("form", [oracle.PMCHWT_INT, oracle.PMCHWT_EXT])
+def test_calderon_solutions_and_iterations(form):
+    """Every Calderon variant solves the PMCHWT system itself (the same
+    solution as dense LU: the right-hand side is preconditioned like the
+    operator), and squaring the operator cuts GMRES iterations against the
+    mass-matrix preconditioner (the paper's Cases 15-26)."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, form)
+    bD, bN = oracle.rhs(m, ch, 4.0)
+    x = np.linalg.solve(A, oracle.system_rhs(bD, bN, form))
+    for prec in oracle.CALDERON:
+        r = oracle.solve(m, ch, formulation=form, preconditioner=prec, tol=1e-13, A=A)
+        u = np.concatenate([r["phi"], r["dphi"]])
+        ref_phi, ref_dphi = oracle.interior_traces(x, m.n_vertices, form)
+        ref = np.concatenate([ref_phi, ref_dphi])
+        assert np.abs(u - ref).max() < 1e-9 * np.abs(ref).max(), prec
+    m, ch = inputs.config_sphere(8, 10.0, 10, 8.0, 2)
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, form)
+    its = {p: oracle.solve(m, ch, formulation=form, preconditioner=p, A=A)["iterations"]
+           for p in ("mass",) + oracle.CALDERON}
+    assert its["calderon"] < its["mass"], its
+    h = {"int": "calderon_int", "ext": "calderon_ext"}
+    for part, p in h.items():
+        assert its["scaled_" + p] <= its[p], its
