@@ -74,6 +74,18 @@ typedef int32_t pb_status;
 #define PB_MASS         2  /* blockdiag(M, M)^-1, M the P1 mass matrix (Eq. prec:mass) */
 #define PB_SCALED_MASS  3  /* blockdiag(aM, bM)^-1 with a = 1 + e_out/e_in, b = 1 + e_in/e_out
                               (Eq. prec:mass:scaled; Juffer formulation only) */
+/* Calderon preconditioners, PMCHWT formulations only (Calderon preconditioning,
+ * Eqs. prec:calderon:int and prec:calderon:ext).  The system A u = b is solved
+ * as B A u = B b with B = blockdiag(aM, bM)^-1 P blockdiag(M, M)^-1: the
+ * Galerkin form of the operator product P A, mass matrices inverted as for
+ * PB_MASS.  P is assembled like A (same precision, operator mode, near field). */
+#define PB_CALDERON     4  /* P = A itself; a = b = 1 (Eqs. prec:calderon:int:full, ext:full) */
+#define PB_CALDERON_INT 5  /* P = the Laplace ("interior") part of A; a = b = 1 */
+#define PB_CALDERON_EXT 6  /* P = the Yukawa ("exterior") part of A; a = b = 1 */
+#define PB_SCALED_CALDERON_INT 7  /* PB_CALDERON_INT with a, b = the two half accumulation
+                                     points of Eq. precond:calderon:eigenval_semi, each on
+                                     the block row whose eigenvalues gather there */
+#define PB_SCALED_CALDERON_EXT 8  /* PB_CALDERON_EXT scaled the same way */
 
 #define PB_FP64         0  /* every kernel evaluation and sum in FP64 */
 #define PB_FP32         1  /* far-field kernel evaluations in FP32, tile sums FP32,
@@ -104,8 +116,8 @@ typedef struct {
     double eps_in;            /* interior permittivity (paper: 4) */
     double eps_out;           /* exterior permittivity (paper: 80) */
     double kappa;             /* inverse Debye length, 1/angstrom (paper: 0.125) */
-    int32_t formulation;      /* PB_DIRECT_INT or PB_JUFFER */
-    int32_t preconditioner;   /* PB_BLOCK_DIAG or PB_PREC_NONE */
+    int32_t formulation;      /* PB_DIRECT_INT ... PB_PMCHWT_EXT */
+    int32_t preconditioner;   /* PB_PREC_NONE ... PB_SCALED_CALDERON_EXT */
     int32_t precision;        /* PB_FP64, PB_FP32, PB_MIXED_BF16, PB_MIXED_FP16 */
     int32_t operator_mode;    /* PB_MATRIX_FREE, PB_ASSEMBLED, PB_AUTO */
     double tol;               /* relative preconditioned residual (paper: 1e-5) */
@@ -187,7 +199,7 @@ pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result 
 /* Solve for n_sets charge sets on one resident mesh.  In assembled modes the
  * right-hand sides are advanced together and every operator application is
  * one batched dense product (MFMA for 16-bit storage).  out[k] follows the
- * pb_result contract for set k. */
+ * pb_result contract for set k.  PB_E_STATE for the Calderon preconditioners. */
 pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *sets,
                          pb_result *out);
 
@@ -195,8 +207,8 @@ pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *se
  * Exposed for verification and measurement; each runs on the handle's stream
  * and returns after the result is on the host. */
 
-/* y = A x (flags & PB_APPLY_PRECOND: y = P^-1 A x) for the handle's
- * formulation.  x and y are host arrays of 2 n_vertices doubles laid out as
+/* y = A x (flags & PB_APPLY_PRECOND: y = P^-1 A x, or B A x for the Calderon
+ * preconditioners) for the handle's formulation.  x and y are host arrays of 2 n_vertices doubles laid out as
  * [trace_D; trace_N].  PB_APPLY_FAR_ONLY / PB_APPLY_NEAR_ONLY restrict the sum
  * to triangle pairs sharing no vertex / sharing a vertex (plus the mass terms). */
 #define PB_APPLY_PRECOND    1

@@ -409,6 +409,18 @@ def calderon_matrix(mesh, eps_in, eps_out, kappa, formulation, part, nss: int = 
     return np.block([[P11, P12], [P21, P22]])
 
 
+def calderon_rows(mesh, eps_in, eps_out, kappa, formulation, part, rows, x, nss: int = 4):
+    """Sampled rows of y = P x for large meshes: returns (y1[rows], y2[rows])."""
+    rows = np.asarray(rows, dtype=np.int32)
+    nv = mesh.n_vertices
+    oL = operator_rows(mesh, 0.0, rows, 0, ("V", "K", "D"), nss)
+    oY = operator_rows(mesh, kappa, rows, 0, ("V", "K", "D"), nss)
+    oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss)["K"]
+    oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss)["K"]
+    P11, P12, P21, P22 = calderon_blocks(oL, oY, mass_rows(mesh, rows), eps_in, eps_out, formulation, part)
+    return P11 @ x[:nv] + P12 @ x[nv:], P21 @ x[:nv] + P22 @ x[nv:]
+
+
 def calderon_points(eps_in, eps_out):
     """Accumulation points of the Calderon-preconditioned PMCHWT spectra:
     full (Eq. precond:calderon:eigenval) and the two half points (Eq.

@@ -38,6 +38,11 @@ PB_PREC_NONE = 0
 PB_BLOCK_DIAG = 1
 PB_MASS = 2
 PB_SCALED_MASS = 3
+PB_CALDERON = 4
+PB_CALDERON_INT = 5
+PB_CALDERON_EXT = 6
+PB_SCALED_CALDERON_INT = 7
+PB_SCALED_CALDERON_EXT = 8
 PB_FP64 = 0
 PB_FP32 = 1
 PB_MIXED_BF16 = 2

@@ -226,13 +226,14 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                     }
                 } else {
                     // (F_L + rK F_Y) d.n_s, G_L + rV G_Y, G_Y, (F_L + rT F_Y) d.n_t, without the
-                    // factors aL; swapped pair: K with d.n_t, T with d.n_s
+                    // factors aL; swapped pair: K with d.n_t, T with d.n_s.  LROW = 1: no
+                    // Laplace term in any block, F_Y and G_Y alone with the factors aY.
                     const R fy = ekk * ri3;
                     const R gy = ek * ri;
-                    const R a1 = ri3 + cf.rK * fy, a2 = ri3 + cf.rT * fy;
+                    const R a1 = LROW == 0 ? ri3 + cf.rK * fy : fy, a2 = LROW == 0 ? ri3 + cf.rT * fy : fy;
                     const R dnt = ts[21 + p] - ynt;
                     v[0] = a1 * dns;
-                    v[1] = ri + cf.rV * gy;
+                    v[1] = LROW == 0 ? ri + cf.rV * gy : gy;
                     v[2] = gy;
                     v[3] = a2 * dnt;
                     if (SYM) {
@@ -284,11 +285,14 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
             f[0] = sw * c00; f[1] = sw * c01; f[2] = sw * c10; f[3] = sw * c11;
             if (SYM) { f[4] = -sw * c00; f[5] = -sw * c10; }
         } else {
-            f[0] = sw * cf.aL[0][0];
-            f[1] = sw * cf.aL[0][1];
+            // leading factors: aL (ratios aY / aL inside the values), or aY (LROW = 1)
+            const R l00 = LROW == 0 ? cf.aL[0][0] : cf.aY[0][0], l01 = LROW == 0 ? cf.aL[0][1] : cf.aY[0][1];
+            const R l11 = LROW == 0 ? cf.aL[1][1] : cf.aY[1][1];
+            f[0] = sw * l00;
+            f[1] = sw * l01;
             f[2] = sw * cf.aY[1][0] * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
-            f[3] = -sw * cf.aL[1][1];
-            if (SYM) { f[4] = -sw * cf.aL[0][0]; f[5] = sw * cf.aL[1][1]; }
+            f[3] = -sw * l11;
+            if (SYM) { f[4] = -sw * l00; f[5] = sw * l11; }
         }
         // the rank-two target-side part, scaled once: value = f (blk + Cq)
 #pragma unroll
@@ -307,7 +311,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                     // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
                     const R cc = ts[28 + 3 * k] * ss[28 + 3 * l] + ts[29 + 3 * k] * ss[29 + 3 * l] +
                                  ts[30 + 3 * k] * ss[30 + 3 * l];
-                    val[2] += sc * cf.aL[1][0] * cc * Ssum;
+                    val[2] += sc * (LROW == 0 ? cf.aL[1][0] : cf.aY[1][0]) * cc * Ssum;
                 }
                 // a pair sharing a vertex may have produced inf or NaN: select, not scale
                 Quad<R> qd;
@@ -749,11 +753,11 @@ static size_t dense_bytes(const DevMesh &d)
     return n * ld * per;
 }
 
-bool dense_fits(const DevMesh &d)
+bool dense_fits(const DevMesh &d, int copies)
 {
     size_t freeb = 0, total = 0;
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) return false;
-    size_t need = dense_bytes(d);
+    size_t need = dense_bytes(d) * (size_t)copies;
     if (d.opt.memory_budget && d.bytes + need > d.opt.memory_budget) return false;
     return need < 0.8 * (double)freeb;
 }
@@ -862,8 +866,11 @@ static void assemble(DevMesh &d, S *A)
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 2; ++c) { cf.aL[r][c] = (R)fm.aL[r][c]; cf.aY[r][c] = (R)fm.aY[r][c]; }
     const bool direct = fm.family == 0;   // FORM 0: K and V rows; FORM 1: K, V / D, T
-    const int lrow = direct ? laplace_row(fm) : 0;
-    if (!direct) {
+    // FORM 0: the Laplace row; FORM 1: 1 if only Yukawa terms (a Calderon preconditioner's part)
+    const int lrow = direct ? laplace_row(fm) : yukawa_only(fm) ? 1 : 0;
+    if (!direct && lrow == 1) {
+        cf.rK = cf.rV = cf.rD = cf.rT = R(0);
+    } else if (!direct) {
         for (int r = 0; r < 2; ++r)
             for (int c = 0; c < 2; ++c)
                 if (fm.aL[r][c] == 0.0) fail(PB_E_STATE, "formulation without a Laplace term in a block");
@@ -889,7 +896,8 @@ static void assemble(DevMesh &d, S *A)
     hipLaunchKernelGGL((k_assemble_tile<R, S, F, TILE, true, L>), dim3(nb), dim3(TILE), 0, d.stream, T, V, cf,      \
                        D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col,       \
                        D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp)
-                if (!direct) ASM_SYM(1, 0);
+                if (!direct && lrow == 0) ASM_SYM(1, 0);
+                else if (!direct) ASM_SYM(1, 1);
                 else if (lrow == 0) ASM_SYM(0, 0);
                 else ASM_SYM(0, 1);
 #undef ASM_SYM
@@ -925,7 +933,8 @@ static void assemble(DevMesh &d, S *A)
     hipLaunchKernelGGL((k_assemble_tile<R, S, F, TILE, false, L>), grid, block, 0, d.stream, T, V, cf, tg, nt, grp, \
                        tl, nullptr, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp,       \
                        nullptr, (size_t)0)
-                if (!direct) ASM_ALL(1, 0);
+                if (!direct && lrow == 0) ASM_ALL(1, 0);
+                else if (!direct) ASM_ALL(1, 1);
                 else if (lrow == 0) ASM_ALL(0, 0);
                 else ASM_ALL(0, 1);
 #undef ASM_ALL

@@ -104,6 +104,9 @@ constexpr int kFarBlock = 256;
 //   and the hypersingular curl part, per source triangle:
 //   W  += [sum_pq w_p w_q (G_L + rD G_Y)] C_s     (times aD_L in k_far_finish)
 //   (FORM 1: rD = rV, the V sum is reused)
+// FORM 3: no Laplace term (the Yukawa part of a PMCHWT matrix, a Calderon
+//   preconditioner's operator): the FORM 1 sums with F_L, G_L dropped and the
+//   factors aK, aV, aT, aD taken from aY.
 // with d = x_p - y_q, G = e/r, F = e (1 + kappa r)/r^3 (e = 1 for Laplace).
 template <typename R, int FORM>
 __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> cf, const int32_t *__restrict__ tri,
@@ -163,6 +166,12 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
                     const R fl = dns * ri3;
                     a1[p] += fl * c1 + ri * c2;
                     a2[p] += e * (fl * tt * c3 + ri * c4);
+                } else if (FORM == 3) {
+                    const R fy = e * tt * ri3;
+                    const R gy = e * ri;
+                    a1[p] += fy * dns * c1 + gy * c2;
+                    a2[p] += fy * (xnt[p] - ynt) * c3 + kb1 * gy;
+                    g += R(rule_w(p) * rule_w(q)) * gy;
                 } else {
                     const R fy = e * tt * ri3;
                     const R gy = e * ri;
@@ -187,9 +196,9 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
 }
 
 // family 0: rows (Laplace, Yukawa), swapped when the Laplace row is row 2;
-// family 1: row 2 gets D's curl part times aDL
+// family 1: row 2 gets D's curl part times aD (aL of D, or aY without Laplace terms)
 template <typename R>
-__global__ void k_far_finish(int T, int S, int family, int swap, double aDL, const double *__restrict__ geo,
+__global__ void k_far_finish(int T, int S, int family, int swap, double aD, const double *__restrict__ geo,
                              const R *__restrict__ part, double *__restrict__ triout, DevCtl ctl)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -211,7 +220,7 @@ __global__ void k_far_finish(int T, int S, int family, int swap, double aDL, con
             y2 += w * pot[6 + p];
         }
         if (family == 1)
-            y2 += aDL * (g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14]);
+            y2 += aD * (g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14]);
         if (swap) { const double tmp = y1; y1 = y2; y2 = tmp; }
         triout[6 * (size_t)t + k] = sc * y1;
         triout[6 * (size_t)t + 3 + k] = sc * y2;
@@ -301,6 +310,10 @@ static void far_launch(DevMesh &d, const R *stat, const R *dyn)
         const int lr = laplace_row(f);
         cf.kL = (R)f.aL[lr][0]; cf.vL = (R)f.aL[lr][1];
         cf.kY = (R)f.aY[1 - lr][0]; cf.vY = (R)f.aY[1 - lr][1];
+    } else if (yukawa_only(f)) {
+        cf.aK = (R)f.aY[0][0]; cf.aV = (R)f.aY[0][1]; cf.aT = (R)(-f.aY[1][1]); cf.aDY = (R)f.aY[1][0];
+        cf.rK = cf.rV = cf.rD = cf.rT = R(0);
+        form = 3;
     } else {
         // the adjoint double layer's kernel is -F d.n_t: its factor carries the sign
         cf.aK = (R)f.aL[0][0]; cf.aV = (R)f.aL[0][1]; cf.aT = (R)(-f.aL[1][1]); cf.aDY = (R)f.aY[1][0];
@@ -317,6 +330,8 @@ static void far_launch(DevMesh &d, const R *stat, const R *dyn)
         hipLaunchKernelGGL((k_far<R, 0>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     else if (form == 1)
         hipLaunchKernelGGL((k_far<R, 1>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
+    else if (form == 3)
+        hipLaunchKernelGGL((k_far<R, 3>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     else
         hipLaunchKernelGGL((k_far<R, 2>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     HIPCHECK(hipGetLastError());
@@ -346,12 +361,12 @@ void launch_far_finish(DevMesh &d, bool fp32)
     dim3 grid((T + 255) / 256), block(256);
     const FormCoef &f = d.fm;
     const int swap = f.family == 0 && laplace_row(f) == 1;
-    const double aDL = f.family == 1 ? f.aL[1][0] : 0.0;
+    const double aD = f.family == 1 ? (yukawa_only(f) ? f.aY[1][0] : f.aL[1][0]) : 0.0;
     if (fp32)
-        hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, f.family, swap, aDL, d.geo,
+        hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, f.family, swap, aD, d.geo,
                            (const float *)d.part, d.triout, d.ctl);
     else
-        hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, f.family, swap, aDL, d.geo,
+        hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, f.family, swap, aD, d.geo,
                            (const double *)d.part, d.triout, d.ctl);
     HIPCHECK(hipGetLastError());
 }

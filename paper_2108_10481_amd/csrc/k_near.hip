@@ -408,13 +408,18 @@ __global__ void k_cheb_final(int V, double sa, double sb, const double *__restri
 
 void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl)
 {
-    const int V = d.hm.V;
-    if (nvec < 1 || nvec > kMassBatch) fail(PB_E_INVALID_ARG, "mass preconditioner batch size");
     double sa = 1.0, sb = 1.0;
     if (d.prm.preconditioner == PB_SCALED_MASS) {
         sa = 1.0 / (1.0 + d.prm.eps_out / d.prm.eps_in);
         sb = 1.0 / (1.0 + d.prm.eps_in / d.prm.eps_out);
     }
+    mass_precond(d, nvec, in, out, ctl, sa, sb);
+}
+
+void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl, double sa, double sb)
+{
+    const int V = d.hm.V;
+    if (nvec < 1 || nvec > kMassBatch) fail(PB_E_INVALID_ARG, "mass preconditioner batch size");
     const size_t n = 2 * (size_t)V * kMassBatch;
     double *x = d.cheb, *r = d.cheb + n, *dv[2] = {d.cheb + 2 * n, d.cheb + 3 * n};
     const dim3 g((unsigned)((2 * V + 255) / 256), (unsigned)nvec), b(256);
@@ -432,19 +437,29 @@ void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const Dev
     HIPCHECK(hipGetLastError());
 }
 
-void launch_near_assemble(DevMesh &d)
+void launch_near_values(DevMesh &d, const FormCoef &f, double *N, double *Mval)
 {
     NearCoef cf;
     cf.kappa = d.prm.kappa;
-    cf.f = d.fm;
+    cf.f = f;
+    const int64_t nnz = d.nnz();
+    hipLaunchKernelGGL(k_near_slots, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, d.stream, nnz, cf,
+                       d.slot_ptr, d.slot_code, d.pair_t, d.pair_s, d.pair_rev, d.geo, d.pairblk, d.pair_sums, N,
+                       Mval);
+    HIPCHECK(hipGetLastError());
+}
+
+// near-field values of the formulation (and of a Calderon preconditioner's
+// operator P when it is not A), mass matrix, block-diagonal preconditioner
+void launch_near_assemble(DevMesh &d)
+{
     const int V = d.hm.V;
-    const int64_t np = d.npair(), nnz = d.nnz();
-    if (cf.f.family == 1)
+    const int64_t np = d.npair();
+    if (d.fm.family == 1)
         hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, d.stream, np, d.pairblk,
                            d.pair_sums);
-    hipLaunchKernelGGL(k_near_slots, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, d.stream, nnz, cf,
-                       d.slot_ptr, d.slot_code, d.pair_t, d.pair_s, d.pair_rev, d.geo, d.pairblk, d.pair_sums, d.N,
-                       d.Mval);
+    launch_near_values(d, d.fm, d.N, d.Mval);
+    if (d.NP) launch_near_values(d, d.fmP, d.NP, nullptr);
     if (d.Mval)
         hipLaunchKernelGGL(k_mass_diag, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, d.diag_slot, d.Mval,
                            d.Mdinv);

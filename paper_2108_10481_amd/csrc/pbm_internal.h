@@ -141,6 +141,12 @@ struct FormCoef {
 };
 FormCoef formulation_coef(int formulation, double eps_in, double eps_out);
 int laplace_row(const FormCoef &f);   // family 0: the row with only Laplace terms
+// family 1 with no Laplace term in any block (the Yukawa part of a PMCHWT matrix)
+bool yukawa_only(const FormCoef &f);
+// Calderon preconditioners: the operator P (the PMCHWT matrix or one kernel's
+// part of it) and the scales (a, b) of blockdiag(aM, bM)^-1 on the left
+FormCoef calderon_coef(int formulation, int preconditioner, double eps_in, double eps_out);
+void calderon_scales(int formulation, int preconditioner, double eps_in, double eps_out, double *a, double *b);
 
 // HIP-event timing of the dominant kernels on the stream they run on.
 // kind 0: far-field operator product (matrix-free kernel or dense GEMV),
@@ -232,6 +238,13 @@ struct DevMesh {
     Profiler prof;
     int64_t npair() const { return (int64_t)hm.pair_s.size(); }
     FormCoef fm;                    // the formulation's block coefficients
+    // Calderon preconditioners: P's coefficients, near-field values (4 x nnz)
+    // and assembled far field; NP and denseP stay null when P is A itself.
+    // cal1, cal2: 2V work vectors of the product chain.
+    FormCoef fmP;
+    double *NP = nullptr;
+    Dense *denseP = nullptr;
+    double *cal1 = nullptr, *cal2 = nullptr;
     int64_t nnz() const { return (int64_t)hm.col.size(); }
     void *alloc(size_t n);
     ~DevMesh();
@@ -241,6 +254,8 @@ struct DevMesh {
 void launch_geometry(DevMesh &d);
 void launch_near_field(DevMesh &d);
 void launch_near_assemble(DevMesh &d);
+// near-field values of coefficients f into N (4 x nnz); Mval (may be null): the mass matrix
+void launch_near_values(DevMesh &d, const FormCoef &f, double *N, double *Mval);
 void launch_source_prep(DevMesh &d, const double *x, bool fp32);
 void launch_far(DevMesh &d, bool fp32);
 void launch_far_finish(DevMesh &d, bool fp32);
@@ -265,7 +280,7 @@ int gmres_solve(DevMesh &d, const double *pb, double *x, double tol, int max_ite
 void destroy_graphs(DevMesh &d);
 
 // assembled far field and mixed precision (k_dense.hip)
-bool dense_fits(const DevMesh &d);
+bool dense_fits(const DevMesh &d, int copies = 1);
 void build_dense(DevMesh &d);
 void destroy_dense(DevMesh &d);
 void dense_apply(DevMesh &d, const double *x, double *yfar);
@@ -291,7 +306,19 @@ inline bool mass_mode(const DevMesh &d)
 {
     return d.prm.preconditioner == PB_MASS || d.prm.preconditioner == PB_SCALED_MASS;
 }
+inline bool is_calderon(int preconditioner)
+{
+    return preconditioner >= PB_CALDERON && preconditioner <= PB_SCALED_CALDERON_EXT;
+}
+inline bool calderon_mode(const DevMesh &d) { return is_calderon(d.prm.preconditioner); }
+// P is a separate operator (a kernel's part of A), not A itself
+inline bool calderon_part_mode(const DevMesh &d) { return calderon_mode(d) && d.prm.preconditioner != PB_CALDERON; }
+// blockdiag(M, M)^-1 scaled by (sa, sb) = (1/a, 1/b) per half: of the mass
+// preconditioners (first form) or explicit
 void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl);
+void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl, double sa, double sb);
+// Calderon chain on a plain vector: out (offset by ctl) = blockdiag(aM, bM)^-1 P blockdiag(M, M)^-1 in
+void calderon_left(DevMesh &d, const double *in, double *out, const DevCtl &ctl);
 void kr_graph_iteration_tail(hipStream_t s, int n, int m, double *Vb, GState *st, double *H, double *cs, double *sn,
                              double *g, double *h1, double *h2);
 

@@ -47,6 +47,8 @@ DevMesh::~DevMesh()
         for (hipEvent_t e : prof.ev[k]) (void)hipEventDestroy(e);
     destroy_graphs(*this);
     destroy_dense(*this);
+    std::swap(dense, denseP);
+    destroy_dense(*this);
     destroy_batch(*this);
     for (void *p : allocs) (void)hipFreeAsync(p, stream);
     if (stream) (void)hipStreamSynchronize(stream);
@@ -72,10 +74,12 @@ static void check_options(const pb_options *o)
     if (!(o->eps_in > 0) || !(o->eps_out > 0) || !(o->kappa >= 0) || !std::isfinite(o->kappa))
         fail(PB_E_INVALID_ARG, "eps_in, eps_out must be > 0 and kappa >= 0");
     if (o->formulation < PB_DIRECT_INT || o->formulation > PB_PMCHWT_EXT) fail(PB_E_INVALID_ARG, "unknown formulation");
-    if (o->preconditioner < PB_PREC_NONE || o->preconditioner > PB_SCALED_MASS)
+    if (o->preconditioner < PB_PREC_NONE || o->preconditioner > PB_SCALED_CALDERON_EXT)
         fail(PB_E_INVALID_ARG, "unknown preconditioner");
     if (o->preconditioner == PB_SCALED_MASS && o->formulation != PB_JUFFER)
         fail(PB_E_INVALID_ARG, "the scaled mass preconditioner is defined for the Juffer formulation");
+    if (is_calderon(o->preconditioner) && o->formulation != PB_PMCHWT_INT && o->formulation != PB_PMCHWT_EXT)
+        fail(PB_E_INVALID_ARG, "Calderon preconditioners are defined for the PMCHWT formulations");
     if (o->precision < PB_FP64 || o->precision > PB_MIXED_FP16) fail(PB_E_INVALID_ARG, "unknown precision");
     if (o->operator_mode < PB_MATRIX_FREE || o->operator_mode > PB_AUTO) fail(PB_E_INVALID_ARG, "unknown operator mode");
     if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
@@ -139,6 +143,61 @@ FormCoef formulation_coef(int formulation, double eps_in, double eps_out)
     return f;
 }
 
+bool yukawa_only(const FormCoef &f)
+{
+    if (f.family != 1) return false;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c)
+            if (f.aL[r][c] != 0.0) return false;
+    return true;
+}
+
+// Calderon preconditioning (Eqs. prec:calderon:int, prec:calderon:ext): P is
+// the PMCHWT matrix itself or the part of it with one kernel.  The PMCHWT rows
+// combine interior (Laplace) and exterior (Yukawa) trace equations with
+// c_I = -1, c_E = 1 and no identity term; keeping only the interior or the
+// exterior operators gives the printed halves, e.g. for the internal system
+// [[-K_L, V_L], [D_L, T_L]] and [[-K_Y, e V_Y], [D_Y / e, T_Y]].
+FormCoef calderon_coef(int formulation, int preconditioner, double eps_in, double eps_out)
+{
+    FormCoef f = formulation_coef(formulation, eps_in, eps_out);
+    const bool keep_int = preconditioner == PB_CALDERON || preconditioner == PB_CALDERON_INT ||
+                          preconditioner == PB_SCALED_CALDERON_INT;
+    const bool keep_ext = preconditioner == PB_CALDERON || preconditioner == PB_CALDERON_EXT ||
+                          preconditioner == PB_SCALED_CALDERON_EXT;
+    for (int r = 0; r < 2; ++r) {
+        for (int c = 0; c < 2; ++c) {
+            f.mass[r][c] = 0.0;
+            if (!keep_int) f.aL[r][c] = 0.0;
+            if (!keep_ext) f.aY[r][c] = 0.0;
+        }
+        f.rhsD[r] = f.rhsN[r] = 0.0;
+    }
+    return f;
+}
+
+// (a, b) of blockdiag(aM, bM) for the scaled halves: the two half points
+// h1 = 1/4 + eps_out/(4 eps_in), h2 = 1/4 + eps_in/(4 eps_out) (Eq.
+// precond:calderon:eigenval_semi), each on the block row whose eigenvalues
+// gather there.  At high frequency V D = D V -> 1/4 for both kernels while
+// K K, K V and V T vanish, so P A tends to a triangular matrix with diagonal
+// (gamma beta, delta alpha) / 4 for A = [[., alpha V], [beta D, .]] and
+// P = [[., gamma V], [delta D, .]]: internal system alpha = 1 + e, beta = 1 + 1/e,
+// external system alpha = 1 + 1/e, beta = 1 + e (e = eps_in / eps_out).
+void calderon_scales(int formulation, int preconditioner, double eps_in, double eps_out, double *a, double *b)
+{
+    *a = *b = 1.0;
+    if (preconditioner != PB_SCALED_CALDERON_INT && preconditioner != PB_SCALED_CALDERON_EXT) return;
+    const double h1 = 0.25 + eps_out / (4.0 * eps_in), h2 = 0.25 + eps_in / (4.0 * eps_out);
+    // internal system: interior part gamma = delta = 1 -> (h1, h2), exterior part
+    // gamma = e, delta = 1/e -> (h2, h1); external system: interior part
+    // gamma = 1/e, delta = e -> (h1, h2), exterior part -> (h2, h1)
+    (void)formulation;
+    const bool interior_part = preconditioner == PB_SCALED_CALDERON_INT;
+    *a = interior_part ? h1 : h2;
+    *b = interior_part ? h2 : h1;
+}
+
 // direct formulations: one row has only Laplace, the other only Yukawa terms;
 // returns the Laplace row
 int laplace_row(const FormCoef &f)
@@ -148,6 +207,32 @@ int laplace_row(const FormCoef &f)
     fail(PB_E_STATE, "direct formulation with mixed kernels in one row");
 }
 
+// Scope in which the handle's operator fields (coefficients, near-field
+// values, assembled far field) are those of the Calderon preconditioner's
+// operator P, so the formulation's launchers build or apply P instead of A.
+// Launches recorded inside the scope (eager or captured) keep P's buffers.
+struct PrecondOperator {
+    DevMesh &d;
+    const int32_t *vpos;
+    explicit PrecondOperator(DevMesh &dm) : d(dm), vpos(dm.dense_vpos)
+    {
+        if (d.dense && d.denseP) d.denseP->level = d.dense->level;   // same storage level as A
+        swap();
+        if (d.dense) d.dense_vpos = d.dense->vpos;
+    }
+    ~PrecondOperator()
+    {
+        swap();
+        d.dense_vpos = vpos;
+    }
+    void swap()
+    {
+        std::swap(d.fm, d.fmP);
+        std::swap(d.N, d.NP);
+        std::swap(d.dense, d.denseP);
+    }
+};
+
 // every device-side setup stage: geometry, near field, near blocks +
 // preconditioner, dense far field (assembled modes)
 static void device_setup(DevMesh &d)
@@ -155,7 +240,13 @@ static void device_setup(DevMesh &d)
     launch_geometry(d);
     launch_near_field(d);
     launch_near_assemble(d);
-    if (d.want_dense) build_dense(d);
+    if (d.want_dense) {
+        build_dense(d);
+        if (calderon_part_mode(d)) {
+            PrecondOperator use(d);
+            build_dense(d);
+        }
+    }
 }
 
 static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
@@ -167,6 +258,8 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->prm = {opt->eps_in, opt->eps_out, opt->kappa, opt->formulation, opt->preconditioner, opt->precision,
               opt->operator_mode};
     d->fm = formulation_coef(opt->formulation, opt->eps_in, opt->eps_out);
+    if (is_calderon(opt->preconditioner))
+        d->fmP = calderon_coef(opt->formulation, opt->preconditioner, opt->eps_in, opt->eps_out);
     build_host_mesh(mesh, d->hm);   // validation happens before any device call
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) fail(PB_E_DEVICE, "no HIP device available");
@@ -204,13 +297,18 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->pairblk = (double *)d->alloc(sizeof(double) * 36 * d->npair());
     d->N = (double *)d->alloc(sizeof(double) * 4 * d->nnz());
     d->pinv = (double *)d->alloc(sizeof(double) * 4 * V);
-    if (opt->preconditioner == PB_MASS || opt->preconditioner == PB_SCALED_MASS) {
+    if (mass_mode(*d) || calderon_mode(*d)) {
         d->Mval = (double *)d->alloc(sizeof(double) * std::max<int64_t>(d->nnz(), 1));
         d->Mdinv = (double *)d->alloc(sizeof(double) * V);
         // Chebyshev state (x, r, d, d') and the unpreconditioned products, for
         // up to kMassBatch systems
         d->cheb = (double *)d->alloc(sizeof(double) * 4 * kMassBatch * 2 * (size_t)V);
         d->mtmp = (double *)d->alloc(sizeof(double) * kMassBatch * 2 * (size_t)V);
+    }
+    if (calderon_mode(*d)) {
+        d->cal1 = (double *)d->alloc(sizeof(double) * 2 * (size_t)V);
+        d->cal2 = (double *)d->alloc(sizeof(double) * 2 * (size_t)V);
+        if (calderon_part_mode(*d)) d->NP = (double *)d->alloc(sizeof(double) * 4 * d->nnz());
     }
     d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
     d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
@@ -226,7 +324,7 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->yfar = (double *)d->alloc(sizeof(double) * 2 * V);
 
     d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
-                    (opt->operator_mode == PB_AUTO && dense_fits(*d));
+                    (opt->operator_mode == PB_AUTO && dense_fits(*d, calderon_part_mode(*d) ? 2 : 1));
     device_setup(*d);
     HIPCHECK(hipStreamSynchronize(d->stream));
     d->t_setup = now() - t0;
@@ -256,35 +354,65 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     // FP64 matrix, or FP32 matrix plus the 16-bit copy (mixed) or the assembly's
     // side matrix (FP32) of the same size
     const double dense = n * 2.0 * Vp * (o->precision == PB_FP64 ? 8.0 : 6.0);
-    if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense;
-    if (o->preconditioner == PB_MASS || o->preconditioner == PB_SCALED_MASS)
+    const bool cal = is_calderon(o->preconditioner), cal_part = cal && o->preconditioner != PB_CALDERON;
+    if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense * (cal_part ? 2.0 : 1.0);
+    if (o->preconditioner == PB_MASS || o->preconditioner == PB_SCALED_MASS || cal)
         b += 5.0 * kMassBatch * n * 8 + 20.0 * v * 8 + v * 8;   // Chebyshev state, products, M, 1 / M_ii
+    if (cal) b += 2.0 * n * 8 + (cal_part ? 4.0 * 20.0 * v * 8 : 0.0);   // work vectors, P's near field
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
     return (size_t)(b * 1.1);
 }
 
-// y = A x (or P^-1 A x) on device vectors, on stream s of the handle.
+// far-field product of the current operator fields into d.yfar (dense) or
+// the per-triangle outputs (matrix-free); returns launch_gather's use_far
+static int far_product(DevMesh &d, const double *x, int flags)
+{
+    if (flags & PB_APPLY_NEAR_ONLY) return 0;
+    if (d.dense) {
+        dense_apply(d, x, d.yfar);
+        return 2;
+    }
+    const bool fp32 = d.prm.precision == PB_FP32;
+    launch_source_prep(d, x, fp32);
+    launch_far(d, fp32);
+    launch_far_finish(d, fp32);
+    return 1;
+}
+
+// out = blockdiag(aM, bM)^-1 P blockdiag(M, M)^-1 in, in a plain vector, out
+// offset like a captured iteration's output (ctl).  The inner steps honour the
+// stop flag but take no offsets.
+void calderon_left(DevMesh &d, const double *in, double *out, const DevCtl &ctl)
+{
+    const DevCtl inner{nullptr, ctl.skip, 0};
+    mass_precond(d, 1, in, d.cal1, inner, 1.0, 1.0);
+    {
+        const DevCtl keep = d.ctl;
+        d.ctl = inner;
+        std::unique_ptr<PrecondOperator> use(calderon_part_mode(d) ? new PrecondOperator(d) : nullptr);
+        const int use_far = far_product(d, d.cal1, 0);
+        launch_gather(d, d.cal1, d.cal2, 0, use_far, true);
+        use.reset();
+        d.ctl = keep;
+    }
+    double a = 1.0, b = 1.0;
+    calderon_scales(d.prm.formulation, d.prm.preconditioner, d.prm.eps_in, d.prm.eps_out, &a, &b);
+    mass_precond(d, 1, d.cal2, out, ctl, 1.0 / a, 1.0 / b);
+}
+
+// y = A x (or P^-1 A x, or B A x for the Calderon preconditioners) on device
+// vectors, on stream s of the handle.
 void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream_t s)
 {
     hipStream_t keep = d.stream;
     if (s) d.stream = s;
-    const bool near_only = flags & PB_APPLY_NEAR_ONLY;
-    int use_far = 0;
-    if (!near_only) {
-        if (d.dense) {
-            dense_apply(d, x, d.yfar);
-            use_far = 2;
-        } else {
-            const bool fp32 = d.prm.precision == PB_FP32;
-            launch_source_prep(d, x, fp32);
-            launch_far(d, fp32);
-            launch_far_finish(d, fp32);
-            use_far = 1;
-        }
-    }
+    const int use_far = far_product(d, x, flags);
     if ((flags & PB_APPLY_PRECOND) && mass_mode(d)) {
         launch_gather(d, x, d.mtmp, flags & ~PB_APPLY_PRECOND, use_far, false);
         mass_precond(d, 1, d.mtmp, y, d.ctl);
+    } else if ((flags & PB_APPLY_PRECOND) && calderon_mode(d)) {
+        launch_gather(d, x, d.mtmp, flags & ~PB_APPLY_PRECOND, use_far, false);
+        calderon_left(d, d.mtmp, y, d.ctl);
     } else {
         launch_gather(d, x, y, flags, use_far, true);
     }
@@ -626,6 +754,7 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
     HIPCHECK(hipStreamSynchronize(d.stream));
     double t1 = now();
     if (mass_mode(d)) mass_precond(d, 1, b, pb, DevCtl());
+    else if (calderon_mode(d)) calderon_left(d, b, pb, DevCtl());
     else kr_precond(d.stream, V, d.pinv, b, pb);
     HIPCHECK(hipStreamSynchronize(d.stream));
     double t2 = now();
@@ -769,6 +898,7 @@ pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *se
 {
     PB_TRY
     if (!h || n_sets < 1 || !sets || !out) fail(PB_E_INVALID_ARG, "bad pb_solve_multi arguments");
+    if (calderon_mode(*h->d)) fail(PB_E_STATE, "batched solves do not support the Calderon preconditioners");
     return solve_multi(*h->d, n_sets, sets, out);
     PB_CATCH
 }

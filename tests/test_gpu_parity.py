@@ -625,3 +625,120 @@ def test_lu_full_size(sphere32):
                                                           preconditioner=pbm.PB_MASS))
     for g in (r32, gbf):
         assert g["status"] == pbm.PB_OK and abs(g["dG"] - g64["dG"]) < 1e-4 * abs(g64["dG"])
+
+
+# ------------------------------------------- Calderon preconditioners (PMCHWT)
+_CALDERON = [(pbm.PB_CALDERON, "calderon"), (pbm.PB_CALDERON_INT, "calderon_int"),
+             (pbm.PB_CALDERON_EXT, "calderon_ext"), (pbm.PB_SCALED_CALDERON_INT, "scaled_calderon_int"),
+             (pbm.PB_SCALED_CALDERON_EXT, "scaled_calderon_ext")]
+
+
+def _calderon_ref(m, base, form, name):
+    part = oracle.calderon_part(name)
+    Pb = oracle.calderon_blocks(base[0], base[1], base[2], 4.0, 80.0, form, part)
+    a, b = oracle.calderon_scales(4.0, 80.0, form, part) if name.startswith("scaled") else (1.0, 1.0)
+    return oracle.calderon_preconditioner(m, np.block([[Pb[0], Pb[1]], [Pb[2], Pb[3]]]), a, b)
+
+
+@pytest.mark.parametrize("prec,name", _CALDERON)
+@pytest.mark.parametrize("form", [pbm.PB_PMCHWT_INT, pbm.PB_PMCHWT_EXT])
+def test_calderon_product(meshes, base_operators, form, prec, name):
+    """B A x with B = blockdiag(aM, bM)^-1 P blockdiag(M, M)^-1 (Eqs.
+    prec:calderon:int, prec:calderon:ext) on the 980-triangle star, against
+    the oracle's dense P, A and Cholesky mass solves: FP64 matrix-free and
+    assembled within the two Chebyshev mass inverses (2e-9), FP32 within the
+    FP32 far field's 1e-5 carried through M^-1 P M^-1, where the rounding of
+    the far field is spread over all frequencies (2e-6; 2.5e-7 measured)."""
+    m = meshes["star7"]
+    A = _system(base_operators, form)
+    B = _calderon_ref(m, base_operators, form, name)
+    x = np.random.default_rng(91 + prec).standard_normal(2 * m.n_vertices)
+    ref = B(A @ x)
+    for p, mode, tol in ((pbm.PB_FP64, pbm.PB_MATRIX_FREE, 2e-9), (pbm.PB_FP64, pbm.PB_ASSEMBLED, 2e-9),
+                         (pbm.PB_FP32, pbm.PB_ASSEMBLED, 2e-6), (pbm.PB_FP32, pbm.PB_MATRIX_FREE, 2e-6)):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, p, operator_mode=mode, preconditioner=prec)) as h:
+            y = pbm.pb_mesh_apply(h, x)
+            yp = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+            yp2 = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+        assert np.array_equal(yp, yp2)
+        assert _rel(y, A @ x) < (1e-12 if p == pbm.PB_FP64 else 1e-5)
+        print(f"calderon product form {form} {name} prec {p} mode {mode}: rel {_rel(yp, ref):.2e}")
+        assert _rel(yp, ref) < tol, (p, mode, _rel(yp, ref))
+
+
+@pytest.mark.parametrize("prec,name", _CALDERON)
+@pytest.mark.parametrize("form", [pbm.PB_PMCHWT_INT, pbm.PB_PMCHWT_EXT])
+def test_calderon_solve_parity(form, prec, name):
+    """Kirkwood sphere: each Calderon variant takes the oracle's iterations and
+    gives its Delta G; at tight tolerance the traces agree with the oracle's;
+    FP32 assembled and BF16 mixed solves land within 1e-4."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    ref = oracle.solve(m, ch, formulation=form, preconditioner=name)
+    got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=prec))
+    assert got["status"] == pbm.PB_OK
+    assert got["iterations"] == ref["iterations"], (got["iterations"], ref["iterations"])
+    assert abs(got["dG"] - ref["dG"]) < 1e-6 * abs(ref["dG"])
+    tight = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=prec, tol=1e-11))
+    reft = oracle.solve(m, ch, formulation=form, preconditioner=name, tol=1e-11, A=ref["A"])
+    u = np.concatenate([tight["phi"], tight["dphi"]])
+    assert _rel(u, np.concatenate([reft["phi"], reft["dphi"]])) < 1e-8
+    for p in (pbm.PB_FP32, pbm.PB_MIXED_BF16):
+        g = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, p, operator_mode=pbm.PB_ASSEMBLED,
+                                                            preconditioner=prec))
+        assert g["status"] == pbm.PB_OK and abs(g["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"]), (p, g["dG"])
+
+
+def test_calderon_graph_and_refusals(meshes):
+    """Captured and eager GMRES agree with a half Calderon preconditioner on the
+    star (FP32 assembled, two dense operators); Calderon preconditioners are
+    refused for other formulations and for batched solves."""
+    m = meshes["star7"]
+    sets = _sets(900, 2)
+    for prec in (pbm.PB_CALDERON, pbm.PB_SCALED_CALDERON_EXT):
+        og = _opts(pbm.PB_PMCHWT_INT, pbm.PB_FP32, preconditioner=prec, operator_mode=pbm.PB_ASSEMBLED)
+        oe = _opts(pbm.PB_PMCHWT_INT, pbm.PB_FP32, preconditioner=prec, operator_mode=pbm.PB_ASSEMBLED,
+                   use_graph=0)
+        with pbm.MeshHandle(m.xyz, m.tri, og) as hg, pbm.MeshHandle(m.xyz, m.tri, oe) as he:
+            for c in sets:
+                rg = pbm.pb_mesh_solve(hg, c.xyz, c.q)
+                re = pbm.pb_mesh_solve(he, c.xyz, c.q)
+                assert rg["status"] == pbm.PB_OK
+                assert rg["iterations"] == re["iterations"] and abs(rg["dG"] - re["dG"]) <= 1e-12 * abs(re["dG"])
+            with pytest.raises(pbm.PbError):
+                pbm.pb_solve_multi(hg, [(c.xyz, c.q) for c in sets])
+    with pytest.raises(pbm.PbError):
+        pbm.pb_solve(m.xyz, m.tri, sets[0].xyz, sets[0].q, _opts(pbm.PB_JUFFER, preconditioner=pbm.PB_CALDERON))
+
+
+def test_calderon_full_size(sphere32):
+    """20480-triangle sphere, internal PMCHWT, FP32 assembled: with
+    z = blockdiag(M, M)^-1 A x from the mass-preconditioned handle, sampled
+    rows of M (B A x) equal the oracle's rows of P z for the full and both half
+    operators; B_int A x + B_ext A x = B_full A x at every row; the full
+    Calderon solve needs fewer iterations than the mass-preconditioned one and
+    reaches the same Delta G."""
+    m, ch = sphere32
+    nv = m.n_vertices
+    form = pbm.PB_PMCHWT_INT
+    rng = np.random.default_rng(53)
+    x = rng.standard_normal(2 * nv)
+    rows = np.sort(rng.choice(nv, 6, replace=False))
+    Mr = oracle.mass_rows(m, rows)
+    base = dict(operator_mode=pbm.PB_ASSEMBLED)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, preconditioner=pbm.PB_MASS, **base)) as h:
+        z = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+        rm = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+    out = {}
+    for prec, part in ((pbm.PB_CALDERON, "full"), (pbm.PB_CALDERON_INT, "int"), (pbm.PB_CALDERON_EXT, "ext")):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, preconditioner=prec, **base)) as h:
+            out[part] = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+            if part == "full":
+                rc = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+        r1, r2 = oracle.calderon_rows(m, 4.0, 80.0, 0.125, oracle.PMCHWT_INT, part, rows, z)
+        got = np.concatenate([Mr @ out[part][:nv], Mr @ out[part][nv:]])
+        print(f"calderon full size {part}: rel {_rel(got, np.concatenate([r1, r2])):.2e}")
+        assert _rel(got, np.concatenate([r1, r2])) < 2e-6, part
+    assert _rel(out["int"] + out["ext"], out["full"]) < 1e-6
+    print(f"calderon full size iterations: mass {rm['iterations']} calderon {rc['iterations']}")
+    assert rc["status"] == pbm.PB_OK and rc["iterations"] < rm["iterations"]
+    assert abs(rc["dG"] - rm["dG"]) < 1e-4 * abs(rm["dG"])

@@ -92,9 +92,13 @@ def test_host_validation_rejects_bad_meshes(pbm):
     assert _create_status(pbm, m.xyz, m.tri, eps_in=-1.0) == pbm.PB_E_INVALID_ARG
     assert _create_status(pbm, m.xyz, m.tri, formulation=10) == pbm.PB_E_INVALID_ARG
     assert _create_status(pbm, m.xyz, m.tri, singular_order=0) == pbm.PB_E_INVALID_ARG
-    assert _create_status(pbm, m.xyz, m.tri, preconditioner=4) == pbm.PB_E_INVALID_ARG
-    # the scaled mass matrix is defined for the Juffer formulation only
+    assert _create_status(pbm, m.xyz, m.tri, preconditioner=9) == pbm.PB_E_INVALID_ARG
+    # the scaled mass matrix is defined for the Juffer formulation only, the
+    # Calderon preconditioners for the PMCHWT formulations only
     assert _create_status(pbm, m.xyz, m.tri, preconditioner=pbm.PB_SCALED_MASS) == pbm.PB_E_INVALID_ARG
+    for prec in range(pbm.PB_CALDERON, pbm.PB_SCALED_CALDERON_EXT + 1):
+        assert _create_status(pbm, m.xyz, m.tri, preconditioner=prec) == pbm.PB_E_INVALID_ARG
+        assert _create_status(pbm, m.xyz, m.tri, formulation=pbm.PB_LU, preconditioner=prec) == pbm.PB_E_INVALID_ARG
 
 
 def test_valid_mesh_without_gpu_fails_loudly(pbm):
