@@ -84,7 +84,7 @@ def lib():
         L.orc_pair_block.argtypes = [_dp, _ip, _c_int, _c_int, _c_dbl, _c_int, _c_int, _c_int, _dp, _dp]
         L.orc_pair_block.restype = _c_int
         L.orc_operator_rows.argtypes = [_c_int, _c_int, _dp, _ip, _c_dbl, _c_int, _c_int, _ip, _c_int,
-                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _c_int]
         L.orc_mass_rows.argtypes = [_c_int, _c_int, _dp, _ip, _c_int, _ip, _dp]
         L.orc_rhs.argtypes = [_c_int, _c_int, _dp, _ip, _c_int, _dp, _dp, _c_dbl, _dp, _dp]
         L.orc_reaction_potential.argtypes = [_c_int, _c_int, _dp, _ip, _dp, _dp, _c_int, _dp, _dp]
@@ -133,21 +133,23 @@ def pair_block(mesh, t: int, s: int, kappa: float, nss: int = 4,
 
 
 # -------------------------------------------------------------- operators
-def operator_rows(mesh, kappa: float, rows, mode: int = 0, want=("V", "K", "D"), nss: int = 4):
-    """Rows (mode 0) or columns (mode 1) of V, K, D for the kernel exp(-kappa r)/(4 pi r)."""
+def operator_rows(mesh, kappa: float, rows, mode: int = 0, want=("V", "K", "D"), nss: int = 4,
+                  centroid: bool = False):
+    """Rows (mode 0) or columns (mode 1) of V, K, D for the kernel exp(-kappa r)/(4 pi r).
+    centroid: the one-point rule instead of the 6-point rule on pairs sharing no vertex."""
     xyz, tri = _mesh_arrays(mesh)
     rows = np.ascontiguousarray(rows, dtype=np.int32)
     nv = len(xyz)
     out = {k: np.zeros((len(rows), nv)) for k in want}
     ptr = lambda k: out[k].ctypes.data_as(ctypes.c_void_p) if k in out else None
     lib().orc_operator_rows(nv, len(tri), xyz, tri, float(kappa), int(nss), len(rows), rows,
-                            int(mode), ptr("V"), ptr("K"), ptr("D"))
+                            int(mode), ptr("V"), ptr("K"), ptr("D"), 2 if centroid else 0)
     return out
 
 
-def assemble(mesh, kappa: float, want=("V", "K", "D"), nss: int = 4):
+def assemble(mesh, kappa: float, want=("V", "K", "D"), nss: int = 4, centroid: bool = False):
     """Dense V, K, D (rows = test vertex, columns = trial vertex)."""
-    return operator_rows(mesh, kappa, np.arange(mesh.n_vertices), 0, want, nss)
+    return operator_rows(mesh, kappa, np.arange(mesh.n_vertices), 0, want, nss, centroid)
 
 
 def mass_rows(mesh, rows):
@@ -399,24 +401,35 @@ def calderon_blocks(ops_L, ops_Y, M, eps_in, eps_out, formulation, part):
     raise ValueError(part)
 
 
-def calderon_matrix(mesh, eps_in, eps_out, kappa, formulation, part, nss: int = 4):
-    """Galerkin matrix of the preconditioning operator P (weak form, 2V x 2V)."""
-    oL = assemble(mesh, 0.0, ("V", "K", "D"), nss)
-    oY = assemble(mesh, kappa, ("V", "K", "D"), nss)
+#: fast Calderon (Discussion): the preconditioner's operator with relaxed
+#: quadrature, the one-point rule on pairs sharing no vertex and one Gauss
+#: point fewer per dimension in the Sauter-Schwab rule
+FAST_NSS = 3
+
+
+def calderon_matrix(mesh, eps_in, eps_out, kappa, formulation, part, nss: int = 4, fast: bool = False):
+    """Galerkin matrix of the preconditioning operator P (weak form, 2V x 2V);
+    fast: assembled with the relaxed quadrature of the fast variant."""
+    if fast:
+        nss = FAST_NSS
+    oL = assemble(mesh, 0.0, ("V", "K", "D"), nss, centroid=fast)
+    oY = assemble(mesh, kappa, ("V", "K", "D"), nss, centroid=fast)
     oL["T"] = oL["K"].T.copy()
     oY["T"] = oY["K"].T.copy()
     P11, P12, P21, P22 = calderon_blocks(oL, oY, mass(mesh), eps_in, eps_out, formulation, part)
     return np.block([[P11, P12], [P21, P22]])
 
 
-def calderon_rows(mesh, eps_in, eps_out, kappa, formulation, part, rows, x, nss: int = 4):
+def calderon_rows(mesh, eps_in, eps_out, kappa, formulation, part, rows, x, nss: int = 4, fast: bool = False):
     """Sampled rows of y = P x for large meshes: returns (y1[rows], y2[rows])."""
     rows = np.asarray(rows, dtype=np.int32)
     nv = mesh.n_vertices
-    oL = operator_rows(mesh, 0.0, rows, 0, ("V", "K", "D"), nss)
-    oY = operator_rows(mesh, kappa, rows, 0, ("V", "K", "D"), nss)
-    oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss)["K"]
-    oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss)["K"]
+    if fast:
+        nss = FAST_NSS
+    oL = operator_rows(mesh, 0.0, rows, 0, ("V", "K", "D"), nss, fast)
+    oY = operator_rows(mesh, kappa, rows, 0, ("V", "K", "D"), nss, fast)
+    oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss, fast)["K"]
+    oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss, fast)["K"]
     P11, P12, P21, P22 = calderon_blocks(oL, oY, mass_rows(mesh, rows), eps_in, eps_out, formulation, part)
     return P11 @ x[:nv] + P12 @ x[nv:], P21 @ x[:nv] + P22 @ x[nv:]
 
@@ -511,10 +524,11 @@ def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
 
 
 def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRECT,
-          preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None):
+          preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None, fast: bool = False):
     """Dense FP64 solve: returns dict(phi, dphi, dG, iterations, rel_residual).
     preconditioner: True or "block_diag", False or None, "mass", "scaled_mass",
-    or one of CALDERON (PMCHWT formulations)."""
+    or one of CALDERON (PMCHWT formulations); fast: the Calderon operator with
+    the relaxed quadrature of the fast variant."""
     nv = mesh.n_vertices
     if A is None:
         A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss)
@@ -528,7 +542,8 @@ def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRE
         P = mass_preconditioner(mesh, a, bb)
     elif preconditioner in CALDERON:
         part = calderon_part(preconditioner)
-        Pm = A if part == "full" else calderon_matrix(mesh, eps_in, eps_out, kappa, formulation, part, nss)
+        Pm = (A if part == "full" and not fast
+              else calderon_matrix(mesh, eps_in, eps_out, kappa, formulation, part, nss, fast))
         a, bb = (calderon_scales(eps_in, eps_out, formulation, part) if preconditioner.startswith("scaled")
                  else (1.0, 1.0))
         P = calderon_preconditioner(mesh, Pm, a, bb)

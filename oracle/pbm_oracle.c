@@ -208,6 +208,24 @@ static void block_regular(const otri *t, const otri *s, double kappa, int mode,
     }
 }
 
+/* One-point rule (the centroid, weight |t| |s|, every hat 1/3 there): the
+ * relaxed regular quadrature of the fast Calderon preconditioner (Discussion,
+ * fast Calderon preconditioning). */
+static void block_centroid(const otri *t, const otri *s, double kappa, int mode, double *V, double *K)
+{
+    double x[3], y[3], g, d;
+    for (int c = 0; c < 3; ++c) {
+        x[c] = (t->p[0][c] + t->p[1][c] + t->p[2][c]) / 3.0;
+        y[c] = (s->p[0][c] + s->p[1][c] + s->p[2][c]) / 3.0;
+    }
+    kern(mode, x, y, s->n, kappa, &g, &d);
+    double w = t->area * s->area / 9.0;
+    for (int i = 0; i < 9; ++i) {
+        V[i] = w * g;
+        K[i] = w * d;
+    }
+}
+
 /* ------------------------------------------ Sauter-Schwab singular quadrature
  *
  * Reference triangle {0 <= u2 <= u1 <= 1}; chi(u) = P0 + u1 (P1 - P0) + u2 (P2 - P1),
@@ -338,7 +356,8 @@ static void block_singular(const otri *t, const otri *s, int same, double kappa,
  *   V[3k+l] = int_t int_s lambda_k(x) g(x,y) lambda_l(y),
  *   K[3k+l] = int_t int_s lambda_k(x) d(x,y) lambda_l(y).
  * quad_mode 0: singular rule with nss points per dimension when the pair shares
- * a vertex, regular rule otherwise; quad_mode 1: regular rule always.
+ * a vertex, regular rule otherwise; quad_mode 1: regular rule always;
+ * quad_mode 2: as 0 with the one-point rule in place of the regular rule.
  * Returns the number of shared vertices. */
 int orc_pair_block(const double *xyz, const int32_t *tri, int t, int s, double kappa,
                    int nss, int kernel_mode, int quad_mode, double *V, double *K)
@@ -352,7 +371,8 @@ int orc_pair_block(const double *xyz, const int32_t *tri, int t, int s, double k
     else
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l) ns += (ot.v[k] == os.v[l]);
-    if (ns == 0 || quad_mode == 1) block_regular(&ot, &os, kappa, kernel_mode, V, K);
+    if (ns == 0 && quad_mode == 2) block_centroid(&ot, &os, kappa, kernel_mode, V, K);
+    else if (ns == 0 || quad_mode == 1) block_regular(&ot, &os, kappa, kernel_mode, V, K);
     else block_singular(&ot, &os, t == s, kappa, kernel_mode, nss, V, K);
     return ns;
 }
@@ -388,11 +408,11 @@ static int incident(const int32_t *tri, int nt, int v, int *out, int cap)
  *   mode 0 (rows)   : outX[r*nv + j] = X_ij, i the test vertex;
  *   mode 1 (columns): outX[r*nv + j] = X_ji, i the trial vertex.
  * X in {V, K, D} for the kernel with screening kappa (kappa = 0: Laplace);
- * any output pointer may be NULL.  Rows are independent and computed in
- * parallel. */
+ * any output pointer may be NULL; quad_mode as for orc_pair_block (0 or 2).
+ * Rows are independent and computed in parallel. */
 void orc_operator_rows(int nv, int nt, const double *xyz, const int32_t *tri, double kappa,
                        int nss, int nrows, const int32_t *rows, int mode,
-                       double *outV, double *outK, double *outD)
+                       double *outV, double *outK, double *outD, int quad_mode)
 {
     init_rule();
 #pragma omp parallel for schedule(dynamic, 1)
@@ -413,7 +433,7 @@ void orc_operator_rows(int nv, int nt, const double *xyz, const int32_t *tri, do
                 int t = (mode == 0) ? fixed : other;
                 int s = (mode == 0) ? other : fixed;
                 double V[9], K[9], D[9];
-                orc_pair_block(xyz, tri, t, s, kappa, nss, 0, 0, V, K);
+                orc_pair_block(xyz, tri, t, s, kappa, nss, 0, quad_mode, V, K);
                 otri ot, os;
                 tri_geom(xyz, tri, t, &ot);
                 tri_geom(xyz, tri, s, &os);

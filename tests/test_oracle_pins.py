@@ -576,3 +576,65 @@ def test_calderon_solutions_and_iterations(form):
     h = {"int": "calderon_int", "ext": "calderon_ext"}
     for part, p in h.items():
         assert its["scaled_" + p] <= its[p], its
+
+
+def test_centroid_rule_blocks(skew_mesh):
+    """One-point rule of the fast Calderon preconditioner: all nine hat products
+    equal |t||s|/9 times the kernel at the centroids, so the block sum is
+    exact for a kernel bilinear in x and y (checked against the 6-point rule,
+    exact for it) and differs for a quadratic one."""
+    m, _ = skew_mesh
+    found = 0
+    for t in range(0, m.n_triangles, 7):
+        for s in range(3, m.n_triangles, 11):
+            Vc, Kc, ns = oracle.pair_block(m, t, s, 0.3, 4, kernel_mode=1, quad_mode=2)
+            if ns:
+                continue
+            V6, K6, _ = oracle.pair_block(m, t, s, 0.3, 4, kernel_mode=1, quad_mode=0)
+            assert np.ptp(Kc) < 1e-14 * np.abs(Kc).max() and np.ptp(Vc) < 1e-14 * np.abs(Vc).max()
+            assert abs(Kc.sum() - K6.sum()) < 1e-12 * abs(K6).sum()      # bilinear kernel
+            assert abs(Vc.sum() - V6.sum()) > 1e-6 * abs(V6).sum()       # 1 + |x-y|^2 is not
+            found += 1
+    assert found > 20
+
+
+def test_centroid_rule_operators_converge(sphere4, sphere8):
+    """V, K and D with the one-point rule on far pairs (Sauter-Schwab order 3
+    on near pairs) still approach the sphere eigenvalues: V and K at first
+    order (the pairs next to the near field carry an O(1) relative rule error
+    over a band of width h), D within 1% on both meshes."""
+    errs = {}
+    for tag, (m, _, _, M) in (("4", sphere4), ("8", sphere8)):
+        o = oracle.assemble(m, 0.7, ("V", "K", "D"), oracle.FAST_NSS, centroid=True)
+        z = m.xyz[:, 2] / np.linalg.norm(m.xyz, axis=1)
+        for l, u in {1: z, 2: 1.5 * z * z - 0.5}.items():
+            ex = sphere_eigenvalues(l, 1.0, 0.7)
+            for op in ("V", "K", "D"):
+                errs[(tag, l, op)] = abs(_rayleigh(o[op], u, M) - ex[op]) / abs(ex[op])
+    for (tag, l, op), e in errs.items():
+        if op == "D":
+            assert e < 0.01, (tag, l, e)
+        elif tag == "8":
+            assert e < 0.04 and e < errs[("4", l, op)] / 1.6, (l, op, e, errs[("4", l, op)])
+
+
+@pytest.mark.parametrize("form", [oracle.PMCHWT_INT, oracle.PMCHWT_EXT])
+def test_fast_calderon_solutions_and_iterations(form):
+    """Fast Calderon (relaxed quadrature on the preconditioner only): the
+    solution is the PMCHWT solution itself, and the iterations stay within a
+    few of the accurately integrated preconditioner's (the paper's Cases 20b
+    and 23b)."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, form)
+    bD, bN = oracle.rhs(m, ch, 4.0)
+    x = np.linalg.solve(A, oracle.system_rhs(bD, bN, form))
+    ref = np.concatenate(oracle.interior_traces(x, m.n_vertices, form))
+    for prec in ("calderon", "scaled_calderon_int"):
+        r = oracle.solve(m, ch, formulation=form, preconditioner=prec, tol=1e-13, A=A, fast=True)
+        assert np.abs(np.concatenate([r["phi"], r["dphi"]]) - ref).max() < 1e-9 * np.abs(ref).max()
+    m, ch = inputs.config_sphere(8, 10.0, 10, 8.0, 2)
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, form)
+    for prec in ("calderon", "scaled_calderon_int"):
+        acc = oracle.solve(m, ch, formulation=form, preconditioner=prec, A=A)["iterations"]
+        fast = oracle.solve(m, ch, formulation=form, preconditioner=prec, A=A, fast=True)["iterations"]
+        assert acc <= fast <= acc + 3, (prec, acc, fast)
