@@ -79,7 +79,8 @@ typedef int32_t pb_status;
  * as B A u = B b with B = blockdiag(aM, bM)^-1 P blockdiag(M, M)^-1: the
  * Galerkin form of the operator product P A, mass matrices inverted as for
  * PB_MASS.  P is assembled like A (same precision, operator mode, near field). */
-#define PB_CALDERON     4  /* P = A itself; a = b = 1 (Eqs. prec:calderon:int:full, ext:full) */
+#define PB_CALDERON     4  /* P = A itself (an operator of its own with calderon_fast);
+                              a = b = 1 (Eqs. prec:calderon:int:full, ext:full) */
 #define PB_CALDERON_INT 5  /* P = the Laplace ("interior") part of A; a = b = 1 */
 #define PB_CALDERON_EXT 6  /* P = the Yukawa ("exterior") part of A; a = b = 1 */
 #define PB_SCALED_CALDERON_INT 7  /* PB_CALDERON_INT with a, b = the two half accumulation
@@ -129,6 +130,12 @@ typedef struct {
     size_t memory_budget;     /* bytes the handle may hold on the device; 0 = 90% of free */
     int32_t use_graph;        /* 1 (default): GMRES iterations replayed from a captured HIP
                                  graph with device-side Givens rotations; 0: eager launches */
+    int32_t calderon_fast;    /* Calderon preconditioners only.  0 (default): P integrated like A;
+                                 1: fast Calderon (Discussion): P with relaxed quadrature, the
+                                 one-point (centroid) rule on triangle pairs sharing no vertex,
+                                 evaluated matrix-free in FP32 whatever the handle's precision
+                                 and operator mode, and Sauter-Schwab with singular_order - 1
+                                 Gauss points per dimension (at least 1) on pairs sharing one */
 } pb_options;
 
 typedef struct {

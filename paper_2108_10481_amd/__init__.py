@@ -77,7 +77,8 @@ class pb_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("operator_mode", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("singular_order", ctypes.c_int32),
                 ("source_chunks", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("memory_budget", ctypes.c_size_t), ("use_graph", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("memory_budget", ctypes.c_size_t), ("use_graph", ctypes.c_int32),
+                ("calderon_fast", ctypes.c_int32)]
 
 
 class pb_result(ctypes.Structure):

@@ -19,9 +19,10 @@
 
 namespace pbm {
 
+// dync (may be null): the one-point rule's source weights |s| mean(u1), |s| mean(u2)
 __global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, const double *__restrict__ geo,
                               const double *__restrict__ x, double *__restrict__ dyn64, float *__restrict__ dyn32,
-                              DevCtl ctl)
+                              float *__restrict__ dync, DevCtl ctl)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= T || ctl_skip(ctl)) return;
@@ -53,13 +54,17 @@ __global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, con
     }
     d64[15] = 0.0;
     d32[15] = 0.0f;
+    if (dync) {
+        dync[2 * (size_t)s] = (float)(area * (u1[0] + u1[1] + u1[2]) / 3.0);
+        dync[2 * (size_t)s + 1] = (float)(area * (u2[0] + u2[1] + u2[2]) / 3.0);
+    }
 }
 
 void launch_source_prep(DevMesh &d, const double *x, bool)
 {
     int T = d.hm.T;
     hipLaunchKernelGGL(k_source_prep, dim3((T + 255) / 256), dim3(256), 0, d.stream, T, d.hm.V, d.tri, d.geo, x,
-                       d.dyn64, d.dyn32, d.ctl);
+                       d.dyn64, d.dyn32, d.far_rule == 1 ? d.dync32 : nullptr, d.ctl);
     HIPCHECK(hipGetLastError());
 }
 
@@ -195,6 +200,85 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
     o[12] = W0; o[13] = W1; o[14] = W2; o[15] = 0;
 }
 
+// One-point (centroid) rule on every triangle pair sharing no vertex, FP32:
+// the relaxed far field of fast Calderon's preconditioner.  Same sums as
+// k_far with the centroids c_t, c_s as the only points, source weights
+// b1 = |s| mean(u1), b2 = |s| mean(u2) and unit pair weight for the curl sum;
+// the per-point outputs repeat the centroid value, so k_far_finish's test
+// projection with the 6-point rule yields exactly |t| / 3 per hat (the rule
+// integrates the hats exactly).  Terms are summed in FP32 over runs of
+// kCenRun sources and the runs in FP64: long FP32 sums would put a rounding
+// noise of about 1e-6 into every product, the order of the preconditioned
+// residual GMRES stops at.
+constexpr int kCenRun = 16;
+template <int FORM>
+__global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, FarCoef<float> cf,
+                                                             const int32_t *__restrict__ tri,
+                                                             const float *__restrict__ stat,
+                                                             const float *__restrict__ dyn,
+                                                             const float *__restrict__ dync, float *__restrict__ part,
+                                                             DevCtl ctl)
+{
+    const int t = blockIdx.x * kFarBlock + threadIdx.x;
+    const int s0 = blockIdx.y * chunk;
+    const int s1 = min(T, s0 + chunk);
+    if (t >= T || ctl_skip(ctl)) return;
+    const float *ts = stat + (size_t)t * kStat;
+    const float cx = ts[37], cy = ts[38], cz = ts[39];
+    const float ntx = ts[18], nty = ts[19], ntz = ts[20];
+    const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
+    double A1 = 0, A2 = 0, X0 = 0, X1 = 0, X2 = 0;
+    for (int sr = s0; sr < s1; sr += kCenRun) {
+        float a1 = 0, a2 = 0, W0 = 0, W1 = 0, W2 = 0;
+        for (int s = sr; s < min(s1, sr + kCenRun); ++s) {
+            const int j0 = tri[3 * s], j1 = tri[3 * s + 1], j2 = tri[3 * s + 2];
+            const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
+                             (j2 == v0) | (j2 == v1) | (j2 == v2);
+            if (adj) continue;
+            const float *st = stat + (size_t)s * kStat;
+            const float nsx = st[18], nsy = st[19], nsz = st[20];
+            const float b1 = dync[2 * (size_t)s], b2 = dync[2 * (size_t)s + 1];
+            const float dx = cx - st[37], dy = cy - st[38], dz = cz - st[39];
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const float ri = rsqrt_r(r2);
+            const float r = r2 * ri;
+            const float e = expneg(cf.kexp, r);
+            const float ri3 = ri * ri * ri;
+            const float dns = dx * nsx + dy * nsy + dz * nsz;
+            const float tt = cf.kappa * r + 1.0f;
+            float g = 0.0f;
+            if (FORM == 0) {
+                a1 += ri3 * dns * cf.kL * b1 + ri * cf.vL * b2;
+                a2 += e * (ri3 * tt * dns * cf.kY * b1 + ri * cf.vY * b2);
+            } else {
+                const float fy = e * tt * ri3, gy = e * ri;
+                const float dnt = dx * ntx + dy * nty + dz * ntz;
+                const float k2nn = cf.aDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
+                const float fk = FORM == 3 ? fy : ri3 + cf.rK * fy, fv = FORM == 3 ? gy : ri + cf.rV * gy;
+                const float ft = FORM == 3 ? fy : ri3 + cf.rT * fy;
+                a1 += fk * dns * cf.aK * b1 + fv * cf.aV * b2;
+                a2 += ft * dnt * cf.aT * b2 + k2nn * gy * b1;
+                g = FORM == 3 ? gy : FORM == 1 ? fv : ri + cf.rD * gy;
+            }
+            if (FORM >= 1) {
+                const float *sd = dyn + (size_t)s * kDyn;
+                W0 += g * sd[12];
+                W1 += g * sd[13];
+                W2 += g * sd[14];
+            }
+        }
+        A1 += a1;
+        A2 += a2;
+        X0 += W0;
+        X1 += W1;
+        X2 += W2;
+    }
+    float *o = part + ((size_t)blockIdx.y * T + t) * 16;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) { o[p] = (float)A1; o[6 + p] = (float)A2; }
+    o[12] = (float)X0; o[13] = (float)X1; o[14] = (float)X2; o[15] = 0;
+}
+
 // family 0: rows (Laplace, Yukawa), swapped when the Laplace row is row 2;
 // family 1: row 2 gets D's curl part times aD (aL of D, or aY without Laplace terms)
 template <typename R>
@@ -294,12 +378,10 @@ int choose_chunks(int T)
     return S;
 }
 
+// coefficients of the current operator fields; returns the kernel FORM
 template <typename R>
-static void far_launch(DevMesh &d, const R *stat, const R *dyn)
+static int far_coef(const DevMesh &d, FarCoef<R> &cf)
 {
-    const int T = d.hm.T, S = d.S;
-    const int chunk = (T + S - 1) / S;
-    FarCoef<R> cf;
     const double kap = d.prm.kappa;
     cf.kappa = (R)kap;
     cf.kexp = (sizeof(R) == 4) ? (R)(kap * 1.4426950408889634) : (R)kap;
@@ -324,6 +406,16 @@ static void far_launch(DevMesh &d, const R *stat, const R *dyn)
         cf.rT = (R)(f.aY[1][1] / f.aL[1][1]);
         form = rD == rV ? 1 : 2;
     }
+    return form;
+}
+
+template <typename R>
+static void far_launch(DevMesh &d, const R *stat, const R *dyn)
+{
+    const int T = d.hm.T, S = d.S;
+    const int chunk = (T + S - 1) / S;
+    FarCoef<R> cf;
+    const int form = far_coef(d, cf);
     dim3 grid((T + kFarBlock - 1) / kFarBlock, S), block(kFarBlock);
     R *part = (R *)d.part;
     if (form == 0)
@@ -353,6 +445,25 @@ void launch_far(DevMesh &d, bool fp32)
         const double P = 6.0 * d.hm.T;
         pf.record(0, e0, e1, P * P);   // kernel pairs, near-masked pairs included
     }
+}
+
+void launch_far_centroid(DevMesh &d)
+{
+    const int T = d.hm.T, S = d.S;
+    const int chunk = (T + S - 1) / S;
+    FarCoef<float> cf;
+    const int form = far_coef(d, cf);
+    const dim3 grid((T + kFarBlock - 1) / kFarBlock, S), block(kFarBlock);
+    float *part = (float *)d.part;
+#define FAR_C(F)                                                                                               \
+    hipLaunchKernelGGL((k_far_centroid<F>), grid, block, 0, d.stream, T, chunk, cf, d.tri, d.stat32, d.dyn32, \
+                       d.dync32, part, d.ctl)
+    if (form == 0) FAR_C(0);
+    else if (form == 1) FAR_C(1);
+    else if (form == 2) FAR_C(2);
+    else FAR_C(3);
+#undef FAR_C
+    HIPCHECK(hipGetLastError());
 }
 
 void launch_far_finish(DevMesh &d, bool fp32)

@@ -58,7 +58,12 @@ __global__ void k_geometry(int T, const double *__restrict__ xyz, const int32_t 
         s64[28 + i] = g[22 + i];
         s32[28 + i] = (float)g[22 + i];
     }
-    for (int i = 37; i < kStat; ++i) { s64[i] = 0.0; s32[i] = 0.0f; }
+    // centroid (the one-point rule of fast Calderon's preconditioner)
+    for (int c = 0; c < 3; ++c) {
+        const double m = (P[0][c] + P[1][c] + P[2][c]) / 3.0;
+        s64[37 + c] = m;
+        s32[37 + c] = (float)m;
+    }
 }
 
 void launch_geometry(DevMesh &d)

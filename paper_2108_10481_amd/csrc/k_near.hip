@@ -235,12 +235,12 @@ static void launch_ss_n(hipStream_t st, const int count[4], const int32_t *idx, 
 }
 
 static void launch_ss(DevMesh &d, const int count[4], const int32_t *idx, const int32_t *pt, const int32_t *ps,
-                      double *out)
+                      double *out, int order)
 {
     if (count[1] + count[2] + count[3] == 0) return;
     upload_gauss_tables();
     const double kap = d.prm.kappa;
-    switch (d.opt.singular_order) {
+    switch (order) {
 #define SS_CASE(n) \
     case n: launch_ss_n<n>(d.stream, count, idx, pt, ps, d, kap, out); break;
         SS_CASE(1) SS_CASE(2) SS_CASE(3) SS_CASE(4) SS_CASE(5) SS_CASE(6) SS_CASE(7) SS_CASE(8)
@@ -250,13 +250,16 @@ static void launch_ss(DevMesh &d, const int count[4], const int32_t *idx, const 
     HIPCHECK(hipGetLastError());
 }
 
-void launch_near_field(DevMesh &d) { launch_ss(d, d.ss_count, d.ss_idx, d.pair_t, d.pair_s, d.pairblk); }
+void launch_near_field(DevMesh &d)
+{
+    launch_ss(d, d.ss_count, d.ss_idx, d.pair_t, d.pair_s, d.pairblk, d.opt.singular_order);
+}
 
 void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const int32_t *s_sorted,
                                const int32_t *idx, const int count[4], double *out)
 {
     (void)n;
-    launch_ss(d, count, idx, t_sorted, s_sorted, out);
+    launch_ss(d, count, idx, t_sorted, s_sorted, out, d.opt.singular_order);
 }
 
 // Near-field vertex blocks (mass terms included) of the chosen formulation.
@@ -437,15 +440,24 @@ void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const Dev
     HIPCHECK(hipGetLastError());
 }
 
-void launch_near_values(DevMesh &d, const FormCoef &f, double *N, double *Mval)
+void launch_near_values(DevMesh &d, const FormCoef &f, const double *blk, const double *sums, double *N,
+                        double *Mval)
 {
     NearCoef cf;
     cf.kappa = d.prm.kappa;
     cf.f = f;
     const int64_t nnz = d.nnz();
     hipLaunchKernelGGL(k_near_slots, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, d.stream, nnz, cf,
-                       d.slot_ptr, d.slot_code, d.pair_t, d.pair_s, d.pair_rev, d.geo, d.pairblk, d.pair_sums, N,
-                       Mval);
+                       d.slot_ptr, d.slot_code, d.pair_t, d.pair_s, d.pair_rev, d.geo, blk, sums, N, Mval);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_near_field_fast(DevMesh &d)
+{
+    launch_ss(d, d.ss_count, d.ss_idx, d.pair_t, d.pair_s, d.pairblkP, calderon_fast_order(d.opt));
+    const int64_t np = d.npair();
+    hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, d.stream, np, d.pairblkP,
+                       d.pair_sumsP);
     HIPCHECK(hipGetLastError());
 }
 
@@ -458,8 +470,11 @@ void launch_near_assemble(DevMesh &d)
     if (d.fm.family == 1)
         hipLaunchKernelGGL(k_pair_sums, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, d.stream, np, d.pairblk,
                            d.pair_sums);
-    launch_near_values(d, d.fm, d.N, d.Mval);
-    if (d.NP) launch_near_values(d, d.fmP, d.NP, nullptr);
+    launch_near_values(d, d.fm, d.pairblk, d.pair_sums, d.N, d.Mval);
+    if (d.NP) {
+        if (d.pairblkP) launch_near_values(d, d.fmP, d.pairblkP, d.pair_sumsP, d.NP, nullptr);
+        else launch_near_values(d, d.fmP, d.pairblk, d.pair_sums, d.NP, nullptr);
+    }
     if (d.Mval)
         hipLaunchKernelGGL(k_mass_diag, dim3((V + 255) / 256), dim3(256), 0, d.stream, V, d.diag_slot, d.Mval,
                            d.Mdinv);

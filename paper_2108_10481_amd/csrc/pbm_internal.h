@@ -67,7 +67,7 @@ void build_host_mesh(const pb_mesh *m, HostMesh &hm);
 // ------------------------------------------------------------ device state
 // Source / target records of the far-field kernels, one per triangle:
 //   static  (kStat reals): 6 quadrature points x 3, normal 3, y_q . n 6, area 1,
-//                          surface curls of the three hat functions 9, zero padding
+//                          surface curls of the three hat functions 9, centroid 3
 //   dynamic (kDyn reals) : b1[6] = w_q|s| u1(y_q), b2[6] = w_q|s| u2(y_q), C[3] = |s| curl u1|_s
 constexpr int kStat = 40;
 constexpr int kDyn = 16;
@@ -245,6 +245,14 @@ struct DevMesh {
     double *NP = nullptr;
     Dense *denseP = nullptr;
     double *cal1 = nullptr, *cal2 = nullptr;
+    // far-field rule of the current operator: 0 = 6-point rule (the handle's
+    // precision and mode), 1 = one-point rule, matrix-free FP32 (fast
+    // Calderon's P); swapped with far_ruleP like the fields above
+    int far_rule = 0, far_ruleP = 0;
+    // fast Calderon: P's Sauter-Schwab blocks and pair sums at the relaxed
+    // order, and the centroid source weights (T x 2: |s| mean u1, |s| mean u2)
+    double *pairblkP = nullptr, *pair_sumsP = nullptr;
+    float *dync32 = nullptr;
     int64_t nnz() const { return (int64_t)hm.col.size(); }
     void *alloc(size_t n);
     ~DevMesh();
@@ -254,8 +262,14 @@ struct DevMesh {
 void launch_geometry(DevMesh &d);
 void launch_near_field(DevMesh &d);
 void launch_near_assemble(DevMesh &d);
-// near-field values of coefficients f into N (4 x nnz); Mval (may be null): the mass matrix
-void launch_near_values(DevMesh &d, const FormCoef &f, double *N, double *Mval);
+// near-field values of coefficients f from pair blocks blk and pair sums into N (4 x nnz);
+// Mval (may be null): the mass matrix
+void launch_near_values(DevMesh &d, const FormCoef &f, const double *blk, const double *sums, double *N,
+                        double *Mval);
+// fast Calderon's P: Sauter-Schwab blocks at the relaxed order and their pair sums
+void launch_near_field_fast(DevMesh &d);
+// one-point-rule far field (FP32) of the current operator fields into d.part
+void launch_far_centroid(DevMesh &d);
 void launch_source_prep(DevMesh &d, const double *x, bool fp32);
 void launch_far(DevMesh &d, bool fp32);
 void launch_far_finish(DevMesh &d, bool fp32);
@@ -311,8 +325,13 @@ inline bool is_calderon(int preconditioner)
     return preconditioner >= PB_CALDERON && preconditioner <= PB_SCALED_CALDERON_EXT;
 }
 inline bool calderon_mode(const DevMesh &d) { return is_calderon(d.prm.preconditioner); }
-// P is a separate operator (a kernel's part of A), not A itself
-inline bool calderon_part_mode(const DevMesh &d) { return calderon_mode(d) && d.prm.preconditioner != PB_CALDERON; }
+// P is an operator of its own (a kernel's part of A, or relaxed quadrature), not A itself
+inline bool calderon_separate(const DevMesh &d)
+{
+    return calderon_mode(d) && (d.prm.preconditioner != PB_CALDERON || d.opt.calderon_fast);
+}
+// Sauter-Schwab order of fast Calderon's P
+inline int calderon_fast_order(const pb_options &o) { return o.singular_order > 1 ? o.singular_order - 1 : 1; }
 // blockdiag(M, M)^-1 scaled by (sa, sb) = (1/a, 1/b) per half: of the mass
 // preconditioners (first form) or explicit
 void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl);

@@ -80,6 +80,9 @@ static void check_options(const pb_options *o)
         fail(PB_E_INVALID_ARG, "the scaled mass preconditioner is defined for the Juffer formulation");
     if (is_calderon(o->preconditioner) && o->formulation != PB_PMCHWT_INT && o->formulation != PB_PMCHWT_EXT)
         fail(PB_E_INVALID_ARG, "Calderon preconditioners are defined for the PMCHWT formulations");
+    if (o->calderon_fast != 0 && o->calderon_fast != 1) fail(PB_E_INVALID_ARG, "calderon_fast must be 0 or 1");
+    if (o->calderon_fast && !is_calderon(o->preconditioner))
+        fail(PB_E_INVALID_ARG, "calderon_fast needs a Calderon preconditioner");
     if (o->precision < PB_FP64 || o->precision > PB_MIXED_FP16) fail(PB_E_INVALID_ARG, "unknown precision");
     if (o->operator_mode < PB_MATRIX_FREE || o->operator_mode > PB_AUTO) fail(PB_E_INVALID_ARG, "unknown operator mode");
     if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
@@ -220,6 +223,8 @@ struct PrecondOperator {
         swap();
         if (d.dense) d.dense_vpos = d.dense->vpos;
     }
+    PrecondOperator(const PrecondOperator &) = delete;
+    PrecondOperator &operator=(const PrecondOperator &) = delete;
     ~PrecondOperator()
     {
         swap();
@@ -230,6 +235,7 @@ struct PrecondOperator {
         std::swap(d.fm, d.fmP);
         std::swap(d.N, d.NP);
         std::swap(d.dense, d.denseP);
+        std::swap(d.far_rule, d.far_ruleP);
     }
 };
 
@@ -239,10 +245,11 @@ static void device_setup(DevMesh &d)
 {
     launch_geometry(d);
     launch_near_field(d);
+    if (d.pairblkP) launch_near_field_fast(d);
     launch_near_assemble(d);
     if (d.want_dense) {
         build_dense(d);
-        if (calderon_part_mode(d)) {
+        if (calderon_separate(d) && d.far_ruleP == 0) {
             PrecondOperator use(d);
             build_dense(d);
         }
@@ -308,7 +315,13 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     if (calderon_mode(*d)) {
         d->cal1 = (double *)d->alloc(sizeof(double) * 2 * (size_t)V);
         d->cal2 = (double *)d->alloc(sizeof(double) * 2 * (size_t)V);
-        if (calderon_part_mode(*d)) d->NP = (double *)d->alloc(sizeof(double) * 4 * d->nnz());
+        if (calderon_separate(*d)) d->NP = (double *)d->alloc(sizeof(double) * 4 * d->nnz());
+        if (opt->calderon_fast) {
+            d->far_ruleP = 1;
+            d->pairblkP = (double *)d->alloc(sizeof(double) * 36 * std::max<int64_t>(d->npair(), 1));
+            d->pair_sumsP = (double *)d->alloc(sizeof(double) * 2 * std::max<int64_t>(d->npair(), 1));
+            d->dync32 = (float *)d->alloc(sizeof(float) * 2 * (size_t)T);
+        }
     }
     d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
     d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
@@ -324,7 +337,8 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     d->yfar = (double *)d->alloc(sizeof(double) * 2 * V);
 
     d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
-                    (opt->operator_mode == PB_AUTO && dense_fits(*d, calderon_part_mode(*d) ? 2 : 1));
+                    (opt->operator_mode == PB_AUTO &&
+                     dense_fits(*d, calderon_separate(*d) && !opt->calderon_fast ? 2 : 1));
     device_setup(*d);
     HIPCHECK(hipStreamSynchronize(d->stream));
     d->t_setup = now() - t0;
@@ -354,11 +368,13 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     // FP64 matrix, or FP32 matrix plus the 16-bit copy (mixed) or the assembly's
     // side matrix (FP32) of the same size
     const double dense = n * 2.0 * Vp * (o->precision == PB_FP64 ? 8.0 : 6.0);
-    const bool cal = is_calderon(o->preconditioner), cal_part = cal && o->preconditioner != PB_CALDERON;
-    if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense * (cal_part ? 2.0 : 1.0);
+    const bool cal = is_calderon(o->preconditioner);
+    const bool cal_sep = cal && (o->preconditioner != PB_CALDERON || o->calderon_fast);
+    if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense * (cal_sep && !o->calderon_fast ? 2.0 : 1.0);
     if (o->preconditioner == PB_MASS || o->preconditioner == PB_SCALED_MASS || cal)
         b += 5.0 * kMassBatch * n * 8 + 20.0 * v * 8 + v * 8;   // Chebyshev state, products, M, 1 / M_ii
-    if (cal) b += 2.0 * n * 8 + (cal_part ? 4.0 * 20.0 * v * 8 : 0.0);   // work vectors, P's near field
+    if (cal) b += 2.0 * n * 8 + (cal_sep ? 4.0 * 20.0 * v * 8 : 0.0);   // work vectors, P's near field
+    if (cal && o->calderon_fast) b += 16.0 * t * (38 * 8) + t * 8;   // P's pair blocks and sums, centroid weights
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
     return (size_t)(b * 1.1);
 }
@@ -368,6 +384,12 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
 static int far_product(DevMesh &d, const double *x, int flags)
 {
     if (flags & PB_APPLY_NEAR_ONLY) return 0;
+    if (d.far_rule == 1) {
+        launch_source_prep(d, x, true);
+        launch_far_centroid(d);
+        launch_far_finish(d, true);
+        return 1;
+    }
     if (d.dense) {
         dense_apply(d, x, d.yfar);
         return 2;
@@ -389,7 +411,7 @@ void calderon_left(DevMesh &d, const double *in, double *out, const DevCtl &ctl)
     {
         const DevCtl keep = d.ctl;
         d.ctl = inner;
-        std::unique_ptr<PrecondOperator> use(calderon_part_mode(d) ? new PrecondOperator(d) : nullptr);
+        std::unique_ptr<PrecondOperator> use(calderon_separate(d) ? new PrecondOperator(d) : nullptr);
         const int use_far = far_product(d, d.cal1, 0);
         launch_gather(d, d.cal1, d.cal2, 0, use_far, true);
         use.reset();

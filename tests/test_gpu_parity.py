@@ -742,3 +742,93 @@ def test_calderon_full_size(sphere32):
     print(f"calderon full size iterations: mass {rm['iterations']} calderon {rc['iterations']}")
     assert rc["status"] == pbm.PB_OK and rc["iterations"] < rm["iterations"]
     assert abs(rc["dG"] - rm["dG"]) < 1e-4 * abs(rm["dG"])
+
+
+@pytest.fixture(scope="module")
+def fast_operators(meshes):
+    """Fast Calderon's P on the star: V, K, D, T of both kernels with the
+    one-point rule on far pairs and Sauter-Schwab order 3 on near pairs."""
+    m = meshes["star7"]
+    oL = oracle.assemble(m, 0.0, ("V", "K", "D"), oracle.FAST_NSS, centroid=True)
+    oY = oracle.assemble(m, 0.125, ("V", "K", "D"), oracle.FAST_NSS, centroid=True)
+    for o in (oL, oY):
+        o["T"] = o["K"].T.copy()
+    return oL, oY, oracle.mass(m)
+
+
+@pytest.mark.parametrize("prec,name", [(pbm.PB_CALDERON, "calderon"), (pbm.PB_SCALED_CALDERON_INT,
+                                                                        "scaled_calderon_int"),
+                                       (pbm.PB_CALDERON_EXT, "calderon_ext")])
+@pytest.mark.parametrize("form", [pbm.PB_PMCHWT_INT, pbm.PB_PMCHWT_EXT])
+def test_fast_calderon_product(meshes, base_operators, fast_operators, form, prec, name):
+    """Fast Calderon (one-point rule far field evaluated in FP32, Sauter-Schwab
+    order 3): B A x against the oracle's relaxed P on the 980-triangle star,
+    for FP64 matrix-free and FP32 assembled handles (the relaxed P is the same
+    in both): within the FP32 evaluation of P's far field (2e-6)."""
+    m = meshes["star7"]
+    A = _system(base_operators, form)
+    B = _calderon_ref(m, fast_operators, form, name)
+    x = np.random.default_rng(97 + prec).standard_normal(2 * m.n_vertices)
+    ref = B(A @ x)
+    for p, mode in ((pbm.PB_FP64, pbm.PB_MATRIX_FREE), (pbm.PB_FP32, pbm.PB_ASSEMBLED)):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, p, operator_mode=mode, preconditioner=prec,
+                                                calderon_fast=1)) as h:
+            yp = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+        print(f"fast calderon product form {form} {name} prec {p}: rel {_rel(yp, ref):.2e}")
+        assert _rel(yp, ref) < 2e-6, (p, mode, _rel(yp, ref))
+
+
+@pytest.mark.parametrize("prec,name", [(pbm.PB_CALDERON, "calderon"), (pbm.PB_SCALED_CALDERON_INT,
+                                                                        "scaled_calderon_int")])
+@pytest.mark.parametrize("form", [pbm.PB_PMCHWT_INT, pbm.PB_PMCHWT_EXT])
+def test_fast_calderon_solve_parity(form, prec, name):
+    """Kirkwood sphere, fast Calderon (the paper's Cases 20b and 23b): the
+    oracle's iterations, Delta G within 1e-5 (the preconditioner differs from
+    the oracle's by its FP32 far field, the solution does not), the oracle's
+    traces at tolerance 1e-11 to within the conditioning of B A times that
+    tolerance (1e-7; 1.4e-8 measured)."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    ref = oracle.solve(m, ch, formulation=form, preconditioner=name, fast=True)
+    got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=prec, calderon_fast=1))
+    assert got["status"] == pbm.PB_OK
+    assert got["iterations"] == ref["iterations"], (got["iterations"], ref["iterations"])
+    assert abs(got["dG"] - ref["dG"]) < 1e-5 * abs(ref["dG"])
+    tight = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=prec, calderon_fast=1, tol=1e-11))
+    reft = oracle.solve(m, ch, formulation=form, preconditioner=name, tol=1e-11, A=ref["A"], fast=True)
+    u = np.concatenate([tight["phi"], tight["dphi"]])
+    assert _rel(u, np.concatenate([reft["phi"], reft["dphi"]])) < 1e-7
+    with pytest.raises(pbm.PbError):
+        pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=pbm.PB_MASS, calderon_fast=1))
+
+
+def test_fast_calderon_full_size(sphere32):
+    """20480-triangle sphere, internal PMCHWT, FP32 assembled, fast full and
+    scaled-interior Calderon: sampled rows of M (B A x) against the oracle's
+    relaxed P applied to z = blockdiag(M, M)^-1 A x; the solves reach the mass
+    preconditioner's Delta G with at most two iterations more than the
+    accurately integrated Calderon preconditioner."""
+    m, ch = sphere32
+    nv = m.n_vertices
+    form = pbm.PB_PMCHWT_INT
+    rng = np.random.default_rng(59)
+    x = rng.standard_normal(2 * nv)
+    rows = np.sort(rng.choice(nv, 6, replace=False))
+    Mr = oracle.mass_rows(m, rows)
+    base = dict(operator_mode=pbm.PB_ASSEMBLED)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, preconditioner=pbm.PB_MASS, **base)) as h:
+        z = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+        rm = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+    for prec, part in ((pbm.PB_CALDERON, "full"), (pbm.PB_SCALED_CALDERON_INT, "int")):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, preconditioner=prec, calderon_fast=1,
+                                                **base)) as h:
+            yp = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+            rf = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+        ra = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, pbm.PB_FP32, preconditioner=prec, **base))
+        a, b = (1.0, 1.0) if part == "full" else oracle.calderon_scales(4.0, 80.0, oracle.PMCHWT_INT, "int")
+        r1, r2 = oracle.calderon_rows(m, 4.0, 80.0, 0.125, oracle.PMCHWT_INT, part, rows, z, fast=True)
+        got = np.concatenate([a * (Mr @ yp[:nv]), b * (Mr @ yp[nv:])])
+        print(f"fast calderon full size {part}: rel {_rel(got, np.concatenate([r1, r2])):.2e} "
+              f"iterations fast {rf['iterations']} accurate {ra['iterations']} mass {rm['iterations']}")
+        assert _rel(got, np.concatenate([r1, r2])) < 2e-6, part
+        assert rf["status"] == pbm.PB_OK and ra["iterations"] <= rf["iterations"] <= ra["iterations"] + 2
+        assert abs(rf["dG"] - rm["dG"]) < 1e-4 * abs(rm["dG"])
