@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--operator-mode", default="auto", choices=["matrix-free", "assembled", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=160, help="oracle rows per formulation in the CPU sample")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "star", "multi", "serving"])
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "star", "multi", "serving", "calderon"])
     ap.add_argument("--overlap", default="serial", choices=["streams", "serial"],
                     help="timed region: formulations solved one after the other (serial), or from one host "
                          "thread each on their handles' own HIP streams (streams); the other mode is timed "
@@ -451,6 +451,61 @@ def multi(argv=None):
     print(json.dumps(rec), flush=True)
 
 
+def calderon(argv=None):
+    """PMCHWT formulations on the 20480-triangle sphere with the mass matrix and
+    every Calderon preconditioner (the paper's Cases 15-26, 20b, 23b): complete
+    solves (every device stage redone per solve, as in the default workload),
+    iterations, Krylov time per iteration, Delta G against the FP64 matrix-free
+    mass-preconditioned solve."""
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "mixed-bf16"])
+    a, _ = ap.parse_known_args(argv)
+    import paper_2108_10481_amd as pbm
+    prec = {"fp64": pbm.PB_FP64, "fp32": pbm.PB_FP32, "mixed-bf16": pbm.PB_MIXED_BF16}[a.precision]
+    mesh, ch = inputs.config_sphere()
+    cases = [("mass", pbm.PB_MASS, 0), ("calderon", pbm.PB_CALDERON, 0), ("calderon_int", pbm.PB_CALDERON_INT, 0),
+             ("calderon_ext", pbm.PB_CALDERON_EXT, 0), ("scaled_calderon_int", pbm.PB_SCALED_CALDERON_INT, 0),
+             ("scaled_calderon_ext", pbm.PB_SCALED_CALDERON_EXT, 0), ("fast_calderon", pbm.PB_CALDERON, 1),
+             ("fast_scaled_calderon_int", pbm.PB_SCALED_CALDERON_INT, 1)]
+    out = {}
+    for form, fname in ((pbm.PB_PMCHWT_INT, "pmchwt_int"), (pbm.PB_PMCHWT_EXT, "pmchwt_ext")):
+        ref = pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q,
+                           pbm.pb_default_options(formulation=form, preconditioner=pbm.PB_MASS))["dG"]
+        for name, pc, fast in cases:
+            opt = pbm.pb_default_options(formulation=form, precision=prec, operator_mode=pbm.PB_ASSEMBLED,
+                                         preconditioner=pc, calderon_fast=fast)
+            with pbm.MeshHandle(mesh.xyz, mesh.tri, opt) as h:
+                for _ in range(a.warmup):
+                    pbm.pb_mesh_refresh(h)
+                    pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+                t_set, t_kry, res = [], [], None
+                t0 = time.perf_counter()
+                for _ in range(a.steps):
+                    s0 = time.perf_counter()
+                    pbm.pb_mesh_refresh(h)
+                    t_set.append(time.perf_counter() - s0)
+                    res = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+                    t_kry.append(res["t_gmres"])
+                dt = (time.perf_counter() - t0) / a.steps
+                gb = h.info()["device_bytes"] / 1e9
+            its = res["iterations"]
+            out[f"{fname}/{name}"] = {
+                "solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(1e3 * dt, 2),
+                "setup_ms": round(1e3 * min(t_set), 2), "iterations": its,
+                "krylov_ms": round(1e3 * min(t_kry), 3),
+                "krylov_ms_per_iteration": round(1e3 * min(t_kry) / max(its, 1), 3),
+                "status": res["status"], "rel_residual": res["rel_residual"],
+                "dG_rel_err_vs_fp64_mass": abs(res["dG"] - ref) / abs(ref), "device_GB": round(gb, 2)}
+            print(f"calderon: {fname}/{name} done", file=sys.stderr, flush=True)
+    rec = {"workload": f"sphere R=10 A, {mesh.n_triangles} triangles / {mesh.n_vertices} vertices, 50 charges, "
+                       f"PMCHWT int/ext, {a.precision} assembled, GMRES tol 1e-5; one solve = refresh (geometry, "
+                       "near field, assembly of A and P) + solve", "steps": a.steps, "results": out}
+    print(json.dumps(rec), flush=True)
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device-to-device copy of known size (the runtime's copy kernel),
     used to scale the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -478,5 +533,7 @@ if __name__ == "__main__":
         serving()
     elif wl == "multi":
         multi()
+    elif wl == "calderon":
+        calderon()
     else:
         main()

@@ -206,10 +206,13 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
 // b1 = |s| mean(u1), b2 = |s| mean(u2) and unit pair weight for the curl sum;
 // the per-point outputs repeat the centroid value, so k_far_finish's test
 // projection with the 6-point rule yields exactly |t| / 3 per hat (the rule
-// integrates the hats exactly).  Terms are summed in FP32 over runs of
-// kCenRun sources and the runs in FP64: long FP32 sums would put a rounding
-// noise of about 1e-6 into every product, the order of the preconditioned
-// residual GMRES stops at.
+// integrates the hats exactly).  One evaluation per source is too little work
+// to hide per-source scalar loads, so each block stages kFarBlock source
+// records (centroid, normal, weights, curl weights, vertex ids) in LDS with
+// coalesced loads and every lane reads them as broadcasts.  Terms are summed in
+// FP32 over runs of kCenRun sources and the runs in FP64: long FP32 sums would
+// put a rounding noise of about 1e-6 into every product, the order of the
+// preconditioned residual GMRES stops at.
 constexpr int kCenRun = 16;
 template <int FORM>
 __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, FarCoef<float> cf,
@@ -219,60 +222,74 @@ __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, Fa
                                                              const float *__restrict__ dync, float *__restrict__ part,
                                                              DevCtl ctl)
 {
+    __shared__ float4 rec[3][kFarBlock];   // (c, b1), (n, b2), (C, -)
+    __shared__ int4 vid[kFarBlock];
     const int t = blockIdx.x * kFarBlock + threadIdx.x;
     const int s0 = blockIdx.y * chunk;
     const int s1 = min(T, s0 + chunk);
-    if (t >= T || ctl_skip(ctl)) return;
-    const float *ts = stat + (size_t)t * kStat;
+    if (ctl_skip(ctl)) return;   // uniform: the whole block leaves
+    const int tc = t < T ? t : T - 1;   // lanes past the end compute, never store
+    const float *ts = stat + (size_t)tc * kStat;
     const float cx = ts[37], cy = ts[38], cz = ts[39];
     const float ntx = ts[18], nty = ts[19], ntz = ts[20];
-    const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
+    const int v0 = tri[3 * tc], v1 = tri[3 * tc + 1], v2 = tri[3 * tc + 2];
     double A1 = 0, A2 = 0, X0 = 0, X1 = 0, X2 = 0;
-    for (int sr = s0; sr < s1; sr += kCenRun) {
-        float a1 = 0, a2 = 0, W0 = 0, W1 = 0, W2 = 0;
-        for (int s = sr; s < min(s1, sr + kCenRun); ++s) {
-            const int j0 = tri[3 * s], j1 = tri[3 * s + 1], j2 = tri[3 * s + 2];
-            const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
-                             (j2 == v0) | (j2 == v1) | (j2 == v2);
-            if (adj) continue;
+    for (int sb = s0; sb < s1; sb += kFarBlock) {
+        const int ns = min(kFarBlock, s1 - sb);
+        __syncthreads();   // the previous tile is consumed
+        if ((int)threadIdx.x < ns) {
+            const int s = sb + threadIdx.x;
             const float *st = stat + (size_t)s * kStat;
-            const float nsx = st[18], nsy = st[19], nsz = st[20];
-            const float b1 = dync[2 * (size_t)s], b2 = dync[2 * (size_t)s + 1];
-            const float dx = cx - st[37], dy = cy - st[38], dz = cz - st[39];
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float ri = rsqrt_r(r2);
-            const float r = r2 * ri;
-            const float e = expneg(cf.kexp, r);
-            const float ri3 = ri * ri * ri;
-            const float dns = dx * nsx + dy * nsy + dz * nsz;
-            const float tt = cf.kappa * r + 1.0f;
-            float g = 0.0f;
-            if (FORM == 0) {
-                a1 += ri3 * dns * cf.kL * b1 + ri * cf.vL * b2;
-                a2 += e * (ri3 * tt * dns * cf.kY * b1 + ri * cf.vY * b2);
-            } else {
-                const float fy = e * tt * ri3, gy = e * ri;
-                const float dnt = dx * ntx + dy * nty + dz * ntz;
-                const float k2nn = cf.aDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
-                const float fk = FORM == 3 ? fy : ri3 + cf.rK * fy, fv = FORM == 3 ? gy : ri + cf.rV * gy;
-                const float ft = FORM == 3 ? fy : ri3 + cf.rT * fy;
-                a1 += fk * dns * cf.aK * b1 + fv * cf.aV * b2;
-                a2 += ft * dnt * cf.aT * b2 + k2nn * gy * b1;
-                g = FORM == 3 ? gy : FORM == 1 ? fv : ri + cf.rD * gy;
-            }
-            if (FORM >= 1) {
-                const float *sd = dyn + (size_t)s * kDyn;
-                W0 += g * sd[12];
-                W1 += g * sd[13];
-                W2 += g * sd[14];
-            }
+            const float *sd = dyn + (size_t)s * kDyn;
+            rec[0][threadIdx.x] = make_float4(st[37], st[38], st[39], dync[2 * (size_t)s]);
+            rec[1][threadIdx.x] = make_float4(st[18], st[19], st[20], dync[2 * (size_t)s + 1]);
+            rec[2][threadIdx.x] = make_float4(sd[12], sd[13], sd[14], 0.0f);
+            vid[threadIdx.x] = make_int4(tri[3 * s], tri[3 * s + 1], tri[3 * s + 2], 0);
         }
-        A1 += a1;
-        A2 += a2;
-        X0 += W0;
-        X1 += W1;
-        X2 += W2;
+        __syncthreads();
+        for (int r0 = 0; r0 < ns; r0 += kCenRun) {
+            float a1 = 0, a2 = 0, W0 = 0, W1 = 0, W2 = 0;
+            for (int k = r0; k < min(ns, r0 + kCenRun); ++k) {
+                const int4 j = vid[k];
+                const bool adj = (j.x == v0) | (j.x == v1) | (j.x == v2) | (j.y == v0) | (j.y == v1) |
+                                 (j.y == v2) | (j.z == v0) | (j.z == v1) | (j.z == v2);
+                if (adj) continue;
+                const float4 c = rec[0][k], n = rec[1][k];
+                const float b1 = c.w, b2 = n.w;
+                const float dx = cx - c.x, dy = cy - c.y, dz = cz - c.z;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float ri = rsqrt_r(r2);
+                const float r = r2 * ri;
+                const float e = expneg(cf.kexp, r);
+                const float ri3 = ri * ri * ri;
+                const float dns = dx * n.x + dy * n.y + dz * n.z;
+                const float tt = cf.kappa * r + 1.0f;
+                if (FORM == 0) {
+                    a1 += ri3 * dns * cf.kL * b1 + ri * cf.vL * b2;
+                    a2 += e * (ri3 * tt * dns * cf.kY * b1 + ri * cf.vY * b2);
+                } else {
+                    const float fy = e * tt * ri3, gy = e * ri;
+                    const float dnt = dx * ntx + dy * nty + dz * ntz;
+                    const float k2nn = cf.aDY * cf.k2 * (ntx * n.x + nty * n.y + ntz * n.z);
+                    const float fk = FORM == 3 ? fy : ri3 + cf.rK * fy, fv = FORM == 3 ? gy : ri + cf.rV * gy;
+                    const float ft = FORM == 3 ? fy : ri3 + cf.rT * fy;
+                    a1 += fk * dns * cf.aK * b1 + fv * cf.aV * b2;
+                    a2 += ft * dnt * cf.aT * b2 + k2nn * gy * b1;
+                    const float g = FORM == 3 ? gy : FORM == 1 ? fv : ri + cf.rD * gy;
+                    const float4 C = rec[2][k];
+                    W0 += g * C.x;
+                    W1 += g * C.y;
+                    W2 += g * C.z;
+                }
+            }
+            A1 += a1;
+            A2 += a2;
+            X0 += W0;
+            X1 += W1;
+            X2 += W2;
+        }
     }
+    if (t >= T) return;
     float *o = part + ((size_t)blockIdx.y * T + t) * 16;
 #pragma unroll
     for (int p = 0; p < 6; ++p) { o[p] = (float)A1; o[6 + p] = (float)A2; }
