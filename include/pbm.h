@@ -98,6 +98,13 @@ typedef int32_t pb_status;
 #define PB_MATRIX_FREE  0  /* far field recomputed on every matvec */
 #define PB_ASSEMBLED    1  /* far field assembled once as a dense 2V x 2V matrix */
 #define PB_AUTO         2  /* assembled when it fits the device-memory budget */
+#define PB_TREECODE     3  /* matrix-free with the far field approximated by a barycentric
+                              Lagrange treecode (a hierarchical scheme in place of the paper's
+                              FMM, Implementation): source clusters whose bounding spheres and
+                              the target batch's are well separated (r_batch + r_cluster <
+                              tree_theta * distance) act through (tree_degree + 1)^3 Chebyshev
+                              proxy points; other pairs are summed directly as in
+                              PB_MATRIX_FREE.  FP64 or FP32 evaluation as for PB_MATRIX_FREE. */
 
 typedef struct {
     int32_t n_vertices;
@@ -120,7 +127,7 @@ typedef struct {
     int32_t formulation;      /* PB_DIRECT_INT ... PB_PMCHWT_EXT */
     int32_t preconditioner;   /* PB_PREC_NONE ... PB_SCALED_CALDERON_EXT */
     int32_t precision;        /* PB_FP64, PB_FP32, PB_MIXED_BF16, PB_MIXED_FP16 */
-    int32_t operator_mode;    /* PB_MATRIX_FREE, PB_ASSEMBLED, PB_AUTO */
+    int32_t operator_mode;    /* PB_MATRIX_FREE, PB_ASSEMBLED, PB_AUTO, PB_TREECODE */
     double tol;               /* relative preconditioned residual (paper: 1e-5) */
     int32_t max_iter;         /* GMRES iterations (no restart), default 1000 */
     int32_t singular_order;   /* Gauss points per dimension, Sauter-Schwab (default 4) */
@@ -136,6 +143,8 @@ typedef struct {
                                  evaluated matrix-free in FP32 whatever the handle's precision
                                  and operator mode, and Sauter-Schwab with singular_order - 1
                                  Gauss points per dimension (at least 1) on pairs sharing one */
+    int32_t tree_degree;      /* PB_TREECODE: interpolation degree per dimension, 2..7 (default 5) */
+    double tree_theta;        /* PB_TREECODE: separation ratio, 0 < theta < 1 (default 0.5) */
 } pb_options;
 
 typedef struct {

@@ -50,6 +50,7 @@ PB_MIXED_FP16 = 3
 PB_MATRIX_FREE = 0
 PB_ASSEMBLED = 1
 PB_AUTO = 2
+PB_TREECODE = 3
 PB_APPLY_PRECOND = 1
 PB_APPLY_FAR_ONLY = 2
 PB_APPLY_NEAR_ONLY = 4
@@ -78,7 +79,7 @@ class pb_options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("singular_order", ctypes.c_int32),
                 ("source_chunks", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("memory_budget", ctypes.c_size_t), ("use_graph", ctypes.c_int32),
-                ("calderon_fast", ctypes.c_int32)]
+                ("calderon_fast", ctypes.c_int32), ("tree_degree", ctypes.c_int32), ("tree_theta", ctypes.c_double)]
 
 
 class pb_result(ctypes.Structure):

@@ -1,0 +1,472 @@
+// Far-field acceleration: a barycentric Lagrange treecode (cluster-particle,
+// kernel independent; L. Wang, R. Krasny and S. Tlupova, Commun. Comput. Phys.
+// 28 (2020)), the GPU-friendly hierarchical scheme standing in for the
+// paper's FMM (Implementation, Results: ExaFMM).
+//
+// Sources: the 6 regular quadrature points of every triangle with the
+// matrix-free weights (b1, b2, curl weights).  A binary tree splits the
+// Morton-ordered triangles at the highest differing bit of their Morton codes
+// (so every node is an octree-like cell) down to leaves of at most kTreeLeaf
+// triangles.  Targets: batches of kTreeBatch consecutive triangles (one
+// wavefront, a lane per triangle and its 6 points).  A batch takes a cluster
+// through its proxies when r_batch + r_cluster < theta * |c_batch - c_cluster|
+// (bounding spheres of the triangles' vertices: triangles sharing a vertex
+// never pass, so near pairs are always summed directly) and the cluster has
+// more points than proxies; otherwise leaves are summed directly with the
+// regular rule, pairs sharing a vertex skipped as in k_far.
+//
+// Proxies: the (degree+1)^3 tensor Chebyshev points of the second kind on the
+// cluster's box.  With L_k the tensor barycentric Lagrange basis, every
+// kernel is interpolated in its source variable, G(x, y) ~ sum_k G(x, s_k)
+// L_k(y), so per proxy
+//   qK = sum_y b1 n_y . grad L_k(y)    (double layer: n_y . grad_y G)
+//   qV = sum_y b2 L_k(y)               (single layer; adjoint double layer
+//                                       and curl part use the target-side
+//                                       kernel at s_k)
+//   qC = sum_y w_q C_s L_k(y)          (hypersingular curl part, 3 components)
+//   qN = sum_y b1 n_y L_k(y)           (its kappa^2 (n_x . n_y) term)
+// and a target point sees every kernel of the formulation evaluated at s_k.
+// Per batch the interaction list is split into `nsplit` pieces of about
+// equal work; each piece writes its own partial sums (the layout of k_far's
+// source chunks), which k_far_finish adds in FP64.
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <vector>
+
+#include "far.h"
+
+namespace pbm {
+
+constexpr int kTreeLeaf = 64;
+constexpr int kTreeBatch = 64;
+constexpr int kProxRec = 12;   // proxy record: position 3, qK, qV, qC 3, qN 3, pad
+
+struct Tree {
+    int degree = 0, np = 0, nfar = 0, nbatch = 0, nsplit = 1;
+    double theta = 0.0;
+    double evals = 0.0;                 // kernel evaluations per product (point pairs + point-proxy pairs)
+    int32_t *node_range = nullptr;      // node -> first, end triangle
+    int32_t *far_node = nullptr;        // far cluster f -> node
+    double *box = nullptr;              // far cluster f -> centre 3, half-width 3
+    int32_t *piece_ptr = nullptr;       // (batch * nsplit + piece) -> first entry
+    int32_t *entry = nullptr;           // f << 1 | 1 (proxies of far cluster f) or node << 1 (leaf, direct)
+    void *prox = nullptr;               // nfar x np x kProxRec reals (FP64 or FP32 as the handle evaluates)
+};
+
+int tree_splits(const Tree &t) { return t.nsplit; }
+
+namespace {
+
+struct Node {
+    int b, e, c0 = -1, c1 = -1;
+    double lo[3], hi[3];
+    double centre(int c) const { return 0.5 * (lo[c] + hi[c]); }
+    double radius() const
+    {
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) s += 0.25 * (hi[c] - lo[c]) * (hi[c] - lo[c]);
+        return std::sqrt(s);
+    }
+};
+
+void tri_box(const HostMesh &hm, int b, int e, double *lo, double *hi)
+{
+    for (int c = 0; c < 3; ++c) { lo[c] = 1e300; hi[c] = -1e300; }
+    for (int t = b; t < e; ++t)
+        for (int k = 0; k < 3; ++k) {
+            const double *p = &hm.xyz[3 * (size_t)hm.tri[3 * (size_t)t + k]];
+            for (int c = 0; c < 3; ++c) { lo[c] = std::min(lo[c], p[c]); hi[c] = std::max(hi[c], p[c]); }
+        }
+}
+
+}  // namespace
+
+Tree *tree_create(DevMesh &d)
+{
+    const HostMesh &hm = d.hm;
+    const int T = hm.T;
+    std::unique_ptr<Tree> tr(new Tree());
+    tr->degree = d.opt.tree_degree;
+    tr->theta = d.opt.tree_theta;
+    const int n1 = tr->degree + 1;
+    tr->np = n1 * n1 * n1;
+
+    // source tree
+    std::vector<Node> nodes;
+    nodes.reserve(4 * (size_t)(T / kTreeLeaf + 1));
+    nodes.push_back(Node{0, T});
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        Node nd = nodes[i];
+        tri_box(hm, nd.b, nd.e, nd.lo, nd.hi);
+        if (nd.e - nd.b > kTreeLeaf) {
+            const uint32_t kb = hm.mkey[nd.b], ke = hm.mkey[nd.e - 1];
+            int m = (nd.b + nd.e) / 2;
+            if (kb != ke) {
+                const int bit = 31 - __builtin_clz(kb ^ ke);
+                m = (int)(std::partition_point(hm.mkey.begin() + nd.b, hm.mkey.begin() + nd.e,
+                                               [bit](uint32_t k) { return ((k >> bit) & 1u) == 0u; }) -
+                          hm.mkey.begin());
+                if (m <= nd.b || m >= nd.e) m = (nd.b + nd.e) / 2;
+            }
+            nd.c0 = (int)nodes.size();
+            nd.c1 = nd.c0 + 1;
+            nodes.push_back(Node{nd.b, m});
+            nodes.push_back(Node{m, nd.e});
+        }
+        nodes[i] = nd;
+    }
+
+    // target batches and their interaction lists
+    tr->nbatch = (T + kTreeBatch - 1) / kTreeBatch;
+    tr->nsplit = std::max(1, std::min(16, (4096 + tr->nbatch - 1) / tr->nbatch));
+    std::vector<int32_t> far_of(nodes.size(), -1), far_node, piece_ptr(1, 0), entry;
+    std::vector<int32_t> list;
+    std::vector<double> cost;
+    std::vector<int> stack;
+    double evals = 0.0;
+    for (int bt = 0; bt < tr->nbatch; ++bt) {
+        const int tb = bt * kTreeBatch, te = std::min(T, tb + kTreeBatch);
+        Node bn{tb, te};
+        tri_box(hm, tb, te, bn.lo, bn.hi);
+        const double rb = bn.radius();
+        list.clear();
+        cost.clear();
+        stack.assign(1, 0);
+        while (!stack.empty()) {
+            const int i = stack.back();
+            stack.pop_back();
+            const Node &nd = nodes[i];
+            double dist2 = 0.0;
+            for (int c = 0; c < 3; ++c) dist2 += (bn.centre(c) - nd.centre(c)) * (bn.centre(c) - nd.centre(c));
+            const bool sep = rb + nd.radius() < tr->theta * std::sqrt(dist2);
+            if (sep && 6 * (nd.e - nd.b) > tr->np) {
+                if (far_of[i] < 0) {
+                    far_of[i] = (int32_t)far_node.size();
+                    far_node.push_back(i);
+                }
+                list.push_back(far_of[i] << 1 | 1);
+                cost.push_back((double)tr->np);
+            } else if (nd.c0 < 0) {
+                list.push_back(i << 1);
+                cost.push_back(6.0 * (nd.e - nd.b));
+            } else {
+                stack.push_back(nd.c1);
+                stack.push_back(nd.c0);
+            }
+        }
+        double total = 0.0;
+        for (double c : cost) total += c;
+        evals += 6.0 * (te - tb) * total;
+        // nsplit pieces of about total / nsplit work each, in list order
+        double acc = 0.0;
+        size_t k = 0;
+        for (int p = 0; p < tr->nsplit; ++p) {
+            const double stop = total * (p + 1) / tr->nsplit;
+            while (k < list.size() && (acc + 0.5 * cost[k] <= stop || p == tr->nsplit - 1)) {
+                entry.push_back(list[k]);
+                acc += cost[k];
+                ++k;
+            }
+            piece_ptr.push_back((int32_t)entry.size());
+        }
+    }
+    tr->nfar = (int)far_node.size();
+    tr->evals = evals;
+
+    // interpolation boxes: the cluster's vertex box, no dimension thinner
+    // than 1e-3 of its widest (flat clusters)
+    std::vector<double> box(6 * (size_t)std::max(tr->nfar, 1), 0.0);
+    for (int f = 0; f < tr->nfar; ++f) {
+        const Node &nd = nodes[far_node[f]];
+        double hmax = 0.0;
+        for (int c = 0; c < 3; ++c) hmax = std::max(hmax, 0.5 * (nd.hi[c] - nd.lo[c]));
+        for (int c = 0; c < 3; ++c) {
+            box[6 * (size_t)f + c] = nd.centre(c);
+            box[6 * (size_t)f + 3 + c] = std::max(0.5 * (nd.hi[c] - nd.lo[c]), 1e-3 * hmax);
+        }
+    }
+    std::vector<int32_t> range(2 * nodes.size());
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        range[2 * i] = nodes[i].b;
+        range[2 * i + 1] = nodes[i].e;
+    }
+    auto up = [&](const void *src, size_t bytes) {
+        void *p = d.alloc(std::max<size_t>(bytes, 4));
+        if (bytes) HIPCHECK(hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, d.stream));
+        return p;
+    };
+    tr->node_range = (int32_t *)up(range.data(), sizeof(int32_t) * range.size());
+    tr->far_node = (int32_t *)up(far_node.data(), sizeof(int32_t) * far_node.size());
+    tr->box = (double *)up(box.data(), sizeof(double) * box.size());
+    tr->piece_ptr = (int32_t *)up(piece_ptr.data(), sizeof(int32_t) * piece_ptr.size());
+    tr->entry = (int32_t *)up(entry.data(), sizeof(int32_t) * entry.size());
+    const size_t rsz = d.prm.precision == PB_FP64 ? sizeof(double) : sizeof(float);
+    tr->prox = d.alloc(rsz * kProxRec * (size_t)tr->np * std::max(tr->nfar, 1));
+    HIPCHECK(hipStreamSynchronize(d.stream));   // host vectors go out of scope
+    return tr.release();
+}
+
+void tree_destroy(DevMesh &d)
+{
+    delete d.tree;   // device memory belongs to the handle's allocation list
+    d.tree = nullptr;
+}
+
+// ------------------------------------------------------------ upward pass
+// One block per far cluster: 64 source points at a time are staged in LDS;
+// threads (point, dimension) form the 1-D barycentric basis values and
+// derivatives at the Chebyshev nodes, then each thread accumulates the
+// charges of its proxies.  FP64 throughout; stored as RP.
+constexpr int kUpPts = 64;
+
+template <typename RP>
+__global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int32_t *__restrict__ far_node,
+                                                      const int32_t *__restrict__ node_range,
+                                                      const double *__restrict__ box,
+                                                      const double *__restrict__ stat,
+                                                      const double *__restrict__ dyn, RP *__restrict__ prox,
+                                                      DevCtl ctl)
+{
+    __shared__ double tn[kTreeMaxDegree + 1], wb[kTreeMaxDegree + 1];
+    __shared__ double pt[kUpPts][11];                            // t 3, b1, b2, w C 3, n 3
+    __shared__ double la[kUpPts][3][kTreeMaxDegree + 1], lb[kUpPts][3][kTreeMaxDegree + 1];
+    if (ctl_skip(ctl)) return;
+    const int f = blockIdx.x, tid = threadIdx.x, n1 = deg + 1;
+    const int node = far_node[f];
+    const int b = node_range[2 * node], e = node_range[2 * node + 1];
+    const double *bx = box + 6 * (size_t)f;
+    if (tid < n1) {
+        tn[tid] = cos(kPi * tid / deg);
+        wb[tid] = ((tid & 1) ? -1.0 : 1.0) * ((tid == 0 || tid == deg) ? 0.5 : 1.0);
+    }
+    double acc[2][8];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[a][c] = 0.0;
+    const int npts = 6 * (e - b);
+    for (int base = 0; base < npts; base += kUpPts) {
+        __syncthreads();   // previous chunk consumed (and tn, wb written)
+        if (tid < kUpPts) {
+            const int p = base + tid;
+            if (p < npts) {
+                const int s = b + p / 6, q = p % 6;
+                const double *st = stat + (size_t)s * kStat;
+                const double *sd = dyn + (size_t)s * kDyn;
+                for (int c = 0; c < 3; ++c) pt[tid][c] = (st[3 * q + c] - bx[c]) / bx[3 + c];
+                pt[tid][3] = sd[q];
+                pt[tid][4] = sd[6 + q];
+                for (int c = 0; c < 3; ++c) pt[tid][5 + c] = rule_w(q) * sd[12 + c];
+                for (int c = 0; c < 3; ++c) pt[tid][8 + c] = st[18 + c];
+            } else {
+                for (int c = 0; c < 11; ++c) pt[tid][c] = 0.0;
+                pt[tid][0] = pt[tid][1] = pt[tid][2] = 0.5;   // any point in the box; weights are zero
+            }
+        }
+        __syncthreads();
+        if (tid < 3 * kUpPts) {
+            const int pp = tid / 3, dim = tid % 3;
+            const double t = pt[pp][dim];
+            int hit = -1;
+            for (int m = 0; m < n1; ++m)
+                if (fabs(t - tn[m]) < 1e-13) hit = m;
+            if (hit < 0) {
+                double S = 0.0, S2 = 0.0;
+                for (int m = 0; m < n1; ++m) {
+                    const double r = wb[m] / (t - tn[m]);
+                    S += r;
+                    S2 += r / (t - tn[m]);
+                }
+                for (int m = 0; m < n1; ++m) {
+                    const double L = wb[m] / (t - tn[m]) / S;
+                    la[pp][dim][m] = L;
+                    lb[pp][dim][m] = L * (S2 / S - 1.0 / (t - tn[m]));
+                }
+            } else {
+                // at a node: Kronecker values, the differentiation matrix row
+                double diag = 0.0;
+                for (int m = 0; m < n1; ++m) {
+                    la[pp][dim][m] = m == hit ? 1.0 : 0.0;
+                    if (m != hit) {
+                        const double v = (wb[m] / wb[hit]) / (tn[hit] - tn[m]);
+                        lb[pp][dim][m] = v;
+                        diag -= v;
+                    }
+                }
+                lb[pp][dim][hit] = diag;
+            }
+        }
+        __syncthreads();
+        const int cnt = min(kUpPts, npts - base);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int k = tid + 256 * a;
+            if (k >= np) break;
+            const int i = k / (n1 * n1), j = (k / n1) % n1, l = k % n1;
+            for (int pp = 0; pp < cnt; ++pp) {
+                const double Lx = la[pp][0][i], Ly = la[pp][1][j], Lz = la[pp][2][l];
+                const double L = Lx * Ly * Lz;
+                const double gx = lb[pp][0][i] * Ly * Lz / bx[3], gy = Lx * lb[pp][1][j] * Lz / bx[4],
+                             gz = Lx * Ly * lb[pp][2][l] / bx[5];
+                const double *P = pt[pp];
+                acc[a][0] += P[3] * (P[8] * gx + P[9] * gy + P[10] * gz);
+                acc[a][1] += P[4] * L;
+                acc[a][2] += P[5] * L;
+                acc[a][3] += P[6] * L;
+                acc[a][4] += P[7] * L;
+                acc[a][5] += P[3] * P[8] * L;
+                acc[a][6] += P[3] * P[9] * L;
+                acc[a][7] += P[3] * P[10] * L;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int k = tid + 256 * a;
+        if (k >= np) break;
+        const int i = k / (n1 * n1), j = (k / n1) % n1, l = k % n1;
+        RP *o = prox + ((size_t)f * np + k) * kProxRec;
+        o[0] = (RP)(bx[0] + bx[3] * tn[i]);
+        o[1] = (RP)(bx[1] + bx[4] * tn[j]);
+        o[2] = (RP)(bx[2] + bx[5] * tn[l]);
+        for (int c = 0; c < 8; ++c) o[3 + c] = (RP)acc[a][c];
+        o[11] = (RP)0;
+    }
+}
+
+// ------------------------------------------------------------- evaluation
+// One wavefront per (batch, piece): lanes own target triangles; list entries
+// are wavefront-uniform, so proxy records and source triangles come through
+// scalar loads.  Each entry is summed in R, the entries in FP64.
+template <typename R, int FORM>
+__global__ __launch_bounds__(kTreeBatch) void k_tree_eval(int T, int nsplit, int np, FarCoef<R> cf,
+                                                          const int32_t *__restrict__ tri,
+                                                          const R *__restrict__ stat, const R *__restrict__ dyn,
+                                                          const int32_t *__restrict__ node_range,
+                                                          const int32_t *__restrict__ piece_ptr,
+                                                          const int32_t *__restrict__ entry,
+                                                          const R *__restrict__ prox, R *__restrict__ part,
+                                                          DevCtl ctl)
+{
+    if (ctl_skip(ctl)) return;
+    const int t = blockIdx.x * kTreeBatch + threadIdx.x;
+    const int tc = t < T ? t : T - 1;   // lanes past the end compute, never store
+    const R *ts = stat + (size_t)tc * kStat;
+    R tx[6], ty[6], tz[6], xnt[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2];
+        xnt[p] = ts[21 + p];
+    }
+    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+    const int v0 = tri[3 * tc], v1 = tri[3 * tc + 1], v2 = tri[3 * tc + 2];
+    double A1[6], A2[6], X0 = 0, X1 = 0, X2 = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) { A1[p] = 0; A2[p] = 0; }
+    const int pc = blockIdx.x * nsplit + blockIdx.y;
+    for (int en = piece_ptr[pc]; en < piece_ptr[pc + 1]; ++en) {
+        const int code = entry[en];
+        R a1[6], a2[6], W0 = 0, W1 = 0, W2 = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) { a1[p] = 0; a2[p] = 0; }
+        if (code & 1) {
+            const R *P = prox + (size_t)(code >> 1) * np * kProxRec;
+            for (int k = 0; k < np; ++k, P += kProxRec) {
+                const R sx = P[0], sy = P[1], sz = P[2];
+                const R qK = P[3], qV = P[4];
+                R gw = 0, ntqN = 0, snt = 0;
+                if (FORM >= 1) {
+                    ntqN = cf.aDY * cf.k2 * (ntx * P[8] + nty * P[9] + ntz * P[10]);
+                    snt = sx * ntx + sy * nty + sz * ntz;
+                }
+#pragma unroll
+                for (int p = 0; p < 6; ++p) {
+                    const R dx = tx[p] - sx, dy = ty[p] - sy, dz = tz[p] - sz;
+                    const R r2 = dx * dx + dy * dy + dz * dz;
+                    const R ri = rsqrt_r(r2);
+                    const R r = r2 * ri;
+                    const R e = expneg(cf.kexp, r);
+                    if (FORM == 0) {
+                        a1[p] += ri * (cf.kL * qK + cf.vL * qV);
+                        a2[p] += e * ri * (cf.kY * qK + cf.vY * qV);
+                    } else {
+                        const R ri3 = ri * ri * ri;
+                        const R gy = e * ri, fy = e * (cf.kappa * r + R(1)) * ri3;
+                        const R dnt = xnt[p] - snt;
+                        const R gk = FORM == 3 ? gy : ri + cf.rK * gy, gv = FORM == 3 ? gy : ri + cf.rV * gy;
+                        const R ft = FORM == 3 ? fy : ri3 + cf.rT * fy;
+                        a1[p] += cf.aK * gk * qK + cf.aV * gv * qV;
+                        a2[p] += cf.aT * ft * dnt * qV + ntqN * gy;
+                        gw += R(rule_w(p)) * (FORM == 3 || FORM == 1 ? gv : ri + cf.rD * gy);
+                    }
+                }
+                if (FORM >= 1) {
+                    W0 += gw * P[5];
+                    W1 += gw * P[6];
+                    W2 += gw * P[7];
+                }
+            }
+        } else {
+            const int nd = code >> 1;
+            const int sb = node_range[2 * nd], se = node_range[2 * nd + 1];
+            for (int s = sb; s < se; ++s) {
+                const int j0 = tri[3 * s], j1 = tri[3 * s + 1], j2 = tri[3 * s + 2];
+                const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
+                                 (j2 == v0) | (j2 == v1) | (j2 == v2);
+                if (adj) continue;
+                far_source<R, FORM>(s, cf, stat, dyn, tx, ty, tz, xnt, ntx, nty, ntz, a1, a2, W0, W1, W2);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 6; ++p) { A1[p] += a1[p]; A2[p] += a2[p]; }
+        X0 += W0;
+        X1 += W1;
+        X2 += W2;
+    }
+    if (t >= T) return;
+    R *o = part + ((size_t)blockIdx.y * T + t) * 16;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) { o[p] = (R)A1[p]; o[6 + p] = (R)A2[p]; }
+    o[12] = (R)X0; o[13] = (R)X1; o[14] = (R)X2; o[15] = 0;
+}
+
+template <typename R>
+static void tree_launch(DevMesh &d, const R *stat, const R *dyn)
+{
+    Tree &tr = *d.tree;
+    if (tr.nfar > 0)
+        hipLaunchKernelGGL(k_tree_charges<R>, dim3(tr.nfar), dim3(256), 0, d.stream, tr.degree, tr.np, tr.far_node,
+                           tr.node_range, tr.box, d.stat64, d.dyn64, (R *)tr.prox, d.ctl);
+    FarCoef<R> cf;
+    const int form = far_coef(d, cf);
+    const dim3 grid(tr.nbatch, tr.nsplit), block(kTreeBatch);
+#define TREE_EVAL(F)                                                                                              \
+    hipLaunchKernelGGL((k_tree_eval<R, F>), grid, block, 0, d.stream, d.hm.T, tr.nsplit, tr.np, cf, d.tri, stat,  \
+                       dyn, tr.node_range, tr.piece_ptr, tr.entry, (const R *)tr.prox, (R *)d.part, d.ctl)
+    if (form == 0) TREE_EVAL(0);
+    else if (form == 1) TREE_EVAL(1);
+    else if (form == 2) TREE_EVAL(2);
+    else TREE_EVAL(3);
+#undef TREE_EVAL
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_tree_far(DevMesh &d, bool fp32)
+{
+    Profiler &pf = d.prof;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (pf.on(0)) {
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, d.stream));
+    }
+    if (fp32) tree_launch<float>(d, d.stat32, d.dyn32);
+    else tree_launch<double>(d, d.stat64, d.dyn64);
+    if (pf.on(0)) {
+        HIPCHECK(hipEventRecord(e1, d.stream));
+        pf.record(0, e0, e1, d.tree->evals);   // point-pair and point-proxy kernel evaluations
+    }
+}
+
+}  // namespace pbm

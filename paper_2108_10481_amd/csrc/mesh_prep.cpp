@@ -146,6 +146,8 @@ void build_host_mesh(const pb_mesh *m, HostMesh &hm)
     std::sort(key.begin(), key.end());
     hm.perm.resize(T);
     hm.iperm.resize(T);
+    hm.mkey.resize(T);
+    for (int t = 0; t < T; ++t) hm.mkey[t] = (uint32_t)(key[t] >> 32);
     hm.tri.resize(3 * (size_t)T);
     for (int t = 0; t < T; ++t) {
         int orig = (int)(key[t] & 0xffffffffu);

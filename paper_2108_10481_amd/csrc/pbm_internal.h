@@ -50,6 +50,7 @@ struct HostMesh {
     std::vector<double> xyz;          // V x 3
     std::vector<int32_t> tri;         // T x 3, sorted triangle order, input local order
     std::vector<int32_t> perm;        // sorted position -> input triangle id
+    std::vector<uint32_t> mkey;       // 30-bit Morton code of each sorted triangle's centroid (ascending)
     std::vector<int32_t> iperm;       // input triangle id -> sorted position
     std::vector<int32_t> inc_ptr;     // V + 1
     std::vector<int32_t> inc_tk;      // 4 t + k for each incidence (t sorted id)
@@ -169,6 +170,8 @@ struct Profiler {
 };
 
 struct Dense;       // assembled far field (k_dense.hip)
+struct Tree;        // treecode far field (k_tree.hip)
+constexpr int kTreeMaxDegree = 7;
 struct BatchWork;   // multi right-hand side workspaces (k_batch.hip)
 
 struct Krylov {
@@ -233,6 +236,7 @@ struct DevMesh {
     int redcap = 0;
     Dense *dense = nullptr;
     const int32_t *dense_vpos = nullptr;   // vertex -> row of the dense far field
+    Tree *tree = nullptr;                  // treecode plan (PB_TREECODE)
     BatchWork *bw = nullptr;
 
     Profiler prof;
@@ -292,6 +296,13 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res);
 int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
 int gmres_solve(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
 void destroy_graphs(DevMesh &d);
+
+// treecode far field (k_tree.hip): plan built on the host at creation; the
+// product writes d.part in the layout of tree_splits() source chunks
+Tree *tree_create(DevMesh &d);
+int tree_splits(const Tree &t);
+void tree_destroy(DevMesh &d);
+void launch_tree_far(DevMesh &d, bool fp32);
 
 // assembled far field and mixed precision (k_dense.hip)
 bool dense_fits(const DevMesh &d, int copies = 1);

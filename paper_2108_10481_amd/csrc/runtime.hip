@@ -49,6 +49,7 @@ DevMesh::~DevMesh()
     destroy_dense(*this);
     std::swap(dense, denseP);
     destroy_dense(*this);
+    tree_destroy(*this);
     destroy_batch(*this);
     for (void *p : allocs) (void)hipFreeAsync(p, stream);
     if (stream) (void)hipStreamSynchronize(stream);
@@ -84,7 +85,14 @@ static void check_options(const pb_options *o)
     if (o->calderon_fast && !is_calderon(o->preconditioner))
         fail(PB_E_INVALID_ARG, "calderon_fast needs a Calderon preconditioner");
     if (o->precision < PB_FP64 || o->precision > PB_MIXED_FP16) fail(PB_E_INVALID_ARG, "unknown precision");
-    if (o->operator_mode < PB_MATRIX_FREE || o->operator_mode > PB_AUTO) fail(PB_E_INVALID_ARG, "unknown operator mode");
+    if (o->operator_mode < PB_MATRIX_FREE || o->operator_mode > PB_TREECODE)
+        fail(PB_E_INVALID_ARG, "unknown operator mode");
+    if (o->operator_mode == PB_TREECODE) {
+        if (o->precision >= PB_MIXED_BF16)
+            fail(PB_E_INVALID_ARG, "the treecode far field runs in FP64 or FP32 (mixed modes need the assembled field)");
+        if (o->tree_degree < 2 || o->tree_degree > kTreeMaxDegree) fail(PB_E_INVALID_ARG, "tree_degree must be in [2, 7]");
+        if (!(o->tree_theta > 0.0 && o->tree_theta < 1.0)) fail(PB_E_INVALID_ARG, "tree_theta must be in (0, 1)");
+    }
     if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
     if (o->singular_order < 1 || o->singular_order > 8) fail(PB_E_INVALID_ARG, "singular_order must be in [1, 8]");
     if (o->source_chunks < 0 || o->source_chunks > 1024) fail(PB_E_INVALID_ARG, "source_chunks must be in [0, 1024]");
@@ -275,6 +283,10 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     const HostMesh &hm = d->hm;
     const int V = hm.V, T = hm.T;
     d->S = opt->source_chunks > 0 ? std::min(opt->source_chunks, T) : choose_chunks(T);
+    if (opt->operator_mode == PB_TREECODE) {
+        d->tree = tree_create(*d);
+        d->S = tree_splits(*d->tree);
+    }
 
     d->xyz = upload(*d, hm.xyz);
     d->tri = upload(*d, hm.tri);
@@ -375,6 +387,11 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
         b += 5.0 * kMassBatch * n * 8 + 20.0 * v * 8 + v * 8;   // Chebyshev state, products, M, 1 / M_ii
     if (cal) b += 2.0 * n * 8 + (cal_sep ? 4.0 * 20.0 * v * 8 : 0.0);   // work vectors, P's near field
     if (cal && o->calderon_fast) b += 16.0 * t * (38 * 8) + t * 8;   // P's pair blocks and sums, centroid weights
+    if (o->operator_mode == PB_TREECODE) {
+        const double np = std::pow(o->tree_degree + 1.0, 3.0);
+        b += t / 16.0 * np * 12 * 8 + 64.0 * t;   // proxies of about T/16 clusters, lists
+        b += 16.0 * 16 * t * 8;                    // up to 16 pieces of partial sums
+    }
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
     return (size_t)(b * 1.1);
 }
@@ -395,6 +412,12 @@ static int far_product(DevMesh &d, const double *x, int flags)
         return 2;
     }
     const bool fp32 = d.prm.precision == PB_FP32;
+    if (d.tree) {
+        launch_source_prep(d, x, fp32);
+        launch_tree_far(d, fp32);
+        launch_far_finish(d, fp32);
+        return 1;
+    }
     launch_source_prep(d, x, fp32);
     launch_far(d, fp32);
     launch_far_finish(d, fp32);
@@ -838,6 +861,8 @@ void pb_default_options(pb_options *o)
     o->inner_tol = 1e-3;
     o->memory_budget = 0;
     o->use_graph = 1;
+    o->tree_degree = 5;
+    o->tree_theta = 0.5;
 }
 
 const char *pb_last_error(void) { return g_err.c_str(); }

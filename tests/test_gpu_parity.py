@@ -832,3 +832,89 @@ def test_fast_calderon_full_size(sphere32):
         assert _rel(got, np.concatenate([r1, r2])) < 2e-6, part
         assert rf["status"] == pbm.PB_OK and ra["iterations"] <= rf["iterations"] <= ra["iterations"] + 2
         assert abs(rf["dG"] - rm["dG"]) < 1e-4 * abs(rm["dG"])
+
+
+# ------------------------------------------------------- treecode far field
+@pytest.fixture(scope="module")
+def sphere16():
+    return inputs.icosphere(16, 10.0)
+
+
+@pytest.mark.parametrize("form", [pbm.PB_DIRECT_INT, pbm.PB_JUFFER, pbm.PB_MULLER_INT, pbm.PB_PMCHWT_INT])
+def test_treecode_without_separated_clusters_is_direct(meshes, sphere16, form):
+    """With a separation ratio so small that no cluster qualifies, every pair
+    is summed directly: the treecode product equals the direct matrix-free
+    one to FP64 rounding (same sums, other order) and to FP32 rounding."""
+    for m in (meshes["star7"], sphere16):
+        x = np.random.default_rng(7).standard_normal(2 * m.n_vertices)
+        for p, tol in ((pbm.PB_FP64, 1e-13), (pbm.PB_FP32, 2e-7)):
+            with pbm.MeshHandle(m.xyz, m.tri, _opts(form, p)) as h:
+                ref = pbm.pb_mesh_apply(h, x)
+            with pbm.MeshHandle(m.xyz, m.tri, _opts(form, p, operator_mode=pbm.PB_TREECODE, tree_theta=0.01)) as h:
+                y = pbm.pb_mesh_apply(h, x)
+            assert _rel(y, ref) < tol, (form, p, _rel(y, ref))
+
+
+@pytest.mark.parametrize("form", [pbm.PB_DIRECT_INT, pbm.PB_JUFFER, pbm.PB_LU, pbm.PB_PMCHWT_EXT])
+def test_treecode_converges_with_degree(sphere16, form):
+    """5120-triangle sphere: the treecode's error against the exact product
+    (the FP64 direct matrix-free product, itself equal to the oracle's to
+    1e-12) falls geometrically with the interpolation degree, by at least 5x
+    per degree, and is below 1e-6 at the default degree 5 (theta 0.5)."""
+    m = sphere16
+    x = np.random.default_rng(11).standard_normal(2 * m.n_vertices)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form)) as h:
+        ref = pbm.pb_mesh_apply(h, x)
+    errs = []
+    for deg in (2, 3, 4, 5, 6, 7):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, operator_mode=pbm.PB_TREECODE, tree_degree=deg)) as h:
+            errs.append(_rel(pbm.pb_mesh_apply(h, x), ref))
+    print(f"treecode form {form}: errors by degree 2..7 {['%.1e' % e for e in errs]}")
+    assert all(errs[k + 1] < errs[k] / 5.0 for k in range(len(errs) - 1)), errs
+    assert errs[3] < 1e-6 and errs[-1] < 1e-9
+
+
+def test_treecode_full_size_rows_and_solve(sphere32):
+    """20480-triangle sphere, FP32 treecode (degree 5, theta 0.5): sampled rows
+    of the Juffer and internal PMCHWT products against the oracle's rows; the
+    Juffer solve (scaled mass) and the direct one reach the FP64 direct
+    matrix-free Delta G within 1e-5 with the same iterations."""
+    m, ch = sphere32
+    nv = m.n_vertices
+    rng = np.random.default_rng(61)
+    x = rng.standard_normal(2 * nv)
+    rows = np.sort(rng.choice(nv, 6, replace=False))
+    for form in (oracle.JUFFER, oracle.PMCHWT_INT):
+        r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, form, rows, x)
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_TREECODE)) as h:
+            y = pbm.pb_mesh_apply(h, x)
+        got = np.concatenate([y[rows], y[nv + rows]])
+        print(f"treecode full size form {form}: rows rel {_rel(got, np.concatenate([r1, r2])):.2e}")
+        assert _rel(got, np.concatenate([r1, r2])) < 2e-6
+    for form, prec in ((pbm.PB_JUFFER, pbm.PB_SCALED_MASS), (pbm.PB_DIRECT_INT, pbm.PB_BLOCK_DIAG)):
+        ref = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=prec))
+        got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, pbm.PB_FP32, preconditioner=prec,
+                                                              operator_mode=pbm.PB_TREECODE))
+        assert got["status"] == pbm.PB_OK and abs(got["iterations"] - ref["iterations"]) <= 1
+        assert abs(got["dG"] - ref["dG"]) < 1e-5 * abs(ref["dG"]), (form, got["dG"], ref["dG"])
+
+
+@pytest.mark.parametrize("prec", [pbm.PB_CALDERON_EXT, pbm.PB_SCALED_CALDERON_INT])
+def test_treecode_calderon(sphere16, prec):
+    """Calderon preconditioners on the treecode far field (P's far field through
+    the same tree, the Yukawa-only kernels for the exterior part): B A x within
+    1e-6 of the direct matrix-free chain; the captured solve equals the eager one."""
+    m = sphere16
+    x = np.random.default_rng(13).standard_normal(2 * m.n_vertices)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(pbm.PB_PMCHWT_INT, preconditioner=prec)) as h:
+        ref = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+    ot = _opts(pbm.PB_PMCHWT_INT, preconditioner=prec, operator_mode=pbm.PB_TREECODE)
+    with pbm.MeshHandle(m.xyz, m.tri, ot) as h:
+        y = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_PRECOND)
+    assert _rel(y, ref) < 1e-6, _rel(y, ref)
+    ch = inputs.charges_ball(5, 20, 8.0)
+    rg = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, ot)
+    ot.use_graph = 0
+    re = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, ot)
+    assert rg["status"] == pbm.PB_OK and rg["iterations"] == re["iterations"]
+    assert abs(rg["dG"] - re["dG"]) <= 1e-12 * abs(re["dG"])

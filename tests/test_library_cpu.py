@@ -96,6 +96,13 @@ def test_host_validation_rejects_bad_meshes(pbm):
     # the scaled mass matrix is defined for the Juffer formulation only, the
     # Calderon preconditioners for the PMCHWT formulations only
     assert _create_status(pbm, m.xyz, m.tri, preconditioner=pbm.PB_SCALED_MASS) == pbm.PB_E_INVALID_ARG
+    # treecode: degree in [2, 7], theta in (0, 1), FP64 or FP32 only
+    assert _create_status(pbm, m.xyz, m.tri, operator_mode=pbm.PB_TREECODE, tree_degree=1) == pbm.PB_E_INVALID_ARG
+    assert _create_status(pbm, m.xyz, m.tri, operator_mode=pbm.PB_TREECODE, tree_degree=8) == pbm.PB_E_INVALID_ARG
+    assert _create_status(pbm, m.xyz, m.tri, operator_mode=pbm.PB_TREECODE, tree_theta=1.0) == pbm.PB_E_INVALID_ARG
+    assert _create_status(pbm, m.xyz, m.tri, operator_mode=pbm.PB_TREECODE,
+                          precision=pbm.PB_MIXED_BF16) == pbm.PB_E_INVALID_ARG
+    assert _create_status(pbm, m.xyz, m.tri, operator_mode=4) == pbm.PB_E_INVALID_ARG
     for prec in range(pbm.PB_CALDERON, pbm.PB_SCALED_CALDERON_EXT + 1):
         assert _create_status(pbm, m.xyz, m.tri, preconditioner=prec) == pbm.PB_E_INVALID_ARG
         assert _create_status(pbm, m.xyz, m.tri, formulation=pbm.PB_LU, preconditioner=prec) == pbm.PB_E_INVALID_ARG
