@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--operator-mode", default="auto", choices=["matrix-free", "assembled", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=160, help="oracle rows per formulation in the CPU sample")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "star", "multi", "serving", "calderon"])
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "star", "multi", "serving", "calderon", "large"])
     ap.add_argument("--overlap", default="serial", choices=["streams", "serial"],
                     help="timed region: formulations solved one after the other (serial), or from one host "
                          "thread each on their handles' own HIP streams (streams); the other mode is timed "
@@ -506,6 +506,75 @@ def calderon(argv=None):
     print(json.dumps(rec), flush=True)
 
 
+def large(argv=None):
+    """Treecode far field at the paper's largest size: a 450000-triangle /
+    225002-vertex star surface (the paper's 1igt has 226312 vertices), 4000
+    charges, direct + block-diagonal and Juffer + scaled mass (the paper's
+    Cases 2 and 10), FP32 treecode, complete solves with every device stage
+    redone; the direct O(N^2) matrix-free product timed once beside it."""
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload")
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--freq", type=int, default=150)
+    ap.add_argument("--no-direct", action="store_true")
+    a, _ = ap.parse_known_args(argv)
+    import paper_2108_10481_amd as pbm
+    mesh, ch = inputs.config_star_large(freq=a.freq)
+    print(f"large: {mesh.n_triangles} triangles, {mesh.n_vertices} vertices", file=sys.stderr, flush=True)
+    out = {}
+    x = np.random.default_rng(0).standard_normal(2 * mesh.n_vertices)
+    for fname, form, prec in (("direct", pbm.PB_DIRECT_INT, pbm.PB_BLOCK_DIAG),
+                              ("juffer", pbm.PB_JUFFER, pbm.PB_SCALED_MASS)):
+        opt = pbm.pb_default_options(formulation=form, precision=pbm.PB_FP32, operator_mode=pbm.PB_TREECODE,
+                                     preconditioner=prec)
+        t0 = time.perf_counter()
+        with pbm.MeshHandle(mesh.xyz, mesh.tri, opt) as h:
+            t_create = time.perf_counter() - t0
+            for _ in range(a.warmup):
+                pbm.pb_mesh_refresh(h)
+                pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+            pbm.pb_mesh_profile(h, 1)
+            t1 = time.perf_counter()
+            for _ in range(a.steps):
+                pbm.pb_mesh_refresh(h)
+                r = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
+            dt = (time.perf_counter() - t1) / a.steps
+            n, ms, w = pbm.pb_mesh_profile_read(h, 0)
+            gb = h.info()["device_bytes"] / 1e9
+        # treecode product (upward pass + evaluation), HIP events on the handle's stream;
+        # algorithmic: every kernel evaluation (target point x source point or proxy)
+        # at the direct kernel's flops per pair
+        tf = w * FLOPS_PER_PAIR[form] / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        out[fname] = {"s_per_solve": round(dt, 3), "iterations": r["iterations"], "status": r["status"],
+                      "dG_kcal": r["dG"], "t_setup_s": round(r["t_setup"], 3), "t_gmres_s": round(r["t_gmres"], 3),
+                      "handle_create_s": round(t_create, 2), "device_GB": round(gb, 2),
+                      "treecode_product": {"launches": n, "avg_ms": round(ms / max(n, 1), 2),
+                                           "evals_per_product": w / max(n, 1),
+                                           "evals_per_s": round(w / (ms * 1e-3), 1) if ms > 0 else None},
+                      "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_TFLOPS["f32"],
+                                   "unit": "TFLOP/s", "frac": round(tf / PEAK_TFLOPS["f32"], 4), "traffic": None,
+                                   "kernel": "treecode product (k_tree_charges, k_tree_proxies, k_tree_eval)"}}
+        print(f"large: {fname} done", file=sys.stderr, flush=True)
+    if not a.no_direct:
+        with pbm.MeshHandle(mesh.xyz, mesh.tri, pbm.pb_default_options(formulation=pbm.PB_JUFFER,
+                                                                       precision=pbm.PB_FP32)) as h:
+            yd = pbm.pb_mesh_apply(h, x)
+            pbm.pb_mesh_profile(h, 1)
+            pbm.pb_mesh_apply(h, x)
+            n, ms, w = pbm.pb_mesh_profile_read(h, 0)
+        with pbm.MeshHandle(mesh.xyz, mesh.tri, pbm.pb_default_options(
+                formulation=pbm.PB_JUFFER, precision=pbm.PB_FP32, operator_mode=pbm.PB_TREECODE)) as h:
+            yt = pbm.pb_mesh_apply(h, x)
+        out["direct_product_fp32"] = {"ms": round(ms / max(n, 1), 1), "kernel_pairs": w / max(n, 1),
+                                      "treecode_rel_err": float(np.linalg.norm(yt - yd) / np.linalg.norm(yd))}
+    rec = {"workload": f"star surface R=36 A (seed 7), {mesh.n_triangles} triangles / {mesh.n_vertices} vertices, "
+                       f"{ch.n} charges, FP32 treecode (degree {opt.tree_degree}, theta {opt.tree_theta}), GMRES tol "
+                       "1e-5; one solve = refresh + "
+                       "solve", "steps": a.steps, "results": out}
+    print(json.dumps(rec), flush=True)
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device-to-device copy of known size (the runtime's copy kernel),
     used to scale the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -535,5 +604,7 @@ if __name__ == "__main__":
         multi()
     elif wl == "calderon":
         calderon()
+    elif wl == "large":
+        large()
     else:
         main()

@@ -143,8 +143,8 @@ typedef struct {
                                  evaluated matrix-free in FP32 whatever the handle's precision
                                  and operator mode, and Sauter-Schwab with singular_order - 1
                                  Gauss points per dimension (at least 1) on pairs sharing one */
-    int32_t tree_degree;      /* PB_TREECODE: interpolation degree per dimension, 2..7 (default 5) */
-    double tree_theta;        /* PB_TREECODE: separation ratio, 0 < theta < 1 (default 0.5) */
+    int32_t tree_degree;      /* PB_TREECODE: interpolation degree per dimension, 2..7 (default 6) */
+    double tree_theta;        /* PB_TREECODE: separation ratio, 0 < theta < 1 (default 0.7) */
 } pb_options;
 
 typedef struct {

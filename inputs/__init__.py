@@ -259,6 +259,13 @@ def config_star(freq: int = 64, seed: int = 3, n_charges: int = 2000, base_radiu
     return mesh, charges_in_star(seed + 1000, n_charges, shape)
 
 
+def config_star_large(freq: int = 150, seed: int = 7, n_charges: int = 4000, base_radius: float = 36.0):
+    """Star surface at the size of the paper's largest molecule: 450000 triangles /
+    225002 vertices at freq 150 (1igt has 226312 vertices), 4000 charges."""
+    mesh, shape = star_surface(seed, freq, base_radius)
+    return mesh, charges_in_star(seed + 1000, n_charges, shape)
+
+
 def config_sphere_multi(freq: int = 64, radius: float = 10.0, n_sets: int = 16,
                         n_charges: int = 50, seed0: int = 40):
     """Sphere (40962 vertices at freq 64) with n_sets independent charge sets."""

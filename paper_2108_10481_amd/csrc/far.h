@@ -35,16 +35,16 @@ struct FarCoef {
     R aK, aV, aT, aDY, rK, rV, rD, rT;
 };
 
-// One source triangle s against the six points of a target triangle: the
+// One source triangle against the six points of a target triangle: the
 // regular-rule sums of k_far (the caller has excluded pairs sharing a vertex).
+// st: the source's static record (entries 0..26 are read), sd: its dynamic
+// record (entries 0..14).
 template <typename R, int FORM>
-__device__ __forceinline__ void far_source(int s, const FarCoef<R> &cf, const R *__restrict__ stat,
-                                           const R *__restrict__ dyn, const R (&tx)[6], const R (&ty)[6],
+__device__ __forceinline__ void far_source(const FarCoef<R> &cf, const R *__restrict__ st,
+                                           const R *__restrict__ sd, const R (&tx)[6], const R (&ty)[6],
                                            const R (&tz)[6], const R (&xnt)[6], R ntx, R nty, R ntz, R (&a1)[6],
                                            R (&a2)[6], R &W0, R &W1, R &W2)
 {
-    const R *st = stat + (size_t)s * kStat;
-    const R *sd = dyn + (size_t)s * kDyn;
     const R nsx = st[18], nsy = st[19], nsz = st[20];
     R xns[6];
 #pragma unroll

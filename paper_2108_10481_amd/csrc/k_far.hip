@@ -112,7 +112,8 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
         const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
                          (j2 == v0) | (j2 == v1) | (j2 == v2);
         if (adj) continue;
-        far_source<R, FORM>(s, cf, stat, dyn, tx, ty, tz, xnt, ntx, nty, ntz, a1, a2, W0, W1, W2);
+        far_source<R, FORM>(cf, stat + (size_t)s * kStat, dyn + (size_t)s * kDyn, tx, ty, tz, xnt, ntx, nty, ntz,
+                            a1, a2, W0, W1, W2);
     }
     R *o = part + ((size_t)blockIdx.y * T + t) * 16;
 #pragma unroll

@@ -40,18 +40,27 @@ namespace pbm {
 
 constexpr int kTreeLeaf = 64;
 constexpr int kTreeBatch = 64;
+constexpr int kTreeBlock = 256;   // four independent wavefronts per block: one-wavefront
+                                  // blocks would cap residency at the workgroup slots
 constexpr int kProxRec = 12;   // proxy record: position 3, qK, qV, qC 3, qN 3, pad
 
+// a far cluster's points are split into work items of at most kUpTri
+// triangles for the upward pass (the largest clusters hold a good part of the
+// mesh), summed per cluster in a fixed order afterwards
+constexpr int kUpTri = 512;
+
 struct Tree {
-    int degree = 0, np = 0, nfar = 0, nbatch = 0, nsplit = 1;
+    int degree = 0, np = 0, nfar = 0, nbatch = 0, nsplit = 1, nitem = 0;
     double theta = 0.0;
     double evals = 0.0;                 // kernel evaluations per product (point pairs + point-proxy pairs)
     int32_t *node_range = nullptr;      // node -> first, end triangle
-    int32_t *far_node = nullptr;        // far cluster f -> node
     double *box = nullptr;              // far cluster f -> centre 3, half-width 3
     int32_t *piece_ptr = nullptr;       // (batch * nsplit + piece) -> first entry
     int32_t *entry = nullptr;           // f << 1 | 1 (proxies of far cluster f) or node << 1 (leaf, direct)
     void *prox = nullptr;               // nfar x np x kProxRec reals (FP64 or FP32 as the handle evaluates)
+    int32_t *item = nullptr;            // work item -> cluster f, first, end triangle
+    int32_t *item_ptr = nullptr;        // cluster f -> its first work item (nfar + 1)
+    double *upart = nullptr;            // nitem x np x 8 partial charges
 };
 
 int tree_splits(const Tree &t) { return t.nsplit; }
@@ -119,7 +128,9 @@ Tree *tree_create(DevMesh &d)
 
     // target batches and their interaction lists
     tr->nbatch = (T + kTreeBatch - 1) / kTreeBatch;
-    tr->nsplit = std::max(1, std::min(16, (4096 + tr->nbatch - 1) / tr->nbatch));
+    // many short pieces: every SIMD runs about 16 of them one after the other,
+    // so uneven lists even out
+    tr->nsplit = std::max(1, std::min(64, (16384 + tr->nbatch - 1) / tr->nbatch));
     std::vector<int32_t> far_of(nodes.size(), -1), far_node, piece_ptr(1, 0), entry;
     std::vector<int32_t> list;
     std::vector<double> cost;
@@ -186,6 +197,17 @@ Tree *tree_create(DevMesh &d)
             box[6 * (size_t)f + 3 + c] = std::max(0.5 * (nd.hi[c] - nd.lo[c]), 1e-3 * hmax);
         }
     }
+    std::vector<int32_t> item, item_ptr(1, 0);
+    for (int f = 0; f < tr->nfar; ++f) {
+        const Node &nd = nodes[far_node[f]];
+        for (int b = nd.b; b < nd.e; b += kUpTri) {
+            item.push_back(f);
+            item.push_back(b);
+            item.push_back(std::min(nd.e, b + kUpTri));
+        }
+        item_ptr.push_back((int32_t)(item.size() / 3));
+    }
+    tr->nitem = (int)(item.size() / 3);
     std::vector<int32_t> range(2 * nodes.size());
     for (size_t i = 0; i < nodes.size(); ++i) {
         range[2 * i] = nodes[i].b;
@@ -197,12 +219,14 @@ Tree *tree_create(DevMesh &d)
         return p;
     };
     tr->node_range = (int32_t *)up(range.data(), sizeof(int32_t) * range.size());
-    tr->far_node = (int32_t *)up(far_node.data(), sizeof(int32_t) * far_node.size());
     tr->box = (double *)up(box.data(), sizeof(double) * box.size());
     tr->piece_ptr = (int32_t *)up(piece_ptr.data(), sizeof(int32_t) * piece_ptr.size());
     tr->entry = (int32_t *)up(entry.data(), sizeof(int32_t) * entry.size());
     const size_t rsz = d.prm.precision == PB_FP64 ? sizeof(double) : sizeof(float);
     tr->prox = d.alloc(rsz * kProxRec * (size_t)tr->np * std::max(tr->nfar, 1));
+    tr->item = (int32_t *)up(item.data(), sizeof(int32_t) * item.size());
+    tr->item_ptr = (int32_t *)up(item_ptr.data(), sizeof(int32_t) * item_ptr.size());
+    tr->upart = (double *)d.alloc(sizeof(double) * 8 * (size_t)tr->np * std::max(tr->nitem, 1));
     HIPCHECK(hipStreamSynchronize(d.stream));   // host vectors go out of scope
     return tr.release();
 }
@@ -214,30 +238,31 @@ void tree_destroy(DevMesh &d)
 }
 
 // ------------------------------------------------------------ upward pass
-// One block per far cluster: 64 source points at a time are staged in LDS;
-// threads (point, dimension) form the 1-D barycentric basis values and
-// derivatives at the Chebyshev nodes, then each thread accumulates the
-// charges of its proxies.  FP64 throughout; stored as RP.
+// One block per work item (a far cluster's triangles [b, e)): 64 source
+// points at a time are staged in LDS; threads (point, dimension) form the 1-D
+// barycentric basis values and derivatives at the Chebyshev nodes, then each
+// thread accumulates the charges of its proxies.  FP64 throughout; the item's
+// partial charges are written to upart and summed per cluster by
+// k_tree_proxies.
 constexpr int kUpPts = 64;
 
-template <typename RP>
-__global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int32_t *__restrict__ far_node,
-                                                      const int32_t *__restrict__ node_range,
+__device__ inline double cheb_node(int m, int deg) { return cos(kPi * m / deg); }
+
+__global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int32_t *__restrict__ item,
                                                       const double *__restrict__ box,
                                                       const double *__restrict__ stat,
-                                                      const double *__restrict__ dyn, RP *__restrict__ prox,
+                                                      const double *__restrict__ dyn, double *__restrict__ upart,
                                                       DevCtl ctl)
 {
     __shared__ double tn[kTreeMaxDegree + 1], wb[kTreeMaxDegree + 1];
     __shared__ double pt[kUpPts][11];                            // t 3, b1, b2, w C 3, n 3
     __shared__ double la[kUpPts][3][kTreeMaxDegree + 1], lb[kUpPts][3][kTreeMaxDegree + 1];
     if (ctl_skip(ctl)) return;
-    const int f = blockIdx.x, tid = threadIdx.x, n1 = deg + 1;
-    const int node = far_node[f];
-    const int b = node_range[2 * node], e = node_range[2 * node + 1];
+    const int tid = threadIdx.x, n1 = deg + 1;
+    const int f = item[3 * blockIdx.x], b = item[3 * blockIdx.x + 1], e = item[3 * blockIdx.x + 2];
     const double *bx = box + 6 * (size_t)f;
     if (tid < n1) {
-        tn[tid] = cos(kPi * tid / deg);
+        tn[tid] = cheb_node(tid, deg);
         wb[tid] = ((tid & 1) ? -1.0 : 1.0) * ((tid == 0 || tid == deg) ? 0.5 : 1.0);
     }
     double acc[2][8];
@@ -325,22 +350,47 @@ __global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int
     for (int a = 0; a < 2; ++a) {
         const int k = tid + 256 * a;
         if (k >= np) break;
+        double *o = upart + ((size_t)blockIdx.x * np + k) * 8;
+        for (int c = 0; c < 8; ++c) o[c] = acc[a][c];
+    }
+}
+
+// proxy records of cluster f: positions and the sum of its items' charges
+template <typename RP>
+__global__ __launch_bounds__(256) void k_tree_proxies(int deg, int np, const int32_t *__restrict__ item_ptr,
+                                                      const double *__restrict__ box,
+                                                      const double *__restrict__ upart, RP *__restrict__ prox,
+                                                      DevCtl ctl)
+{
+    if (ctl_skip(ctl)) return;
+    const int f = blockIdx.x, n1 = deg + 1;
+    const double *bx = box + 6 * (size_t)f;
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int it = item_ptr[f]; it < item_ptr[f + 1]; ++it) {
+            const double *u = upart + ((size_t)it * np + k) * 8;
+            for (int c = 0; c < 8; ++c) q[c] += u[c];
+        }
         const int i = k / (n1 * n1), j = (k / n1) % n1, l = k % n1;
         RP *o = prox + ((size_t)f * np + k) * kProxRec;
-        o[0] = (RP)(bx[0] + bx[3] * tn[i]);
-        o[1] = (RP)(bx[1] + bx[4] * tn[j]);
-        o[2] = (RP)(bx[2] + bx[5] * tn[l]);
-        for (int c = 0; c < 8; ++c) o[3 + c] = (RP)acc[a][c];
+        o[0] = (RP)(bx[0] + bx[3] * cheb_node(i, deg));
+        o[1] = (RP)(bx[1] + bx[4] * cheb_node(j, deg));
+        o[2] = (RP)(bx[2] + bx[5] * cheb_node(l, deg));
+        for (int c = 0; c < 8; ++c) o[3 + c] = (RP)q[c];
         o[11] = (RP)0;
     }
 }
 
 // ------------------------------------------------------------- evaluation
-// One wavefront per (batch, piece): lanes own target triangles; list entries
+// One wavefront per (batch, piece), four per block: lanes own target triangles; list entries
 // are wavefront-uniform, so proxy records and source triangles come through
-// scalar loads.  Each entry is summed in R, the entries in FP64.
+// scalar loads.  Sums in R, as the direct kernel's chunks (a piece holds a
+// few thousand sources at most); pieces are added in FP64 by k_far_finish.
+// FP32: at most 85 VGPRs (6 wavefronts per SIMD) without spills, which hides
+// the per-source scalar loads of the direct sums (99 VGPRs, 4 wavefronts,
+// otherwise).
 template <typename R, int FORM>
-__global__ __launch_bounds__(kTreeBatch) void k_tree_eval(int T, int nsplit, int np, FarCoef<R> cf,
+__global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 1))) void k_tree_eval(int T, int nsplit, int nwork, int np, FarCoef<R> cf,
                                                           const int32_t *__restrict__ tri,
                                                           const R *__restrict__ stat, const R *__restrict__ dyn,
                                                           const int32_t *__restrict__ node_range,
@@ -350,7 +400,13 @@ __global__ __launch_bounds__(kTreeBatch) void k_tree_eval(int T, int nsplit, int
                                                           DevCtl ctl)
 {
     if (ctl_skip(ctl)) return;
-    const int t = blockIdx.x * kTreeBatch + threadIdx.x;
+    // four independent wavefronts per block, one (batch, piece) each
+    // wavefront-uniform (readfirstlane), so the list walk stays on scalar loads
+    const int wi = blockIdx.x * (kTreeBlock / kTreeBatch) +
+                   __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kTreeBatch));
+    if (wi >= nwork) return;
+    const int bt = wi / nsplit, piece = wi % nsplit;
+    const int t = bt * kTreeBatch + (int)(threadIdx.x % kTreeBatch);
     const int tc = t < T ? t : T - 1;   // lanes past the end compute, never store
     const R *ts = stat + (size_t)tc * kStat;
     R tx[6], ty[6], tz[6], xnt[6];
@@ -361,23 +417,20 @@ __global__ __launch_bounds__(kTreeBatch) void k_tree_eval(int T, int nsplit, int
     }
     const R ntx = ts[18], nty = ts[19], ntz = ts[20];
     const int v0 = tri[3 * tc], v1 = tri[3 * tc + 1], v2 = tri[3 * tc + 2];
-    double A1[6], A2[6], X0 = 0, X1 = 0, X2 = 0;
+    R a1[6], a2[6], W0 = 0, W1 = 0, W2 = 0;
 #pragma unroll
-    for (int p = 0; p < 6; ++p) { A1[p] = 0; A2[p] = 0; }
-    const int pc = blockIdx.x * nsplit + blockIdx.y;
-    for (int en = piece_ptr[pc]; en < piece_ptr[pc + 1]; ++en) {
+    for (int p = 0; p < 6; ++p) { a1[p] = 0; a2[p] = 0; }
+    for (int en = piece_ptr[wi]; en < piece_ptr[wi + 1]; ++en) {
         const int code = entry[en];
-        R a1[6], a2[6], W0 = 0, W1 = 0, W2 = 0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) { a1[p] = 0; a2[p] = 0; }
         if (code & 1) {
             const R *P = prox + (size_t)(code >> 1) * np * kProxRec;
-            for (int k = 0; k < np; ++k, P += kProxRec) {
-                const R sx = P[0], sy = P[1], sz = P[2];
-                const R qK = P[3], qV = P[4];
+            for (int k = 0; k < np; ++k) {
+                const R *cur = P + (size_t)k * kProxRec;
+                const R sx = cur[0], sy = cur[1], sz = cur[2];
+                const R qK = cur[3], qV = cur[4];
                 R gw = 0, ntqN = 0, snt = 0;
                 if (FORM >= 1) {
-                    ntqN = cf.aDY * cf.k2 * (ntx * P[8] + nty * P[9] + ntz * P[10]);
+                    ntqN = cf.aDY * cf.k2 * (ntx * cur[8] + nty * cur[9] + ntz * cur[10]);
                     snt = sx * ntx + sy * nty + sz * ntz;
                 }
 #pragma unroll
@@ -402,9 +455,9 @@ __global__ __launch_bounds__(kTreeBatch) void k_tree_eval(int T, int nsplit, int
                     }
                 }
                 if (FORM >= 1) {
-                    W0 += gw * P[5];
-                    W1 += gw * P[6];
-                    W2 += gw * P[7];
+                    W0 += gw * cur[5];
+                    W1 += gw * cur[6];
+                    W2 += gw * cur[7];
                 }
             }
         } else {
@@ -415,35 +468,35 @@ __global__ __launch_bounds__(kTreeBatch) void k_tree_eval(int T, int nsplit, int
                 const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
                                  (j2 == v0) | (j2 == v1) | (j2 == v2);
                 if (adj) continue;
-                far_source<R, FORM>(s, cf, stat, dyn, tx, ty, tz, xnt, ntx, nty, ntz, a1, a2, W0, W1, W2);
+                far_source<R, FORM>(cf, stat + (size_t)s * kStat, dyn + (size_t)s * kDyn, tx, ty, tz, xnt, ntx, nty,
+                                    ntz, a1, a2, W0, W1, W2);
             }
         }
-#pragma unroll
-        for (int p = 0; p < 6; ++p) { A1[p] += a1[p]; A2[p] += a2[p]; }
-        X0 += W0;
-        X1 += W1;
-        X2 += W2;
     }
     if (t >= T) return;
-    R *o = part + ((size_t)blockIdx.y * T + t) * 16;
+    R *o = part + ((size_t)piece * T + t) * 16;
 #pragma unroll
-    for (int p = 0; p < 6; ++p) { o[p] = (R)A1[p]; o[6 + p] = (R)A2[p]; }
-    o[12] = (R)X0; o[13] = (R)X1; o[14] = (R)X2; o[15] = 0;
+    for (int p = 0; p < 6; ++p) { o[p] = a1[p]; o[6 + p] = a2[p]; }
+    o[12] = W0; o[13] = W1; o[14] = W2; o[15] = 0;
 }
 
 template <typename R>
 static void tree_launch(DevMesh &d, const R *stat, const R *dyn)
 {
     Tree &tr = *d.tree;
-    if (tr.nfar > 0)
-        hipLaunchKernelGGL(k_tree_charges<R>, dim3(tr.nfar), dim3(256), 0, d.stream, tr.degree, tr.np, tr.far_node,
-                           tr.node_range, tr.box, d.stat64, d.dyn64, (R *)tr.prox, d.ctl);
+    if (tr.nfar > 0) {
+        hipLaunchKernelGGL(k_tree_charges, dim3(tr.nitem), dim3(256), 0, d.stream, tr.degree, tr.np, tr.item, tr.box,
+                           d.stat64, d.dyn64, tr.upart, d.ctl);
+        hipLaunchKernelGGL(k_tree_proxies<R>, dim3(tr.nfar), dim3(256), 0, d.stream, tr.degree, tr.np, tr.item_ptr,
+                           tr.box, tr.upart, (R *)tr.prox, d.ctl);
+    }
     FarCoef<R> cf;
     const int form = far_coef(d, cf);
-    const dim3 grid(tr.nbatch, tr.nsplit), block(kTreeBatch);
+    const int nwork = tr.nbatch * tr.nsplit, per = kTreeBlock / kTreeBatch;
+    const dim3 grid((nwork + per - 1) / per), block(kTreeBlock);
 #define TREE_EVAL(F)                                                                                              \
-    hipLaunchKernelGGL((k_tree_eval<R, F>), grid, block, 0, d.stream, d.hm.T, tr.nsplit, tr.np, cf, d.tri, stat,  \
-                       dyn, tr.node_range, tr.piece_ptr, tr.entry, (const R *)tr.prox, (R *)d.part, d.ctl)
+    hipLaunchKernelGGL((k_tree_eval<R, F>), grid, block, 0, d.stream, d.hm.T, tr.nsplit, nwork, tr.np, cf, d.tri, \
+                       stat, dyn, tr.node_range, tr.piece_ptr, tr.entry, (const R *)tr.prox, (R *)d.part, d.ctl)
     if (form == 0) TREE_EVAL(0);
     else if (form == 1) TREE_EVAL(1);
     else if (form == 2) TREE_EVAL(2);

@@ -390,7 +390,7 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     if (o->operator_mode == PB_TREECODE) {
         const double np = std::pow(o->tree_degree + 1.0, 3.0);
         b += t / 16.0 * np * 12 * 8 + 64.0 * t;   // proxies of about T/16 clusters, lists
-        b += 16.0 * 16 * t * 8;                    // up to 16 pieces of partial sums
+        b += 16.0 * std::min(64.0, std::ceil(16384.0 / std::ceil(t / 64.0))) * t * 8;   // pieces' partial sums
     }
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
     return (size_t)(b * 1.1);
@@ -861,8 +861,8 @@ void pb_default_options(pb_options *o)
     o->inner_tol = 1e-3;
     o->memory_budget = 0;
     o->use_graph = 1;
-    o->tree_degree = 5;
-    o->tree_theta = 0.5;
+    o->tree_degree = 6;
+    o->tree_theta = 0.7;
 }
 
 const char *pb_last_error(void) { return g_err.c_str(); }

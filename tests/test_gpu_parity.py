@@ -860,14 +860,15 @@ def test_treecode_converges_with_degree(sphere16, form):
     """5120-triangle sphere: the treecode's error against the exact product
     (the FP64 direct matrix-free product, itself equal to the oracle's to
     1e-12) falls geometrically with the interpolation degree, by at least 5x
-    per degree, and is below 1e-6 at the default degree 5 (theta 0.5)."""
+    per degree, and is below 1e-6 at degree 5 with theta 0.5."""
     m = sphere16
     x = np.random.default_rng(11).standard_normal(2 * m.n_vertices)
     with pbm.MeshHandle(m.xyz, m.tri, _opts(form)) as h:
         ref = pbm.pb_mesh_apply(h, x)
     errs = []
     for deg in (2, 3, 4, 5, 6, 7):
-        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, operator_mode=pbm.PB_TREECODE, tree_degree=deg)) as h:
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, operator_mode=pbm.PB_TREECODE, tree_degree=deg,
+                                                tree_theta=0.5)) as h:
             errs.append(_rel(pbm.pb_mesh_apply(h, x), ref))
     print(f"treecode form {form}: errors by degree 2..7 {['%.1e' % e for e in errs]}")
     assert all(errs[k + 1] < errs[k] / 5.0 for k in range(len(errs) - 1)), errs
@@ -875,7 +876,7 @@ def test_treecode_converges_with_degree(sphere16, form):
 
 
 def test_treecode_full_size_rows_and_solve(sphere32):
-    """20480-triangle sphere, FP32 treecode (degree 5, theta 0.5): sampled rows
+    """20480-triangle sphere, FP32 treecode (defaults: degree 6, theta 0.7): sampled rows
     of the Juffer and internal PMCHWT products against the oracle's rows; the
     Juffer solve (scaled mass) and the direct one reach the FP64 direct
     matrix-free Delta G within 1e-5 with the same iterations."""
@@ -890,7 +891,7 @@ def test_treecode_full_size_rows_and_solve(sphere32):
             y = pbm.pb_mesh_apply(h, x)
         got = np.concatenate([y[rows], y[nv + rows]])
         print(f"treecode full size form {form}: rows rel {_rel(got, np.concatenate([r1, r2])):.2e}")
-        assert _rel(got, np.concatenate([r1, r2])) < 2e-6
+        assert _rel(got, np.concatenate([r1, r2])) < 5e-6   # the defaults' error is about 1e-6 here
     for form, prec in ((pbm.PB_JUFFER, pbm.PB_SCALED_MASS), (pbm.PB_DIRECT_INT, pbm.PB_BLOCK_DIAG)):
         ref = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=prec))
         got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, pbm.PB_FP32, preconditioner=prec,
