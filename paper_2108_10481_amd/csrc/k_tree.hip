@@ -26,9 +26,10 @@
 //   qC = sum_y w_q C_s L_k(y)          (hypersingular curl part, 3 components)
 //   qN = sum_y b1 n_y L_k(y)           (its kappa^2 (n_x . n_y) term)
 // and a target point sees every kernel of the formulation evaluated at s_k.
-// Per batch the interaction list is split into `nsplit` pieces of about
-// equal work; each piece writes its own partial sums (the layout of k_far's
-// source chunks), which k_far_finish adds in FP64.
+// A batch's interaction list is split into up to `nsplit` pieces of about
+// equal work (pieces past a light batch's count stay empty and write zeros);
+// each piece writes its own partial sums (the layout of k_far's source
+// chunks), which k_far_finish adds in FP64.
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -42,6 +43,8 @@ constexpr int kTreeLeaf = 64;
 constexpr int kTreeBatch = 64;
 constexpr int kTreeBlock = 256;   // four independent wavefronts per block: one-wavefront
                                   // blocks would cap residency at the workgroup slots
+constexpr int kMaxPieces = 64;  // pieces of one batch at most
+constexpr int kStage = 32;     // near-leaf source records staged per wavefront at a time
 constexpr int kProxRec = 12;   // proxy record: position 3, qK, qV, qC 3, qN 3, pad
 
 // a far cluster's points are split into work items of at most kUpTri
@@ -56,6 +59,7 @@ struct Tree {
     int32_t *node_range = nullptr;      // node -> first, end triangle
     double *box = nullptr;              // far cluster f -> centre 3, half-width 3
     int32_t *piece_ptr = nullptr;       // (batch * nsplit + piece) -> first entry
+    int32_t *order = nullptr;           // dispatch order of the (batch, piece) work items, heaviest first
     int32_t *entry = nullptr;           // f << 1 | 1 (proxies of far cluster f) or node << 1 (leaf, direct)
     void *prox = nullptr;               // nfar x np x kProxRec reals (FP64 or FP32 as the handle evaluates)
     int32_t *item = nullptr;            // work item -> cluster f, first, end triangle
@@ -128,12 +132,8 @@ Tree *tree_create(DevMesh &d)
 
     // target batches and their interaction lists
     tr->nbatch = (T + kTreeBatch - 1) / kTreeBatch;
-    // many short pieces: every SIMD runs about 16 of them one after the other,
-    // so uneven lists even out
-    tr->nsplit = std::max(1, std::min(64, (16384 + tr->nbatch - 1) / tr->nbatch));
-    std::vector<int32_t> far_of(nodes.size(), -1), far_node, piece_ptr(1, 0), entry;
-    std::vector<int32_t> list;
-    std::vector<double> cost;
+    std::vector<int32_t> far_of(nodes.size(), -1), far_node, list, list_ptr(1, 0);
+    std::vector<double> cost, bcost(tr->nbatch);
     std::vector<int> stack;
     double evals = 0.0;
     for (int bt = 0; bt < tr->nbatch; ++bt) {
@@ -141,8 +141,7 @@ Tree *tree_create(DevMesh &d)
         Node bn{tb, te};
         tri_box(hm, tb, te, bn.lo, bn.hi);
         const double rb = bn.radius();
-        list.clear();
-        cost.clear();
+        double total = 0.0;
         stack.assign(1, 0);
         while (!stack.empty()) {
             const int i = stack.back();
@@ -164,24 +163,50 @@ Tree *tree_create(DevMesh &d)
             } else {
                 stack.push_back(nd.c1);
                 stack.push_back(nd.c0);
+                continue;
             }
+            total += cost.back();
         }
-        double total = 0.0;
-        for (double c : cost) total += c;
+        list_ptr.push_back((int32_t)list.size());
+        bcost[bt] = total;
         evals += 6.0 * (te - tb) * total;
-        // nsplit pieces of about total / nsplit work each, in list order
+    }
+    // Pieces of about equal work over the whole mesh (a batch's list is cut
+    // into a number of pieces proportional to its work; about 64 per SIMD in
+    // all), dispatched heaviest first so that no long piece starts last: with
+    // a fixed number of pieces per batch the uneven batches left most SIMDs
+    // idle while a few long wavefronts finished.
+    double sum = 0.0;
+    for (double c : bcost) sum += c;
+    const double target = std::max(sum / 65536.0, 1.0);
+    std::vector<int> npc(tr->nbatch);
+    tr->nsplit = 1;
+    for (int bt = 0; bt < tr->nbatch; ++bt) {
+        npc[bt] = std::max(1, std::min(kMaxPieces, (int)std::ceil(bcost[bt] / target)));
+        tr->nsplit = std::max(tr->nsplit, npc[bt]);
+    }
+    const int S = tr->nsplit;
+    std::vector<int32_t> piece_ptr(1, 0), entry;
+    std::vector<double> pcost((size_t)tr->nbatch * S, 0.0);
+    entry.reserve(list.size());
+    for (int bt = 0; bt < tr->nbatch; ++bt) {
         double acc = 0.0;
-        size_t k = 0;
-        for (int p = 0; p < tr->nsplit; ++p) {
-            const double stop = total * (p + 1) / tr->nsplit;
-            while (k < list.size() && (acc + 0.5 * cost[k] <= stop || p == tr->nsplit - 1)) {
+        int k = list_ptr[bt];
+        for (int p = 0; p < S; ++p) {
+            const double stop = bcost[bt] * (p + 1) / npc[bt];
+            const double before = acc;
+            while (k < list_ptr[bt + 1] && (acc + 0.5 * cost[k] <= stop || p == npc[bt] - 1)) {
                 entry.push_back(list[k]);
                 acc += cost[k];
                 ++k;
             }
             piece_ptr.push_back((int32_t)entry.size());
+            pcost[(size_t)bt * S + p] = acc - before;
         }
     }
+    std::vector<int32_t> order((size_t)tr->nbatch * S);
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return pcost[a] > pcost[b]; });
     tr->nfar = (int)far_node.size();
     tr->evals = evals;
 
@@ -221,6 +246,7 @@ Tree *tree_create(DevMesh &d)
     tr->node_range = (int32_t *)up(range.data(), sizeof(int32_t) * range.size());
     tr->box = (double *)up(box.data(), sizeof(double) * box.size());
     tr->piece_ptr = (int32_t *)up(piece_ptr.data(), sizeof(int32_t) * piece_ptr.size());
+    tr->order = (int32_t *)up(order.data(), sizeof(int32_t) * order.size());
     tr->entry = (int32_t *)up(entry.data(), sizeof(int32_t) * entry.size());
     const size_t rsz = d.prm.precision == PB_FP64 ? sizeof(double) : sizeof(float);
     tr->prox = d.alloc(rsz * kProxRec * (size_t)tr->np * std::max(tr->nfar, 1));
@@ -390,22 +416,27 @@ __global__ __launch_bounds__(256) void k_tree_proxies(int deg, int np, const int
 // the per-source scalar loads of the direct sums (99 VGPRs, 4 wavefronts,
 // otherwise).
 template <typename R, int FORM>
-__global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 6 : 1))) void k_tree_eval(int T, int nsplit, int nwork, int np, FarCoef<R> cf,
+__global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1))) void k_tree_eval(int T, int nsplit, int nwork, int np, FarCoef<R> cf,
                                                           const int32_t *__restrict__ tri,
                                                           const R *__restrict__ stat, const R *__restrict__ dyn,
                                                           const int32_t *__restrict__ node_range,
                                                           const int32_t *__restrict__ piece_ptr,
+                                                          const int32_t *__restrict__ order,
                                                           const int32_t *__restrict__ entry,
                                                           const R *__restrict__ prox, R *__restrict__ part,
                                                           DevCtl ctl)
 {
+    __shared__ R srec[kTreeBlock / kTreeBatch][kStage][42];
+    __shared__ int4 sid[kTreeBlock / kTreeBatch][kStage];
     if (ctl_skip(ctl)) return;
     // four independent wavefronts per block, one (batch, piece) each
     // wavefront-uniform (readfirstlane), so the list walk stays on scalar loads
     const int wi = blockIdx.x * (kTreeBlock / kTreeBatch) +
                    __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kTreeBatch));
     if (wi >= nwork) return;
-    const int bt = wi / nsplit, piece = wi % nsplit;
+    const int item = order[wi];
+    const int bt = item / nsplit, piece = item % nsplit;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kTreeBatch)), lane = threadIdx.x % kTreeBatch;
     const int t = bt * kTreeBatch + (int)(threadIdx.x % kTreeBatch);
     const int tc = t < T ? t : T - 1;   // lanes past the end compute, never store
     const R *ts = stat + (size_t)tc * kStat;
@@ -420,7 +451,7 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
     R a1[6], a2[6], W0 = 0, W1 = 0, W2 = 0;
 #pragma unroll
     for (int p = 0; p < 6; ++p) { a1[p] = 0; a2[p] = 0; }
-    for (int en = piece_ptr[wi]; en < piece_ptr[wi + 1]; ++en) {
+    for (int en = piece_ptr[item]; en < piece_ptr[item + 1]; ++en) {
         const int code = entry[en];
         if (code & 1) {
             const R *P = prox + (size_t)(code >> 1) * np * kProxRec;
@@ -463,13 +494,32 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
         } else {
             const int nd = code >> 1;
             const int sb = node_range[2 * nd], se = node_range[2 * nd + 1];
-            for (int s = sb; s < se; ++s) {
-                const int j0 = tri[3 * s], j1 = tri[3 * s + 1], j2 = tri[3 * s + 2];
-                const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
-                                 (j2 == v0) | (j2 == v1) | (j2 == v2);
-                if (adj) continue;
-                far_source<R, FORM>(cf, stat + (size_t)s * kStat, dyn + (size_t)s * kDyn, tx, ty, tz, xnt, ntx, nty,
-                                    ntz, a1, a2, W0, W1, W2);
+            // kStage source records at a time staged in the wavefront's own LDS
+            // slice (one lane per source, all loads in flight together), then read
+            // back as broadcasts: the leaves differ from wavefront to wavefront,
+            // so a scalar-load walk would wait on every source
+            for (int s0 = sb; s0 < se; s0 += kStage) {
+                const int ns = min(kStage, se - s0);
+                __builtin_amdgcn_wave_barrier();   // the previous records are consumed
+                if (lane < ns) {
+                    const R *st = stat + (size_t)(s0 + lane) * kStat, *sd = dyn + (size_t)(s0 + lane) * kDyn;
+#pragma unroll
+                    for (int c = 0; c < 27; ++c) srec[wv][lane][c] = st[c];
+#pragma unroll
+                    for (int c = 0; c < 15; ++c) srec[wv][lane][27 + c] = sd[c];
+                    sid[wv][lane] = make_int4(tri[3 * (s0 + lane)], tri[3 * (s0 + lane) + 1], tri[3 * (s0 + lane) + 2], 0);
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                for (int k = 0; k < ns; ++k) {
+                    const int4 j = sid[wv][k];
+                    const bool adj = (j.x == v0) | (j.x == v1) | (j.x == v2) | (j.y == v0) | (j.y == v1) |
+                                     (j.y == v2) | (j.z == v0) | (j.z == v1) | (j.z == v2);
+                    if (adj) continue;
+                    far_source<R, FORM>(cf, srec[wv][k], srec[wv][k] + 27, tx, ty, tz, xnt, ntx, nty, ntz, a1, a2, W0,
+                                        W1, W2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
         }
     }
@@ -496,7 +546,8 @@ static void tree_launch(DevMesh &d, const R *stat, const R *dyn)
     const dim3 grid((nwork + per - 1) / per), block(kTreeBlock);
 #define TREE_EVAL(F)                                                                                              \
     hipLaunchKernelGGL((k_tree_eval<R, F>), grid, block, 0, d.stream, d.hm.T, tr.nsplit, nwork, tr.np, cf, d.tri, \
-                       stat, dyn, tr.node_range, tr.piece_ptr, tr.entry, (const R *)tr.prox, (R *)d.part, d.ctl)
+                       stat, dyn, tr.node_range, tr.piece_ptr, tr.order, tr.entry, (const R *)tr.prox, (R *)d.part, \
+                       d.ctl)
     if (form == 0) TREE_EVAL(0);
     else if (form == 1) TREE_EVAL(1);
     else if (form == 2) TREE_EVAL(2);
