@@ -47,24 +47,22 @@ constexpr int kMaxPieces = 64;  // pieces of one batch at most
 constexpr int kStage = 32;     // near-leaf source records staged per wavefront at a time
 constexpr int kProxRec = 12;   // proxy record: position 3, qK, qV, qC 3, qN 3, pad
 
-// a far cluster's points are split into work items of at most kUpTri
-// triangles for the upward pass (the largest clusters hold a good part of the
-// mesh), summed per cluster in a fixed order afterwards
-constexpr int kUpTri = 512;
-
 struct Tree {
     int degree = 0, np = 0, nfar = 0, nbatch = 0, nsplit = 1, nitem = 0;
     double theta = 0.0;
     double evals = 0.0;                 // kernel evaluations per product (point pairs + point-proxy pairs)
     int32_t *node_range = nullptr;      // node -> first, end triangle
-    double *box = nullptr;              // far cluster f -> centre 3, half-width 3
+    double *box = nullptr;              // node -> centre 3, half-width 3 (interpolation box)
+    int32_t *far_node = nullptr;        // far cluster f -> node
+    int32_t *far_slot = nullptr;        // far cluster f -> charge slot
     int32_t *piece_ptr = nullptr;       // (batch * nsplit + piece) -> first entry
     int32_t *order = nullptr;           // dispatch order of the (batch, piece) work items, heaviest first
     int32_t *entry = nullptr;           // f << 1 | 1 (proxies of far cluster f) or node << 1 (leaf, direct)
     void *prox = nullptr;               // nfar x np x kProxRec reals (FP64 or FP32 as the handle evaluates)
-    int32_t *item = nullptr;            // work item -> cluster f, first, end triangle
-    int32_t *item_ptr = nullptr;        // cluster f -> its first work item (nfar + 1)
-    double *upart = nullptr;            // nitem x np x 8 partial charges
+    int32_t *item = nullptr;            // leaf with charges -> slot, node, first, end triangle
+    int32_t *m2m = nullptr;             // parent slot, node, child slots and nodes, deepest level first
+    std::vector<int32_t> level_ptr;     // m2m entries per level (host)
+    double *charges = nullptr;          // slot x np x 8 proxy charges (FP64)
 };
 
 int tree_splits(const Tree &t) { return t.nsplit; }
@@ -210,29 +208,58 @@ Tree *tree_create(DevMesh &d)
     tr->nfar = (int)far_node.size();
     tr->evals = evals;
 
-    // interpolation boxes: the cluster's vertex box, no dimension thinner
+    // interpolation boxes of every node: the vertex box, no dimension thinner
     // than 1e-3 of its widest (flat clusters)
-    std::vector<double> box(6 * (size_t)std::max(tr->nfar, 1), 0.0);
-    for (int f = 0; f < tr->nfar; ++f) {
-        const Node &nd = nodes[far_node[f]];
+    const size_t nn = nodes.size();
+    std::vector<double> box(6 * nn, 0.0);
+    for (size_t i = 0; i < nn; ++i) {
+        const Node &nd = nodes[i];
         double hmax = 0.0;
         for (int c = 0; c < 3; ++c) hmax = std::max(hmax, 0.5 * (nd.hi[c] - nd.lo[c]));
         for (int c = 0; c < 3; ++c) {
-            box[6 * (size_t)f + c] = nd.centre(c);
-            box[6 * (size_t)f + 3 + c] = std::max(0.5 * (nd.hi[c] - nd.lo[c]), 1e-3 * hmax);
+            box[6 * i + c] = nd.centre(c);
+            box[6 * i + 3 + c] = std::max(0.5 * (nd.hi[c] - nd.lo[c]), 1e-3 * hmax);
         }
     }
-    std::vector<int32_t> item, item_ptr(1, 0);
-    for (int f = 0; f < tr->nfar; ++f) {
-        const Node &nd = nodes[far_node[f]];
-        for (int b = nd.b; b < nd.e; b += kUpTri) {
-            item.push_back(f);
-            item.push_back(b);
-            item.push_back(std::min(nd.e, b + kUpTri));
+    // Upward pass: charges of every far cluster and of everything below it.
+    // Leaves from their points; a parent from its two children's proxies
+    // (k_tree_m2m): its tensor basis is a polynomial of the interpolation
+    // degree in each variable, which the children's interpolation reproduces
+    // exactly, so this equals the sum over the parent's points to rounding.
+    std::vector<char> need(nn, 0);
+    for (int32_t f : far_node) need[f] = 1;
+    std::vector<int> depth(nn, 0);
+    int maxdepth = 0;
+    for (size_t i = 0; i < nn; ++i)   // parents come before their children
+        if (nodes[i].c0 >= 0) {
+            depth[nodes[i].c0] = depth[nodes[i].c1] = depth[i] + 1;
+            maxdepth = std::max(maxdepth, depth[i] + 1);
+            if (need[i]) need[nodes[i].c0] = need[nodes[i].c1] = 1;
         }
-        item_ptr.push_back((int32_t)(item.size() / 3));
+    std::vector<int32_t> slot(nn, -1);
+    int nslot = 0;
+    for (size_t i = 0; i < nn; ++i)
+        if (need[i]) slot[i] = nslot++;
+    std::vector<int32_t> item;   // leaves: slot, node, first, end triangle
+    std::vector<std::vector<int32_t>> lev(maxdepth + 1);
+    for (size_t i = 0; i < nn; ++i) {
+        if (!need[i]) continue;
+        const Node &nd = nodes[i];
+        if (nd.c0 < 0) {
+            item.insert(item.end(), {slot[i], (int32_t)i, nd.b, nd.e});
+        } else {
+            lev[depth[i]].insert(lev[depth[i]].end(), {slot[i], (int32_t)i, slot[nd.c0], nd.c0, slot[nd.c1], nd.c1});
+        }
     }
-    tr->nitem = (int)(item.size() / 3);
+    tr->nitem = (int)(item.size() / 4);
+    std::vector<int32_t> m2m;   // deepest level first
+    tr->level_ptr.assign(1, 0);
+    for (int L = maxdepth; L >= 0; --L) {
+        m2m.insert(m2m.end(), lev[L].begin(), lev[L].end());
+        tr->level_ptr.push_back((int32_t)(m2m.size() / 6));
+    }
+    std::vector<int32_t> far_slot(tr->nfar);
+    for (int f = 0; f < tr->nfar; ++f) far_slot[f] = slot[far_node[f]];
     std::vector<int32_t> range(2 * nodes.size());
     for (size_t i = 0; i < nodes.size(); ++i) {
         range[2 * i] = nodes[i].b;
@@ -245,14 +272,16 @@ Tree *tree_create(DevMesh &d)
     };
     tr->node_range = (int32_t *)up(range.data(), sizeof(int32_t) * range.size());
     tr->box = (double *)up(box.data(), sizeof(double) * box.size());
+    tr->far_node = (int32_t *)up(far_node.data(), sizeof(int32_t) * far_node.size());
+    tr->far_slot = (int32_t *)up(far_slot.data(), sizeof(int32_t) * far_slot.size());
+    tr->m2m = (int32_t *)up(m2m.data(), sizeof(int32_t) * m2m.size());
     tr->piece_ptr = (int32_t *)up(piece_ptr.data(), sizeof(int32_t) * piece_ptr.size());
     tr->order = (int32_t *)up(order.data(), sizeof(int32_t) * order.size());
     tr->entry = (int32_t *)up(entry.data(), sizeof(int32_t) * entry.size());
     const size_t rsz = d.prm.precision == PB_FP64 ? sizeof(double) : sizeof(float);
     tr->prox = d.alloc(rsz * kProxRec * (size_t)tr->np * std::max(tr->nfar, 1));
     tr->item = (int32_t *)up(item.data(), sizeof(int32_t) * item.size());
-    tr->item_ptr = (int32_t *)up(item_ptr.data(), sizeof(int32_t) * item_ptr.size());
-    tr->upart = (double *)d.alloc(sizeof(double) * 8 * (size_t)tr->np * std::max(tr->nitem, 1));
+    tr->charges = (double *)d.alloc(sizeof(double) * 8 * (size_t)tr->np * std::max(nslot, 1));
     HIPCHECK(hipStreamSynchronize(d.stream));   // host vectors go out of scope
     return tr.release();
 }
@@ -264,20 +293,55 @@ void tree_destroy(DevMesh &d)
 }
 
 // ------------------------------------------------------------ upward pass
-// One block per work item (a far cluster's triangles [b, e)): 64 source
-// points at a time are staged in LDS; threads (point, dimension) form the 1-D
-// barycentric basis values and derivatives at the Chebyshev nodes, then each
-// thread accumulates the charges of its proxies.  FP64 throughout; the item's
-// partial charges are written to upart and summed per cluster by
-// k_tree_proxies.
+// Leaves (k_tree_charges, one block per leaf): 64 source points at a time are
+// staged in LDS; threads (point, dimension) form the 1-D barycentric basis
+// values and derivatives at the Chebyshev nodes, then each thread accumulates
+// the charges of its proxies.  Parents (k_tree_m2m, level by level from the
+// deepest): their children's charges carried by the parent's basis evaluated
+// at the children's proxies.  FP64 throughout.
 constexpr int kUpPts = 64;
 
 __device__ inline double cheb_node(int m, int deg) { return cos(kPi * m / deg); }
 
+// 1-D barycentric Lagrange basis at the deg+1 Chebyshev nodes tn (weights wb)
+// of normalised coordinate t: values L[m] and derivatives dL[m] (dL may be null)
+__device__ inline void bary_basis(int deg, double t, const double *tn, const double *wb, double *L, double *dL)
+{
+    const int n1 = deg + 1;
+    int hit = -1;
+    for (int m = 0; m < n1; ++m)
+        if (fabs(t - tn[m]) < 1e-13) hit = m;
+    if (hit < 0) {
+        double S = 0.0, S2 = 0.0;
+        for (int m = 0; m < n1; ++m) {
+            const double r = wb[m] / (t - tn[m]);
+            S += r;
+            S2 += r / (t - tn[m]);
+        }
+        for (int m = 0; m < n1; ++m) {
+            const double v = wb[m] / (t - tn[m]) / S;
+            L[m] = v;
+            if (dL) dL[m] = v * (S2 / S - 1.0 / (t - tn[m]));
+        }
+    } else {
+        // at a node: Kronecker values, the differentiation matrix row
+        double diag = 0.0;
+        for (int m = 0; m < n1; ++m) {
+            L[m] = m == hit ? 1.0 : 0.0;
+            if (dL && m != hit) {
+                const double v = (wb[m] / wb[hit]) / (tn[hit] - tn[m]);
+                dL[m] = v;
+                diag -= v;
+            }
+        }
+        if (dL) dL[hit] = diag;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int32_t *__restrict__ item,
                                                       const double *__restrict__ box,
                                                       const double *__restrict__ stat,
-                                                      const double *__restrict__ dyn, double *__restrict__ upart,
+                                                      const double *__restrict__ dyn, double *__restrict__ charges,
                                                       DevCtl ctl)
 {
     __shared__ double tn[kTreeMaxDegree + 1], wb[kTreeMaxDegree + 1];
@@ -285,8 +349,9 @@ __global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int
     __shared__ double la[kUpPts][3][kTreeMaxDegree + 1], lb[kUpPts][3][kTreeMaxDegree + 1];
     if (ctl_skip(ctl)) return;
     const int tid = threadIdx.x, n1 = deg + 1;
-    const int f = item[3 * blockIdx.x], b = item[3 * blockIdx.x + 1], e = item[3 * blockIdx.x + 2];
-    const double *bx = box + 6 * (size_t)f;
+    const int32_t *it = item + 4 * (size_t)blockIdx.x;
+    const int sl = it[0], b = it[2], e = it[3];
+    const double *bx = box + 6 * (size_t)it[1];
     if (tid < n1) {
         tn[tid] = cheb_node(tid, deg);
         wb[tid] = ((tid & 1) ? -1.0 : 1.0) * ((tid == 0 || tid == deg) ? 0.5 : 1.0);
@@ -318,35 +383,7 @@ __global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int
         __syncthreads();
         if (tid < 3 * kUpPts) {
             const int pp = tid / 3, dim = tid % 3;
-            const double t = pt[pp][dim];
-            int hit = -1;
-            for (int m = 0; m < n1; ++m)
-                if (fabs(t - tn[m]) < 1e-13) hit = m;
-            if (hit < 0) {
-                double S = 0.0, S2 = 0.0;
-                for (int m = 0; m < n1; ++m) {
-                    const double r = wb[m] / (t - tn[m]);
-                    S += r;
-                    S2 += r / (t - tn[m]);
-                }
-                for (int m = 0; m < n1; ++m) {
-                    const double L = wb[m] / (t - tn[m]) / S;
-                    la[pp][dim][m] = L;
-                    lb[pp][dim][m] = L * (S2 / S - 1.0 / (t - tn[m]));
-                }
-            } else {
-                // at a node: Kronecker values, the differentiation matrix row
-                double diag = 0.0;
-                for (int m = 0; m < n1; ++m) {
-                    la[pp][dim][m] = m == hit ? 1.0 : 0.0;
-                    if (m != hit) {
-                        const double v = (wb[m] / wb[hit]) / (tn[hit] - tn[m]);
-                        lb[pp][dim][m] = v;
-                        diag -= v;
-                    }
-                }
-                lb[pp][dim][hit] = diag;
-            }
+            bary_basis(deg, pt[pp][dim], tn, wb, la[pp][dim], lb[pp][dim]);
         }
         __syncthreads();
         const int cnt = min(kUpPts, npts - base);
@@ -376,27 +413,69 @@ __global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int
     for (int a = 0; a < 2; ++a) {
         const int k = tid + 256 * a;
         if (k >= np) break;
-        double *o = upart + ((size_t)blockIdx.x * np + k) * 8;
+        double *o = charges + ((size_t)sl * np + k) * 8;
         for (int c = 0; c < 8; ++c) o[c] = acc[a][c];
     }
 }
 
-// proxy records of cluster f: positions and the sum of its items' charges
+// One block per parent of one level: q_P[k] = sum over both children c and
+// their proxies k' of L^P_k(s^c_k') q_c[k'], the parent's tensor basis at the
+// child's proxy points taken dimension by dimension from LDS tables.
+__global__ __launch_bounds__(256) void k_tree_m2m(int deg, int np, const int32_t *__restrict__ m2m,
+                                                  const double *__restrict__ box, double *__restrict__ charges,
+                                                  DevCtl ctl)
+{
+    __shared__ double tn[kTreeMaxDegree + 1], wb[kTreeMaxDegree + 1];
+    __shared__ double tab[2][3][kTreeMaxDegree + 1][kTreeMaxDegree + 1];   // [child][dim][child node][parent basis]
+    if (ctl_skip(ctl)) return;
+    const int tid = threadIdx.x, n1 = deg + 1;
+    const int32_t *en = m2m + 6 * (size_t)blockIdx.x;
+    const int ps = en[0];
+    const double *pb = box + 6 * (size_t)en[1];
+    if (tid < n1) {
+        tn[tid] = cheb_node(tid, deg);
+        wb[tid] = ((tid & 1) ? -1.0 : 1.0) * ((tid == 0 || tid == deg) ? 0.5 : 1.0);
+    }
+    __syncthreads();
+    if (tid < 2 * 3 * n1) {
+        const int c = tid / (3 * n1), dim = (tid / n1) % 3, m = tid % n1;
+        const double *cb = box + 6 * (size_t)en[3 + 2 * c];
+        // the child's node m in dimension dim, in the parent's normalised coordinate
+        const double t = (cb[dim] + cb[3 + dim] * tn[m] - pb[dim]) / pb[3 + dim];
+        bary_basis(deg, t, tn, wb, tab[c][dim][m], nullptr);
+    }
+    __syncthreads();
+    for (int k = tid; k < np; k += blockDim.x) {
+        const int i = k / (n1 * n1), j = (k / n1) % n1, l = k % n1;
+        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < 2; ++c) {
+            const double *cq = charges + (size_t)en[2 + 2 * c] * np * 8;
+            for (int kc = 0; kc < np; ++kc) {
+                const int ic = kc / (n1 * n1), jc = (kc / n1) % n1, lc = kc % n1;
+                const double w = tab[c][0][ic][i] * tab[c][1][jc][j] * tab[c][2][lc][l];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) q[v] += w * cq[8 * (size_t)kc + v];
+            }
+        }
+        double *o = charges + ((size_t)ps * np + k) * 8;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) o[v] = q[v];
+    }
+}
+
+// proxy records of far cluster f: positions and charges, in the evaluation precision
 template <typename RP>
-__global__ __launch_bounds__(256) void k_tree_proxies(int deg, int np, const int32_t *__restrict__ item_ptr,
+__global__ __launch_bounds__(256) void k_tree_proxies(int deg, int np, const int32_t *__restrict__ far_node,
+                                                      const int32_t *__restrict__ far_slot,
                                                       const double *__restrict__ box,
-                                                      const double *__restrict__ upart, RP *__restrict__ prox,
+                                                      const double *__restrict__ charges, RP *__restrict__ prox,
                                                       DevCtl ctl)
 {
     if (ctl_skip(ctl)) return;
     const int f = blockIdx.x, n1 = deg + 1;
-    const double *bx = box + 6 * (size_t)f;
+    const double *bx = box + 6 * (size_t)far_node[f];
     for (int k = threadIdx.x; k < np; k += blockDim.x) {
-        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int it = item_ptr[f]; it < item_ptr[f + 1]; ++it) {
-            const double *u = upart + ((size_t)it * np + k) * 8;
-            for (int c = 0; c < 8; ++c) q[c] += u[c];
-        }
+        const double *q = charges + ((size_t)far_slot[f] * np + k) * 8;
         const int i = k / (n1 * n1), j = (k / n1) % n1, l = k % n1;
         RP *o = prox + ((size_t)f * np + k) * kProxRec;
         o[0] = (RP)(bx[0] + bx[3] * cheb_node(i, deg));
@@ -536,9 +615,15 @@ static void tree_launch(DevMesh &d, const R *stat, const R *dyn)
     Tree &tr = *d.tree;
     if (tr.nfar > 0) {
         hipLaunchKernelGGL(k_tree_charges, dim3(tr.nitem), dim3(256), 0, d.stream, tr.degree, tr.np, tr.item, tr.box,
-                           d.stat64, d.dyn64, tr.upart, d.ctl);
-        hipLaunchKernelGGL(k_tree_proxies<R>, dim3(tr.nfar), dim3(256), 0, d.stream, tr.degree, tr.np, tr.item_ptr,
-                           tr.box, tr.upart, (R *)tr.prox, d.ctl);
+                           d.stat64, d.dyn64, tr.charges, d.ctl);
+        for (size_t L = 0; L + 1 < tr.level_ptr.size(); ++L) {
+            const int n = tr.level_ptr[L + 1] - tr.level_ptr[L];
+            if (n > 0)
+                hipLaunchKernelGGL(k_tree_m2m, dim3(n), dim3(256), 0, d.stream, tr.degree, tr.np,
+                                   tr.m2m + 6 * (size_t)tr.level_ptr[L], tr.box, tr.charges, d.ctl);
+        }
+        hipLaunchKernelGGL(k_tree_proxies<R>, dim3(tr.nfar), dim3(256), 0, d.stream, tr.degree, tr.np, tr.far_node,
+                           tr.far_slot, tr.box, tr.charges, (R *)tr.prox, d.ctl);
     }
     FarCoef<R> cf;
     const int form = far_coef(d, cf);

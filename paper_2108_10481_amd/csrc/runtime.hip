@@ -389,7 +389,7 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     if (cal && o->calderon_fast) b += 16.0 * t * (38 * 8) + t * 8;   // P's pair blocks and sums, centroid weights
     if (o->operator_mode == PB_TREECODE) {
         const double np = std::pow(o->tree_degree + 1.0, 3.0);
-        b += t / 16.0 * np * 12 * 8 + 64.0 * t;   // proxies of about T/16 clusters, lists
+        b += t / 16.0 * np * (12 * 8 + 8 * 8) + 64.0 * t;   // proxies and charges of about T/16 nodes, lists
         b += 16.0 * std::min(64.0, 4.0 * std::ceil(65536.0 / std::ceil(t / 64.0))) * t * 8;   // pieces' partial sums
     }
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
