@@ -419,16 +419,20 @@ __global__ __launch_bounds__(256) void k_tree_charges(int deg, int np, const int
 }
 
 // One block per parent of one level: q_P[k] = sum over both children c and
-// their proxies k' of L^P_k(s^c_k') q_c[k'], the parent's tensor basis at the
-// child's proxy points taken dimension by dimension from LDS tables.
+// their proxies k' of L^P_k(s^c_k') q_c[k'].  The parent's tensor basis at the
+// child's tensor grid factorises, so the sum is applied one dimension at a
+// time (z, then y, then x) through LDS: 3 (deg+1) instead of (deg+1)^3
+// products per proxy and charge.
 __global__ __launch_bounds__(256) void k_tree_m2m(int deg, int np, const int32_t *__restrict__ m2m,
                                                   const double *__restrict__ box, double *__restrict__ charges,
                                                   DevCtl ctl)
 {
+    constexpr int kMaxNp = (kTreeMaxDegree + 1) * (kTreeMaxDegree + 1) * (kTreeMaxDegree + 1);
     __shared__ double tn[kTreeMaxDegree + 1], wb[kTreeMaxDegree + 1];
     __shared__ double tab[2][3][kTreeMaxDegree + 1][kTreeMaxDegree + 1];   // [child][dim][child node][parent basis]
+    __shared__ double buf[2][kMaxNp][8];
     if (ctl_skip(ctl)) return;
-    const int tid = threadIdx.x, n1 = deg + 1;
+    const int tid = threadIdx.x, n1 = deg + 1, n2 = n1 * n1;
     const int32_t *en = m2m + 6 * (size_t)blockIdx.x;
     const int ps = en[0];
     const double *pb = box + 6 * (size_t)en[1];
@@ -444,22 +448,62 @@ __global__ __launch_bounds__(256) void k_tree_m2m(int deg, int np, const int32_t
         const double t = (cb[dim] + cb[3 + dim] * tn[m] - pb[dim]) / pb[3 + dim];
         bary_basis(deg, t, tn, wb, tab[c][dim][m], nullptr);
     }
-    __syncthreads();
-    for (int k = tid; k < np; k += blockDim.x) {
-        const int i = k / (n1 * n1), j = (k / n1) % n1, l = k % n1;
-        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        for (int c = 0; c < 2; ++c) {
-            const double *cq = charges + (size_t)en[2 + 2 * c] * np * 8;
-            for (int kc = 0; kc < np; ++kc) {
-                const int ic = kc / (n1 * n1), jc = (kc / n1) % n1, lc = kc % n1;
-                const double w = tab[c][0][ic][i] * tab[c][1][jc][j] * tab[c][2][lc][l];
+    double acc[2][8];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) q[v] += w * cq[8 * (size_t)kc + v];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[a][v] = 0.0;
+    for (int c = 0; c < 2; ++c) {
+        const double *cq = charges + (size_t)en[2 + 2 * c] * np * 8;
+        __syncthreads();   // tables ready; the previous child's buffers consumed
+        for (int e = tid; e < np * 8; e += blockDim.x) buf[0][e / 8][e % 8] = cq[e];
+        __syncthreads();
+        // z: buf1[i', j', l] = sum_l' T_z[l'][l] buf0[i', j', l']
+        for (int k = tid; k < np; k += blockDim.x) {
+            const int l = k % n1, base = k - l;
+            double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int lc = 0; lc < n1; ++lc) {
+                const double w = tab[c][2][lc][l];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) q[v] += w * buf[0][base + lc][v];
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) buf[1][k][v] = q[v];
+        }
+        __syncthreads();
+        // y: buf0[i', j, l] = sum_j' T_y[j'][j] buf1[i', j', l]
+        for (int k = tid; k < np; k += blockDim.x) {
+            const int j = (k / n1) % n1, base = k - j * n1;
+            double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int jc = 0; jc < n1; ++jc) {
+                const double w = tab[c][1][jc][j];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) q[v] += w * buf[1][base + jc * n1][v];
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) buf[0][k][v] = q[v];
+        }
+        __syncthreads();
+        // x: q_P[i, j, l] += sum_i' T_x[i'][i] buf0[i', j, l]
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int k = tid + 256 * a;
+            if (k >= np) break;
+            const int i = k / n2, base = k - i * n2;
+            for (int ic = 0; ic < n1; ++ic) {
+                const double w = tab[c][0][ic][i];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) acc[a][v] += w * buf[0][base + ic * n2][v];
             }
         }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int k = tid + 256 * a;
+        if (k >= np) break;
         double *o = charges + ((size_t)ps * np + k) * 8;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) o[v] = q[v];
+        for (int v = 0; v < 8; ++v) o[v] = acc[a][v];
     }
 }
 
