@@ -107,8 +107,10 @@ template <typename R> struct alignas(4 * sizeof(R)) Quad {
 //   block, not per point pair.
 // Phase 2: lane v sums, for one vertex touched by the tile, the block columns
 //   of its incident tile triangles, and adds the 3 x 4 values to rows t_0..t_2.
-//   The lane's matrix entries are read before phase 1, so the read-modify-write
-//   does not wait on memory at the end.
+//   SYM reads the lane's matrix entries at the start of phase 2, where the
+//   LDS sums cover part of their latency: held through phase 1, those 18
+//   registers made the compiler spill.  The FP64 kernel, with fewer values
+//   per pair, reads them before phase 1.
 // SYM (one evaluation per unordered pair): only pairs with s > t are
 // evaluated.  The symmetric values (V-type, and D in the Juffer system) are
 // added in the (t, s) orientation only; the two non-symmetric ones (K-type,
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                 }
             }
         };
-        load_old(c0);
+        if constexpr (!SYM) load_old(c0);
 
         const R ntx = ts[18], nty = ts[19], ntz = ts[20];
         const R rho = (R)RuleOrbit::rho, al = (R)RuleOrbit::al, be = (R)RuleOrbit::be;
@@ -332,8 +334,9 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                 c = (size_t)tv_col[e];
                 fb = tv_eptr[e];
                 fe = tv_eptr[e + 1];
-                load_old(c);
+                if constexpr (!SYM) load_old(c);
             }
+            if constexpr (SYM) load_old(c);
             R acc[3][NV];
 #pragma unroll
             for (int k = 0; k < 3; ++k)
