@@ -216,6 +216,30 @@ pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result 
  * right-hand sides are advanced together and every operator application is
  * one batched dense product (MFMA for 16-bit storage).  out[k] follows the
  * pb_result contract for set k.  PB_E_STATE for the Calderon preconditioners. */
+/* Solve one charge set on each of n resident meshes of any, unequal, sizes
+ * (1 <= n <= PB_MAX_BATCH_REQUESTS, distinct handles): their GMRES runs in
+ * lockstep and every iteration computes the far fields of all requests still
+ * iterating in one persistent kernel launch per kernel form, over a work queue
+ * of (request, 64 target triangles, source chunk) items, heaviest first
+ * (Numerical discretization: regular quadrature of the far pairs; the same
+ * operators and GMRES as pb_mesh_solve).  Every request's arithmetic equals
+ * that of pb_mesh_solve on its handle, so results[r] equals that solve's
+ * result bit for bit, timings aside: t_rhs, t_prec are the request's own,
+ * t_gmres the whole batch's.  charges[r] and results[r] belong to handles[r]
+ * and follow the pb_mesh_solve contract; the call returns PB_NOT_CONVERGED if
+ * any request did not converge (all results filled).  The handles must share
+ * the precision (PB_FP64 or PB_FP32) and be matrix-free (operator mode
+ * PB_MATRIX_FREE, or PB_AUTO resolved to it; no treecode), with any
+ * formulation and the block-diagonal or mass preconditioners; otherwise
+ * PB_E_STATE.  All work runs on handles[0]'s stream; each handle's stream is
+ * drained first.  Not thread-safe against other calls on the same handles.
+ * With pb_mesh_profile bit 0 on handles[0], its operator profile records the
+ * fused launches (work = kernel pairs of the requests in each launch) and
+ * nothing else of the call. */
+#define PB_MAX_BATCH_REQUESTS 1024
+pb_status pb_solve_batch(int32_t n, pb_mesh_handle *const *handles, const pb_charges *charges,
+                         pb_result *results);
+
 pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *sets,
                          pb_result *out);
 

@@ -54,6 +54,7 @@ PB_TREECODE = 3
 PB_APPLY_PRECOND = 1
 PB_APPLY_FAR_ONLY = 2
 PB_APPLY_NEAR_ONLY = 4
+PB_MAX_BATCH_REQUESTS = 1024
 
 
 class PbError(RuntimeError):
@@ -109,7 +110,7 @@ class pb_mesh_info(ctypes.Structure):
 
 
 EXPORTS = ["pb_default_options", "pb_last_error", "pb_device_count", "pb_solve", "pb_mesh_create",
-           "pb_mesh_destroy", "pb_mesh_get_info", "pb_mesh_refresh", "pb_mesh_solve", "pb_solve_multi", "pb_mesh_apply",
+           "pb_mesh_destroy", "pb_mesh_get_info", "pb_mesh_refresh", "pb_mesh_solve", "pb_solve_multi", "pb_solve_batch", "pb_mesh_apply",
            "pb_mesh_apply_device", "pb_mesh_rhs", "pb_mesh_reaction_potential", "pb_mesh_near_blocks",
            "pb_mesh_preconditioner", "pb_mesh_profile", "pb_mesh_profile_read", "pb_mesh_synchronize",
            "pb_estimate_device_bytes", "pb_server_create", "pb_server_destroy", "pb_submit", "pb_poll", "pb_cancel",
@@ -139,6 +140,7 @@ def load():
     L.pb_mesh_refresh.argtypes = [vp]
     L.pb_mesh_solve.argtypes = [vp, P(pb_charges), P(pb_result)]
     L.pb_solve_multi.argtypes = [vp, ctypes.c_int32, P(pb_charges), P(pb_result)]
+    L.pb_solve_batch.argtypes = [ctypes.c_int32, P(vp), P(pb_charges), P(pb_result)]
     L.pb_mesh_apply.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int32]
     L.pb_mesh_apply_device.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
     L.pb_mesh_rhs.argtypes = [vp, P(pb_charges), P(ctypes.c_double)]
@@ -319,6 +321,31 @@ def pb_solve_multi(h: MeshHandle, sets) -> list:
         rs[k] = r
         outs.append((phi, dphi))
     st = _check(load().pb_solve_multi(h.h, n, cs, rs))
+    return [_result_dict(st, rs[k], outs[k][0], outs[k][1]) for k in range(n)]
+
+
+def pb_solve_batch(handles, sets) -> list:
+    """handles: list of matrix-free MeshHandle (distinct, one precision);
+    sets: one (qxyz, q) per handle.  The far-field products of all requests run
+    fused (one persistent launch per kernel form and GMRES iteration).
+    Returns one result dict per request."""
+    n = len(handles)
+    if len(sets) != n:
+        raise ValueError("one charge set per handle")
+    hs = (ctypes.c_void_p * max(n, 1))(*[h.h for h in handles])
+    cs = (pb_charges * max(n, 1))()
+    keep = []
+    for k, (qx, qq) in enumerate(sets):
+        c, kp = _charges_struct(qx, qq)
+        cs[k] = c
+        keep.append(kp)
+    rs = (pb_result * max(n, 1))()
+    outs = []
+    for k in range(n):
+        r, phi, dphi = _result(handles[k].nv)
+        rs[k] = r
+        outs.append((phi, dphi))
+    st = _check(load().pb_solve_batch(n, hs, cs, rs))
     return [_result_dict(st, rs[k], outs[k][0], outs[k][1]) for k in range(n)]
 
 

@@ -35,13 +35,27 @@ struct FarCoef {
     R aK, aV, aT, aDY, rK, rV, rD, rT;
 };
 
+// one request of the batched far field: its mesh data, partial-sum buffer and
+// coefficients
+template <typename R>
+struct FarReq {
+    const int32_t *tri;
+    const R *stat;
+    const R *dyn;
+    R *part;
+    FarCoef<R> cf;
+    int T, chunk;
+};
+
 // One source triangle against the six points of a target triangle: the
 // regular-rule sums of k_far (the caller has excluded pairs sharing a vertex).
 // st: the source's static record (entries 0..26 are read), sd: its dynamic
 // record (entries 0..14).
-template <typename R, int FORM>
-__device__ __forceinline__ void far_source(const FarCoef<R> &cf, const R *__restrict__ st,
-                                           const R *__restrict__ sd, const R (&tx)[6], const R (&ty)[6],
+// SP: pointer type of the source records (a generic pointer, or one into the
+// constant address space where the caller needs scalar loads)
+template <typename R, int FORM, typename SP = const R *>
+__device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__ st,
+                                           SP __restrict__ sd, const R (&tx)[6], const R (&ty)[6],
                                            const R (&tz)[6], const R (&xnt)[6], R ntx, R nty, R ntz, R (&a1)[6],
                                            R (&a2)[6], R &W0, R &W1, R &W2)
 {

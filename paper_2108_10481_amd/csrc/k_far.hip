@@ -15,6 +15,8 @@
 //                   triangle -> 3 values per block row.
 //   k_gather      : per vertex, fixed-order sum of triangle contributions,
 //                   near-field CSR product, optional 2x2 preconditioner.
+#include <algorithm>
+
 #include "far.h"
 
 namespace pbm {
@@ -84,16 +86,14 @@ constexpr int kFarBlock = 256;
 //   preconditioner's operator): the FORM 1 sums with F_L, G_L dropped and the
 //   factors aK, aV, aT, aD taken from aY.
 // with d = x_p - y_q, G = e/r, F = e (1 + kappa r)/r^3 (e = 1 for Laplace).
-template <typename R, int FORM>
-__global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> cf, const int32_t *__restrict__ tri,
-                                                    const R *__restrict__ stat, const R *__restrict__ dyn,
-                                                    R *__restrict__ part, DevCtl ctl)
+// The sums of target triangle t over the sources s0..s1-1 (pairs sharing a
+// vertex skipped) into o[0..15]: one lane's work, shared by k_far and the
+// batched k_far_batch so that both round identically.
+template <typename R, int FORM, typename IP, typename SP, typename OP>
+__device__ __forceinline__ void far_lane(const FarCoef<R> &cf, IP __restrict__ tri, SP __restrict__ stat,
+                                         SP __restrict__ dyn, int t, int s0, int s1, OP __restrict__ o)
 {
-    const int t = blockIdx.x * kFarBlock + threadIdx.x;
-    const int s0 = blockIdx.y * chunk;
-    const int s1 = min(T, s0 + chunk);
-    if (t >= T || ctl_skip(ctl)) return;
-    const R *ts = stat + (size_t)t * kStat;
+    const SP ts = stat + (size_t)t * kStat;
     R tx[6], ty[6], tz[6];
 #pragma unroll
     for (int p = 0; p < 6; ++p) { tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2]; }
@@ -115,11 +115,58 @@ __global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> 
         far_source<R, FORM>(cf, stat + (size_t)s * kStat, dyn + (size_t)s * kDyn, tx, ty, tz, xnt, ntx, nty, ntz,
                             a1, a2, W0, W1, W2);
     }
-    R *o = part + ((size_t)blockIdx.y * T + t) * 16;
 #pragma unroll
     for (int p = 0; p < 6; ++p) { o[p] = a1[p]; o[6 + p] = a2[p]; }
     o[12] = W0; o[13] = W1; o[14] = W2; o[15] = 0;
 }
+
+template <typename R, int FORM>
+__global__ __launch_bounds__(kFarBlock) void k_far(int T, int chunk, FarCoef<R> cf, const int32_t *__restrict__ tri,
+                                                    const R *__restrict__ stat, const R *__restrict__ dyn,
+                                                    R *__restrict__ part, DevCtl ctl)
+{
+    const int t = blockIdx.x * kFarBlock + threadIdx.x;
+    const int s0 = blockIdx.y * chunk;
+    const int s1 = min(T, s0 + chunk);
+    if (t >= T || ctl_skip(ctl)) return;
+    far_lane<R, FORM>(cf, tri, stat, dyn, t, s0, s1, part + ((size_t)blockIdx.y * T + t) * 16);
+}
+
+// Persistent far field over several meshes at once (requests of uneven
+// size): a work queue of items {request, first target of a wavefront, source
+// chunk}, heaviest first.  Each wavefront takes the next item from a device
+// counter until the queue is empty (every wavefront reaches that exit), and
+// computes its 64 targets over the chunk exactly as k_far does, into the
+// request's own partial-sum buffer in k_far's layout.
+template <typename R, int FORM>
+__global__ __launch_bounds__(kFarBlock) void k_far_batch(const FarReq<R> *__restrict__ reqs,
+                                                          const int4 *__restrict__ items, int nitems,
+                                                          int *__restrict__ next)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int i = 0;
+        if (lane == 0) i = atomicAdd(next, 1);
+        i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
+        if (i >= nitems) return;
+        const int4 it = items[i];
+        const FarReq<R> rq = reqs[it.x];
+        const int t = it.y + lane;
+        const int s0 = it.z * rq.chunk;
+        const int s1 = min(rq.T, s0 + rq.chunk);
+        // the mesh data are not written during the launch: read through the
+        // constant address space so that wavefront-uniform records come
+        // through scalar loads (as in k_far) although the loop stores results
+        using CI = const __attribute__((address_space(4))) int32_t *;
+        using CR = const __attribute__((address_space(4))) R *;
+        using GR = __attribute__((address_space(1))) R *;
+        if (t < rq.T)
+            far_lane<R, FORM>(rq.cf, (CI)rq.tri, (CR)rq.stat, (CR)rq.dyn, t, s0, s1,
+                              (GR)(rq.part + ((size_t)it.z * rq.T + t) * 16));
+    }
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
 
 // One-point (centroid) rule on every triangle pair sharing no vertex, FP32:
 // the relaxed far field of fast Calderon's preconditioner.  Same sums as
@@ -352,6 +399,104 @@ void launch_far(DevMesh &d, bool fp32)
         const double P = 6.0 * d.hm.T;
         pf.record(0, e0, e1, P * P);   // kernel pairs, near-masked pairs included
     }
+}
+
+// One queue per kernel form over the requests in `live` (indices into ds);
+// items of a request follow its own source split (d.S chunks), so
+// k_far_finish applies unchanged.
+template <typename R>
+static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, FarBatch &fb)
+{
+    for (int f = 0; f < 4; ++f) fb.nitems[f] = 0;
+    std::vector<FarReq<R>> reqs(ds.size());
+    std::vector<std::vector<std::pair<int, int4>>> q(4);   // (cost, item) per form
+    for (int r : live) {
+        DevMesh &d = *ds[r];
+        FarReq<R> &rq = reqs[r];
+        const int form = far_coef(d, rq.cf);
+        const int T = d.hm.T, S = d.S, chunk = (T + S - 1) / S;
+        rq.tri = d.tri;
+        rq.stat = sizeof(R) == 4 ? (const R *)d.stat32 : (const R *)d.stat64;
+        rq.dyn = sizeof(R) == 4 ? (const R *)d.dyn32 : (const R *)d.dyn64;
+        rq.part = (R *)d.part;
+        rq.T = T;
+        rq.chunk = chunk;
+        // every chunk, empty ones too: k_far_finish sums all S of them
+        for (int c = 0; c < S; ++c) {
+            const int len = std::max(0, std::min(T, (c + 1) * chunk) - c * chunk);
+            for (int t0 = 0; t0 < T; t0 += 64) q[form].push_back({len, make_int4(r, t0, c, 0)});
+        }
+    }
+    std::vector<int4> items;
+    for (int f = 0; f < 4; ++f) {
+        std::stable_sort(q[f].begin(), q[f].end(),
+                         [](const std::pair<int, int4> &a, const std::pair<int, int4> &b) { return a.first > b.first; });
+        fb.first[f] = (int)items.size();
+        for (auto &e : q[f]) items.push_back(e.second);
+        fb.nitems[f] = (int)q[f].size();
+    }
+    const size_t rb = sizeof(FarReq<R>) * reqs.size(), ib = sizeof(int4) * std::max<size_t>(items.size(), 1);
+    if (rb > fb.req_cap) {
+        if (fb.reqs) HIPCHECK(hipFree(fb.reqs));
+        HIPCHECK(hipMalloc(&fb.reqs, rb));
+        fb.req_cap = rb;
+    }
+    if (ib > fb.item_cap) {
+        if (fb.items) HIPCHECK(hipFree(fb.items));
+        HIPCHECK(hipMalloc(&fb.items, ib));
+        fb.item_cap = ib;
+    }
+    if (!fb.next) HIPCHECK(hipMalloc(&fb.next, 4 * sizeof(int)));
+    HIPCHECK(hipMemcpyAsync(fb.reqs, reqs.data(), rb, hipMemcpyHostToDevice, fb.stream));
+    if (!items.empty())
+        HIPCHECK(hipMemcpyAsync(fb.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice,
+                                fb.stream));
+    HIPCHECK(hipStreamSynchronize(fb.stream));   // host vectors go out of scope
+}
+
+template <typename R, int FORM>
+static void batch_launch(FarBatch &fb)
+{
+    const int n = fb.nitems[FORM];
+    if (n == 0) return;
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_far_batch<R, FORM>), kFarBlock, 0));
+    const int waves = kFarBlock / 64;
+    const long long nb = std::max(1LL, std::min((long long)(n + waves - 1) / waves,
+                                                (long long)std::max(ncu, 1) * std::max(per_cu, 1)));
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, fb.stream, fb.next + FORM, 0);
+    hipLaunchKernelGGL((k_far_batch<R, FORM>), dim3((unsigned)nb), dim3(kFarBlock), 0, fb.stream,
+                       (const FarReq<R> *)fb.reqs, (const int4 *)fb.items + fb.first[FORM], n, fb.next + FORM);
+    HIPCHECK(hipGetLastError());
+}
+
+void far_batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, bool fp32, FarBatch &fb)
+{
+    if (fp32) batch_plan<float>(ds, live, fb);
+    else batch_plan<double>(ds, live, fb);
+}
+
+void launch_far_batch(FarBatch &fb, bool fp32)
+{
+    if (fp32) {
+        batch_launch<float, 0>(fb); batch_launch<float, 1>(fb); batch_launch<float, 2>(fb); batch_launch<float, 3>(fb);
+    } else {
+        batch_launch<double, 0>(fb); batch_launch<double, 1>(fb); batch_launch<double, 2>(fb); batch_launch<double, 3>(fb);
+    }
+}
+
+void far_batch_free(FarBatch &fb)
+{
+    if (fb.reqs) (void)hipFree(fb.reqs);
+    if (fb.items) (void)hipFree(fb.items);
+    if (fb.next) (void)hipFree(fb.next);
+    fb.reqs = nullptr;
+    fb.items = nullptr;
+    fb.next = nullptr;
+    fb.req_cap = fb.item_cap = 0;
 }
 
 void launch_far_centroid(DevMesh &d)

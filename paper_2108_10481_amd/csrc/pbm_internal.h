@@ -277,6 +277,21 @@ void launch_far_centroid(DevMesh &d);
 void launch_source_prep(DevMesh &d, const double *x, bool fp32);
 void launch_far(DevMesh &d, bool fp32);
 void launch_far_finish(DevMesh &d, bool fp32);
+// batched far field of several matrix-free handles (requests of uneven size):
+// the work-queue plan of the requests still iterating, then one persistent
+// launch per kernel form; each request's sources must be prepared first
+// (launch_source_prep) and its k_far_finish follows as usual
+struct FarBatch {
+    hipStream_t stream = nullptr;
+    void *reqs = nullptr;
+    void *items = nullptr;
+    int *next = nullptr;           // one queue counter per kernel form
+    size_t req_cap = 0, item_cap = 0;
+    int first[4] = {0, 0, 0, 0}, nitems[4] = {0, 0, 0, 0};
+};
+void far_batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, bool fp32, FarBatch &fb);
+void launch_far_batch(FarBatch &fb, bool fp32);
+void far_batch_free(FarBatch &fb);
 // use_far: 0 = near only, 1 = far from per-triangle outputs, 2 = far from d.yfar
 // y_offset false: y is a plain vector even inside a captured iteration
 void launch_gather(DevMesh &d, const double *x, double *y, int flags, int use_far, bool y_offset);

@@ -445,13 +445,9 @@ void calderon_left(DevMesh &d, const double *in, double *out, const DevCtl &ctl)
     mass_precond(d, 1, d.cal2, out, ctl, 1.0 / a, 1.0 / b);
 }
 
-// y = A x (or P^-1 A x, or B A x for the Calderon preconditioners) on device
-// vectors, on stream s of the handle.
-void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream_t s)
+// the rest of the product once the far field is in (use_far as launch_gather)
+static void apply_after_far(DevMesh &d, const double *x, double *y, int flags, int use_far)
 {
-    hipStream_t keep = d.stream;
-    if (s) d.stream = s;
-    const int use_far = far_product(d, x, flags);
     if ((flags & PB_APPLY_PRECOND) && mass_mode(d)) {
         launch_gather(d, x, d.mtmp, flags & ~PB_APPLY_PRECOND, use_far, false);
         mass_precond(d, 1, d.mtmp, y, d.ctl);
@@ -461,6 +457,15 @@ void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream
     } else {
         launch_gather(d, x, y, flags, use_far, true);
     }
+}
+
+// y = A x (or P^-1 A x, or B A x for the Calderon preconditioners) on device
+// vectors, on stream s of the handle.
+void apply_operator(DevMesh &d, const double *x, double *y, int flags, hipStream_t s)
+{
+    hipStream_t keep = d.stream;
+    if (s) d.stream = s;
+    apply_after_far(d, x, y, flags, far_product(d, x, flags));
     d.stream = keep;
 }
 
@@ -474,6 +479,79 @@ static void ensure_krylov(DevMesh &d, int m)
     d.kry.kbuf = (double *)d.alloc(sizeof(double) * (2 * (m + 2) + 2));
     d.kry.y = (double *)d.alloc(sizeof(double) * (m + 1));
     d.kry.cap = m + 1;
+}
+
+// Host side of one unrestarted GMRES: Hessenberg columns from the device's
+// CGS2 coefficients, Givens rotations, and the final triangular solve.  The
+// single-handle and the batched solvers share it, so they round identically.
+struct HostArnoldi {
+    int m = 0, k = 0;
+    double beta = 0.0, res = 0.0;
+    std::vector<double> H, cs, sn, g, hb;
+    void init(int m_, double beta_)
+    {
+        m = m_;
+        beta = beta_;
+        res = beta_;
+        k = 0;
+        H.assign((size_t)(m + 1) * m, 0.0);
+        cs.assign(m, 0.0);
+        sn.assign(m, 0.0);
+        g.assign(m + 1, 0.0);
+        hb.assign(2 * (m + 1) + 1, 0.0);
+        g[0] = beta;
+    }
+    // hb holds the two CGS passes' coefficients and |w|^2 of step j; returns the
+    // norm that w must be divided by (0: breakdown, leave w)
+    double column(int j)
+    {
+        double *col = &H[(size_t)j * (m + 1)];
+        for (int i = 0; i <= j; ++i) col[i] = hb[i] + hb[j + 1 + i];
+        col[j + 1] = std::sqrt(std::max(hb[2 * (j + 1)], 0.0));
+        return col[j + 1];
+    }
+    // rotations of step j; true when converged or broken down
+    bool rotate(int j, double tol)
+    {
+        double *col = &H[(size_t)j * (m + 1)];
+        for (int i = 0; i < j; ++i) {   // explicit FMAs: same arithmetic as the device Givens kernel
+            const double a = std::fma(cs[i], col[i], sn[i] * col[i + 1]);
+            col[i + 1] = std::fma(-sn[i], col[i], cs[i] * col[i + 1]);
+            col[i] = a;
+        }
+        const double den = std::sqrt(std::fma(col[j], col[j], col[j + 1] * col[j + 1]));
+        cs[j] = col[j] / den;
+        sn[j] = col[j + 1] / den;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        k = j + 1;
+        res = std::fabs(g[j + 1]);
+        return res <= tol * beta || !(den > 0.0);
+    }
+    std::vector<double> solution() const
+    {
+        std::vector<double> y(k);
+        for (int i = k - 1; i >= 0; --i) {
+            double a = g[i];
+            for (int l = i + 1; l < k; ++l) a -= H[(size_t)l * (m + 1) + i] * y[l];
+            y[i] = a / H[(size_t)i * (m + 1) + i];
+        }
+        return y;
+    }
+};
+
+// device part of Arnoldi step j: w <- w - V h twice (CGS2), |w|^2; the
+// coefficients land in kb
+static void arnoldi_device(hipStream_t s, int n, int j, const double *Vb, double *w, double *kb)
+{
+    double *h1 = kb, *h2 = kb + (j + 1), *nr = kb + 2 * (j + 1);
+    kr_dots(s, n, j + 1, Vb, n, w, h1);
+    kr_update(s, n, j + 1, Vb, n, h1, w, -1.0);
+    kr_dots(s, n, j + 1, Vb, n, w, h2);
+    kr_update(s, n, j + 1, Vb, n, h2, w, -1.0);
+    kr_dots(s, n, 1, w, n, w, nr);
 }
 
 // Unrestarted GMRES from x0 = 0 on P^-1 A u = pb (pb already preconditioned):
@@ -498,51 +576,24 @@ int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, dou
         return 0;
     }
     kr_scale_copy(s, n, pb, 1.0 / beta, Vb);
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), hb(2 * (m + 1) + 1);
-    g[0] = beta;
-    int k = 0;
-    double res = beta;
+    HostArnoldi ha;
+    ha.init(m, beta);
     for (int j = 0; j < m; ++j) {
         double *w = Vb + (size_t)(j + 1) * n;
         apply_operator(d, Vb + (size_t)j * n, w, PB_APPLY_PRECOND, nullptr);
-        double *h1 = kb, *h2 = kb + (j + 1), *nr = kb + 2 * (j + 1);
-        kr_dots(s, n, j + 1, Vb, n, w, h1);
-        kr_update(s, n, j + 1, Vb, n, h1, w, -1.0);
-        kr_dots(s, n, j + 1, Vb, n, w, h2);
-        kr_update(s, n, j + 1, Vb, n, h2, w, -1.0);
-        kr_dots(s, n, 1, w, n, w, nr);
-        HIPCHECK(hipMemcpyAsync(hb.data(), kb, sizeof(double) * (2 * (j + 1) + 1), hipMemcpyDeviceToHost, s));
+        arnoldi_device(s, n, j, Vb, w, kb);
+        HIPCHECK(hipMemcpyAsync(ha.hb.data(), kb, sizeof(double) * (2 * (j + 1) + 1), hipMemcpyDeviceToHost, s));
         HIPCHECK(hipStreamSynchronize(s));
-        double *col = &H[(size_t)j * (m + 1)];
-        for (int i = 0; i <= j; ++i) col[i] = hb[i] + hb[j + 1 + i];
-        col[j + 1] = std::sqrt(std::max(hb[2 * (j + 1)], 0.0));
-        if (col[j + 1] > 0.0) kr_scale_copy(s, n, w, 1.0 / col[j + 1], w);
-        for (int i = 0; i < j; ++i) {   // explicit FMAs: same arithmetic as the device Givens kernel
-            const double a = std::fma(cs[i], col[i], sn[i] * col[i + 1]);
-            col[i + 1] = std::fma(-sn[i], col[i], cs[i] * col[i + 1]);
-            col[i] = a;
-        }
-        const double den = std::sqrt(std::fma(col[j], col[j], col[j + 1] * col[j + 1]));
-        cs[j] = col[j] / den;
-        sn[j] = col[j + 1] / den;
-        col[j] = den;
-        col[j + 1] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        k = j + 1;
-        res = std::fabs(g[j + 1]);
-        if (res <= tol * beta || !(den > 0.0)) break;
+        const double h = ha.column(j);
+        if (h > 0.0) kr_scale_copy(s, n, w, 1.0 / h, w);
+        if (ha.rotate(j, tol)) break;
     }
-    std::vector<double> y(k);
-    for (int i = k - 1; i >= 0; --i) {
-        double a = g[i];
-        for (int l = i + 1; l < k; ++l) a -= H[(size_t)l * (m + 1) + i] * y[l];
-        y[i] = a / H[(size_t)i * (m + 1) + i];
-    }
-    HIPCHECK(hipMemcpyAsync(d.kry.y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-    kr_combine(s, n, k, Vb, n, d.kry.y, x);
-    *est = res / beta;
-    return k;
+    const std::vector<double> y = ha.solution();
+    HIPCHECK(hipMemcpyAsync(d.kry.y, y.data(), sizeof(double) * ha.k, hipMemcpyHostToDevice, s));
+    kr_combine(s, n, ha.k, Vb, n, d.kry.y, x);
+    *est = ha.res / beta;
+    HIPCHECK(hipStreamSynchronize(s));   // y is a host vector
+    return ha.k;
 }
 
 // ------------------------------------------------------ captured GMRES
@@ -676,6 +727,157 @@ int gmres_solve(DevMesh &d, const double *pb, double *x, double tol, int max_ite
 {
     if (d.prof.on(0) || d.opt.use_graph == 0) return gmres(d, pb, x, tol, max_iter, est);
     return gmres_graph(d, pb, x, tol, max_iter, est);
+}
+
+// ------------------------------------------- batched solves of uneven requests
+// GMRES of several matrix-free handles in lockstep on one stream: per
+// iteration the far fields of every request still iterating run as one
+// persistent launch per kernel form (k_far_batch, a work queue over all of
+// them), the rest of each product and each request's Arnoldi step as in
+// gmres(), and one host synchronisation serves every request.  Every
+// request's arithmetic is that of gmres(), so its iterates are bitwise those
+// of its own solve.
+static void gmres_batch(const std::vector<DevMesh *> &ds, hipStream_t s, bool fp32, std::vector<int> &its,
+                        std::vector<double> &est)
+{
+    const int R = (int)ds.size();
+    std::vector<HostArnoldi> ha(R);
+    std::vector<int> n(R), live;
+    std::vector<double> beta2(R, 0.0);
+    its.assign(R, 0);
+    est.assign(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+        DevMesh &d = *ds[r];
+        n[r] = 2 * d.hm.V;
+        ensure_krylov(d, std::min(d.opt.max_iter, n[r]));
+        kr_dots(s, n[r], 1, d.ytmp, n[r], d.ytmp, d.kry.kbuf);
+        HIPCHECK(hipMemcpyAsync(&beta2[r], d.kry.kbuf, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int r = 0; r < R; ++r) {
+        DevMesh &d = *ds[r];
+        const double beta = std::sqrt(beta2[r]);
+        ha[r].init(std::min(d.opt.max_iter, n[r]), beta);
+        if (!(beta > 0.0)) {
+            HIPCHECK(hipMemsetAsync(d.u, 0, sizeof(double) * n[r], s));
+            continue;
+        }
+        kr_scale_copy(s, n[r], d.ytmp, 1.0 / beta, d.kry.basis);
+        live.push_back(r);
+    }
+    FarBatch fb;
+    fb.stream = s;
+    struct Free {
+        FarBatch &fb;
+        ~Free() { far_batch_free(fb); }
+    } free_fb{fb};
+    std::vector<int> planned;
+    for (int j = 0; !live.empty(); ++j) {
+        if (live != planned) {
+            far_batch_plan(ds, live, fp32, fb);
+            planned = live;
+        }
+        for (int r : live) launch_source_prep(*ds[r], ds[r]->kry.basis + (size_t)j * n[r], fp32);
+        // the first handle's profiler (operator kind) times the fused launches
+        Profiler &pf = ds[0]->prof;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (pf.on(0)) {
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+            HIPCHECK(hipEventRecord(e0, s));
+        }
+        launch_far_batch(fb, fp32);
+        if (pf.on(0)) {
+            HIPCHECK(hipEventRecord(e1, s));
+            double pairs = 0.0;   // kernel pairs, near-masked pairs included
+            for (int r : live) pairs += 36.0 * (double)ds[r]->hm.T * (double)ds[r]->hm.T;
+            pf.record(0, e0, e1, pairs);
+        }
+        for (int r : live) {
+            DevMesh &d = *ds[r];
+            double *Vb = d.kry.basis, *w = Vb + (size_t)(j + 1) * n[r];
+            launch_far_finish(d, fp32);
+            apply_after_far(d, Vb + (size_t)j * n[r], w, PB_APPLY_PRECOND, 1);
+            arnoldi_device(s, n[r], j, Vb, w, d.kry.kbuf);
+            HIPCHECK(hipMemcpyAsync(ha[r].hb.data(), d.kry.kbuf, sizeof(double) * (2 * (j + 1) + 1),
+                                    hipMemcpyDeviceToHost, s));
+        }
+        HIPCHECK(hipStreamSynchronize(s));
+        std::vector<int> next;
+        for (int r : live) {
+            DevMesh &d = *ds[r];
+            double *w = d.kry.basis + (size_t)(j + 1) * n[r];
+            const double h = ha[r].column(j);
+            if (h > 0.0) kr_scale_copy(s, n[r], w, 1.0 / h, w);
+            if (!ha[r].rotate(j, d.opt.tol) && j + 1 < ha[r].m) next.push_back(r);
+        }
+        live.swap(next);
+    }
+    for (int r = 0; r < R; ++r) {
+        if (!(ha[r].beta > 0.0)) continue;
+        DevMesh &d = *ds[r];
+        const std::vector<double> y = ha[r].solution();
+        HIPCHECK(hipMemcpyAsync(d.kry.y, y.data(), sizeof(double) * ha[r].k, hipMemcpyHostToDevice, s));
+        kr_combine(s, n[r], ha[r].k, d.kry.basis, n[r], d.kry.y, d.u);
+        HIPCHECK(hipStreamSynchronize(s));   // y is a host vector
+        its[r] = ha[r].k;
+        est[r] = ha[r].res / ha[r].beta;
+    }
+}
+
+// Solves one charge set per handle with the far-field products of all of
+// them fused (gmres_batch), everything on the first handle's stream; the
+// handles' own streams are drained first and restored afterwards.
+static pb_status solve_batch(const std::vector<DevMesh *> &ds, const pb_charges *ch, pb_result *res)
+{
+    const int R = (int)ds.size();
+    hipStream_t s = ds[0]->stream;
+    std::vector<hipStream_t> keep(R);
+    for (int r = 0; r < R; ++r) {
+        keep[r] = ds[r]->stream;
+        HIPCHECK(hipStreamSynchronize(keep[r]));
+    }
+    struct Restore {
+        const std::vector<DevMesh *> &ds;
+        const std::vector<hipStream_t> &keep;
+        ~Restore()
+        {
+            for (size_t r = 0; r < ds.size(); ++r) ds[r]->stream = keep[r];
+        }
+    } restore{ds, keep};
+    for (DevMesh *d : ds) d->stream = s;
+    std::vector<double> t_rhs(R), t_prec(R);
+    for (int r = 0; r < R; ++r) {
+        DevMesh &d = *ds[r];
+        const double t0 = now();
+        charges_to_device(d, &ch[r]);
+        check_charges_inside(d, ch[r].n);
+        formulation_rhs(d, ch[r].n, d.qbuf, d.xtmp);
+        HIPCHECK(hipStreamSynchronize(s));
+        const double t1 = now();
+        if (mass_mode(d)) mass_precond(d, 1, d.xtmp, d.ytmp, DevCtl());
+        else kr_precond(s, d.hm.V, d.pinv, d.xtmp, d.ytmp);
+        if (!d.u) d.u = (double *)d.alloc(sizeof(double) * 2 * (size_t)d.hm.V);
+        HIPCHECK(hipStreamSynchronize(s));
+        t_rhs[r] = t1 - t0;
+        t_prec[r] = now() - t1;
+    }
+    const double t2 = now();
+    std::vector<int> its;
+    std::vector<double> est;
+    gmres_batch(ds, s, ds[0]->prm.precision == PB_FP32, its, est);
+    const double t_gmres = now() - t2;
+    pb_status worst = PB_OK;
+    for (int r = 0; r < R; ++r) {
+        // the profile keeps the fused launches only, not the residual check's product
+        const int mask = ds[r]->prof.mask;
+        ds[r]->prof.mask = 0;
+        const pb_status st = finish_result(*ds[r], &ch[r], ds[r]->ytmp, ds[r]->u, its[r], 1, t_rhs[r], t_prec[r],
+                                           t_gmres, &res[r]);
+        ds[r]->prof.mask = mask;
+        if (st != PB_OK) worst = st;
+    }
+    return worst;
 }
 
 // ------------------------------------------------------------ charges, dG
@@ -947,6 +1149,31 @@ pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *se
     if (!h || n_sets < 1 || !sets || !out) fail(PB_E_INVALID_ARG, "bad pb_solve_multi arguments");
     if (calderon_mode(*h->d)) fail(PB_E_STATE, "batched solves do not support the Calderon preconditioners");
     return solve_multi(*h->d, n_sets, sets, out);
+    PB_CATCH
+}
+
+pb_status pb_solve_batch(int32_t n, pb_mesh_handle *const *handles, const pb_charges *charges,
+                         pb_result *results)
+{
+    PB_TRY
+    if (n < 1 || n > PB_MAX_BATCH_REQUESTS || !handles || !charges || !results)
+        fail(PB_E_INVALID_ARG, "bad pb_solve_batch arguments");
+    std::vector<DevMesh *> ds(n);
+    for (int r = 0; r < n; ++r) {
+        if (!handles[r]) fail(PB_E_INVALID_ARG, "NULL handle in pb_solve_batch");
+        ds[r] = handles[r]->d;
+        for (int q = 0; q < r; ++q)
+            if (ds[q] == ds[r]) fail(PB_E_INVALID_ARG, "a handle appears twice in pb_solve_batch");
+    }
+    const int prec = ds[0]->prm.precision;
+    for (DevMesh *d : ds) {
+        if (d->prm.precision != prec || (prec != PB_FP32 && prec != PB_FP64))
+            fail(PB_E_STATE, "pb_solve_batch needs handles of one precision, PB_FP64 or PB_FP32");
+        if (d->dense || d->tree || d->far_rule != 0)
+            fail(PB_E_STATE, "pb_solve_batch needs matrix-free handles (no assembled far field, no treecode)");
+        if (calderon_mode(*d)) fail(PB_E_STATE, "pb_solve_batch does not support the Calderon preconditioners");
+    }
+    return solve_batch(ds, charges, results);
     PB_CATCH
 }
 

@@ -141,3 +141,16 @@ def test_server_host_logic_without_gpu(pbm):
             assert e.value.code == pbm.PB_E_DEVICE
         st = s.stats()
         assert st["submitted"] >= 1 and st["failed"] >= 1 and st["running"] == 0
+
+
+def test_batch_solve_argument_checks(pbm):
+    """pb_solve_batch rejects bad counts and NULL arrays before any device work."""
+    L = pbm.load()
+    cs = (pbm.pb_charges * 1)()
+    rs = (pbm.pb_result * 1)()
+    hs = (ctypes.c_void_p * 1)(None)
+    assert L.pb_solve_batch(0, hs, cs, rs) == pbm.PB_E_INVALID_ARG
+    assert L.pb_solve_batch(pbm.PB_MAX_BATCH_REQUESTS + 1, hs, cs, rs) == pbm.PB_E_INVALID_ARG
+    assert L.pb_solve_batch(1, None, cs, rs) == pbm.PB_E_INVALID_ARG
+    assert L.pb_solve_batch(1, hs, cs, rs) == pbm.PB_E_INVALID_ARG   # NULL handle
+    assert "handle" in pbm.pb_last_error()
