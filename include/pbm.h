@@ -227,7 +227,9 @@ pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result 
  * result bit for bit, timings aside: t_rhs, t_prec are the request's own,
  * t_gmres the whole batch's.  charges[r] and results[r] belong to handles[r]
  * and follow the pb_mesh_solve contract; the call returns PB_NOT_CONVERGED if
- * any request did not converge (all results filled).  The handles must share
+ * any request did not converge (all results filled), and fails as a whole,
+ * with no result, if any request's charges are invalid (the message names the
+ * request).  The handles must share
  * the precision (PB_FP64 or PB_FP32) and be matrix-free (operator mode
  * PB_MATRIX_FREE, or PB_AUTO resolved to it; no treecode), with any
  * formulation and the block-diagonal or mass preconditioners; otherwise

@@ -850,8 +850,12 @@ static pb_status solve_batch(const std::vector<DevMesh *> &ds, const pb_charges 
     for (int r = 0; r < R; ++r) {
         DevMesh &d = *ds[r];
         const double t0 = now();
-        charges_to_device(d, &ch[r]);
-        check_charges_inside(d, ch[r].n);
+        try {
+            charges_to_device(d, &ch[r]);
+            check_charges_inside(d, ch[r].n);
+        } catch (const Error &e) {
+            fail(e.code, "request " + std::to_string(r) + ": " + e.msg);
+        }
         formulation_rhs(d, ch[r].n, d.qbuf, d.xtmp);
         HIPCHECK(hipStreamSynchronize(s));
         const double t1 = now();

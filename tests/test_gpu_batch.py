@@ -101,6 +101,11 @@ def test_batch_refusals():
             with pytest.raises(pbm.PbError) as e:
                 pbm.pb_solve_batch(hs, sets)
             assert e.value.code == code
+        # a charge outside one request's surface fails the call and names the request
+        far = np.array([[100.0, 0.0, 0.0]])
+        with pytest.raises(pbm.PbError) as e:
+            pbm.pb_solve_batch(mf, [sets[0], (far, np.ones(1))])
+        assert e.value.code == pbm.PB_E_CHARGES and "request 1" in pbm.pb_last_error()
         # the refused calls left the handles usable
         _same(pbm.pb_solve_batch(mf, sets)[1], pbm.pb_mesh_solve(mf[1], *sets[1]))
     finally:
