@@ -305,7 +305,12 @@ pb_status pb_mesh_profile_read(pb_mesh_handle *h, int32_t kind, int64_t *launche
  * budget beside the requests already running (first fit in arrival order);
  * then it runs on its own worker thread, HIP stream and memory, overlapping on
  * the device with the other running requests.  A request's result does not
- * depend on what runs beside it.  Times are seconds since pb_server_create. */
+ * depend on what runs beside it.  Device blocks of 64 MiB and more (the
+ * assembled far field, the near-field blocks) that a finished request leaves
+ * are kept by the server and handed to later requests of similar size
+ * (best fit within 5/4, in 256 MiB steps); idle blocks go back to the device
+ * while a new one would take the server past its budget, and all of them at
+ * pb_server_destroy.  Times are seconds since pb_server_create. */
 typedef struct pb_server pb_server;
 
 typedef struct {

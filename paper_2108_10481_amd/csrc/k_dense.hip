@@ -758,10 +758,13 @@ static size_t dense_bytes(const DevMesh &d)
 
 bool dense_fits(const DevMesh &d, int copies)
 {
-    size_t freeb = 0, total = 0;
-    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return false;
     size_t need = dense_bytes(d) * (size_t)copies;
     if (d.opt.memory_budget && d.bytes + need > d.opt.memory_budget) return false;
+    // a server's handle: admission reserved its footprint, and the free memory
+    // the device reports leaves out the blocks the server keeps for reuse
+    if (d.cache) return true;
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return false;
     return need < 0.8 * (double)freeb;
 }
 

@@ -181,6 +181,16 @@ struct Krylov {
     double *y = nullptr;       // least-squares coefficients
 };
 
+// Device blocks of at least kCacheMin bytes that a server keeps after its
+// requests finish and hands to later requests (runtime.hip): mapping and
+// unmapping tens of GB per request took longer than the request's
+// arithmetic and serialised concurrent requests.
+constexpr size_t kCacheMin = (size_t)64 << 20;
+struct BlockCache;
+BlockCache *block_cache_create(size_t limit);
+void block_cache_destroy(BlockCache *c);
+size_t block_cache_bytes(const BlockCache *c);   // held, idle and in use
+
 struct DevMesh {
     HostMesh hm;
     Params prm;
@@ -189,6 +199,8 @@ struct DevMesh {
     hipStream_t stream = nullptr;
     size_t bytes = 0;
     std::vector<void *> allocs;
+    BlockCache *cache = nullptr;   // server handles: large blocks come from and return to it
+    std::vector<std::pair<void *, size_t>> cached;   // (block, its size) taken from the cache
 
     // geometry (sorted triangle order)
     double *xyz = nullptr;         // V x 3

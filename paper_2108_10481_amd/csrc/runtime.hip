@@ -6,7 +6,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "dense.h"
@@ -27,12 +29,89 @@ void hip_check(hipError_t e, const char *what, const char *file, int line)
     throw Error{e == hipErrorOutOfMemory ? PB_E_NOMEM : PB_E_DEVICE, m};
 }
 
+// ------------------------------------------------------ server block cache
+struct BlockCache {
+    std::mutex mu;
+    std::multimap<size_t, void *> idle;   // by size
+    size_t held = 0;                       // idle + in use
+    size_t limit = 0;
+};
+
+BlockCache *block_cache_create(size_t limit)
+{
+    BlockCache *c = new BlockCache();
+    c->limit = limit;
+    return c;
+}
+
+void block_cache_destroy(BlockCache *c)
+{
+    if (!c) return;
+    for (auto &e : c->idle) (void)hipFree(e.second);
+    delete c;
+}
+
+size_t block_cache_bytes(const BlockCache *c) { return c ? c->held : 0; }
+
+// A block of at least n bytes: an idle one of at most 5/4 of n rounded up to
+// 256 MiB (best fit), else a new one, after idle blocks are given back to the
+// device while the new one would pass the limit (or the device is full).
+static void *cache_take(BlockCache &c, size_t n, size_t *got)
+{
+    const size_t gran = (size_t)256 << 20;
+    const size_t want = (n + gran - 1) / gran * gran;
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.idle.lower_bound(want);
+    if (it != c.idle.end() && it->first <= want + want / 4) {
+        void *p = it->second;
+        *got = it->first;
+        c.idle.erase(it);
+        return p;
+    }
+    while (!c.idle.empty() && c.held + want > c.limit) {
+        auto big = std::prev(c.idle.end());
+        (void)hipFree(big->second);
+        c.held -= big->first;
+        c.idle.erase(big);
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    while (e != hipSuccess && !c.idle.empty()) {
+        (void)hipGetLastError();
+        auto big = std::prev(c.idle.end());
+        (void)hipFree(big->second);
+        c.held -= big->first;
+        c.idle.erase(big);
+        e = hipMalloc(&p, want);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(PB_E_NOMEM, "device memory exhausted");
+    }
+    c.held += want;
+    *got = want;
+    return p;
+}
+
+static void cache_give(BlockCache &c, void *p, size_t size)
+{
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.idle.insert({size, p});
+}
+
 void *DevMesh::alloc(size_t n)
 {
     void *p = nullptr;
     n = std::max<size_t>(n, 256);
     if (opt.memory_budget && bytes + n > opt.memory_budget)
         fail(PB_E_NOMEM, "device memory budget of the handle exceeded");
+    if (cache && n >= kCacheMin) {
+        size_t got = 0;
+        p = cache_take(*cache, n, &got);
+        cached.push_back({p, got});
+        bytes += n;
+        return p;
+    }
     // stream-ordered allocation: frees of one handle never stall another handle's stream
     HIPCHECK(hipMallocAsync(&p, n, stream));
     allocs.push_back(p);
@@ -53,6 +132,8 @@ DevMesh::~DevMesh()
     destroy_batch(*this);
     for (void *p : allocs) (void)hipFreeAsync(p, stream);
     if (stream) (void)hipStreamSynchronize(stream);
+    // the stream is idle: the cached blocks may serve the next request
+    for (auto &b : cached) cache_give(*cache, b.first, b.second);
     if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -264,11 +345,12 @@ static void device_setup(DevMesh &d)
     }
 }
 
-static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
+static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCache *cache = nullptr)
 {
     check_options(opt);
     const double t0 = now();
     std::unique_ptr<DevMesh> d(new DevMesh());
+    d->cache = cache;
     d->opt = *opt;
     d->prm = {opt->eps_in, opt->eps_out, opt->kappa, opt->formulation, opt->preconditioner, opt->precision,
               opt->operator_mode};
@@ -357,7 +439,10 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt)
     return d.release();
 }
 
-DevMesh *create_mesh_checked(const pb_mesh *mesh, const pb_options *opt) { return create_mesh(mesh, opt); }
+DevMesh *create_mesh_checked(const pb_mesh *mesh, const pb_options *opt, BlockCache *cache)
+{
+    return create_mesh(mesh, opt, cache);
+}
 
 // Device bytes a handle is expected to hold for V vertices, T triangles:
 // geometry and source/target records, far-field partial sums, near pairs and

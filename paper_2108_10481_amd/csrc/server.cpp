@@ -20,7 +20,7 @@
 #include "pbm_internal.h"
 
 namespace pbm {
-DevMesh *create_mesh_checked(const pb_mesh *mesh, const pb_options *opt);
+DevMesh *create_mesh_checked(const pb_mesh *mesh, const pb_options *opt, BlockCache *cache);
 size_t estimate_device_bytes(int V, int T, const pb_options *opt);
 }  // namespace pbm
 
@@ -62,6 +62,7 @@ struct pb_server {
     int64_t submitted = 0, completed = 0, cancelled = 0, failed = 0;
     uint64_t next_id = 1;
     bool stop = false;
+    BlockCache *cache = nullptr;   // large device blocks kept between requests (null without a device)
     std::vector<std::thread> workers;
 
     Request *pick()
@@ -84,7 +85,7 @@ struct pb_server {
         r->res.phi = r->phi.data();
         r->res.dphi = r->dphi.data();
         try {
-            std::unique_ptr<DevMesh> d(create_mesh_checked(&m, &r->opt));
+            std::unique_ptr<DevMesh> d(create_mesh_checked(&m, &r->opt, cache));
             r->status = solve_on_mesh(*d, &c, &r->res);
         } catch (const Error &e) {
             r->status = e.code;
@@ -172,6 +173,8 @@ pb_status pb_server_create(size_t hbm_budget, int32_t max_slots, pb_server **out
         budget = (size_t)(0.9 * (double)freeb);
     }
     std::unique_ptr<pb_server> s(new pb_server());
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) s->cache = block_cache_create(budget);
     s->budget = budget;
     s->slots = max_slots;
     s->t0 = clock_s();
@@ -197,6 +200,7 @@ pb_status pb_server_destroy(pb_server *s)
     }
     s->cv_work.notify_all();
     for (auto &t : s->workers) t.join();
+    block_cache_destroy(s->cache);
     delete s;
     return PB_OK;
     SV_CATCH

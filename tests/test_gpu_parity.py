@@ -360,6 +360,42 @@ def test_server_same_alone_and_in_the_mix():
         assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["dphi"], b["dphi"])
 
 
+def test_server_reused_blocks_change_nothing():
+    """Requests large enough for the server's block cache (assembled far fields
+    of 0.5 to 1.7 GB, near-field blocks above 64 MiB), repeated and interleaved
+    so that later ones run in blocks earlier ones left (of the same or another
+    size, holding their stale values): bitwise the results they give alone."""
+    reqs = []
+    for k, (f, prec, form) in enumerate([(24, pbm.PB_MIXED_BF16, 1), (32, pbm.PB_FP32, 0), (28, pbm.PB_MIXED_FP16, 0)]):
+        base = 18.0 * (20 * f * f / 81920.0) ** 0.5
+        mesh, shape = inputs.star_surface(500 + k, f, base)
+        ch = inputs.charges_in_star(600 + k, 40, shape, values="uniform")
+        reqs.append((mesh, ch, pbm.pb_default_options(formulation=form, precision=prec,
+                                                      operator_mode=pbm.PB_ASSEMBLED)))
+    alone = []
+    for mesh, ch, opt in reqs:
+        o = pbm.pb_default_options()
+        for f, _ in pbm.pb_options._fields_:
+            setattr(o, f, getattr(opt, f))
+        o.memory_budget = pbm.pb_estimate_device_bytes(mesh.xyz, mesh.tri, opt)
+        alone.append(pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q, o))
+    order = [0, 1, 2, 0, 1, 2, 1]
+    with pbm.Server(max_slots=2) as s:
+        got = []
+        for k in order:   # one at a time, so every later request finds idle blocks
+            m, c, o = reqs[k]
+            got.append(s.wait(s.submit(m.xyz, m.tri, c.xyz, c.q, o)))
+        tickets = [s.submit(reqs[k][0].xyz, reqs[k][0].tri, reqs[k][1].xyz, reqs[k][1].q, reqs[k][2])
+                   for k in order]
+        got += [s.wait(t) for t in tickets]
+        st = s.stats()
+    assert st["failed"] == 0
+    for k, b in zip(order + order, got):
+        a = alone[k]
+        assert a["dG"] == b["dG"] and a["iterations"] == b["iterations"]
+        assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["dphi"], b["dphi"])
+
+
 def test_server_admission_by_footprint_and_cancel():
     """Equal-size requests under a budget that fits only one of them run one
     at a time; a queued request can be cancelled; results stay correct."""
