@@ -29,6 +29,7 @@ pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, doub
 void charges_to_device(DevMesh &d, const pb_charges *c);
 void check_charges_inside(DevMesh &d, int nq);
 int autotune_pick(const std::string &key, int nvariants, const std::function<void(int)> &run, hipStream_t st);
+std::string size_class(long long n);
 
 // ------------------------------------------------------------------ GEMM
 // One wavefront per 16-row tile, all 16 right-hand sides.  v_mfma_f32_16x16x32
@@ -277,7 +278,7 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
                                    D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
         };
         if (D->gemm_rows == 0) {
-            const std::string key = std::string("gemm16/") + (D->kind16 == 1 ? "bf16/" : "fp16/") + std::to_string(n);
+            const std::string key = std::string("gemm16/") + (D->kind16 == 1 ? "bf16/" : "fp16/") + size_class(n);
             D->gemm_rows = 1 + autotune_pick(key, 2, launch, d.stream);
         }
         Profiler &pf = d.prof;

@@ -1088,6 +1088,7 @@ static void gemv_dispatch(Dense &D, int variant, hipStream_t st, bool lo, double
 }
 
 int autotune_pick(const std::string &key, int nvariants, const std::function<void(int)> &run, hipStream_t st);
+std::string size_class(long long n);
 
 static int gemv_variant(DevMesh &d, bool lo)
 {
@@ -1095,7 +1096,7 @@ static int gemv_variant(DevMesh &d, bool lo)
     int &slot = lo ? D.gemv_lo : D.gemv_hi;
     if (slot >= 0) return slot;
     const char *kind = D.A64 ? "f64" : !lo ? "f32" : D.kind16 == 1 ? "bf16" : "fp16";
-    const std::string key = std::string("gemv/") + kind + "/" + std::to_string(D.n);
+    const std::string key = std::string("gemv/") + kind + "/" + size_class(D.n);
     slot = autotune_pick(key, 6, [&](int v) { gemv_dispatch(D, v, d.stream, lo, d.yfar); }, d.stream);
     return slot;
 }
