@@ -525,70 +525,75 @@ def calderon(argv=None):
 
 
 def batch(argv=None):
-    """Uneven requests solved together (pb_solve_batch): the serving-trace
-    generator's star surfaces capped at 20480 triangles (1280 to 20480
-    triangles, 50 to about 1000 charges, direct or Juffer), FP32 matrix-free,
-    handles resident.  One step = every request solved once with the far
-    fields of all requests fused into one persistent launch per kernel form and
-    GMRES iteration; beside it the same requests solved one after the other
-    (pb_mesh_solve, captured GMRES).  The two give bitwise the same results,
-    which the run checks; the fused launches are timed with HIP events."""
+    """Uneven requests solved together (pb_solve_batch) against the same
+    requests solved one after the other (pb_mesh_solve, captured GMRES), on two
+    mixes of the serving-trace generator's star surfaces (seed 5, FP32
+    matrix-free, direct or Juffer, handles resident): 16 requests of
+    1280-15680 triangles, and 64 small ones of 1280-5120 triangles, which
+    alone leave most of the device idle.  One step = every request of the mix
+    solved once; in the fused solve the far fields of all requests still
+    iterating run in one persistent launch per kernel form and GMRES
+    iteration.  The two give bitwise the same results, which the run checks;
+    the fused launches are timed with HIP events."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload")
-    ap.add_argument("--requests", type=int, default=16)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     a, _ = ap.parse_known_args(argv)
     import paper_2108_10481_amd as pbm
-    trace = inputs.serving_trace(seed=5, n_requests=a.requests, fmax=32)
-    reqs = [inputs.build_request(r) + (r["formulation"],) for r in trace]
-    hs = [pbm.MeshHandle(m.xyz, m.tri, pbm.pb_default_options(formulation=f, precision=pbm.PB_FP32,
-                                                               operator_mode=pbm.PB_MATRIX_FREE))
-          for m, _, f in reqs]
-    sets = [(c.xyz, c.q) for _, c, _ in reqs]
+    out = {}
+    for name, nreq, fmax in (("mix16_1280_15680", 16, 32), ("small64_1280_5120", 64, 16)):
+        trace = inputs.serving_trace(seed=5, n_requests=nreq, fmax=fmax)
+        reqs = [inputs.build_request(r) + (r["formulation"],) for r in trace]
+        hs = [pbm.MeshHandle(m.xyz, m.tri, pbm.pb_default_options(formulation=f, precision=pbm.PB_FP32,
+                                                                   operator_mode=pbm.PB_MATRIX_FREE))
+              for m, _, f in reqs]
+        sets = [(c.xyz, c.q) for _, c, _ in reqs]
 
-    def singles():
-        return [pbm.pb_mesh_solve(h, *st) for h, st in zip(hs, sets)]
+        def singles():
+            return [pbm.pb_mesh_solve(h, *st) for h, st in zip(hs, sets)]
 
-    def fused():
-        return pbm.pb_solve_batch(hs, sets)
+        def fused():
+            return pbm.pb_solve_batch(hs, sets)
 
-    for _ in range(a.warmup):
-        singles()
-        fused()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        rs = singles()
-    t_single = (time.perf_counter() - t0) / a.steps
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        rb = fused()
-    t_fused = (time.perf_counter() - t0) / a.steps
-    same = all(x["dG"] == y["dG"] and x["iterations"] == y["iterations"] and np.array_equal(x["phi"], y["phi"])
-               for x, y in zip(rb, rs))
-    # one more fused step with the fused far-field launches timed (first handle's profile)
-    pbm.pb_mesh_profile(hs[0], 1)
-    rp = fused()
-    pbm.pb_mesh_synchronize(hs[0])
-    launches, ms, pairs = pbm.pb_mesh_profile_read(hs[0], 0)
-    pbm.pb_mesh_profile(hs[0], 0)
-    flops = sum(rp[k]["iterations"] * 36.0 * m.n_triangles ** 2 * FLOPS_PER_PAIR[f] for k, (m, _, f) in enumerate(reqs))
-    achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    for h in hs:
-        h.close()
-    sizes = sorted(m.n_triangles for m, _, _ in reqs)
-    rec = {"workload": f"{len(reqs)} serving-trace star surfaces (seed 5), {sizes[0]}-{sizes[-1]} triangles, "
-                       "FP32 matrix-free, direct/Juffer mixed, resident handles; one step = every request solved once",
-           "steps": a.steps, "triangles": sizes,
-           "fused": {"solves_per_s": round(len(reqs) / t_fused, 3), "s_per_step": round(t_fused, 4)},
-           "one_after_another": {"solves_per_s": round(len(reqs) / t_single, 3), "s_per_step": round(t_single, 4)},
-           "speedup": round(t_single / t_fused, 3), "bitwise_equal": bool(same),
-           "iterations": [r["iterations"] for r in rb],
-           "fused_far_field": {"kernel": "k_far_batch (one launch per kernel form and GMRES iteration)",
-                               "products": int(launches), "avg_product_ms": round(ms / max(launches, 1), 4),
-                               "kernel_pairs_per_s": round(pairs / (ms * 1e-3), 1) if ms > 0 else None,
-                               "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32"],
-                               "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32"], 4)}}
+        for _ in range(a.warmup):
+            singles()
+            fused()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            rs = singles()
+        t_single = (time.perf_counter() - t0) / a.steps
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            rb = fused()
+        t_fused = (time.perf_counter() - t0) / a.steps
+        same = all(x["dG"] == y["dG"] and x["iterations"] == y["iterations"] and np.array_equal(x["phi"], y["phi"])
+                   for x, y in zip(rb, rs))
+        # one more fused step with the fused far-field launches timed (first handle's profile)
+        pbm.pb_mesh_profile(hs[0], 1)
+        rp = fused()
+        pbm.pb_mesh_synchronize(hs[0])
+        launches, ms, pairs = pbm.pb_mesh_profile_read(hs[0], 0)
+        pbm.pb_mesh_profile(hs[0], 0)
+        flops = sum(rp[k]["iterations"] * 36.0 * m.n_triangles ** 2 * FLOPS_PER_PAIR[f]
+                    for k, (m, _, f) in enumerate(reqs))
+        achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        for h in hs:
+            h.close()
+        sizes = sorted(m.n_triangles for m, _, _ in reqs)
+        out[name] = {
+            "requests": len(reqs), "triangles_min_max": [sizes[0], sizes[-1]],
+            "fused": {"solves_per_s": round(len(reqs) / t_fused, 3), "s_per_step": round(t_fused, 4)},
+            "one_after_another": {"solves_per_s": round(len(reqs) / t_single, 3), "s_per_step": round(t_single, 4)},
+            "speedup": round(t_single / t_fused, 3), "bitwise_equal": bool(same),
+            "fused_far_field": {"kernel": "k_far_batch (one launch per kernel form and GMRES iteration)",
+                                "products": int(launches), "avg_product_ms": round(ms / max(launches, 1), 4),
+                                "kernel_pairs_per_s": round(pairs / (ms * 1e-3), 1) if ms > 0 else None,
+                                "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["f32"],
+                                "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS["f32"], 4)}}
+        print(f"batch: {name} done", file=sys.stderr, flush=True)
+    rec = {"workload": "serving-trace star surfaces (seed 5), FP32 matrix-free, direct/Juffer mixed, resident "
+                       "handles; one step = every request of the mix solved once", "steps": a.steps, "mixes": out}
     print(json.dumps(rec), flush=True)
 
 
