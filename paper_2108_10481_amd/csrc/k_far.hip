@@ -266,18 +266,34 @@ __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, Fa
 
 // family 0: rows (Laplace, Yukawa), swapped when the Laplace row is row 2;
 // family 1: row 2 gets D's curl part times aD (aL of D, or aY without Laplace terms)
+// kFinishLanes lanes per target sum every kFinishLanes-th chunk, then a fixed
+// butterfly inside the lane group (one wavefront holds whole groups): with
+// one thread per target a small mesh gave too few threads for up to 128 chunks.
+constexpr int kFinishLanes = 16;
+
 template <typename R>
-__global__ void k_far_finish(int T, int S, int family, int swap, double aD, const double *__restrict__ geo,
-                             const R *__restrict__ part, double *__restrict__ triout, DevCtl ctl)
+__global__ __launch_bounds__(256) void k_far_finish(int T, int S, int family, int swap, double aD,
+                                                    const double *__restrict__ geo, const R *__restrict__ part,
+                                                    double *__restrict__ triout, DevCtl ctl)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T || ctl_skip(ctl)) return;
+    if (ctl_skip(ctl)) return;
+    const int t = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kFinishLanes);
+    const int l = threadIdx.x % kFinishLanes;
+    const bool ok = t < T;   // the whole lane group agrees
     double pot[15];
+#pragma unroll
     for (int v = 0; v < 15; ++v) pot[v] = 0.0;
-    for (int c = 0; c < S; ++c) {
-        const R *o = part + ((size_t)c * T + t) * 16;
-        for (int v = 0; v < 15; ++v) pot[v] += (double)o[v];
-    }
+    if (ok)
+        for (int c = l; c < S; c += kFinishLanes) {
+            const R *o = part + ((size_t)c * T + t) * 16;
+#pragma unroll
+            for (int v = 0; v < 15; ++v) pot[v] += (double)o[v];
+        }
+#pragma unroll
+    for (int v = 0; v < 15; ++v)
+#pragma unroll
+        for (int off = kFinishLanes / 2; off > 0; off >>= 1) pot[v] += __shfl_xor(pot[v], off);
+    if (!ok || l != 0) return;
     const double *g = geo + (size_t)t * kGeo;
     const double sc = g[21] * kInv4Pi;
     for (int k = 0; k < 3; ++k) {
@@ -524,7 +540,7 @@ void launch_far_centroid(DevMesh &d)
 void launch_far_finish(DevMesh &d, bool fp32)
 {
     const int T = d.hm.T;
-    dim3 grid((T + 255) / 256), block(256);
+    dim3 grid((unsigned)(((size_t)T * kFinishLanes + 255) / 256)), block(256);
     const FormCoef &f = d.fm;
     const int swap = f.family == 0 && laplace_row(f) == 1;
     const double aD = f.family == 1 ? (yukawa_only(f) ? f.aY[1][0] : f.aL[1][0]) : 0.0;
