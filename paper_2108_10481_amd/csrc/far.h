@@ -43,6 +43,7 @@ struct FarReq {
     const R *stat;
     const R *dyn;
     R *part;
+    const int *skip;   // when set and nonzero (the request's GMRES stopped), its items do nothing
     FarCoef<R> cf;
     int T, chunk;
 };

@@ -151,6 +151,7 @@ __global__ __launch_bounds__(kFarBlock) void k_far_batch(const FarReq<R> *__rest
         if (i >= nitems) return;
         const int4 it = items[i];
         const FarReq<R> rq = reqs[it.x];
+        if (rq.skip && *rq.skip) continue;
         const int t = it.y + lane;
         const int s0 = it.z * rq.chunk;
         const int s1 = min(rq.T, s0 + rq.chunk);
@@ -423,8 +424,22 @@ void launch_far(DevMesh &d, bool fp32)
 // One queue per kernel form over the requests in `live` (indices into ds);
 // items of a request follow its own source split (d.S chunks), so
 // k_far_finish applies unchanged.
+template <typename R, int FORM>
+static int batch_blocks(int n)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_far_batch<R, FORM>), kFarBlock, 0));
+    const int waves = kFarBlock / 64;
+    return (int)std::max(1LL, std::min((long long)(n + waves - 1) / waves,
+                                       (long long)std::max(ncu, 1) * std::max(per_cu, 1)));
+}
+
 template <typename R>
-static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, FarBatch &fb)
+static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live,
+                       const std::vector<const int *> &skip, FarBatch &fb)
 {
     for (int f = 0; f < 4; ++f) fb.nitems[f] = 0;
     std::vector<FarReq<R>> reqs(ds.size());
@@ -438,6 +453,7 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         rq.stat = sizeof(R) == 4 ? (const R *)d.stat32 : (const R *)d.stat64;
         rq.dyn = sizeof(R) == 4 ? (const R *)d.dyn32 : (const R *)d.dyn64;
         rq.part = (R *)d.part;
+        rq.skip = skip.empty() ? nullptr : skip[r];
         rq.T = T;
         rq.chunk = chunk;
         // every chunk, empty ones too: k_far_finish sums all S of them
@@ -454,6 +470,10 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         for (auto &e : q[f]) items.push_back(e.second);
         fb.nitems[f] = (int)q[f].size();
     }
+    fb.nblocks[0] = fb.nitems[0] ? batch_blocks<R, 0>(fb.nitems[0]) : 0;
+    fb.nblocks[1] = fb.nitems[1] ? batch_blocks<R, 1>(fb.nitems[1]) : 0;
+    fb.nblocks[2] = fb.nitems[2] ? batch_blocks<R, 2>(fb.nitems[2]) : 0;
+    fb.nblocks[3] = fb.nitems[3] ? batch_blocks<R, 3>(fb.nitems[3]) : 0;
     const size_t rb = sizeof(FarReq<R>) * reqs.size(), ib = sizeof(int4) * std::max<size_t>(items.size(), 1);
     if (rb > fb.req_cap) {
         if (fb.reqs) HIPCHECK(hipFree(fb.reqs));
@@ -473,29 +493,23 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
     HIPCHECK(hipStreamSynchronize(fb.stream));   // host vectors go out of scope
 }
 
+// launch only (no host query or synchronisation), so it can be captured
 template <typename R, int FORM>
 static void batch_launch(FarBatch &fb)
 {
     const int n = fb.nitems[FORM];
     if (n == 0) return;
-    int dev = 0, ncu = 0, per_cu = 0;
-    HIPCHECK(hipGetDevice(&dev));
-    HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(&k_far_batch<R, FORM>), kFarBlock, 0));
-    const int waves = kFarBlock / 64;
-    const long long nb = std::max(1LL, std::min((long long)(n + waves - 1) / waves,
-                                                (long long)std::max(ncu, 1) * std::max(per_cu, 1)));
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, fb.stream, fb.next + FORM, 0);
-    hipLaunchKernelGGL((k_far_batch<R, FORM>), dim3((unsigned)nb), dim3(kFarBlock), 0, fb.stream,
+    hipLaunchKernelGGL((k_far_batch<R, FORM>), dim3((unsigned)fb.nblocks[FORM]), dim3(kFarBlock), 0, fb.stream,
                        (const FarReq<R> *)fb.reqs, (const int4 *)fb.items + fb.first[FORM], n, fb.next + FORM);
     HIPCHECK(hipGetLastError());
 }
 
-void far_batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, bool fp32, FarBatch &fb)
+void far_batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, bool fp32, FarBatch &fb,
+                    const std::vector<const int *> &skip)
 {
-    if (fp32) batch_plan<float>(ds, live, fb);
-    else batch_plan<double>(ds, live, fb);
+    if (fp32) batch_plan<float>(ds, live, skip, fb);
+    else batch_plan<double>(ds, live, skip, fb);
 }
 
 void launch_far_batch(FarBatch &fb, bool fp32)

@@ -299,9 +299,12 @@ struct FarBatch {
     void *items = nullptr;
     int *next = nullptr;           // one queue counter per kernel form
     size_t req_cap = 0, item_cap = 0;
-    int first[4] = {0, 0, 0, 0}, nitems[4] = {0, 0, 0, 0};
+    int first[4] = {0, 0, 0, 0}, nitems[4] = {0, 0, 0, 0}, nblocks[4] = {0, 0, 0, 0};
 };
-void far_batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, bool fp32, FarBatch &fb);
+// skip (empty, or one per handle): device stop flags; a request whose flag is
+// set contributes no work (captured iterations keep replaying after it stops)
+void far_batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &live, bool fp32, FarBatch &fb,
+                    const std::vector<const int *> &skip = {});
 void launch_far_batch(FarBatch &fb, bool fp32);
 void far_batch_free(FarBatch &fb);
 // use_far: 0 = near only, 1 = far from per-triangle outputs, 2 = far from d.yfar

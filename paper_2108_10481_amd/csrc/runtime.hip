@@ -704,7 +704,9 @@ struct GraphGmres {
 
 constexpr int kReplay = 8;
 
-static GraphGmres *capture_iteration(DevMesh &d, int m)
+// device state of one handle's captured GMRES (Hessenberg, rotations, stop
+// flag); shared by its own captured iteration and by batched solves
+static GraphGmres *graph_state(DevMesh &d, int m)
 {
     const int n = 2 * d.hm.V;
     std::unique_ptr<GraphGmres> G(new GraphGmres());
@@ -718,15 +720,29 @@ static GraphGmres *capture_iteration(DevMesh &d, int m)
     G->g = (double *)d.alloc(sizeof(double) * (m + 1));
     G->h1 = (double *)d.alloc(sizeof(double) * (m + 1));
     G->h2 = (double *)d.alloc(sizeof(double) * (m + 1));
+    return G.release();
+}
+
+// the handle's Arnoldi step after its far field (as apply_operator without
+// far_product) and the device Givens step, for capture under d.ctl
+static void iteration_tail(DevMesh &d, GraphGmres &G, int use_far)
+{
+    double *Vb = d.kry.basis;
+    apply_after_far(d, Vb, Vb + G.n, PB_APPLY_PRECOND, use_far);
+    kr_graph_iteration_tail(d.stream, G.n, G.m, Vb, G.st, G.H, G.cs, G.sn, G.g, G.h1, G.h2);
+}
+
+static void capture_into(DevMesh &d, GraphGmres &G)
+{
+    const int n = G.n;
     // one eager product first: settles autotuned launch shapes outside the capture
     apply_operator(d, d.kry.basis, d.ztmp, PB_APPLY_PRECOND, nullptr);
     HIPCHECK(hipStreamSynchronize(d.stream));
     double *Vb = d.kry.basis;
-    d.ctl = DevCtl{&G->st->j, &G->st->done, (size_t)n};
+    d.ctl = DevCtl{&G.st->j, &G.st->done, (size_t)n};
     HIPCHECK(hipStreamBeginCapture(d.stream, hipStreamCaptureModeThreadLocal));
     try {
-        apply_operator(d, Vb, Vb + n, PB_APPLY_PRECOND, nullptr);
-        kr_graph_iteration_tail(d.stream, n, m, Vb, G->st, G->H, G->cs, G->sn, G->g, G->h1, G->h2);
+        iteration_tail(d, G, far_product(d, Vb, 0));
         HIPCHECK(hipGetLastError());
     } catch (...) {
         hipGraph_t dead = nullptr;
@@ -736,9 +752,8 @@ static GraphGmres *capture_iteration(DevMesh &d, int m)
         throw;
     }
     d.ctl = DevCtl();
-    HIPCHECK(hipStreamEndCapture(d.stream, &G->graph));
-    HIPCHECK(hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0));
-    return G.release();
+    HIPCHECK(hipStreamEndCapture(d.stream, &G.graph));
+    HIPCHECK(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
 }
 
 void destroy_graphs(DevMesh &d)
@@ -747,6 +762,26 @@ void destroy_graphs(DevMesh &d)
         delete g;
         g = nullptr;
     }
+}
+
+// x = V y after k captured iterations: the triangular solve on the device's
+// Hessenberg matrix and rotated right-hand side, on the host
+static void graph_solution(DevMesh &d, GraphGmres &G, int k, double *x)
+{
+    const int n = G.n, m = G.m;
+    hipStream_t s = d.stream;
+    std::vector<double> H((size_t)(m + 1) * k), g(k + 1), y(k);
+    HIPCHECK(hipMemcpyAsync(H.data(), G.H, sizeof(double) * H.size(), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(g.data(), G.g, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (int i = k - 1; i >= 0; --i) {
+        double a = g[i];
+        for (int l = i + 1; l < k; ++l) a -= H[(size_t)l * (m + 1) + i] * y[l];
+        y[i] = a / H[(size_t)i * (m + 1) + i];
+    }
+    HIPCHECK(hipMemcpyAsync(d.kry.y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    kr_combine(s, n, k, d.kry.basis, n, d.kry.y, x);
+    HIPCHECK(hipStreamSynchronize(s));   // y is a host vector
 }
 
 static int gmres_graph(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est)
@@ -772,7 +807,8 @@ static int gmres_graph(DevMesh &d, const double *pb, double *x, double tol, int 
         return 0;
     }
     kr_scale_copy(s, n, pb, 1.0 / beta, d.kry.basis);
-    if (!G) G = capture_iteration(d, m);
+    if (!G) G = graph_state(d, m);
+    if (!G->exec) capture_into(d, *G);
     GState h0{};
     h0.j = 0;
     h0.done = 0;
@@ -790,20 +826,9 @@ static int gmres_graph(DevMesh &d, const double *pb, double *x, double tol, int 
         HIPCHECK(hipStreamSynchronize(s));
         if (hs.done || hs.j >= m) break;
     }
-    const int k = hs.j;
-    std::vector<double> H((size_t)(m + 1) * k), g(k + 1), y(k);
-    HIPCHECK(hipMemcpyAsync(H.data(), G->H, sizeof(double) * H.size(), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(g.data(), G->g, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    for (int i = k - 1; i >= 0; --i) {
-        double a = g[i];
-        for (int l = i + 1; l < k; ++l) a -= H[(size_t)l * (m + 1) + i] * y[l];
-        y[i] = a / H[(size_t)i * (m + 1) + i];
-    }
-    HIPCHECK(hipMemcpyAsync(d.kry.y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-    kr_combine(s, n, k, d.kry.basis, n, d.kry.y, x);
+    graph_solution(d, *G, hs.j, x);
     *est = hs.res / beta;
-    return k;
+    return hs.j;
 }
 
 // captured iterations unless profiling the operator kernels (their events
@@ -910,6 +935,113 @@ static void gmres_batch(const std::vector<DevMesh *> &ds, hipStream_t s, bool fp
     }
 }
 
+// The same lockstep with the whole iteration of every request captured once
+// into one HIP graph: each request's source weights, the fused far-field
+// launches, then each request's finish, near field, preconditioner, CGS2 and
+// device Givens step under its own stop flag, replayed kReplay times between
+// checks.  A request's kernels are those of its own captured iteration
+// (gmres_graph) with k_far replaced by its items of k_far_batch, so the
+// results are bitwise those of its solve; once its flag is set its kernels
+// and far-field items do nothing.
+static void gmres_batch_graph(const std::vector<DevMesh *> &ds, hipStream_t s, bool fp32, std::vector<int> &its,
+                              std::vector<double> &est)
+{
+    const int R = (int)ds.size();
+    std::vector<int> n(R), m(R), live;
+    std::vector<double> beta2(R, 0.0), beta(R, 0.0);
+    std::vector<GraphGmres *> G(R, nullptr);
+    its.assign(R, 0);
+    est.assign(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+        DevMesh &d = *ds[r];
+        n[r] = 2 * d.hm.V;
+        m[r] = std::min(d.opt.max_iter, n[r]);
+        ensure_krylov(d, m[r]);
+        kr_dots(s, n[r], 1, d.ytmp, n[r], d.ytmp, d.red1);
+        HIPCHECK(hipMemcpyAsync(&beta2[r], d.red1, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    std::vector<GState> h0(R);
+    std::vector<std::vector<double>> g0(R);
+    for (int r = 0; r < R; ++r) {
+        DevMesh &d = *ds[r];
+        beta[r] = std::sqrt(beta2[r]);
+        if (!(beta[r] > 0.0)) {
+            HIPCHECK(hipMemsetAsync(d.u, 0, sizeof(double) * n[r], s));
+            continue;
+        }
+        kr_scale_copy(s, n[r], d.ytmp, 1.0 / beta[r], d.kry.basis);
+        GraphGmres *&g = d.gg[d.dense ? d.dense->level : 1];
+        if (g && (g->m != m[r] || g->basis != d.kry.basis)) {
+            delete g;
+            g = nullptr;
+        }
+        if (!g) g = graph_state(d, m[r]);
+        G[r] = g;
+        h0[r] = GState{};
+        h0[r].m = m[r];
+        h0[r].tolb = d.opt.tol * beta[r];
+        h0[r].res = beta[r];
+        g0[r].assign(m[r] + 1, 0.0);
+        g0[r][0] = beta[r];
+        HIPCHECK(hipMemcpyAsync(g->st, &h0[r], sizeof(GState), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(g->g, g0[r].data(), sizeof(double) * (m[r] + 1), hipMemcpyHostToDevice, s));
+        live.push_back(r);
+    }
+    HIPCHECK(hipStreamSynchronize(s));   // h0, g0 are host vectors
+    if (live.empty()) return;
+    FarBatch fb;
+    fb.stream = s;
+    struct Free {
+        FarBatch &fb;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~Free()
+        {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            far_batch_free(fb);
+        }
+    } res{fb};
+    std::vector<const int *> skip(R, nullptr);
+    for (int r : live) skip[r] = &G[r]->st->done;
+    far_batch_plan(ds, live, fp32, fb, skip);
+    for (int r : live) ds[r]->ctl = DevCtl{&G[r]->st->j, &G[r]->st->done, (size_t)n[r]};
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int r : live) launch_source_prep(*ds[r], ds[r]->kry.basis, fp32);
+        launch_far_batch(fb, fp32);
+        for (int r : live) {
+            launch_far_finish(*ds[r], fp32);
+            iteration_tail(*ds[r], *G[r], 1);
+        }
+        HIPCHECK(hipGetLastError());
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(s, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        for (int r : live) ds[r]->ctl = DevCtl();
+        throw;
+    }
+    for (int r : live) ds[r]->ctl = DevCtl();
+    HIPCHECK(hipStreamEndCapture(s, &res.graph));
+    HIPCHECK(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+    std::vector<GState> hs(R);
+    for (;;) {
+        for (int k = 0; k < kReplay; ++k) HIPCHECK(hipGraphLaunch(res.exec, s));
+        for (int r : live) HIPCHECK(hipMemcpyAsync(&hs[r], G[r]->st, sizeof(GState), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        bool all = true;
+        for (int r : live) all = all && (hs[r].done || hs[r].j >= m[r]);
+        if (all) break;
+    }
+    for (int r : live) {
+        graph_solution(*ds[r], *G[r], hs[r].j, ds[r]->u);
+        its[r] = hs[r].j;
+        est[r] = hs[r].res / beta[r];
+    }
+}
+
 // Solves one charge set per handle with the far-field products of all of
 // them fused (gmres_batch), everything on the first handle's stream; the
 // handles' own streams are drained first and restored afterwards.
@@ -954,7 +1086,10 @@ static pb_status solve_batch(const std::vector<DevMesh *> &ds, const pb_charges 
     const double t2 = now();
     std::vector<int> its;
     std::vector<double> est;
-    gmres_batch(ds, s, ds[0]->prm.precision == PB_FP32, its, est);
+    const bool fp32 = ds[0]->prm.precision == PB_FP32;
+    // captured iterations unless timing the fused launches or eager launches are asked for
+    if (ds[0]->opt.use_graph && !ds[0]->prof.on(0)) gmres_batch_graph(ds, s, fp32, its, est);
+    else gmres_batch(ds, s, fp32, its, est);
     const double t_gmres = now() - t2;
     pb_status worst = PB_OK;
     for (int r = 0; r < R; ++r) {
