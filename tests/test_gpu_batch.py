@@ -30,10 +30,11 @@ def _requests():
     ]
 
 
-def _handles(reqs, precision, mode=None):
+def _handles(reqs, precision, mode=None, use_graph=1):
     mode = pbm.PB_MATRIX_FREE if mode is None else mode
     return [pbm.MeshHandle(m.xyz, m.tri, pbm.pb_default_options(formulation=f, preconditioner=p,
-                                                                precision=precision, operator_mode=mode))
+                                                                precision=precision, operator_mode=mode,
+                                                                use_graph=use_graph))
             for m, _, f, p in reqs]
 
 
@@ -66,6 +67,21 @@ def test_batch_equals_single_solves(precision):
         ref = oracle.solve(m, c, formulation=oracle.DIRECT)
         assert abs(batch[0]["dG"] - ref["dG"]) < 1e-6 * abs(ref["dG"])
         assert batch[0]["iterations"] == ref["iterations"]
+
+
+def test_batch_eager_lockstep_equals_single_solves():
+    """With use_graph = 0 the lockstep runs eagerly (host Givens, one
+    synchronisation per iteration): still bitwise the single solves."""
+    reqs = _requests()
+    hs = _handles(reqs, pbm.PB_FP32, use_graph=0)
+    try:
+        single = [pbm.pb_mesh_solve(h, c.xyz, c.q) for h, (_, c, _, _) in zip(hs, reqs)]
+        batch = pbm.pb_solve_batch(hs, [(c.xyz, c.q) for _, c, _, _ in reqs])
+        for a, b in zip(batch, single):
+            _same(a, b)
+    finally:
+        for h in hs:
+            h.close()
 
 
 def test_batch_degenerate_requests():
