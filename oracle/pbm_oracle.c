@@ -395,12 +395,16 @@ static void block_hyper(const otri *t, const otri *s, double kappa, const double
 /* ---------------------------------------------------------- operator rows */
 
 /* vertex -> incident triangles (plain O(T) scan) */
-static int incident(const int32_t *tri, int nt, int v, int *out, int cap)
+/* triangles incident to vertex v; out NULL: count only */
+static int incident(const int32_t *tri, int nt, int v, int *out)
 {
     int n = 0;
     for (int t = 0; t < nt; ++t)
         for (int k = 0; k < 3; ++k)
-            if (tri[3 * t + k] == v && n < cap) out[n++] = t;
+            if (tri[3 * t + k] == v) {
+                if (out) out[n] = t;
+                ++n;
+            }
     return n;
 }
 
@@ -418,8 +422,9 @@ void orc_operator_rows(int nv, int nt, const double *xyz, const int32_t *tri, do
 #pragma omp parallel for schedule(dynamic, 1)
     for (int r = 0; r < nrows; ++r) {
         int i = rows[r];
-        int inc[64];
-        int ni = incident(tri, nt, i, inc, 64);
+        const int ni = incident(tri, nt, i, NULL);
+        int *inc = (int *)malloc(sizeof(int) * (ni > 0 ? ni : 1));
+        incident(tri, nt, i, inc);
         if (outV) memset(outV + (size_t)r * nv, 0, sizeof(double) * nv);
         if (outK) memset(outK + (size_t)r * nv, 0, sizeof(double) * nv);
         if (outD) memset(outD + (size_t)r * nv, 0, sizeof(double) * nv);
@@ -447,6 +452,7 @@ void orc_operator_rows(int nv, int nt, const double *xyz, const int32_t *tri, do
                 }
             }
         }
+        free(inc);
     }
 }
 
