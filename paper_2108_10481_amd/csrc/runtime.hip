@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dense.h"
+#include "trace.h"
 
 namespace pbm {
 
@@ -345,6 +346,14 @@ static void device_setup(DevMesh &d)
     }
 }
 
+// the setup phase (geometry, near field, assembly) run to completion
+static void setup_and_wait(DevMesh &d)
+{
+    TraceRange range("pb.setup");
+    device_setup(d);
+    HIPCHECK(hipStreamSynchronize(d.stream));
+}
+
 static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCache *cache = nullptr)
 {
     check_options(opt);
@@ -433,8 +442,7 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
     d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
                     (opt->operator_mode == PB_AUTO &&
                      dense_fits(*d, calderon_separate(*d) && !opt->calderon_fast ? 2 : 1));
-    device_setup(*d);
-    HIPCHECK(hipStreamSynchronize(d->stream));
+    setup_and_wait(*d);
     d->t_setup = now() - t0;
     return d.release();
 }
@@ -1047,6 +1055,7 @@ static void gmres_batch_graph(const std::vector<DevMesh *> &ds, hipStream_t s, b
 // handles' own streams are drained first and restored afterwards.
 static pb_status solve_batch(const std::vector<DevMesh *> &ds, const pb_charges *ch, pb_result *res)
 {
+    TraceRange batch_range("pb.batch");
     const int R = (int)ds.size();
     hipStream_t s = ds[0]->stream;
     std::vector<hipStream_t> keep(R);
@@ -1065,6 +1074,7 @@ static pb_status solve_batch(const std::vector<DevMesh *> &ds, const pb_charges 
     for (DevMesh *d : ds) d->stream = s;
     std::vector<double> t_rhs(R), t_prec(R);
     for (int r = 0; r < R; ++r) {
+        TraceRange range("pb.rhs+precond");
         DevMesh &d = *ds[r];
         const double t0 = now();
         try {
@@ -1087,9 +1097,12 @@ static pb_status solve_batch(const std::vector<DevMesh *> &ds, const pb_charges 
     std::vector<int> its;
     std::vector<double> est;
     const bool fp32 = ds[0]->prm.precision == PB_FP32;
-    // captured iterations unless timing the fused launches or eager launches are asked for
-    if (ds[0]->opt.use_graph && !ds[0]->prof.on(0)) gmres_batch_graph(ds, s, fp32, its, est);
-    else gmres_batch(ds, s, fp32, its, est);
+    {
+        TraceRange range("pb.gmres");
+        // captured iterations unless timing the fused launches or eager launches are asked for
+        if (ds[0]->opt.use_graph && !ds[0]->prof.on(0)) gmres_batch_graph(ds, s, fp32, its, est);
+        else gmres_batch(ds, s, fp32, its, est);
+    }
     const double t_gmres = now() - t2;
     pb_status worst = PB_OK;
     for (int r = 0; r < R; ++r) {
@@ -1180,6 +1193,7 @@ static void rhs_device(DevMesh &d, int nq, double *b)
 pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, double *u, int its, int outer,
                         double t_rhs, double t_prec, double t_gmres, pb_result *res)
 {
+    TraceRange range("pb.dG");
     const int V = d.hm.V, n = 2 * V;
     const double t3 = now();
         apply_operator(d, u, d.ztmp, PB_APPLY_PRECOND, nullptr);
@@ -1216,27 +1230,37 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
 {
     if (!res) fail(PB_E_INVALID_ARG, "result must not be NULL");
     const int V = d.hm.V, n = 2 * V;
+    TraceRange solve_range("pb.solve");
     double t0 = now();
-    charges_to_device(d, ch);
-    const int nq = ch->n;
-    check_charges_inside(d, nq);
     double *b = d.xtmp, *pb = d.ytmp;
-    formulation_rhs(d, nq, d.qbuf, b);
-    HIPCHECK(hipStreamSynchronize(d.stream));
+    {
+        TraceRange range("pb.rhs");
+        charges_to_device(d, ch);
+        const int nq = ch->n;
+        check_charges_inside(d, nq);
+        formulation_rhs(d, nq, d.qbuf, b);
+        HIPCHECK(hipStreamSynchronize(d.stream));
+    }
     double t1 = now();
-    if (mass_mode(d)) mass_precond(d, 1, b, pb, DevCtl());
-    else if (calderon_mode(d)) calderon_left(d, b, pb, DevCtl());
-    else kr_precond(d.stream, V, d.pinv, b, pb);
-    HIPCHECK(hipStreamSynchronize(d.stream));
+    {
+        TraceRange range("pb.precond");
+        if (mass_mode(d)) mass_precond(d, 1, b, pb, DevCtl());
+        else if (calderon_mode(d)) calderon_left(d, b, pb, DevCtl());
+        else kr_precond(d.stream, V, d.pinv, b, pb);
+        HIPCHECK(hipStreamSynchronize(d.stream));
+    }
     double t2 = now();
     if (!d.u) d.u = (double *)d.alloc(sizeof(double) * n);
     double est = 0.0;
     int outer = 1, its;
-    if (d.prm.precision >= PB_MIXED_BF16)
-        its = mixed_refinement_solve(d, b, pb, d.u, &est, &outer);
-    else
-        its = gmres_solve(d, pb, d.u, d.opt.tol, d.opt.max_iter, &est);
-    HIPCHECK(hipStreamSynchronize(d.stream));
+    {
+        TraceRange range("pb.gmres");
+        if (d.prm.precision >= PB_MIXED_BF16)
+            its = mixed_refinement_solve(d, b, pb, d.u, &est, &outer);
+        else
+            its = gmres_solve(d, pb, d.u, d.opt.tol, d.opt.max_iter, &est);
+        HIPCHECK(hipStreamSynchronize(d.stream));
+    }
     double t3 = now();
     return finish_result(d, ch, pb, d.u, its, outer, t1 - t0, t2 - t1, t3 - t2, res);
 }
@@ -1344,8 +1368,7 @@ pb_status pb_mesh_refresh(pb_mesh_handle *h)
     if (!h) fail(PB_E_INVALID_ARG, "NULL handle");
     DevMesh &d = *h->d;
     const double t0 = now();
-    device_setup(d);
-    HIPCHECK(hipStreamSynchronize(d.stream));
+    setup_and_wait(d);
     d.t_setup = now() - t0;
     return PB_OK;
     PB_CATCH
