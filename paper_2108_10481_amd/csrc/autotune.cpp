@@ -53,7 +53,10 @@ int autotune_pick(const std::string &key, int nvariants, const std::function<voi
         std::lock_guard<std::mutex> lk(g_mu);
         load_file();
         auto it = g_cache.find(key);
-        if (it != g_cache.end() && it->second >= 0 && it->second < nvariants) return it->second;
+        if (it != g_cache.end()) {
+            if (it->second >= 0 && it->second < nvariants) return it->second;
+            g_cache.erase(it);   // a stale or corrupt file entry: time the variants again
+        }
     }
     hipEvent_t a, b;
     HIPCHECK(hipEventCreate(&a));
