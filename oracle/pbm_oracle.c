@@ -17,6 +17,9 @@
  *     rule for pairs sharing no vertex and Sauter-Schwab singular quadrature
  *     for pairs sharing a vertex, an edge, or the whole triangle
  *     (Numerical discretization: continuous P1 Galerkin on flat triangles);
+ *     the local vertex arrangement of a singular pair is found by searching
+ *     the rotations and arrangements of the two triangles for the stated
+ *     property;
  *   - the hypersingular D block from the integration-by-parts identity
  *     D = curl.curl G + kappa^2 (n_x . n_y) G;
  *   - rows (or columns) of V, K, D and of the mass matrix M;
@@ -228,128 +231,153 @@ static void block_centroid(const otri *t, const otri *s, double kappa, int mode,
 
 /* ------------------------------------------ Sauter-Schwab singular quadrature
  *
- * Reference triangle {0 <= u2 <= u1 <= 1}; chi(u) = P0 + u1 (P1 - P0) + u2 (P2 - P1),
- * barycentric coordinates of (P0, P1, P2) are (1-u1, u1-u2, u2), and the surface
- * element is 2|T| du.  The local vertices of both triangles are reordered so
- * that shared vertices come first:
- *   coincident : both triangles in their stored order;
- *   edge       : the test triangle is rotated cyclically so that the shared
- *                edge occupies positions (0,1) in its own orientation, and the
- *                trial triangle is arranged with the same two vertices in the
- *                same order, its free vertex last;
- *   vertex     : both triangles rotated cyclically so the shared vertex is first.
- * Normals are always the stored (outward) triangle normals.
- * Each case splits [0,1]^4 (variables xi, e1, e2, e3) into regions mapped onto
- * the reference pair with a Jacobian that cancels the 1/r singularity
- * (S. Sauter and C. Schwab, Boundary Element Methods, Springer 2011, sec. 5.2). */
+ * (S. Sauter and C. Schwab, Boundary Element Methods, Springer 2011, sec. 5.2.)
+ * Reference triangle {0 <= xh2 <= xh1 <= 1} with chi(xh) = A0 + xh1 (A1 - A0)
+ * + xh2 (A2 - A1) for the arranged vertices (A0, A1, A2); the hats of A0, A1, A2
+ * are (1 - xh1, xh1 - xh2, xh2) there and the surface element is 2|T| dxh.
+ *
+ * Arrangement of the two triangles (the reading used throughout): the vertices
+ * both triangles share come first and in the same order on both, the free ones
+ * after them; the test triangle is only rotated (its leading shared vertices
+ * follow its own counter-clockwise order), the trial triangle is arranged to
+ * match.  Two identical triangles keep their stored order.  Normals are always
+ * the stored outward ones, whatever the arrangement.
+ *
+ * Each case splits the unit hypercube of (xi, eta1, eta2, eta3) into regions;
+ * region r maps onto a pair of reference points xh = xi (X1, X2) and
+ * yh = xi (Y1, Y2) with the Jacobian xi^3 J(eta), which cancels the 1/r
+ * singularity at the shared set. */
 
-typedef struct { double u1, u2, v1, v2, jac; } ssmap;
+/* The three cyclic rotations first, then the three reflections. */
+static const int arrangement[6][3] = {{0, 1, 2}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {2, 1, 0}, {1, 0, 2}};
 
-static int ss_coincident(int r, double xi, double a, double b, double c, ssmap *m)
+static int slot_of(const otri *o, int vertex)
 {
-    m->jac = xi * xi * xi * a * a * b;
-    switch (r) {
-    case 0: m->u1 = xi; m->u2 = xi * (1 - a + a * b); m->v1 = xi * (1 - a * b * c); m->v2 = xi * (1 - a); break;
-    case 1: m->u1 = xi * (1 - a * b * c); m->u2 = xi * (1 - a); m->v1 = xi; m->v2 = xi * (1 - a + a * b); break;
-    case 2: m->u1 = xi; m->u2 = xi * a * (1 - b + b * c); m->v1 = xi * (1 - a * b); m->v2 = xi * a * (1 - b); break;
-    case 3: m->u1 = xi * (1 - a * b); m->u2 = xi * a * (1 - b); m->v1 = xi; m->v2 = xi * a * (1 - b + b * c); break;
-    case 4: m->u1 = xi * (1 - a * b * c); m->u2 = xi * a * (1 - b * c); m->v1 = xi; m->v2 = xi * a * (1 - b); break;
-    default: m->u1 = xi; m->u2 = xi * a * (1 - b); m->v1 = xi * (1 - a * b * c); m->v2 = xi * a * (1 - b * c); break;
-    }
-    return 0;
-}
-
-static int ss_edge(int r, double xi, double a, double b, double c, ssmap *m)
-{
-    if (r == 0) {
-        m->jac = xi * xi * xi * a * a;
-        m->u1 = xi; m->u2 = xi * a * c; m->v1 = xi * (1 - a * b); m->v2 = xi * a * (1 - b);
-        return 0;
-    }
-    m->jac = xi * xi * xi * a * a * b;
-    switch (r) {
-    case 1: m->u1 = xi; m->u2 = xi * a; m->v1 = xi * (1 - a * b * c); m->v2 = xi * a * b * (1 - c); break;
-    case 2: m->u1 = xi * (1 - a * b); m->u2 = xi * a * (1 - b); m->v1 = xi; m->v2 = xi * a * b * c; break;
-    case 3: m->u1 = xi * (1 - a * b * c); m->u2 = xi * a * b * (1 - c); m->v1 = xi; m->v2 = xi * a; break;
-    default: m->u1 = xi * (1 - a * b * c); m->u2 = xi * a * (1 - b * c); m->v1 = xi; m->v2 = xi * a * b; break;
-    }
-    return 0;
-}
-
-static int ss_vertex(int r, double xi, double a, double b, double c, ssmap *m)
-{
-    m->jac = xi * xi * xi * b;
-    if (r == 0) { m->u1 = xi; m->u2 = xi * a; m->v1 = xi * b; m->v2 = xi * b * c; }
-    else        { m->u1 = xi * b; m->u2 = xi * b * c; m->v1 = xi; m->v2 = xi * a; }
-    return 0;
-}
-
-/* local vertex order for the singular cases; returns the number of shared vertices */
-static int pair_order(const otri *t, const otri *s, int same, int pt[3], int ps[3])
-{
-    for (int k = 0; k < 3; ++k) pt[k] = ps[k] = k;
-    if (same) return 3;
-    int ns = 0, kt[3], ks[3];
     for (int k = 0; k < 3; ++k)
-        for (int l = 0; l < 3; ++l)
-            if (t->v[k] == s->v[l]) { kt[ns] = k; ks[ns] = l; ++ns; }
-    if (ns == 2) {
-        int k0 = kt[0], k1 = kt[1];
-        /* shared edge in the test triangle's cyclic order: k0 -> k1 */
-        if ((k0 + 1) % 3 != k1) { int tmp = k0; k0 = k1; k1 = tmp; }
-        pt[0] = k0; pt[1] = k1; pt[2] = 3 - k0 - k1;
-        for (int l = 0; l < 3; ++l) {
-            if (s->v[l] == t->v[k0]) ps[0] = l;
-            if (s->v[l] == t->v[k1]) ps[1] = l;
+        if (o->v[k] == vertex) return k;
+    return -1;
+}
+
+/* The arrangement above, found by search: the first rotation of the test
+ * triangle whose leading vertices are all shared, then the first arrangement
+ * of the trial triangle (a rotation when one vertex is shared) that starts
+ * with the same shared vertices in the same order.  Returns the number of
+ * shared vertices; at[m] / as[m] = stored slot of arranged vertex m. */
+static int arrange_pair(const otri *t, const otri *s, int same, int at[3], int as[3])
+{
+    int common = 0;
+    for (int k = 0; k < 3; ++k) common += slot_of(s, t->v[k]) >= 0;
+    if (same) common = 3;
+    for (int m = 0; m < 3; ++m) at[m] = as[m] = m;
+    if (common == 0 || common == 3) return common;
+    for (int r = 0; r < 3; ++r) {
+        int lead_shared = 1;
+        for (int m = 0; m < common; ++m) lead_shared &= slot_of(s, t->v[arrangement[r][m]]) >= 0;
+        if (lead_shared) {
+            for (int m = 0; m < 3; ++m) at[m] = arrangement[r][m];
+            break;
         }
-        ps[2] = 3 - ps[0] - ps[1];
-    } else if (ns == 1) {
-        for (int m = 0; m < 3; ++m) { pt[m] = (kt[0] + m) % 3; ps[m] = (ks[0] + m) % 3; }
     }
-    return ns;
+    const int tries = (common == 1) ? 3 : 6;
+    for (int r = 0; r < tries; ++r) {
+        int match = 1;
+        for (int m = 0; m < common; ++m) match &= s->v[arrangement[r][m]] == t->v[at[m]];
+        if (match) {
+            for (int m = 0; m < 3; ++m) as[m] = arrangement[r][m];
+            break;
+        }
+    }
+    return common;
+}
+
+/* Region r of the case with `common` shared vertices at (eta1, eta2, eta3):
+ * fills X, Y (the bracketed factors of xh and yh) and returns J(eta). */
+static double region(int common, int r, double eta1, double eta2, double eta3, double X[2], double Y[2])
+{
+    if (common == 3) {                 /* identical triangles, six regions */
+        switch (r) {
+        case 0: X[0] = 1; X[1] = 1 - eta1 + eta1 * eta2;
+                Y[0] = 1 - eta1 * eta2 * eta3; Y[1] = 1 - eta1; break;
+        case 1: X[0] = 1 - eta1 * eta2 * eta3; X[1] = 1 - eta1;
+                Y[0] = 1; Y[1] = 1 - eta1 + eta1 * eta2; break;
+        case 2: X[0] = 1; X[1] = eta1 * (1 - eta2 + eta2 * eta3);
+                Y[0] = 1 - eta1 * eta2; Y[1] = eta1 * (1 - eta2); break;
+        case 3: X[0] = 1 - eta1 * eta2; X[1] = eta1 * (1 - eta2);
+                Y[0] = 1; Y[1] = eta1 * (1 - eta2 + eta2 * eta3); break;
+        case 4: X[0] = 1 - eta1 * eta2 * eta3; X[1] = eta1 * (1 - eta2 * eta3);
+                Y[0] = 1; Y[1] = eta1 * (1 - eta2); break;
+        default: X[0] = 1; X[1] = eta1 * (1 - eta2);
+                 Y[0] = 1 - eta1 * eta2 * eta3; Y[1] = eta1 * (1 - eta2 * eta3); break;
+        }
+        return eta1 * eta1 * eta2;
+    }
+    if (common == 2) {                 /* shared edge xh2 = 0, five regions */
+        switch (r) {
+        case 0: X[0] = 1; X[1] = eta1 * eta3;
+                Y[0] = 1 - eta1 * eta2; Y[1] = eta1 * (1 - eta2);
+                return eta1 * eta1;
+        case 1: X[0] = 1; X[1] = eta1;
+                Y[0] = 1 - eta1 * eta2 * eta3; Y[1] = eta1 * eta2 * (1 - eta3); break;
+        case 2: X[0] = 1 - eta1 * eta2; X[1] = eta1 * (1 - eta2);
+                Y[0] = 1; Y[1] = eta1 * eta2 * eta3; break;
+        case 3: X[0] = 1 - eta1 * eta2 * eta3; X[1] = eta1 * eta2 * (1 - eta3);
+                Y[0] = 1; Y[1] = eta1; break;
+        default: X[0] = 1 - eta1 * eta2 * eta3; X[1] = eta1 * (1 - eta2 * eta3);
+                 Y[0] = 1; Y[1] = eta1 * eta2; break;
+        }
+        return eta1 * eta1 * eta2;
+    }
+    /* shared vertex xh = 0, two regions */
+    if (r == 0) { X[0] = 1; X[1] = eta1; Y[0] = eta2; Y[1] = eta2 * eta3; }
+    else        { X[0] = eta2; X[1] = eta2 * eta3; Y[0] = 1; Y[1] = eta1; }
+    return eta2;
 }
 
 static void block_singular(const otri *t, const otri *s, int same, double kappa, int mode,
                            int nss, double *V, double *K)
 {
-    int pt[3], ps[3];
-    int ns = pair_order(t, s, same, pt, ps);
+    int at[3], as[3];
+    const int common = arrange_pair(t, s, same, at, as);
+    const int nregions = (common == 3) ? 6 : (common == 2) ? 5 : 2;
     double gx[64], gw[64];
     orc_gauss_legendre01(nss, gx, gw);
-    int nreg = (ns == 3) ? 6 : (ns == 2) ? 5 : 2;
-    double P[3][3], Q[3][3];
+    double A[3][3], B[3][3];           /* arranged vertices of the test / trial triangle */
     for (int m = 0; m < 3; ++m)
-        for (int c = 0; c < 3; ++c) { P[m][c] = t->p[pt[m]][c]; Q[m][c] = s->p[ps[m]][c]; }
-    double accV[9] = {0}, accK[9] = {0};
-    for (int r = 0; r < nreg; ++r)
-        for (int i0 = 0; i0 < nss; ++i0)
-            for (int i1 = 0; i1 < nss; ++i1)
-                for (int i2 = 0; i2 < nss; ++i2)
-                    for (int i3 = 0; i3 < nss; ++i3) {
-                        ssmap m;
-                        double xi = gx[i0], a = gx[i1], b = gx[i2], c = gx[i3];
-                        if (ns == 3) ss_coincident(r, xi, a, b, c, &m);
-                        else if (ns == 2) ss_edge(r, xi, a, b, c, &m);
-                        else ss_vertex(r, xi, a, b, c, &m);
-                        double W = gw[i0] * gw[i1] * gw[i2] * gw[i3] * m.jac;
-                        double lx[3] = {1.0 - m.u1, m.u1 - m.u2, m.u2};
-                        double ly[3] = {1.0 - m.v1, m.v1 - m.v2, m.v2};
+        for (int c = 0; c < 3; ++c) { A[m][c] = t->p[at[m]][c]; B[m][c] = s->p[as[m]][c]; }
+    double sumV[3][3] = {{0}}, sumK[3][3] = {{0}};   /* indexed by arranged vertices */
+    for (int r = 0; r < nregions; ++r)
+        for (int i = 0; i < nss; ++i)
+            for (int j = 0; j < nss; ++j)
+                for (int k = 0; k < nss; ++k)
+                    for (int l = 0; l < nss; ++l) {
+                        const double xi = gx[i];
+                        double X[2], Y[2];
+                        const double J = region(common, r, gx[j], gx[k], gx[l], X, Y);
+                        const double wt = gw[i] * gw[j] * gw[k] * gw[l] * xi * xi * xi * J;
+                        const double xh1 = xi * X[0], xh2 = xi * X[1];
+                        const double yh1 = xi * Y[0], yh2 = xi * Y[1];
+                        const double hx[3] = {1.0 - xh1, xh1 - xh2, xh2};
+                        const double hy[3] = {1.0 - yh1, yh1 - yh2, yh2};
                         double x[3], y[3];
-                        for (int cc = 0; cc < 3; ++cc) {
-                            x[cc] = P[0][cc] + m.u1 * (P[1][cc] - P[0][cc]) + m.u2 * (P[2][cc] - P[1][cc]);
-                            y[cc] = Q[0][cc] + m.v1 * (Q[1][cc] - Q[0][cc]) + m.v2 * (Q[2][cc] - Q[1][cc]);
+                        for (int c = 0; c < 3; ++c) {
+                            x[c] = hx[0] * A[0][c] + hx[1] * A[1][c] + hx[2] * A[2][c];
+                            y[c] = hy[0] * B[0][c] + hy[1] * B[1][c] + hy[2] * B[2][c];
                         }
                         double g, d;
                         kern(mode, x, y, s->n, kappa, &g, &d);
-                        for (int k = 0; k < 3; ++k)
-                            for (int l = 0; l < 3; ++l) {
-                                double bb = W * lx[k] * ly[l];
-                                accV[3 * pt[k] + ps[l]] += bb * g;
-                                accK[3 * pt[k] + ps[l]] += bb * d;
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) {
+                                sumV[a][b] += wt * hx[a] * hy[b] * g;
+                                sumK[a][b] += wt * hx[a] * hy[b] * d;
                             }
                     }
-    double scale = 4.0 * t->area * s->area;
-    for (int i = 0; i < 9; ++i) { V[i] = accV[i] * scale; K[i] = accK[i] * scale; }
+    /* (2|t|)(2|s|) surface elements; arranged vertex a of t is stored slot at[a] */
+    const double jac = 4.0 * t->area * s->area;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            V[3 * at[a] + as[b]] = jac * sumV[a][b];
+            K[3 * at[a] + as[b]] = jac * sumK[a][b];
+        }
 }
 
 /* Local blocks of the ordered pair (test t, trial s):
