@@ -17,6 +17,9 @@ here is synthetic with the same shape statistics:
                        r(theta, phi) = R (1 + 0.15 f), f a random sum of real
                        spherical harmonics of degree <= 6 with coefficients
                        N(0,1)/(l+1): a smooth, star-shaped, protein-like blob.
+* ``bipyramid``      - two cones over a regular n-gon: two apexes of valence n
+                       and 2n skinny triangles (apex angle 2 pi / n), a
+                       stress case for vertex valence and aspect ratio.
 * ``charges_*``      - charges strictly inside the surface.
 """
 from __future__ import annotations
@@ -29,7 +32,7 @@ import numpy as np
 __all__ = [
     "Mesh", "Charges", "icosphere", "star_surface", "charges_ball",
     "charges_in_star", "config_kirkwood", "config_sphere", "config_star",
-    "config_sphere_multi", "serving_trace",
+    "config_sphere_multi", "serving_trace", "bipyramid",
 ]
 
 
@@ -194,6 +197,19 @@ class StarShape:
 
     def radius(self, u: np.ndarray) -> np.ndarray:
         return self.base_radius * (1.0 + self.amp * self._f(u))
+
+
+def bipyramid(n: int, radius: float = 1.0, height: float = 1.0) -> Mesh:
+    """Closed bipyramid over a regular n-gon of the given radius in the plane
+    z = 0, apexes at z = +-height; counter-clockwise seen from outside."""
+    ang = 2.0 * math.pi * np.arange(n) / n
+    ring = np.stack([radius * np.cos(ang), radius * np.sin(ang), np.zeros(n)], axis=1)
+    xyz = np.vstack([ring, [[0.0, 0.0, height], [0.0, 0.0, -height]]])
+    tri = []
+    for i in range(n):
+        j = (i + 1) % n
+        tri += [[i, j, n], [j, i, n + 1]]
+    return Mesh(xyz, np.array(tri, dtype=np.int32), {"kind": "bipyramid", "n": int(n)})
 
 
 def star_surface(seed: int, freq: int, base_radius: float = 18.0) -> tuple:

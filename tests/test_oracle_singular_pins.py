@@ -76,25 +76,12 @@ def test_singular_blocks_match_closed_form(skew_pairs):
             assert ek[-1] < 1e-13
 
 
-def _bipyramid(n, radius=1.0, height=1.0):
-    """Closed bipyramid over an n-gon: two apexes of valence n, 2n skinny
-    triangles (apex angle 2 pi / n), counter-clockwise seen from outside."""
-    ang = 2 * np.pi * np.arange(n) / n
-    ring = np.stack([radius * np.cos(ang), radius * np.sin(ang), 0 * ang], 1)
-    xyz = np.vstack([ring, [[0, 0, height], [0, 0, -height]]])
-    tri = []
-    for i in range(n):
-        j = (i + 1) % n
-        tri += [[i, j, n], [j, i, n + 1]]
-    return _Mesh(xyz, tri)
-
-
 def test_skinny_high_valence_pairs_converge():
     """Valence-80 apexes: triangles of aspect ratio about 25 sharing the apex,
     a spoke edge (coplanar neighbours) or a ring edge (sharp fold).  The rule
     converges more slowly on such pairs, but to the independently computed
     integral."""
-    m = _bipyramid(80)
+    m = inputs.bipyramid(80)
     cases = {(0, 0): 3, (0, 2): 2, (0, 1): 2, (0, 10): 1, (0, 3): 1, (1, 3): 2}
     for (t, s), k in cases.items():
         Vr, Kr = laplace_blocks(m.xyz[m.tri[t]], m.xyz[m.tri[s]], step=1.0 / 32)
