@@ -20,7 +20,8 @@
  *
  * Conventions for every entry point:
  *   - Units: angstrom, elementary charge, 1/angstrom; Delta G in kcal/mol.
- *   - Unless a name ends in _device, pointer arguments are HOST pointers.
+ *   - Unless a name ends in _device or _noalloc, pointer arguments are HOST
+ *     pointers.
  *     Inputs are read-only and copied during the call; the caller keeps
  *     ownership.  Output arrays are caller-allocated with the stated length.
  *   - Handles are owned by the library: every *_create has a *_destroy.
@@ -273,6 +274,24 @@ pb_status pb_mesh_rhs(pb_mesh_handle *h, const pb_charges *charges, double *b);
  * dphi (host, n_vertices each); out: npts doubles. */
 pb_status pb_mesh_reaction_potential(pb_mesh_handle *h, const double *phi, const double *dphi,
                                      int32_t npts, const double *pts, double *out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the reaction
+ * potential of pb_mesh_reaction_potential on device arrays, allocating nothing.
+ * traces_device: 2 n_vertices doubles [phi; dphi] (the P1 interior traces);
+ * pts_device: npts x 3 doubles (row-major points); out_device: npts doubles.
+ * All three are device pointers owned by the caller.  Runs on hip_stream
+ * (NULL = the handle's stream) and returns without synchronising.
+ * Per-point partial sums over the source chunks (min(1, ceil(T / 4096)) of
+ * them) go to a static device array of 4 MiB (524288 doubles) that each GPU the
+ * library runs on holds until the process ends: npts x chunks above 524288 is
+ * rejected with PB_E_INVALID_ARG (at 81920 triangles, 20 chunks, up to 26214
+ * points).  Every call on one GPU shares that array, so calls that overlap in
+ * time on one GPU (any handles, any streams) race; every call writes all the
+ * partial sums it reads, so nothing needs clearing between calls.  Results
+ * equal pb_mesh_reaction_potential's bit for bit. */
+pb_status pb_mesh_reaction_potential_noalloc(pb_mesh_handle *h, const double *traces_device, int32_t npts,
+                                             const double *pts_device, double *out_device, void *hip_stream);
 
 /* Sauter-Schwab local blocks of near pairs (original triangle ids t[k], s[k],
  * which must share a vertex): out[36 k + 9 op + 3 a + b] with op = 0 V_L,

@@ -114,7 +114,7 @@ EXPORTS = ["pb_default_options", "pb_last_error", "pb_device_count", "pb_solve",
            "pb_mesh_apply_device", "pb_mesh_rhs", "pb_mesh_reaction_potential", "pb_mesh_near_blocks",
            "pb_mesh_preconditioner", "pb_mesh_profile", "pb_mesh_profile_read", "pb_mesh_synchronize",
            "pb_estimate_device_bytes", "pb_server_create", "pb_server_destroy", "pb_submit", "pb_poll", "pb_cancel",
-           "pb_wait", "pb_server_get_stats"]
+           "pb_wait", "pb_server_get_stats", "pb_mesh_reaction_potential_noalloc"]
 
 _lib = None
 
@@ -146,6 +146,7 @@ def load():
     L.pb_mesh_rhs.argtypes = [vp, P(pb_charges), P(ctypes.c_double)]
     L.pb_mesh_reaction_potential.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int32,
                                              P(ctypes.c_double), P(ctypes.c_double)]
+    L.pb_mesh_reaction_potential_noalloc.argtypes = [vp, vp, ctypes.c_int32, vp, vp, vp]
     L.pb_mesh_near_blocks.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32),
                                       P(ctypes.c_double)]
     L.pb_mesh_preconditioner.argtypes = [vp, P(ctypes.c_double)]
@@ -377,6 +378,15 @@ def pb_mesh_reaction_potential(h: MeshHandle, phi, dphi, pts) -> np.ndarray:
     out = np.zeros(pts.shape[0])
     _check(load().pb_mesh_reaction_potential(h.h, _dptr(phi), _dptr(dphi), pts.shape[0], _dptr(pts), _dptr(out)))
     return out
+
+
+def pb_mesh_reaction_potential_noalloc(h: MeshHandle, traces_ptr: int, npts: int, pts_ptr: int, out_ptr: int,
+                                       stream: int = 0) -> None:
+    """Device-pointer variant that allocates nothing: traces_ptr -> 2 V doubles
+    [phi; dphi], pts_ptr -> npts x 3 doubles, out_ptr -> npts doubles."""
+    _check(load().pb_mesh_reaction_potential_noalloc(h.h, ctypes.c_void_p(traces_ptr), int(npts),
+                                                     ctypes.c_void_p(pts_ptr), ctypes.c_void_p(out_ptr),
+                                                     ctypes.c_void_p(stream)))
 
 
 def pb_mesh_near_blocks(h: MeshHandle, t, s) -> np.ndarray:

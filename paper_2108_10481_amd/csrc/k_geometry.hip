@@ -1,5 +1,7 @@
 // Geometry, charge-to-surface projections (Eq. sources), reaction potential
 // (Eq. phireac_bie) and the charge-inside-surface check.
+#include <mutex>
+
 #include "pbm_internal.h"
 
 namespace pbm {
@@ -262,5 +264,62 @@ void launch_inside_test(DevMesh &d, int nq, const double *qpts, double *out_part
 }
 
 int reduction_chunks(int T) { return red_chunks(T); }
+
+// ------------------------------------------- reaction potential, no allocation
+// Partial sums (point x source chunk) of pb_mesh_reaction_potential_noalloc
+// live in this file-scope array: one copy per device, held until the process
+// ends.  Host code never uses the array's name as an address; it uses the
+// device address resolved once per device by noalloc_scratch().
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+static double *noalloc_scratch()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(PB_E_DEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(PB_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[dev] = (double *)p;
+    }
+    return addr[dev];
+}
+
+// out[k] = (sum over chunks c, in order, of part[k C + c]) / (4 pi): the same
+// sum, in the same order, as the host finish of pb_mesh_reaction_potential
+__global__ void k_reaction_finish(int npts, int C, const double *__restrict__ part, double *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npts) return;
+    double s = 0.0;
+    for (int c = 0; c < C; ++c) s += part[(size_t)k * C + c];
+    out[k] = s * kInv4Pi;
+}
+
+void reaction_potential_noalloc(DevMesh &d, const double *traces, int npts, const double *pts, double *out,
+                                hipStream_t stream)
+{
+    const int C = red_chunks(d.hm.T);
+    if ((size_t)npts * (size_t)C > kNoAllocScratchDoubles)
+        fail(PB_E_INVALID_ARG, "npts x source chunks (" + std::to_string((size_t)npts * C) +
+                                   ") exceeds the scratch of " + std::to_string(kNoAllocScratchDoubles) + " doubles");
+    double *part = noalloc_scratch();
+    struct StreamSwap {
+        DevMesh &d;
+        hipStream_t keep;
+        StreamSwap(DevMesh &dm, hipStream_t s) : d(dm), keep(dm.stream) { if (s) d.stream = s; }
+        ~StreamSwap() { d.stream = keep; }
+    } swap(d, stream);
+    launch_source_prep(d, traces, false);
+    launch_reaction(d, npts, pts, part);
+    hipLaunchKernelGGL(k_reaction_finish, dim3((npts + 255) / 256), dim3(256), 0, d.stream, npts, C, part, out);
+    HIPCHECK(hipGetLastError());
+}
 
 }  // namespace pbm

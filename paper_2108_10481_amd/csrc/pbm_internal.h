@@ -344,6 +344,11 @@ pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result 
 void destroy_batch(DevMesh &d);
 void charges_to_device(DevMesh &d, const pb_charges *c);
 void check_charges_inside(DevMesh &d, int nq);
+// reaction potential with its partial sums in the library's static scratch
+// (k_geometry.hip): no allocation; npts x reduction_chunks(T) must fit
+constexpr size_t kNoAllocScratchDoubles = size_t(1) << 19;   // 4 MiB
+void reaction_potential_noalloc(DevMesh &d, const double *traces, int npts, const double *pts, double *out,
+                                hipStream_t stream);
 pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, double *u, int its, int outer,
                         double t_rhs, double t_prec, double t_gmres, pb_result *res);
 

@@ -1477,6 +1477,16 @@ pb_status pb_mesh_reaction_potential(pb_mesh_handle *h, const double *phi, const
     PB_CATCH
 }
 
+pb_status pb_mesh_reaction_potential_noalloc(pb_mesh_handle *h, const double *traces_device, int32_t npts,
+                                             const double *pts_device, double *out_device, void *hip_stream)
+{
+    PB_TRY
+    if (!h || !traces_device || !pts_device || !out_device || npts < 1) fail(PB_E_INVALID_ARG, "bad arguments");
+    reaction_potential_noalloc(*h->d, traces_device, npts, pts_device, out_device, (hipStream_t)hip_stream);
+    return PB_OK;
+    PB_CATCH
+}
+
 pb_status pb_mesh_near_blocks(pb_mesh_handle *h, int32_t n, const int32_t *t, const int32_t *s, double *out)
 {
     PB_TRY
