@@ -69,6 +69,24 @@ typedef int32_t pb_status;
 #define PB_LU           7  /* Eq. bie:lu:ext: second-kind (exterior) */
 #define PB_PMCHWT_INT   8  /* Eq. bie:pmchwt:int: first-kind */
 #define PB_PMCHWT_EXT   9  /* Eq. bie:pmchwt:ext: first-kind (exterior) */
+/* Combined-field formulations with real constants alpha = cfie_alpha, beta =
+ * cfie_beta (The combined field formulation):
+ *   PB_CFIE_INT, Eq. bie:combined:int, interior unknowns:
+ *     [[M/2+K_L, -V_L], [-D_L, M/2-T_L]] + diag(alpha, beta) [[M/2-K_Y, e V_Y], [D_Y/e, M/2+T_Y]],
+ *     right-hand side [phi_D; phi_N];
+ *   PB_CFIE_EXT, Eq. bie:combined:ext, exterior unknowns:
+ *     [[M/2-K_Y, V_Y], [D_Y, M/2+T_Y]] + diag(alpha, beta) [[M/2+K_L, -V_L/e], [-e D_L, M/2-T_L]],
+ *     right-hand side diag(alpha, beta) [phi_D; e phi_N].
+ * alpha = beta = 1 gives Mueller, alpha = beta = -1 PMCHWT (Eq. bie:pmchwt:ext
+ * as printed, Eq. bie:pmchwt:int with the opposite sign), (e_out/e_in,
+ * e_in/e_out) Juffer, and the external form at (e, 1/e) is Lu before its
+ * second row is scaled.  Any
+ * real alpha, beta is accepted; with a zero coefficient in the external form
+ * a block has no Laplace term, which the matrix-free and treecode far fields
+ * handle and the assembled one refuses (PB_E_STATE; PB_AUTO then stays
+ * matrix-free). */
+#define PB_CFIE_INT    10
+#define PB_CFIE_EXT    11
 
 #define PB_PREC_NONE    0
 #define PB_BLOCK_DIAG   1  /* per-vertex 2x2 inverse of the four blocks' diagonals */
@@ -125,7 +143,7 @@ typedef struct {
     double eps_in;            /* interior permittivity (paper: 4) */
     double eps_out;           /* exterior permittivity (paper: 80) */
     double kappa;             /* inverse Debye length, 1/angstrom (paper: 0.125) */
-    int32_t formulation;      /* PB_DIRECT_INT ... PB_PMCHWT_EXT */
+    int32_t formulation;      /* PB_DIRECT_INT ... PB_CFIE_EXT */
     int32_t preconditioner;   /* PB_PREC_NONE ... PB_SCALED_CALDERON_EXT */
     int32_t precision;        /* PB_FP64, PB_FP32, PB_MIXED_BF16, PB_MIXED_FP16 */
     int32_t operator_mode;    /* PB_MATRIX_FREE, PB_ASSEMBLED, PB_AUTO, PB_TREECODE */
@@ -146,6 +164,8 @@ typedef struct {
                                  Gauss points per dimension (at least 1) on pairs sharing one */
     int32_t tree_degree;      /* PB_TREECODE: interpolation degree per dimension, 2..7 (default 6) */
     double tree_theta;        /* PB_TREECODE: separation ratio, 0 < theta < 1 (default 0.7) */
+    double cfie_alpha;        /* PB_CFIE_INT / PB_CFIE_EXT: alpha (default 1) */
+    double cfie_beta;         /* PB_CFIE_INT / PB_CFIE_EXT: beta (default 1) */
 } pb_options;
 
 typedef struct {
@@ -176,7 +196,7 @@ typedef struct {
 
 /* Fill *opt with the paper's settings: eps 4/80, kappa 0.125, direct
  * formulation, block-diagonal preconditioner, FP64, matrix-free, tol 1e-5,
- * max_iter 1000, singular order 4. */
+ * max_iter 1000, singular order 4; cfie_alpha = cfie_beta = 1. */
 void pb_default_options(pb_options *opt);
 
 /* Thread-local description of the last error on this thread ("" if none). */
@@ -213,10 +233,6 @@ pb_status pb_mesh_refresh(pb_mesh_handle *h);
 /* Solve for one charge set on a resident mesh (same outputs as pb_solve). */
 pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result *result);
 
-/* Solve for n_sets charge sets on one resident mesh.  In assembled modes the
- * right-hand sides are advanced together and every operator application is
- * one batched dense product (MFMA for 16-bit storage).  out[k] follows the
- * pb_result contract for set k.  PB_E_STATE for the Calderon preconditioners. */
 /* Solve one charge set on each of n resident meshes of any, unequal, sizes
  * (1 <= n <= PB_MAX_BATCH_REQUESTS, distinct handles): their GMRES runs in
  * lockstep and every iteration computes the far fields of all requests still
@@ -243,6 +259,10 @@ pb_status pb_mesh_solve(pb_mesh_handle *h, const pb_charges *charges, pb_result 
 pb_status pb_solve_batch(int32_t n, pb_mesh_handle *const *handles, const pb_charges *charges,
                          pb_result *results);
 
+/* Solve for n_sets charge sets on one resident mesh.  In assembled modes the
+ * right-hand sides are advanced together and every operator application is
+ * one batched dense product (MFMA for 16-bit storage).  out[k] follows the
+ * pb_result contract for set k.  PB_E_STATE for the Calderon preconditioners. */
 pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *sets,
                          pb_result *out);
 

@@ -14,6 +14,7 @@ Citations are to Search, Cooper & van 't Wout, arXiv 2108.10481:
   * internal / external direct ......... Eqs. bie:dirichlet:int, bie:dirichlet:ext
   * Juffer, Lu formulations ............. Eqs. bie:juffer:int, bie:lu:ext
   * Mueller, PMCHWT formulations ........ Eqs. bie:muller:int/ext, bie:pmchwt:int/ext
+  * combined field (alpha, beta) ........ Eqs. bie:combined:int, bie:combined:ext
   * source projections .................. Eq. sources
   * reaction potential, energy .......... Eqs. phireac_bie and dG
   * block-diagonal preconditioner ....... Preconditioning / Algebraic preconditioners
@@ -50,9 +51,11 @@ MULLER_EXT = 6        # Eq. bie:muller:ext
 LU = 7                # Eq. bie:lu:ext
 PMCHWT_INT = 8        # Eq. bie:pmchwt:int
 PMCHWT_EXT = 9        # Eq. bie:pmchwt:ext
-FORMULATIONS = tuple(range(10))
+CFIE_INT = 10         # Eq. bie:combined:int (real alpha, beta)
+CFIE_EXT = 11         # Eq. bie:combined:ext (real alpha, beta)
+FORMULATIONS = tuple(range(12))
 #: formulations whose unknowns are the exterior traces (gamma_D^+, gamma_N^+)
-EXTERIOR = (DIRECT_EXT, DIRECT_EXT_PERM, MULLER_EXT, LU, PMCHWT_EXT)
+EXTERIOR = (DIRECT_EXT, DIRECT_EXT_PERM, MULLER_EXT, LU, PMCHWT_EXT, CFIE_EXT)
 #: formulations with only single- and double-layer operators
 DIRECT_FAMILY = (DIRECT, DIRECT_EXT, DIRECT_INT_PERM, DIRECT_EXT_PERM)
 
@@ -194,16 +197,31 @@ def solvation_energy(mesh, charges, phi, dphi):
 
 
 # ------------------------------------------------------------ formulations
-def system_blocks(ops_L, ops_Y, M, eps_in, eps_out, formulation):
+def system_blocks(ops_L, ops_Y, M, eps_in, eps_out, formulation, alpha=1.0, beta=1.0):
     """2x2 block system of the chosen formulation, Galerkin form, typed in as
     the paper prints it.
 
     ops_L / ops_Y hold V, K and (second-kind and PMCHWT formulations) D and T
     of the Laplace ("int") and Yukawa ("ext") kernels; the identity becomes
-    the mass matrix M.  e = eps_in / eps_out.
+    the mass matrix M.  e = eps_in / eps_out; alpha, beta: the constants of
+    the combined-field formulations.
     """
     e = eps_in / eps_out
     L, Y = ops_L, ops_Y
+    if formulation == CFIE_INT:                     # Eq. bie:combined:int
+        # interior trace equations + diag(alpha, beta) exterior trace equations
+        A11 = (0.5 * M + L["K"]) + alpha * (0.5 * M - Y["K"])
+        A12 = -L["V"] + alpha * (e * Y["V"])
+        A21 = -L["D"] + beta * ((1.0 / e) * Y["D"])
+        A22 = (0.5 * M - L["T"]) + beta * (0.5 * M + Y["T"])
+        return A11, A12, A21, A22
+    if formulation == CFIE_EXT:                     # Eq. bie:combined:ext
+        # exterior trace equations + diag(alpha, beta) interior trace equations
+        A11 = (0.5 * M - Y["K"]) + alpha * (0.5 * M + L["K"])
+        A12 = Y["V"] + alpha * (-(1.0 / e) * L["V"])
+        A21 = Y["D"] + beta * (-e * L["D"])
+        A22 = (0.5 * M + Y["T"]) + beta * (0.5 * M - L["T"])
+        return A11, A12, A21, A22
     if formulation == DIRECT:                       # Eq. bie:dirichlet:int
         A11 = 0.5 * M + L["K"]
         A12 = -L["V"]
@@ -265,7 +283,7 @@ def _want(formulation):
     return ("V", "K") if formulation in DIRECT_FAMILY else ("V", "K", "D")
 
 
-def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4):
+def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4, alpha=1.0, beta=1.0):
     want = _want(formulation)
     oL = assemble(mesh, 0.0, want, nss)
     oY = assemble(mesh, kappa, want, nss)
@@ -273,18 +291,19 @@ def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4):
         oL["T"] = oL["K"].T.copy()                  # adjoint double layer as K^T
         oY["T"] = oY["K"].T.copy()
     M = mass(mesh)
-    A11, A12, A21, A22 = system_blocks(oL, oY, M, eps_in, eps_out, formulation)
+    A11, A12, A21, A22 = system_blocks(oL, oY, M, eps_in, eps_out, formulation, alpha, beta)
     return np.block([[A11, A12], [A21, A22]])
 
 
-def system_rhs(bD, bN, formulation, eps_in: float = 4.0, eps_out: float = 80.0):
+def system_rhs(bD, bN, formulation, eps_in: float = 4.0, eps_out: float = 80.0, alpha=1.0, beta=1.0):
     """Right-hand side of the formulation from the source projections
     <phi_i, varphi_D>, <phi_i, varphi_N> (Eq. sources), as printed."""
     e = eps_in / eps_out
     z = np.zeros_like(bD)
     rhs = {DIRECT: (bD, z), DIRECT_EXT: (z, bD), DIRECT_INT_PERM: (z, bD), DIRECT_EXT_PERM: (bD, z),
            JUFFER: (bD, bN), MULLER_INT: (bD, bN), MULLER_EXT: (bD, e * bN), LU: (e * bD, e * bN),
-           PMCHWT_INT: (-bD, -bN), PMCHWT_EXT: (-bD, -e * bN)}[formulation]
+           PMCHWT_INT: (-bD, -bN), PMCHWT_EXT: (-bD, -e * bN),
+           CFIE_INT: (bD, bN), CFIE_EXT: (alpha * bD, beta * e * bN)}[formulation]
     return np.concatenate(rhs)
 
 
@@ -298,7 +317,7 @@ def interior_traces(u, nv, formulation, eps_in: float = 4.0, eps_out: float = 80
     return phi, dphi
 
 
-def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4):
+def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4, alpha=1.0, beta=1.0):
     """Sampled rows of y = A x for large meshes: returns (y1[rows], y2[rows])."""
     rows = np.asarray(rows, dtype=np.int32)
     nv = mesh.n_vertices
@@ -310,7 +329,7 @@ def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4
         oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss)["K"]
         oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss)["K"]
     M = mass_rows(mesh, rows)
-    A11, A12, A21, A22 = system_blocks(oL, oY, M, eps_in, eps_out, formulation)
+    A11, A12, A21, A22 = system_blocks(oL, oY, M, eps_in, eps_out, formulation, alpha, beta)
     return A11 @ x1 + A12 @ x2, A21 @ x1 + A22 @ x2
 
 
@@ -524,16 +543,18 @@ def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
 
 
 def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRECT,
-          preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None, fast: bool = False):
+          preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None, fast: bool = False,
+          alpha=1.0, beta=1.0):
     """Dense FP64 solve: returns dict(phi, dphi, dG, iterations, rel_residual).
     preconditioner: True or "block_diag", False or None, "mass", "scaled_mass",
     or one of CALDERON (PMCHWT formulations); fast: the Calderon operator with
-    the relaxed quadrature of the fast variant."""
+    the relaxed quadrature of the fast variant; alpha, beta: the constants of
+    the combined-field formulations."""
     nv = mesh.n_vertices
     if A is None:
-        A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss)
+        A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss, alpha, beta)
     bD, bN = rhs(mesh, charges, eps_in)
-    b = system_rhs(bD, bN, formulation, eps_in, eps_out)
+    b = system_rhs(bD, bN, formulation, eps_in, eps_out, alpha, beta)
     if preconditioner is True or preconditioner == "block_diag":
         inv = block_diagonal_inverse(A, nv)
         P = lambda v: apply_block_diag(inv, v)

@@ -34,6 +34,8 @@ PB_MULLER_EXT = 6
 PB_LU = 7
 PB_PMCHWT_INT = 8
 PB_PMCHWT_EXT = 9
+PB_CFIE_INT = 10
+PB_CFIE_EXT = 11
 PB_PREC_NONE = 0
 PB_BLOCK_DIAG = 1
 PB_MASS = 2
@@ -80,7 +82,8 @@ class pb_options(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("singular_order", ctypes.c_int32),
                 ("source_chunks", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("memory_budget", ctypes.c_size_t), ("use_graph", ctypes.c_int32),
-                ("calderon_fast", ctypes.c_int32), ("tree_degree", ctypes.c_int32), ("tree_theta", ctypes.c_double)]
+                ("calderon_fast", ctypes.c_int32), ("tree_degree", ctypes.c_int32), ("tree_theta", ctypes.c_double),
+                ("cfie_alpha", ctypes.c_double), ("cfie_beta", ctypes.c_double)]
 
 
 class pb_result(ctypes.Structure):

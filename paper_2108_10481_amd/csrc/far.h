@@ -27,12 +27,15 @@ struct FarCoef {
     R kappa;   // screening
     R kexp;    // argument scale for expneg
     R k2;      // kappa^2
-    // FORM 0: coefficients of the Laplace row (kL K_L + vL V_L) and of the
-    // Yukawa row (kY K_Y + vY V_Y)
-    R kL, vL, kY, vY;
-    // FORM 1, 2: factors aL of the K and V blocks, -aL of the T block, aY of D's
-    // kappa^2 term; ratios aY / aL of the K, V, D, T blocks
-    R aK, aV, aT, aDY, rK, rV, rD, rT;
+    // FORM 0 (direct formulations): coefficients of the Laplace row
+    // (kL K_L + vL V_L) and of the Yukawa row (kY K_Y + vY V_Y); kYk = kY kappa
+    R kL, vL, kY, vY, kYk;
+    // FORM 1 (every other formulation) and FORM 3 (no Laplace term at all):
+    // row 1 = cKL K_L + cKY K_Y + cVL V_L + cVY V_Y, row 2 = cTL (F_L d.n_t)
+    // + cTY (F_Y d.n_t) + cDL D_L + cDY D_Y; the adjoint double layer's kernel
+    // is -F d.n_t, so cTL, cTY carry that sign.  No coefficient divides
+    // another: any of them may be zero.
+    R cKL, cKY, cVL, cVY, cTL, cTY, cDL, cDY;
 };
 
 // one request of the batched far field: its mesh data, partial-sum buffer and
@@ -54,6 +57,11 @@ struct FarReq {
 // record (entries 0..14).
 // SP: pointer type of the source records (a generic pointer, or one into the
 // constant address space where the caller needs scalar loads)
+// With d = x_p - y_q, r = |d|, e = exp(-kappa r), G_L = 1/r, G_Y = e/r,
+// F_L = 1/r^3, F_Y = e (1 + kappa r)/r^3 and g = (d.n_s)/r^2, h = (d.n_t)/r^2:
+//   F_L d.n_s = g/r,  F_Y d.n_s = e (g/r + kappa g),
+// so each row is a few fused multiply-adds on 1/r, e/r and e with the source
+// weights folded into per-point constants.
 template <typename R, int FORM, typename SP = const R *>
 __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__ st,
                                            SP __restrict__ sd, const R (&tx)[6], const R (&ty)[6],
@@ -64,51 +72,58 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
     R xns[6];
 #pragma unroll
     for (int p = 0; p < 6; ++p) xns[p] = tx[p] * nsx + ty[p] * nsy + tz[p] * nsz;
-    R g = 0, k2nn = 0;
-    if (FORM >= 1) k2nn = cf.aDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
+    R gL = 0, gY = 0, k2nn = 0;
+    if (FORM >= 1) k2nn = cf.cDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const R yx = st[3 * q], yy = st[3 * q + 1], yz = st[3 * q + 2];
         const R yns = st[21 + q];
         const R b1 = sd[q], b2 = sd[6 + q];
-        R ynt = 0, kb1 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0;
-        if (FORM == 0) { c1 = cf.kL * b1; c2 = cf.vL * b2; c3 = cf.kY * b1; c4 = cf.vY * b2; }
-        else { ynt = yx * ntx + yy * nty + yz * ntz; kb1 = k2nn * b1; c1 = cf.aK * b1; c2 = cf.aV * b2; c3 = cf.aT * b2; }
+        if (FORM == 0) {
+            const R c1 = cf.kL * b1, c2 = cf.vL * b2, c3 = cf.kY * b1, c4 = cf.vY * b2, c3k = cf.kYk * b1;
 #pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
-            const R r2 = dx * dx + dy * dy + dz * dz;
-            const R ri = rsqrt_r(r2);
-            const R r = r2 * ri;
-            const R e = expneg(cf.kexp, r);
-            const R ri3 = ri * ri * ri;
-            const R dns = xns[p] - yns;
-            const R tt = cf.kappa * r + R(1);
-            if (FORM == 0) {
-                const R fl = dns * ri3;
-                a1[p] += fl * c1 + ri * c2;
-                a2[p] += e * (fl * tt * c3 + ri * c4);
-            } else if (FORM == 3) {
-                const R fy = e * tt * ri3;
+            for (int p = 0; p < 6; ++p) {
+                const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = rsqrt_r(r2);
+                const R g = (xns[p] - yns) * (ri * ri);
+                a1[p] = fma(ri, fma(c1, g, c2), a1[p]);
+                const R e = expneg(cf.kexp, r2 * ri);
+                a2[p] = fma(e, fma(ri, fma(c3, g, c4), c3k * g), a2[p]);
+            }
+        } else {
+            const R ynt = yx * ntx + yy * nty + yz * ntz;
+            const R c1L = cf.cKL * b1, c1Y = cf.cKY * b1, c2L = cf.cVL * b2, c2Y = cf.cVY * b2;
+            const R c3L = cf.cTL * b2, c3Y = cf.cTY * b2, kb1 = k2nn * b1;
+            const R c1Yk = c1Y * cf.kappa, c3Yk = c3Y * cf.kappa;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) {
+                const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = rsqrt_r(r2);
+                const R ri2 = ri * ri;
+                const R e = expneg(cf.kexp, r2 * ri);
                 const R gy = e * ri;
-                a1[p] += fy * dns * c1 + gy * c2;
-                a2[p] += fy * (xnt[p] - ynt) * c3 + kb1 * gy;
-                g += R(rule_w(p) * rule_w(q)) * gy;
-            } else {
-                const R fy = e * tt * ri3;
-                const R gy = e * ri;
-                const R gv = ri + cf.rV * gy;
-                const R dnt = xnt[p] - ynt;
-                a1[p] += (ri3 + cf.rK * fy) * dns * c1 + gv * c2;
-                a2[p] += (ri3 + cf.rT * fy) * dnt * c3 + kb1 * gy;
-                g += R(rule_w(p) * rule_w(q)) * (FORM == 1 ? gv : ri + cf.rD * gy);
+                const R g = (xns[p] - yns) * ri2, h = (xnt[p] - ynt) * ri2;
+                if (FORM == 3) {
+                    a1[p] = fma(g, fma(e, c1Yk, gy * c1Y), fma(gy, c2Y, a1[p]));
+                    a2[p] = fma(h, fma(e, c3Yk, gy * c3Y), fma(gy, kb1, a2[p]));
+                } else {
+                    const R u = fma(e, c1Yk, fma(gy, c1Y, ri * c1L));
+                    a1[p] = fma(g, u, fma(ri, c2L, fma(gy, c2Y, a1[p])));
+                    const R v = fma(e, c3Yk, fma(gy, c3Y, ri * c3L));
+                    a2[p] = fma(h, v, fma(gy, kb1, a2[p]));
+                    gL = fma(R(rule_w(p) * rule_w(q)), ri, gL);
+                }
+                gY = fma(R(rule_w(p) * rule_w(q)), gy, gY);
             }
         }
     }
     if (FORM >= 1) {
-        W0 += g * sd[12];
-        W1 += g * sd[13];
-        W2 += g * sd[14];
+        const R gc = FORM == 3 ? cf.cDY * gY : cf.cDL * gL + cf.cDY * gY;
+        W0 += gc * sd[12];
+        W1 += gc * sd[13];
+        W2 += gc * sd[14];
     }
 }
 
@@ -117,30 +132,23 @@ template <typename R>
 inline int far_coef(const DevMesh &d, FarCoef<R> &cf)
 {
     const double kap = d.prm.kappa;
+    cf = FarCoef<R>{};
     cf.kappa = (R)kap;
     cf.kexp = (sizeof(R) == 4) ? (R)(kap * 1.4426950408889634) : (R)kap;
     cf.k2 = (R)(kap * kap);
     const FormCoef &f = d.fm;
-    int form = 0;
     if (f.family == 0) {
         const int lr = laplace_row(f);
         cf.kL = (R)f.aL[lr][0]; cf.vL = (R)f.aL[lr][1];
         cf.kY = (R)f.aY[1 - lr][0]; cf.vY = (R)f.aY[1 - lr][1];
-    } else if (yukawa_only(f)) {
-        cf.aK = (R)f.aY[0][0]; cf.aV = (R)f.aY[0][1]; cf.aT = (R)(-f.aY[1][1]); cf.aDY = (R)f.aY[1][0];
-        cf.rK = cf.rV = cf.rD = cf.rT = R(0);
-        form = 3;
-    } else {
-        // the adjoint double layer's kernel is -F d.n_t: its factor carries the sign
-        cf.aK = (R)f.aL[0][0]; cf.aV = (R)f.aL[0][1]; cf.aT = (R)(-f.aL[1][1]); cf.aDY = (R)f.aY[1][0];
-        const double rV = f.aY[0][1] / f.aL[0][1], rD = f.aY[1][0] / f.aL[1][0];
-        cf.rK = (R)(f.aY[0][0] / f.aL[0][0]);
-        cf.rV = (R)rV;
-        cf.rD = (R)rD;
-        cf.rT = (R)(f.aY[1][1] / f.aL[1][1]);
-        form = rD == rV ? 1 : 2;
+        cf.kYk = (R)(f.aY[1 - lr][0] * kap);
+        return 0;
     }
-    return form;
+    cf.cKL = (R)f.aL[0][0]; cf.cKY = (R)f.aY[0][0];
+    cf.cVL = (R)f.aL[0][1]; cf.cVY = (R)f.aY[0][1];
+    cf.cTL = (R)(-f.aL[1][1]); cf.cTY = (R)(-f.aY[1][1]);
+    cf.cDL = (R)f.aL[1][0]; cf.cDY = (R)f.aY[1][0];
+    return yukawa_only(f) ? 3 : 1;
 }
 
 }  // namespace pbm

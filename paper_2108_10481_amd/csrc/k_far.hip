@@ -76,15 +76,13 @@ constexpr int kFarBlock = 256;
 // point p accumulates (no 1/4pi)
 //   a1 += kL F_L (d.n_s) b1 + vL G_L b2                (Laplace row)
 //   a2 += kY F_Y (d.n_s) b1 + vY G_Y b2                (Yukawa row)
-// FORM 1, 2: second-kind and PMCHWT formulations.
-//   a1 += aK (F_L + rK F_Y)(d.n_s) b1 + aV (G_L + rV G_Y) b2
-//   a2 += aT (F_L + rT F_Y)(d.n_t) b2 + aDY kappa^2 (n_t.n_s) G_Y b1   (aT = -aL of T)
+// FORM 1: second-kind, PMCHWT and combined-field formulations.
+//   a1 += (cKL F_L + cKY F_Y)(d.n_s) b1 + (cVL G_L + cVY G_Y) b2
+//   a2 += (cTL F_L + cTY F_Y)(d.n_t) b2 + cDY kappa^2 (n_t.n_s) G_Y b1   (cT = -a of T)
 //   and the hypersingular curl part, per source triangle:
-//   W  += [sum_pq w_p w_q (G_L + rD G_Y)] C_s     (times aD_L in k_far_finish)
-//   (FORM 1: rD = rV, the V sum is reused)
+//   W  += [sum_pq w_p w_q (cDL G_L + cDY G_Y)] C_s
 // FORM 3: no Laplace term (the Yukawa part of a PMCHWT matrix, a Calderon
-//   preconditioner's operator): the FORM 1 sums with F_L, G_L dropped and the
-//   factors aK, aV, aT, aD taken from aY.
+//   preconditioner's operator): the FORM 1 sums without F_L, G_L.
 // with d = x_p - y_q, G = e/r, F = e (1 + kappa r)/r^3 (e = 1 for Laplace).
 // The sums of target triangle t over the sources s0..s1-1 (pairs sharing a
 // vertex skipped) into o[0..15]: one lane's work, shared by k_far and the
@@ -239,12 +237,13 @@ __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, Fa
                 } else {
                     const float fy = e * tt * ri3, gy = e * ri;
                     const float dnt = dx * ntx + dy * nty + dz * ntz;
-                    const float k2nn = cf.aDY * cf.k2 * (ntx * n.x + nty * n.y + ntz * n.z);
-                    const float fk = FORM == 3 ? fy : ri3 + cf.rK * fy, fv = FORM == 3 ? gy : ri + cf.rV * gy;
-                    const float ft = FORM == 3 ? fy : ri3 + cf.rT * fy;
-                    a1 += fk * dns * cf.aK * b1 + fv * cf.aV * b2;
-                    a2 += ft * dnt * cf.aT * b2 + k2nn * gy * b1;
-                    const float g = FORM == 3 ? gy : FORM == 1 ? fv : ri + cf.rD * gy;
+                    const float k2nn = cf.cDY * cf.k2 * (ntx * n.x + nty * n.y + ntz * n.z);
+                    const float fk = FORM == 3 ? cf.cKY * fy : cf.cKL * ri3 + cf.cKY * fy;
+                    const float fv = FORM == 3 ? cf.cVY * gy : cf.cVL * ri + cf.cVY * gy;
+                    const float ft = FORM == 3 ? cf.cTY * fy : cf.cTL * ri3 + cf.cTY * fy;
+                    a1 += fk * dns * b1 + fv * b2;
+                    a2 += ft * dnt * b2 + k2nn * gy * b1;
+                    const float g = FORM == 3 ? cf.cDY * gy : cf.cDL * ri + cf.cDY * gy;
                     const float4 C = rec[2][k];
                     W0 += g * C.x;
                     W1 += g * C.y;
@@ -266,14 +265,14 @@ __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, Fa
 }
 
 // family 0: rows (Laplace, Yukawa), swapped when the Laplace row is row 2;
-// family 1: row 2 gets D's curl part times aD (aL of D, or aY without Laplace terms)
+// family 1: row 2 gets D's curl part (its coefficients applied by the producers)
 // kFinishLanes lanes per target sum every kFinishLanes-th chunk, then a fixed
 // butterfly inside the lane group (one wavefront holds whole groups): with
 // one thread per target a small mesh gave too few threads for up to 128 chunks.
 constexpr int kFinishLanes = 16;
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_far_finish(int T, int S, int family, int swap, double aD,
+__global__ __launch_bounds__(256) void k_far_finish(int T, int S, int family, int swap,
                                                     const double *__restrict__ geo, const R *__restrict__ part,
                                                     double *__restrict__ triout, DevCtl ctl)
 {
@@ -305,8 +304,7 @@ __global__ __launch_bounds__(256) void k_far_finish(int T, int S, int family, in
             y1 += w * pot[p];
             y2 += w * pot[6 + p];
         }
-        if (family == 1)
-            y2 += aD * (g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14]);
+        if (family == 1) y2 += g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14];
         if (swap) { const double tmp = y1; y1 = y2; y2 = tmp; }
         triout[6 * (size_t)t + k] = sc * y1;
         triout[6 * (size_t)t + 3 + k] = sc * y2;
@@ -396,10 +394,8 @@ static void far_launch(DevMesh &d, const R *stat, const R *dyn)
         hipLaunchKernelGGL((k_far<R, 0>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     else if (form == 1)
         hipLaunchKernelGGL((k_far<R, 1>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
-    else if (form == 3)
-        hipLaunchKernelGGL((k_far<R, 3>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     else
-        hipLaunchKernelGGL((k_far<R, 2>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
+        hipLaunchKernelGGL((k_far<R, 3>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, part, d.ctl);
     HIPCHECK(hipGetLastError());
 }
 
@@ -472,7 +468,7 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
     }
     fb.nblocks[0] = fb.nitems[0] ? batch_blocks<R, 0>(fb.nitems[0]) : 0;
     fb.nblocks[1] = fb.nitems[1] ? batch_blocks<R, 1>(fb.nitems[1]) : 0;
-    fb.nblocks[2] = fb.nitems[2] ? batch_blocks<R, 2>(fb.nitems[2]) : 0;
+    fb.nblocks[2] = 0;   // kernel forms 0, 1 and 3 only
     fb.nblocks[3] = fb.nitems[3] ? batch_blocks<R, 3>(fb.nitems[3]) : 0;
     const size_t rb = sizeof(FarReq<R>) * reqs.size(), ib = sizeof(int4) * std::max<size_t>(items.size(), 1);
     if (rb > fb.req_cap) {
@@ -515,9 +511,9 @@ void far_batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> &li
 void launch_far_batch(FarBatch &fb, bool fp32)
 {
     if (fp32) {
-        batch_launch<float, 0>(fb); batch_launch<float, 1>(fb); batch_launch<float, 2>(fb); batch_launch<float, 3>(fb);
+        batch_launch<float, 0>(fb); batch_launch<float, 1>(fb); batch_launch<float, 3>(fb);
     } else {
-        batch_launch<double, 0>(fb); batch_launch<double, 1>(fb); batch_launch<double, 2>(fb); batch_launch<double, 3>(fb);
+        batch_launch<double, 0>(fb); batch_launch<double, 1>(fb); batch_launch<double, 3>(fb);
     }
 }
 
@@ -545,7 +541,6 @@ void launch_far_centroid(DevMesh &d)
                        d.dync32, part, d.ctl)
     if (form == 0) FAR_C(0);
     else if (form == 1) FAR_C(1);
-    else if (form == 2) FAR_C(2);
     else FAR_C(3);
 #undef FAR_C
     HIPCHECK(hipGetLastError());
@@ -557,12 +552,11 @@ void launch_far_finish(DevMesh &d, bool fp32)
     dim3 grid((unsigned)(((size_t)T * kFinishLanes + 255) / 256)), block(256);
     const FormCoef &f = d.fm;
     const int swap = f.family == 0 && laplace_row(f) == 1;
-    const double aD = f.family == 1 ? (yukawa_only(f) ? f.aY[1][0] : f.aL[1][0]) : 0.0;
     if (fp32)
-        hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, f.family, swap, aD, d.geo,
+        hipLaunchKernelGGL(k_far_finish<float>, grid, block, 0, d.stream, T, d.S, f.family, swap, d.geo,
                            (const float *)d.part, d.triout, d.ctl);
     else
-        hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, f.family, swap, aD, d.geo,
+        hipLaunchKernelGGL(k_far_finish<double>, grid, block, 0, d.stream, T, d.S, f.family, swap, d.geo,
                            (const double *)d.part, d.triout, d.ctl);
     HIPCHECK(hipGetLastError());
 }

@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
                 const R qK = cur[3], qV = cur[4];
                 R gw = 0, ntqN = 0, snt = 0;
                 if (FORM >= 1) {
-                    ntqN = cf.aDY * cf.k2 * (ntx * cur[8] + nty * cur[9] + ntz * cur[10]);
+                    ntqN = cf.cDY * cf.k2 * (ntx * cur[8] + nty * cur[9] + ntz * cur[10]);
                     snt = sx * ntx + sy * nty + sz * ntz;
                 }
 #pragma unroll
@@ -601,11 +601,12 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
                         const R ri3 = ri * ri * ri;
                         const R gy = e * ri, fy = e * (cf.kappa * r + R(1)) * ri3;
                         const R dnt = xnt[p] - snt;
-                        const R gk = FORM == 3 ? gy : ri + cf.rK * gy, gv = FORM == 3 ? gy : ri + cf.rV * gy;
-                        const R ft = FORM == 3 ? fy : ri3 + cf.rT * fy;
-                        a1[p] += cf.aK * gk * qK + cf.aV * gv * qV;
-                        a2[p] += cf.aT * ft * dnt * qV + ntqN * gy;
-                        gw += R(rule_w(p)) * (FORM == 3 || FORM == 1 ? gv : ri + cf.rD * gy);
+                        const R gk = FORM == 3 ? cf.cKY * gy : cf.cKL * ri + cf.cKY * gy;
+                        const R gv = FORM == 3 ? cf.cVY * gy : cf.cVL * ri + cf.cVY * gy;
+                        const R ft = FORM == 3 ? cf.cTY * fy : cf.cTL * ri3 + cf.cTY * fy;
+                        a1[p] += gk * qK + gv * qV;
+                        a2[p] += ft * dnt * qV + ntqN * gy;
+                        gw += R(rule_w(p)) * (FORM == 3 ? cf.cDY * gy : cf.cDL * ri + cf.cDY * gy);
                     }
                 }
                 if (FORM >= 1) {
@@ -679,7 +680,6 @@ static void tree_launch(DevMesh &d, const R *stat, const R *dyn)
                        d.ctl)
     if (form == 0) TREE_EVAL(0);
     else if (form == 1) TREE_EVAL(1);
-    else if (form == 2) TREE_EVAL(2);
     else TREE_EVAL(3);
 #undef TREE_EVAL
     HIPCHECK(hipGetLastError());

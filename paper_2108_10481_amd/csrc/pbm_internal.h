@@ -140,10 +140,11 @@ struct FormCoef {
     double mass[2][2] = {}, aL[2][2] = {}, aY[2][2] = {};
     double rhsD[2] = {}, rhsN[2] = {};
 };
-FormCoef formulation_coef(int formulation, double eps_in, double eps_out);
+FormCoef formulation_coef(int formulation, double eps_in, double eps_out, double alpha, double beta);
 int laplace_row(const FormCoef &f);   // family 0: the row with only Laplace terms
 // family 1 with no Laplace term in any block (the Yukawa part of a PMCHWT matrix)
 bool yukawa_only(const FormCoef &f);
+bool dense_supported(const FormCoef &f);
 // Calderon preconditioners: the operator P (the PMCHWT matrix or one kernel's
 // part of it) and the scales (a, b) of blockdiag(aM, bM)^-1 on the left
 FormCoef calderon_coef(int formulation, int preconditioner, double eps_in, double eps_out);
@@ -190,6 +191,7 @@ struct BlockCache;
 BlockCache *block_cache_create(size_t limit);
 void block_cache_destroy(BlockCache *c);
 size_t block_cache_bytes(const BlockCache *c);   // held, idle and in use
+size_t cache_charge(size_t n);                    // bytes a cached block for n bytes can hold
 
 struct DevMesh {
     HostMesh hm;

@@ -100,6 +100,31 @@ static void cache_give(BlockCache &c, void *p, size_t size)
     c.idle.insert({size, p});
 }
 
+// Give every idle block back to the device (a smaller allocation outside the
+// cache failed); returns whether any was held.
+static bool cache_trim(BlockCache &c)
+{
+    std::lock_guard<std::mutex> lk(c.mu);
+    const bool any = !c.idle.empty();
+    for (auto &e : c.idle) {
+        (void)hipFree(e.second);
+        c.held -= e.first;
+    }
+    c.idle.clear();
+    return any;
+}
+
+// Bytes a block taken for a request of n bytes can hold: n rounded up to the
+// cache's 256 MiB steps, plus the best-fit slack of a quarter.  Handles and
+// admission estimates charge this much for every block of kCacheMin or more.
+size_t cache_charge(size_t n)
+{
+    if (n < kCacheMin) return n;
+    const size_t gran = (size_t)256 << 20;
+    const size_t want = (n + gran - 1) / gran * gran;
+    return want + want / 4;
+}
+
 void *DevMesh::alloc(size_t n)
 {
     void *p = nullptr;
@@ -107,14 +132,23 @@ void *DevMesh::alloc(size_t n)
     if (opt.memory_budget && bytes + n > opt.memory_budget)
         fail(PB_E_NOMEM, "device memory budget of the handle exceeded");
     if (cache && n >= kCacheMin) {
+        // charge the whole block the cache hands out (rounded up, best fit)
         size_t got = 0;
+        if (opt.memory_budget && bytes + cache_charge(n) > opt.memory_budget)
+            fail(PB_E_NOMEM, "device memory budget of the handle exceeded");
         p = cache_take(*cache, n, &got);
         cached.push_back({p, got});
-        bytes += n;
+        bytes += got;
         return p;
     }
     // stream-ordered allocation: frees of one handle never stall another handle's stream
-    HIPCHECK(hipMallocAsync(&p, n, stream));
+    hipError_t e = hipMallocAsync(&p, n, stream);
+    if (e == hipErrorOutOfMemory && cache) {
+        // idle blocks of finished requests may hold the memory: give them back and retry
+        (void)hipGetLastError();
+        if (cache_trim(*cache)) e = hipMallocAsync(&p, n, stream);
+    }
+    HIPCHECK(e);
     allocs.push_back(p);
     bytes += n;
     return p;
@@ -156,7 +190,10 @@ static void check_options(const pb_options *o)
     if (!o) fail(PB_E_INVALID_ARG, "options must not be NULL");
     if (!(o->eps_in > 0) || !(o->eps_out > 0) || !(o->kappa >= 0) || !std::isfinite(o->kappa))
         fail(PB_E_INVALID_ARG, "eps_in, eps_out must be > 0 and kappa >= 0");
-    if (o->formulation < PB_DIRECT_INT || o->formulation > PB_PMCHWT_EXT) fail(PB_E_INVALID_ARG, "unknown formulation");
+    if (o->formulation < PB_DIRECT_INT || o->formulation > PB_CFIE_EXT) fail(PB_E_INVALID_ARG, "unknown formulation");
+    if ((o->formulation == PB_CFIE_INT || o->formulation == PB_CFIE_EXT) &&
+        !(std::isfinite(o->cfie_alpha) && std::isfinite(o->cfie_beta)))
+        fail(PB_E_INVALID_ARG, "cfie_alpha and cfie_beta must be finite");
     if (o->preconditioner < PB_PREC_NONE || o->preconditioner > PB_SCALED_CALDERON_EXT)
         fail(PB_E_INVALID_ARG, "unknown preconditioner");
     if (o->preconditioner == PB_SCALED_MASS && o->formulation != PB_JUFFER)
@@ -193,7 +230,7 @@ static void check_options(const pb_options *o)
 //   kind 1, exterior: [M/2 - K_Y, V_Y]           = 0
 //   kind 2, interior: [-e D_L, M/2 - T_L]        = e varphi_N
 //   kind 2, exterior: [D_Y, M/2 + T_Y]           = 0
-FormCoef formulation_coef(int formulation, double eps_in, double eps_out)
+FormCoef formulation_coef(int formulation, double eps_in, double eps_out, double alpha, double beta)
 {
     const double e = eps_in / eps_out;
     struct Row { int kind; double cI, cE; };
@@ -210,6 +247,8 @@ FormCoef formulation_coef(int formulation, double eps_in, double eps_out)
     case PB_LU: ext = 1; r[0] = {1, e, 1}; r[1] = {2, 1, e}; break;                 // alpha = e, beta = 1/e, row 2 times e
     case PB_PMCHWT_INT: r[0] = {1, -1, 1}; r[1] = {2, -1, 1}; break;                // the paper's sign: -(I) + (E)
     case PB_PMCHWT_EXT: ext = 1; r[0] = {1, -1, 1}; r[1] = {2, -1, 1}; break;
+    case PB_CFIE_INT: r[0] = {1, 1, alpha}; r[1] = {2, 1, beta}; break;            // Eq. bie:combined:int
+    case PB_CFIE_EXT: ext = 1; r[0] = {1, alpha, 1}; r[1] = {2, beta, 1}; break;    // Eq. bie:combined:ext
     default: fail(PB_E_INVALID_ARG, "unknown formulation");
     }
     FormCoef f;
@@ -236,6 +275,17 @@ FormCoef formulation_coef(int formulation, double eps_in, double eps_out)
     return f;
 }
 
+// The assembly's second-kind kernels factor each block by its Laplace
+// coefficient: every block needs one unless no block has a Laplace term.
+bool dense_supported(const FormCoef &f)
+{
+    if (f.family != 1 || yukawa_only(f)) return true;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c)
+            if (f.aL[r][c] == 0.0) return false;
+    return true;
+}
+
 bool yukawa_only(const FormCoef &f)
 {
     if (f.family != 1) return false;
@@ -253,7 +303,7 @@ bool yukawa_only(const FormCoef &f)
 // [[-K_L, V_L], [D_L, T_L]] and [[-K_Y, e V_Y], [D_Y / e, T_Y]].
 FormCoef calderon_coef(int formulation, int preconditioner, double eps_in, double eps_out)
 {
-    FormCoef f = formulation_coef(formulation, eps_in, eps_out);
+    FormCoef f = formulation_coef(formulation, eps_in, eps_out, 1.0, 1.0);
     const bool keep_int = preconditioner == PB_CALDERON || preconditioner == PB_CALDERON_INT ||
                           preconditioner == PB_SCALED_CALDERON_INT;
     const bool keep_ext = preconditioner == PB_CALDERON || preconditioner == PB_CALDERON_EXT ||
@@ -363,7 +413,7 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
     d->opt = *opt;
     d->prm = {opt->eps_in, opt->eps_out, opt->kappa, opt->formulation, opt->preconditioner, opt->precision,
               opt->operator_mode};
-    d->fm = formulation_coef(opt->formulation, opt->eps_in, opt->eps_out);
+    d->fm = formulation_coef(opt->formulation, opt->eps_in, opt->eps_out, opt->cfie_alpha, opt->cfie_beta);
     if (is_calderon(opt->preconditioner))
         d->fmP = calderon_coef(opt->formulation, opt->preconditioner, opt->eps_in, opt->eps_out);
     build_host_mesh(mesh, d->hm);   // validation happens before any device call
@@ -439,8 +489,12 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
     d->red1 = (double *)d->alloc(sizeof(double) * 8);
     d->yfar = (double *)d->alloc(sizeof(double) * 2 * V);
 
+    if ((opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16) && !dense_supported(d->fm))
+        fail(PB_E_STATE, "the assembled far field needs a Laplace term in every block of a second-kind or "
+                         "combined-field system (a zero combined-field coefficient of the external form): use "
+                         "the matrix-free or treecode far field");
     d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
-                    (opt->operator_mode == PB_AUTO &&
+                    (opt->operator_mode == PB_AUTO && dense_supported(d->fm) &&
                      dense_fits(*d, calderon_separate(*d) && !opt->calderon_fast ? 2 : 1));
     setup_and_wait(*d);
     d->t_setup = now() - t0;
@@ -460,30 +514,34 @@ DevMesh *create_mesh_checked(const pb_mesh *mesh, const pb_options *opt, BlockCa
 size_t estimate_device_bytes(int V, int T, const pb_options *o)
 {
     const double v = V, t = T, n = 2.0 * V;
+    // a buffer of kCacheMin bytes or more may come from a server's block cache,
+    // which hands out whole blocks: charge what such a block can hold
+    auto buf = [](double bytes) { return (double)cache_charge((size_t)bytes); };
     const int S = o->source_chunks > 0 ? std::min(o->source_chunks, T) : choose_chunks(T);
     double b = t * (kGeo * 8 + kStat * 12 + kDyn * 12 + 6 * 8 + 12 * 8 + 3 * 4 * 2);
-    b += (double)S * t * 16 * 8;
-    b += 16.0 * t * (36 * 8 + 3 * 4);
+    b += buf((double)S * t * 16 * 8);
+    b += buf(16.0 * t * (36 * 8 + 3 * 4));
     b += 24.0 * v * (4 * 8 + 4) + v * (4 * 8 + 4 * 4);
     b += 12.0 * n * 8;
     const bool mixed = o->precision >= PB_MIXED_BF16;
     const double m = std::min<double>(mixed ? std::min(o->inner_max_iter, o->max_iter) : o->max_iter, n) + 2;
-    b += m * n * 8;
+    b += buf(m * n * 8);
     const double Vp = std::ceil(v / 64.0) * 64.0;
     // FP64 matrix, or FP32 matrix plus the 16-bit copy (mixed) or the assembly's
-    // side matrix (FP32) of the same size
-    const double dense = n * 2.0 * Vp * (o->precision == PB_FP64 ? 8.0 : 6.0);
+    // side matrix (FP32) of half its size
+    const double dense = o->precision == PB_FP64 ? buf(n * 2.0 * Vp * 8.0)
+                                                 : buf(n * 2.0 * Vp * 4.0) + buf(n * 2.0 * Vp * 2.0);
     const bool cal = is_calderon(o->preconditioner);
     const bool cal_sep = cal && (o->preconditioner != PB_CALDERON || o->calderon_fast);
     if (o->operator_mode == PB_ASSEMBLED || mixed) b += dense * (cal_sep && !o->calderon_fast ? 2.0 : 1.0);
     if (o->preconditioner == PB_MASS || o->preconditioner == PB_SCALED_MASS || cal)
         b += 5.0 * kMassBatch * n * 8 + 20.0 * v * 8 + v * 8;   // Chebyshev state, products, M, 1 / M_ii
     if (cal) b += 2.0 * n * 8 + (cal_sep ? 4.0 * 20.0 * v * 8 : 0.0);   // work vectors, P's near field
-    if (cal && o->calderon_fast) b += 16.0 * t * (38 * 8) + t * 8;   // P's pair blocks and sums, centroid weights
+    if (cal && o->calderon_fast) b += buf(16.0 * t * (38 * 8)) + t * 8;   // P's pair blocks and sums, centroid weights
     if (o->operator_mode == PB_TREECODE) {
         const double np = std::pow(o->tree_degree + 1.0, 3.0);
         b += t / 16.0 * np * (12 * 8 + 8 * 8) + 64.0 * t;   // proxies and charges of about T/16 nodes, lists
-        b += 16.0 * std::min(64.0, 4.0 * std::ceil(65536.0 / std::ceil(t / 64.0))) * t * 8;   // pieces' partial sums
+        b += buf(16.0 * std::min(64.0, 4.0 * std::ceil(65536.0 / std::ceil(t / 64.0))) * t * 8);   // pieces' partial sums
     }
     b += 64.0 * 1024 * 1024;   // small buffers, charges, allocator rounding
     return (size_t)(b * 1.1);
@@ -1313,6 +1371,8 @@ void pb_default_options(pb_options *o)
     o->use_graph = 1;
     o->tree_degree = 6;
     o->tree_theta = 0.7;
+    o->cfie_alpha = 1.0;
+    o->cfie_beta = 1.0;
 }
 
 const char *pb_last_error(void) { return g_err.c_str(); }

@@ -767,6 +767,66 @@ def test_formulation_solve_parity(form):
     assert abs(g32["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"])
 
 
+_CFIE_CASES = [(pbm.PB_CFIE_INT, 0.5, 2.0), (pbm.PB_CFIE_INT, 0.0, 3.0), (pbm.PB_CFIE_EXT, 3.0, 0.25),
+               (pbm.PB_CFIE_EXT, 0.0, 1.0), (pbm.PB_CFIE_EXT, 1.0, 0.0), (pbm.PB_CFIE_EXT, 0.0, 0.0)]
+
+
+def _degenerate(form, a, b):
+    """External combined field with a zero constant: a block without a Laplace term."""
+    return form == pbm.PB_CFIE_EXT and (a == 0.0) != (b == 0.0)
+
+
+@pytest.mark.parametrize("form,a,b", _CFIE_CASES)
+def test_cfie_operator(meshes, base_operators, form, a, b):
+    """Combined-field systems with general and zero constants (Eqs.
+    bie:combined:int, bie:combined:ext) against the oracle's typed system:
+    matrix-free FP64 (1e-12) and FP32 (1e-5), treecode without separated
+    clusters (the direct sums, 1e-12), and assembled FP64 / FP32 where every
+    block has a Laplace term; otherwise the assembled mode is refused and
+    PB_AUTO stays matrix-free."""
+    m = meshes["star7"]
+    A11, A12, A21, A22 = oracle.system_blocks(base_operators[0], base_operators[1], base_operators[2], 4.0, 80.0,
+                                              form, a, b)
+    A = np.block([[A11, A12], [A21, A22]])
+    x = np.random.default_rng(91).standard_normal(2 * m.n_vertices)
+    ref = A @ x
+    modes = [(pbm.PB_FP64, pbm.PB_MATRIX_FREE, 1e-12), (pbm.PB_FP32, pbm.PB_MATRIX_FREE, 1e-5)]
+    if not _degenerate(form, a, b):
+        modes += [(pbm.PB_FP64, pbm.PB_ASSEMBLED, 1e-12), (pbm.PB_FP32, pbm.PB_ASSEMBLED, 1e-5)]
+    for prec, mode, tol in modes:
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec, operator_mode=mode, cfie_alpha=a, cfie_beta=b)) as h:
+            y = pbm.pb_mesh_apply(h, x)
+        assert _rel(y, ref) < tol, (form, a, b, prec, mode, _rel(y, ref))
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, operator_mode=pbm.PB_TREECODE, tree_theta=1e-3,
+                                            cfie_alpha=a, cfie_beta=b)) as h:
+        assert _rel(pbm.pb_mesh_apply(h, x), ref) < 1e-12
+    if _degenerate(form, a, b):
+        with pytest.raises(pbm.PbError) as e:
+            pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_ASSEMBLED,
+                                               cfie_alpha=a, cfie_beta=b))
+        assert e.value.code == pbm.PB_E_STATE
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_AUTO,
+                                                cfie_alpha=a, cfie_beta=b)) as h:
+            assert h.info()["assembled"] == 0
+            assert _rel(pbm.pb_mesh_apply(h, x), ref) < 1e-5
+
+
+@pytest.mark.parametrize("form,a,b", [c for c in _CFIE_CASES if c[1:] != (0.0, 0.0)])
+def test_cfie_solve_parity(form, a, b):
+    """Kirkwood sphere with the mass preconditioner: the oracle's iterations
+    and Delta G (1e-6 in FP64, 1e-4 in FP32)."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    ref = oracle.solve(m, ch, formulation=form, preconditioner="mass", alpha=a, beta=b)
+    got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=pbm.PB_MASS, cfie_alpha=a,
+                                                          cfie_beta=b))
+    assert got["status"] == pbm.PB_OK
+    assert got["iterations"] == ref["iterations"], (form, a, b, got["iterations"], ref["iterations"])
+    assert abs(got["dG"] - ref["dG"]) < 1e-6 * abs(ref["dG"]), (form, a, b, got["dG"], ref["dG"])
+    g32 = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, pbm.PB_FP32, preconditioner=pbm.PB_MASS,
+                                                          cfie_alpha=a, cfie_beta=b))
+    assert abs(g32["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"])
+
+
 def test_lu_full_size(sphere32):
     """20480-triangle sphere, Lu formulation (exterior unknowns) with the mass
     preconditioner (the paper's Case 12): sampled rows of A x in FP32 assembled

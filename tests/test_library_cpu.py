@@ -90,7 +90,8 @@ def test_host_validation_rejects_bad_meshes(pbm):
     x[0, 0] = np.nan
     assert _create_status(pbm, x, m.tri) == pbm.PB_E_INVALID_ARG
     assert _create_status(pbm, m.xyz, m.tri, eps_in=-1.0) == pbm.PB_E_INVALID_ARG
-    assert _create_status(pbm, m.xyz, m.tri, formulation=10) == pbm.PB_E_INVALID_ARG
+    assert _create_status(pbm, m.xyz, m.tri, formulation=12) == pbm.PB_E_INVALID_ARG
+    assert _create_status(pbm, m.xyz, m.tri, formulation=pbm.PB_CFIE_EXT, cfie_alpha=np.inf) == pbm.PB_E_INVALID_ARG
     assert _create_status(pbm, m.xyz, m.tri, singular_order=0) == pbm.PB_E_INVALID_ARG
     assert _create_status(pbm, m.xyz, m.tri, preconditioner=9) == pbm.PB_E_INVALID_ARG
     # the scaled mass matrix is defined for the Juffer formulation only, the

@@ -446,6 +446,72 @@ def test_every_formulation_reaches_kirkwood(form):
     assert errs[1] < 0.03 and errs[1] < errs[0] / 2.5, (errs, ref)
 
 
+# ------------------------------------------------- combined field (alpha, beta)
+def test_cfie_reduces_to_the_printed_formulations():
+    """The combined-field systems (Eqs. bie:combined:int, bie:combined:ext,
+    typed in with general alpha, beta) at the printed choices of alpha, beta
+    equal the printed Mueller (1, 1), PMCHWT (-1, -1: the printed internal
+    equation is the combination multiplied by -1, right-hand side too, the
+    external one the combination itself), Juffer
+    (e_out/e_in, e_in/e_out) and Lu systems (external, (e, 1/e), second row
+    then multiplied by e), matrices and right-hand sides."""
+    m, ch = inputs.config_kirkwood(3, 2.0)
+    ein, eout = 4.0, 80.0
+    e = ein / eout
+    oL = oracle.assemble(m, 0.0)
+    oY = oracle.assemble(m, 0.125)
+    for o in (oL, oY):
+        o["T"] = o["K"].T.copy()
+    M = oracle.mass(m)
+    bD, bN = oracle.rhs(m, ch, ein)
+
+    def system(form, a=1.0, b=1.0):
+        A = np.block([list(oracle.system_blocks(oL, oY, M, ein, eout, form, a, b)[:2]),
+                      list(oracle.system_blocks(oL, oY, M, ein, eout, form, a, b)[2:])])
+        return A, oracle.system_rhs(bD, bN, form, ein, eout, a, b)
+
+    nv = m.n_vertices
+    cases = [(oracle.CFIE_INT, 1.0, 1.0, oracle.MULLER_INT, 1.0, 1.0),
+             (oracle.CFIE_EXT, 1.0, 1.0, oracle.MULLER_EXT, 1.0, 1.0),
+             (oracle.CFIE_INT, -1.0, -1.0, oracle.PMCHWT_INT, -1.0, -1.0),
+             (oracle.CFIE_EXT, -1.0, -1.0, oracle.PMCHWT_EXT, 1.0, 1.0),
+             (oracle.CFIE_INT, eout / ein, ein / eout, oracle.JUFFER, 1.0, 1.0),
+             (oracle.CFIE_EXT, e, 1.0 / e, oracle.LU, 1.0, e)]
+    for form, a, b, printed, s1, s2 in cases:
+        A, rhs = system(form, a, b)
+        P, prhs = system(printed)
+        scale = np.concatenate([np.full(nv, s1), np.full(nv, s2)])   # row scaling of the printed system
+        assert np.abs(scale[:, None] * A - P).max() < 1e-14 * np.abs(P).max(), (form, a, b, printed)
+        assert np.abs(scale * rhs - prhs).max() < 1e-14 * np.abs(prhs).max(), (form, a, b, printed)
+
+
+@pytest.mark.parametrize("form,alpha,beta", [(oracle.CFIE_INT, 0.5, 2.0), (oracle.CFIE_INT, 0.0, 3.0),
+                                             (oracle.CFIE_EXT, 3.0, 0.25), (oracle.CFIE_EXT, 0.0, 1.0),
+                                             (oracle.CFIE_EXT, 1.0, 0.0)])
+def test_cfie_reaches_kirkwood(form, alpha, beta):
+    """General and degenerate (a zero constant) combined-field systems solve
+    the same interface problem: a central charge converges to the Kirkwood
+    closed form at O(h^2) and six off-centre charges to the multipole series.
+    (Both constants zero in the internal form leaves the interior trace
+    equations alone, which do not couple to the exterior problem: not a
+    formulation of it.)"""
+    err = []
+    for f in (4, 8):
+        m, ch = inputs.config_kirkwood(f, 2.0)
+        r = oracle.solve(m, ch, formulation=form, preconditioner="mass", alpha=alpha, beta=beta)
+        assert r["rel_residual"] < 1e-5 * 1.01
+        err.append((r["dG"] - kirkwood_central(2.0)) / kirkwood_central(2.0))
+    assert abs(err[0]) < 0.015 and abs(err[1]) < 0.004 and 3.0 < err[0] / err[1] < 5.0, err
+    ch = inputs.charges_ball(2, 6, 8.0)
+    ref = kirkwood_energy(10.0, ch.xyz, ch.q)
+    errs = []
+    for f in (4, 8):
+        m = inputs.icosphere(f, 10.0)
+        r = oracle.solve(m, ch, formulation=form, preconditioner="mass", alpha=alpha, beta=beta)
+        errs.append(abs(r["dG"] - ref) / abs(ref))
+    assert errs[1] < 0.03 and errs[1] < errs[0] / 2.5, (errs, ref)
+
+
 # ----------------------------------------------------------- Calderon (PMCHWT)
 def _sphere_symbol(l, kap, form, part, eps_in=4.0, eps_out=80.0):
     """2 x 2 symbol of P A on degree-l spherical harmonics of the unit sphere,
