@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark: complete boundary-element Poisson-Boltzmann solves on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): sphere of
-radius 10 A meshed as a frequency-32 icosphere (20480 flat triangles, 10242
-vertices), 50 charges uniform in r < 8 A with values U[-1, 1] e (seed 2),
-eps_in 4, eps_out 80, kappa 0.125 / A, block-diagonal preconditioner (with
---preconditioner scaled-mass, the Juffer solves use the scaled mass matrix),
-GMRES tolerance 1e-5 without restart.
+Default workload (the configuration the headline metric is quoted on):
+protein-shaped star surface r = 18 A (1 + 0.15 f), f a random sum of real
+spherical harmonics of degree <= 6 (seed 3), frequency-64 icosphere mapping
+(81920 flat triangles, 40962 vertices), 2000 charges N(0, 0.4) e inside
+0.8 r, eps_in 4, eps_out 80, kappa 0.125 / A, matrix-free FP32 far field with
+the FP64 Sauter-Schwab near field, block-diagonal preconditioner, GMRES
+tolerance 1e-5 without restart.
 
-One step = one complete solve with the internal direct formulation plus one
-with the Juffer formulation, each covering every stage of the hot path:
-geometry, Sauter-Schwab near field, mass terms, preconditioner, right-hand
-side, GMRES with the far-field operator, reaction potential and Delta G.
-The mesh's host-side index plan (validation, Morton order, sparsity) is built
-once before timing; every device stage is redone in every step.
+Step k = one complete solve with the internal direct formulation (k even)
+or the Juffer formulation (k odd), covering every stage of the hot path:
+geometry, near field, mass terms, preconditioner, right-hand side, GMRES with
+the far-field operator, reaction potential and Delta G.  The mesh's host-side
+index plan (validation, Morton order, sparsity) is built once before timing
+(its cost is reported as the cold solve); every device stage is redone in
+every step.  value = operator-product kernel pairs per second over the timed
+solves; solves/s, p50 / p99 latency, the far-field kernel's roofline, the
+first requests of the serving trace (served vs serial plain FP64) and the
+oracle's CPU rate are reported beside it.  --workload sphere runs the
+20480-triangle sphere the same way; the other workloads are listed in parse().
 
 Prints one JSON line (rank 0; there is only one GPU).
 """
@@ -47,20 +53,24 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X published vector peaks
 ASM_FLOPS_PER_PP = {0: 25.83, 1: 29.25}
 ASM_LANE_OPS_PER_PP = {0: 20.0, 1: 22.25}   # one of them transcendental (half of rsqrt + exp2)
 ASM_TRANS_PER_PP = 1.0
-# VALU issue: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane operations per second
-# without packed FP32; a transcendental occupies four issue slots
-VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-TRANS_SLOTS = 4
+# executed VALU instructions per kernel pair in k_far's inner loop (AMD assembly
+# of this build's k_far<float, FORM>, loop body / 36 point pairs): non-transcendental
+# ones, and the two transcendentals (v_rsq_f32, v_exp_f32) whose issue cost in
+# FMA slots is measured (profiles/peaks.json)
+FAR_LANE_OPS_PER_PAIR = {0: 18.67, 1: 30.08}
+FAR_TRANS_PER_PAIR = 2.0
 
 
-def measured_traffic(workload_key: str):
-    """HBM bytes per assembly (and per GEMV launch) from the rocprofv3 FETCH_SIZE /
+def measured_traffic(workload_key: str, kernel: str = "assembly"):
+    """HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs summarised in profiles/traffic.json, scaled by the copy-kernel
-    calibration stored there; None when the assembly source changed since."""
+    calibration stored there; None when the kernel's source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         t = json.load(open(path))
+        if kernel != "assembly":
+            t = t["kernels"][kernel]
         src = open(os.path.join(ROOT, t["source"]), "rb").read()
     except (OSError, ValueError, KeyError):
         return None
@@ -69,27 +79,41 @@ def measured_traffic(workload_key: str):
     return t
 
 
+def measured_peaks():
+    """Peaks measured on gfx950 by ``bench.py --measure-peaks`` (profiles/peaks.json):
+    FP32 FMA lane instructions/s, the issue cost of v_exp_f32 / v_rsq_f32 in
+    FMA slots, FP64 FMA/s, BF16 MFMA flop/s, HBM read and copy bytes/s."""
+    try:
+        return json.load(open(os.path.join(ROOT, "profiles", "peaks.json")))
+    except (OSError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "mixed-bf16", "mixed-fp16"])
-    ap.add_argument("--operator-mode", default="auto", choices=["matrix-free", "assembled", "auto"])
+    ap.add_argument("--operator-mode", default=None, choices=["matrix-free", "assembled", "auto"],
+                    help="default: matrix-free for the star workload, auto for the sphere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=160, help="oracle rows per formulation in the CPU sample")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "star", "multi", "serving", "calderon", "large", "batch"])
-    ap.add_argument("--overlap", default="serial", choices=["streams", "serial"],
-                    help="timed region: formulations solved one after the other (serial), or from one host "
-                         "thread each on their handles' own HIP streams (streams)")
-    ap.add_argument("--report-overlap", action="store_true",
-                    help="also time the other overlap mode after the readings and report it beside them "
-                         "(off by default: a profiler run of the default command then sees the timed "
-                         "region's kernels only)")
+    ap.add_argument("--cpu-rows", type=int, default=24, help="oracle rows per formulation in the CPU sample")
+    ap.add_argument("--workload", default="star",
+                    choices=["star", "sphere", "multi", "serving", "calderon", "large", "batch"])
+    ap.add_argument("--serving-requests", type=int, default=48,
+                    help="requests of the serving trace replayed after the timed steps (0: none)")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="skip the FP64 reference solves of the accuracy gate")
     ap.add_argument("--preconditioner", default="block-diag", choices=["block-diag", "scaled-mass"],
                     help="scaled-mass: the Juffer solves use blockdiag(aM, bM)^-1 (the paper's Case 10), "
                          "the direct ones keep the block-diagonal preconditioner (Case 2)")
     return ap.parse_known_args()[0]
+
+
+def _pct(values, q):
+    v = sorted(values)
+    return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
 
 
 def main():
@@ -105,200 +129,276 @@ def main():
 
     prec = {"fp64": pbm.PB_FP64, "fp32": pbm.PB_FP32, "mixed-bf16": pbm.PB_MIXED_BF16,
             "mixed-fp16": pbm.PB_MIXED_FP16}[a.precision]
-    mode = {"matrix-free": pbm.PB_MATRIX_FREE, "assembled": pbm.PB_ASSEMBLED, "auto": pbm.PB_AUTO}[a.operator_mode]
+    mode_name = a.operator_mode or ("matrix-free" if a.workload == "star" else "auto")
+    mode = {"matrix-free": pbm.PB_MATRIX_FREE, "assembled": pbm.PB_ASSEMBLED, "auto": pbm.PB_AUTO}[mode_name]
     if a.workload == "star":
         mesh, ch = inputs.config_star()
-        workload = ("star surface R=18 A (1 + 0.15 sum Y_lm, l<=6, seed 3), 81920 triangles / 40962 vertices, 2000 "
-                    "charges N(0,0.4) e inside 0.8 r, eps 4/80, kappa 0.125, direct + Juffer, "
-                    "GMRES tol 1e-5; one step = one solve per formulation")
+        workload = ("star surface R=18 A (1 + 0.15 sum Y_lm, l<=6, seed 3), 81920 triangles / 40962 vertices, "
+                    "2000 charges N(0,0.4) e inside 0.8 r (seed 1003), eps 4/80, kappa 0.125, GMRES tol 1e-5; "
+                    "step k = one complete solve (every device stage redone) with the direct formulation "
+                    "(k even) or the Juffer formulation (k odd)")
+        key = "star81920"
     else:
         mesh, ch = inputs.config_sphere()
         workload = ("sphere R=10 A, icosphere 20480 triangles / 10242 vertices, 50 charges U[-1,1] e in r<8 A "
-                    "(seed 2), eps 4/80, kappa 0.125, direct + Juffer, GMRES tol 1e-5; "
-                    "one step = one solve per formulation")
+                    "(seed 2), eps 4/80, kappa 0.125, GMRES tol 1e-5; step k = one complete solve (every "
+                    "device stage redone) with the direct (k even) or the Juffer (k odd) formulation")
+        key = "sphere20480"
     T = mesh.n_triangles
     P = 6 * T
     forms = (pbm.PB_DIRECT_INT, pbm.PB_JUFFER)
-
-    # FP64 matrix-free reference (outside the timed region) for the accuracy gate
-    ref = {}
-    for f in forms:
-        r = pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q,
-                         pbm.pb_default_options(formulation=f, precision=pbm.PB_FP64,
-                                                operator_mode=pbm.PB_MATRIX_FREE))
-        ref[f] = r
+    print(f"bench: {key}, {a.precision} {mode_name}", file=sys.stderr, flush=True)
 
     precs = {f: pbm.PB_SCALED_MASS if (a.preconditioner == "scaled-mass" and f == pbm.PB_JUFFER)
              else pbm.PB_BLOCK_DIAG for f in forms}
-    handles = {f: pbm.MeshHandle(mesh.xyz, mesh.tri,
-                                 pbm.pb_default_options(formulation=f, precision=prec, operator_mode=mode,
-                                                        preconditioner=precs[f]))
-               for f in forms}
+    opts = {f: pbm.pb_default_options(formulation=f, precision=prec, operator_mode=mode, preconditioner=precs[f])
+            for f in forms}
+    # cold solve: handle creation (validation, Morton order, near-pair lists and
+    # every device stage) plus the first solve, from host arrays
+    handles, cold = {}, {}
+    for f in forms:
+        t0 = time.perf_counter()
+        handles[f] = pbm.MeshHandle(mesh.xyz, mesh.tri, opts[f])
+        t1 = time.perf_counter()
+        pbm.pb_mesh_solve(handles[f], ch.xyz, ch.q)
+        t2 = time.perf_counter()
+        cold[f] = {"t_create_ms": round(1e3 * (t1 - t0), 1), "cold_solve_ms": round(1e3 * (t2 - t0), 1)}
+    print("bench: handles created", file=sys.stderr, flush=True)
 
-    solve_lat = []
-    solve_res = {f: [] for f in forms}
+    # FP64 reference (the plain method's precision) for the accuracy gate, outside the timed region
+    ref = {}
+    if not a.no_reference:
+        for f in forms:
+            ref[f] = pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q,
+                                  pbm.pb_default_options(formulation=f, precision=pbm.PB_FP64,
+                                                         operator_mode=pbm.PB_MATRIX_FREE, preconditioner=precs[f]))
+        print("bench: FP64 reference solves done", file=sys.stderr, flush=True)
 
-    def one(f):
+    lat = {f: [] for f in forms}
+    res = {f: [] for f in forms}
+
+    def step(k):
+        f = forms[k % len(forms)]
         s0 = time.perf_counter()
         h = handles[f]
         pbm.pb_mesh_refresh(h)
         r = pbm.pb_mesh_solve(h, ch.xyz, ch.q)
-        solve_lat.append(time.perf_counter() - s0)
-        solve_res[f].append(r)
-        return r
+        lat[f].append(time.perf_counter() - s0)
+        res[f].append(r)
 
-    # streams: each handle owns its HIP stream and the library releases the
-    # interpreter lock inside its calls, so one solve's latency-bound GMRES
-    # phase overlaps the other's assembly on the device
-    from concurrent.futures import ThreadPoolExecutor
-    pool = ThreadPoolExecutor(max_workers=len(forms))
-
-    def step(mode=a.overlap):
-        if mode == "serial":
-            return {f: one(f) for f in forms}
-        futs = {f: pool.submit(one, f) for f in forms}
-        return {f: futs[f].result() for f in forms}
-
-    for _ in range(a.warmup):
-        step()
+    for k in range(a.warmup):
+        step(k)
     assembled = any(h.info()["assembled"] for h in handles.values())
-    # assembled: time the dominant kernel (assembly) and keep the captured GMRES
-    # graphs; matrix-free: time the far-field kernel (GMRES then runs eagerly)
+    # the far-field product kernel (matrix-free) or the assembly (assembled), HIP events on its stream
     for h in handles.values():
         pbm.pb_mesh_profile(h, 2 if assembled else 1)
-    results = None
-    solve_lat.clear()
     for f in forms:
-        solve_res[f].clear()
-    step_ms = []
+        lat[f].clear()
+        res[f].clear()
+    print("bench: timed steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        s0 = time.perf_counter()
-        results = step()
-        step_ms.append(1e3 * (time.perf_counter() - s0))
+    for k in range(a.steps):
+        step(k)
     for h in handles.values():
         pbm.pb_mesh_synchronize(h)
     elapsed = time.perf_counter() - t0
-    main_lat = list(solve_lat)
-    # the paper's five timing columns (setup = geometry, near field, preconditioner
-    # and far-field assembly redone by the refresh), median over the timed solves
-    phases_ms = {str(f): {k: round(1e3 * float(np.median([r[k] for r in solve_res[f]])), 3)
-                          for k in ("t_setup", "t_rhs", "t_prec", "t_gmres", "t_dG")} for f in forms}
-
-    # dominant kernel: far-field operator kernel (or dense product), HIP events on its stream
-    prof_asm = {f: pbm.pb_mesh_profile_read(handles[f], 1) for f in forms}
-    if assembled:
-        # the dense product, timed on its own stream right after the timed steps
-        xs = np.random.default_rng(0).standard_normal(2 * mesh.n_vertices)
-        for h in handles.values():
-            pbm.pb_mesh_profile(h, 1)
-            for _ in range(20):
-                pbm.pb_mesh_apply(h, xs)
+    print(f"bench: timed steps done, {elapsed:.1f} s", file=sys.stderr, flush=True)
+    done = [f for f in forms if res[f]]
+    phases_ms = {str(f): {k: round(1e3 * float(np.median([r[k] for r in res[f]])), 3)
+                          for k in ("t_setup", "t_rhs", "t_prec", "t_gmres", "t_dG")} for f in done}
+    for f in done:
+        phases_ms[str(f)].update(cold[f])
     prof = {f: pbm.pb_mesh_profile_read(handles[f], 0) for f in forms}
+    prof_asm = {f: pbm.pb_mesh_profile_read(handles[f], 1) for f in forms}
     info = {f: handles[f].info() for f in forms}
-    # the other overlap mode, same steps, profiling off, after the readings above
-    other = "streams" if a.overlap == "serial" else "serial"
-    elapsed_other = None
-    if a.report_overlap:
-        for h in handles.values():
-            pbm.pb_mesh_profile(h, 0)
-        t1 = time.perf_counter()
-        for _ in range(a.steps):
-            step(other)
-        for h in handles.values():
-            pbm.pb_mesh_synchronize(h)
-        elapsed_other = time.perf_counter() - t1
-    pool.shutdown()
+    dtype = "f64" if prec == pbm.PB_FP64 else "f32"
+    peaks = measured_peaks()
     launches = sum(prof[f][0] for f in forms)
     kern_ms = sum(prof[f][1] for f in forms)
-    dtype = "f64" if prec == pbm.PB_FP64 else "f32"
-    asm_ms = sum(prof_asm[f][1] for f in forms)
+    pairs_timed = 0.0
     if assembled:
-        # dominant kernel: the far-field assembly (VALU); the dense product is
-        # reported against the HBM roofline beside it
+        asm_ms = sum(prof_asm[f][1] for f in forms)
         evals = sum(prof_asm[f][2] for f in forms)
-        # algorithmic: each far point pair once (the recorded work) times the
-        # formula's flops per point pair
         flops = sum(prof_asm[f][2] * ASM_FLOPS_PER_PP[f] for f in forms)
         achieved = flops / (asm_ms * 1e-3) / 1e12 if asm_ms > 0 else 0.0
-        slots = sum(prof_asm[f][2] * (ASM_LANE_OPS_PER_PP[f] + ASM_TRANS_PER_PP * (TRANS_SLOTS - 1)) for f in forms)
-        issue = slots / (asm_ms * 1e-3) if asm_ms > 0 else 0.0
         nasm = sum(prof_asm[f][0] for f in forms)
-        tr = measured_traffic("sphere20480") if (a.workload == "sphere" and dtype == "f32") else None
+        tr = measured_traffic(key) if dtype == "f32" else None
         traffic = None
         if tr and nasm > 0:
             traffic = round(sum(tr["assembly_bytes"][str(f)] * prof_asm[f][0] for f in forms) / nasm, 1)
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS[dtype], 4), "traffic": traffic,
-                "kernel": "far-field assembly (k_fill x2, k_assemble_tile x80, k_sym_finish x4 per assembly)",
+                "kernel": "far-field assembly (k_fill x2, k_assemble_tile, k_sym_finish x4 per assembly)",
                 "launches": nasm, "avg_launch_ms": round(asm_ms / max(nasm, 1), 4),
-                "point_pair_evals_per_s": round(evals / (asm_ms * 1e-3), 1) if asm_ms > 0 else None,
-                "valu_issue": {"slots_per_s": round(issue, 1), "peak_slots_per_s": VALU_SLOTS_PER_S,
-                               "frac": round(issue / VALU_SLOTS_PER_S, 4)} if dtype == "f32" else None}
+                "point_pair_evals_per_s": round(evals / (asm_ms * 1e-3), 1) if asm_ms > 0 else None}
+        if peaks and dtype == "f32" and asm_ms > 0:
+            slots = sum(prof_asm[f][2] * (ASM_LANE_OPS_PER_PP[f] + ASM_TRANS_PER_PP * (peaks["trans_slots"] - 1))
+                        for f in forms)
+            roof["valu_issue"] = {"slots_per_s": round(slots / (asm_ms * 1e-3), 1),
+                                  "peak_slots_per_s": peaks["fma32_lane_ops_per_s"],
+                                  "frac": round(slots / (asm_ms * 1e-3) / peaks["fma32_lane_ops_per_s"], 4),
+                                  "trans_slots": peaks["trans_slots"], "source": "profiles/peaks.json"}
+        # products stream the matrix: each solve's products counted from iterations
+        for f in done:
+            pairs_timed += sum((r["iterations"] + 1) * float(P) * P for r in res[f])
         gbytes = sum(prof[f][2] for f in forms)
-        gbs = gbytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
-        dense_product = {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(gbs / 8000.0, 4), "kernel": "k_gemv", "launches": launches,
-                         "avg_launch_ms": round(kern_ms / max(launches, 1), 4)}
-        kernel_pairs = None
+        dense_product = ({"bound": "hbm", "achieved": round(gbytes / (kern_ms * 1e-3) / 1e9, 1), "peak": 8000.0,
+                          "unit": "GB/s", "frac": round(gbytes / (kern_ms * 1e-3) / 8e12, 4), "kernel": "k_gemv",
+                          "launches": launches, "avg_launch_ms": round(kern_ms / max(launches, 1), 4)}
+                         if kern_ms > 0 else None)
     else:
+        pairs_timed = sum(prof[f][2] for f in forms)
         flops = sum(prof[f][2] * FLOPS_PER_PAIR[f] for f in forms)
         achieved = flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
+        tr = measured_traffic(key, kernel="k_far") if dtype == "f32" else None
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_TFLOPS[dtype], 4), "traffic": None,
-                "kernel": "k_far", "launches": launches,
-                "avg_launch_ms": round(kern_ms / max(launches, 1), 4)}
+                "frac": round(achieved / PEAK_TFLOPS[dtype], 4),
+                "traffic": (round(sum(tr["bytes_per_launch"][str(f)] * prof[f][0] for f in forms)
+                                  / max(launches, 1), 1) if tr else None),
+                "kernel": "k_far (matrix-free far field; k_far_finish and the near field excluded)",
+                "launches": launches, "avg_launch_ms": round(kern_ms / max(launches, 1), 4),
+                "kernel_pairs_per_s": round(pairs_timed / (kern_ms * 1e-3), 1) if kern_ms > 0 else None}
+        if peaks and dtype == "f32" and kern_ms > 0:
+            slots = sum(prof[f][2] * (FAR_LANE_OPS_PER_PAIR[f] + FAR_TRANS_PER_PAIR * peaks["trans_slots"])
+                        for f in forms)
+            roof["valu_issue"] = {"slots_per_s": round(slots / (kern_ms * 1e-3), 1),
+                                  "peak_slots_per_s": peaks["fma32_lane_ops_per_s"],
+                                  "frac": round(slots / (kern_ms * 1e-3) / peaks["fma32_lane_ops_per_s"], 4),
+                                  "trans_slots": peaks["trans_slots"], "source": "profiles/peaks.json"}
+        by_form = {}
+        for f in forms:
+            n, ms, w = prof[f]
+            if n == 0 or ms <= 0:
+                continue
+            e = {"launches": n, "avg_launch_ms": round(ms / n, 3), "kernel_pairs_per_s": round(w / (ms * 1e-3), 1),
+                 "tflops": round(w * FLOPS_PER_PAIR[f] / (ms * 1e-3) / 1e12, 3)}
+            if peaks and dtype == "f32":
+                e["valu_issue_frac"] = round(w * (FAR_LANE_OPS_PER_PAIR[f] + FAR_TRANS_PER_PAIR * peaks["trans_slots"])
+                                             / (ms * 1e-3) / peaks["fma32_lane_ops_per_s"], 4)
+            by_form[str(f)] = e
+        roof["by_formulation"] = by_form
         dense_product = None
-        kernel_pairs = sum(prof[f][2] for f in forms)
 
-    solves = len(forms) * a.steps
-    rel_err = max(abs(results[f]["dG"] - ref[f]["dG"]) / abs(ref[f]["dG"]) for f in forms)
-    lat_ms = sorted(1e3 * x for x in main_lat)
+    solves = sum(len(res[f]) for f in forms)
+    all_lat = [1e3 * x for f in forms for x in lat[f]]
+    last = {f: res[f][-1] for f in done}
+    rel_err = (max(abs(last[f]["dG"] - ref[f]["dG"]) / abs(ref[f]["dG"]) for f in done) if ref else None)
     rec = {
         "metric": METRIC,
-        "value": round(solves / elapsed, 4),
-        "unit": "solves/s",
+        "value": round(pairs_timed / elapsed, 1),
+        "unit": "kernel-pairs/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(1e3 * elapsed / a.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": workload,
-                   "precision": a.precision, "operator_mode": "assembled" if assembled else "matrix-free",
+        "config": {"workload": workload, "precision": a.precision,
+                   "operator_mode": "assembled" if assembled else "matrix-free",
                    "source_chunks": info[forms[0]]["source_chunks"],
-                   "overlap": ("one host thread and HIP stream per formulation" if a.overlap == "streams"
-                               else "formulations solved one after the other"),
                    "preconditioner": {"direct": "block-diagonal",
                                       "juffer": "scaled mass" if a.preconditioner == "scaled-mass"
                                       else "block-diagonal"}},
-        "kernel_pairs_per_s": round(kernel_pairs / (kern_ms * 1e-3), 1) if kernel_pairs and kern_ms > 0 else None,
-        "dense_product": dense_product,
-        "other_overlap_mode": ({"overlap": other, "value": round(len(forms) * a.steps / elapsed_other, 4),
-                                "ms_per_step": round(1e3 * elapsed_other / a.steps, 3)} if elapsed_other else None),
-        "median_ms_per_step": round(float(np.median(step_ms)), 3),
-        "p50_ms": round(lat_ms[len(lat_ms) // 2], 3),
-        "p99_ms": round(lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)], 3),
+        "value_definition": ("operator-product kernel pairs (P^2 = (6T)^2 target x source quadrature-point pairs "
+                             "per product, near pairs included) of every product in the timed complete solves, "
+                             "divided by the timed region's wall time"),
+        "solves_per_s": round(solves / elapsed, 4),
+        "p50_ms": round(_pct(all_lat, 0.5), 3),
+        "p99_ms": round(_pct(all_lat, 0.99), 3),
+        "latency_ms_by_formulation": {str(f): {"p50": round(_pct([1e3 * x for x in lat[f]], 0.5), 3),
+                                               "max": round(1e3 * max(lat[f]), 3)} for f in done},
         "phases_ms": phases_ms,
-        "dG_kcal": {str(f): results[f]["dG"] for f in forms},
+        "dG_kcal": {str(f): last[f]["dG"] for f in done},
         "dG_rel_err_vs_fp64": rel_err,
-        "iterations": {str(f): results[f]["iterations"] for f in forms},
-        "fp64_matrix_free_solve_s": {str(f): round(ref[f]["t_setup"] + ref[f]["t_rhs"] + ref[f]["t_prec"]
-                                                   + ref[f]["t_gmres"] + ref[f]["t_dG"], 4) for f in forms},
+        "iterations": {str(f): last[f]["iterations"] for f in done},
+        "fp64_reference_solve_s": ({str(f): round(ref[f]["t_setup"] + ref[f]["t_rhs"] + ref[f]["t_prec"]
+                                                  + ref[f]["t_gmres"] + ref[f]["t_dG"], 4) for f in forms}
+                                   if ref else None),
+        "dense_product": dense_product,
         "roofline": roof,
     }
-    if rel_err > 1e-4:
+    if rel_err is not None and rel_err > 1e-4:
         rec["accuracy_gate"] = "FAILED"
-
-    if not a.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(mesh, rec["iterations"], a.cpu_rows, P)
     for h in handles.values():
         h.close()
+    if a.serving_requests > 0:
+        rec["serving"] = serving_prefix(a.serving_requests)
+    if not a.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(mesh, rec["iterations"], a.cpu_rows, P, key)
     print(json.dumps(rec), flush=True)
 
 
-def cpu_baseline(mesh, iterations, nrows, P):
-    """The FP64 oracle timed on this host: operator rows for a bounded sample
-    of vertices, extrapolated to full matvecs and to solves/s with the GPU
-    run's iteration counts (other phases are negligible next to the matvecs)."""
+def serving_prefix(nreq, rate=20.0, slots=8):
+    """The first nreq requests of the serving trace (seed 5: Poisson arrivals at
+    20 req/s, star surfaces of 1280-81920 triangles log-uniform, 50-4000
+    charges, direct or Juffer), replayed twice with their arrival times: on the
+    continuous-batching server in mixed BF16 (assembled 16-bit far field, FP64
+    refinement), and one after another in FIFO order with the plain FP64 solve
+    (pb_solve, FP64, assembled when it fits), each request starting at its
+    arrival or when the previous one ends.  Both measured; every served
+    Delta G is checked against the FP64 one."""
+    import threading
+    import paper_2108_10481_amd as pbm
+    trace = inputs.serving_trace(5, nreq, rate)
+    reqs = [(r,) + inputs.build_request(r) for r in trace]
+    print(f"bench: serving {nreq} requests built", file=sys.stderr, flush=True)
+    opt_mixed = {f: pbm.pb_default_options(formulation=f, precision=pbm.PB_MIXED_BF16,
+                                           operator_mode=pbm.PB_ASSEMBLED) for f in (0, 1)}
+    opt_fp64 = {f: pbm.pb_default_options(formulation=f, precision=pbm.PB_FP64, operator_mode=pbm.PB_AUTO)
+                for f in (0, 1)}
+    served = [None] * len(reqs)
+    with pbm.Server(max_slots=slots) as srv:
+        r0, m0, c0 = reqs[0]
+        srv.wait(srv.submit(m0.xyz, m0.tri, c0.xyz, c0.q, opt_mixed[r0["formulation"]]))   # warm-up
+        tickets = [None] * len(reqs)
+        base = time.perf_counter()
+
+        def submitter():
+            for k, (r, m, c) in enumerate(reqs):
+                delay = base + r["arrival_s"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[k] = srv.submit(m.xyz, m.tri, c.xyz, c.q, opt_mixed[r["formulation"]])
+        th = threading.Thread(target=submitter)
+        th.start()
+        for k in range(len(reqs)):
+            while tickets[k] is None:
+                time.sleep(0.001)
+            served[k] = srv.wait(tickets[k])
+        th.join()
+        stats = srv.stats()
+    lat = [x["t_end"] - x["t_submit"] for x in served]
+    span = max(x["t_end"] for x in served) - min(x["t_submit"] for x in served)
+    print("bench: served run done", file=sys.stderr, flush=True)
+    # serial plain FP64, FIFO on the same arrival times
+    ser_lat, worst = [], 0.0
+    base = time.perf_counter()
+    for k, (r, m, c) in enumerate(reqs):
+        delay = base + r["arrival_s"] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        g = pbm.pb_solve(m.xyz, m.tri, c.xyz, c.q, opt_fp64[r["formulation"]])
+        ser_lat.append(time.perf_counter() - (base + r["arrival_s"]))
+        worst = max(worst, abs(served[k]["dG"] - g["dG"]) / abs(g["dG"]))
+        if k % 16 == 15:
+            print(f"bench: serial FP64 {k + 1}/{len(reqs)}", file=sys.stderr, flush=True)
+    ser_span = time.perf_counter() - (base + reqs[0][0]["arrival_s"])
+    sizes = sorted(r["n_triangles"] for r, _, _ in reqs)
+    return {"workload": f"first {len(reqs)} requests of the serving trace (seed 5, Poisson arrivals at {rate} req/s, "
+                        f"star surfaces of {sizes[0]}-{sizes[-1]} triangles, direct/Juffer mixed)",
+            "served_mixed_bf16": {"slots": slots, "solves_per_s": round(len(reqs) / span, 4),
+                                  "p50_s": round(_pct(lat, 0.5), 4), "p99_s": round(_pct(lat, 0.99), 4),
+                                  "peak_running": stats["peak_running"],
+                                  "peak_inflight_GB": round(stats["peak_inflight_bytes"] / 1e9, 2)},
+            "serial_fp64_fifo": {"solves_per_s": round(len(reqs) / ser_span, 4),
+                                 "p50_s": round(_pct(ser_lat, 0.5), 4), "p99_s": round(_pct(ser_lat, 0.99), 4),
+                                 "how": "pb_solve FP64 (assembled when it fits), one request at a time in "
+                                        "arrival order, measured"},
+            "dG_rel_err_vs_fp64_max": worst}
+
+
+def cpu_baseline(mesh, iterations, nrows, P, key):
+    """The FP64 oracle timed on this host: operator rows of a bounded sample of
+    vertices (both formulations), in kernel pairs per second, and the solves/s
+    it implies when scaled to full products times the GPU run's iterations."""
     import oracle
     oracle.lib()
     rng = np.random.default_rng(7)
@@ -312,21 +412,19 @@ def cpu_baseline(mesh, iterations, nrows, P):
         oracle.system_rows(mesh, 4.0, 80.0, 0.125, f, rows, x)
         dt = time.perf_counter() - t0
         t_all += dt
-        t_matvec = dt * mesh.n_vertices / nrows
-        t_solve += t_matvec * iterations[str(f)]
+        t_solve += dt * mesh.n_vertices / nrows * (iterations.get(str(f), 0) + 1)
         pairs += float(P) * P * nrows / mesh.n_vertices
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
     cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
-    return {"value": round(2.0 / t_solve, 6), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "kernel_pairs_per_s": round(pairs / t_all, 1),
-            "sample": f"oracle operator rows for {nrows} sampled vertices per formulation (direct, Juffer) on the "
-                      f"20480-triangle sphere, {t_all:.1f} s of CPU time, scaled to full matvecs x the GPU "
-                      f"run's GMRES iterations"}
-
-
+    return {"value": round(pairs / t_all, 1), "unit": "kernel-pairs/s", "cores": cores, "kind": "oracle",
+            "solves_per_s": round(2.0 / t_solve, 7) if t_solve > 0 else None,
+            "sample": f"oracle operator rows (FP64, every ordered triangle pair of the sampled rows) for {nrows} "
+                      f"sampled vertices per formulation (direct, Juffer) on the {key} workload, {t_all:.1f} s "
+                      f"of CPU time: their share of the products' kernel pairs per second; solves/s scales "
+                      f"the rows to full products times the GPU run's iterations + 1"}
 
 
 def serving(argv=None):
@@ -684,11 +782,63 @@ def calibrate_copy(nbytes=1 << 30):
     print(json.dumps({"calibration_copy_bytes": nbytes, "copies": 3}), flush=True)
 
 
+def measure_peaks():
+    """Peaks of this MI355X measured by the microbenchmarks of
+    paper_2108_10481_amd/csrc/peaks.hip (libpbm_peaks.so): lane instructions
+    per second of v_fma_f32, v_exp_f32, v_rsq_f32 and v_fma_f64 (8 independent
+    chains per lane, 8 blocks of 256 lanes per CU), a 4-FMA + 1-exp mix, BF16
+    MFMA flop/s (v_mfma_f32_16x16x32_bf16, 4 independent accumulators per
+    wavefront) and HBM read / copy bandwidth (4 GiB buffers).  The
+    transcendental issue cost is the FMA rate over the transcendental rate."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2108_10481_amd", "libpbm_peaks.so"))
+    lib.pbk_compute.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_double)]
+    lib.pbk_stream.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)]
+    cus = lib.pbk_cu_count()
+    rates = {}
+    for kind, name, iters in ((0, "fma32", 200000), (1, "exp32", 100000), (2, "rsq32", 100000),
+                              (3, "fma4_exp1", 50000), (4, "fma64", 100000), (5, "mfma_bf16", 50000)):
+        ms = ctypes.c_float()
+        ops = ctypes.c_double()
+        if lib.pbk_compute(kind, 8, iters, ctypes.byref(ms), ctypes.byref(ops)) != 0:
+            raise RuntimeError(f"peak kernel {name} failed")
+        rates[name] = ops.value / (ms.value * 1e-3)
+        print(f"peaks: {name} {rates[name]:.4e} /s ({ms.value:.2f} ms)", file=sys.stderr, flush=True)
+    bw = {}
+    for kind, name, factor in ((0, "hbm_read", 1.0), (1, "hbm_copy", 2.0)):
+        ms = ctypes.c_float()
+        nbytes = 4 << 30
+        if lib.pbk_stream(kind, nbytes, ctypes.byref(ms)) != 0:
+            raise RuntimeError(f"stream kernel {name} failed")
+        bw[name] = factor * nbytes / (ms.value * 1e-3)
+        print(f"peaks: {name} {bw[name] / 1e9:.1f} GB/s", file=sys.stderr, flush=True)
+    trans = rates["fma32"] / min(rates["exp32"], rates["rsq32"])
+    # the mix: 4 FMA + 1 exp per iteration; if issue slots add, its rate in
+    # lane instructions is 5 / (4 + trans) of the FMA rate
+    mix_pred = rates["fma32"] * 5.0 / (4.0 + trans)
+    rec = {"device_cus": cus,
+           "fma32_lane_ops_per_s": rates["fma32"], "fma32_tflops": 2.0 * rates["fma32"] / 1e12,
+           "exp32_lane_ops_per_s": rates["exp32"], "rsq32_lane_ops_per_s": rates["rsq32"],
+           "trans_slots": round(trans, 3),
+           "mix_4fma_1exp_lane_ops_per_s": rates["fma4_exp1"], "mix_predicted_if_slots_add": mix_pred,
+           "fma64_lane_ops_per_s": rates["fma64"], "fma64_tflops": 2.0 * rates["fma64"] / 1e12,
+           "mfma_bf16_tflops": 2.0 * rates["mfma_bf16"] / 1e12,
+           "hbm_read_GBps": bw["hbm_read"] / 1e9, "hbm_copy_GBps": bw["hbm_copy"] / 1e9,
+           "datasheet": {"fp32_vector_tflops": 157.3, "fp64_vector_tflops": 78.6, "bf16_mfma_tflops": 2500.0,
+                         "hbm_GBps": 8000.0},
+           "note": "packed FP32 (v_pk_fma_f32) is not used by this build; the FMA rate is the unpacked one"}
+    print(json.dumps(rec), flush=True)
+
+
 if __name__ == "__main__":
     if "--calibrate-copy" in sys.argv:
         calibrate_copy()
         sys.exit(0)
-    wl = sys.argv[sys.argv.index("--workload") + 1] if "--workload" in sys.argv else "sphere"
+    if "--measure-peaks" in sys.argv:
+        measure_peaks()
+        sys.exit(0)
+    wl = sys.argv[sys.argv.index("--workload") + 1] if "--workload" in sys.argv else "star"
     if wl == "serving":
         serving()
     elif wl == "multi":

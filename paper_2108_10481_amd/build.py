@@ -15,6 +15,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpbm.so")
+# measurement library (roofline peaks), not part of the solver
+PEAKS_SRC = "peaks.hip"
+PEAKS_OUT = os.path.join(HERE, "libpbm_peaks.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PBM_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["mesh_prep.cpp", "k_geometry.hip", "k_near.hip", "k_far.hip", "k_tree.hip", "k_krylov.hip", "k_dense.hip",
@@ -54,8 +57,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    tmp = PEAKS_OUT + ".tmp"
+    cmd = [hipcc()] + FLAGS + ["-shared", os.path.join(SRC, PEAKS_SRC), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {PEAKS_SRC}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PEAKS_OUT)
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", PEAKS_OUT)
     return OUT
 
 
