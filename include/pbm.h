@@ -166,6 +166,12 @@ typedef struct {
     double tree_theta;        /* PB_TREECODE: separation ratio, 0 < theta < 1 (default 0.7) */
     double cfie_alpha;        /* PB_CFIE_INT / PB_CFIE_EXT: alpha (default 1) */
     double cfie_beta;         /* PB_CFIE_INT / PB_CFIE_EXT: beta (default 1) */
+    int32_t regular_order;    /* quadrature of the triangle pairs sharing no vertex (Numerical
+                                 discretization; the paper's "quadrature order"): 4 (default, 0
+                                 means the same): the symmetric 6-point degree-4 rule on each
+                                 triangle; 1: the one-point (centroid) rule, matrix-free in FP64
+                                 or FP32 only, not with the Calderon preconditioners.  The source
+                                 projections and Delta G always use the 6-point rule. */
 } pb_options;
 
 typedef struct {
@@ -196,7 +202,7 @@ typedef struct {
 
 /* Fill *opt with the paper's settings: eps 4/80, kappa 0.125, direct
  * formulation, block-diagonal preconditioner, FP64, matrix-free, tol 1e-5,
- * max_iter 1000, singular order 4; cfie_alpha = cfie_beta = 1. */
+ * max_iter 1000, singular order 4, regular order 4; cfie_alpha = cfie_beta = 1. */
 void pb_default_options(pb_options *opt);
 
 /* Thread-local description of the last error on this thread ("" if none). */

@@ -283,10 +283,13 @@ def _want(formulation):
     return ("V", "K") if formulation in DIRECT_FAMILY else ("V", "K", "D")
 
 
-def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4, alpha=1.0, beta=1.0):
+def system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss: int = 4, alpha=1.0, beta=1.0,
+                  centroid: bool = False):
+    """Dense system; centroid: the one-point rule on pairs sharing no vertex
+    (regular order 1) instead of the 6-point rule."""
     want = _want(formulation)
-    oL = assemble(mesh, 0.0, want, nss)
-    oY = assemble(mesh, kappa, want, nss)
+    oL = assemble(mesh, 0.0, want, nss, centroid)
+    oY = assemble(mesh, kappa, want, nss, centroid)
     if "D" in want:
         oL["T"] = oL["K"].T.copy()                  # adjoint double layer as K^T
         oY["T"] = oY["K"].T.copy()
@@ -317,17 +320,18 @@ def interior_traces(u, nv, formulation, eps_in: float = 4.0, eps_out: float = 80
     return phi, dphi
 
 
-def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4, alpha=1.0, beta=1.0):
+def system_rows(mesh, eps_in, eps_out, kappa, formulation, rows, x, nss: int = 4, alpha=1.0, beta=1.0,
+                centroid: bool = False):
     """Sampled rows of y = A x for large meshes: returns (y1[rows], y2[rows])."""
     rows = np.asarray(rows, dtype=np.int32)
     nv = mesh.n_vertices
     x1, x2 = x[:nv], x[nv:]
     want = _want(formulation)
-    oL = operator_rows(mesh, 0.0, rows, 0, want, nss)
-    oY = operator_rows(mesh, kappa, rows, 0, want, nss)
+    oL = operator_rows(mesh, 0.0, rows, 0, want, nss, centroid)
+    oY = operator_rows(mesh, kappa, rows, 0, want, nss, centroid)
     if "D" in want:
-        oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss)["K"]
-        oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss)["K"]
+        oL["T"] = operator_rows(mesh, 0.0, rows, 1, ("K",), nss, centroid)["K"]
+        oY["T"] = operator_rows(mesh, kappa, rows, 1, ("K",), nss, centroid)["K"]
     M = mass_rows(mesh, rows)
     A11, A12, A21, A22 = system_blocks(oL, oY, M, eps_in, eps_out, formulation, alpha, beta)
     return A11 @ x1 + A12 @ x2, A21 @ x1 + A22 @ x2
@@ -544,15 +548,17 @@ def gmres(apply, b, tol: float = 1e-5, max_iter: int = 1000):
 
 def solve(mesh, charges, eps_in=4.0, eps_out=80.0, kappa=0.125, formulation=DIRECT,
           preconditioner=True, tol=1e-5, max_iter=1000, nss: int = 4, A=None, fast: bool = False,
-          alpha=1.0, beta=1.0):
+          alpha=1.0, beta=1.0, centroid: bool = False):
     """Dense FP64 solve: returns dict(phi, dphi, dG, iterations, rel_residual).
     preconditioner: True or "block_diag", False or None, "mass", "scaled_mass",
     or one of CALDERON (PMCHWT formulations); fast: the Calderon operator with
     the relaxed quadrature of the fast variant; alpha, beta: the constants of
-    the combined-field formulations."""
+    the combined-field formulations; centroid: the system with the one-point
+    rule on pairs sharing no vertex (regular order 1; right-hand side and
+    Delta G keep the 6-point rule)."""
     nv = mesh.n_vertices
     if A is None:
-        A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss, alpha, beta)
+        A = system_matrix(mesh, eps_in, eps_out, kappa, formulation, nss, alpha, beta, centroid)
     bD, bN = rhs(mesh, charges, eps_in)
     b = system_rhs(bD, bN, formulation, eps_in, eps_out, alpha, beta)
     if preconditioner is True or preconditioner == "block_diag":

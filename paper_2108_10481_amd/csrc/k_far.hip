@@ -21,10 +21,11 @@
 
 namespace pbm {
 
-// dync (may be null): the one-point rule's source weights |s| mean(u1), |s| mean(u2)
+// dync, dync64 (either may be null): the one-point rule's source weights
+// |s| mean(u1), |s| mean(u2) in FP32 / FP64
 __global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, const double *__restrict__ geo,
                               const double *__restrict__ x, double *__restrict__ dyn64, float *__restrict__ dyn32,
-                              float *__restrict__ dync, DevCtl ctl)
+                              float *__restrict__ dync, double *__restrict__ dync64, DevCtl ctl)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= T || ctl_skip(ctl)) return;
@@ -60,13 +61,18 @@ __global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, con
         dync[2 * (size_t)s] = (float)(area * (u1[0] + u1[1] + u1[2]) / 3.0);
         dync[2 * (size_t)s + 1] = (float)(area * (u2[0] + u2[1] + u2[2]) / 3.0);
     }
+    if (dync64) {
+        dync64[2 * (size_t)s] = area * (u1[0] + u1[1] + u1[2]) / 3.0;
+        dync64[2 * (size_t)s + 1] = area * (u2[0] + u2[1] + u2[2]) / 3.0;
+    }
 }
 
 void launch_source_prep(DevMesh &d, const double *x, bool)
 {
     int T = d.hm.T;
     hipLaunchKernelGGL(k_source_prep, dim3((T + 255) / 256), dim3(256), 0, d.stream, T, d.hm.V, d.tri, d.geo, x,
-                       d.dyn64, d.dyn32, d.far_rule == 1 ? d.dync32 : nullptr, d.ctl);
+                       d.dyn64, d.dyn32, d.far_rule != 0 ? d.dync32 : nullptr, d.far_rule == 2 ? d.dync64 : nullptr,
+                       d.ctl);
     HIPCHECK(hipGetLastError());
 }
 
@@ -181,24 +187,28 @@ __global__ void k_set_int(int *p, int v) { *p = v; }
 // put a rounding noise of about 1e-6 into every product, the order of the
 // preconditioned residual GMRES stops at.
 constexpr int kCenRun = 16;
-template <int FORM>
-__global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, FarCoef<float> cf,
+template <typename R>
+struct Rec4 {
+    R x, y, z, w;
+};
+template <typename R, int FORM>
+__global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, FarCoef<R> cf,
                                                              const int32_t *__restrict__ tri,
-                                                             const float *__restrict__ stat,
-                                                             const float *__restrict__ dyn,
-                                                             const float *__restrict__ dync, float *__restrict__ part,
+                                                             const R *__restrict__ stat,
+                                                             const R *__restrict__ dyn,
+                                                             const R *__restrict__ dync, R *__restrict__ part,
                                                              DevCtl ctl)
 {
-    __shared__ float4 rec[3][kFarBlock];   // (c, b1), (n, b2), (C, -)
+    __shared__ Rec4<R> rec[3][kFarBlock];   // (c, b1), (n, b2), (C, -)
     __shared__ int4 vid[kFarBlock];
     const int t = blockIdx.x * kFarBlock + threadIdx.x;
     const int s0 = blockIdx.y * chunk;
     const int s1 = min(T, s0 + chunk);
     if (ctl_skip(ctl)) return;   // uniform: the whole block leaves
     const int tc = t < T ? t : T - 1;   // lanes past the end compute, never store
-    const float *ts = stat + (size_t)tc * kStat;
-    const float cx = ts[37], cy = ts[38], cz = ts[39];
-    const float ntx = ts[18], nty = ts[19], ntz = ts[20];
+    const R *ts = stat + (size_t)tc * kStat;
+    const R cx = ts[37], cy = ts[38], cz = ts[39];
+    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
     const int v0 = tri[3 * tc], v1 = tri[3 * tc + 1], v2 = tri[3 * tc + 2];
     double A1 = 0, A2 = 0, X0 = 0, X1 = 0, X2 = 0;
     for (int sb = s0; sb < s1; sb += kFarBlock) {
@@ -206,45 +216,45 @@ __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, Fa
         __syncthreads();   // the previous tile is consumed
         if ((int)threadIdx.x < ns) {
             const int s = sb + threadIdx.x;
-            const float *st = stat + (size_t)s * kStat;
-            const float *sd = dyn + (size_t)s * kDyn;
-            rec[0][threadIdx.x] = make_float4(st[37], st[38], st[39], dync[2 * (size_t)s]);
-            rec[1][threadIdx.x] = make_float4(st[18], st[19], st[20], dync[2 * (size_t)s + 1]);
-            rec[2][threadIdx.x] = make_float4(sd[12], sd[13], sd[14], 0.0f);
+            const R *st = stat + (size_t)s * kStat;
+            const R *sd = dyn + (size_t)s * kDyn;
+            rec[0][threadIdx.x] = Rec4<R>{st[37], st[38], st[39], dync[2 * (size_t)s]};
+            rec[1][threadIdx.x] = Rec4<R>{st[18], st[19], st[20], dync[2 * (size_t)s + 1]};
+            rec[2][threadIdx.x] = Rec4<R>{sd[12], sd[13], sd[14], R(0)};
             vid[threadIdx.x] = make_int4(tri[3 * s], tri[3 * s + 1], tri[3 * s + 2], 0);
         }
         __syncthreads();
         for (int r0 = 0; r0 < ns; r0 += kCenRun) {
-            float a1 = 0, a2 = 0, W0 = 0, W1 = 0, W2 = 0;
+            R a1 = 0, a2 = 0, W0 = 0, W1 = 0, W2 = 0;
             for (int k = r0; k < min(ns, r0 + kCenRun); ++k) {
                 const int4 j = vid[k];
                 const bool adj = (j.x == v0) | (j.x == v1) | (j.x == v2) | (j.y == v0) | (j.y == v1) |
                                  (j.y == v2) | (j.z == v0) | (j.z == v1) | (j.z == v2);
                 if (adj) continue;
-                const float4 c = rec[0][k], n = rec[1][k];
-                const float b1 = c.w, b2 = n.w;
-                const float dx = cx - c.x, dy = cy - c.y, dz = cz - c.z;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float ri = rsqrt_r(r2);
-                const float r = r2 * ri;
-                const float e = expneg(cf.kexp, r);
-                const float ri3 = ri * ri * ri;
-                const float dns = dx * n.x + dy * n.y + dz * n.z;
-                const float tt = cf.kappa * r + 1.0f;
+                const Rec4<R> c = rec[0][k], n = rec[1][k];
+                const R b1 = c.w, b2 = n.w;
+                const R dx = cx - c.x, dy = cy - c.y, dz = cz - c.z;
+                const R r2 = dx * dx + dy * dy + dz * dz;
+                const R ri = rsqrt_r(r2);
+                const R r = r2 * ri;
+                const R e = expneg(cf.kexp, r);
+                const R ri3 = ri * ri * ri;
+                const R dns = dx * n.x + dy * n.y + dz * n.z;
+                const R tt = cf.kappa * r + R(1);
                 if (FORM == 0) {
                     a1 += ri3 * dns * cf.kL * b1 + ri * cf.vL * b2;
                     a2 += e * (ri3 * tt * dns * cf.kY * b1 + ri * cf.vY * b2);
                 } else {
-                    const float fy = e * tt * ri3, gy = e * ri;
-                    const float dnt = dx * ntx + dy * nty + dz * ntz;
-                    const float k2nn = cf.cDY * cf.k2 * (ntx * n.x + nty * n.y + ntz * n.z);
-                    const float fk = FORM == 3 ? cf.cKY * fy : cf.cKL * ri3 + cf.cKY * fy;
-                    const float fv = FORM == 3 ? cf.cVY * gy : cf.cVL * ri + cf.cVY * gy;
-                    const float ft = FORM == 3 ? cf.cTY * fy : cf.cTL * ri3 + cf.cTY * fy;
+                    const R fy = e * tt * ri3, gy = e * ri;
+                    const R dnt = dx * ntx + dy * nty + dz * ntz;
+                    const R k2nn = cf.cDY * cf.k2 * (ntx * n.x + nty * n.y + ntz * n.z);
+                    const R fk = FORM == 3 ? cf.cKY * fy : cf.cKL * ri3 + cf.cKY * fy;
+                    const R fv = FORM == 3 ? cf.cVY * gy : cf.cVL * ri + cf.cVY * gy;
+                    const R ft = FORM == 3 ? cf.cTY * fy : cf.cTL * ri3 + cf.cTY * fy;
                     a1 += fk * dns * b1 + fv * b2;
                     a2 += ft * dnt * b2 + k2nn * gy * b1;
-                    const float g = FORM == 3 ? cf.cDY * gy : cf.cDL * ri + cf.cDY * gy;
-                    const float4 C = rec[2][k];
+                    const R g = FORM == 3 ? cf.cDY * gy : cf.cDL * ri + cf.cDY * gy;
+                    const Rec4<R> C = rec[2][k];
                     W0 += g * C.x;
                     W1 += g * C.y;
                     W2 += g * C.z;
@@ -258,10 +268,10 @@ __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, Fa
         }
     }
     if (t >= T) return;
-    float *o = part + ((size_t)blockIdx.y * T + t) * 16;
+    R *o = part + ((size_t)blockIdx.y * T + t) * 16;
 #pragma unroll
-    for (int p = 0; p < 6; ++p) { o[p] = (float)A1; o[6 + p] = (float)A2; }
-    o[12] = (float)X0; o[13] = (float)X1; o[14] = (float)X2; o[15] = 0;
+    for (int p = 0; p < 6; ++p) { o[p] = (R)A1; o[6 + p] = (R)A2; }
+    o[12] = (R)X0; o[13] = (R)X1; o[14] = (R)X2; o[15] = 0;
 }
 
 // family 0: rows (Laplace, Yukawa), swapped when the Laplace row is row 2;
@@ -528,22 +538,29 @@ void far_batch_free(FarBatch &fb)
     fb.req_cap = fb.item_cap = 0;
 }
 
-void launch_far_centroid(DevMesh &d)
+template <typename R>
+static void centroid_launch(DevMesh &d, const R *stat, const R *dyn, const R *dync)
 {
     const int T = d.hm.T, S = d.S;
     const int chunk = (T + S - 1) / S;
-    FarCoef<float> cf;
+    FarCoef<R> cf;
     const int form = far_coef(d, cf);
     const dim3 grid((T + kFarBlock - 1) / kFarBlock, S), block(kFarBlock);
-    float *part = (float *)d.part;
-#define FAR_C(F)                                                                                               \
-    hipLaunchKernelGGL((k_far_centroid<F>), grid, block, 0, d.stream, T, chunk, cf, d.tri, d.stat32, d.dyn32, \
-                       d.dync32, part, d.ctl)
+    R *part = (R *)d.part;
+#define FAR_C(F)                                                                                                \
+    hipLaunchKernelGGL((k_far_centroid<R, F>), grid, block, 0, d.stream, T, chunk, cf, d.tri, stat, dyn, dync, \
+                       part, d.ctl)
     if (form == 0) FAR_C(0);
     else if (form == 1) FAR_C(1);
     else FAR_C(3);
 #undef FAR_C
     HIPCHECK(hipGetLastError());
+}
+
+void launch_far_centroid(DevMesh &d, bool fp32)
+{
+    if (fp32) centroid_launch<float>(d, d.stat32, d.dyn32, d.dync32);
+    else centroid_launch<double>(d, d.stat64, d.dyn64, d.dync64);
 }
 
 void launch_far_finish(DevMesh &d, bool fp32)

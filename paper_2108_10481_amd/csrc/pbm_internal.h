@@ -265,12 +265,14 @@ struct DevMesh {
     double *cal1 = nullptr, *cal2 = nullptr;
     // far-field rule of the current operator: 0 = 6-point rule (the handle's
     // precision and mode), 1 = one-point rule, matrix-free FP32 (fast
-    // Calderon's P); swapped with far_ruleP like the fields above
+    // Calderon's P), 2 = one-point rule, matrix-free in the handle's precision
+    // (A with regular_order 1); swapped with far_ruleP like the fields above
     int far_rule = 0, far_ruleP = 0;
     // fast Calderon: P's Sauter-Schwab blocks and pair sums at the relaxed
     // order, and the centroid source weights (T x 2: |s| mean u1, |s| mean u2)
     double *pairblkP = nullptr, *pair_sumsP = nullptr;
     float *dync32 = nullptr;
+    double *dync64 = nullptr;   // the same weights in FP64 (far_rule 2, FP64 precision)
     int64_t nnz() const { return (int64_t)hm.col.size(); }
     void *alloc(size_t n);
     ~DevMesh();
@@ -287,7 +289,7 @@ void launch_near_values(DevMesh &d, const FormCoef &f, const double *blk, const 
 // fast Calderon's P: Sauter-Schwab blocks at the relaxed order and their pair sums
 void launch_near_field_fast(DevMesh &d);
 // one-point-rule far field (FP32) of the current operator fields into d.part
-void launch_far_centroid(DevMesh &d);
+void launch_far_centroid(DevMesh &d, bool fp32);
 void launch_source_prep(DevMesh &d, const double *x, bool fp32);
 void launch_far(DevMesh &d, bool fp32);
 void launch_far_finish(DevMesh &d, bool fp32);

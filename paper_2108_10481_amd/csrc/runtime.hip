@@ -215,6 +215,15 @@ static void check_options(const pb_options *o)
     if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
     if (o->singular_order < 1 || o->singular_order > 8) fail(PB_E_INVALID_ARG, "singular_order must be in [1, 8]");
     if (o->source_chunks < 0 || o->source_chunks > 1024) fail(PB_E_INVALID_ARG, "source_chunks must be in [0, 1024]");
+    if (o->regular_order != 0 && o->regular_order != 1 && o->regular_order != 4)
+        fail(PB_E_INVALID_ARG, "regular_order must be 4 (the 6-point rule) or 1 (the one-point rule)");
+    if (o->regular_order == 1) {
+        if (o->operator_mode == PB_ASSEMBLED || o->operator_mode == PB_TREECODE || o->precision >= PB_MIXED_BF16)
+            fail(PB_E_INVALID_ARG, "regular_order 1 (one-point rule) runs matrix-free in FP64 or FP32");
+        if (is_calderon(o->preconditioner))
+            fail(PB_E_INVALID_ARG, "regular_order 1 is not combined with the Calderon preconditioners "
+                                   "(calderon_fast relaxes the preconditioner's quadrature)");
+    }
 }
 
 // Coefficients of a formulation from the combination rule: output row r is
@@ -476,6 +485,11 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
             d->dync32 = (float *)d->alloc(sizeof(float) * 2 * (size_t)T);
         }
     }
+    if (opt->regular_order == 1) {
+        d->far_rule = 2;
+        d->dync32 = (float *)d->alloc(sizeof(float) * 2 * (size_t)T);
+        d->dync64 = (double *)d->alloc(sizeof(double) * 2 * (size_t)T);
+    }
     d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
     d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
     d->part = d->alloc(sizeof(double) * 16 * (size_t)d->S * T);
@@ -494,7 +508,7 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
                          "combined-field system (a zero combined-field coefficient of the external form): use "
                          "the matrix-free or treecode far field");
     d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
-                    (opt->operator_mode == PB_AUTO && dense_supported(d->fm) &&
+                    (opt->operator_mode == PB_AUTO && d->far_rule == 0 && dense_supported(d->fm) &&
                      dense_fits(*d, calderon_separate(*d) && !opt->calderon_fast ? 2 : 1));
     setup_and_wait(*d);
     d->t_setup = now() - t0;
@@ -552,10 +566,12 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
 static int far_product(DevMesh &d, const double *x, int flags)
 {
     if (flags & PB_APPLY_NEAR_ONLY) return 0;
-    if (d.far_rule == 1) {
-        launch_source_prep(d, x, true);
-        launch_far_centroid(d);
-        launch_far_finish(d, true);
+    if (d.far_rule != 0) {
+        // one-point rule: FP32 for fast Calderon's P, else the handle's precision
+        const bool fp32c = d.far_rule == 1 || d.prm.precision == PB_FP32;
+        launch_source_prep(d, x, fp32c);
+        launch_far_centroid(d, fp32c);
+        launch_far_finish(d, fp32c);
         return 1;
     }
     if (d.dense) {
@@ -1373,6 +1389,7 @@ void pb_default_options(pb_options *o)
     o->tree_theta = 0.7;
     o->cfie_alpha = 1.0;
     o->cfie_beta = 1.0;
+    o->regular_order = 4;
 }
 
 const char *pb_last_error(void) { return g_err.c_str(); }

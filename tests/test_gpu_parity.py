@@ -767,6 +767,33 @@ def test_formulation_solve_parity(form):
     assert abs(g32["dG"] - ref["dG"]) < 1e-4 * abs(ref["dG"])
 
 
+@pytest.mark.parametrize("form", [0, 1])
+def test_one_point_regular_rule(meshes, form):
+    """regular_order 1: the one-point rule on every pair sharing no vertex,
+    matrix-free in FP64 (1e-12) and FP32 (1e-5) against the oracle's system
+    with the same rule; the solve's iterations and Delta G (1e-6) against the
+    oracle's; the modes that cannot take it are refused."""
+    m = meshes["star7"]
+    A = oracle.system_matrix(m, 4.0, 80.0, 0.125, form, centroid=True)
+    x = np.random.default_rng(93).standard_normal(2 * m.n_vertices)
+    ref = A @ x
+    for prec, tol in ((pbm.PB_FP64, 1e-12), (pbm.PB_FP32, 1e-5)):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec, regular_order=1)) as h:
+            assert _rel(pbm.pb_mesh_apply(h, x), ref) < tol, (form, prec)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_AUTO, regular_order=1)) as h:
+        assert h.info()["assembled"] == 0
+    ch = inputs.charges_ball(9, 20, 2.5)
+    r = oracle.solve(m, ch, formulation=form, A=A)
+    g = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, regular_order=1))
+    assert g["status"] == pbm.PB_OK and abs(g["iterations"] - r["iterations"]) <= 1
+    assert abs(g["dG"] - r["dG"]) < 1e-6 * abs(r["dG"]), (g["dG"], r["dG"])
+    for kw in ({"operator_mode": pbm.PB_ASSEMBLED}, {"operator_mode": pbm.PB_TREECODE},
+               {"precision": pbm.PB_MIXED_BF16}):
+        with pytest.raises(pbm.PbError) as e:
+            pbm.MeshHandle(m.xyz, m.tri, _opts(form, regular_order=1, **kw))
+        assert e.value.code == pbm.PB_E_INVALID_ARG
+
+
 _CFIE_CASES = [(pbm.PB_CFIE_INT, 0.5, 2.0), (pbm.PB_CFIE_INT, 0.0, 3.0), (pbm.PB_CFIE_EXT, 3.0, 0.25),
                (pbm.PB_CFIE_EXT, 0.0, 1.0), (pbm.PB_CFIE_EXT, 1.0, 0.0), (pbm.PB_CFIE_EXT, 0.0, 0.0)]
 
@@ -1099,23 +1126,37 @@ def test_treecode_converges_with_degree(sphere16, form):
     assert errs[3] < 1e-6 and errs[-1] < 1e-9
 
 
+# Accuracy target of the treecode at its defaults (degree 6, theta 0.7): a
+# relative operator error of at most 5e-6 (the _rel measure), below the FP32
+# direct far field's own bound (2e-5), so that the treecode leaves the reduced
+# precision Delta G contract (1e-4) a margin of 10 over the FP32 rounding.
+TREE_TARGET = 5e-6
+
+
 def test_treecode_full_size_rows_and_solve(sphere32):
-    """20480-triangle sphere, FP32 treecode (defaults: degree 6, theta 0.7): sampled rows
-    of the Juffer and internal PMCHWT products against the oracle's rows; the
-    Juffer solve (scaled mass) and the direct one reach the FP64 direct
-    matrix-free Delta G within 1e-5 with the same iterations."""
+    """20480-triangle sphere, FP32 treecode at its defaults: the whole product
+    of the direct, Juffer and internal PMCHWT systems within the accuracy
+    target of the FP64 direct matrix-free product, sampled rows of the Juffer
+    and PMCHWT products within it of the oracle's rows; the Juffer solve
+    (scaled mass) and the direct one reach the FP64 direct matrix-free Delta G
+    within 1e-5 with the same iterations."""
     m, ch = sphere32
     nv = m.n_vertices
     rng = np.random.default_rng(61)
     x = rng.standard_normal(2 * nv)
     rows = np.sort(rng.choice(nv, 6, replace=False))
-    for form in (oracle.JUFFER, oracle.PMCHWT_INT):
-        r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, form, rows, x)
+    for form in (oracle.DIRECT, oracle.JUFFER, oracle.PMCHWT_INT):
         with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_TREECODE)) as h:
             y = pbm.pb_mesh_apply(h, x)
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(form)) as h:
+            yd = pbm.pb_mesh_apply(h, x)
+        print(f"treecode full size form {form}: product rel {_rel(y, yd):.2e}")
+        assert _rel(y, yd) < TREE_TARGET, (form, _rel(y, yd))
+        if form == oracle.DIRECT:
+            continue
+        r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, form, rows, x)
         got = np.concatenate([y[rows], y[nv + rows]])
-        print(f"treecode full size form {form}: rows rel {_rel(got, np.concatenate([r1, r2])):.2e}")
-        assert _rel(got, np.concatenate([r1, r2])) < 5e-6   # the defaults' error is about 1e-6 here
+        assert _rel(got, np.concatenate([r1, r2])) < TREE_TARGET
     for form, prec in ((pbm.PB_JUFFER, pbm.PB_SCALED_MASS), (pbm.PB_DIRECT_INT, pbm.PB_BLOCK_DIAG)):
         ref = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, preconditioner=prec))
         got = pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, _opts(form, pbm.PB_FP32, preconditioner=prec,

@@ -446,6 +446,26 @@ def test_every_formulation_reaches_kirkwood(form):
     assert errs[1] < 0.03 and errs[1] < errs[0] / 2.5, (errs, ref)
 
 
+@pytest.mark.parametrize("form", [oracle.DIRECT, oracle.JUFFER])
+def test_one_point_regular_rule_solve_converges(form):
+    """Regular order 1 (the one-point rule on every pair sharing no vertex,
+    Sauter-Schwab and the 6-point source projection and Delta G kept): the
+    Kirkwood central-charge error falls at least at first order (halving per
+    refinement) and stays within 0.6 percentage points of the 6-point rule's
+    on the coarsest mesh."""
+    errs = []
+    for f in (4, 8, 16):
+        m, ch = inputs.config_kirkwood(f, 2.0)
+        r = oracle.solve(m, ch, formulation=form, centroid=True)
+        assert r["rel_residual"] < 1e-5 * 1.01
+        errs.append(abs(r["dG"] - kirkwood_central(2.0)) / abs(kirkwood_central(2.0)))
+        if f == 4:
+            r6 = oracle.solve(m, ch, formulation=form)
+            e6 = abs(r6["dG"] - kirkwood_central(2.0)) / abs(kirkwood_central(2.0))
+            assert abs(errs[0] - e6) < 0.006, (errs[0], e6)
+    assert errs[0] / errs[1] > 2.0 and errs[1] / errs[2] > 2.0, errs
+
+
 # ------------------------------------------------- combined field (alpha, beta)
 def test_cfie_reduces_to_the_printed_formulations():
     """The combined-field systems (Eqs. bie:combined:int, bie:combined:ext,
