@@ -53,12 +53,14 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X published vector peaks
 ASM_FLOPS_PER_PP = {0: 25.83, 1: 29.25}
 ASM_LANE_OPS_PER_PP = {0: 20.0, 1: 22.25}   # one of them transcendental (half of rsqrt + exp2)
 ASM_TRANS_PER_PP = 1.0
-# executed VALU instructions per kernel pair in k_far's inner loop (AMD assembly
-# of this build's k_far<float, FORM>, loop body / 36 point pairs): non-transcendental
-# ones, and the two transcendentals (v_rsq_f32, v_exp_f32) whose issue cost in
-# FMA slots is measured (profiles/peaks.json)
-FAR_LANE_OPS_PER_PAIR = {0: 18.67, 1: 30.08}
-FAR_TRANS_PER_PAIR = 2.0
+# executed VALU instructions per (ordered) kernel pair in the FP32 far field of
+# meshes of 8192 triangles and more, k_far_sym<FORM> (AMD assembly of this
+# build: the step body / 36 unordered point pairs / 2 directions):
+# non-transcendental ones, and the transcendentals (one v_rsq_f32 and one
+# v_exp_f32 per unordered pair) whose issue cost in FMA slots is measured
+# (profiles/peaks.json)
+FAR_LANE_OPS_PER_PAIR = {0: 13.42, 1: 20.5}
+FAR_TRANS_PER_PAIR = 1.0
 
 
 def measured_traffic(workload_key: str, kernel: str = "assembly"):

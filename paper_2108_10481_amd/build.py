@@ -20,7 +20,7 @@ PEAKS_SRC = "peaks.hip"
 PEAKS_OUT = os.path.join(HERE, "libpbm_peaks.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("PBM_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["mesh_prep.cpp", "k_geometry.hip", "k_near.hip", "k_far.hip", "k_tree.hip", "k_krylov.hip", "k_dense.hip",
+SOURCES = ["mesh_prep.cpp", "k_geometry.hip", "k_near.hip", "k_far.hip", "k_far_sym.hip", "k_tree.hip", "k_krylov.hip", "k_dense.hip",
            "k_batch.hip", "runtime.hip", "server.cpp", "autotune.cpp"]
 FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

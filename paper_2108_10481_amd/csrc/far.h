@@ -49,6 +49,7 @@ struct FarReq {
     const int *skip;   // when set and nonzero (the request's GMRES stopped), its items do nothing
     FarCoef<R> cf;
     int T, chunk;
+    int rt, nr;        // symmetric split (k_far_sym.hip): tiles per range, ranges; 0 if unused
 };
 
 // One source triangle against the six points of a target triangle: the

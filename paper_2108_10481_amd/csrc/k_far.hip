@@ -394,6 +394,10 @@ int choose_chunks(int T)
 template <typename R>
 static void far_launch(DevMesh &d, const R *stat, const R *dyn)
 {
+    if (sizeof(R) == 4 && d.sym_nitems > 0) {
+        launch_far_sym(d);   // FP32, every unordered pair once (k_far_sym.hip)
+        return;
+    }
     const int T = d.hm.T, S = d.S;
     const int chunk = (T + S - 1) / S;
     FarCoef<R> cf;
@@ -450,6 +454,7 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
     for (int f = 0; f < 4; ++f) fb.nitems[f] = 0;
     std::vector<FarReq<R>> reqs(ds.size());
     std::vector<std::vector<std::pair<int, int4>>> q(4);   // (cost, item) per form
+    std::vector<std::vector<std::pair<int, int4>>> sq(3);  // symmetric items per form 0, 1, 3
     for (int r : live) {
         DevMesh &d = *ds[r];
         FarReq<R> &rq = reqs[r];
@@ -462,13 +467,29 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         rq.skip = skip.empty() ? nullptr : skip[r];
         rq.T = T;
         rq.chunk = chunk;
+        rq.rt = rq.nr = 0;
+        if (sizeof(R) == 4 && d.sym_nitems > 0) {
+            // symmetric split: the request's range pairs, in its own (heaviest first) order
+            rq.rt = d.sym_rt;
+            rq.nr = d.sym_nr;
+            std::vector<int2> its;
+            int rt = 0, nr = 0;
+            sym_plan(T, rt, nr, its);
+            const int sf = form == 0 ? 0 : form == 1 ? 1 : 2;
+            for (const int2 &e : its) {
+                const int na = std::min((T + 63) / 64, (e.x + 1) * rt) - e.x * rt;
+                const int nb = std::min((T + 63) / 64, (e.y + 1) * rt) - e.y * rt;
+                sq[sf].push_back({e.x == e.y ? na * (na + 1) / 2 : na * nb, make_int4(r, e.x, e.y, 0)});
+            }
+            continue;
+        }
         // every chunk, empty ones too: k_far_finish sums all S of them
         for (int c = 0; c < S; ++c) {
             const int len = std::max(0, std::min(T, (c + 1) * chunk) - c * chunk);
             for (int t0 = 0; t0 < T; t0 += 64) q[form].push_back({len, make_int4(r, t0, c, 0)});
         }
     }
-    std::vector<int4> items;
+    std::vector<int4> items, sitems;
     for (int f = 0; f < 4; ++f) {
         std::stable_sort(q[f].begin(), q[f].end(),
                          [](const std::pair<int, int4> &a, const std::pair<int, int4> &b) { return a.first > b.first; });
@@ -476,6 +497,23 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         for (auto &e : q[f]) items.push_back(e.second);
         fb.nitems[f] = (int)q[f].size();
     }
+    for (int f = 0; f < 3; ++f) {
+        std::stable_sort(sq[f].begin(), sq[f].end(),
+                         [](const std::pair<int, int4> &a, const std::pair<int, int4> &b) { return a.first > b.first; });
+        fb.sym_first[f] = (int)sitems.size();
+        for (auto &e : sq[f]) sitems.push_back(e.second);
+        fb.sym_n[f] = (int)sq[f].size();
+        fb.sym_nblocks[f] = fb.sym_n[f] ? sym_batch_blocks_for(f == 0 ? 0 : f == 1 ? 1 : 3, fb.sym_n[f]) : 0;
+    }
+    const size_t sb = sizeof(int4) * std::max<size_t>(sitems.size(), 1);
+    if (sb > fb.sym_cap) {
+        if (fb.sym_items) HIPCHECK(hipFree(fb.sym_items));
+        HIPCHECK(hipMalloc(&fb.sym_items, sb));
+        fb.sym_cap = sb;
+    }
+    if (!sitems.empty())
+        HIPCHECK(hipMemcpyAsync(fb.sym_items, sitems.data(), sizeof(int4) * sitems.size(), hipMemcpyHostToDevice,
+                                fb.stream));
     fb.nblocks[0] = fb.nitems[0] ? batch_blocks<R, 0>(fb.nitems[0]) : 0;
     fb.nblocks[1] = fb.nitems[1] ? batch_blocks<R, 1>(fb.nitems[1]) : 0;
     fb.nblocks[2] = 0;   // kernel forms 0, 1 and 3 only
@@ -491,7 +529,7 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         HIPCHECK(hipMalloc(&fb.items, ib));
         fb.item_cap = ib;
     }
-    if (!fb.next) HIPCHECK(hipMalloc(&fb.next, 4 * sizeof(int)));
+    if (!fb.next) HIPCHECK(hipMalloc(&fb.next, 7 * sizeof(int)));
     HIPCHECK(hipMemcpyAsync(fb.reqs, reqs.data(), rb, hipMemcpyHostToDevice, fb.stream));
     if (!items.empty())
         HIPCHECK(hipMemcpyAsync(fb.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice,
@@ -522,6 +560,10 @@ void launch_far_batch(FarBatch &fb, bool fp32)
 {
     if (fp32) {
         batch_launch<float, 0>(fb); batch_launch<float, 1>(fb); batch_launch<float, 3>(fb);
+        const int forms[3] = {0, 1, 3};
+        for (int f = 0; f < 3; ++f)
+            launch_far_sym_batch(forms[f], fb.reqs, (const int4 *)fb.sym_items + fb.sym_first[f], fb.sym_n[f],
+                                 fb.sym_nblocks[f], fb.next + 4 + f, fb.stream);
     } else {
         batch_launch<double, 0>(fb); batch_launch<double, 1>(fb); batch_launch<double, 3>(fb);
     }
@@ -531,11 +573,13 @@ void far_batch_free(FarBatch &fb)
 {
     if (fb.reqs) (void)hipFree(fb.reqs);
     if (fb.items) (void)hipFree(fb.items);
+    if (fb.sym_items) (void)hipFree(fb.sym_items);
     if (fb.next) (void)hipFree(fb.next);
     fb.reqs = nullptr;
     fb.items = nullptr;
+    fb.sym_items = nullptr;
     fb.next = nullptr;
-    fb.req_cap = fb.item_cap = 0;
+    fb.req_cap = fb.item_cap = fb.sym_cap = 0;
 }
 
 template <typename R>
@@ -565,6 +609,10 @@ void launch_far_centroid(DevMesh &d, bool fp32)
 
 void launch_far_finish(DevMesh &d, bool fp32)
 {
+    if (fp32 && d.sym_nitems > 0 && d.far_rule == 0 && !d.tree) {
+        launch_far_sym_finish(d);   // the symmetric far field's slots
+        return;
+    }
     const int T = d.hm.T;
     dim3 grid((unsigned)(((size_t)T * kFinishLanes + 255) / 256)), block(256);
     const FormCoef &f = d.fm;

@@ -198,6 +198,12 @@ struct DevMesh {
     Params prm;
     pb_options opt;
     int S = 1;                     // far-field source chunks
+    // symmetric FP32 far field (k_far_sym.hip): tiles per range, ranges, work
+    // list of range pairs (heaviest first), its counter, blocks per kernel form
+    int sym_rt = 0, sym_nr = 0, sym_nitems = 0;
+    int2 *sym_items = nullptr;
+    int *sym_next = nullptr;
+    int sym_blocks[3] = {1, 1, 1};
     hipStream_t stream = nullptr;
     size_t bytes = 0;
     std::vector<void *> allocs;
@@ -301,9 +307,13 @@ struct FarBatch {
     hipStream_t stream = nullptr;
     void *reqs = nullptr;
     void *items = nullptr;
-    int *next = nullptr;           // one queue counter per kernel form
+    int *next = nullptr;           // one queue counter per kernel form, then three for the symmetric queues
     size_t req_cap = 0, item_cap = 0;
     int first[4] = {0, 0, 0, 0}, nitems[4] = {0, 0, 0, 0}, nblocks[4] = {0, 0, 0, 0};
+    // symmetric FP32 items {request, a, b} of the requests with a symmetric split (forms 0, 1, 3)
+    void *sym_items = nullptr;
+    size_t sym_cap = 0;
+    int sym_first[3] = {0, 0, 0}, sym_n[3] = {0, 0, 0}, sym_nblocks[3] = {0, 0, 0};
 };
 // skip (empty, or one per handle): device stop flags; a request whose flag is
 // set contributes no work (captured iterations keep replaying after it stops)
@@ -325,6 +335,15 @@ void launch_pair_blocks_subset(DevMesh &d, int n, const int32_t *t_sorted, const
 void ss_group(const std::vector<int32_t> &tri, int n, const int32_t *t, const int32_t *s, std::vector<int32_t> &idx,
               int count[4]);
 int choose_chunks(int T);
+// symmetric FP32 far field (k_far_sym.hip)
+bool sym_eligible(int T);
+void sym_plan(int T, int &rt, int &nr, std::vector<int2> &items);
+int sym_blocks(int nitems, int form);
+void launch_far_sym(DevMesh &d);
+void launch_far_sym_finish(DevMesh &d);
+int sym_batch_blocks_for(int form, int n);
+void launch_far_sym_batch(int form, const void *reqs, const int4 *items, int n, int nblocks, int *next,
+                          hipStream_t s);
 int reduction_chunks(int T);
 pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res);
 int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);

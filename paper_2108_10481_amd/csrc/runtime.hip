@@ -492,7 +492,20 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
     }
     d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
     d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
-    d->part = d->alloc(sizeof(double) * 16 * (size_t)d->S * T);
+    size_t part_bytes = sizeof(double) * 16 * (size_t)d->S * T;
+    if (opt->precision == PB_FP32 && opt->operator_mode != PB_TREECODE && d->far_rule == 0 && sym_eligible(T)) {
+        // symmetric FP32 far field: 2 nr slots of 16 values per triangle
+        std::vector<int2> items;
+        sym_plan(T, d->sym_rt, d->sym_nr, items);
+        d->sym_items = upload(*d, items);
+        d->sym_nitems = (int)items.size();
+        d->sym_next = (int *)d->alloc(sizeof(int));
+        d->sym_blocks[0] = sym_blocks(d->sym_nitems, 0);
+        d->sym_blocks[1] = sym_blocks(d->sym_nitems, 1);
+        d->sym_blocks[2] = sym_blocks(d->sym_nitems, 3);
+        part_bytes = std::max(part_bytes, sizeof(float) * 16 * 2 * (size_t)d->sym_nr * T);
+    }
+    d->part = d->alloc(part_bytes);
     d->triout = (double *)d->alloc(sizeof(double) * 6 * T);
     d->fpts = (double *)d->alloc(sizeof(double) * 12 * T);
     d->xtmp = (double *)d->alloc(sizeof(double) * 2 * V);
@@ -533,7 +546,12 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     auto buf = [](double bytes) { return (double)cache_charge((size_t)bytes); };
     const int S = o->source_chunks > 0 ? std::min(o->source_chunks, T) : choose_chunks(T);
     double b = t * (kGeo * 8 + kStat * 12 + kDyn * 12 + 6 * 8 + 12 * 8 + 3 * 4 * 2);
-    b += buf((double)S * t * 16 * 8);
+    double part = (double)S * t * 16 * 8;
+    if (o->precision == PB_FP32 && o->operator_mode != PB_TREECODE && o->regular_order != 1 && sym_eligible(T)) {
+        const double ntile = std::ceil(t / 64.0), rt = std::ceil(ntile / 320.0);
+        part = std::max(part, 2.0 * std::ceil(ntile / rt) * t * 16 * 4);   // the symmetric far field's slots
+    }
+    b += buf(part);
     b += buf(16.0 * t * (36 * 8 + 3 * 4));
     b += 24.0 * v * (4 * 8 + 4) + v * (4 * 8 + 4 * 4);
     b += 12.0 * n * 8;

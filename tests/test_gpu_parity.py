@@ -189,6 +189,40 @@ def test_full_size_sampled_rows(sphere32, form):
         assert _rel(got, ref) < tol, (prec, _rel(got, ref))
 
 
+@pytest.mark.parametrize("form,a,b", [(pbm.PB_DIRECT_INT, 1.0, 1.0), (pbm.PB_JUFFER, 1.0, 1.0),
+                                       (pbm.PB_DIRECT_EXT, 1.0, 1.0), (pbm.PB_MULLER_INT, 1.0, 1.0),
+                                       (pbm.PB_CFIE_EXT, 0.0, 1.0), (pbm.PB_CFIE_EXT, 0.0, 0.0)])
+def test_symmetric_far_field_full_size(sphere32, form, a, b):
+    """20480-triangle sphere: the FP32 matrix-free far field, which evaluates
+    every unordered pair once for both directions, against the FP64 one, which
+    evaluates every ordered pair (the direct, second-kind and Yukawa-only
+    kernel forms; a zero combined-field constant leaves a row without Laplace
+    terms, both zero no Laplace term at all), within FP32 rounding; and its
+    sampled rows against the oracle's."""
+    m, _ = sphere32
+    nv = m.n_vertices
+    rng = np.random.default_rng(83)
+    x = rng.standard_normal(2 * nv)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, cfie_alpha=a, cfie_beta=b)) as h:
+        y32 = pbm.pb_mesh_apply(h, x)
+        y32b = pbm.pb_mesh_apply(h, x)
+        yf = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_FAR_ONLY)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, cfie_alpha=a, cfie_beta=b)) as h:
+        y64 = pbm.pb_mesh_apply(h, x)
+        yf64 = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_FAR_ONLY)
+    assert np.array_equal(y32, y32b), "the symmetric product must be deterministic"
+    assert _rel(y32, y64) < 2e-6, (form, a, b, _rel(y32, y64))
+    # the far part alone: second-kind rows combine -V_L + V_Y, which cancel to
+    # (1 - exp(-kappa r))/r, about a tenth of either term at the pairs' distances,
+    # so FP32 rounding weighs up to ten times more: the FP32 far-field bound
+    assert _rel(yf, yf64) < 2e-5, (form, a, b, _rel(yf, yf64))
+    rows = np.sort(rng.choice(nv, 4, replace=False))
+    oform = {pbm.PB_DIRECT_INT: oracle.DIRECT, pbm.PB_JUFFER: oracle.JUFFER, pbm.PB_DIRECT_EXT: oracle.DIRECT_EXT,
+             pbm.PB_MULLER_INT: oracle.MULLER_INT, pbm.PB_CFIE_EXT: oracle.CFIE_EXT}[form]
+    r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, oform, rows, x, alpha=a, beta=b)
+    assert _rel(np.concatenate([y32[rows], y32[nv + rows]]), np.concatenate([r1, r2])) < 2e-5
+
+
 def test_full_size_solve_kirkwood(sphere32):
     """Full-size sphere: FP64 and FP32 GPU solves agree to 1e-4 on Delta G and
     both sit within the discretisation error of the Kirkwood series."""
