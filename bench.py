@@ -51,16 +51,38 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X published vector peaks
 # Juffer 32.5 / 26.5, plus the basis contraction in the two-orbit form of the
 # 6-point rule (4.33 flops / 3 lane operations per value); halved per ordered pair
 ASM_FLOPS_PER_PP = {0: 25.83, 1: 29.25}
-ASM_LANE_OPS_PER_PP = {0: 20.0, 1: 22.25}   # one of them transcendental (half of rsqrt + exp2)
-ASM_TRANS_PER_PP = 1.0
-# executed VALU instructions per (ordered) kernel pair in the FP32 far field of
-# meshes of 8192 triangles and more, k_far_sym<FORM> (AMD assembly of this
-# build: the step body / 36 unordered point pairs / 2 directions):
-# non-transcendental ones, and the transcendentals (one v_rsq_f32 and one
-# v_exp_f32 per unordered pair) whose issue cost in FMA slots is measured
-# (profiles/peaks.json)
-FAR_LANE_OPS_PER_PAIR = {0: 13.42, 1: 20.5}
+# VALU issue: a SIMD issues one wave64 VALU instruction per 4 cycles, so the
+# device's issue capacity is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
+# instructions per second.  The rocprofv3 counters show the far-field kernels'
+# transcendentals (v_rsq_f32, v_exp_f32) overlapping the other VALU work there
+# (SQ_ACTIVE_INST_VALU, which counts each of them as two quad-cycles, exceeds
+# the kernel's SIMD cycles), so the issue fraction charges the executed
+# non-transcendental instructions and the transcendentals are reported beside
+# it against the measured v_exp_f32 rate.  Executed non-transcendental VALU
+# lane instructions per ordered kernel pair, from SQ_INSTS_VALU -
+# SQ_INSTS_VALU_TRANS_F32 (profiles/k_far_star81920_trace_and_counters.md,
+# profiles/sphere20480_fp32_assembled_trace_and_traffic.md):
+ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+FAR_VALU_PER_PAIR = {0: 13.61, 1: 20.70}   # k_far_sym<FORM>, one transcendental per pair
 FAR_TRANS_PER_PAIR = 1.0
+ASM_VALU_PER_PP = {0: 23.35, 1: 26.60}     # far-field assembly, one transcendental per pair
+ASM_TRANS_PER_PP = 1.0
+
+
+def valu_issue(pairs_by_form, valu_per_pair, trans_per_pair, seconds, peaks):
+    """Issue fraction of executed non-transcendental VALU lane instructions and
+    the transcendental rate against the measured v_exp_f32 rate."""
+    if seconds <= 0:
+        return None
+    lane = sum(w * valu_per_pair[f] for f, w in pairs_by_form.items()) / seconds
+    trans = sum(w * trans_per_pair for w in pairs_by_form.values()) / seconds
+    out = {"lane_instr_per_s": round(lane, 1), "peak_lane_instr_per_s": ISSUE_PEAK,
+           "frac": round(lane / ISSUE_PEAK, 4), "transcendentals_per_s": round(trans, 1)}
+    if peaks:
+        out["trans_frac_of_measured_exp_rate"] = round(trans / peaks["exp32_lane_ops_per_s"], 4)
+        out["fma_microbenchmark_lane_instr_per_s"] = peaks["fma32_lane_ops_per_s"]
+        out["source"] = "profiles/peaks.json"
+    return out
 
 
 def measured_traffic(workload_key: str, kernel: str = "assembly"):
@@ -233,13 +255,9 @@ def main():
                 "kernel": "far-field assembly (k_fill x2, k_assemble_tile, k_sym_finish x4 per assembly)",
                 "launches": nasm, "avg_launch_ms": round(asm_ms / max(nasm, 1), 4),
                 "point_pair_evals_per_s": round(evals / (asm_ms * 1e-3), 1) if asm_ms > 0 else None}
-        if peaks and dtype == "f32" and asm_ms > 0:
-            slots = sum(prof_asm[f][2] * (ASM_LANE_OPS_PER_PP[f] + ASM_TRANS_PER_PP * (peaks["trans_slots"] - 1))
-                        for f in forms)
-            roof["valu_issue"] = {"slots_per_s": round(slots / (asm_ms * 1e-3), 1),
-                                  "peak_slots_per_s": peaks["fma32_lane_ops_per_s"],
-                                  "frac": round(slots / (asm_ms * 1e-3) / peaks["fma32_lane_ops_per_s"], 4),
-                                  "trans_slots": peaks["trans_slots"], "source": "profiles/peaks.json"}
+        if dtype == "f32" and asm_ms > 0:
+            roof["valu_issue"] = valu_issue({f: prof_asm[f][2] for f in forms}, ASM_VALU_PER_PP, ASM_TRANS_PER_PP,
+                                            asm_ms * 1e-3, peaks)
         # products stream the matrix: each solve's products counted from iterations
         for f in done:
             pairs_timed += sum((r["iterations"] + 1) * float(P) * P for r in res[f])
@@ -260,13 +278,9 @@ def main():
                 "kernel": "k_far (matrix-free far field; k_far_finish and the near field excluded)",
                 "launches": launches, "avg_launch_ms": round(kern_ms / max(launches, 1), 4),
                 "kernel_pairs_per_s": round(pairs_timed / (kern_ms * 1e-3), 1) if kern_ms > 0 else None}
-        if peaks and dtype == "f32" and kern_ms > 0:
-            slots = sum(prof[f][2] * (FAR_LANE_OPS_PER_PAIR[f] + FAR_TRANS_PER_PAIR * peaks["trans_slots"])
-                        for f in forms)
-            roof["valu_issue"] = {"slots_per_s": round(slots / (kern_ms * 1e-3), 1),
-                                  "peak_slots_per_s": peaks["fma32_lane_ops_per_s"],
-                                  "frac": round(slots / (kern_ms * 1e-3) / peaks["fma32_lane_ops_per_s"], 4),
-                                  "trans_slots": peaks["trans_slots"], "source": "profiles/peaks.json"}
+        if dtype == "f32" and kern_ms > 0:
+            roof["valu_issue"] = valu_issue({f: prof[f][2] for f in forms}, FAR_VALU_PER_PAIR, FAR_TRANS_PER_PAIR,
+                                            kern_ms * 1e-3, peaks)
         by_form = {}
         for f in forms:
             n, ms, w = prof[f]
@@ -274,9 +288,8 @@ def main():
                 continue
             e = {"launches": n, "avg_launch_ms": round(ms / n, 3), "kernel_pairs_per_s": round(w / (ms * 1e-3), 1),
                  "tflops": round(w * FLOPS_PER_PAIR[f] / (ms * 1e-3) / 1e12, 3)}
-            if peaks and dtype == "f32":
-                e["valu_issue_frac"] = round(w * (FAR_LANE_OPS_PER_PAIR[f] + FAR_TRANS_PER_PAIR * peaks["trans_slots"])
-                                             / (ms * 1e-3) / peaks["fma32_lane_ops_per_s"], 4)
+            if dtype == "f32":
+                e["valu_issue_frac"] = round(w * FAR_VALU_PER_PAIR[f] / (ms * 1e-3) / ISSUE_PEAK, 4)
             by_form[str(f)] = e
         roof["by_formulation"] = by_form
         dense_product = None
@@ -800,7 +813,8 @@ def measure_peaks():
     cus = lib.pbk_cu_count()
     rates = {}
     for kind, name, iters in ((0, "fma32", 200000), (1, "exp32", 100000), (2, "rsq32", 100000),
-                              (3, "fma4_exp1", 50000), (4, "fma64", 100000), (5, "mfma_bf16", 50000)):
+                              (3, "fma4_exp1", 50000), (4, "fma64", 100000), (5, "mfma_bf16", 50000),
+                              (6, "fma4_exp1_indep", 50000), (7, "fma1_exp1_indep", 100000)):
         ms = ctypes.c_float()
         ops = ctypes.c_double()
         if lib.pbk_compute(kind, 8, iters, ctypes.byref(ms), ctypes.byref(ops)) != 0:
@@ -816,14 +830,25 @@ def measure_peaks():
         bw[name] = factor * nbytes / (ms.value * 1e-3)
         print(f"peaks: {name} {bw[name] / 1e9:.1f} GB/s", file=sys.stderr, flush=True)
     trans = rates["fma32"] / min(rates["exp32"], rates["rsq32"])
-    # the mix: 4 FMA + 1 exp per iteration; if issue slots add, its rate in
-    # lane instructions is 5 / (4 + trans) of the FMA rate
+    # the mixes: n FMA + 1 exp per iteration.  If issue slots add, the rate in
+    # lane instructions is (n + 1) / (n + trans) of the FMA rate; if the
+    # transcendental unit runs beside the FMA pipeline it is (n + 1) / max(n, trans).
+    # The extra FMA-pipeline slots one transcendental takes when independent
+    # FMAs are there to issue: (n + 1) fma / mix - n, from the 4 + 1 mix.
     mix_pred = rates["fma32"] * 5.0 / (4.0 + trans)
+    beside = max(0.0, 5.0 * rates["fma32"] / rates["fma4_exp1_indep"] - 4.0)
     rec = {"device_cus": cus,
            "fma32_lane_ops_per_s": rates["fma32"], "fma32_tflops": 2.0 * rates["fma32"] / 1e12,
            "exp32_lane_ops_per_s": rates["exp32"], "rsq32_lane_ops_per_s": rates["rsq32"],
            "trans_slots": round(trans, 3),
            "mix_4fma_1exp_lane_ops_per_s": rates["fma4_exp1"], "mix_predicted_if_slots_add": mix_pred,
+           "mix_4fma_1exp_indep_lane_ops_per_s": rates["fma4_exp1_indep"],
+           "mix_4fma_1exp_indep_predicted": {"if_slots_add": mix_pred,
+                                             "if_beside": rates["fma32"] * 5.0 / max(4.0, trans)},
+           "mix_1fma_1exp_indep_lane_ops_per_s": rates["fma1_exp1_indep"],
+           "mix_1fma_1exp_indep_predicted": {"if_slots_add": rates["fma32"] * 2.0 / (1.0 + trans),
+                                             "if_beside": rates["fma32"] * 2.0 / max(1.0, trans)},
+           "trans_slots_beside_fma": round(beside, 3),
            "fma64_lane_ops_per_s": rates["fma64"], "fma64_tflops": 2.0 * rates["fma64"] / 1e12,
            "mfma_bf16_tflops": 2.0 * rates["mfma_bf16"] / 1e12,
            "hbm_read_GBps": bw["hbm_read"] / 1e9, "hbm_copy_GBps": bw["hbm_copy"] / 1e9,

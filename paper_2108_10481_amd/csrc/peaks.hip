@@ -1,6 +1,8 @@
 // Measured MI355X (gfx950) peaks for the roofline denominators: FP32 and FP64
 // fused multiply-add, the two transcendentals of the far-field kernels
-// (v_exp_f32, v_rsq_f32), both mixed with FMAs, the BF16 matrix-core
+// (v_exp_f32, v_rsq_f32), exp mixed with FMAs that feed it and with FMAs of
+// independent chains (whether the transcendental unit issues beside the FMA
+// pipeline), the BF16 matrix-core
 // instruction v_mfma_f32_16x16x32_bf16, and an HBM read stream and copy.
 // Measurement only: no part of the solver calls this library.
 //
@@ -24,9 +26,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_valu32(int iters, float a, float b, float *out)
 {
-    float x[kChains];
+    float x[kChains], y[kChains];
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) x[c] = 0.25f + 1e-4f * (threadIdx.x + c);
+    for (int c = 0; c < kChains; ++c) x[c] = y[c] = 0.25f + 1e-4f * (threadIdx.x + c);
 #pragma unroll 4
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
@@ -37,18 +39,27 @@ __global__ __launch_bounds__(kBlock) void k_valu32(int iters, float a, float b, 
                 x[c] = __builtin_amdgcn_exp2f(-x[c]);
             } else if (KIND == 2) {             // 1 rsqrt
                 x[c] = __builtin_amdgcn_rsqf(x[c]);
-            } else {                            // 4 FMA + 1 exp2
-                float y = fmaf(x[c], a, b);
-                y = fmaf(y, a, b);
-                y = fmaf(y, a, b);
-                y = fmaf(y, a, b);
-                x[c] = __builtin_amdgcn_exp2f(-y);
+            } else if (KIND == 3) {             // 4 FMA + 1 exp2 of their result
+                float z = fmaf(x[c], a, b);
+                z = fmaf(z, a, b);
+                z = fmaf(z, a, b);
+                z = fmaf(z, a, b);
+                x[c] = __builtin_amdgcn_exp2f(-z);
+            } else if (KIND == 4) {             // 4 FMA, 1 exp2 of an independent chain
+                float z = fmaf(x[c], a, b);
+                z = fmaf(z, a, b);
+                z = fmaf(z, a, b);
+                x[c] = fmaf(z, a, b);
+                y[c] = __builtin_amdgcn_exp2f(-y[c]);
+            } else {                            // 1 FMA, 1 exp2 of an independent chain
+                x[c] = fmaf(x[c], a, b);
+                y[c] = __builtin_amdgcn_exp2f(-y[c]);
             }
         }
     }
     float s = 0.0f;
 #pragma unroll
-    for (int c = 0; c < kChains; ++c) s += x[c];
+    for (int c = 0; c < kChains; ++c) s += x[c] + y[c];
     out[(size_t)blockIdx.x * kBlock + threadIdx.x] = s;
 }
 
@@ -139,15 +150,16 @@ extern "C" {
 // Number of compute units of device 0 (-1 on error).
 int pbk_cu_count(void) { return cu_count(); }
 
-// kind 0..3: FP32 FMA, exp2, rsqrt, 4 FMA + 1 exp2; kind 4: FP64 FMA;
-// kind 5: BF16 MFMA 16x16x32.  blocks_per_cu blocks of 256 lanes per CU,
+// kind 0..3: FP32 FMA, exp2, rsqrt, 4 FMA + 1 exp2 of their result; kind 4:
+// FP64 FMA; kind 5: BF16 MFMA 16x16x32; kind 6: 4 FMA + 1 independent exp2;
+// kind 7: 1 FMA + 1 independent exp2.  blocks_per_cu blocks of 256 lanes per CU,
 // iters loop iterations.  *ms: duration of one timed launch; *lane_ops:
 // instructions times lanes executed (MFMA: multiply-adds).  Returns 0 on
 // success.
 int pbk_compute(int kind, int blocks_per_cu, int iters, float *ms, double *lane_ops)
 {
     const int cus = cu_count();
-    if (cus <= 0 || blocks_per_cu < 1 || iters < 1 || kind < 0 || kind > 5) return -1;
+    if (cus <= 0 || blocks_per_cu < 1 || iters < 1 || kind < 0 || kind > 7) return -1;
     const int blocks = cus * blocks_per_cu;
     void *out = nullptr;
     if (hipMalloc(&out, (size_t)blocks * kBlock * sizeof(double)) != hipSuccess) return -1;
@@ -164,8 +176,12 @@ int pbk_compute(int kind, int blocks_per_cu, int iters, float *ms, double *lane_
             *lane_ops = lanes * iters * kChains * 5.0; break;
     case 4: rc = timed([&] { k_fma64<<<blocks, kBlock>>>(iters, 0.999, 1e-3, (double *)out); }, ms);
             *lane_ops = lanes * iters * kChains; break;
-    default: rc = timed([&] { k_mfma_bf16<<<blocks, kBlock>>>(iters, (float *)out); }, ms);
+    case 5: rc = timed([&] { k_mfma_bf16<<<blocks, kBlock>>>(iters, (float *)out); }, ms);
             *lane_ops = (double)blocks * (kBlock / 64) * iters * 4.0 * 16 * 16 * 32; break;
+    case 6: rc = timed([&] { k_valu32<4><<<blocks, kBlock>>>(iters, 0.999f, 1e-3f, (float *)out); }, ms);
+            *lane_ops = lanes * iters * kChains * 5.0; break;
+    default: rc = timed([&] { k_valu32<5><<<blocks, kBlock>>>(iters, 0.999f, 1e-3f, (float *)out); }, ms);
+            *lane_ops = lanes * iters * kChains * 2.0; break;
     }
     (void)hipFree(out);
     return rc;
