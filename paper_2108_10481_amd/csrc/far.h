@@ -128,6 +128,88 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
     }
 }
 
+// ------------------------------------------------- far-field finish pieces
+// P1 test projection of one target triangle's 15 point sums (6 + 6 point
+// sums, 3 curl sums) into its 6 outputs (3 hats x 2 rows, 1/4pi and |t|
+// applied).  family 0: rows (Laplace, Yukawa), swapped when the Laplace row
+// is row 2; family 1: row 2 gets D's curl part (its coefficients applied by
+// the producers).
+__device__ __forceinline__ void far_project(int t, int family, int swap, const double *__restrict__ geo,
+                                            const double (&pot)[15], double *__restrict__ triout)
+{
+    const double *g = geo + (size_t)t * kGeo;
+    const double sc = g[21] * kInv4Pi;
+    for (int k = 0; k < 3; ++k) {
+        double y1 = 0.0, y2 = 0.0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) {
+            const double w = rule_w(p) * rule_bary(p, k);
+            y1 += w * pot[p];
+            y2 += w * pot[6 + p];
+        }
+        if (family == 1) y2 += g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14];
+        if (swap) { const double tmp = y1; y1 = y2; y2 = tmp; }
+        triout[6 * (size_t)t + k] = sc * y1;
+        triout[6 * (size_t)t + 3 + k] = sc * y2;
+    }
+}
+
+// kFinishLanes lanes per target sum every kFinishLanes-th partial, then a
+// fixed butterfly inside the lane group (one wavefront holds whole groups)
+constexpr int kFinishLanes = 16;
+
+// regular split: lane l of target t's group over the S chunk partials; every
+// lane of the group calls it (ok: t < T, the same for the whole group)
+template <typename R>
+__device__ __forceinline__ void finish_group(int t, int l, bool ok, int T, int S, int family, int swap,
+                                             const double *__restrict__ geo, const R *__restrict__ part,
+                                             double *__restrict__ triout)
+{
+    double pot[15];
+#pragma unroll
+    for (int v = 0; v < 15; ++v) pot[v] = 0.0;
+    if (ok)
+        for (int c = l; c < S; c += kFinishLanes) {
+            const R *o = part + ((size_t)c * T + t) * 16;
+#pragma unroll
+            for (int v = 0; v < 15; ++v) pot[v] += (double)o[v];
+        }
+#pragma unroll
+    for (int v = 0; v < 15; ++v)
+#pragma unroll
+        for (int off = kFinishLanes / 2; off > 0; off >>= 1) pot[v] += __shfl_xor(pot[v], off);
+    if (!ok || l != 0) return;
+    far_project(t, family, swap, geo, pot, triout);
+}
+
+// symmetric split (ranges of rt tiles of 64 triangles, nr ranges): target t's
+// nr + 1 slots, the target-side slots of the source ranges b >= c and the
+// source-side slots of the target ranges a <= c (c its own range)
+__device__ __forceinline__ void sym_finish_group(int t, int l, bool ok, int T, int rt, int nr, int family, int swap,
+                                                 const double *__restrict__ geo, const float *__restrict__ part,
+                                                 double *__restrict__ triout)
+{
+    double pot[15];
+#pragma unroll
+    for (int v = 0; v < 15; ++v) pot[v] = 0.0;
+    if (ok) {
+        const int c = (t / 64) / rt;
+        const int nslot = (nr - c) + (c + 1);
+        for (int k = l; k < nslot; k += kFinishLanes) {
+            const int slot = k < nr - c ? c + k : nr + (k - (nr - c));
+            const float *o = part + ((size_t)slot * T + t) * 16;
+#pragma unroll
+            for (int v = 0; v < 15; ++v) pot[v] += (double)o[v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 15; ++v)
+#pragma unroll
+        for (int off = kFinishLanes / 2; off > 0; off >>= 1) pot[v] += __shfl_xor(pot[v], off);
+    if (!ok || l != 0) return;
+    far_project(t, family, swap, geo, pot, triout);
+}
+
 // coefficients of the current operator fields; returns the kernel FORM
 template <typename R>
 inline int far_coef(const DevMesh &d, FarCoef<R> &cf)

@@ -21,15 +21,14 @@
 
 namespace pbm {
 
-// dync, dync64 (either may be null): the one-point rule's source weights
-// |s| mean(u1), |s| mean(u2) in FP32 / FP64
-__global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, const double *__restrict__ geo,
-                              const double *__restrict__ x, double *__restrict__ dyn64, float *__restrict__ dyn32,
-                              float *__restrict__ dync, double *__restrict__ dync64, DevCtl ctl)
+// Source weights of triangle s from the vector x (2V): b1 = w |s| u1(y_q),
+// b2 = w |s| u2(y_q), C = |s| curl u1; dync, dync64 (either may be null): the
+// one-point rule's source weights |s| mean(u1), |s| mean(u2) in FP32 / FP64.
+__device__ __forceinline__ void source_prep_tri(int s, int V, const int32_t *__restrict__ tri,
+                                                const double *__restrict__ geo, const double *__restrict__ x,
+                                                double *__restrict__ dyn64, float *__restrict__ dyn32,
+                                                float *__restrict__ dync, double *__restrict__ dync64)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= T || ctl_skip(ctl)) return;
-    x += ctl_off(ctl);
     const double *g = geo + (size_t)s * kGeo;
     const double area = g[21];
     double u1[3], u2[3];
@@ -65,6 +64,15 @@ __global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, con
         dync64[2 * (size_t)s] = area * (u1[0] + u1[1] + u1[2]) / 3.0;
         dync64[2 * (size_t)s + 1] = area * (u2[0] + u2[1] + u2[2]) / 3.0;
     }
+}
+
+__global__ void k_source_prep(int T, int V, const int32_t *__restrict__ tri, const double *__restrict__ geo,
+                              const double *__restrict__ x, double *__restrict__ dyn64, float *__restrict__ dyn32,
+                              float *__restrict__ dync, double *__restrict__ dync64, DevCtl ctl)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= T || ctl_skip(ctl)) return;
+    source_prep_tri(s, V, tri, geo, x + ctl_off(ctl), dyn64, dyn32, dync, dync64);
 }
 
 void launch_source_prep(DevMesh &d, const double *x, bool)
@@ -274,13 +282,6 @@ __global__ __launch_bounds__(kFarBlock) void k_far_centroid(int T, int chunk, Fa
     o[12] = (R)X0; o[13] = (R)X1; o[14] = (R)X2; o[15] = 0;
 }
 
-// family 0: rows (Laplace, Yukawa), swapped when the Laplace row is row 2;
-// family 1: row 2 gets D's curl part (its coefficients applied by the producers)
-// kFinishLanes lanes per target sum every kFinishLanes-th chunk, then a fixed
-// butterfly inside the lane group (one wavefront holds whole groups): with
-// one thread per target a small mesh gave too few threads for up to 128 chunks.
-constexpr int kFinishLanes = 16;
-
 template <typename R>
 __global__ __launch_bounds__(256) void k_far_finish(int T, int S, int family, int swap,
                                                     const double *__restrict__ geo, const R *__restrict__ part,
@@ -289,53 +290,21 @@ __global__ __launch_bounds__(256) void k_far_finish(int T, int S, int family, in
     if (ctl_skip(ctl)) return;
     const int t = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kFinishLanes);
     const int l = threadIdx.x % kFinishLanes;
-    const bool ok = t < T;   // the whole lane group agrees
-    double pot[15];
-#pragma unroll
-    for (int v = 0; v < 15; ++v) pot[v] = 0.0;
-    if (ok)
-        for (int c = l; c < S; c += kFinishLanes) {
-            const R *o = part + ((size_t)c * T + t) * 16;
-#pragma unroll
-            for (int v = 0; v < 15; ++v) pot[v] += (double)o[v];
-        }
-#pragma unroll
-    for (int v = 0; v < 15; ++v)
-#pragma unroll
-        for (int off = kFinishLanes / 2; off > 0; off >>= 1) pot[v] += __shfl_xor(pot[v], off);
-    if (!ok || l != 0) return;
-    const double *g = geo + (size_t)t * kGeo;
-    const double sc = g[21] * kInv4Pi;
-    for (int k = 0; k < 3; ++k) {
-        double y1 = 0.0, y2 = 0.0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const double w = rule_w(p) * rule_bary(p, k);
-            y1 += w * pot[p];
-            y2 += w * pot[6 + p];
-        }
-        if (family == 1) y2 += g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14];
-        if (swap) { const double tmp = y1; y1 = y2; y2 = tmp; }
-        triout[6 * (size_t)t + k] = sc * y1;
-        triout[6 * (size_t)t + 3 + k] = sc * y2;
-    }
+    finish_group<R>(t, l, t < T, T, S, family, swap, geo, part, triout);   // the whole lane group agrees on t < T
 }
 
-// flags: PB_APPLY_PRECOND, PB_APPLY_NEAR_ONLY, PB_APPLY_FAR_ONLY (near part skipped)
-__global__ void k_gather(int V, int use_far, int use_near, int precond, const int32_t *__restrict__ inc_ptr,
-                         const int32_t *__restrict__ inc_tk, const double *__restrict__ triout,
-                         const double *__restrict__ yfar, const int32_t *__restrict__ vpos,
-                         const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                         const double *__restrict__ N, int64_t nnz, const double *__restrict__ pinv,
-                         const double *__restrict__ x, double *__restrict__ y, DevCtl ctl, DevCtl ctly)
+// Row i of the product, lane c of its kRowLanes group (every lane of the group
+// calls it): near-field CSR product, the far field (1: per-triangle outputs
+// through the vertex's incidence list, 2: a dense product's rows in dense
+// vertex order), optional 2x2 preconditioner; x, y already offset.
+__device__ __forceinline__ void gather_row(int i, int c, int V, int use_far, int use_near, int precond,
+                                           const int32_t *__restrict__ inc_ptr, const int32_t *__restrict__ inc_tk,
+                                           const double *__restrict__ triout, const double *__restrict__ yfar,
+                                           const int32_t *__restrict__ vpos, const int32_t *__restrict__ row_ptr,
+                                           const int32_t *__restrict__ col, const double *__restrict__ N,
+                                           int64_t nnz, const double *__restrict__ pinv,
+                                           const double *__restrict__ x, double *__restrict__ y)
 {
-    // kRowLanes lanes per row; the lane group sits inside one wavefront, so a
-    // whole group is either active or retired together
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
-    const int c = threadIdx.x % kRowLanes;
-    if (i >= V || ctl_skip(ctl)) return;
-    x += ctl_off(ctl);
-    y += ctl_off(ctly);
     double n1 = 0.0, n2 = 0.0;
     if (use_near) {
         for (int sl = row_ptr[i] + c; sl < row_ptr[i + 1]; sl += kRowLanes) {
@@ -376,6 +345,99 @@ __global__ void k_gather(int V, int use_far, int use_near, int precond, const in
     }
     y[i] = y1;
     y[V + i] = y2;
+}
+
+// flags: PB_APPLY_PRECOND, PB_APPLY_NEAR_ONLY, PB_APPLY_FAR_ONLY (near part skipped)
+__global__ void k_gather(int V, int use_far, int use_near, int precond, const int32_t *__restrict__ inc_ptr,
+                         const int32_t *__restrict__ inc_tk, const double *__restrict__ triout,
+                         const double *__restrict__ yfar, const int32_t *__restrict__ vpos,
+                         const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                         const double *__restrict__ N, int64_t nnz, const double *__restrict__ pinv,
+                         const double *__restrict__ x, double *__restrict__ y, DevCtl ctl, DevCtl ctly)
+{
+    // kRowLanes lanes per row; the lane group sits inside one wavefront, so a
+    // whole group is either active or retired together
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
+    const int c = threadIdx.x % kRowLanes;
+    if (i >= V || ctl_skip(ctl)) return;
+    gather_row(i, c, V, use_far, use_near, precond, inc_ptr, inc_tk, triout, yfar, vpos, row_ptr, col, N, nnz,
+               pinv, x + ctl_off(ctl), y + ctl_off(ctly));
+}
+
+// ------------------------- batched steps of a captured lockstep iteration
+// One launch per step for every solve of the batch (TailReq per solve, block
+// ranges boff per solve as in the batched Krylov steps); each block runs the
+// single kernel's code for its solve, so the results are bitwise the same.
+__device__ __forceinline__ int tail_owner(const int *__restrict__ boff, int R, int b)
+{
+    int lo = 0, hi = R - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_bsource_prep(int R, const TailReq *__restrict__ rq, const int *__restrict__ boff)
+{
+    const int r = tail_owner(boff, R, blockIdx.x);
+    const TailReq &q = rq[r];
+    const int s = (blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    if (s >= q.T || ctl_skip(q.ctl)) return;
+    source_prep_tri(s, q.V, q.tri, q.geo, q.x + ctl_off(q.ctl), q.dyn64, q.dyn32, nullptr, nullptr);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_bfinish(int NR, const TailReq *__restrict__ rq, const int *__restrict__ boff)
+{
+    const int r = tail_owner(boff, NR, blockIdx.x);
+    const TailReq &q = rq[r];
+    if (ctl_skip(q.ctl)) return;   // uniform: the block belongs to one solve
+    const int t = (int)(((blockIdx.x - boff[r]) * (size_t)blockDim.x + threadIdx.x) / kFinishLanes);
+    const int l = threadIdx.x % kFinishLanes;
+    if (sizeof(R) == 4 && q.nr > 0)
+        sym_finish_group(t, l, t < q.T, q.T, q.rt, q.nr, q.family, q.swap, q.geo, (const float *)q.part, q.triout);
+    else
+        finish_group<R>(t, l, t < q.T, q.T, q.S, q.family, q.swap, q.geo, (const R *)q.part, q.triout);
+}
+
+__global__ void k_bgather(int R, const TailReq *__restrict__ rq, const int *__restrict__ boff)
+{
+    const int r = tail_owner(boff, R, blockIdx.x);
+    const TailReq &q = rq[r];
+    const int i = ((blockIdx.x - boff[r]) * blockDim.x + threadIdx.x) / kRowLanes;
+    const int c = threadIdx.x % kRowLanes;
+    if (i >= q.V || ctl_skip(q.ctl)) return;
+    const size_t off = ctl_off(q.ctl);
+    gather_row(i, c, q.V, 1, 1, q.precond, q.inc_ptr, q.inc_tk, q.triout, nullptr, nullptr, q.row_ptr, q.col, q.N,
+               q.nnz, q.pinv, q.x + off, q.gout + (q.gout_offset ? off : 0));
+}
+
+int tail_blocks_source(const TailReq &q) { return (q.T + 255) / 256; }
+int tail_blocks_finish(const TailReq &q) { return (int)(((size_t)q.T * kFinishLanes + 255) / 256); }
+int tail_blocks_gather(const TailReq &q) { return (q.V + 256 / kRowLanes - 1) / (256 / kRowLanes); }
+
+void launch_batch_source_prep(hipStream_t s, int R, const TailReq *rq, const int *boff, int nblocks)
+{
+    if (nblocks < 1) return;
+    hipLaunchKernelGGL(k_bsource_prep, dim3(nblocks), dim3(256), 0, s, R, rq, boff);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_batch_finish(hipStream_t s, bool fp32, int R, const TailReq *rq, const int *boff, int nblocks)
+{
+    if (nblocks < 1) return;
+    if (fp32) hipLaunchKernelGGL(k_bfinish<float>, dim3(nblocks), dim3(256), 0, s, R, rq, boff);
+    else hipLaunchKernelGGL(k_bfinish<double>, dim3(nblocks), dim3(256), 0, s, R, rq, boff);
+    HIPCHECK(hipGetLastError());
+}
+
+void launch_batch_gather(hipStream_t s, int R, const TailReq *rq, const int *boff, int nblocks)
+{
+    if (nblocks < 1) return;
+    hipLaunchKernelGGL(k_bgather, dim3(nblocks), dim3(256), 0, s, R, rq, boff);
+    HIPCHECK(hipGetLastError());
 }
 
 int choose_chunks(int T)

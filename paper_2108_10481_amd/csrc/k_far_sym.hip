@@ -279,53 +279,17 @@ __global__ __launch_bounds__(64 * kSymWaves) void k_far_sym_batch(const FarReq<f
     }
 }
 
-// kFinishLanes lanes per triangle over its nr + 1 slots (target-side slots of
-// the source ranges b >= c, source-side slots of the target ranges a <= c, c
-// its own range), then the test projection of k_far_finish
-constexpr int kSymFinishLanes = 16;
+// kFinishLanes lanes per triangle over its nr + 1 slots, then the test
+// projection of k_far_finish (sym_finish_group, far.h)
 __global__ __launch_bounds__(256) void k_far_sym_finish(int T, int rt, int nr, int family, int swap,
                                                           const double *__restrict__ geo,
                                                           const float *__restrict__ part,
                                                           double *__restrict__ triout, DevCtl ctl)
 {
     if (ctl_skip(ctl)) return;
-    const int t = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kSymFinishLanes);
-    const int l = threadIdx.x % kSymFinishLanes;
-    const bool ok = t < T;   // the whole lane group agrees
-    double pot[15];
-#pragma unroll
-    for (int v = 0; v < 15; ++v) pot[v] = 0.0;
-    if (ok) {
-        const int c = (t / 64) / rt;
-        // slot list: b = c .. nr-1 (target side), then nr + a for a = 0 .. c (source side)
-        const int nslot = (nr - c) + (c + 1);
-        for (int k = l; k < nslot; k += kSymFinishLanes) {
-            const int slot = k < nr - c ? c + k : nr + (k - (nr - c));
-            const float *o = part + ((size_t)slot * T + t) * 16;
-#pragma unroll
-            for (int v = 0; v < 15; ++v) pot[v] += (double)o[v];
-        }
-    }
-#pragma unroll
-    for (int v = 0; v < 15; ++v)
-#pragma unroll
-        for (int off = kSymFinishLanes / 2; off > 0; off >>= 1) pot[v] += __shfl_xor(pot[v], off);
-    if (!ok || l != 0) return;
-    const double *g = geo + (size_t)t * kGeo;
-    const double sc = g[21] * kInv4Pi;
-    for (int k = 0; k < 3; ++k) {
-        double y1 = 0.0, y2 = 0.0;
-#pragma unroll
-        for (int p = 0; p < 6; ++p) {
-            const double w = rule_w(p) * rule_bary(p, k);
-            y1 += w * pot[p];
-            y2 += w * pot[6 + p];
-        }
-        if (family == 1) y2 += g[22 + 3 * k] * pot[12] + g[23 + 3 * k] * pot[13] + g[24 + 3 * k] * pot[14];
-        if (swap) { const double tmp = y1; y1 = y2; y2 = tmp; }
-        triout[6 * (size_t)t + k] = sc * y1;
-        triout[6 * (size_t)t + 3 + k] = sc * y2;
-    }
+    const int t = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kFinishLanes);
+    const int l = threadIdx.x % kFinishLanes;
+    sym_finish_group(t, l, t < T, T, rt, nr, family, swap, geo, part, triout);   // the group agrees on t < T
 }
 
 __global__ void k_sym_set(int *p, int v) { *p = v; }
@@ -391,7 +355,7 @@ void launch_far_sym_finish(DevMesh &d)
     const int T = d.hm.T;
     const FormCoef &f = d.fm;
     const int swap = f.family == 0 && laplace_row(f) == 1;
-    hipLaunchKernelGGL(k_far_sym_finish, dim3((unsigned)(((size_t)T * kSymFinishLanes + 255) / 256)), dim3(256), 0,
+    hipLaunchKernelGGL(k_far_sym_finish, dim3((unsigned)(((size_t)T * kFinishLanes + 255) / 256)), dim3(256), 0,
                        d.stream, T, d.sym_rt, d.sym_nr, f.family, swap, d.geo, (const float *)d.part, d.triout,
                        d.ctl);
     HIPCHECK(hipGetLastError());

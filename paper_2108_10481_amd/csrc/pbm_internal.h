@@ -119,6 +119,34 @@ struct GState {
     double inv;     // 1 / |w|
 };
 
+// One solve of a lockstep batch, for the batched steps of a captured
+// iteration: its mesh data (source weights, far-field finish, gather) and its
+// Krylov state (basis, Hessenberg, rotations, CGS2 coefficients).
+struct KrylovReq {
+    int n, m;                  // 2V, basis capacity
+    double *Vb;                // basis, column-major n x (m + 1)
+    GState *st;
+    double *H, *cs, *sn, *g, *h1, *h2;
+};
+struct TailReq {
+    int T, V, S;               // triangles, vertices, source chunks of the regular split
+    int rt, nr;                // symmetric split (nr = 0: regular)
+    int family, swap, precond;
+    const int32_t *tri;
+    const double *geo;
+    double *dyn64;
+    float *dyn32;
+    const void *part;          // far-field partial sums (float or double)
+    double *triout;
+    const int32_t *inc_ptr, *inc_tk, *row_ptr, *col;
+    const double *N, *pinv;
+    int64_t nnz;
+    const double *x;           // the basis: input column V_j (offset by ctl)
+    double *gout;              // gather output: V_{j+1} (offset by ctl), or a plain vector (mass mode)
+    int gout_offset;           // 1: gout is offset by j n like the input
+    DevCtl ctl;                // j, stop flag, stride n: the input column V_j
+};
+
 struct Params {
     double eps_in, eps_out, kappa;
     int formulation, preconditioner, precision, operator_mode;
@@ -407,6 +435,18 @@ void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const Dev
 void mass_precond(DevMesh &d, int nvec, const double *in, double *out, const DevCtl &ctl, double sa, double sb);
 // Calderon chain on a plain vector: out (offset by ctl) = blockdiag(aM, bM)^-1 P blockdiag(M, M)^-1 in
 void calderon_left(DevMesh &d, const double *in, double *out, const DevCtl &ctl);
+int kr_batch_blocks(int n);
+// boff: prefix of kr_batch_blocks(n_r) over the R solves (device); ndot: an
+// upper bound of the dot-product items (sum of the capacities + 1)
+void kr_batch_iteration_tail(hipStream_t s, int R, const KrylovReq *rq, const int *boff, int nblocks, int ndot);
+// batched source weights, far-field finish (regular and symmetric splits) and
+// gather of R solves; boff_* prefixes of the blocks each solve takes
+int tail_blocks_source(const TailReq &q);
+int tail_blocks_finish(const TailReq &q);
+int tail_blocks_gather(const TailReq &q);
+void launch_batch_source_prep(hipStream_t s, int R, const TailReq *rq, const int *boff, int nblocks);
+void launch_batch_finish(hipStream_t s, bool fp32, int R, const TailReq *rq, const int *boff, int nblocks);
+void launch_batch_gather(hipStream_t s, int R, const TailReq *rq, const int *boff, int nblocks);
 void kr_graph_iteration_tail(hipStream_t s, int n, int m, double *Vb, GState *st, double *H, double *cs, double *sn,
                              double *g, double *h1, double *h2);
 

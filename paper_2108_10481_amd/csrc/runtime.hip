@@ -1035,14 +1035,191 @@ static void gmres_batch(const std::vector<DevMesh *> &ds, hipStream_t s, bool fp
     }
 }
 
-// The same lockstep with the whole iteration of every request captured once
-// into one HIP graph: each request's source weights, the fused far-field
-// launches, then each request's finish, near field, preconditioner, CGS2 and
-// device Givens step under its own stop flag, replayed kReplay times between
-// checks.  A request's kernels are those of its own captured iteration
-// (gmres_graph) with k_far replaced by its items of k_far_batch, so the
-// results are bitwise those of its solve; once its flag is set its kernels
-// and far-field items do nothing.
+// The same lockstep with the whole iteration of every request captured into
+// one HIP graph of batched launches: the source weights of every request, the
+// fused far-field launches, every request's far-field finish, gather (near
+// field, preconditioner) and each CGS2 / norm / Givens / normalisation step
+// run as one launch for all requests (KrylovReq / TailReq tables; each block
+// runs the single kernel's code for its request), replayed kReplay times
+// between checks.  A request's arithmetic is that of its own captured
+// iteration (gmres_graph), so its results are bitwise those of its single
+// solve; once its stop flag is set its blocks and far-field items do nothing,
+// and at the next check the requests still iterating continue on a graph of
+// their own, so stopped requests leave the work queues.  Graphs, tables and
+// far-field work lists are kept per set of requests for later calls (key: the
+// bytes of everything a graph refers to), so repeated calls with the same
+// resident handles plan and capture nothing.
+struct LockstepGraph {
+    std::vector<char> key;
+    unsigned long long used = 0;
+    FarBatch fb;
+    void *tables = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void release()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (tables) (void)hipFree(tables);
+        far_batch_free(fb);
+        exec = nullptr;
+        graph = nullptr;
+        tables = nullptr;
+        key.clear();
+    }
+};
+// per device, the kLockstepCache most recently used graphs, kept until the
+// process ends (never destroyed from a static destructor, which may run after
+// the HIP runtime's)
+constexpr int kLockstepCache = 16;
+static std::mutex g_lockstep_mu;
+static std::map<int, std::vector<LockstepGraph *>> g_lockstep;
+static unsigned long long g_lockstep_clock = 0;
+
+template <typename T>
+static void key_append(std::vector<char> &k, const T &v)
+{
+    const char *p = reinterpret_cast<const char *>(&v);
+    k.insert(k.end(), p, p + sizeof(T));
+}
+
+// The captured iteration of the requests `live` (indices into ds), from the
+// cache or captured now; caller holds g_lockstep_mu.
+static LockstepGraph &lockstep_graph(const std::vector<DevMesh *> &ds, const std::vector<int> &live,
+                                     const std::vector<GraphGmres *> &G, const std::vector<int> &n,
+                                     const std::vector<int> &m, bool fp32, hipStream_t s)
+{
+    const int L = (int)live.size();
+    std::vector<TailReq> tq(L);
+    std::vector<KrylovReq> kq(L);
+    std::vector<int> bsrc(L + 1, 0), bfin(L + 1, 0), bgat(L + 1, 0), bkry(L + 1, 0);
+    int ndot = 0;
+    std::vector<char> key;
+    key_append(key, fp32);
+    for (int k = 0; k < L; ++k) {
+        const int r = live[k];
+        DevMesh &d = *ds[r];
+        GraphGmres &g = *G[r];
+        const bool mass = mass_mode(d);
+        const bool sym = fp32 && d.sym_nitems > 0;
+        TailReq &t = tq[k];
+        t = TailReq{};
+        t.T = d.hm.T;
+        t.V = d.hm.V;
+        t.S = d.S;
+        t.rt = sym ? d.sym_rt : 0;
+        t.nr = sym ? d.sym_nr : 0;
+        t.family = d.fm.family;
+        t.swap = d.fm.family == 0 && laplace_row(d.fm) == 1;
+        t.precond = mass ? 0 : 1;
+        t.tri = d.tri;
+        t.geo = d.geo;
+        t.dyn64 = d.dyn64;
+        t.dyn32 = d.dyn32;
+        t.part = d.part;
+        t.triout = d.triout;
+        t.inc_ptr = d.inc_ptr;
+        t.inc_tk = d.inc_tk;
+        t.row_ptr = d.row_ptr;
+        t.col = d.col;
+        t.N = d.N;
+        t.pinv = d.pinv;
+        t.nnz = d.nnz();
+        t.x = d.kry.basis;
+        t.gout = mass ? d.mtmp : d.kry.basis + n[r];
+        t.gout_offset = mass ? 0 : 1;
+        t.ctl = DevCtl{&g.st->j, &g.st->done, (size_t)n[r]};
+        KrylovReq &q = kq[k];
+        q = KrylovReq{n[r], m[r], d.kry.basis, g.st, g.H, g.cs, g.sn, g.g, g.h1, g.h2};
+        bsrc[k + 1] = bsrc[k] + tail_blocks_source(t);
+        bfin[k + 1] = bfin[k] + tail_blocks_finish(t);
+        bgat[k + 1] = bgat[k] + tail_blocks_gather(t);
+        bkry[k + 1] = bkry[k] + kr_batch_blocks(n[r]);
+        ndot += m[r] + 1;
+        key_append(key, t);
+        key_append(key, q);
+        key_append(key, d.fm);   // the far-field coefficients follow from fm and kappa
+        key_append(key, d.prm.kappa);
+        key_append(key, sym);
+        key_append(key, d.stat32);
+        key_append(key, d.stat64);
+        if (mass) {   // the mass preconditioner's launches: buffers and scales
+            key_append(key, d.prm.preconditioner);
+            key_append(key, d.prm.eps_in);
+            key_append(key, d.prm.eps_out);
+            key_append(key, d.cheb);
+            key_append(key, d.Mdinv);
+            key_append(key, d.Mval);
+        }
+    }
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    std::vector<LockstepGraph *> &cache = g_lockstep[dev];
+    for (LockstepGraph *e : cache)
+        if (e->exec && e->key == key) {
+            e->used = ++g_lockstep_clock;
+            return *e;
+        }
+    LockstepGraph *slot = nullptr;
+    if ((int)cache.size() < kLockstepCache) {
+        cache.push_back(new LockstepGraph());
+        slot = cache.back();
+    } else {
+        slot = *std::min_element(cache.begin(), cache.end(),
+                                 [](const LockstepGraph *x, const LockstepGraph *y) { return x->used < y->used; });
+    }
+    LockstepGraph &lg = *slot;
+    lg.release();
+    lg.fb.stream = s;
+    std::vector<const int *> skip(ds.size(), nullptr);
+    for (int r : live) skip[r] = &G[r]->st->done;
+    far_batch_plan(ds, live, fp32, lg.fb, skip);
+    const size_t bt = sizeof(TailReq) * L, bk = sizeof(KrylovReq) * L, bi = sizeof(int) * (L + 1);
+    HIPCHECK(hipMalloc(&lg.tables, bt + bk + 4 * bi));
+    char *base = (char *)lg.tables;
+    HIPCHECK(hipMemcpyAsync(base, tq.data(), bt, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(base + bt, kq.data(), bk, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(base + bt + bk, bsrc.data(), bi, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(base + bt + bk + bi, bfin.data(), bi, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(base + bt + bk + 2 * bi, bgat.data(), bi, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(base + bt + bk + 3 * bi, bkry.data(), bi, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));   // host tables go out of scope
+    const TailReq *dt = (const TailReq *)base;
+    const KrylovReq *dk = (const KrylovReq *)(base + bt);
+    const int *dsrc = (const int *)(base + bt + bk), *dfin = dsrc + (L + 1), *dgat = dfin + (L + 1),
+              *dkry = dgat + (L + 1);
+    for (int r : live) ds[r]->ctl = DevCtl{&G[r]->st->j, &G[r]->st->done, (size_t)n[r]};
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+        launch_batch_source_prep(s, L, dt, dsrc, bsrc[L]);
+        launch_far_batch(lg.fb, fp32);
+        launch_batch_finish(s, fp32, L, dt, dfin, bfin[L]);
+        launch_batch_gather(s, L, dt, dgat, bgat[L]);
+        for (int r : live)   // apply_after_far's mass-preconditioner step, per request
+            if (mass_mode(*ds[r])) mass_precond(*ds[r], 1, ds[r]->mtmp, ds[r]->kry.basis + n[r], ds[r]->ctl);
+        kr_batch_iteration_tail(s, L, dk, dkry, bkry[L], ndot);
+        HIPCHECK(hipGetLastError());
+    } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(s, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        for (int r : live) ds[r]->ctl = DevCtl();
+        lg.release();
+        throw;
+    }
+    for (int r : live) ds[r]->ctl = DevCtl();
+    try {
+        HIPCHECK(hipStreamEndCapture(s, &lg.graph));
+        HIPCHECK(hipGraphInstantiate(&lg.exec, lg.graph, nullptr, nullptr, 0));
+    } catch (...) {
+        lg.release();
+        throw;
+    }
+    lg.key = key;
+    lg.used = ++g_lockstep_clock;
+    return lg;
+}
+
 static void gmres_batch_graph(const std::vector<DevMesh *> &ds, hipStream_t s, bool fp32, std::vector<int> &its,
                               std::vector<double> &est)
 {
@@ -1090,50 +1267,21 @@ static void gmres_batch_graph(const std::vector<DevMesh *> &ds, hipStream_t s, b
     }
     HIPCHECK(hipStreamSynchronize(s));   // h0, g0 are host vectors
     if (live.empty()) return;
-    FarBatch fb;
-    fb.stream = s;
-    struct Free {
-        FarBatch &fb;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        ~Free()
-        {
-            if (exec) (void)hipGraphExecDestroy(exec);
-            if (graph) (void)hipGraphDestroy(graph);
-            far_batch_free(fb);
-        }
-    } res{fb};
-    std::vector<const int *> skip(R, nullptr);
-    for (int r : live) skip[r] = &G[r]->st->done;
-    far_batch_plan(ds, live, fp32, fb, skip);
-    for (int r : live) ds[r]->ctl = DevCtl{&G[r]->st->j, &G[r]->st->done, (size_t)n[r]};
-    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    try {
-        for (int r : live) launch_source_prep(*ds[r], ds[r]->kry.basis, fp32);
-        launch_far_batch(fb, fp32);
-        for (int r : live) {
-            launch_far_finish(*ds[r], fp32);
-            iteration_tail(*ds[r], *G[r], 1);
-        }
-        HIPCHECK(hipGetLastError());
-    } catch (...) {
-        hipGraph_t dead = nullptr;
-        (void)hipStreamEndCapture(s, &dead);
-        if (dead) (void)hipGraphDestroy(dead);
-        for (int r : live) ds[r]->ctl = DevCtl();
-        throw;
-    }
-    for (int r : live) ds[r]->ctl = DevCtl();
-    HIPCHECK(hipStreamEndCapture(s, &res.graph));
-    HIPCHECK(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
     std::vector<GState> hs(R);
-    for (;;) {
-        for (int k = 0; k < kReplay; ++k) HIPCHECK(hipGraphLaunch(res.exec, s));
-        for (int r : live) HIPCHECK(hipMemcpyAsync(&hs[r], G[r]->st, sizeof(GState), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        bool all = true;
-        for (int r : live) all = all && (hs[r].done || hs[r].j >= m[r]);
-        if (all) break;
+    std::vector<int> running = live;
+    {
+        std::lock_guard<std::mutex> lk(g_lockstep_mu);
+        while (!running.empty()) {
+            LockstepGraph &lg = lockstep_graph(ds, running, G, n, m, fp32, s);
+            for (int k = 0; k < kReplay; ++k) HIPCHECK(hipGraphLaunch(lg.exec, s));
+            for (int r : running)
+                HIPCHECK(hipMemcpyAsync(&hs[r], G[r]->st, sizeof(GState), hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            std::vector<int> next;
+            for (int r : running)
+                if (!(hs[r].done || hs[r].j >= m[r])) next.push_back(r);
+            running.swap(next);
+        }
     }
     for (int r : live) {
         graph_solution(*ds[r], *G[r], hs[r].j, ds[r]->u);

@@ -69,6 +69,43 @@ def test_batch_equals_single_solves(precision):
         assert batch[0]["iterations"] == ref["iterations"]
 
 
+def test_batch_repeated_calls_reuse_graph():
+    """The captured batch graph is kept for the next call with the same
+    requests: repeated calls, calls on other subsets in between, and a batch
+    after a handle was closed and another created (possibly at the same
+    addresses, with another formulation) all give bitwise the single solves."""
+    reqs = _requests()
+    hs = _handles(reqs, pbm.PB_FP32)
+    extra = []
+    try:
+        sets = [(c.xyz, c.q) for _, c, _, _ in reqs]
+        single = [pbm.pb_mesh_solve(h, *st) for h, st in zip(hs, sets)]
+        for _ in range(2):
+            for a, b in zip(pbm.pb_solve_batch(hs, sets), single):
+                _same(a, b)
+        sub = [2, 0]
+        for k, a in zip(sub, pbm.pb_solve_batch([hs[k] for k in sub], [sets[k] for k in sub])):
+            _same(a, single[k])
+        for a, b in zip(pbm.pb_solve_batch(hs, sets), single):
+            _same(a, b)
+        # the same charges on other charge values: a new right-hand side, same graph
+        q2 = [(x, 0.5 * q) for x, q in sets]
+        single2 = [pbm.pb_mesh_solve(h, *st) for h, st in zip(hs, q2)]
+        for a, b in zip(pbm.pb_solve_batch(hs, q2), single2):
+            _same(a, b)
+        hs[1].close()
+        m1, c1 = reqs[1][0], reqs[1][1]
+        extra.append(pbm.MeshHandle(m1.xyz, m1.tri, pbm.pb_default_options(
+            formulation=pbm.PB_DIRECT_INT, precision=pbm.PB_FP32, operator_mode=pbm.PB_MATRIX_FREE)))
+        hs2 = [hs[0], extra[0], hs[2], hs[3]]
+        single3 = [pbm.pb_mesh_solve(h, *st) for h, st in zip(hs2, sets)]
+        for a, b in zip(pbm.pb_solve_batch(hs2, sets), single3):
+            _same(a, b)
+    finally:
+        for h in hs + extra:
+            h.close()
+
+
 def test_batch_eager_lockstep_equals_single_solves():
     """With use_graph = 0 the lockstep runs eagerly (host Givens, one
     synchronisation per iteration): still bitwise the single solves."""
