@@ -81,7 +81,10 @@ typedef int32_t pb_status;
  * as printed, Eq. bie:pmchwt:int with the opposite sign), (e_out/e_in,
  * e_in/e_out) Juffer, and the external form at (e, 1/e) is Lu before its
  * second row is scaled.  Any
- * real alpha, beta is accepted; with a zero coefficient in the external form
+ * real alpha, beta is accepted; alpha = beta = 0 leaves one side's trace
+ * equations alone, which do not couple the interior and exterior problems:
+ * such a handle applies its operator (pb_mesh_apply) but every solve entry
+ * point refuses it with PB_E_STATE.  With a zero coefficient in the external form
  * a block has no Laplace term, which the matrix-free and treecode far fields
  * handle and the assembled one refuses (PB_E_STATE; PB_AUTO then stays
  * matrix-free). */

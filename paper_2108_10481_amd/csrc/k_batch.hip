@@ -399,6 +399,7 @@ static double now_s()
 
 pb_status solve_multi(DevMesh &d, int n_sets, const pb_charges *sets, pb_result *out)
 {
+    check_solvable(d);
     if (!d.dense) {   // matrix-free: the far field is recomputed per product anyway
         pb_status worst = PB_OK;
         for (int k = 0; k < n_sets; ++k) {

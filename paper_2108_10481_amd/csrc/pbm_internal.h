@@ -377,6 +377,7 @@ pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res);
 int gmres(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
 int gmres_solve(DevMesh &d, const double *pb, double *x, double tol, int max_iter, double *est);
 void destroy_graphs(DevMesh &d);
+void check_solvable(const DevMesh &d);   // PB_E_STATE for systems that are no formulation
 
 // treecode far field (k_tree.hip): plan built on the host at creation; the
 // product writes d.part in the layout of tree_splits() source chunks

@@ -1295,6 +1295,7 @@ static void gmres_batch_graph(const std::vector<DevMesh *> &ds, hipStream_t s, b
 // handles' own streams are drained first and restored afterwards.
 static pb_status solve_batch(const std::vector<DevMesh *> &ds, const pb_charges *ch, pb_result *res)
 {
+    for (const DevMesh *d : ds) check_solvable(*d);
     TraceRange batch_range("pb.batch");
     const int R = (int)ds.size();
     hipStream_t s = ds[0]->stream;
@@ -1466,8 +1467,20 @@ pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, doub
     return res->rel_residual <= d.opt.tol * 1.0000001 ? PB_OK : PB_NOT_CONVERGED;
 }
 
+// The combined field with alpha = beta = 0 is one side's trace equations
+// alone: a well-defined operator (pb_mesh_apply), but no formulation of the
+// interface problem, so the solvers refuse it.
+void check_solvable(const DevMesh &d)
+{
+    if ((d.prm.formulation == PB_CFIE_INT || d.prm.formulation == PB_CFIE_EXT) && d.opt.cfie_alpha == 0.0 &&
+        d.opt.cfie_beta == 0.0)
+        fail(PB_E_STATE, "cfie_alpha = cfie_beta = 0 keeps one side's trace equations only, which do not couple "
+                         "the two problems: the operator can be applied, not solved");
+}
+
 pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res)
 {
+    check_solvable(d);
     if (!res) fail(PB_E_INVALID_ARG, "result must not be NULL");
     const int V = d.hm.V, n = 2 * V;
     TraceRange solve_range("pb.solve");

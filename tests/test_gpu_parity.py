@@ -872,6 +872,26 @@ def test_cfie_operator(meshes, base_operators, form, a, b):
             assert _rel(pbm.pb_mesh_apply(h, x), ref) < 1e-5
 
 
+def test_cfie_without_coupling_is_applied_not_solved():
+    """alpha = beta = 0 keeps one side's trace equations only: the operator is
+    applied (checked against the oracle above), every solve entry point
+    refuses it with PB_E_STATE."""
+    m, ch = inputs.config_kirkwood(4, 2.0)
+    for form in (pbm.PB_CFIE_INT, pbm.PB_CFIE_EXT):
+        opt = pbm.pb_default_options(formulation=form, cfie_alpha=0.0, cfie_beta=0.0)
+        with pbm.MeshHandle(m.xyz, m.tri, opt) as h:
+            assert np.all(np.isfinite(pbm.pb_mesh_apply(h, np.ones(2 * m.n_vertices))))
+            for call in (lambda: pbm.pb_mesh_solve(h, ch.xyz, ch.q),
+                         lambda: pbm.pb_solve_multi(h, [(ch.xyz, ch.q)]),
+                         lambda: pbm.pb_solve_batch([h], [(ch.xyz, ch.q)])):
+                with pytest.raises(pbm.PbError) as e:
+                    call()
+                assert e.value.code == pbm.PB_E_STATE
+        with pytest.raises(pbm.PbError) as e:
+            pbm.pb_solve(m.xyz, m.tri, ch.xyz, ch.q, opt)
+        assert e.value.code == pbm.PB_E_STATE
+
+
 @pytest.mark.parametrize("form,a,b", [c for c in _CFIE_CASES if c[1:] != (0.0, 0.0)])
 def test_cfie_solve_parity(form, a, b):
     """Kirkwood sphere with the mass preconditioner: the oracle's iterations
