@@ -5,7 +5,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <numeric>
+#include <thread>
 
 #include "pbm_internal.h"
 
@@ -71,6 +74,42 @@ static uint32_t spread10(uint32_t v)
     v = (v | (v << 4)) & 0x030C30C3u;
     v = (v | (v << 2)) & 0x09249249u;
     return v;
+}
+
+// Contiguous row ranges of a host loop run on worker threads; the callers
+// write disjoint outputs per row (or per worker, joined in row order), so the
+// result does not depend on the number of workers.
+constexpr int kPrepMaxThreads = 16;
+constexpr int kPrepMinRows = 4096;
+
+static int prep_workers(int n, int min_rows)
+{
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    return std::max(1, std::min({kPrepMaxThreads, hw, n / min_rows}));
+}
+
+// fn(worker, begin, end) over nw contiguous ranges of [0, n); an exception in a
+// worker is rethrown on the calling thread
+template <typename F>
+static void parallel_chunks(int n, int nw, F &&fn)
+{
+    if (nw <= 1) { fn(0, 0, n); return; }
+    std::vector<std::thread> th;
+    std::exception_ptr err;
+    std::mutex mu;
+    for (int w = 0; w < nw; ++w) {
+        const int b = (int)((int64_t)n * w / nw), e = (int)((int64_t)n * (w + 1) / nw);
+        th.emplace_back([&, w, b, e] {
+            try {
+                fn(w, b, e);
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (!err) err = std::current_exception();
+            }
+        });
+    }
+    for (auto &t : th) t.join();
+    if (err) std::rethrow_exception(err);
 }
 
 void build_host_mesh(const pb_mesh *m, HostMesh &hm)
@@ -168,81 +207,132 @@ void build_host_mesh(const pb_mesh *m, HostMesh &hm)
             for (int k = 0; k < 3; ++k) hm.inc_tk[fill[hm.tri[3 * t + k]]++] = 4 * t + k;
     }
 
-    // near pairs: for each t, every s sharing at least one vertex (incl. t)
+    // near pairs: for each t, every s sharing at least one vertex (incl. t),
+    // ascending
     hm.pair_ptr.assign(T + 1, 0);
-    hm.pair_s.clear();
-    hm.pair_s.reserve(14 * (size_t)T);
-    std::vector<int32_t> buf;
-    for (int t = 0; t < T; ++t) {
-        buf.clear();
-        for (int k = 0; k < 3; ++k) {
-            int v = hm.tri[3 * t + k];
-            for (int e2 = hm.inc_ptr[v]; e2 < hm.inc_ptr[v + 1]; ++e2) buf.push_back(hm.inc_tk[e2] >> 2);
-        }
-        std::sort(buf.begin(), buf.end());
-        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-        hm.pair_s.insert(hm.pair_s.end(), buf.begin(), buf.end());
-        hm.pair_ptr[t + 1] = (int32_t)hm.pair_s.size();
-    }
-    const size_t np = hm.pair_s.size();
-    if (np > (size_t)INT32_MAX / 2) fail(PB_E_INVALID_ARG, "mesh too large");
-    hm.pair_rev.resize(np);
-    for (int t = 0; t < T; ++t)
-        for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) {
-            int s = hm.pair_s[p];
-            auto b = hm.pair_s.begin() + hm.pair_ptr[s], en = hm.pair_s.begin() + hm.pair_ptr[s + 1];
-            auto it = std::lower_bound(b, en, t);
-            hm.pair_rev[p] = (int32_t)(it - hm.pair_s.begin());
-        }
-
-    // near vertex CSR: j appears in row i if some near pair (t ni i, s ni j)
-    hm.row_ptr.assign(V + 1, 0);
-    hm.col.clear();
-    hm.col.reserve(20 * (size_t)V);
-    hm.diag_slot.resize(V);
-    for (int i = 0; i < V; ++i) {
-        buf.clear();
-        for (int e2 = hm.inc_ptr[i]; e2 < hm.inc_ptr[i + 1]; ++e2) {
-            int t = hm.inc_tk[e2] >> 2;
-            for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) {
-                int s = hm.pair_s[p];
-                for (int l = 0; l < 3; ++l) buf.push_back(hm.tri[3 * s + l]);
-            }
-        }
-        std::sort(buf.begin(), buf.end());
-        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-        hm.diag_slot[i] = (int32_t)(hm.col.size() + (std::lower_bound(buf.begin(), buf.end(), i) - buf.begin()));
-        hm.col.insert(hm.col.end(), buf.begin(), buf.end());
-        hm.row_ptr[i + 1] = (int32_t)hm.col.size();
-    }
-
-    // per nonzero slot (i, j), its contributions (near pair p, local vertex k
-    // of i in t, local vertex l of j in s) in the order row i visits them --
-    // incidence, pair, l -- as codes p << 4 | k << 2 | l
-    if (np >= ((size_t)1 << 28)) fail(PB_E_INVALID_ARG, "mesh too large");
-    const size_t nnz = hm.col.size();
-    hm.slot_ptr.assign(nnz + 1, 0);
-    for (int pass = 0; pass < 2; ++pass) {
-        std::vector<int32_t> fill;
-        if (pass == 1) {
-            for (size_t a = 0; a < nnz; ++a) hm.slot_ptr[a + 1] += hm.slot_ptr[a];
-            hm.slot_code.assign(hm.slot_ptr[nnz], 0);
-            fill.assign(hm.slot_ptr.begin(), hm.slot_ptr.end() - 1);
-        }
-        for (int i = 0; i < V; ++i) {
-            const auto cb = hm.col.begin() + hm.row_ptr[i], ce = hm.col.begin() + hm.row_ptr[i + 1];
-            for (int e2 = hm.inc_ptr[i]; e2 < hm.inc_ptr[i + 1]; ++e2) {
-                const int t = hm.inc_tk[e2] >> 2, k = hm.inc_tk[e2] & 3;
-                for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) {
-                    const int s = hm.pair_s[p];
-                    for (int l = 0; l < 3; ++l) {
-                        const size_t slot = (size_t)(std::lower_bound(cb, ce, hm.tri[3 * s + l]) - hm.col.begin());
-                        if (pass == 0) hm.slot_ptr[slot + 1]++;
-                        else hm.slot_code[fill[slot]++] = ((uint32_t)p << 4) | ((uint32_t)k << 2) | (uint32_t)l;
+    {
+        std::vector<std::vector<int32_t>> part(prep_workers(T, kPrepMinRows));
+        std::vector<int32_t> cnt(T);
+        parallel_chunks(T, (int)part.size(), [&](int w, int b, int e) {
+            std::vector<int32_t> stamp(T, -1), buf;
+            auto &out = part[w];
+            out.reserve(14 * (size_t)(e - b));
+            for (int t = b; t < e; ++t) {
+                buf.clear();
+                for (int k = 0; k < 3; ++k) {
+                    const int v = hm.tri[3 * t + k];
+                    for (int e2 = hm.inc_ptr[v]; e2 < hm.inc_ptr[v + 1]; ++e2) {
+                        const int s = hm.inc_tk[e2] >> 2;
+                        if (stamp[s] != t) { stamp[s] = t; buf.push_back(s); }
                     }
                 }
+                std::sort(buf.begin(), buf.end());
+                out.insert(out.end(), buf.begin(), buf.end());
+                cnt[t] = (int32_t)buf.size();
             }
+        });
+        size_t np = 0;
+        for (int t = 0; t < T; ++t) np += (size_t)cnt[t];
+        if (np > (size_t)INT32_MAX / 2) fail(PB_E_INVALID_ARG, "mesh too large");
+        for (int t = 0; t < T; ++t) hm.pair_ptr[t + 1] = hm.pair_ptr[t] + cnt[t];
+        hm.pair_s.clear();
+        hm.pair_s.reserve(np);
+        for (auto &v : part) hm.pair_s.insert(hm.pair_s.end(), v.begin(), v.end());
+    }
+    const size_t np = hm.pair_s.size();
+    hm.pair_rev.resize(np);
+    parallel_chunks(T, prep_workers(T, kPrepMinRows), [&](int, int b, int e) {
+        for (int t = b; t < e; ++t)
+            for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) {
+                const int s = hm.pair_s[p];
+                auto bs = hm.pair_s.begin() + hm.pair_ptr[s], es = hm.pair_s.begin() + hm.pair_ptr[s + 1];
+                hm.pair_rev[p] = (int32_t)(std::lower_bound(bs, es, t) - hm.pair_s.begin());
+            }
+    });
+
+    // Near vertex CSR: j appears in row i if some near pair (t ni i, s ni j)
+    // does; columns ascending.  Per nonzero slot (i, j), its contributions
+    // (near pair p, local vertex k of i in t, local vertex l of j in s) in the
+    // order row i visits them -- incidence, pair, l -- as codes
+    // p << 4 | k << 2 | l.  Each worker builds its rows' columns, slot counts
+    // and codes; the parts are joined in row order.
+    if (np >= ((size_t)1 << 28)) fail(PB_E_INVALID_ARG, "mesh too large");
+    {
+        struct Rows {
+            std::vector<int32_t> ncol, col, diag, scount;
+            std::vector<uint32_t> code;
+        };
+        std::vector<Rows> part(prep_workers(V, kPrepMinRows));
+        parallel_chunks(V, (int)part.size(), [&](int w, int b, int e) {
+            std::vector<int32_t> stamp(V, -1), pos(V, 0), buf, off;
+            Rows &r = part[w];
+            r.col.reserve(20 * (size_t)(e - b));
+            r.scount.reserve(20 * (size_t)(e - b));
+            r.code.reserve(240 * (size_t)(e - b));
+            auto visit = [&](int i, auto &&f) {
+                for (int e2 = hm.inc_ptr[i]; e2 < hm.inc_ptr[i + 1]; ++e2) {
+                    const int t = hm.inc_tk[e2] >> 2, k = hm.inc_tk[e2] & 3;
+                    for (int p = hm.pair_ptr[t]; p < hm.pair_ptr[t + 1]; ++p) {
+                        const int s = hm.pair_s[p];
+                        for (int l = 0; l < 3; ++l) f(hm.tri[3 * s + l], ((uint32_t)p << 4) | ((uint32_t)k << 2) | (uint32_t)l);
+                    }
+                }
+            };
+            for (int i = b; i < e; ++i) {
+                buf.clear();
+                visit(i, [&](int j, uint32_t) {
+                    if (stamp[j] != i) { stamp[j] = i; buf.push_back(j); }
+                });
+                std::sort(buf.begin(), buf.end());
+                const int nc = (int)buf.size();
+                for (int a = 0; a < nc; ++a) pos[buf[a]] = a;
+                r.ncol.push_back(nc);
+                r.diag.push_back(pos[i]);
+                r.col.insert(r.col.end(), buf.begin(), buf.end());
+                off.assign(nc + 1, 0);
+                visit(i, [&](int j, uint32_t) { off[pos[j] + 1]++; });
+                for (int a = 0; a < nc; ++a) {
+                    r.scount.push_back(off[a + 1]);
+                    off[a + 1] += off[a];
+                }
+                const size_t base = r.code.size();
+                r.code.resize(base + (size_t)off[nc]);
+                visit(i, [&](int j, uint32_t c) { r.code[base + (size_t)off[pos[j]]++] = c; });
+            }
+        });
+        // each worker's first row, column and code in the joined arrays
+        const int nw = (int)part.size();
+        std::vector<size_t> r0(nw + 1, 0), c0(nw + 1, 0), k0(nw + 1, 0);
+        for (int w = 0; w < nw; ++w) {
+            r0[w + 1] = r0[w] + part[w].ncol.size();
+            c0[w + 1] = c0[w] + part[w].col.size();
+            k0[w + 1] = k0[w] + part[w].code.size();
         }
+        if (c0[nw] > (size_t)INT32_MAX || k0[nw] > (size_t)INT32_MAX) fail(PB_E_INVALID_ARG, "mesh too large");
+        hm.row_ptr.assign(V + 1, 0);
+        hm.diag_slot.resize(V);
+        hm.col.resize(c0[nw]);
+        hm.slot_ptr.resize(c0[nw] + 1);
+        hm.slot_code.resize(k0[nw]);
+        hm.slot_ptr[0] = 0;
+        parallel_chunks(nw, nw, [&](int, int b, int e) {
+            for (int w = b; w < e; ++w) {
+                const Rows &r = part[w];
+                int32_t rp = (int32_t)c0[w];
+                for (size_t a = 0; a < r.ncol.size(); ++a) {
+                    hm.diag_slot[r0[w] + a] = rp + r.diag[a];
+                    rp += r.ncol[a];
+                    hm.row_ptr[r0[w] + a + 1] = rp;
+                }
+                std::copy(r.col.begin(), r.col.end(), hm.col.begin() + c0[w]);
+                std::copy(r.code.begin(), r.code.end(), hm.slot_code.begin() + k0[w]);
+                int32_t sp = (int32_t)k0[w];
+                for (size_t a = 0; a < r.scount.size(); ++a) {
+                    sp += r.scount[a];
+                    hm.slot_ptr[c0[w] + a + 1] = sp;
+                }
+            }
+        });
     }
 }
 

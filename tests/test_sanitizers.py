@@ -4,8 +4,9 @@ Two drivers in tests/sanitize/ are built with the sanitizers and run:
   * oracle_driver.c: every C routine of the oracle on a closed mesh with two
     vertices of valence 80;
   * host_driver.cpp: the library's host-side mesh preparation (mesh_prep.cpp,
-    built host-only) on the same mesh and on malformed ones, which must be
-    rejected with PB_E_MESH / PB_E_INVALID_ARG.
+    built host-only) on the same mesh, on a torus large enough for its
+    threaded passes, and on malformed ones, which must be rejected with
+    PB_E_MESH / PB_E_INVALID_ARG; also built with ThreadSanitizer.
 Device code is not instrumented (GPU sanitizers are not used here)."""
 import os
 import shutil
@@ -38,12 +39,13 @@ HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
-@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)), reason="ROCm compilers not available")
-def test_host_mesh_preparation_under_sanitizers(tmp_path):
+def _host_driver(tmp_path, sanitizers):
     flags = ["-x", "hip", "--cuda-host-only", "-O1", "-g", "-std=c++17",
-             "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
-             "-I", os.path.join(ROOT, "include")]
+             "-Xarch_host", "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include")]
+    for s in sanitizers:
+        flags += ["-Xarch_host", "-fsanitize=" + s]
+    if "thread" not in sanitizers:
+        flags += ["-Xarch_host", "-fno-sanitize-recover=all"]
     objs = []
     for src in (os.path.join(ROOT, "paper_2108_10481_amd", "csrc", "mesh_prep.cpp"),
                 os.path.join(SAN, "host_driver.cpp")):
@@ -51,6 +53,17 @@ def test_host_mesh_preparation_under_sanitizers(tmp_path):
         _run([HIPCC] + flags + ["-c", src, "-o", obj])
         objs.append(obj)
     exe = str(tmp_path / "host_driver")
-    _run([CLANG, "-fsanitize=address,undefined", "-o", exe] + objs)
-    r = _run([exe], env=ENV)
+    _run([CLANG, "-fsanitize=" + ",".join(sanitizers), "-pthread", "-o", exe] + objs)
+    env = dict(ENV, TSAN_OPTIONS="halt_on_error=1")
+    r = _run([exe], env=env)
     assert r.stdout.strip() == "ok"
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)), reason="ROCm compilers not available")
+def test_host_mesh_preparation_under_sanitizers(tmp_path):
+    _host_driver(tmp_path, ["address", "undefined"])
+
+
+@pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)), reason="ROCm compilers not available")
+def test_host_mesh_preparation_under_thread_sanitizer(tmp_path):
+    _host_driver(tmp_path, ["thread"])
