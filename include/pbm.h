@@ -85,9 +85,8 @@ typedef int32_t pb_status;
  * equations alone, which do not couple the interior and exterior problems:
  * such a handle applies its operator (pb_mesh_apply) but every solve entry
  * point refuses it with PB_E_STATE.  With a zero coefficient in the external form
- * a block has no Laplace term, which the matrix-free and treecode far fields
- * handle and the assembled one refuses (PB_E_STATE; PB_AUTO then stays
- * matrix-free). */
+ * a block has no Laplace term; every far-field mode (matrix-free, treecode,
+ * assembled) takes such systems. */
 #define PB_CFIE_INT    10
 #define PB_CFIE_EXT    11
 

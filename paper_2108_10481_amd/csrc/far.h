@@ -60,8 +60,8 @@ struct FarReq {
 // constant address space where the caller needs scalar loads)
 // With d = x_p - y_q, r = |d|, e = exp(-kappa r), G_L = 1/r, G_Y = e/r,
 // F_L = 1/r^3, F_Y = e (1 + kappa r)/r^3 and g = (d.n_s)/r^2, h = (d.n_t)/r^2:
-//   F_L d.n_s = g/r,  F_Y d.n_s = e (g/r + kappa g),
-// so each row is a few fused multiply-adds on 1/r, e/r and e with the source
+//   F_L d.n_s = g/r,  F_Y d.n_s = e (g/r + kappa g) = ek g with ek = e (1/r + kappa),
+// so each row is a few fused multiply-adds on 1/r, e/r and ek with the source
 // weights folded into per-point constants.
 template <typename R, int FORM, typename SP = const R *>
 __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__ st,
@@ -96,7 +96,6 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
             const R ynt = yx * ntx + yy * nty + yz * ntz;
             const R c1L = cf.cKL * b1, c1Y = cf.cKY * b1, c2L = cf.cVL * b2, c2Y = cf.cVY * b2;
             const R c3L = cf.cTL * b2, c3Y = cf.cTY * b2, kb1 = k2nn * b1;
-            const R c1Yk = c1Y * cf.kappa, c3Yk = c3Y * cf.kappa;
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
@@ -105,14 +104,15 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
                 const R ri2 = ri * ri;
                 const R e = expneg(cf.kexp, r2 * ri);
                 const R gy = e * ri;
+                const R ek = e * (ri + cf.kappa);   // F_Y d.n = ek g
                 const R g = (xns[p] - yns) * ri2, h = (xnt[p] - ynt) * ri2;
                 if (FORM == 3) {
-                    a1[p] = fma(g, fma(e, c1Yk, gy * c1Y), fma(gy, c2Y, a1[p]));
-                    a2[p] = fma(h, fma(e, c3Yk, gy * c3Y), fma(gy, kb1, a2[p]));
+                    a1[p] = fma(g, ek * c1Y, fma(gy, c2Y, a1[p]));
+                    a2[p] = fma(h, ek * c3Y, fma(gy, kb1, a2[p]));
                 } else {
-                    const R u = fma(e, c1Yk, fma(gy, c1Y, ri * c1L));
+                    const R u = fma(ek, c1Y, ri * c1L);
                     a1[p] = fma(g, u, fma(ri, c2L, fma(gy, c2Y, a1[p])));
-                    const R v = fma(e, c3Yk, fma(gy, c3Y, ri * c3L));
+                    const R v = fma(ek, c3Y, ri * c3L);
                     a2[p] = fma(h, v, fma(gy, kb1, a2[p]));
                     gL = fma(R(rule_w(p) * rule_w(q)), ri, gL);
                 }
@@ -232,6 +232,30 @@ inline int far_coef(const DevMesh &d, FarCoef<R> &cf)
     cf.cTL = (R)(-f.aL[1][1]); cf.cTY = (R)(-f.aY[1][1]);
     cf.cDL = (R)f.aL[1][0]; cf.cDY = (R)f.aY[1][0];
     return yukawa_only(f) ? 3 : 1;
+}
+
+// Coefficients of the symmetric kernel (k_far_sym.hip), whose coordinates are
+// scaled by s = kappa log2(e) (kappa > 0): with x' = s x, 1/r = s / r', the
+// normal-derivative factors (d.n)/r^2 = s (d'.n)/r'^2 and exp(-kappa r) =
+// exp2(-r'), so the K- and T-type coefficients take s^2, the V-type ones, the
+// kappa-weighted FORM 0 one and D's s, and kappa becomes kappa / s; kexp
+// carries s.  Returns the kernel FORM.
+inline int far_coef_sym(const DevMesh &d, FarCoef<float> &cf)
+{
+    FarCoef<double> c;
+    const int form = far_coef(d, c);
+    const double s = d.prm.kappa * 1.4426950408889634, s2 = s * s;
+    cf = FarCoef<float>{};
+    cf.kappa = (float)(d.prm.kappa / s);
+    cf.kexp = (float)s;
+    cf.k2 = (float)c.k2;
+    cf.kL = (float)(c.kL * s2); cf.vL = (float)(c.vL * s);
+    cf.kY = (float)(c.kY * s2); cf.vY = (float)(c.vY * s); cf.kYk = (float)(c.kYk * s);
+    cf.cKL = (float)(c.cKL * s2); cf.cKY = (float)(c.cKY * s2);
+    cf.cVL = (float)(c.cVL * s); cf.cVY = (float)(c.cVY * s);
+    cf.cTL = (float)(c.cTL * s2); cf.cTY = (float)(c.cTY * s2);
+    cf.cDL = (float)(c.cDL * s); cf.cDY = (float)(c.cDY * s);
+    return form;
 }
 
 }  // namespace pbm

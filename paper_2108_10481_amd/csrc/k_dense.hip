@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "dense.h"
+#include "far.h"
 
 namespace pbm {
 
@@ -63,19 +64,6 @@ struct AsmCoef {
     // FORM 1: ratios aY / aL of the K, V, D and T blocks (aL != 0 there)
     R rK, rV, rD, rT;
 };
-
-__device__ __forceinline__ float rsq_a(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq_a(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    y = fma(0.5 * y, fma(-h, y, 1.0), y);
-    h = x * y;
-    y = fma(0.5 * y, fma(-h, y, 1.0), y);
-    return y;
-}
-__device__ __forceinline__ float expn_a(float kl, float r) { return __builtin_amdgcn_exp2f(-kl * r); }
-__device__ __forceinline__ double expn_a(double k, double r) { return exp(-k * r); }
 
 // Orbit form of the 6-point rule (Numerical integration): its points form two
 // orbits of three with barycentric coordinates (1-2a, a, a) and (1-2b, b, b).
@@ -200,14 +188,15 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
         for (int q = 0; q < 6; ++q) {
             const R ynt = (FORM == 1 || SYM) ? sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz : R(0);
             R X[3][NV], SA[NV], SB[NV];
+            R sLA = 0, sLB = 0;   // orbit sums of G_L over the target points (FORM 1, LROW 2)
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const R tx = ts[3 * p], ty = ts[3 * p + 1], tz = ts[3 * p + 2];
                 const R dx = tx - sy[q][0], dy = ty - sy[q][1], dz = tz - sy[q][2];
                 const R r2 = dx * dx + dy * dy + dz * dz;
-                const R ri = rsq_a(r2);
+                const R ri = rsqrt_r(r2);
                 const R r = r2 * ri;
-                const R ek = expn_a(cf.kexp, r);
+                const R ek = expneg(cf.kexp, r);
                 const R ri3 = ri * ri * ri;
                 const R dns = (tx * nsx + ty * nsy + tz * nsz) - yns[q];
                 const R ekk = ek * (cf.kappa * r + R(1));
@@ -230,17 +219,28 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                     // (F_L + rK F_Y) d.n_s, G_L + rV G_Y, G_Y, (F_L + rT F_Y) d.n_t, without the
                     // factors aL; swapped pair: K with d.n_t, T with d.n_s.  LROW = 1: no
                     // Laplace term in any block, F_Y and G_Y alone with the factors aY.
+                    // LROW = 2 (some block without a Laplace term, another with one):
+                    // both coefficients of each block inside the values, no factor.
                     const R fy = ekk * ri3;
                     const R gy = ek * ri;
-                    const R a1 = LROW == 0 ? ri3 + cf.rK * fy : fy, a2 = LROW == 0 ? ri3 + cf.rT * fy : fy;
+                    R a1, a2;
+                    if (LROW == 0) { a1 = ri3 + cf.rK * fy; a2 = ri3 + cf.rT * fy; }
+                    else if (LROW == 1) { a1 = fy; a2 = fy; }
+                    else { a1 = cf.aL[0][0] * ri3 + cf.aY[0][0] * fy; a2 = cf.aL[1][1] * ri3 + cf.aY[1][1] * fy; }
                     const R dnt = ts[21 + p] - ynt;
                     v[0] = a1 * dns;
-                    v[1] = LROW == 0 ? ri + cf.rV * gy : gy;
+                    v[1] = LROW == 0 ? ri + cf.rV * gy : LROW == 1 ? gy : cf.aL[0][1] * ri + cf.aY[0][1] * gy;
                     v[2] = gy;
                     v[3] = a2 * dnt;
                     if (SYM) {
                         v[4] = a1 * dnt;
                         v[5] = a2 * dns;
+                    }
+                    // D's curl part integrates aL[1][0] G_L + aY[1][0] G_Y; the G_L part
+                    // by its own orbit sums (LROW = 2)
+                    if (LROW == 2) {
+                        if (p < 3) sLA = p == 0 ? ri : sLA + ri;
+                        else sLB = p == 3 ? ri : sLB + ri;
                     }
                 }
 #pragma unroll
@@ -260,10 +260,14 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
 #pragma unroll
                 for (int k = 0; k < 3; ++k) X[k][o] += cc;
             }
-            // D's curl part integrates G_L + rD G_Y = v1 + (rD - rV) v2
-            if (FORM == 1)
+            // D's curl part integrates G_L + rD G_Y = v1 + (rD - rV) v2 (LROW 0, 1), or
+            // aL[1][0] G_L + aY[1][0] G_Y (LROW 2)
+            if (FORM == 1 && LROW != 2)
                 Ssum += R(rule_w(q)) * ((R(kRuleWA) * SA[1] + R(kRuleWB) * SB[1]) +
                                         (cf.rD - cf.rV) * (R(kRuleWA) * SA[2] + R(kRuleWB) * SB[2]));
+            if (FORM == 1 && LROW == 2)
+                Ssum += R(rule_w(q)) * (cf.aL[1][0] * (R(kRuleWA) * sLA + R(kRuleWB) * sLB) +
+                                        cf.aY[1][0] * (R(kRuleWA) * SA[2] + R(kRuleWB) * SB[2]));
             const R wc = q < 3 ? al : be;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
@@ -287,9 +291,11 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
             f[0] = sw * c00; f[1] = sw * c01; f[2] = sw * c10; f[3] = sw * c11;
             if (SYM) { f[4] = -sw * c00; f[5] = -sw * c10; }
         } else {
-            // leading factors: aL (ratios aY / aL inside the values), or aY (LROW = 1)
-            const R l00 = LROW == 0 ? cf.aL[0][0] : cf.aY[0][0], l01 = LROW == 0 ? cf.aL[0][1] : cf.aY[0][1];
-            const R l11 = LROW == 0 ? cf.aL[1][1] : cf.aY[1][1];
+            // leading factors: aL (ratios aY / aL inside the values), aY (LROW = 1), or
+            // none (LROW = 2: the coefficients are inside the values)
+            const R l00 = LROW == 0 ? cf.aL[0][0] : LROW == 1 ? cf.aY[0][0] : R(1);
+            const R l01 = LROW == 0 ? cf.aL[0][1] : LROW == 1 ? cf.aY[0][1] : R(1);
+            const R l11 = LROW == 0 ? cf.aL[1][1] : LROW == 1 ? cf.aY[1][1] : R(1);
             f[0] = sw * l00;
             f[1] = sw * l01;
             f[2] = sw * cf.aY[1][0] * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
@@ -313,7 +319,7 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                     // hypersingular: curl_k(t) . curl_l(s) int int (G_Y - G_L) + kappa^2 (n_t . n_s) V_Y
                     const R cc = ts[28 + 3 * k] * ss[28 + 3 * l] + ts[29 + 3 * k] * ss[29 + 3 * l] +
                                  ts[30 + 3 * k] * ss[30 + 3 * l];
-                    val[2] += sc * (LROW == 0 ? cf.aL[1][0] : cf.aY[1][0]) * cc * Ssum;
+                    val[2] += sc * (LROW == 0 ? cf.aL[1][0] : LROW == 1 ? cf.aY[1][0] : R(1)) * cc * Ssum;
                 }
                 // a pair sharing a vertex may have produced inf or NaN: select, not scale
                 Quad<R> qd;
@@ -872,14 +878,16 @@ static void assemble(DevMesh &d, S *A)
     for (int r = 0; r < 2; ++r)
         for (int c = 0; c < 2; ++c) { cf.aL[r][c] = (R)fm.aL[r][c]; cf.aY[r][c] = (R)fm.aY[r][c]; }
     const bool direct = fm.family == 0;   // FORM 0: K and V rows; FORM 1: K, V / D, T
-    // FORM 0: the Laplace row; FORM 1: 1 if only Yukawa terms (a Calderon preconditioner's part)
-    const int lrow = direct ? laplace_row(fm) : yukawa_only(fm) ? 1 : 0;
-    if (!direct && lrow == 1) {
+    // FORM 0: the Laplace row.  FORM 1: 0 if every block has a Laplace term
+    // (ratio form), 1 if none has (a Calderon preconditioner's part), 2 if
+    // only some have (a combined field with one zero constant)
+    bool all_laplace = true;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) all_laplace &= fm.aL[r][c] != 0.0;
+    const int lrow = direct ? laplace_row(fm) : yukawa_only(fm) ? 1 : all_laplace ? 0 : 2;
+    if (!direct && lrow != 0) {
         cf.rK = cf.rV = cf.rD = cf.rT = R(0);
     } else if (!direct) {
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 2; ++c)
-                if (fm.aL[r][c] == 0.0) fail(PB_E_STATE, "formulation without a Laplace term in a block");
         cf.rK = (R)(fm.aY[0][0] / fm.aL[0][0]);
         cf.rV = (R)(fm.aY[0][1] / fm.aL[0][1]);
         cf.rD = (R)(fm.aY[1][0] / fm.aL[1][0]);
@@ -903,7 +911,8 @@ static void assemble(DevMesh &d, S *A)
                        D.color_tri, 0, 0, nullptr, D.sym_blocks + b0, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col,       \
                        D.tv_eptr, D.te, A, D.ld, D.Vp, D.C32, D.Vp)
                 if (!direct && lrow == 0) ASM_SYM(1, 0);
-                else if (!direct) ASM_SYM(1, 1);
+                else if (!direct && lrow == 1) ASM_SYM(1, 1);
+                else if (!direct) ASM_SYM(1, 2);
                 else if (lrow == 0) ASM_SYM(0, 0);
                 else ASM_SYM(0, 1);
 #undef ASM_SYM
@@ -940,7 +949,8 @@ static void assemble(DevMesh &d, S *A)
                        tl, nullptr, d.tri, stat, D.vpos, D.tv_ptr, D.tv_col, D.tv_eptr, D.te, A, D.ld, D.Vp,       \
                        nullptr, (size_t)0)
                 if (!direct && lrow == 0) ASM_ALL(1, 0);
-                else if (!direct) ASM_ALL(1, 1);
+                else if (!direct && lrow == 1) ASM_ALL(1, 1);
+                else if (!direct) ASM_ALL(1, 2);
                 else if (lrow == 0) ASM_ALL(0, 0);
                 else ASM_ALL(0, 1);
 #undef ASM_ALL

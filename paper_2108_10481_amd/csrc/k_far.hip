@@ -17,6 +17,8 @@
 //                   near-field CSR product, optional 2x2 preconditioner.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "far.h"
 
 namespace pbm {
@@ -531,7 +533,9 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         rq.chunk = chunk;
         rq.rt = rq.nr = 0;
         if (sizeof(R) == 4 && d.sym_nitems > 0) {
-            // symmetric split: the request's range pairs, in its own (heaviest first) order
+            // symmetric split: the request's range pairs, in its own (heaviest first)
+            // order, with the split's scaled coefficients
+            if constexpr (std::is_same<R, float>::value) far_coef_sym(d, rq.cf);
             rq.rt = d.sym_rt;
             rq.nr = d.sym_nr;
             std::vector<int2> its;

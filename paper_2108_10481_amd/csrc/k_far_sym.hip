@@ -17,6 +17,11 @@
 // in LDS (one array per field, so the lanes' rotated reads hit distinct
 // banks).
 //
+// Coordinates (points and the y . n values) are used scaled by s = kappa
+// log2(e), with the coefficients of far_coef_sym: then exp(-kappa r) =
+// exp2(-r') with r' = r2' / sqrt(r2') and no multiply for the argument.  The
+// split is used for kappa > 0 only.
+//
 // Output: per triangle, one 16-value partial (6 + 6 point sums, 3 curl sums)
 // per target-side item (slot b, the source range) and one per source-side
 // item (slot nr + a, the target range): every slot is written by exactly one
@@ -74,39 +79,40 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
                 const float g = (xns[p] - yns) * ri2, h = (xnt[p] - ynt[q]) * ri2;
                 a1[p] = fmaf(ri, fmaf(c1, g, c2), a1[p]);
                 acc[q] = fmaf(ri, fmaf(cs[0][p], h, cs[1][p]), acc[q]);
-                const float e = expneg(cf.kexp, r2 * ri);
+                const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
                 a2[p] = fmaf(e, fmaf(ri, fmaf(c3, g, c4), c3k * g), a2[p]);
                 acc[6 + q] = fmaf(e, fmaf(ri, fmaf(cs[2][p], h, cs[3][p]), cs[4][p] * h), acc[6 + q]);
             }
         } else {
             // target side as far_source; source side: row 1 with -h (K at n_t), row 2
-            // with -g (T at n_s): cs = -cKL b1_t, -cKY b1_t, -cKY kappa b1_t, cVL b2_t,
-            // cVY b2_t, -cTL b2_t, -cTY b2_t, -cTY kappa b2_t, b1_t
+            // with -g (T at n_s): cs = -cKL b1_t, -cKY b1_t, (unused), cVL b2_t,
+            // cVY b2_t, -cTL b2_t, -cTY b2_t, (unused), b1_t.  The Yukawa double-layer
+            // kernel e (1 + kappa r) / r^3 d.n is ek g with ek = e (1/r + kappa).
             const float c1L = cf.cKL * b1, c1Y = cf.cKY * b1, c2L = cf.cVL * b2, c2Y = cf.cVY * b2;
             const float c3L = cf.cTL * b2, c3Y = cf.cTY * b2, kb1 = nn * b1;
-            const float c1Yk = c1Y * cf.kappa, c3Yk = c3Y * cf.kappa;
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const float dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float ri = rsqrt_r(r2);
                 const float ri2 = ri * ri;
-                const float e = expneg(cf.kexp, r2 * ri);
+                const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
                 const float gy = e * ri;
+                const float ek = e * (ri + cf.kappa);
                 const float g = (xns[p] - yns) * ri2, h = (xnt[p] - ynt[q]) * ri2;
                 if (FORM == 3) {
-                    a1[p] = fmaf(g, fmaf(e, c1Yk, gy * c1Y), fmaf(gy, c2Y, a1[p]));
-                    a2[p] = fmaf(h, fmaf(e, c3Yk, gy * c3Y), fmaf(gy, kb1, a2[p]));
-                    acc[q] = fmaf(h, fmaf(e, cs[2][p], gy * cs[1][p]), fmaf(gy, cs[4][p], acc[q]));
-                    acc[6 + q] = fmaf(g, fmaf(e, cs[7][p], gy * cs[6][p]), fmaf(gy, nn * cs[8][p], acc[6 + q]));
+                    a1[p] = fmaf(g, ek * c1Y, fmaf(gy, c2Y, a1[p]));
+                    a2[p] = fmaf(h, ek * c3Y, fmaf(gy, kb1, a2[p]));
+                    acc[q] = fmaf(h, ek * cs[1][p], fmaf(gy, cs[4][p], acc[q]));
+                    acc[6 + q] = fmaf(g, ek * cs[6][p], fmaf(gy, nn * cs[8][p], acc[6 + q]));
                 } else {
-                    const float u = fmaf(e, c1Yk, fmaf(gy, c1Y, ri * c1L));
+                    const float u = fmaf(ek, c1Y, ri * c1L);
                     a1[p] = fmaf(g, u, fmaf(ri, c2L, fmaf(gy, c2Y, a1[p])));
-                    const float v = fmaf(e, c3Yk, fmaf(gy, c3Y, ri * c3L));
+                    const float v = fmaf(ek, c3Y, ri * c3L);
                     a2[p] = fmaf(h, v, fmaf(gy, kb1, a2[p]));
-                    const float us = fmaf(e, cs[2][p], fmaf(gy, cs[1][p], ri * cs[0][p]));
+                    const float us = fmaf(ek, cs[1][p], ri * cs[0][p]);
                     acc[q] = fmaf(h, us, fmaf(ri, cs[3][p], fmaf(gy, cs[4][p], acc[q])));
-                    const float vs = fmaf(e, cs[7][p], fmaf(gy, cs[6][p], ri * cs[5][p]));
+                    const float vs = fmaf(ek, cs[6][p], ri * cs[5][p]);
                     acc[6 + q] = fmaf(g, vs, fmaf(gy, nn * cs[8][p], acc[6 + q]));
                     gL = fmaf(float(rule_w(p) * rule_w(q)), ri, gL);
                 }
@@ -144,8 +150,9 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
             if (s < T) {
                 const auto st = stat + (size_t)s * kStat;
                 const auto sd = dyn + (size_t)s * kDyn;
+                // points and y . n scaled by s, the normal as it is
 #pragma unroll
-                for (int c = 0; c < 27; ++c) L.f[c][lane] = st[c];
+                for (int c = 0; c < 27; ++c) L.f[c][lane] = (c < 18 || c >= 21) ? st[c] * cf.kexp : st[c];
 #pragma unroll
                 for (int c = 0; c < 15; ++c) L.f[27 + c][lane] = sd[c];
                 L.id[0][lane] = tri[3 * s];
@@ -172,8 +179,8 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
             float tx[6], ty[6], tz[6], xnt[6];
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
-                tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2];
-                xnt[p] = ts[21 + p];
+                tx[p] = ts[3 * p] * cf.kexp; ty[p] = ts[3 * p + 1] * cf.kexp; tz[p] = ts[3 * p + 2] * cf.kexp;
+                xnt[p] = ts[21 + p] * cf.kexp;
             }
             const float ntx = ts[18], nty = ts[19], ntz = ts[20];
             const int v0 = tri[3 * tc], v1 = tri[3 * tc + 1], v2 = tri[3 * tc + 2];
@@ -185,9 +192,9 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
                     cs[0][p] = -cf.kL * b1; cs[1][p] = cf.vL * b2; cs[2][p] = -cf.kY * b1;
                     cs[3][p] = cf.vY * b2; cs[4][p] = -cf.kYk * b1;
                 } else {
-                    cs[0][p] = -cf.cKL * b1; cs[1][p] = -cf.cKY * b1; cs[2][p] = -cf.cKY * cf.kappa * b1;
+                    cs[0][p] = -cf.cKL * b1; cs[1][p] = -cf.cKY * b1; cs[2][p] = 0.0f;
                     cs[3][p] = cf.cVL * b2; cs[4][p] = cf.cVY * b2;
-                    cs[5][p] = -cf.cTL * b2; cs[6][p] = -cf.cTY * b2; cs[7][p] = -cf.cTY * cf.kappa * b2;
+                    cs[5][p] = -cf.cTL * b2; cs[6][p] = -cf.cTY * b2; cs[7][p] = 0.0f;
                     cs[8][p] = b1;
                 }
             }
@@ -298,7 +305,8 @@ __global__ void k_sym_set(int *p, int v) { *p = v; }
 
 // The symmetric split applies to FP32 matrix-free meshes of at least 128 tiles
 // (8192 triangles): smaller meshes have too few tile pairs to fill the device.
-bool sym_eligible(int T) { return T >= 8192; }
+// It needs kappa > 0 (the coordinate scale); kappa = 0 takes k_far.
+bool sym_eligible(int T, double kappa) { return T >= 8192 && kappa > 0.0; }
 
 // Ranges of rt tiles: about 320 ranges (51000 items) so that the heaviest-first
 // work list ends with items of a few milliseconds at most.
@@ -337,7 +345,7 @@ int sym_blocks(int nitems, int form)
 void launch_far_sym(DevMesh &d)
 {
     FarCoef<float> cf;
-    const int form = far_coef(d, cf);
+    const int form = far_coef_sym(d, cf);
     const int nb = d.sym_blocks[form == 0 ? 0 : form == 1 ? 1 : 2];
     hipLaunchKernelGGL(k_sym_set, dim3(1), dim3(1), 0, d.stream, d.sym_next, 0);
 #define SYM(F)                                                                                                 \

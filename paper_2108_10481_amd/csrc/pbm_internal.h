@@ -172,7 +172,6 @@ FormCoef formulation_coef(int formulation, double eps_in, double eps_out, double
 int laplace_row(const FormCoef &f);   // family 0: the row with only Laplace terms
 // family 1 with no Laplace term in any block (the Yukawa part of a PMCHWT matrix)
 bool yukawa_only(const FormCoef &f);
-bool dense_supported(const FormCoef &f);
 // Calderon preconditioners: the operator P (the PMCHWT matrix or one kernel's
 // part of it) and the scales (a, b) of blockdiag(aM, bM)^-1 on the left
 FormCoef calderon_coef(int formulation, int preconditioner, double eps_in, double eps_out);
@@ -364,7 +363,7 @@ void ss_group(const std::vector<int32_t> &tri, int n, const int32_t *t, const in
               int count[4]);
 int choose_chunks(int T);
 // symmetric FP32 far field (k_far_sym.hip)
-bool sym_eligible(int T);
+bool sym_eligible(int T, double kappa);
 void sym_plan(int T, int &rt, int &nr, std::vector<int2> &items);
 int sym_blocks(int nitems, int form);
 void launch_far_sym(DevMesh &d);

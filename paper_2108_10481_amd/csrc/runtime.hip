@@ -284,17 +284,6 @@ FormCoef formulation_coef(int formulation, double eps_in, double eps_out, double
     return f;
 }
 
-// The assembly's second-kind kernels factor each block by its Laplace
-// coefficient: every block needs one unless no block has a Laplace term.
-bool dense_supported(const FormCoef &f)
-{
-    if (f.family != 1 || yukawa_only(f)) return true;
-    for (int r = 0; r < 2; ++r)
-        for (int c = 0; c < 2; ++c)
-            if (f.aL[r][c] == 0.0) return false;
-    return true;
-}
-
 bool yukawa_only(const FormCoef &f)
 {
     if (f.family != 1) return false;
@@ -493,7 +482,7 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
     d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
     d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
     size_t part_bytes = sizeof(double) * 16 * (size_t)d->S * T;
-    if (opt->precision == PB_FP32 && opt->operator_mode != PB_TREECODE && d->far_rule == 0 && sym_eligible(T)) {
+    if (opt->precision == PB_FP32 && opt->operator_mode != PB_TREECODE && d->far_rule == 0 && sym_eligible(T, opt->kappa)) {
         // symmetric FP32 far field: 2 nr slots of 16 values per triangle
         std::vector<int2> items;
         sym_plan(T, d->sym_rt, d->sym_nr, items);
@@ -516,12 +505,8 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
     d->red1 = (double *)d->alloc(sizeof(double) * 8);
     d->yfar = (double *)d->alloc(sizeof(double) * 2 * V);
 
-    if ((opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16) && !dense_supported(d->fm))
-        fail(PB_E_STATE, "the assembled far field needs a Laplace term in every block of a second-kind or "
-                         "combined-field system (a zero combined-field coefficient of the external form): use "
-                         "the matrix-free or treecode far field");
     d->want_dense = opt->operator_mode == PB_ASSEMBLED || opt->precision >= PB_MIXED_BF16 ||
-                    (opt->operator_mode == PB_AUTO && d->far_rule == 0 && dense_supported(d->fm) &&
+                    (opt->operator_mode == PB_AUTO && d->far_rule == 0 &&
                      dense_fits(*d, calderon_separate(*d) && !opt->calderon_fast ? 2 : 1));
     setup_and_wait(*d);
     d->t_setup = now() - t0;
@@ -547,7 +532,7 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     const int S = o->source_chunks > 0 ? std::min(o->source_chunks, T) : choose_chunks(T);
     double b = t * (kGeo * 8 + kStat * 12 + kDyn * 12 + 6 * 8 + 12 * 8 + 3 * 4 * 2);
     double part = (double)S * t * 16 * 8;
-    if (o->precision == PB_FP32 && o->operator_mode != PB_TREECODE && o->regular_order != 1 && sym_eligible(T)) {
+    if (o->precision == PB_FP32 && o->operator_mode != PB_TREECODE && o->regular_order != 1 && sym_eligible(T, o->kappa)) {
         const double ntile = std::ceil(t / 64.0), rt = std::ceil(ntile / 320.0);
         part = std::max(part, 2.0 * std::ceil(ntile / rt) * t * 16 * 4);   // the symmetric far field's slots
     }

@@ -189,25 +189,29 @@ def test_full_size_sampled_rows(sphere32, form):
         assert _rel(got, ref) < tol, (prec, _rel(got, ref))
 
 
-@pytest.mark.parametrize("form,a,b", [(pbm.PB_DIRECT_INT, 1.0, 1.0), (pbm.PB_JUFFER, 1.0, 1.0),
-                                       (pbm.PB_DIRECT_EXT, 1.0, 1.0), (pbm.PB_MULLER_INT, 1.0, 1.0),
-                                       (pbm.PB_CFIE_EXT, 0.0, 1.0), (pbm.PB_CFIE_EXT, 0.0, 0.0)])
-def test_symmetric_far_field_full_size(sphere32, form, a, b):
+@pytest.mark.parametrize("form,a,b,kappa", [(pbm.PB_DIRECT_INT, 1.0, 1.0, 0.125), (pbm.PB_JUFFER, 1.0, 1.0, 0.125),
+                                             (pbm.PB_DIRECT_EXT, 1.0, 1.0, 0.125),
+                                             (pbm.PB_MULLER_INT, 1.0, 1.0, 0.125),
+                                             (pbm.PB_CFIE_EXT, 0.0, 1.0, 0.125), (pbm.PB_CFIE_EXT, 0.0, 0.0, 0.125),
+                                             (pbm.PB_DIRECT_INT, 1.0, 1.0, 0.0), (pbm.PB_JUFFER, 1.0, 1.0, 0.0)])
+def test_symmetric_far_field_full_size(sphere32, form, a, b, kappa):
     """20480-triangle sphere: the FP32 matrix-free far field, which evaluates
-    every unordered pair once for both directions, against the FP64 one, which
-    evaluates every ordered pair (the direct, second-kind and Yukawa-only
-    kernel forms; a zero combined-field constant leaves a row without Laplace
-    terms, both zero no Laplace term at all), within FP32 rounding; and its
-    sampled rows against the oracle's."""
+    every unordered pair once for both directions on coordinates scaled by
+    kappa log2(e), against the FP64 one, which evaluates every ordered pair
+    (the direct, second-kind and Yukawa-only kernel forms; a zero
+    combined-field constant leaves a row without Laplace terms, both zero no
+    Laplace term at all), within FP32 rounding; and its sampled rows against
+    the oracle's.  kappa = 0 (no screening) takes the per-ordered-pair FP32
+    kernel instead and is held to the same bounds."""
     m, _ = sphere32
     nv = m.n_vertices
     rng = np.random.default_rng(83)
     x = rng.standard_normal(2 * nv)
-    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, cfie_alpha=a, cfie_beta=b)) as h:
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, cfie_alpha=a, cfie_beta=b, kappa=kappa)) as h:
         y32 = pbm.pb_mesh_apply(h, x)
         y32b = pbm.pb_mesh_apply(h, x)
         yf = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_FAR_ONLY)
-    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, cfie_alpha=a, cfie_beta=b)) as h:
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, cfie_alpha=a, cfie_beta=b, kappa=kappa)) as h:
         y64 = pbm.pb_mesh_apply(h, x)
         yf64 = pbm.pb_mesh_apply(h, x, pbm.PB_APPLY_FAR_ONLY)
     assert np.array_equal(y32, y32b), "the symmetric product must be deterministic"
@@ -219,7 +223,7 @@ def test_symmetric_far_field_full_size(sphere32, form, a, b):
     rows = np.sort(rng.choice(nv, 4, replace=False))
     oform = {pbm.PB_DIRECT_INT: oracle.DIRECT, pbm.PB_JUFFER: oracle.JUFFER, pbm.PB_DIRECT_EXT: oracle.DIRECT_EXT,
              pbm.PB_MULLER_INT: oracle.MULLER_INT, pbm.PB_CFIE_EXT: oracle.CFIE_EXT}[form]
-    r1, r2 = oracle.system_rows(m, 4.0, 80.0, 0.125, oform, rows, x, alpha=a, beta=b)
+    r1, r2 = oracle.system_rows(m, 4.0, 80.0, kappa, oform, rows, x, alpha=a, beta=b)
     assert _rel(np.concatenate([y32[rows], y32[nv + rows]]), np.concatenate([r1, r2])) < 2e-5
 
 
@@ -833,7 +837,8 @@ _CFIE_CASES = [(pbm.PB_CFIE_INT, 0.5, 2.0), (pbm.PB_CFIE_INT, 0.0, 3.0), (pbm.PB
 
 
 def _degenerate(form, a, b):
-    """External combined field with a zero constant: a block without a Laplace term."""
+    """External combined field with one zero constant: one block row without a
+    Laplace term, the other with one."""
     return form == pbm.PB_CFIE_EXT and (a == 0.0) != (b == 0.0)
 
 
@@ -841,34 +846,31 @@ def _degenerate(form, a, b):
 def test_cfie_operator(meshes, base_operators, form, a, b):
     """Combined-field systems with general and zero constants (Eqs.
     bie:combined:int, bie:combined:ext) against the oracle's typed system:
-    matrix-free FP64 (1e-12) and FP32 (1e-5), treecode without separated
-    clusters (the direct sums, 1e-12), and assembled FP64 / FP32 where every
-    block has a Laplace term; otherwise the assembled mode is refused and
-    PB_AUTO stays matrix-free."""
+    matrix-free and assembled FP64 (1e-12) and FP32 (1e-5), and the treecode
+    without separated clusters
+    (the direct sums, 1e-12).  A zero constant leaves blocks without a
+    Laplace term, which the assembly takes with both coefficients inside the
+    kernel values (PB_AUTO assembles them too)."""
     m = meshes["star7"]
     A11, A12, A21, A22 = oracle.system_blocks(base_operators[0], base_operators[1], base_operators[2], 4.0, 80.0,
                                               form, a, b)
     A = np.block([[A11, A12], [A21, A22]])
     x = np.random.default_rng(91).standard_normal(2 * m.n_vertices)
     ref = A @ x
-    modes = [(pbm.PB_FP64, pbm.PB_MATRIX_FREE, 1e-12), (pbm.PB_FP32, pbm.PB_MATRIX_FREE, 1e-5)]
-    if not _degenerate(form, a, b):
-        modes += [(pbm.PB_FP64, pbm.PB_ASSEMBLED, 1e-12), (pbm.PB_FP32, pbm.PB_ASSEMBLED, 1e-5)]
+    modes = [(pbm.PB_FP64, pbm.PB_MATRIX_FREE, 1e-12), (pbm.PB_FP32, pbm.PB_MATRIX_FREE, 1e-5),
+             (pbm.PB_FP64, pbm.PB_ASSEMBLED, 1e-12), (pbm.PB_FP32, pbm.PB_ASSEMBLED, 1e-5)]
     for prec, mode, tol in modes:
         with pbm.MeshHandle(m.xyz, m.tri, _opts(form, prec, operator_mode=mode, cfie_alpha=a, cfie_beta=b)) as h:
+            assert h.info()["assembled"] == (1 if mode == pbm.PB_ASSEMBLED else 0)
             y = pbm.pb_mesh_apply(h, x)
         assert _rel(y, ref) < tol, (form, a, b, prec, mode, _rel(y, ref))
     with pbm.MeshHandle(m.xyz, m.tri, _opts(form, operator_mode=pbm.PB_TREECODE, tree_theta=1e-3,
                                             cfie_alpha=a, cfie_beta=b)) as h:
         assert _rel(pbm.pb_mesh_apply(h, x), ref) < 1e-12
     if _degenerate(form, a, b):
-        with pytest.raises(pbm.PbError) as e:
-            pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_ASSEMBLED,
-                                               cfie_alpha=a, cfie_beta=b))
-        assert e.value.code == pbm.PB_E_STATE
         with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, operator_mode=pbm.PB_AUTO,
                                                 cfie_alpha=a, cfie_beta=b)) as h:
-            assert h.info()["assembled"] == 0
+            assert h.info()["assembled"] == 1
             assert _rel(pbm.pb_mesh_apply(h, x), ref) < 1e-5
 
 
