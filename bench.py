@@ -353,7 +353,11 @@ def serving_prefix(nreq, rate=20.0, slots=8):
     import threading
     import paper_2108_10481_amd as pbm
     trace = inputs.serving_trace(5, nreq, rate)
-    reqs = [(r,) + inputs.build_request(r) for r in trace]
+    reqs = []
+    for k, r in enumerate(trace):
+        reqs.append((r,) + inputs.build_request(r))
+        if k % 64 == 63:
+            print(f"bench: serving {k + 1}/{nreq} requests built", file=sys.stderr, flush=True)
     print(f"bench: serving {nreq} requests built", file=sys.stderr, flush=True)
     opt_mixed = {f: pbm.pb_default_options(formulation=f, precision=pbm.PB_MIXED_BF16,
                                            operator_mode=pbm.PB_ASSEMBLED) for f in (0, 1)}
@@ -378,6 +382,8 @@ def serving_prefix(nreq, rate=20.0, slots=8):
             while tickets[k] is None:
                 time.sleep(0.001)
             served[k] = srv.wait(tickets[k])
+            if k % 64 == 63:
+                print(f"bench: served {k + 1}/{len(reqs)}", file=sys.stderr, flush=True)
         th.join()
         stats = srv.stats()
     lat = [x["t_end"] - x["t_submit"] for x in served]
@@ -443,96 +449,18 @@ def cpu_baseline(mesh, iterations, nrows, P, key):
 
 
 def serving(argv=None):
-    """Serving trace: Poisson arrivals of star-surface solve requests of
-    log-uniform size, replayed against the continuous-batching server."""
-    import threading
+    """The whole serving trace (512 requests by default): served on the
+    continuous-batching server in mixed BF16 and replayed serially in FIFO
+    order with the plain FP64 solve, both measured (serving_prefix)."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=20.0)
     ap.add_argument("--slots", type=int, default=8)
-    ap.add_argument("--precision", default="mixed-bf16", choices=["fp32", "mixed-bf16", "mixed-fp16"])
-    ap.add_argument("--subset", type=int, default=16)
     a, _ = ap.parse_known_args(argv)
-    import paper_2108_10481_amd as pbm
-    prec = {"fp32": pbm.PB_FP32, "mixed-bf16": pbm.PB_MIXED_BF16, "mixed-fp16": pbm.PB_MIXED_FP16}[a.precision]
-    trace = inputs.serving_trace(5, a.requests, a.rate)
-    reqs = []
-    for k, r in enumerate(trace):
-        if k % 64 == 0:
-            print(f"serving: building request {k}/{len(trace)}", file=sys.stderr, flush=True)
-        mesh, ch = inputs.build_request(r)
-        opt = pbm.pb_default_options(formulation=r["formulation"], precision=prec, operator_mode=pbm.PB_ASSEMBLED)
-        reqs.append((r, mesh, ch, opt))
-    results = [None] * len(reqs)
-    with pbm.Server(max_slots=a.slots) as srv:
-        # warm the device and libraries once, outside the trace
-        r0, m0, c0, o0 = reqs[0]
-        srv.wait(srv.submit(m0.xyz, m0.tri, c0.xyz, c0.q, o0))
-        tickets = [None] * len(reqs)
-        t_base = time.perf_counter()
-
-        def submitter():
-            for k, (r, mesh, ch, opt) in enumerate(reqs):
-                delay = t_base + r["arrival_s"] - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
-                tickets[k] = (time.perf_counter(), srv.submit(mesh.xyz, mesh.tri, ch.xyz, ch.q, opt))
-        th = threading.Thread(target=submitter)
-        th.start()
-        for k in range(len(reqs)):
-            while tickets[k] is None:
-                time.sleep(0.001)
-            t_sub, tk = tickets[k]
-            res = srv.wait(tk)
-            res["latency_s"] = res["t_end"] - res["t_submit"]
-            results[k] = res
-            if k % 64 == 63:
-                print(f"serving: {k + 1}/{len(reqs)} done", file=sys.stderr, flush=True)
-        th.join()
-        stats = srv.stats()
-    first = min(r["t_submit"] for r in results)
-    last = max(r["t_end"] for r in results)
-    lat = sorted(r["latency_s"] for r in results)
-    p = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
-
-    # serial plain FP64 comparator: measured on a stratified subset (sizes
-    # spread over the trace), modelled as time = c T^e, FIFO-queued on the trace
-    order = sorted(range(len(reqs)), key=lambda k: reqs[k][0]["n_triangles"])
-    pick = [order[int(i * (len(order) - 1) / max(a.subset - 1, 1))] for i in range(a.subset)]
-    meas = []
-    worst = 0.0
-    for k in pick:
-        r, mesh, ch, _ = reqs[k]
-        print(f"serving: FP64 comparator solve, {r['n_triangles']} triangles", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        g = pbm.pb_solve(mesh.xyz, mesh.tri, ch.xyz, ch.q,
-                         pbm.pb_default_options(formulation=r["formulation"], precision=pbm.PB_FP64))
-        meas.append((r["n_triangles"], time.perf_counter() - t0))
-        worst = max(worst, abs(results[k]["dG"] - g["dG"]) / abs(g["dG"]))
-    lt = np.log([m[0] for m in meas])
-    ly = np.log([m[1] for m in meas])
-    e, c = np.polyfit(lt, ly, 1)
-    free = 0.0
-    ser_lat, ser_end = [], []
-    for r, _, _, _ in reqs:
-        start = max(free, r["arrival_s"])
-        free = start + math.exp(c) * r["n_triangles"] ** e
-        ser_lat.append(free - r["arrival_s"])
-        ser_end.append(free)
-    ser_lat.sort()
-    sp = lambda q: ser_lat[min(len(ser_lat) - 1, int(math.ceil(q * len(ser_lat))) - 1)]
-    rec = {"workload": f"serving trace: {len(reqs)} star-surface requests, Poisson arrivals at {a.rate} req/s, "
-                       "1280-81920 triangles log-uniform, 50-4000 charges, direct/Juffer mixed",
-           "precision": a.precision, "slots": a.slots,
-           "solves_per_s": round(len(reqs) / (last - first), 4), "p50_s": round(p(0.5), 4),
-           "p99_s": round(p(0.99), 4), "max_latency_s": round(lat[-1], 4),
-           "peak_running": stats["peak_running"], "peak_inflight_GB": round(stats["peak_inflight_bytes"] / 1e9, 2),
-           "dG_rel_err_vs_fp64_subset_max": worst,
-           "serial_fp64_model": {"solves_per_s": round(len(reqs) / (ser_end[-1] - reqs[0][0]["arrival_s"]), 4),
-                                 "p50_s": round(sp(0.5), 3), "p99_s": round(sp(0.99), 3),
-                                 "fit": f"t = {math.exp(c):.3e} * T^{e:.3f} s from {len(meas)} measured FP64 "
-                                        "matrix-free solves spanning the trace's sizes"}}
+    rec = serving_prefix(a.requests, a.rate, a.slots)
+    rec["workload"] = rec["workload"].replace(f"first {a.requests} requests of the serving trace",
+                                              f"serving trace, {a.requests} requests")
     print(json.dumps(rec), flush=True)
 
 
