@@ -8,6 +8,7 @@
 #include <exception>
 #include <mutex>
 #include <numeric>
+#include <system_error>
 #include <thread>
 
 #include "pbm_internal.h"
@@ -89,24 +90,33 @@ static int prep_workers(int n, int min_rows)
 }
 
 // fn(worker, begin, end) over nw contiguous ranges of [0, n); an exception in a
-// worker is rethrown on the calling thread
+// worker is rethrown on the calling thread.  A range whose thread cannot be
+// started runs on the calling thread.
 template <typename F>
 static void parallel_chunks(int n, int nw, F &&fn)
 {
     if (nw <= 1) { fn(0, 0, n); return; }
     std::vector<std::thread> th;
+    th.reserve(nw);
     std::exception_ptr err;
     std::mutex mu;
+    auto run = [&](int w, int b, int e) {
+        try {
+            fn(w, b, e);
+        } catch (...) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (!err) err = std::current_exception();
+        }
+    };
     for (int w = 0; w < nw; ++w) {
         const int b = (int)((int64_t)n * w / nw), e = (int)((int64_t)n * (w + 1) / nw);
-        th.emplace_back([&, w, b, e] {
-            try {
-                fn(w, b, e);
-            } catch (...) {
-                std::lock_guard<std::mutex> lk(mu);
-                if (!err) err = std::current_exception();
-            }
-        });
+        bool started = false;
+        try {
+            th.emplace_back(run, w, b, e);
+            started = true;
+        } catch (const std::system_error &) {
+        }
+        if (!started) run(w, b, e);
     }
     for (auto &t : th) t.join();
     if (err) std::rethrow_exception(err);
