@@ -174,6 +174,16 @@ typedef struct {
                                  triangle; 1: the one-point (centroid) rule, matrix-free in FP64
                                  or FP32 only, not with the Calderon preconditioners.  The source
                                  projections and Delta G always use the 6-point rule. */
+    int32_t far_symmetric;    /* FP32 matrix-free far field with kappa > 0 (Numerical
+                                 discretization; the kernels are symmetric in x, y): every
+                                 unordered triangle pair evaluated once for both directions or
+                                 every ordered pair.  0 (default): once per unordered pair on
+                                 meshes of 3584 triangles and more, per ordered pair below (where
+                                 one mesh leaves most of the device idle); 1: once per unordered
+                                 pair at every size (faster for many small meshes solved together
+                                 by pb_solve_batch); -1: per ordered pair.  Single and batched
+                                 solves of a handle use the same choice, so their results stay
+                                 bitwise equal; the two choices agree to FP32 rounding. */
 } pb_options;
 
 typedef struct {
@@ -204,7 +214,8 @@ typedef struct {
 
 /* Fill *opt with the paper's settings: eps 4/80, kappa 0.125, direct
  * formulation, block-diagonal preconditioner, FP64, matrix-free, tol 1e-5,
- * max_iter 1000, singular order 4, regular order 4; cfie_alpha = cfie_beta = 1. */
+ * max_iter 1000, singular order 4, regular order 4; cfie_alpha = cfie_beta = 1;
+ * far_symmetric 0 (automatic). */
 void pb_default_options(pb_options *opt);
 
 /* Thread-local description of the last error on this thread ("" if none). */

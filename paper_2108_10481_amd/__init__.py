@@ -83,7 +83,8 @@ class pb_options(ctypes.Structure):
                 ("source_chunks", ctypes.c_int32), ("inner_max_iter", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("memory_budget", ctypes.c_size_t), ("use_graph", ctypes.c_int32),
                 ("calderon_fast", ctypes.c_int32), ("tree_degree", ctypes.c_int32), ("tree_theta", ctypes.c_double),
-                ("cfie_alpha", ctypes.c_double), ("cfie_beta", ctypes.c_double), ("regular_order", ctypes.c_int32)]
+                ("cfie_alpha", ctypes.c_double), ("cfie_beta", ctypes.c_double), ("regular_order", ctypes.c_int32),
+                ("far_symmetric", ctypes.c_int32)]
 
 
 class pb_result(ctypes.Structure):

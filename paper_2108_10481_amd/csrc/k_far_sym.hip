@@ -303,10 +303,18 @@ __global__ void k_sym_set(int *p, int v) { *p = v; }
 
 // ------------------------------------------------------------------ host
 
-// The symmetric split applies to FP32 matrix-free meshes of at least 128 tiles
-// (8192 triangles): smaller meshes have too few tile pairs to fill the device.
-// It needs kappa > 0 (the coordinate scale); kappa = 0 takes k_far.
-bool sym_eligible(int T, double kappa) { return T >= 8192 && kappa > 0.0; }
+// The symmetric split applies to FP32 matrix-free meshes with kappa > 0 (the
+// coordinate scale; kappa = 0 takes k_far).  Automatic (mode 0): 56 tiles
+// (3584 triangles) and more -- on one smaller mesh too few tile pairs fill the
+// device (measured: at 2880 triangles both kernels take about 0.25 ms per
+// product, at 3920 the split is 7% / 33% faster, direct / Juffer, at 8000 35% /
+// 40%), while many small meshes batched together fill it either way; mode 1
+// always, mode -1 never.
+bool sym_eligible(int T, double kappa, int mode)
+{
+    if (!(kappa > 0.0) || mode < 0) return false;
+    return mode > 0 || T >= 3584;
+}
 
 // Ranges of rt tiles: about 320 ranges (51000 items) so that the heaviest-first
 // work list ends with items of a few milliseconds at most.

@@ -363,7 +363,7 @@ void ss_group(const std::vector<int32_t> &tri, int n, const int32_t *t, const in
               int count[4]);
 int choose_chunks(int T);
 // symmetric FP32 far field (k_far_sym.hip)
-bool sym_eligible(int T, double kappa);
+bool sym_eligible(int T, double kappa, int mode);
 void sym_plan(int T, int &rt, int &nr, std::vector<int2> &items);
 int sym_blocks(int nitems, int form);
 void launch_far_sym(DevMesh &d);

@@ -215,6 +215,8 @@ static void check_options(const pb_options *o)
     if (!(o->tol > 0) || o->max_iter < 1) fail(PB_E_INVALID_ARG, "tol must be > 0 and max_iter >= 1");
     if (o->singular_order < 1 || o->singular_order > 8) fail(PB_E_INVALID_ARG, "singular_order must be in [1, 8]");
     if (o->source_chunks < 0 || o->source_chunks > 1024) fail(PB_E_INVALID_ARG, "source_chunks must be in [0, 1024]");
+    if (o->far_symmetric < -1 || o->far_symmetric > 1)
+        fail(PB_E_INVALID_ARG, "far_symmetric must be 0 (automatic), 1 (always) or -1 (never)");
     if (o->regular_order != 0 && o->regular_order != 1 && o->regular_order != 4)
         fail(PB_E_INVALID_ARG, "regular_order must be 4 (the 6-point rule) or 1 (the one-point rule)");
     if (o->regular_order == 1) {
@@ -482,7 +484,8 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
     d->dyn64 = (double *)d->alloc(sizeof(double) * kDyn * T);
     d->dyn32 = (float *)d->alloc(sizeof(float) * kDyn * T);
     size_t part_bytes = sizeof(double) * 16 * (size_t)d->S * T;
-    if (opt->precision == PB_FP32 && opt->operator_mode != PB_TREECODE && d->far_rule == 0 && sym_eligible(T, opt->kappa)) {
+    if (opt->precision == PB_FP32 && opt->operator_mode != PB_TREECODE && d->far_rule == 0 &&
+        sym_eligible(T, opt->kappa, opt->far_symmetric)) {
         // symmetric FP32 far field: 2 nr slots of 16 values per triangle
         std::vector<int2> items;
         sym_plan(T, d->sym_rt, d->sym_nr, items);
@@ -532,7 +535,8 @@ size_t estimate_device_bytes(int V, int T, const pb_options *o)
     const int S = o->source_chunks > 0 ? std::min(o->source_chunks, T) : choose_chunks(T);
     double b = t * (kGeo * 8 + kStat * 12 + kDyn * 12 + 6 * 8 + 12 * 8 + 3 * 4 * 2);
     double part = (double)S * t * 16 * 8;
-    if (o->precision == PB_FP32 && o->operator_mode != PB_TREECODE && o->regular_order != 1 && sym_eligible(T, o->kappa)) {
+    if (o->precision == PB_FP32 && o->operator_mode != PB_TREECODE && o->regular_order != 1 &&
+        sym_eligible(T, o->kappa, o->far_symmetric)) {
         const double ntile = std::ceil(t / 64.0), rt = std::ceil(ntile / 320.0);
         part = std::max(part, 2.0 * std::ceil(ntile / rt) * t * 16 * 4);   // the symmetric far field's slots
     }
@@ -1554,6 +1558,7 @@ void pb_default_options(pb_options *o)
     o->cfie_alpha = 1.0;
     o->cfie_beta = 1.0;
     o->regular_order = 4;
+    o->far_symmetric = 0;
 }
 
 const char *pb_last_error(void) { return g_err.c_str(); }

@@ -30,11 +30,11 @@ def _requests():
     ]
 
 
-def _handles(reqs, precision, mode=None, use_graph=1):
+def _handles(reqs, precision, mode=None, use_graph=1, far_symmetric=0):
     mode = pbm.PB_MATRIX_FREE if mode is None else mode
     return [pbm.MeshHandle(m.xyz, m.tri, pbm.pb_default_options(formulation=f, preconditioner=p,
                                                                 precision=precision, operator_mode=mode,
-                                                                use_graph=use_graph))
+                                                                use_graph=use_graph, far_symmetric=far_symmetric))
             for m, _, f, p in reqs]
 
 
@@ -44,10 +44,12 @@ def _same(a, b):
     assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["dphi"], b["dphi"])
 
 
-@pytest.mark.parametrize("precision", [pbm.PB_FP64, pbm.PB_FP32])
-def test_batch_equals_single_solves(precision):
+@pytest.mark.parametrize("precision,sym", [(pbm.PB_FP64, 0), (pbm.PB_FP32, 0), (pbm.PB_FP32, 1)])
+def test_batch_equals_single_solves(precision, sym):
+    """sym = 1: every request's far field evaluated once per unordered
+    triangle pair (far_symmetric 1) in its single solve and in the batch."""
     reqs = _requests()
-    hs = _handles(reqs, precision)
+    hs = _handles(reqs, precision, far_symmetric=sym)
     try:
         single = [pbm.pb_mesh_solve(h, c.xyz, c.q) for h, (_, c, _, _) in zip(hs, reqs)]
         batch = pbm.pb_solve_batch(hs, [(c.xyz, c.q) for _, c, _, _ in reqs])

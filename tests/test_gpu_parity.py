@@ -113,13 +113,40 @@ def test_operator_fp64(meshes, dense_systems, name, form):
 
 
 @pytest.mark.parametrize("form", [0, 1])
-def test_operator_fp32(meshes, dense_systems, form):
+@pytest.mark.parametrize("sym", [0, 1])
+def test_operator_fp32(meshes, dense_systems, form, sym):
+    """FP32 matrix-free products of a 980-triangle mesh against the oracle's
+    dense system: each ordered triangle pair evaluated (far_symmetric 0, the
+    automatic choice at this size) or each unordered pair once for both
+    directions (far_symmetric 1); the two agree to FP32 rounding."""
     m = meshes["star7"]
     A = dense_systems[("star7", form)]
     x = np.random.default_rng(5).standard_normal(2 * m.n_vertices)
-    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32)) as h:
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(form, pbm.PB_FP32, far_symmetric=sym)) as h:
         y = pbm.pb_mesh_apply(h, x)
+        y2 = pbm.pb_mesh_apply(h, x)
     assert _rel(y, A @ x) < 1e-5
+    assert np.array_equal(y, y2), "FP32 products must be deterministic"
+
+
+def test_far_symmetric_option():
+    """far_symmetric -1 on a mesh the automatic choice splits symmetrically
+    (5120 triangles) gives the per-ordered-pair product to FP32 rounding of
+    the symmetric one and of FP64; values outside {-1, 0, 1} are refused."""
+    m, _ = inputs.star_surface(9, 16, 9.0)                     # T = 5120
+    x = np.random.default_rng(17).standard_normal(2 * m.n_vertices)
+    ys = {}
+    for sym in (0, 1, -1):
+        with pbm.MeshHandle(m.xyz, m.tri, _opts(1, pbm.PB_FP32, far_symmetric=sym)) as h:
+            ys[sym] = pbm.pb_mesh_apply(h, x)
+    with pbm.MeshHandle(m.xyz, m.tri, _opts(1)) as h:
+        y64 = pbm.pb_mesh_apply(h, x)
+    assert np.array_equal(ys[0], ys[1]), "5120 triangles take the symmetric split automatically"
+    for sym in (0, -1):
+        assert _rel(ys[sym], y64) < 2e-6, (sym, _rel(ys[sym], y64))
+    with pytest.raises(pbm.PbError) as e:
+        pbm.MeshHandle(m.xyz, m.tri, _opts(1, pbm.PB_FP32, far_symmetric=2))
+    assert e.value.code == pbm.PB_E_INVALID_ARG
 
 
 @pytest.mark.parametrize("name", ["sphere6", "star7"])

@@ -56,6 +56,7 @@ def test_default_options_match_paper(pbm):
     assert (o.eps_in, o.eps_out, o.kappa, o.tol) == (4.0, 80.0, 0.125, 1e-5)
     assert o.formulation == pbm.PB_DIRECT_INT and o.preconditioner == pbm.PB_BLOCK_DIAG
     assert o.singular_order == 4 and o.max_iter == 1000
+    assert o.regular_order == 4 and o.far_symmetric == 0
 
 
 def _create_status(pbm, xyz, tri, **kw):
