@@ -495,6 +495,7 @@ def multi(argv=None):
                 res = pbm.pb_solve_multi(h, args)
             dt = (time.perf_counter() - t0) / steps
             n, ms, work = pbm.pb_mesh_profile_read(h, 0)
+            t_setup = h.info()   # after the batched products (the GEMM's tiled copy included)
             err = max(abs(r["dG"] - g) / abs(g) for r, g in zip(res, ref))
             out[name] = {"solves_per_s": round(len(sets) / dt, 3), "s_per_16_set_batch": round(dt, 4),
                          "inner_iterations_max": max(r["iterations"] for r in res),

@@ -280,8 +280,11 @@ pb_status pb_solve_batch(int32_t n, pb_mesh_handle *const *handles, const pb_cha
 
 /* Solve for n_sets charge sets on one resident mesh.  In assembled modes the
  * right-hand sides are advanced together and every operator application is
- * one batched dense product (MFMA for 16-bit storage).  out[k] follows the
- * pb_result contract for set k.  PB_E_STATE for the Calderon preconditioners. */
+ * one batched dense product (MFMA for 16-bit storage; the first such product
+ * adds to the handle a copy of the 16-bit matrix in the MFMA operand order,
+ * 2 bytes per entry, rebuilt after each reassembly, or reads the row-major
+ * copy when the budget leaves no room for it).  out[k] follows the pb_result
+ * contract for set k.  PB_E_STATE for the Calderon preconditioners. */
 pb_status pb_solve_multi(pb_mesh_handle *h, int32_t n_sets, const pb_charges *sets,
                          pb_result *out);
 

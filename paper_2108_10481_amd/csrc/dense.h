@@ -45,10 +45,17 @@ struct Dense {
     double *gpart = nullptr;       // 2 n partial row sums of the split GEMV
     int level = 1;                 // 1: accurate operator, 0: 16-bit operator
     int gemv_hi = -1, gemv_lo = -1;   // autotuned GEMV variants (-1: not tuned yet)
-    int gemm_rows = 0;                // autotuned rows per wavefront of the MFMA GEMM (0: not tuned)
     // multi right-hand side workspaces (allocated on first use)
     uint16_t *X16 = nullptr;       // 16 x ld
     double *Y16 = nullptr;         // 16 x n
+    // the 16-bit copy in the MFMA GEMM's operand order (allocated on the first
+    // batched product): for each 16-row tile and 32-column step, the 16 x 32
+    // block as 64 lanes x 8 values (lane l: row l % 16, columns 8 (l / 16) ..),
+    // so each of the GEMM's loads reads 1 KB of consecutive bytes; refreshed
+    // when the 16-bit copy is rewritten (the versions differ)
+    uint16_t *A16t = nullptr;
+    bool a16t_failed = false;      // no room for it: the GEMM reads the row-major copy
+    unsigned a16_version = 0, a16t_version = 0;
 };
 
 constexpr int kMaxBatch = 16;

@@ -28,8 +28,6 @@ pb_status finish_result(DevMesh &d, const pb_charges *ch, const double *pb, doub
                         double t_rhs, double t_prec, double t_gmres, pb_result *res);
 void charges_to_device(DevMesh &d, const pb_charges *c);
 void check_charges_inside(DevMesh &d, int nq);
-int autotune_pick(const std::string &key, int nvariants, const std::function<void(int)> &run, hipStream_t st);
-std::string size_class(long long n);
 
 // ------------------------------------------------------------------ GEMM
 // One wavefront per 16-row tile, all 16 right-hand sides.  v_mfma_f32_16x16x32
@@ -45,7 +43,9 @@ __device__ __forceinline__ f32x4 mfma16(const uint16_t *a, const uint16_t *b, f3
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(*(const f16x8 *)a, *(const f16x8 *)b, c, 0, 0, 0);
 }
 
-// RT row tiles of 16 per wavefront share each B (x) fragment.
+// Row-major operand (used when the tiled copy below does not fit): RT row
+// tiles of 16 per wavefront share each B (x) fragment.  Each load reads 64
+// bytes of 16 rows.
 template <int KIND, int RT>
 __global__ __launch_bounds__(256) void k_gemm16(int n, int V, size_t Vp, size_t ld, const uint16_t *__restrict__ A,
                                                 const uint16_t *__restrict__ X, float i0, float i1, float i2, float i3,
@@ -87,6 +87,58 @@ __global__ __launch_bounds__(256) void k_gemm16(int n, int V, size_t Vp, size_t 
                     Y[(size_t)cl * n + r] = (double)c0[t][i] * (top ? i0 : i2) + (double)c1[t][i] * (top ? i1 : i3);
                 }
             }
+    }
+}
+
+// Tiled operand: nk = ld / 32 steps per 16-row tile, the first nk0 = Vp / 32
+// in the first column block; lane l reads the 16 bytes at (tile nk + s) 512 +
+// 8 l, so a wavefront's load is 1 KB of consecutive bytes.  The MFMA sequence
+// and every lane's operands are those of k_gemm16<KIND, 1>, so the results are
+// bitwise the same.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_gemm16t(int n, int V, int nk0, int nk, size_t ld,
+                                                 const uint16_t *__restrict__ At, const uint16_t *__restrict__ X,
+                                                 float i0, float i1, float i2, float i3, double *__restrict__ Y)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int nwave = gridDim.x * 4;
+    const int ntile = (n + 15) / 16;
+    const int kq = (lane >> 4) * 8;
+    const int cl = lane & 15;
+    const uint16_t *xrow = X + (size_t)cl * ld + kq;
+    for (int tile = wave; tile < ntile; tile += nwave) {
+        const uint16_t *at = At + (size_t)tile * nk * 512 + 8 * lane;
+        f32x4 c0 = f32x4{0.f, 0.f, 0.f, 0.f}, c1 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int st = 0; st < nk0; ++st) c0 = mfma16<KIND>(at + (size_t)st * 512, xrow + (size_t)st * 32, c0);
+#pragma unroll 4
+        for (int st = nk0; st < nk; ++st) c1 = mfma16<KIND>(at + (size_t)st * 512, xrow + (size_t)st * 32, c1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = tile * 16 + 4 * (lane >> 4) + i;
+            if (r < n) {
+                const bool top = r < V;
+                Y[(size_t)cl * n + r] = (double)c0[i] * (top ? i0 : i2) + (double)c1[i] * (top ? i1 : i3);
+            }
+        }
+    }
+}
+
+// Row-major 16-bit copy -> tiled copy (k_gemm16t's operand order); rows past
+// n are zero.  One 16-byte chunk per (tile, step, lane).
+__global__ void k_tile16(int n, size_t ld, int ntile, int nk, const uint16_t *__restrict__ A,
+                         uint16_t *__restrict__ At)
+{
+    const size_t total = (size_t)ntile * nk * 64;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < total; c += (size_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(c & 63);
+        const size_t ts = c >> 6;                    // tile * nk + step
+        const int tile = (int)(ts / (size_t)nk), st = (int)(ts % (size_t)nk);
+        const int row = tile * 16 + (lane & 15);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (row < n) v = *(const uint4 *)(A + (size_t)row * ld + (size_t)st * 32 + (lane >> 4) * 8);
+        *(uint4 *)(At + c * 8) = v;
     }
 }
 
@@ -260,27 +312,39 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
         float inv[4] = {1.f, 1.f, 1.f, 1.f};
         if (D->kind16 == 2)
             for (int b = 0; b < 4; ++b) inv[b] = 1.f / D->scale16[b];
-        auto launch = [&](int v) {   // v = 0: one 16-row tile per wavefront, 1: two
-            const int rt = v == 0 ? 1 : 2;
-            const int ntile = (n + 16 * rt - 1) / (16 * rt);
-            const int nwg = std::min((ntile + 3) / 4, 4096);
-            if (D->kind16 == 1 && rt == 1)
-                hipLaunchKernelGGL((k_gemm16<1, 1>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
-                                   D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
-            else if (D->kind16 == 1)
+        const int ntile = (n + 15) / 16, nk = (int)(D->ld / 32), nk0 = (int)(D->Vp / 32);
+        if (!D->A16t && !D->a16t_failed) {
+            try {
+                D->A16t = (uint16_t *)d.alloc(sizeof(uint16_t) * (size_t)ntile * nk * 512);
+            } catch (const Error &) {
+                (void)hipGetLastError();
+                D->a16t_failed = true;
+            }
+        }
+        if (D->A16t && D->a16t_version != D->a16_version) {
+            hipLaunchKernelGGL(k_tile16, dim3(8192), dim3(256), 0, d.stream, n, D->ld, ntile, nk, D->A16, D->A16t);
+            D->a16t_version = D->a16_version;
+        }
+        auto launch = [&]() {
+            if (D->A16t) {
+                const int nwg = std::min((ntile + 3) / 4, 4096);
+                if (D->kind16 == 1)
+                    hipLaunchKernelGGL((k_gemm16t<1>), dim3(nwg), dim3(256), 0, d.stream, n, V, nk0, nk, D->ld,
+                                       D->A16t, D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
+                else
+                    hipLaunchKernelGGL((k_gemm16t<2>), dim3(nwg), dim3(256), 0, d.stream, n, V, nk0, nk, D->ld,
+                                       D->A16t, D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
+                return;
+            }
+            const int nt2 = (n + 31) / 32;
+            const int nwg = std::min((nt2 + 3) / 4, 4096);
+            if (D->kind16 == 1)
                 hipLaunchKernelGGL((k_gemm16<1, 2>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
-                                   D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
-            else if (rt == 1)
-                hipLaunchKernelGGL((k_gemm16<2, 1>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
                                    D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
             else
                 hipLaunchKernelGGL((k_gemm16<2, 2>), dim3(nwg), dim3(256), 0, d.stream, n, V, D->Vp, D->ld, D->A16,
                                    D->X16, inv[0], inv[1], inv[2], inv[3], D->Y16);
         };
-        if (D->gemm_rows == 0) {
-            const std::string key = std::string("gemm16/") + (D->kind16 == 1 ? "bf16/" : "fp16/") + size_class(n);
-            D->gemm_rows = 1 + autotune_pick(key, 2, launch, d.stream);
-        }
         Profiler &pf = d.prof;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (pf.on(0)) {
@@ -288,7 +352,7 @@ static void apply_batch(DevMesh &d, int nb, const double *X, double *Y)
             HIPCHECK(hipEventCreate(&e1));
             HIPCHECK(hipEventRecord(e0, d.stream));
         }
-        launch(D->gemm_rows - 1);
+        launch();
         if (pf.on(0)) {
             HIPCHECK(hipEventRecord(e1, d.stream));
             pf.record(0, e0, e1, (double)n * n * 2.0 + kMaxBatch * (double)n * (2.0 + 8.0));

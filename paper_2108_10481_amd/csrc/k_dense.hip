@@ -1037,6 +1037,7 @@ void build_dense(DevMesh &d)
         }
         hipLaunchKernelGGL(k_to16, dim3(8192), dim3(256), 0, d.stream, D.n, V, D.Vp, D.ld, D.kind16, D.scale16[0],
                            D.scale16[1], D.scale16[2], D.scale16[3], D.A32, D.A16);
+        ++D.a16_version;   // a tiled copy for the batched GEMM is now stale
         (void)total;
     }
     HIPCHECK(hipGetLastError());
