@@ -54,8 +54,12 @@ struct FarReq {
 
 // One source triangle against the six points of a target triangle: the
 // regular-rule sums of k_far (the caller has excluded pairs sharing a vertex).
-// st: the source's static record (entries 0..26 are read), sd: its dynamic
-// record (entries 0..14).
+// st: the source's static record (entries 0..21 are read), sd: its dynamic
+// record (entries 0..14); ot: the target's plane offset x . n_t (any of its
+// points).  The points of a flat triangle lie in its plane, so with d =
+// x_p - y_q the normal components d . n_s = x_p . n_s - o_s and d . n_t = o_t -
+// y_q . n_t depend on one of the two points only and are formed once per
+// point, not per point pair.
 // SP: pointer type of the source records (a generic pointer, or one into the
 // constant address space where the caller needs scalar loads)
 // With d = x_p - y_q, r = |d|, e = exp(-kappa r), G_L = 1/r, G_Y = e/r,
@@ -66,19 +70,18 @@ struct FarReq {
 template <typename R, int FORM, typename SP = const R *>
 __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__ st,
                                            SP __restrict__ sd, const R (&tx)[6], const R (&ty)[6],
-                                           const R (&tz)[6], const R (&xnt)[6], R ntx, R nty, R ntz, R (&a1)[6],
+                                           const R (&tz)[6], R ot, R ntx, R nty, R ntz, R (&a1)[6],
                                            R (&a2)[6], R &W0, R &W1, R &W2)
 {
-    const R nsx = st[18], nsy = st[19], nsz = st[20];
-    R xns[6];
+    const R nsx = st[18], nsy = st[19], nsz = st[20], os = st[21];
+    R dns[6];   // (x_p - y) . n_s
 #pragma unroll
-    for (int p = 0; p < 6; ++p) xns[p] = tx[p] * nsx + ty[p] * nsy + tz[p] * nsz;
+    for (int p = 0; p < 6; ++p) dns[p] = fma(tx[p], nsx, fma(ty[p], nsy, fma(tz[p], nsz, -os)));
     R gL = 0, gY = 0, k2nn = 0;
     if (FORM >= 1) k2nn = cf.cDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const R yx = st[3 * q], yy = st[3 * q + 1], yz = st[3 * q + 2];
-        const R yns = st[21 + q];
         const R b1 = sd[q], b2 = sd[6 + q];
         if (FORM == 0) {
             const R c1 = cf.kL * b1, c2 = cf.vL * b2, c3 = cf.kY * b1, c4 = cf.vY * b2, c3k = cf.kYk * b1;
@@ -87,13 +90,13 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
                 const R dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
                 const R r2 = dx * dx + dy * dy + dz * dz;
                 const R ri = rsqrt_r(r2);
-                const R g = (xns[p] - yns) * (ri * ri);
+                const R g = dns[p] * (ri * ri);
                 a1[p] = fma(ri, fma(c1, g, c2), a1[p]);
                 const R e = expneg(cf.kexp, r2 * ri);
                 a2[p] = fma(e, fma(ri, fma(c3, g, c4), c3k * g), a2[p]);
             }
         } else {
-            const R ynt = yx * ntx + yy * nty + yz * ntz;
+            const R dnt = fma(-yx, ntx, fma(-yy, nty, fma(-yz, ntz, ot)));   // (x - y_q) . n_t
             const R c1L = cf.cKL * b1, c1Y = cf.cKY * b1, c2L = cf.cVL * b2, c2Y = cf.cVY * b2;
             const R c3L = cf.cTL * b2, c3Y = cf.cTY * b2, kb1 = k2nn * b1;
 #pragma unroll
@@ -105,7 +108,7 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
                 const R e = expneg(cf.kexp, r2 * ri);
                 const R gy = e * ri;
                 const R ek = e * (ri + cf.kappa);   // F_Y d.n = ek g
-                const R g = (xns[p] - yns) * ri2, h = (xnt[p] - ynt) * ri2;
+                const R g = dns[p] * ri2, h = dnt * ri2;
                 if (FORM == 3) {
                     a1[p] = fma(g, ek * c1Y, fma(gy, c2Y, a1[p]));
                     a2[p] = fma(h, ek * c3Y, fma(gy, kb1, a2[p]));

@@ -134,13 +134,11 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
     const int sl = s < T ? s : T - 1;
     const int j0 = tri[3 * sl], j1 = tri[3 * sl + 1], j2 = tri[3 * sl + 2];
     const R *ss = stat + (size_t)sl * kStat;
-    const R nsx = ss[18], nsy = ss[19], nsz = ss[20], sarea = ss[27];
-    R sy[6][3], yns[6];
+    // os: the source plane's offset y . n_s (the same for its six points)
+    const R nsx = ss[18], nsy = ss[19], nsz = ss[20], os = ss[21], sarea = ss[27];
+    R sy[6][3];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        sy[q][0] = ss[3 * q]; sy[q][1] = ss[3 * q + 1]; sy[q][2] = ss[3 * q + 2];
-        yns[q] = ss[21 + q];
-    }
+    for (int q = 0; q < 6; ++q) { sy[q][0] = ss[3 * q]; sy[q][1] = ss[3 * q + 1]; sy[q][2] = ss[3 * q + 2]; }
     // the lane's vertex column of the tile (a lane without one re-reads the
     // tile's first and never stores it) and its first kPre incidences
     // (tile slot << 2 | local vertex)
@@ -180,13 +178,18 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
         };
         if constexpr (!SYM) load_old(c0);
 
-        const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+        const R ntx = ts[18], nty = ts[19], ntz = ts[20], ot = ts[21];
         const R rho = (R)RuleOrbit::rho, al = (R)RuleOrbit::al, be = (R)RuleOrbit::be;
+        // Flat triangles: with d = x_p - y_q, d . n_s = x_p . n_s - os depends on
+        // the target point only and d . n_t = ot - y_q . n_t on the source point only
+        R dns[6];
+#pragma unroll
+        for (int p = 0; p < 6; ++p) dns[p] = ts[3 * p] * nsx + ts[3 * p + 1] * nsy + ts[3 * p + 2] * nsz - os;
         R blk[3][3][NV], Cq[3][NV];   // [l][k][o]; Cq: rank-two part of the target-side weights
         R Ssum = 0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const R ynt = (FORM == 1 || SYM) ? sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz : R(0);
+            const R dnt = (FORM == 1 || SYM) ? ot - (sy[q][0] * ntx + sy[q][1] * nty + sy[q][2] * ntz) : R(0);
             R X[3][NV], SA[NV], SB[NV];
             R sLA = 0, sLB = 0;   // orbit sums of G_L over the target points (FORM 1, LROW 2)
 #pragma unroll
@@ -198,20 +201,19 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                 const R r = r2 * ri;
                 const R ek = expneg(cf.kexp, r);
                 const R ri3 = ri * ri * ri;
-                const R dns = (tx * nsx + ty * nsy + tz * nsz) - yns[q];
                 const R ekk = ek * (cf.kappa * r + R(1));
                 R v[NV];
                 if (FORM == 0) {
                     // direct formulations: one row has Laplace (F_L d.n_s, G_L), the other
                     // Yukawa kernels (F_Y d.n_s, G_Y); the swapped pair's K of the first
                     // column with d.n_t.  Values ordered by block; LROW = the Laplace row.
-                    const R kl = ri3 * dns, ky = ekk * kl;
+                    const R kl = ri3 * dns[p], ky = ekk * kl;
                     v[LROW == 0 ? 0 : 2] = kl;
                     v[LROW == 0 ? 1 : 3] = ri;
                     v[LROW == 0 ? 2 : 0] = ky;
                     v[LROW == 0 ? 3 : 1] = ek * ri;
                     if (SYM) {
-                        const R klt = ri3 * (ts[21 + p] - ynt);
+                        const R klt = ri3 * dnt;
                         v[LROW == 0 ? 4 : 5] = klt;
                         v[LROW == 0 ? 5 : 4] = ekk * klt;
                     }
@@ -227,14 +229,13 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(SYM ? 2 : 
                     if (LROW == 0) { a1 = ri3 + cf.rK * fy; a2 = ri3 + cf.rT * fy; }
                     else if (LROW == 1) { a1 = fy; a2 = fy; }
                     else { a1 = cf.aL[0][0] * ri3 + cf.aY[0][0] * fy; a2 = cf.aL[1][1] * ri3 + cf.aY[1][1] * fy; }
-                    const R dnt = ts[21 + p] - ynt;
-                    v[0] = a1 * dns;
+                    v[0] = a1 * dns[p];
                     v[1] = LROW == 0 ? ri + cf.rV * gy : LROW == 1 ? gy : cf.aL[0][1] * ri + cf.aY[0][1] * gy;
                     v[2] = gy;
                     v[3] = a2 * dnt;
                     if (SYM) {
                         v[4] = a1 * dnt;
-                        v[5] = a2 * dns;
+                        v[5] = a2 * dns[p];
                     }
                     // D's curl part integrates aL[1][0] G_L + aY[1][0] G_Y; the G_L part
                     // by its own orbit sums (LROW = 2)

@@ -111,10 +111,7 @@ __device__ __forceinline__ void far_lane(const FarCoef<R> &cf, IP __restrict__ t
     R tx[6], ty[6], tz[6];
 #pragma unroll
     for (int p = 0; p < 6; ++p) { tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2]; }
-    const R ntx = ts[18], nty = ts[19], ntz = ts[20];
-    R xnt[6];
-#pragma unroll
-    for (int p = 0; p < 6; ++p) xnt[p] = ts[21 + p];
+    const R ntx = ts[18], nty = ts[19], ntz = ts[20], ot = ts[21];
     const int v0 = tri[3 * t], v1 = tri[3 * t + 1], v2 = tri[3 * t + 2];
     R a1[6], a2[6];
 #pragma unroll
@@ -126,7 +123,7 @@ __device__ __forceinline__ void far_lane(const FarCoef<R> &cf, IP __restrict__ t
         const bool adj = (j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
                          (j2 == v0) | (j2 == v1) | (j2 == v2);
         if (adj) continue;
-        far_source<R, FORM>(cf, stat + (size_t)s * kStat, dyn + (size_t)s * kDyn, tx, ty, tz, xnt, ntx, nty, ntz,
+        far_source<R, FORM>(cf, stat + (size_t)s * kStat, dyn + (size_t)s * kDyn, tx, ty, tz, ot, ntx, nty, ntz,
                             a1, a2, W0, W1, W2);
     }
 #pragma unroll

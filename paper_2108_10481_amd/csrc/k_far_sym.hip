@@ -17,10 +17,16 @@
 // in LDS (one array per field, so the lanes' rotated reads hit distinct
 // banks).
 //
-// Coordinates (points and the y . n values) are used scaled by s = kappa
+// Coordinates (points and the plane offsets) are used scaled by s = kappa
 // log2(e), with the coefficients of far_coef_sym: then exp(-kappa r) =
 // exp2(-r') with r' = r2' / sqrt(r2') and no multiply for the argument.  The
 // split is used for kappa > 0 only.
+//
+// The quadrature points of a flat triangle lie in its plane, so the normal
+// components of d = x_p - y_q factor: d . n_s = x_p . n_s - o_s depends on the
+// target point only and d . n_t = o_t - y_q . n_t on the source point only
+// (o = the triangle's plane offset, y . n for any of its points).  Both are
+// formed once per triangle pair, not per point pair.
 //
 // Output: per triangle, one 16-value partial (6 + 6 point sums, 3 curl sums)
 // per target-side item (slot b, the source range) and one per source-side
@@ -34,10 +40,10 @@
 namespace pbm {
 
 constexpr int kSymWaves = 2;   // independent wavefronts (items) per block
-constexpr int kSymF = 42;      // staged values per source
+constexpr int kSymF = 37;      // staged values per source
 
 // staged source record, one LDS array per field:
-//   0..17 points, 18..20 normal, 21..26 y_q . n_s, 27..32 b1, 33..38 b2, 39..41 C
+//   0..17 points, 18..20 normal, 21 plane offset o_s, 22..27 b1, 28..33 b2, 34..36 C
 struct SymLds {
     float f[kSymF][64];
     int id[3][64];
@@ -47,24 +53,27 @@ struct SymLds {
 // (LDS column j); adds t's sums to a1, a2, W and the source's sums to acc
 template <int FORM>
 __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds &L, int j, const float (&tx)[6],
-                                         const float (&ty)[6], const float (&tz)[6], const float (&xnt)[6],
-                                         float ntx, float nty, float ntz, const float (&cs)[9][6],
-                                         const float (&Ct)[3], float (&a1)[6], float (&a2)[6], float (&W)[3],
-                                         float (&acc)[15])
+                                         const float (&ty)[6], const float (&tz)[6], float ot, float ntx,
+                                         float nty, float ntz, const float (&cs)[9][6], const float (&Ct)[3],
+                                         float (&a1)[6], float (&a2)[6], float (&W)[3], float (&acc)[15])
 {
-    const float nsx = L.f[18][j], nsy = L.f[19][j], nsz = L.f[20][j];
-    float xns[6], ynt[6];
+    const float nsx = L.f[18][j], nsy = L.f[19][j], nsz = L.f[20][j], os = L.f[21][j];
+    // dns[p] = (x_p - y) . n_s, dnt[q] = (x - y_q) . n_t
+    float dns[6], dnt[6];
 #pragma unroll
-    for (int p = 0; p < 6; ++p) xns[p] = tx[p] * nsx + ty[p] * nsy + tz[p] * nsz;
+    for (int p = 0; p < 6; ++p) dns[p] = fmaf(tx[p], nsx, fmaf(ty[p], nsy, fmaf(tz[p], nsz, -os)));
 #pragma unroll
-    for (int q = 0; q < 6; ++q) ynt[q] = L.f[3 * q][j] * ntx + L.f[3 * q + 1][j] * nty + L.f[3 * q + 2][j] * ntz;
+    for (int q = 0; q < 6; ++q)
+        dnt[q] = fmaf(-L.f[3 * q][j], ntx, fmaf(-L.f[3 * q + 1][j], nty, fmaf(-L.f[3 * q + 2][j], ntz, ot)));
     float gL = 0.0f, gY = 0.0f, nn = 0.0f;
+    float P[6];   // FORM 1: target p's row-1 double-layer sum before its factor dns[p]
+#pragma unroll
+    for (int p = 0; p < 6; ++p) P[p] = 0.0f;
     if (FORM >= 1) nn = cf.cDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const float yx = L.f[3 * q][j], yy = L.f[3 * q + 1][j], yz = L.f[3 * q + 2][j];
-        const float yns = L.f[21 + q][j];
-        const float b1 = L.f[27 + q][j], b2 = L.f[33 + q][j];
+        const float b1 = L.f[22 + q][j], b2 = L.f[28 + q][j];
         if (FORM == 0) {
             // target side: Laplace row kL K_L + vL V_L, Yukawa row kY K_Y + vY V_Y;
             // source side (K at the target's normal: -F d.n_t): cs = -kL b1_t, vL b2_t,
@@ -76,7 +85,7 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float ri = rsqrt_r(r2);
                 const float ri2 = ri * ri;
-                const float g = (xns[p] - yns) * ri2, h = (xnt[p] - ynt[q]) * ri2;
+                const float g = dns[p] * ri2, h = dnt[q] * ri2;
                 a1[p] = fmaf(ri, fmaf(c1, g, c2), a1[p]);
                 acc[q] = fmaf(ri, fmaf(cs[0][p], h, cs[1][p]), acc[q]);
                 const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
@@ -90,6 +99,7 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
             // kernel e (1 + kappa r) / r^3 d.n is ek g with ek = e (1/r + kappa).
             const float c1L = cf.cKL * b1, c1Y = cf.cKY * b1, c2L = cf.cVL * b2, c2Y = cf.cVY * b2;
             const float c3L = cf.cTL * b2, c3Y = cf.cTY * b2, kb1 = nn * b1;
+            float S = 0.0f;   // FORM 1: source q's row-1 double-layer sum before its factor dnt[q]
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const float dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
@@ -99,32 +109,39 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
                 const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
                 const float gy = e * ri;
                 const float ek = e * (ri + cf.kappa);
-                const float g = (xns[p] - yns) * ri2, h = (xnt[p] - ynt[q]) * ri2;
                 if (FORM == 3) {
+                    const float g = dns[p] * ri2, h = dnt[q] * ri2;
                     a1[p] = fmaf(g, ek * c1Y, fmaf(gy, c2Y, a1[p]));
                     a2[p] = fmaf(h, ek * c3Y, fmaf(gy, kb1, a2[p]));
                     acc[q] = fmaf(h, ek * cs[1][p], fmaf(gy, cs[4][p], acc[q]));
                     acc[6 + q] = fmaf(g, ek * cs[6][p], fmaf(gy, nn * cs[8][p], acc[6 + q]));
                 } else {
-                    const float u = fmaf(ek, c1Y, ri * c1L);
-                    a1[p] = fmaf(g, u, fmaf(ri, c2L, fmaf(gy, c2Y, a1[p])));
-                    const float v = fmaf(ek, c3Y, ri * c3L);
-                    a2[p] = fmaf(h, v, fmaf(gy, kb1, a2[p]));
-                    const float us = fmaf(ek, cs[1][p], ri * cs[0][p]);
-                    acc[q] = fmaf(h, us, fmaf(ri, cs[3][p], fmaf(gy, cs[4][p], acc[q])));
-                    const float vs = fmaf(ek, cs[6][p], ri * cs[5][p]);
-                    acc[6 + q] = fmaf(g, vs, fmaf(gy, nn * cs[8][p], acc[6 + q]));
+                    // F_L d.n = R3 (d.n), F_Y d.n = E (d.n); the factors dns[p] of target
+                    // p's row 1 and dnt[q] of source q's row 1 are applied once per
+                    // triangle pair (P, S)
+                    const float E = ek * ri2, R3 = ri * ri2;
+                    P[p] = fmaf(c1Y, E, fmaf(c1L, R3, P[p]));
+                    a1[p] = fmaf(ri, c2L, fmaf(gy, c2Y, a1[p]));
+                    a2[p] = fmaf(dnt[q], fmaf(c3Y, E, c3L * R3), fmaf(gy, kb1, a2[p]));
+                    S = fmaf(cs[1][p], E, fmaf(cs[0][p], R3, S));
+                    acc[q] = fmaf(ri, cs[3][p], fmaf(gy, cs[4][p], acc[q]));
+                    acc[6 + q] = fmaf(dns[p], fmaf(cs[6][p], E, cs[5][p] * R3), fmaf(gy, nn * cs[8][p], acc[6 + q]));
                     gL = fmaf(float(rule_w(p) * rule_w(q)), ri, gL);
                 }
                 gY = fmaf(float(rule_w(p) * rule_w(q)), gy, gY);
             }
+            if (FORM == 1) acc[q] = fmaf(dnt[q], S, acc[q]);
         }
+    }
+    if (FORM == 1) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) a1[p] = fmaf(dns[p], P[p], a1[p]);
     }
     if (FORM >= 1) {
         const float gc = FORM == 3 ? cf.cDY * gY : cf.cDL * gL + cf.cDY * gY;
-        W[0] = fmaf(gc, L.f[39][j], W[0]);
-        W[1] = fmaf(gc, L.f[40][j], W[1]);
-        W[2] = fmaf(gc, L.f[41][j], W[2]);
+        W[0] = fmaf(gc, L.f[34][j], W[0]);
+        W[1] = fmaf(gc, L.f[35][j], W[1]);
+        W[2] = fmaf(gc, L.f[36][j], W[2]);
         acc[12] = fmaf(gc, Ct[0], acc[12]);
         acc[13] = fmaf(gc, Ct[1], acc[13]);
         acc[14] = fmaf(gc, Ct[2], acc[14]);
@@ -150,11 +167,12 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
             if (s < T) {
                 const auto st = stat + (size_t)s * kStat;
                 const auto sd = dyn + (size_t)s * kDyn;
-                // points and y . n scaled by s, the normal as it is
+                // points and the plane offset (its first point's y . n) scaled by s,
+                // the normal as it is
 #pragma unroll
-                for (int c = 0; c < 27; ++c) L.f[c][lane] = (c < 18 || c >= 21) ? st[c] * cf.kexp : st[c];
+                for (int c = 0; c < 22; ++c) L.f[c][lane] = (c < 18 || c == 21) ? st[c] * cf.kexp : st[c];
 #pragma unroll
-                for (int c = 0; c < 15; ++c) L.f[27 + c][lane] = sd[c];
+                for (int c = 0; c < 15; ++c) L.f[22 + c][lane] = sd[c];
                 L.id[0][lane] = tri[3 * s];
                 L.id[1][lane] = tri[3 * s + 1];
                 L.id[2][lane] = tri[3 * s + 2];
@@ -176,12 +194,12 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
             const int tc = tv ? t : T - 1;
             const auto ts = stat + (size_t)tc * kStat;
             const auto td = dyn + (size_t)tc * kDyn;
-            float tx[6], ty[6], tz[6], xnt[6];
+            float tx[6], ty[6], tz[6];
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 tx[p] = ts[3 * p] * cf.kexp; ty[p] = ts[3 * p + 1] * cf.kexp; tz[p] = ts[3 * p + 2] * cf.kexp;
-                xnt[p] = ts[21 + p] * cf.kexp;
             }
+            const float ot = ts[21] * cf.kexp;   // the target's plane offset
             const float ntx = ts[18], nty = ts[19], ntz = ts[20];
             const int v0 = tri[3 * tc], v1 = tri[3 * tc + 1], v2 = tri[3 * tc + 2];
             float cs[9][6], Ct[3] = {0.0f, 0.0f, 0.0f};
@@ -216,7 +234,7 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
                 act = act && j0 >= 0 &&
                       !((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
                         (j2 == v0) | (j2 == v1) | (j2 == v2));
-                if (act) sym_pair<FORM>(cf, L, j, tx, ty, tz, xnt, ntx, nty, ntz, cs, Ct, a1, a2, W, acc);
+                if (act) sym_pair<FORM>(cf, L, j, tx, ty, tz, ot, ntx, nty, ntz, cs, Ct, a1, a2, W, acc);
                 // the source sums move one lane down: lane l next meets source (l + k + 1) mod 64
 #pragma unroll
                 for (int v = 0; v < NA; ++v) acc[v] = __shfl(acc[v], (lane + 1) & 63);

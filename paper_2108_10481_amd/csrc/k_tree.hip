@@ -563,13 +563,11 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
     const int t = bt * kTreeBatch + (int)(threadIdx.x % kTreeBatch);
     const int tc = t < T ? t : T - 1;   // lanes past the end compute, never store
     const R *ts = stat + (size_t)tc * kStat;
-    R tx[6], ty[6], tz[6], xnt[6];
+    R tx[6], ty[6], tz[6];
 #pragma unroll
-    for (int p = 0; p < 6; ++p) {
-        tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2];
-        xnt[p] = ts[21 + p];
-    }
+    for (int p = 0; p < 6; ++p) { tx[p] = ts[3 * p]; ty[p] = ts[3 * p + 1]; tz[p] = ts[3 * p + 2]; }
     const R ntx = ts[18], nty = ts[19], ntz = ts[20];
+    const R ot = ts[21];   // plane offset x . n_t, the same for the six points
     const int v0 = tri[3 * tc], v1 = tri[3 * tc + 1], v2 = tri[3 * tc + 2];
     R a1[6], a2[6], W0 = 0, W1 = 0, W2 = 0;
 #pragma unroll
@@ -600,7 +598,7 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
                     } else {
                         const R ri3 = ri * ri * ri;
                         const R gy = e * ri, fy = e * (cf.kappa * r + R(1)) * ri3;
-                        const R dnt = xnt[p] - snt;
+                        const R dnt = ot - snt;
                         const R gk = FORM == 3 ? cf.cKY * gy : cf.cKL * ri + cf.cKY * gy;
                         const R gv = FORM == 3 ? cf.cVY * gy : cf.cVL * ri + cf.cVY * gy;
                         const R ft = FORM == 3 ? cf.cTY * fy : cf.cTL * ri3 + cf.cTY * fy;
@@ -640,7 +638,7 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
                     const bool adj = (j.x == v0) | (j.x == v1) | (j.x == v2) | (j.y == v0) | (j.y == v1) |
                                      (j.y == v2) | (j.z == v0) | (j.z == v1) | (j.z == v2);
                     if (adj) continue;
-                    far_source<R, FORM>(cf, srec[wv][k], srec[wv][k] + 27, tx, ty, tz, xnt, ntx, nty, ntz, a1, a2, W0,
+                    far_source<R, FORM>(cf, srec[wv][k], srec[wv][k] + 27, tx, ty, tz, ot, ntx, nty, ntz, a1, a2, W0,
                                         W1, W2);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
