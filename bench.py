@@ -63,9 +63,9 @@ ASM_FLOPS_PER_PP = {0: 25.83, 1: 29.25}
 # SQ_INSTS_VALU_TRANS_F32 (profiles/k_far_star81920_trace_and_counters.md,
 # profiles/sphere20480_fp32_assembled_trace_and_traffic.md):
 ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
-FAR_VALU_PER_PAIR = {0: 13.12, 1: 19.04}   # k_far_sym<FORM>, one transcendental per pair
+FAR_VALU_PER_PAIR = {0: 12.12, 1: 17.20}   # k_far_sym<FORM>, one transcendental per pair
 FAR_TRANS_PER_PAIR = 1.0
-ASM_VALU_PER_PP = {0: 23.35, 1: 26.60}     # far-field assembly, one transcendental per pair
+ASM_VALU_PER_PP = {0: 22.50, 1: 25.76}     # far-field assembly, one transcendental per pair
 ASM_TRANS_PER_PP = 1.0
 
 
@@ -129,6 +129,9 @@ def parse():
                     help="requests of the serving trace replayed after the timed steps (0: none)")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the FP64 reference solves of the accuracy gate")
+    ap.add_argument("--far-symmetric", type=int, default=0, choices=[0, 1, -1],
+                    help="FP32 matrix-free far field: 0 automatic (the library default), 1 the symmetric "
+                         "kernel at every size, -1 the per-ordered-pair kernel")
     ap.add_argument("--preconditioner", default="block-diag", choices=["block-diag", "scaled-mass"],
                     help="scaled-mass: the Juffer solves use blockdiag(aM, bM)^-1 (the paper's Case 10), "
                          "the direct ones keep the block-diagonal preconditioner (Case 2)")
@@ -175,7 +178,8 @@ def main():
 
     precs = {f: pbm.PB_SCALED_MASS if (a.preconditioner == "scaled-mass" and f == pbm.PB_JUFFER)
              else pbm.PB_BLOCK_DIAG for f in forms}
-    opts = {f: pbm.pb_default_options(formulation=f, precision=prec, operator_mode=mode, preconditioner=precs[f])
+    opts = {f: pbm.pb_default_options(formulation=f, precision=prec, operator_mode=mode, preconditioner=precs[f],
+                                      far_symmetric=a.far_symmetric)
             for f in forms}
     # cold solve: handle creation (validation, Morton order, near-pair lists and
     # every device stage) plus the first solve, from host arrays
@@ -270,15 +274,19 @@ def main():
         pairs_timed = sum(prof[f][2] for f in forms)
         flops = sum(prof[f][2] * FLOPS_PER_PAIR[f] for f in forms)
         achieved = flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else 0.0
-        tr = measured_traffic(key, kernel="k_far") if dtype == "f32" else None
+        # the counters and traffic on record are those of the symmetric kernel
+        sym = all(info[f]["far_symmetric"] for f in forms)
+        tr = measured_traffic(key, kernel="k_far") if (dtype == "f32" and sym) else None
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS[dtype], 4),
                 "traffic": (round(sum(tr["bytes_per_launch"][str(f)] * prof[f][0] for f in forms)
                                   / max(launches, 1), 1) if tr else None),
-                "kernel": "k_far (matrix-free far field; k_far_finish and the near field excluded)",
+                "kernel": ("k_far_sym (matrix-free far field, every unordered pair once" if sym else
+                           "k_far (matrix-free far field, every ordered pair") +
+                          "; the finish and the near field excluded)",
                 "launches": launches, "avg_launch_ms": round(kern_ms / max(launches, 1), 4),
                 "kernel_pairs_per_s": round(pairs_timed / (kern_ms * 1e-3), 1) if kern_ms > 0 else None}
-        if dtype == "f32" and kern_ms > 0:
+        if dtype == "f32" and sym and kern_ms > 0:
             roof["valu_issue"] = valu_issue({f: prof[f][2] for f in forms}, FAR_VALU_PER_PAIR, FAR_TRANS_PER_PAIR,
                                             kern_ms * 1e-3, peaks)
         by_form = {}
@@ -288,7 +296,7 @@ def main():
                 continue
             e = {"launches": n, "avg_launch_ms": round(ms / n, 3), "kernel_pairs_per_s": round(w / (ms * 1e-3), 1),
                  "tflops": round(w * FLOPS_PER_PAIR[f] / (ms * 1e-3) / 1e12, 3)}
-            if dtype == "f32":
+            if dtype == "f32" and sym:
                 e["valu_issue_frac"] = round(w * FAR_VALU_PER_PAIR[f] / (ms * 1e-3) / ISSUE_PEAK, 4)
             by_form[str(f)] = e
         roof["by_formulation"] = by_form
@@ -309,6 +317,7 @@ def main():
         "config": {"workload": workload, "precision": a.precision,
                    "operator_mode": "assembled" if assembled else "matrix-free",
                    "source_chunks": info[forms[0]]["source_chunks"],
+                   "far_symmetric": a.far_symmetric,
                    "preconditioner": {"direct": "block-diagonal",
                                       "juffer": "scaled mass" if a.preconditioner == "scaled-mass"
                                       else "block-diagonal"}},

@@ -210,6 +210,8 @@ typedef struct {
     int32_t source_chunks;    /* far-field source split in use */
     int32_t assembled;        /* 1 if the far field is held as a dense matrix */
     size_t device_bytes;
+    int32_t far_symmetric;    /* 1 if matrix-free products evaluate every unordered
+                                 triangle pair once (FP32, see pb_options.far_symmetric) */
 } pb_mesh_info;
 
 /* Fill *opt with the paper's settings: eps 4/80, kappa 0.125, direct

@@ -110,7 +110,7 @@ class pb_mesh_info(ctypes.Structure):
     _fields_ = [("n_vertices", ctypes.c_int32), ("n_triangles", ctypes.c_int32),
                 ("n_near_pairs", ctypes.c_int64), ("near_nnz", ctypes.c_int64),
                 ("source_chunks", ctypes.c_int32), ("assembled", ctypes.c_int32),
-                ("device_bytes", ctypes.c_size_t)]
+                ("device_bytes", ctypes.c_size_t), ("far_symmetric", ctypes.c_int32)]
 
 
 EXPORTS = ["pb_default_options", "pb_last_error", "pb_device_count", "pb_solve", "pb_mesh_create",

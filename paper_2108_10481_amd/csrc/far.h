@@ -78,6 +78,9 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
 #pragma unroll
     for (int p = 0; p < 6; ++p) dns[p] = fma(tx[p], nsx, fma(ty[p], nsy, fma(tz[p], nsz, -os)));
     R gL = 0, gY = 0, k2nn = 0;
+    R P[6];   // FORM 1, 3: row-1 double-layer sums of the target points before their factor dns[p]
+#pragma unroll
+    for (int p = 0; p < 6; ++p) P[p] = 0;
     if (FORM >= 1) k2nn = cf.cDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -108,20 +111,27 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
                 const R e = expneg(cf.kexp, r2 * ri);
                 const R gy = e * ri;
                 const R ek = e * (ri + cf.kappa);   // F_Y d.n = ek g
-                const R g = dns[p] * ri2, h = dnt * ri2;
+                // F_L d.n = R3 (d.n), F_Y d.n = E (d.n); row 1's factor dns[p] is applied
+                // to its sum P[p] once per source triangle
+                const R E = ek * ri2;
                 if (FORM == 3) {
-                    a1[p] = fma(g, ek * c1Y, fma(gy, c2Y, a1[p]));
-                    a2[p] = fma(h, ek * c3Y, fma(gy, kb1, a2[p]));
+                    P[p] = fma(c1Y, E, P[p]);
+                    a1[p] = fma(gy, c2Y, a1[p]);
+                    a2[p] = fma(dnt * c3Y, E, fma(gy, kb1, a2[p]));
                 } else {
-                    const R u = fma(ek, c1Y, ri * c1L);
-                    a1[p] = fma(g, u, fma(ri, c2L, fma(gy, c2Y, a1[p])));
-                    const R v = fma(ek, c3Y, ri * c3L);
-                    a2[p] = fma(h, v, fma(gy, kb1, a2[p]));
+                    const R R3 = ri * ri2;
+                    P[p] = fma(c1Y, E, fma(c1L, R3, P[p]));
+                    a1[p] = fma(ri, c2L, fma(gy, c2Y, a1[p]));
+                    a2[p] = fma(dnt, fma(c3Y, E, c3L * R3), fma(gy, kb1, a2[p]));
                     gL = fma(R(rule_w(p) * rule_w(q)), ri, gL);
                 }
                 gY = fma(R(rule_w(p) * rule_w(q)), gy, gY);
             }
         }
+    }
+    if (FORM >= 1) {
+#pragma unroll
+        for (int p = 0; p < 6; ++p) a1[p] = fma(dns[p], P[p], a1[p]);
     }
     if (FORM >= 1) {
         const R gc = FORM == 3 ? cf.cDY * gY : cf.cDL * gL + cf.cDY * gY;

@@ -66,7 +66,7 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
     for (int q = 0; q < 6; ++q)
         dnt[q] = fmaf(-L.f[3 * q][j], ntx, fmaf(-L.f[3 * q + 1][j], nty, fmaf(-L.f[3 * q + 2][j], ntz, ot)));
     float gL = 0.0f, gY = 0.0f, nn = 0.0f;
-    float P[6];   // FORM 1: target p's row-1 double-layer sum before its factor dns[p]
+    float P[6];   // FORM 1, 3: target p's row-1 double-layer sum before its factor dns[p]
 #pragma unroll
     for (int p = 0; p < 6; ++p) P[p] = 0.0f;
     if (FORM >= 1) nn = cf.cDY * cf.k2 * (ntx * nsx + nty * nsy + ntz * nsz);
@@ -99,7 +99,7 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
             // kernel e (1 + kappa r) / r^3 d.n is ek g with ek = e (1/r + kappa).
             const float c1L = cf.cKL * b1, c1Y = cf.cKY * b1, c2L = cf.cVL * b2, c2Y = cf.cVY * b2;
             const float c3L = cf.cTL * b2, c3Y = cf.cTY * b2, kb1 = nn * b1;
-            float S = 0.0f;   // FORM 1: source q's row-1 double-layer sum before its factor dnt[q]
+            float S = 0.0f;   // source q's row-1 double-layer sum before its factor dnt[q]
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const float dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
@@ -109,17 +109,19 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
                 const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
                 const float gy = e * ri;
                 const float ek = e * (ri + cf.kappa);
+                // F_L d.n = R3 (d.n), F_Y d.n = E (d.n); the factors dns[p] of target p's
+                // row 1 and dnt[q] of source q's row 1 are applied once per triangle
+                // pair (P, S)
+                const float E = ek * ri2;
                 if (FORM == 3) {
-                    const float g = dns[p] * ri2, h = dnt[q] * ri2;
-                    a1[p] = fmaf(g, ek * c1Y, fmaf(gy, c2Y, a1[p]));
-                    a2[p] = fmaf(h, ek * c3Y, fmaf(gy, kb1, a2[p]));
-                    acc[q] = fmaf(h, ek * cs[1][p], fmaf(gy, cs[4][p], acc[q]));
-                    acc[6 + q] = fmaf(g, ek * cs[6][p], fmaf(gy, nn * cs[8][p], acc[6 + q]));
+                    P[p] = fmaf(c1Y, E, P[p]);
+                    a1[p] = fmaf(gy, c2Y, a1[p]);
+                    a2[p] = fmaf(dnt[q] * c3Y, E, fmaf(gy, kb1, a2[p]));
+                    S = fmaf(cs[1][p], E, S);
+                    acc[q] = fmaf(gy, cs[4][p], acc[q]);
+                    acc[6 + q] = fmaf(dns[p] * cs[6][p], E, fmaf(gy, nn * cs[8][p], acc[6 + q]));
                 } else {
-                    // F_L d.n = R3 (d.n), F_Y d.n = E (d.n); the factors dns[p] of target
-                    // p's row 1 and dnt[q] of source q's row 1 are applied once per
-                    // triangle pair (P, S)
-                    const float E = ek * ri2, R3 = ri * ri2;
+                    const float R3 = ri * ri2;
                     P[p] = fmaf(c1Y, E, fmaf(c1L, R3, P[p]));
                     a1[p] = fmaf(ri, c2L, fmaf(gy, c2Y, a1[p]));
                     a2[p] = fmaf(dnt[q], fmaf(c3Y, E, c3L * R3), fmaf(gy, kb1, a2[p]));
@@ -130,10 +132,10 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
                 }
                 gY = fmaf(float(rule_w(p) * rule_w(q)), gy, gY);
             }
-            if (FORM == 1) acc[q] = fmaf(dnt[q], S, acc[q]);
+            acc[q] = fmaf(dnt[q], S, acc[q]);
         }
     }
-    if (FORM == 1) {
+    if (FORM >= 1) {
 #pragma unroll
         for (int p = 0; p < 6; ++p) a1[p] = fmaf(dns[p], P[p], a1[p]);
     }

@@ -535,11 +535,11 @@ __global__ __launch_bounds__(256) void k_tree_proxies(int deg, int np, const int
 // are wavefront-uniform, so proxy records and source triangles come through
 // scalar loads.  Sums in R, as the direct kernel's chunks (a piece holds a
 // few thousand sources at most); pieces are added in FP64 by k_far_finish.
-// FP32: at most 85 VGPRs (6 wavefronts per SIMD) without spills, which hides
-// the per-source scalar loads of the direct sums (99 VGPRs, 4 wavefronts,
-// otherwise).
+// FP32: 5 wavefronts per SIMD (at most 96 VGPRs, no spills), which hides the
+// per-source scalar loads of the direct sums; the Yukawa-only form (FORM 3)
+// needs 97 VGPRs and runs 4.
 template <typename R, int FORM>
-__global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1))) void k_tree_eval(int T, int nsplit, int nwork, int np, FarCoef<R> cf,
+__global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? (FORM == 3 ? 4 : 5) : 1))) void k_tree_eval(int T, int nsplit, int nwork, int np, FarCoef<R> cf,
                                                           const int32_t *__restrict__ tri,
                                                           const R *__restrict__ stat, const R *__restrict__ dyn,
                                                           const int32_t *__restrict__ node_range,

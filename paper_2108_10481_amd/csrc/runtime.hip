@@ -1604,6 +1604,7 @@ pb_status pb_mesh_get_info(const pb_mesh_handle *h, pb_mesh_info *info)
     info->source_chunks = d.S;
     info->assembled = d.dense ? 1 : 0;
     info->device_bytes = d.bytes;
+    info->far_symmetric = (d.sym_nitems > 0 && !d.dense && !d.tree) ? 1 : 0;
     return PB_OK;
     PB_CATCH
 }
