@@ -265,11 +265,6 @@ def main():
         # products stream the matrix: each solve's products counted from iterations
         for f in done:
             pairs_timed += sum((r["iterations"] + 1) * float(P) * P for r in res[f])
-        gbytes = sum(prof[f][2] for f in forms)
-        dense_product = ({"bound": "hbm", "achieved": round(gbytes / (kern_ms * 1e-3) / 1e9, 1), "peak": 8000.0,
-                          "unit": "GB/s", "frac": round(gbytes / (kern_ms * 1e-3) / 8e12, 4), "kernel": "k_gemv",
-                          "launches": launches, "avg_launch_ms": round(kern_ms / max(launches, 1), 4)}
-                         if kern_ms > 0 else None)
     else:
         pairs_timed = sum(prof[f][2] for f in forms)
         flops = sum(prof[f][2] * FLOPS_PER_PAIR[f] for f in forms)
@@ -300,7 +295,6 @@ def main():
                 e["valu_issue_frac"] = round(w * FAR_VALU_PER_PAIR[f] / (ms * 1e-3) / ISSUE_PEAK, 4)
             by_form[str(f)] = e
         roof["by_formulation"] = by_form
-        dense_product = None
 
     solves = sum(len(res[f]) for f in forms)
     all_lat = [1e3 * x for f in forms for x in lat[f]]
@@ -336,7 +330,6 @@ def main():
         "fp64_reference_solve_s": ({str(f): round(ref[f]["t_setup"] + ref[f]["t_rhs"] + ref[f]["t_prec"]
                                                   + ref[f]["t_gmres"] + ref[f]["t_dG"], 4) for f in forms}
                                    if ref else None),
-        "dense_product": dense_product,
         "roofline": roof,
     }
     if rel_err is not None and rel_err > 1e-4:
