@@ -63,10 +63,11 @@ struct FarReq {
 // SP: pointer type of the source records (a generic pointer, or one into the
 // constant address space where the caller needs scalar loads)
 // With d = x_p - y_q, r = |d|, e = exp(-kappa r), G_L = 1/r, G_Y = e/r,
-// F_L = 1/r^3, F_Y = e (1 + kappa r)/r^3 and g = (d.n_s)/r^2, h = (d.n_t)/r^2:
-//   F_L d.n_s = g/r,  F_Y d.n_s = e (g/r + kappa g) = ek g with ek = e (1/r + kappa),
-// so each row is a few fused multiply-adds on 1/r, e/r and ek with the source
-// weights folded into per-point constants.
+// F_L = 1/r^3, F_Y = e (1 + kappa r)/r^3 = e (r^-3 + kappa r^-2): the direct
+// form takes F d.n_s as g/r and e (g/r + kappa g) with g = (d.n_s)/r^2; the
+// second-kind forms sum R3 = r^-3 and E = e (R3 + kappa r^-2) and apply the
+// point's d.n once, so each row is a few fused multiply-adds on 1/r, e/r, R3
+// and E with the source weights folded into per-point constants.
 template <typename R, int FORM, typename SP = const R *>
 __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__ st,
                                            SP __restrict__ sd, const R (&tx)[6], const R (&ty)[6],
@@ -110,16 +111,16 @@ __device__ __forceinline__ void far_source(const FarCoef<R> &cf, SP __restrict__
                 const R ri2 = ri * ri;
                 const R e = expneg(cf.kexp, r2 * ri);
                 const R gy = e * ri;
-                const R ek = e * (ri + cf.kappa);   // F_Y d.n = ek g
-                // F_L d.n = R3 (d.n), F_Y d.n = E (d.n); row 1's factor dns[p] is applied
-                // to its sum P[p] once per source triangle
-                const R E = ek * ri2;
+                // F_L d.n = R3 (d.n), F_Y d.n = E (d.n) with R3 = r^-3 and E = e (1/r +
+                // kappa) r^-2 = e (R3 + kappa r^-2); row 1's factor dns[p] is applied to its
+                // sum P[p] once per source triangle
+                const R R3 = ri * ri2;
+                const R E = e * fma(cf.kappa, ri2, R3);
                 if (FORM == 3) {
                     P[p] = fma(c1Y, E, P[p]);
                     a1[p] = fma(gy, c2Y, a1[p]);
                     a2[p] = fma(dnt * c3Y, E, fma(gy, kb1, a2[p]));
                 } else {
-                    const R R3 = ri * ri2;
                     P[p] = fma(c1Y, E, fma(c1L, R3, P[p]));
                     a1[p] = fma(ri, c2L, fma(gy, c2Y, a1[p]));
                     a2[p] = fma(dnt, fma(c3Y, E, c3L * R3), fma(gy, kb1, a2[p]));

@@ -40,19 +40,21 @@
 namespace pbm {
 
 constexpr int kSymWaves = 2;   // independent wavefronts (items) per block
-constexpr int kSymF = 37;      // staged values per source
-
-// staged source record, one LDS array per field:
-//   0..17 points, 18..20 normal, 21 plane offset o_s, 22..27 b1, 28..33 b2, 34..36 C
-struct SymLds {
-    float f[kSymF][64];
+// staged source record, one LDS array per field: 0..17 points, 18..20 normal,
+// 21 plane offset o_s, then per source point
+//   FORM 0: 22..27 kL b1, 28..33 vL b2, 34..39 kY b1, 40..45 vY b2 (the
+//           source-point constants of the direct form's target-side sums);
+//   else:   22..27 b1, 28..33 b2, 34..36 C.
+template <int FORM> struct SymLds {
+    static constexpr int NF = FORM == 0 ? 46 : 37;
+    float f[NF][64];
     int id[3][64];
 };
 
 // one step: the 36 point pairs of target t (lane registers) and source j
 // (LDS column j); adds t's sums to a1, a2, W and the source's sums to acc
 template <int FORM>
-__device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds &L, int j, const float (&tx)[6],
+__device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds<FORM> &L, int j, const float (&tx)[6],
                                          const float (&ty)[6], const float (&tz)[6], float ot, float ntx,
                                          float nty, float ntz, const float (&cs)[9][6], const float (&Ct)[3],
                                          float (&a1)[6], float (&a2)[6], float (&W)[3], float (&acc)[15])
@@ -73,12 +75,13 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const float yx = L.f[3 * q][j], yy = L.f[3 * q + 1][j], yz = L.f[3 * q + 2][j];
-        const float b1 = L.f[22 + q][j], b2 = L.f[28 + q][j];
         if (FORM == 0) {
-            // target side: Laplace row kL K_L + vL V_L, Yukawa row kY K_Y + vY V_Y;
-            // source side (K at the target's normal: -F d.n_t): cs = -kL b1_t, vL b2_t,
-            // -kY b1_t, vY b2_t, -kY kappa b1_t per target point
-            const float c1 = cf.kL * b1, c2 = cf.vL * b2, c3 = cf.kY * b1, c4 = cf.vY * b2, c3k = cf.kYk * b1;
+            // target side: Laplace row kL K_L + vL V_L, Yukawa row kY K_Y + vY V_Y, the
+            // source point's constants c1..c4 staged (kYk = kappa kY); source side (K at
+            // the target's normal: -F d.n_t): cs = -kL b1_t, vL b2_t, -kY b1_t, vY b2_t,
+            // -kY kappa b1_t per target point
+            const float c1 = L.f[22 + q][j], c2 = L.f[28 + q][j], c3 = L.f[34 + q][j], c4 = L.f[40 + q][j];
+            const float c3k = cf.kappa * c3;
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const float dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
@@ -96,7 +99,8 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
             // target side as far_source; source side: row 1 with -h (K at n_t), row 2
             // with -g (T at n_s): cs = -cKL b1_t, -cKY b1_t, (unused), cVL b2_t,
             // cVY b2_t, -cTL b2_t, -cTY b2_t, (unused), b1_t.  The Yukawa double-layer
-            // kernel e (1 + kappa r) / r^3 d.n is ek g with ek = e (1/r + kappa).
+            // kernel e (1 + kappa r) / r^3 d.n is E d.n with E = e (r^-3 + kappa r^-2).
+            const float b1 = L.f[22 + q][j], b2 = L.f[28 + q][j];
             const float c1L = cf.cKL * b1, c1Y = cf.cKY * b1, c2L = cf.cVL * b2, c2Y = cf.cVY * b2;
             const float c3L = cf.cTL * b2, c3Y = cf.cTY * b2, kb1 = nn * b1;
             float S = 0.0f;   // source q's row-1 double-layer sum before its factor dnt[q]
@@ -108,11 +112,11 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
                 const float ri2 = ri * ri;
                 const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
                 const float gy = e * ri;
-                const float ek = e * (ri + cf.kappa);
-                // F_L d.n = R3 (d.n), F_Y d.n = E (d.n); the factors dns[p] of target p's
-                // row 1 and dnt[q] of source q's row 1 are applied once per triangle
-                // pair (P, S)
-                const float E = ek * ri2;
+                // F_L d.n = R3 (d.n), F_Y d.n = E (d.n) with R3 = r^-3 and E = e (1/r + kappa)
+                // r^-2 = e (R3 + kappa r^-2); the factors dns[p] of target p's row 1 and
+                // dnt[q] of source q's row 1 are applied once per triangle pair (P, S)
+                const float R3 = ri * ri2;
+                const float E = e * fmaf(cf.kappa, ri2, R3);
                 if (FORM == 3) {
                     P[p] = fmaf(c1Y, E, P[p]);
                     a1[p] = fmaf(gy, c2Y, a1[p]);
@@ -121,7 +125,6 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
                     acc[q] = fmaf(gy, cs[4][p], acc[q]);
                     acc[6 + q] = fmaf(dns[p] * cs[6][p], E, fmaf(gy, nn * cs[8][p], acc[6 + q]));
                 } else {
-                    const float R3 = ri * ri2;
                     P[p] = fmaf(c1Y, E, fmaf(c1L, R3, P[p]));
                     a1[p] = fmaf(ri, c2L, fmaf(gy, c2Y, a1[p]));
                     a2[p] = fmaf(dnt[q], fmaf(c3Y, E, c3L * R3), fmaf(gy, kb1, a2[p]));
@@ -154,7 +157,7 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds 
 template <int FORM, typename IP, typename RP>
 __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict__ tri, RP __restrict__ stat,
                                          RP __restrict__ dyn, int T, int rt, int nr, int a, int b,
-                                         float *__restrict__ part, SymLds &L, int lane)
+                                         float *__restrict__ part, SymLds<FORM> &L, int lane)
 {
     const int ntile = (T + 63) / 64;
     const int I0 = a * rt, I1 = min(ntile, I0 + rt);
@@ -173,14 +176,24 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
                 // the normal as it is
 #pragma unroll
                 for (int c = 0; c < 22; ++c) L.f[c][lane] = (c < 18 || c == 21) ? st[c] * cf.kexp : st[c];
+                if (FORM == 0) {
 #pragma unroll
-                for (int c = 0; c < 15; ++c) L.f[22 + c][lane] = sd[c];
+                    for (int q = 0; q < 6; ++q) {
+                        L.f[22 + q][lane] = cf.kL * sd[q];
+                        L.f[28 + q][lane] = cf.vL * sd[6 + q];
+                        L.f[34 + q][lane] = cf.kY * sd[q];
+                        L.f[40 + q][lane] = cf.vY * sd[6 + q];
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 15; ++c) L.f[22 + c][lane] = sd[c];
+                }
                 L.id[0][lane] = tri[3 * s];
                 L.id[1][lane] = tri[3 * s + 1];
                 L.id[2][lane] = tri[3 * s + 2];
             } else {
 #pragma unroll
-                for (int c = 0; c < kSymF; ++c) L.f[c][lane] = 0.0f;
+                for (int c = 0; c < SymLds<FORM>::NF; ++c) L.f[c][lane] = 0.0f;
                 L.id[0][lane] = L.id[1][lane] = L.id[2][lane] = -1;
             }
         }
@@ -272,7 +285,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void k_far_sym(int T, int rt, int n
                                                               int *__restrict__ next, float *__restrict__ part,
                                                               DevCtl ctl)
 {
-    __shared__ SymLds lds[kSymWaves];
+    __shared__ SymLds<FORM> lds[kSymWaves];
     if (ctl_skip(ctl)) return;   // uniform: every wavefront leaves
     const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
     for (;;) {
@@ -292,7 +305,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void k_far_sym_batch(const FarReq<f
                                                                     const int4 *__restrict__ items, int nitems,
                                                                     int *__restrict__ next)
 {
-    __shared__ SymLds lds[kSymWaves];
+    __shared__ SymLds<FORM> lds[kSymWaves];
     const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
     for (;;) {
         int i = 0;
