@@ -63,7 +63,7 @@ ASM_FLOPS_PER_PP = {0: 25.83, 1: 29.25}
 # SQ_INSTS_VALU_TRANS_F32 (profiles/k_far_star81920_trace_and_counters.md,
 # profiles/sphere20480_fp32_assembled_trace_and_traffic.md):
 ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
-FAR_VALU_PER_PAIR = {0: 12.12, 1: 17.20}   # k_far_sym<FORM>, one transcendental per pair
+FAR_VALU_PER_PAIR = {0: 11.79, 1: 16.70}   # k_far_sym<FORM>, one transcendental per pair
 FAR_TRANS_PER_PAIR = 1.0
 ASM_VALU_PER_PP = {0: 22.50, 1: 25.76}     # far-field assembly, one transcendental per pair
 ASM_TRANS_PER_PP = 1.0
