@@ -580,10 +580,21 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
                 const R *cur = P + (size_t)k * kProxRec;
                 const R sx = cur[0], sy = cur[1], sz = cur[2];
                 const R qK = cur[3], qV = cur[4];
-                R gw = 0, ntqN = 0, snt = 0;
-                if (FORM >= 1) {
+                // per proxy: row 1 = ri (cKL qK + cVL qV) + e ri (cKY qK + cVY qV); row 2 =
+                // (d.n_t) qV (cTL R3 + cTY E) + ntqN e ri with R3 = r^-3, E = e (R3 +
+                // kappa r^-2) and d.n_t = ot - z.n_t the same for the six target points;
+                // the curl part's G sums (GL, GY) take their coefficients once
+                R ntqN = 0, AL = 0, AY = 0, CL = 0, CY = 0, GL = 0, GY = 0;
+                if (FORM == 0) {
+                    AL = cf.kL * qK + cf.vL * qV;
+                    AY = cf.kY * qK + cf.vY * qV;
+                } else {
                     ntqN = cf.cDY * cf.k2 * (ntx * cur[8] + nty * cur[9] + ntz * cur[10]);
-                    snt = sx * ntx + sy * nty + sz * ntz;
+                    const R dq = (ot - (sx * ntx + sy * nty + sz * ntz)) * qV;
+                    AL = cf.cKL * qK + cf.cVL * qV;
+                    AY = cf.cKY * qK + cf.cVY * qV;
+                    CL = cf.cTL * dq;
+                    CY = cf.cTY * dq;
                 }
 #pragma unroll
                 for (int p = 0; p < 6; ++p) {
@@ -592,22 +603,26 @@ __global__ __launch_bounds__(kTreeBlock) __attribute__((amdgpu_waves_per_eu(size
                     const R ri = rsqrt_r(r2);
                     const R r = r2 * ri;
                     const R e = expneg(cf.kexp, r);
+                    const R gy = e * ri;
                     if (FORM == 0) {
-                        a1[p] += ri * (cf.kL * qK + cf.vL * qV);
-                        a2[p] += e * ri * (cf.kY * qK + cf.vY * qV);
+                        a1[p] += ri * AL;
+                        a2[p] += gy * AY;
                     } else {
-                        const R ri3 = ri * ri * ri;
-                        const R gy = e * ri, fy = e * (cf.kappa * r + R(1)) * ri3;
-                        const R dnt = ot - snt;
-                        const R gk = FORM == 3 ? cf.cKY * gy : cf.cKL * ri + cf.cKY * gy;
-                        const R gv = FORM == 3 ? cf.cVY * gy : cf.cVL * ri + cf.cVY * gy;
-                        const R ft = FORM == 3 ? cf.cTY * fy : cf.cTL * ri3 + cf.cTY * fy;
-                        a1[p] += gk * qK + gv * qV;
-                        a2[p] += ft * dnt * qV + ntqN * gy;
-                        gw += R(rule_w(p)) * (FORM == 3 ? cf.cDY * gy : cf.cDL * ri + cf.cDY * gy);
+                        const R ri2 = ri * ri, R3 = ri2 * ri;
+                        const R E = e * fma(cf.kappa, ri2, R3);
+                        if (FORM == 3) {
+                            a1[p] = fma(gy, AY, a1[p]);
+                            a2[p] = fma(CY, E, fma(ntqN, gy, a2[p]));
+                        } else {
+                            a1[p] = fma(ri, AL, fma(gy, AY, a1[p]));
+                            a2[p] = fma(CL, R3, fma(CY, E, fma(ntqN, gy, a2[p])));
+                            GL = fma(R(rule_w(p)), ri, GL);
+                        }
+                        GY = fma(R(rule_w(p)), gy, GY);
                     }
                 }
                 if (FORM >= 1) {
+                    const R gw = FORM == 3 ? cf.cDY * GY : cf.cDL * GL + cf.cDY * GY;
                     W0 += gw * cur[5];
                     W1 += gw * cur[6];
                     W2 += gw * cur[7];
