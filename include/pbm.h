@@ -242,6 +242,9 @@ pb_status pb_solve(const pb_mesh *mesh, const pb_charges *charges,
  * The options fix formulation, precision and operator mode for the handle. */
 pb_status pb_mesh_create(const pb_mesh *mesh, const pb_options *opt, pb_mesh_handle **out);
 pb_status pb_mesh_destroy(pb_mesh_handle *h);
+/* Fill *info (caller-owned) with the handle's sizes, the far-field layout in
+ * use (source split, assembled or not, the symmetric FP32 kernel or not) and
+ * the device bytes it holds.  PB_E_INVALID_ARG for NULL arguments. */
 pb_status pb_mesh_get_info(const pb_mesh_handle *h, pb_mesh_info *info);
 
 /* Redo every device-side setup stage of the handle from the resident mesh:
