@@ -146,8 +146,8 @@ def _pct(values, q):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
-              "(the design of a sharded path is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; it has no multi-GPU path, so only --gpus 1 "
+              "is measured", file=sys.stderr)
         sys.exit(2)
     import paper_2108_10481_amd as pbm
     if pbm.pb_device_count() < 1:
@@ -811,7 +811,7 @@ def measure_peaks():
            "hbm_read_GBps": bw["hbm_read"] / 1e9, "hbm_copy_GBps": bw["hbm_copy"] / 1e9,
            "datasheet": {"fp32_vector_tflops": 157.3, "fp64_vector_tflops": 78.6, "bf16_mfma_tflops": 2500.0,
                          "hbm_GBps": 8000.0},
-           "note": "packed FP32 (v_pk_fma_f32) is not used by this build; the FMA rate is the unpacked one"}
+           "note": "packed FP32 (v_pk_fma_f32) is not used by the library; the FMA rate is the unpacked one"}
     print(json.dumps(rec), flush=True)
 
 
