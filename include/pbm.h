@@ -174,7 +174,7 @@ typedef struct {
                                  triangle; 1: the one-point (centroid) rule, matrix-free in FP64
                                  or FP32 only, not with the Calderon preconditioners.  The source
                                  projections and Delta G always use the 6-point rule. */
-    int32_t far_symmetric;    /* FP32 matrix-free far field with kappa > 0 (Numerical
+    int32_t far_symmetric;    /* FP32 matrix-free far field, screened or not (Numerical
                                  discretization; the kernels are symmetric in x, y): every
                                  unordered triangle pair evaluated once for both directions or
                                  every ordered pair.  0 (default): once per unordered pair on

@@ -253,12 +253,14 @@ inline int far_coef(const DevMesh &d, FarCoef<R> &cf)
 // normal-derivative factors (d.n)/r^2 = s (d'.n)/r'^2 and exp(-kappa r) =
 // exp2(-r'), so the K- and T-type coefficients take s^2, the V-type ones, the
 // kappa-weighted FORM 0 one and D's s, and kappa becomes kappa / s; kexp
-// carries s.  Returns the kernel FORM.
+// carries s.  For kappa = 0, s = 1 (coordinates and coefficients as they are,
+// kappa 0).  Returns the kernel FORM.
 inline int far_coef_sym(const DevMesh &d, FarCoef<float> &cf)
 {
     FarCoef<double> c;
     const int form = far_coef(d, c);
-    const double s = d.prm.kappa * 1.4426950408889634, s2 = s * s;
+    // unscreened meshes keep their coordinates (the kernel skips the exponential)
+    const double s = d.prm.kappa > 0.0 ? d.prm.kappa * 1.4426950408889634 : 1.0, s2 = s * s;
     cf = FarCoef<float>{};
     cf.kappa = (float)(d.prm.kappa / s);
     cf.kexp = (float)s;

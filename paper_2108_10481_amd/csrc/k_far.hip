@@ -515,7 +515,8 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
     for (int f = 0; f < 4; ++f) fb.nitems[f] = 0;
     std::vector<FarReq<R>> reqs(ds.size());
     std::vector<std::vector<std::pair<int, int4>>> q(4);   // (cost, item) per form
-    std::vector<std::vector<std::pair<int, int4>>> sq(3);  // symmetric items per form 0, 1, 3
+    // symmetric items per form 0, 1, 3 (kappa > 0), then per form with kappa = 0
+    std::vector<std::vector<std::pair<int, int4>>> sq(6);
     for (int r : live) {
         DevMesh &d = *ds[r];
         FarReq<R> &rq = reqs[r];
@@ -538,7 +539,7 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
             std::vector<int2> its;
             int rt = 0, nr = 0;
             sym_plan(T, rt, nr, its);
-            const int sf = form == 0 ? 0 : form == 1 ? 1 : 2;
+            const int sf = (form == 0 ? 0 : form == 1 ? 1 : 2) + (d.prm.kappa > 0.0 ? 0 : 3);
             for (const int2 &e : its) {
                 const int na = std::min((T + 63) / 64, (e.x + 1) * rt) - e.x * rt;
                 const int nb = std::min((T + 63) / 64, (e.y + 1) * rt) - e.y * rt;
@@ -560,13 +561,14 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         for (auto &e : q[f]) items.push_back(e.second);
         fb.nitems[f] = (int)q[f].size();
     }
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < 6; ++f) {
         std::stable_sort(sq[f].begin(), sq[f].end(),
                          [](const std::pair<int, int4> &a, const std::pair<int, int4> &b) { return a.first > b.first; });
         fb.sym_first[f] = (int)sitems.size();
         for (auto &e : sq[f]) sitems.push_back(e.second);
         fb.sym_n[f] = (int)sq[f].size();
-        fb.sym_nblocks[f] = fb.sym_n[f] ? sym_batch_blocks_for(f == 0 ? 0 : f == 1 ? 1 : 3, fb.sym_n[f]) : 0;
+        const int kf = f % 3 == 0 ? 0 : f % 3 == 1 ? 1 : 3;
+        fb.sym_nblocks[f] = fb.sym_n[f] ? sym_batch_blocks_for(kf, f >= 3, fb.sym_n[f]) : 0;
     }
     const size_t sb = sizeof(int4) * std::max<size_t>(sitems.size(), 1);
     if (sb > fb.sym_cap) {
@@ -592,7 +594,7 @@ static void batch_plan(const std::vector<DevMesh *> &ds, const std::vector<int> 
         HIPCHECK(hipMalloc(&fb.items, ib));
         fb.item_cap = ib;
     }
-    if (!fb.next) HIPCHECK(hipMalloc(&fb.next, 7 * sizeof(int)));
+    if (!fb.next) HIPCHECK(hipMalloc(&fb.next, 10 * sizeof(int)));
     HIPCHECK(hipMemcpyAsync(fb.reqs, reqs.data(), rb, hipMemcpyHostToDevice, fb.stream));
     if (!items.empty())
         HIPCHECK(hipMemcpyAsync(fb.items, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice,
@@ -624,9 +626,9 @@ void launch_far_batch(FarBatch &fb, bool fp32)
     if (fp32) {
         batch_launch<float, 0>(fb); batch_launch<float, 1>(fb); batch_launch<float, 3>(fb);
         const int forms[3] = {0, 1, 3};
-        for (int f = 0; f < 3; ++f)
-            launch_far_sym_batch(forms[f], fb.reqs, (const int4 *)fb.sym_items + fb.sym_first[f], fb.sym_n[f],
-                                 fb.sym_nblocks[f], fb.next + 4 + f, fb.stream);
+        for (int f = 0; f < 6; ++f)
+            launch_far_sym_batch(forms[f % 3], f >= 3, fb.reqs, (const int4 *)fb.sym_items + fb.sym_first[f],
+                                 fb.sym_n[f], fb.sym_nblocks[f], fb.next + 4 + f, fb.stream);
     } else {
         batch_launch<double, 0>(fb); batch_launch<double, 1>(fb); batch_launch<double, 3>(fb);
     }

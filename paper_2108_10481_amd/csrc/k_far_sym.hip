@@ -19,8 +19,9 @@
 //
 // Coordinates (points and the plane offsets) are used scaled by s = kappa
 // log2(e), with the coefficients of far_coef_sym: then exp(-kappa r) =
-// exp2(-r') with r' = r2' / sqrt(r2') and no multiply for the argument.  The
-// split is used for kappa > 0 only.
+// exp2(-r') with r' = r2' / sqrt(r2') and no multiply for the argument.
+// Unscreened meshes (kappa = 0, K0) keep their coordinates and skip the
+// exponential: e = 1, so the Yukawa kernels are the Laplace ones.
 //
 // The quadrature points of a flat triangle lie in its plane, so the normal
 // components of d = x_p - y_q factor: d . n_s = x_p . n_s - o_s depends on the
@@ -53,7 +54,7 @@ template <int FORM> struct SymLds {
 
 // one step: the 36 point pairs of target t (lane registers) and source j
 // (LDS column j); adds t's sums to a1, a2, W and the source's sums to acc
-template <int FORM>
+template <int FORM, bool K0>
 __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds<FORM> &L, int j, const float (&tx)[6],
                                          const float (&ty)[6], const float (&tz)[6], float ot, float ntx,
                                          float nty, float ntz, const float (&cs)[9][6], const float (&Ct)[3],
@@ -81,7 +82,7 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds<
             // the target's normal: -F d.n_t): cs = -kL b1_t, vL b2_t, -kY b1_t, vY b2_t,
             // -kY kappa b1_t per target point
             const float c1 = L.f[22 + q][j], c2 = L.f[28 + q][j], c3 = L.f[34 + q][j], c4 = L.f[40 + q][j];
-            const float c3k = cf.kappa * c3;
+            const float c3k = cf.kappa * c3;   // kYk = kappa kY (unused when K0)
 #pragma unroll
             for (int p = 0; p < 6; ++p) {
                 const float dx = tx[p] - yx, dy = ty[p] - yy, dz = tz[p] - yz;
@@ -91,9 +92,14 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds<
                 const float g = dns[p] * ri2, h = dnt[q] * ri2;
                 a1[p] = fmaf(ri, fmaf(c1, g, c2), a1[p]);
                 acc[q] = fmaf(ri, fmaf(cs[0][p], h, cs[1][p]), acc[q]);
-                const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
-                a2[p] = fmaf(e, fmaf(ri, fmaf(c3, g, c4), c3k * g), a2[p]);
-                acc[6 + q] = fmaf(e, fmaf(ri, fmaf(cs[2][p], h, cs[3][p]), cs[4][p] * h), acc[6 + q]);
+                if constexpr (K0) {
+                    a2[p] = fmaf(ri, fmaf(c3, g, c4), a2[p]);
+                    acc[6 + q] = fmaf(ri, fmaf(cs[2][p], h, cs[3][p]), acc[6 + q]);
+                } else {
+                    const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
+                    a2[p] = fmaf(e, fmaf(ri, fmaf(c3, g, c4), c3k * g), a2[p]);
+                    acc[6 + q] = fmaf(e, fmaf(ri, fmaf(cs[2][p], h, cs[3][p]), cs[4][p] * h), acc[6 + q]);
+                }
             }
         } else {
             // target side as far_source; source side: row 1 with -h (K at n_t), row 2
@@ -110,13 +116,13 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds<
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float ri = rsqrt_r(r2);
                 const float ri2 = ri * ri;
-                const float e = __builtin_amdgcn_exp2f(-(r2 * ri));
-                const float gy = e * ri;
+                const float e = K0 ? 1.0f : __builtin_amdgcn_exp2f(-(r2 * ri));
+                const float gy = K0 ? ri : e * ri;
                 // F_L d.n = R3 (d.n), F_Y d.n = E (d.n) with R3 = r^-3 and E = e (1/r + kappa)
                 // r^-2 = e (R3 + kappa r^-2); the factors dns[p] of target p's row 1 and
                 // dnt[q] of source q's row 1 are applied once per triangle pair (P, S)
                 const float R3 = ri * ri2;
-                const float E = e * fmaf(cf.kappa, ri2, R3);
+                const float E = K0 ? R3 : e * fmaf(cf.kappa, ri2, R3);
                 if (FORM == 3) {
                     P[p] = fmaf(c1Y, E, P[p]);
                     a1[p] = fmaf(gy, c2Y, a1[p]);
@@ -154,7 +160,7 @@ __device__ __forceinline__ void sym_pair(const FarCoef<float> &cf, const SymLds<
 }
 
 // Item (a, b) of one mesh by one wavefront; part holds the 2 nr slots
-template <int FORM, typename IP, typename RP>
+template <int FORM, bool K0, typename IP, typename RP>
 __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict__ tri, RP __restrict__ stat,
                                          RP __restrict__ dyn, int T, int rt, int nr, int a, int b,
                                          float *__restrict__ part, SymLds<FORM> &L, int lane)
@@ -249,7 +255,7 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
                 act = act && j0 >= 0 &&
                       !((j0 == v0) | (j0 == v1) | (j0 == v2) | (j1 == v0) | (j1 == v1) | (j1 == v2) |
                         (j2 == v0) | (j2 == v1) | (j2 == v2));
-                if (act) sym_pair<FORM>(cf, L, j, tx, ty, tz, ot, ntx, nty, ntz, cs, Ct, a1, a2, W, acc);
+                if (act) sym_pair<FORM, K0>(cf, L, j, tx, ty, tz, ot, ntx, nty, ntz, cs, Ct, a1, a2, W, acc);
                 // the source sums move one lane down: lane l next meets source (l + k + 1) mod 64
 #pragma unroll
                 for (int v = 0; v < NA; ++v) acc[v] = __shfl(acc[v], (lane + 1) & 63);
@@ -276,7 +282,7 @@ __device__ __forceinline__ void sym_item(const FarCoef<float> &cf, IP __restrict
 
 // One mesh: each wavefront takes items (heaviest first) from a device counter
 // until the list is done.
-template <int FORM>
+template <int FORM, bool K0>
 __global__ __launch_bounds__(64 * kSymWaves) void k_far_sym(int T, int rt, int nr, FarCoef<float> cf,
                                                               const int32_t *__restrict__ tri,
                                                               const float *__restrict__ stat,
@@ -294,13 +300,13 @@ __global__ __launch_bounds__(64 * kSymWaves) void k_far_sym(int T, int rt, int n
         i = __builtin_amdgcn_readfirstlane(__shfl(i, 0));
         if (i >= nitems) return;
         const int2 it = items[i];
-        sym_item<FORM>(cf, tri, stat, dyn, T, rt, nr, it.x, it.y, part, lds[w], lane);
+        sym_item<FORM, K0>(cf, tri, stat, dyn, T, rt, nr, it.x, it.y, part, lds[w], lane);
     }
 }
 
 // Several meshes (batched requests): items {request, a, b}; a request whose
 // stop flag is set contributes nothing.
-template <int FORM>
+template <int FORM, bool K0>
 __global__ __launch_bounds__(64 * kSymWaves) void k_far_sym_batch(const FarReq<float> *__restrict__ reqs,
                                                                     const int4 *__restrict__ items, int nitems,
                                                                     int *__restrict__ next)
@@ -315,7 +321,7 @@ __global__ __launch_bounds__(64 * kSymWaves) void k_far_sym_batch(const FarReq<f
         const int4 it = items[i];
         const FarReq<float> rq = reqs[it.x];
         if (rq.skip && *rq.skip) continue;
-        sym_item<FORM>(rq.cf, rq.tri, rq.stat, rq.dyn, rq.T, rq.rt, rq.nr, it.y, it.z, rq.part, lds[w], lane);
+        sym_item<FORM, K0>(rq.cf, rq.tri, rq.stat, rq.dyn, rq.T, rq.rt, rq.nr, it.y, it.z, rq.part, lds[w], lane);
     }
 }
 
@@ -336,16 +342,16 @@ __global__ void k_sym_set(int *p, int v) { *p = v; }
 
 // ------------------------------------------------------------------ host
 
-// The symmetric split applies to FP32 matrix-free meshes with kappa > 0 (the
-// coordinate scale; kappa = 0 takes k_far).  Automatic (mode 0): 56 tiles
-// (3584 triangles) and more -- on one smaller mesh too few tile pairs fill the
-// device (measured: at 2880 triangles both kernels take about 0.25 ms per
-// product, at 3920 the split is 7% / 33% faster, direct / Juffer, at 8000 35% /
-// 40%), while many small meshes batched together fill it either way; mode 1
-// always, mode -1 never.
+// The symmetric split applies to FP32 matrix-free meshes.  Automatic (mode 0):
+// 56 tiles (3584 triangles) and more -- on one smaller mesh too few tile pairs
+// fill the device (measured: at 2880 triangles both kernels take about 0.25 ms
+// per product, at 3920 the split is 7% / 33% faster, direct / Juffer, at 8000
+// 35% / 40%), while many small meshes batched together fill it either way;
+// mode 1 always, mode -1 never.
 bool sym_eligible(int T, double kappa, int mode)
 {
-    if (!(kappa > 0.0) || mode < 0) return false;
+    (void)kappa;   // kappa = 0 takes the unscreened variant
+    if (mode < 0) return false;
     return mode > 0 || T >= 3584;
 }
 
@@ -370,14 +376,35 @@ void sym_plan(int T, int &rt, int &nr, std::vector<int2> &items)
     for (auto &e : w) items.push_back(e.second);
 }
 
-int sym_blocks(int nitems, int form)
+// the kernel of a form (0, 1, 3) and screening (k0: kappa = 0)
+static const void *sym_kernel(int form, bool k0)
+{
+    if (k0)
+        return form == 0 ? reinterpret_cast<const void *>(&k_far_sym<0, true>)
+               : form == 1 ? reinterpret_cast<const void *>(&k_far_sym<1, true>)
+                           : reinterpret_cast<const void *>(&k_far_sym<3, true>);
+    return form == 0 ? reinterpret_cast<const void *>(&k_far_sym<0, false>)
+           : form == 1 ? reinterpret_cast<const void *>(&k_far_sym<1, false>)
+                       : reinterpret_cast<const void *>(&k_far_sym<3, false>);
+}
+
+static const void *sym_batch_kernel(int form, bool k0)
+{
+    if (k0)
+        return form == 0 ? reinterpret_cast<const void *>(&k_far_sym_batch<0, true>)
+               : form == 1 ? reinterpret_cast<const void *>(&k_far_sym_batch<1, true>)
+                           : reinterpret_cast<const void *>(&k_far_sym_batch<3, true>);
+    return form == 0 ? reinterpret_cast<const void *>(&k_far_sym_batch<0, false>)
+           : form == 1 ? reinterpret_cast<const void *>(&k_far_sym_batch<1, false>)
+                       : reinterpret_cast<const void *>(&k_far_sym_batch<3, false>);
+}
+
+int sym_blocks(int nitems, int form, bool k0)
 {
     int dev = 0, ncu = 0, per_cu = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const void *k = form == 0 ? reinterpret_cast<const void *>(&k_far_sym<0>)
-                    : form == 1 ? reinterpret_cast<const void *>(&k_far_sym<1>)
-                                : reinterpret_cast<const void *>(&k_far_sym<3>);
+    const void *k = sym_kernel(form, k0);
     HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64 * kSymWaves, 0));
     const long long cap = (long long)std::max(ncu, 1) * std::max(per_cu, 1);
     return (int)std::max(1LL, std::min(cap, (long long)(nitems + kSymWaves - 1) / kSymWaves));
@@ -387,14 +414,21 @@ void launch_far_sym(DevMesh &d)
 {
     FarCoef<float> cf;
     const int form = far_coef_sym(d, cf);
+    const bool k0 = !(d.prm.kappa > 0.0);
     const int nb = d.sym_blocks[form == 0 ? 0 : form == 1 ? 1 : 2];
     hipLaunchKernelGGL(k_sym_set, dim3(1), dim3(1), 0, d.stream, d.sym_next, 0);
-#define SYM(F)                                                                                                 \
-    hipLaunchKernelGGL((k_far_sym<F>), dim3(nb), dim3(64 * kSymWaves), 0, d.stream, d.hm.T, d.sym_rt, d.sym_nr, \
+#define SYM(F, Z)                                                                                                 \
+    hipLaunchKernelGGL((k_far_sym<F, Z>), dim3(nb), dim3(64 * kSymWaves), 0, d.stream, d.hm.T, d.sym_rt, d.sym_nr, \
                        cf, d.tri, d.stat32, d.dyn32, d.sym_items, d.sym_nitems, d.sym_next, (float *)d.part, d.ctl)
-    if (form == 0) SYM(0);
-    else if (form == 1) SYM(1);
-    else SYM(3);
+    if (k0) {
+        if (form == 0) SYM(0, true);
+        else if (form == 1) SYM(1, true);
+        else SYM(3, true);
+    } else {
+        if (form == 0) SYM(0, false);
+        else if (form == 1) SYM(1, false);
+        else SYM(3, false);
+    }
 #undef SYM
     HIPCHECK(hipGetLastError());
 }
@@ -410,38 +444,35 @@ void launch_far_sym_finish(DevMesh &d)
     HIPCHECK(hipGetLastError());
 }
 
-// batched requests: one queue per kernel form of {request, a, b} items
-template <int FORM>
-static int sym_batch_blocks(int n)
+// batched requests: one queue per kernel form and screening of {request, a, b} items
+int sym_batch_blocks_for(int form, bool k0, int n)
 {
     int dev = 0, ncu = 0, per_cu = 0;
     HIPCHECK(hipGetDevice(&dev));
     HIPCHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(&k_far_sym_batch<FORM>), 64 * kSymWaves, 0));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sym_batch_kernel(form, k0), 64 * kSymWaves, 0));
     const long long cap = (long long)std::max(ncu, 1) * std::max(per_cu, 1);
     return (int)std::max(1LL, std::min(cap, (long long)(n + kSymWaves - 1) / kSymWaves));
 }
 
-int sym_batch_blocks_for(int form, int n)
-{
-    return form == 0 ? sym_batch_blocks<0>(n) : form == 1 ? sym_batch_blocks<1>(n) : sym_batch_blocks<3>(n);
-}
-
-void launch_far_sym_batch(int form, const void *reqs, const int4 *items, int n, int nblocks, int *next,
+void launch_far_sym_batch(int form, bool k0, const void *reqs, const int4 *items, int n, int nblocks, int *next,
                           hipStream_t s)
 {
     if (n == 0) return;
     hipLaunchKernelGGL(k_sym_set, dim3(1), dim3(1), 0, s, next, 0);
-    if (form == 0)
-        hipLaunchKernelGGL((k_far_sym_batch<0>), dim3(nblocks), dim3(64 * kSymWaves), 0, s,
-                           (const FarReq<float> *)reqs, items, n, next);
-    else if (form == 1)
-        hipLaunchKernelGGL((k_far_sym_batch<1>), dim3(nblocks), dim3(64 * kSymWaves), 0, s,
-                           (const FarReq<float> *)reqs, items, n, next);
-    else
-        hipLaunchKernelGGL((k_far_sym_batch<3>), dim3(nblocks), dim3(64 * kSymWaves), 0, s,
-                           (const FarReq<float> *)reqs, items, n, next);
+#define SYMB(F, Z)                                                                                 \
+    hipLaunchKernelGGL((k_far_sym_batch<F, Z>), dim3(nblocks), dim3(64 * kSymWaves), 0, s,          \
+                       (const FarReq<float> *)reqs, items, n, next)
+    if (k0) {
+        if (form == 0) SYMB(0, true);
+        else if (form == 1) SYMB(1, true);
+        else SYMB(3, true);
+    } else {
+        if (form == 0) SYMB(0, false);
+        else if (form == 1) SYMB(1, false);
+        else SYMB(3, false);
+    }
+#undef SYMB
     HIPCHECK(hipGetLastError());
 }
 

@@ -334,13 +334,14 @@ struct FarBatch {
     hipStream_t stream = nullptr;
     void *reqs = nullptr;
     void *items = nullptr;
-    int *next = nullptr;           // one queue counter per kernel form, then three for the symmetric queues
+    int *next = nullptr;           // one queue counter per kernel form, then six for the symmetric queues
     size_t req_cap = 0, item_cap = 0;
     int first[4] = {0, 0, 0, 0}, nitems[4] = {0, 0, 0, 0}, nblocks[4] = {0, 0, 0, 0};
-    // symmetric FP32 items {request, a, b} of the requests with a symmetric split (forms 0, 1, 3)
+    // symmetric FP32 items {request, a, b} of the requests with a symmetric split:
+    // queues for forms 0, 1, 3 (kappa > 0), then the same for kappa = 0
     void *sym_items = nullptr;
     size_t sym_cap = 0;
-    int sym_first[3] = {0, 0, 0}, sym_n[3] = {0, 0, 0}, sym_nblocks[3] = {0, 0, 0};
+    int sym_first[6] = {}, sym_n[6] = {}, sym_nblocks[6] = {};
 };
 // skip (empty, or one per handle): device stop flags; a request whose flag is
 // set contributes no work (captured iterations keep replaying after it stops)
@@ -365,11 +366,11 @@ int choose_chunks(int T);
 // symmetric FP32 far field (k_far_sym.hip)
 bool sym_eligible(int T, double kappa, int mode);
 void sym_plan(int T, int &rt, int &nr, std::vector<int2> &items);
-int sym_blocks(int nitems, int form);
+int sym_blocks(int nitems, int form, bool k0);
 void launch_far_sym(DevMesh &d);
 void launch_far_sym_finish(DevMesh &d);
-int sym_batch_blocks_for(int form, int n);
-void launch_far_sym_batch(int form, const void *reqs, const int4 *items, int n, int nblocks, int *next,
+int sym_batch_blocks_for(int form, bool k0, int n);
+void launch_far_sym_batch(int form, bool k0, const void *reqs, const int4 *items, int n, int nblocks, int *next,
                           hipStream_t s);
 int reduction_chunks(int T);
 pb_status solve_on_mesh(DevMesh &d, const pb_charges *ch, pb_result *res);

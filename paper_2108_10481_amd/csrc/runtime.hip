@@ -492,9 +492,10 @@ static DevMesh *create_mesh(const pb_mesh *mesh, const pb_options *opt, BlockCac
         d->sym_items = upload(*d, items);
         d->sym_nitems = (int)items.size();
         d->sym_next = (int *)d->alloc(sizeof(int));
-        d->sym_blocks[0] = sym_blocks(d->sym_nitems, 0);
-        d->sym_blocks[1] = sym_blocks(d->sym_nitems, 1);
-        d->sym_blocks[2] = sym_blocks(d->sym_nitems, 3);
+        const bool k0 = !(opt->kappa > 0.0);
+        d->sym_blocks[0] = sym_blocks(d->sym_nitems, 0, k0);
+        d->sym_blocks[1] = sym_blocks(d->sym_nitems, 1, k0);
+        d->sym_blocks[2] = sym_blocks(d->sym_nitems, 3, k0);
         part_bytes = std::max(part_bytes, sizeof(float) * 16 * 2 * (size_t)d->sym_nr * T);
     }
     d->part = d->alloc(part_bytes);

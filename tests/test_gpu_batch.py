@@ -30,12 +30,15 @@ def _requests():
     ]
 
 
-def _handles(reqs, precision, mode=None, use_graph=1, far_symmetric=0):
+def _handles(reqs, precision, mode=None, use_graph=1, far_symmetric=0, kappas=None):
+    """kappas: one screening constant per request (default: the paper's 0.125)."""
     mode = pbm.PB_MATRIX_FREE if mode is None else mode
+    kappas = kappas or [0.125] * len(reqs)
     return [pbm.MeshHandle(m.xyz, m.tri, pbm.pb_default_options(formulation=f, preconditioner=p,
                                                                 precision=precision, operator_mode=mode,
-                                                                use_graph=use_graph, far_symmetric=far_symmetric))
-            for m, _, f, p in reqs]
+                                                                use_graph=use_graph, far_symmetric=far_symmetric,
+                                                                kappa=k))
+            for (m, _, f, p), k in zip(reqs, kappas)]
 
 
 def _same(a, b):
@@ -44,12 +47,15 @@ def _same(a, b):
     assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["dphi"], b["dphi"])
 
 
-@pytest.mark.parametrize("precision,sym", [(pbm.PB_FP64, 0), (pbm.PB_FP32, 0), (pbm.PB_FP32, 1)])
-def test_batch_equals_single_solves(precision, sym):
+@pytest.mark.parametrize("precision,sym,unscreened", [(pbm.PB_FP64, 0, False), (pbm.PB_FP32, 0, False),
+                                                      (pbm.PB_FP32, 1, False), (pbm.PB_FP32, 1, True)])
+def test_batch_equals_single_solves(precision, sym, unscreened):
     """sym = 1: every request's far field evaluated once per unordered
-    triangle pair (far_symmetric 1) in its single solve and in the batch."""
+    triangle pair (far_symmetric 1) in its single solve and in the batch;
+    unscreened: two of the requests have kappa = 0, so the batch runs the
+    screened and the unscreened symmetric kernels side by side."""
     reqs = _requests()
-    hs = _handles(reqs, precision, far_symmetric=sym)
+    hs = _handles(reqs, precision, far_symmetric=sym, kappas=[0.0, 0.125, 0.125, 0.0] if unscreened else None)
     try:
         single = [pbm.pb_mesh_solve(h, c.xyz, c.q) for h, (_, c, _, _) in zip(hs, reqs)]
         batch = pbm.pb_solve_batch(hs, [(c.xyz, c.q) for _, c, _, _ in reqs])

@@ -132,9 +132,9 @@ def test_operator_fp32(meshes, dense_systems, form, sym):
 def test_far_symmetric_option():
     """far_symmetric -1 on a mesh the automatic choice splits symmetrically
     (5120 triangles) gives the per-ordered-pair product to FP32 rounding of
-    the symmetric one and of FP64; the mesh info reports the choice (never for
-    FP64, kappa = 0 or the assembled field); values outside {-1, 0, 1} are
-    refused."""
+    the symmetric one and of FP64; the mesh info reports the choice (also for
+    kappa = 0, never for FP64 or the assembled field); values outside
+    {-1, 0, 1} are refused."""
     m, _ = inputs.star_surface(9, 16, 9.0)                     # T = 5120
     x = np.random.default_rng(17).standard_normal(2 * m.n_vertices)
     ys = {}
@@ -145,9 +145,9 @@ def test_far_symmetric_option():
     with pbm.MeshHandle(m.xyz, m.tri, _opts(1)) as h:
         y64 = pbm.pb_mesh_apply(h, x)
         assert h.info()["far_symmetric"] == 0
-    for extra in (dict(kappa=0.0), dict(operator_mode=pbm.PB_ASSEMBLED)):
+    for extra, want in ((dict(kappa=0.0), 1), (dict(operator_mode=pbm.PB_ASSEMBLED), 0)):
         with pbm.MeshHandle(m.xyz, m.tri, _opts(1, pbm.PB_FP32, far_symmetric=1, **extra)) as h:
-            assert h.info()["far_symmetric"] == 0, extra
+            assert h.info()["far_symmetric"] == want, extra
     assert np.array_equal(ys[0], ys[1]), "5120 triangles take the symmetric split automatically"
     for sym in (0, -1):
         assert _rel(ys[sym], y64) < 2e-6, (sym, _rel(ys[sym], y64))
@@ -235,8 +235,9 @@ def test_symmetric_far_field_full_size(sphere32, form, a, b, kappa):
     (the direct, second-kind and Yukawa-only kernel forms; a zero
     combined-field constant leaves a row without Laplace terms, both zero no
     Laplace term at all), within FP32 rounding; and its sampled rows against
-    the oracle's.  kappa = 0 (no screening) takes the per-ordered-pair FP32
-    kernel instead and is held to the same bounds."""
+    the oracle's.  kappa = 0 (no screening) takes the kernel's unscreened
+    variant (coordinates as they are, no exponential) and is held to the same
+    bounds."""
     m, _ = sphere32
     nv = m.n_vertices
     rng = np.random.default_rng(83)
